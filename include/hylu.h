@@ -1,0 +1,166 @@
+/*
+ * hylu.h - C ABI of an MI355X (gfx950) implementation of HYLU's numerical
+ * factorisation and forward-backward substitution (arXiv 2509.07690).
+ *
+ * The paper solves A x = b in three phases (Sec. 2): preprocessing (static
+ * pivoting and scaling by maximum weighted matching, a fill-reducing ordering,
+ * symbolic factorisation with flop count and supernode detection, Sec. 2.1),
+ * numerical factorisation (up-looking LU with row-row, sup-row and sup-sup
+ * kernels, supernode diagonal pivoting and pivot perturbation, levelised
+ * parallel scheduling, Sec. 2.2 and 2.2.1), and forward-backward substitution
+ * with automatic iterative refinement after perturbation (Sec. 2.3).  The
+ * repeated-solve option (Sec. 3.2) is hylu_refactor: same pattern, new values.
+ *
+ * Conventions
+ *  - CSR input: 0-based, int64 row pointers (n+1), int32 column indices
+ *    sorted and unique within each row, float64 values.  Right-hand sides and
+ *    solutions are n x nrhs column-major with leading dimension ld >= n.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are MI355X
+ *    memory (e.g. from torch tensors on cuda:0).  `stream` is a hipStream_t
+ *    (NULL = the null stream); calls taking a stream are asynchronous with
+ *    respect to the host unless stated otherwise.
+ *  - Ownership: the caller owns every pointer it passes.  hylu_analyze copies
+ *    what it needs from its host arrays before returning.  Device inputs must
+ *    stay valid until the work queued on `stream` has completed.  The handle
+ *    owns all internal device memory and frees it in hylu_destroy.
+ *  - Errors: every call returns a hylu_status; no C++ exception crosses this
+ *    ABI.  A device failure is sticky for the handle.  A handle is not
+ *    thread-safe; distinct handles are independent.
+ */
+#ifndef HYLU_H
+#define HYLU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hylu_handle_s* hylu_handle;
+
+typedef enum {
+    HYLU_OK = 0,
+    HYLU_ERR_ARG = -1,              /* NULL pointer, bad size or option */
+    HYLU_ERR_CSR = -2,              /* unsorted / duplicate / out-of-range column */
+    HYLU_ERR_STRUCT_SINGULAR = -3,  /* no perfect matching (empty row or column, ...) */
+    HYLU_ERR_NOT_ANALYZED = -4,     /* factorize/solve before analyze */
+    HYLU_ERR_NOT_FACTORIZED = -5,   /* refactor/solve before factorize */
+    HYLU_ERR_OOM = -6,              /* host or device allocation failed; handle stays valid */
+    HYLU_ERR_DEVICE = -7,           /* a HIP call failed */
+    HYLU_ERR_NONFINITE = -8,        /* NaN or Inf in the input values */
+    HYLU_ERR_INTERNAL = -9,
+    HYLU_WARN_IR_NOT_CONVERGED = 1  /* solve finished, backward error above ir_tol */
+} hylu_status;
+
+/* Options of the preprocessing and numerical phases. */
+typedef struct {
+    int32_t ordering;      /* 0 AMD, 1 nested dissection, 2 natural, 3 user_perm (Sec. 2.1) */
+    const int32_t* user_perm; /* host, n entries, new -> old; read by hylu_analyze only */
+    int32_t static_pivot;  /* 1: maximum-product matching + scaling (Sec. 2.1); 0: identity, unit scaling */
+    int32_t precision;     /* 0: FP64 factors; 1: FP32 factors + FP64 iterative refinement */
+    double pivot_tau;      /* perturbation threshold relative to max|B|; <= 0: sqrt(eps) of the factor precision */
+    double ir_tol;         /* target normwise backward error of refinement (default 1e-12) */
+    int32_t ir_maxit;      /* refinement iteration cap (default 10 for FP64, 30 for FP32) */
+    int32_t sn_min;        /* shortest run of rows kept as a supernode (default 2) */
+    int32_t sn_max;        /* longest supernode; longer runs are split (default 1<<30) */
+    int32_t kernel_mode;   /* 0 automatic choice, 1 row-row only (no supernodes), 2 supernodal */
+    int32_t repeated;      /* reserved: the relative-index maps are always precomputed */
+    int32_t nd_leaf;       /* nested dissection: parts up to this size are ordered by AMD (default 256) */
+    double amd_dense;      /* AMD: rows with more than max(16, amd_dense*sqrt(n)) entries are ordered last */
+} hylu_options;
+
+/* Optional device allocator (e.g. the PyTorch caching allocator).  alloc
+ * returns NULL on failure; both are called from the host with the stream the
+ * memory is used on. */
+typedef struct {
+    void* ctx;
+    void* (*alloc)(void* ctx, size_t bytes, void* stream);
+    void (*free)(void* ctx, void* ptr, void* stream);
+} hylu_allocator;
+
+typedef struct {
+    int64_t n, nnz_a, nnz_l, nnz_u;   /* exact structure; U includes the diagonal */
+    uint64_t flops;                   /* F = sum_k l_k (1 + 2 u_k) on the exact structure */
+    uint64_t flops_padded;            /* rows padded to whole source supernodes */
+    int64_t factor_entries;           /* stored panel values (padding included) */
+    int32_t n_nodes, n_supernodes, rows_in_supernodes, max_supernode;
+    int32_t n_levels[4];              /* factor / L solve, U solve, U^T solve, L^T solve */
+    int32_t n_perturbed;              /* perturbed pivots of the last (re)factorisation */
+    int32_t ir_iters;                 /* refinement steps of the last solve */
+    double berr;                      /* normwise backward error of the last solve (if refined) */
+    double pivot_tau;                 /* absolute perturbation threshold used */
+} hylu_info;
+
+/* Analysis export for checking: every array is host memory the caller
+ * allocates with the sizes from hylu_get_info (n, nnz_a, n_nodes). */
+typedef struct {
+    int32_t* perm_r;     /* n: row i' of B is row perm_r[i'] of A */
+    int32_t* perm_c;     /* n: column j' of B is column perm_c[j'] of A */
+    double* dr;          /* n: row scaling, by row of A */
+    double* dc;          /* n: column scaling, by column of A */
+    int32_t* node_ptr;   /* n_nodes+1: row boundaries of the nodes */
+    uint8_t* is_sn;      /* n_nodes: 1 for a supernode */
+    int32_t* levels;     /* 4*n_nodes: level of each node in the four task graphs */
+} hylu_symbolic_view;
+
+hylu_status hylu_default_options(hylu_options* opt);
+const char* hylu_status_string(hylu_status s);
+
+/* Create a handle.  alloc may be NULL (hipMalloc/hipFree are used). */
+hylu_status hylu_create(hylu_handle* h, const hylu_allocator* alloc);
+hylu_status hylu_destroy(hylu_handle h);
+
+/* Preprocessing (Sec. 2.1), on the host: validates the CSR, computes the
+ * matching/scaling, the ordering, the symbolic structure, flop count,
+ * supernodes, the level sets (Sec. 2.2.1) and the device layout, and uploads
+ * the index tables.  row_ptr, col, val: host.  val is read for the matching. */
+hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const int32_t* col,
+                         const double* val, const hylu_options* opt);
+
+/* Numerical factorisation with pivot search (Sec. 2.2).  d_val: device,
+ * nnz float64 values in the CSR order given to hylu_analyze. */
+hylu_status hylu_factorize(hylu_handle h, const double* d_val, void* stream);
+
+/* Refactorisation with new values on the same pattern, reusing the pivot
+ * order of the last hylu_factorize (the repeated-solve scenario, Sec. 3.2).
+ * Perturbation stays active.  The level sequence is replayed as a HIP graph. */
+hylu_status hylu_refactor(hylu_handle h, const double* d_val, void* stream);
+
+/* Forward-backward substitution (Sec. 2.3): solves A x = b (transpose = 0) or
+ * A^T x = b (transpose = 1) for nrhs columns.  d_b, d_x: device, n x nrhs,
+ * column-major, leading dimension ld; d_x may equal d_b.  Iterative
+ * refinement in FP64 runs when a pivot was perturbed or precision = 1; its
+ * residual uses the handle's copy of the values of the last (re)factorisation.
+ * Synchronises the stream when refinement runs (the stopping test
+ * reads the backward error on the host). */
+hylu_status hylu_solve(hylu_handle h, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
+                       int32_t transpose, void* stream);
+
+/* Gradient of a scalar loss through x = A^{-1} b with respect to the values of
+ * A: d_gval[p] = -lambda[row p] * x[col p] for every stored entry p, where
+ * lambda = A^{-T} dL/dx (from hylu_solve with transpose = 1).  Device arrays:
+ * d_lambda, d_x of n entries, d_gval of nnz entries. */
+hylu_status hylu_grad_values(hylu_handle h, const double* d_lambda, const double* d_x,
+                             double* d_gval, void* stream);
+
+/* Statistics of the analysis and of the last numerical calls (synchronises). */
+hylu_status hylu_get_info(hylu_handle h, hylu_info* out);
+
+/* Copies of the analysis results (host arrays, sizes from hylu_get_info). */
+hylu_status hylu_export_symbolic(hylu_handle h, const hylu_symbolic_view* v);
+
+/* Copies of the factors after a (re)factorisation, as host arrays in the
+ * oracle-independent panel form: values (factor_entries of float64), the
+ * panel offsets and widths, and the pivot order.  For checking.  Sizes:
+ * vals factor_entries; node_voff n_nodes+1 (int64); node_lw, node_W n_nodes;
+ * cols: sum of W; piv n (global column of each row's pivot). */
+hylu_status hylu_export_factors(hylu_handle h, double* vals, int64_t* node_voff, int32_t* node_lw,
+                                int32_t* node_W, int64_t* node_coff, int32_t* cols, int32_t* piv);
+hylu_status hylu_export_sizes(hylu_handle h, int64_t* ncols_total);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYLU_H */

@@ -1,0 +1,104 @@
+// Host-side preprocessing of HYLU (arXiv 2509.07690, Sec. 2.1) and the data
+// layout the gfx950 kernels consume.  Everything here runs on the CPU once per
+// sparsity pattern; the numerical phases only read the tables it produces.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace hylu {
+
+struct Csr {
+    int32_t n = 0;
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    std::vector<double> v;
+    int64_t nnz() const { return rp.empty() ? 0 : rp[n]; }
+};
+
+// ---------------------------------------------------------------- ordering
+// Static pivoting and scaling by a maximum-product matching (Sec. 2.1):
+// row_of_col[j] is the row matched to column j; dr/dc make the matched entries
+// +-1 and every other entry at most 1 in magnitude.  Returns false when the
+// pattern is structurally singular.
+bool mc64_match_scale(const Csr& a, std::vector<int32_t>& row_of_col,
+                      std::vector<double>& dr, std::vector<double>& dc);
+
+// Symmetric fill-reducing orderings of an undirected graph given as CSR
+// adjacency without self loops.  Both return perm[new] = old.
+std::vector<int32_t> amd_order(int32_t n, const std::vector<int64_t>& xadj,
+                               const std::vector<int32_t>& adj, double dense_alpha = 10.0);
+std::vector<int32_t> nd_order(int32_t n, const std::vector<int64_t>& xadj,
+                              const std::vector<int32_t>& adj, int32_t leaf_size, double dense_alpha = 10.0);
+
+// ---------------------------------------------------------------- symbolic
+// Exact, unpivoted structure of the factors of B in compressed form:
+//  * L(i,:) as a list of row intervals [lo, hi] (inclusive), each inside one
+//    chain run of rows with identical U structure;
+//  * U of every run [r, last]: rows r..last share the columns past `last`,
+//    stored once as the strict upper structure of row r (run_u), whose first
+//    (last - r) entries are r+1..last.
+struct Symbolic {
+    int32_t n = 0;
+    std::vector<int64_t> lp;            // n+1, into lint (pairs)
+    std::vector<int32_t> lint;          // 2 ints per interval
+    std::vector<int32_t> run_of;        // row -> run id
+    std::vector<int32_t> run_start;     // run id -> first row (runs+1 entries)
+    std::vector<int64_t> run_up;        // run id -> offset into run_u (runs+1)
+    std::vector<int32_t> run_u;         // strict upper structure of each run's first row
+    std::vector<int64_t> lcount;        // l_k: rows i > k with L(i,k) != 0
+    std::vector<int64_t> ucount;        // u_k: |U(k,>k)|
+    int64_t nnz_l = 0, nnz_u = 0;       // exact, U includes the diagonal
+    uint64_t flops = 0;                 // F = sum_k l_k (1 + 2 u_k)
+    int32_t nruns() const { return (int32_t)run_start.size() - 1; }
+};
+
+bool symbolic_factor(const Csr& b, Symbolic& s);
+
+// ---------------------------------------------------------------- nodes
+// Supernodes (Sec. 2.2: consecutive rows with identical U structure) and
+// standalone rows, plus the level sets of the task graphs (Sec. 2.2.1).
+struct Nodes {
+    int32_t count = 0;
+    std::vector<int32_t> ptr;           // count+1 row boundaries
+    std::vector<int32_t> of_row;        // row -> node
+    std::vector<uint8_t> is_sn;         // node -> supernode flag
+    // level of every node in the four task graphs:
+    // 0 factor / forward (L) solve, 1 backward (U) solve, 2 U^T solve, 3 L^T solve
+    std::vector<int32_t> level[4];
+    int32_t nlevels[4] = {0, 0, 0, 0};
+    uint64_t flops_padded = 0;          // work with every row padded to whole source nodes
+};
+
+void make_nodes(const Symbolic& s, int32_t sn_min, int32_t sn_max, Nodes& nd);
+void make_levels(const Symbolic& s, Nodes& nd);
+
+// ---------------------------------------------------------------- layout
+// Every node v (a supernode of m rows, or a standalone row with m = 1) owns a
+// dense row-major panel of m x W values: [L region | diagonal block | T],
+// with one shared sorted column list.  The L region holds the multipliers for
+// whole source nodes (one slot per source row), the diagonal block holds the
+// node's own L\U in pivoted column order, T the columns of U past the block.
+struct Layout {
+    int32_t n = 0, nnodes = 0;
+    std::vector<int32_t> r0, m, lw, W;  // per node
+    std::vector<int64_t> voff, coff;    // value / column-list offsets
+    std::vector<int32_t> cols;          // concatenated column lists
+    int64_t nvals = 0;
+    // per target node: its sources in ascending order
+    std::vector<int64_t> eptr;          // nnodes+1
+    std::vector<int32_t> esrc, elpos;   // source node, slot of its first row in the target
+    std::vector<int64_t> eroff;         // offset of the relative map of the source's T
+    std::vector<int32_t> rel;           // relative positions, concatenated
+    // value map: entry q of B (CSR order of A) lands in slot amap[p]
+    std::vector<int64_t> amap;          // per A entry p -> value slot
+    // level lists (node ids sorted by level, then index) for the 4 graphs
+    std::vector<int32_t> lev_ptr[4], lev_nodes[4];
+    uint64_t flops_kernel = 0;          // multiply-adds actually issued by the kernels (x2) + divisions
+};
+
+bool build_layout(const Csr& b, const Symbolic& s, const Nodes& nd, Layout& L,
+                  const std::vector<int64_t>& bsrc, std::string& err);
+
+}  // namespace hylu

@@ -1,0 +1,325 @@
+// Symbolic factorisation, supernode detection, task-graph levels and the
+// panel layout (HYLU Sec. 2.1 last step, Sec. 2.2 supernode definition,
+// Sec. 2.2.1 levelisation).
+//
+// The symbolic step forms the exact structure of every row of L and U in
+// row order (the up-looking order of Sec. 2.2): row i is the union of row i
+// of B and, for every k < i met so far in ascending order, the strict upper
+// structure of row k.  Consecutive rows whose U structures agree once the
+// leading row is dropped form a chain run (the supernode definition); all rows
+// of a run share the columns past the run, so when the smallest k of a run
+// enters row i the whole rest of the run and its shared columns enter
+// together and the other rows of the run need no visit.  Runs are what keeps
+// this pass far below the O(flops) cost of the row-by-row union.
+#include <algorithm>
+#include <cstring>
+#include <functional>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "analysis.hpp"
+
+namespace hylu {
+
+bool symbolic_factor(const Csr& b, Symbolic& s)
+{
+    const int32_t n = b.n;
+    s = Symbolic();
+    s.n = n;
+    s.lp.assign(n + 1, 0);
+    s.run_of.assign(n, -1);
+    s.ucount.assign(n, 0);
+    s.run_up.push_back(0);
+    std::vector<int32_t> mark(n, -1), done(n, -1);
+    std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> heap;
+    std::vector<int32_t> ubuf, open_u;                 // open_u: strict U of the open run's first row
+    int32_t open_run = -1, open_start = 0;
+    for (int32_t i = 0; i < n; i++) {
+        ubuf.clear();
+        mark[i] = i;
+        for (int64_t q = b.rp[i]; q < b.rp[i + 1]; q++) {
+            int32_t j = b.ci[q];
+            if (mark[j] == i) continue;
+            mark[j] = i;
+            if (j < i) heap.push(j); else ubuf.push_back(j);
+        }
+        while (!heap.empty()) {
+            int32_t k = heap.top();
+            heap.pop();
+            if (done[k] == i) continue;
+            int32_t R = s.run_of[k];
+            int32_t rs, last;
+            const int32_t* ul;
+            int64_t ulen;
+            if (R == open_run) {
+                rs = open_start; last = i - 1;
+                ul = open_u.data(); ulen = (int64_t)open_u.size();
+            } else {
+                rs = s.run_start[R]; last = s.run_start[R + 1] - 1;
+                ul = s.run_u.data() + s.run_up[R]; ulen = s.run_up[R + 1] - s.run_up[R];
+            }
+            s.lint.push_back(k);
+            s.lint.push_back(last);
+            for (int32_t t = k; t <= last; t++) { done[t] = i; mark[t] = i; }
+            for (int64_t t = last - rs; t < ulen; t++) {
+                int32_t j = ul[t];
+                if (mark[j] == i) continue;
+                mark[j] = i;
+                if (j < i) heap.push(j); else ubuf.push_back(j);
+            }
+        }
+        s.lp[i + 1] = (int64_t)s.lint.size() / 2;
+        std::sort(ubuf.begin(), ubuf.end());
+        s.ucount[i] = (int64_t)ubuf.size();
+        // does row i extend the open run?  U(i-1,:) \ {i-1, i} == U(i,:) \ {i}
+        bool chain = false;
+        if (open_run >= 0) {
+            int64_t off = (i - 1) - open_start;       // U(i-1, > i-1) = open_u[off:]
+            int64_t plen = (int64_t)open_u.size() - off;
+            if (plen >= 1 && open_u[off] == i && plen - 1 == (int64_t)ubuf.size())
+                chain = std::equal(ubuf.begin(), ubuf.end(), open_u.begin() + off + 1);
+        }
+        if (chain) {
+            s.run_of[i] = open_run;
+        } else {
+            if (open_run >= 0) {
+                s.run_u.insert(s.run_u.end(), open_u.begin(), open_u.end());
+                s.run_up.push_back((int64_t)s.run_u.size());
+            }
+            open_run = (int32_t)s.run_start.size();
+            s.run_start.push_back(i);
+            open_start = i;
+            open_u = ubuf;
+            s.run_of[i] = open_run;
+        }
+    }
+    if (open_run >= 0) {
+        s.run_u.insert(s.run_u.end(), open_u.begin(), open_u.end());
+        s.run_up.push_back((int64_t)s.run_u.size());
+    }
+    s.run_start.push_back(n);
+    // l_k from the intervals, F = sum_k l_k (1 + 2 u_k)
+    std::vector<int64_t> diff(n + 1, 0);
+    for (int64_t t = 0; t < s.lp[n]; t++) {
+        diff[s.lint[2 * t]]++;
+        diff[s.lint[2 * t + 1] + 1]--;
+        s.nnz_l += s.lint[2 * t + 1] - s.lint[2 * t] + 1;
+    }
+    s.lcount.assign(n, 0);
+    int64_t acc = 0;
+    uint64_t F = 0;
+    for (int32_t k = 0; k < n; k++) {
+        acc += diff[k];
+        s.lcount[k] = acc;
+        F += (uint64_t)acc * (1 + 2 * (uint64_t)s.ucount[k]);
+        s.nnz_u += 1 + s.ucount[k];
+    }
+    s.flops = F;
+    return true;
+}
+
+// strict upper structure of row k: a suffix of its run's stored list
+static inline void row_upper(const Symbolic& s, int32_t k, const int32_t*& p, int64_t& len)
+{
+    int32_t R = s.run_of[k];
+    int64_t base = s.run_up[R] + (k - s.run_start[R]);
+    p = s.run_u.data() + base;
+    len = s.run_up[R + 1] - base;
+}
+
+void make_nodes(const Symbolic& s, int32_t sn_min, int32_t sn_max, Nodes& nd)
+{
+    const int32_t n = s.n;
+    if (sn_min < 2) sn_min = 2;
+    if (sn_max < 1) sn_max = 1;
+    nd = Nodes();
+    nd.ptr.push_back(0);
+    nd.of_row.assign(n, 0);
+    for (int32_t R = 0; R < s.nruns(); R++) {
+        int32_t rs = s.run_start[R], re = s.run_start[R + 1];
+        for (int32_t c0 = rs; c0 < re;) {
+            int32_t c = std::min(re - c0, sn_max);
+            if (c >= sn_min) {
+                for (int32_t t = c0; t < c0 + c; t++) nd.of_row[t] = nd.count;
+                nd.is_sn.push_back(1);
+                nd.ptr.push_back(c0 + c);
+                nd.count++;
+            } else {
+                for (int32_t t = c0; t < c0 + c; t++) {
+                    nd.of_row[t] = nd.count;
+                    nd.is_sn.push_back(0);
+                    nd.ptr.push_back(t + 1);
+                    nd.count++;
+                }
+            }
+            c0 += c;
+        }
+    }
+    // padded work: every source row of a supernode source, and the own
+    // supernode's earlier rows, cost 1 + 2 u_k each
+    std::vector<uint64_t> rowcost(n), pre(n + 1, 0);
+    for (int32_t k = 0; k < n; k++) { rowcost[k] = 1 + 2 * (uint64_t)s.ucount[k]; pre[k + 1] = pre[k] + rowcost[k]; }
+    uint64_t fp = 0;
+    for (int32_t i = 0; i < n; i++) {
+        int32_t v = nd.of_row[i];
+        for (int64_t t = s.lp[i]; t < s.lp[i + 1]; t++) {
+            int32_t lo = s.lint[2 * t], hi = s.lint[2 * t + 1];
+            for (int32_t u = nd.of_row[lo]; u <= nd.of_row[hi]; u++) {
+                if (u == v) continue;
+                if (nd.is_sn[u]) fp += pre[nd.ptr[u + 1]] - pre[nd.ptr[u]];
+                else {
+                    int32_t k = nd.ptr[u];
+                    if (k >= lo && k <= hi) fp += rowcost[k];
+                }
+            }
+        }
+        if (nd.is_sn[v]) fp += pre[i] - pre[nd.ptr[v]];
+    }
+    nd.flops_padded = fp;
+}
+
+void make_levels(const Symbolic& s, Nodes& nd)
+{
+    const int32_t nn = nd.count;
+    for (int t = 0; t < 4; t++) nd.level[t].assign(nn, 0);
+    // factor / forward solve: v waits for the nodes covering L(i,:), i in v
+    std::vector<int32_t>& l0 = nd.level[0];
+    std::vector<int32_t>& l3 = nd.level[3];
+    for (int32_t v = 0; v < nn; v++)
+        for (int32_t i = nd.ptr[v]; i < nd.ptr[v + 1]; i++)
+            for (int64_t t = s.lp[i]; t < s.lp[i + 1]; t++)
+                for (int32_t u = nd.of_row[s.lint[2 * t]]; u <= nd.of_row[s.lint[2 * t + 1]]; u++)
+                    if (u != v && l0[u] + 1 > l0[v]) l0[v] = l0[u] + 1;
+    for (int32_t v = nn - 1; v >= 0; v--)
+        for (int32_t i = nd.ptr[v]; i < nd.ptr[v + 1]; i++)
+            for (int64_t t = s.lp[i]; t < s.lp[i + 1]; t++)
+                for (int32_t u = nd.of_row[s.lint[2 * t]]; u <= nd.of_row[s.lint[2 * t + 1]]; u++)
+                    if (u != v && l3[v] + 1 > l3[u]) l3[u] = l3[v] + 1;
+    // backward solve: v waits for the nodes owning the columns past its block
+    std::vector<int32_t>& l1 = nd.level[1];
+    std::vector<int32_t>& l2 = nd.level[2];
+    for (int32_t v = nn - 1; v >= 0; v--) {
+        const int32_t* up; int64_t ul;
+        row_upper(s, nd.ptr[v + 1] - 1, up, ul);
+        for (int64_t t = 0; t < ul; t++) {
+            int32_t u = nd.of_row[up[t]];
+            if (u != v && l1[u] + 1 > l1[v]) l1[v] = l1[u] + 1;
+        }
+    }
+    for (int32_t v = 0; v < nn; v++) {
+        const int32_t* up; int64_t ul;
+        row_upper(s, nd.ptr[v + 1] - 1, up, ul);
+        for (int64_t t = 0; t < ul; t++) {
+            int32_t u = nd.of_row[up[t]];
+            if (u != v && l2[v] + 1 > l2[u]) l2[u] = l2[v] + 1;
+        }
+    }
+    for (int t = 0; t < 4; t++) {
+        int32_t mx = -1;
+        for (int32_t v = 0; v < nn; v++) mx = std::max(mx, nd.level[t][v]);
+        nd.nlevels[t] = mx + 1;
+    }
+}
+
+bool build_layout(const Csr& b, const Symbolic& s, const Nodes& nd, Layout& L,
+                  const std::vector<int64_t>& bsrc, std::string& err)
+{
+    const int32_t n = s.n, nn = nd.count;
+    L = Layout();
+    L.n = n; L.nnodes = nn;
+    L.r0.resize(nn); L.m.resize(nn); L.lw.resize(nn); L.W.resize(nn);
+    L.voff.resize(nn + 1); L.coff.resize(nn + 1);
+    L.eptr.assign(nn + 1, 0);
+    std::vector<int32_t> stamp(nn, -1), srcs, lcols;
+    std::vector<int32_t> pos_of;      // scratch: column -> position in the current node (via stamp)
+    std::vector<int32_t> colstamp(n, -1), colpos(n, 0);
+    int64_t voff = 0;
+    for (int32_t v = 0; v < nn; v++) {
+        int32_t v0 = nd.ptr[v], v1 = nd.ptr[v + 1], m = v1 - v0;
+        // source nodes: union over the node's rows of the nodes covering L(i,:)
+        srcs.clear();
+        for (int32_t i = v0; i < v1; i++)
+            for (int64_t t = s.lp[i]; t < s.lp[i + 1]; t++) {
+                int32_t lo = s.lint[2 * t], hi = s.lint[2 * t + 1];
+                for (int32_t u = nd.of_row[lo]; u <= nd.of_row[hi]; u++) {
+                    if (u == v || stamp[u] == v) continue;
+                    if (!nd.is_sn[u] && !(nd.ptr[u] >= lo && nd.ptr[u] <= hi)) continue;
+                    stamp[u] = v;
+                    srcs.push_back(u);
+                }
+            }
+        std::sort(srcs.begin(), srcs.end());
+        // column list: source rows | block | columns past the block
+        L.coff[v] = (int64_t)L.cols.size();
+        for (int32_t u : srcs)
+            for (int32_t k = nd.ptr[u]; k < nd.ptr[u + 1]; k++) L.cols.push_back(k);
+        int32_t lw = (int32_t)(L.cols.size() - L.coff[v]);
+        for (int32_t k = v0; k < v1; k++) L.cols.push_back(k);
+        const int32_t* up; int64_t ul;
+        row_upper(s, v1 - 1, up, ul);
+        for (int64_t t = 0; t < ul; t++) L.cols.push_back(up[t]);
+        int32_t W = (int32_t)(L.cols.size() - L.coff[v]);
+        L.r0[v] = v0; L.m[v] = m; L.lw[v] = lw; L.W[v] = W;
+        L.voff[v] = voff;
+        voff += (int64_t)m * W;
+        // positions of the node's columns
+        for (int32_t t = 0; t < W; t++) { int32_t c = L.cols[L.coff[v] + t]; colstamp[c] = v; colpos[c] = t; }
+        // edges with relative maps of the source's T into this node
+        int32_t lpos = 0;
+        for (int32_t u : srcs) {
+            L.esrc.push_back(u);
+            L.elpos.push_back(lpos);
+            lpos += nd.ptr[u + 1] - nd.ptr[u];
+            L.eroff.push_back((int64_t)L.rel.size());
+            const int32_t* uu; int64_t uul;
+            row_upper(s, nd.ptr[u + 1] - 1, uu, uul);
+            int32_t mu = nd.ptr[u + 1] - nd.ptr[u];
+            for (int64_t t = 0; t < uul; t++) {
+                int32_t c = uu[t];
+                if (colstamp[c] != v) { err = "layout: source column outside target structure"; return false; }
+                L.rel.push_back(colpos[c]);
+                L.flops_kernel += 2 * (uint64_t)m * mu;
+            }
+            L.flops_kernel += (uint64_t)m * mu * mu;    // the triangular solve with the source block
+        }
+        L.eptr[v + 1] = (int64_t)L.esrc.size();
+        if (nd.is_sn[v]) L.flops_kernel += (uint64_t)m * m * (uint64_t)(m + W - lw) ;
+        // value map for B's entries of these rows
+        for (int32_t i = v0; i < v1; i++)
+            for (int64_t q = b.rp[i]; q < b.rp[i + 1]; q++) {
+                int32_t c = b.ci[q];
+                if (colstamp[c] != v) { err = "layout: entry of B outside the structure"; return false; }
+                int64_t slot = L.voff[v] + (int64_t)(i - v0) * W + colpos[c];
+                if (L.amap.empty()) L.amap.assign(bsrc.size(), -1);
+                L.amap[bsrc[q]] = slot;
+            }
+    }
+    L.voff[nn] = voff;
+    L.coff[nn] = (int64_t)L.cols.size();
+    L.nvals = voff;
+    if (L.amap.empty()) L.amap.assign(bsrc.size(), -1);
+    for (int64_t p = 0; p < (int64_t)L.amap.size(); p++)
+        if (L.amap[p] < 0 || L.amap[p] >= L.nvals) { err = "layout: value map entry out of range"; return false; }
+    for (int32_t v = 0; v < nn; v++)
+        for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
+            int32_t s2 = L.esrc[e];
+            int32_t ws2 = L.W[s2] - L.lw[s2] - L.m[s2];
+            if (L.elpos[e] + L.m[s2] > L.lw[v]) { err = "layout: source block outside the L region"; return false; }
+            for (int32_t t = 0; t < ws2; t++)
+                if (L.rel[L.eroff[e] + t] < 0 || L.rel[L.eroff[e] + t] >= L.W[v]) { err = "layout: relative index out of range"; return false; }
+        }
+    // level lists
+    for (int g = 0; g < 4; g++) {
+        int32_t nl = nd.nlevels[g];
+        L.lev_ptr[g].assign(nl + 1, 0);
+        for (int32_t v = 0; v < nn; v++) L.lev_ptr[g][nd.level[g][v] + 1]++;
+        for (int32_t l = 0; l < nl; l++) L.lev_ptr[g][l + 1] += L.lev_ptr[g][l];
+        L.lev_nodes[g].resize(nn);
+        std::vector<int32_t> fill(L.lev_ptr[g].begin(), L.lev_ptr[g].end() - 1);
+        for (int32_t v = 0; v < nn; v++) L.lev_nodes[g][fill[nd.level[g][v]]++] = v;
+    }
+    return true;
+}
+
+}  // namespace hylu

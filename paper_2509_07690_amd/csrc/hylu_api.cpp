@@ -1,0 +1,823 @@
+// C ABI of the MI355X HYLU solver: handle life cycle, preprocessing on the
+// host (Sec. 2.1), level-scheduled numerical factorisation (Sec. 2.2, 2.2.1),
+// substitution with refinement (Sec. 2.3) and the repeated-solve path
+// (Sec. 3.2) replayed from a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <limits>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include <chrono>
+
+#include "../../include/hylu.h"
+#include "analysis.hpp"
+#include "kernels.hpp"
+
+using namespace hylu;
+
+namespace {
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct LevelTasks {
+    std::vector<int64_t> row_ptr;     // per level into rows
+    std::vector<int32_t> maxW;        // per level
+    std::vector<int64_t> sn_ptr;      // per level into snodes
+    std::vector<int32_t> maxm;
+    std::vector<int32_t> rows, snodes;
+};
+
+}  // namespace
+
+struct hylu_handle_s {
+    hylu_allocator alloc{};
+    bool has_alloc = false;
+    hipStream_t cap_stream = nullptr;
+    int device = 0;
+    // analysis
+    hylu_options opt{};
+    bool analyzed = false, factorized = false, sticky_error = false, uploaded = false;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    Csr A;                                  // pattern (values from analyze)
+    std::vector<int32_t> perm_r, perm_c;
+    std::vector<double> dr, dc;
+    Symbolic sym;
+    Nodes nodes;
+    Layout lay;
+    LevelTasks ft;
+    double tau = 0.0;
+    int32_t max_sn = 0;
+    bool fp32 = false;
+    // device memory
+    std::vector<void*> blocks;
+    DevLayout D{};
+    void* vals = nullptr;                   // factor panels (double or float)
+    int64_t* d_amap = nullptr;
+    double *d_asr = nullptr, *d_asc = nullptr;
+    int32_t *d_rows = nullptr, *d_snodes = nullptr;
+    int32_t* d_lev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t *d_perm_r = nullptr, *d_perm_c = nullptr;
+    double *d_dr = nullptr, *d_dc = nullptr;
+    int64_t* d_arp = nullptr;
+    int32_t* d_aci = nullptr;
+    double* d_aval = nullptr;               // copy of the values of the last (re)factorisation
+    int64_t* d_atp = nullptr;               // A^T as CSR: pointers, columns, value positions
+    int32_t* d_atc = nullptr;
+    int64_t* d_atq = nullptr;
+    double* d_atv = nullptr;
+    bool tlists = false;
+    int32_t* d_pert = nullptr;
+    int32_t* h_pert = nullptr;              // pinned
+    hipEvent_t fact_done = nullptr;
+    int32_t last_pert = 0;
+    bool pert_known = false;
+    // solve workspace
+    int32_t ws_nrhs = 0;
+    void *d_y = nullptr, *d_z = nullptr;
+    double* d_r = nullptr;
+    double* d_bc = nullptr;                 // copy of b when refining in place
+    double* d_norms = nullptr;
+    double* h_norms = nullptr;              // pinned
+    // graphs
+    std::map<const double*, GraphEntry> refac_graphs;
+    std::map<std::tuple<const double*, double*, int32_t, int64_t, int32_t>, GraphEntry> solve_graphs;
+    // last solve
+    int32_t ir_iters = 0;
+    double berr = 0.0;
+};
+
+namespace {
+
+// HYLU_LOG=1 prints the duration of each preprocessing step to stderr
+struct PhaseLog {
+    bool on = std::getenv("HYLU_LOG") != nullptr;
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    void operator()(const char* what) {
+        auto now = std::chrono::steady_clock::now();
+        if (on) std::fprintf(stderr, "hylu: %-10s %8.3f s\n", what, std::chrono::duration<double>(now - t).count());
+        t = now;
+    }
+};
+
+#define HIPCHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { h->sticky_error = true; return HYLU_ERR_DEVICE; } } while (0)
+
+void* dalloc(hylu_handle h, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    void* p = nullptr;
+    if (h->has_alloc) {
+        p = h->alloc.alloc(h->alloc.ctx, bytes, nullptr);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) h->blocks.push_back(p);
+    return p;
+}
+
+void free_device(hylu_handle h)
+{
+    for (auto& kv : h->refac_graphs) { hipGraphExecDestroy(kv.second.exec); hipGraphDestroy(kv.second.graph); }
+    for (auto& kv : h->solve_graphs) { hipGraphExecDestroy(kv.second.exec); hipGraphDestroy(kv.second.graph); }
+    h->refac_graphs.clear();
+    h->solve_graphs.clear();
+    if (!h->blocks.empty()) hipDeviceSynchronize();
+    for (void* p : h->blocks) {
+        if (h->has_alloc) h->alloc.free(h->alloc.ctx, p, nullptr);
+        else hipFree(p);
+    }
+    h->blocks.clear();
+    h->vals = nullptr;
+    h->ws_nrhs = 0;
+    h->tlists = false;
+    h->uploaded = false;
+}
+
+template <typename T>
+hylu_status upload(hylu_handle h, T*& dst, const std::vector<T>& src)
+{
+    dst = (T*)dalloc(h, sizeof(T) * std::max<size_t>(src.size(), 1));
+    if (!dst) return HYLU_ERR_OOM;
+    if (!src.empty() && hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return HYLU_ERR_DEVICE;
+    return HYLU_OK;
+}
+
+#define UP(dst, src) do { hylu_status s_ = upload(h, dst, src); if (s_ != HYLU_OK) return s_; } while (0)
+
+hylu_status validate_csr(int32_t n, const int64_t* rp, const int32_t* ci, const double* v)
+{
+    if (rp[0] != 0) return HYLU_ERR_CSR;
+    for (int32_t i = 0; i < n; i++) {
+        if (rp[i + 1] < rp[i]) return HYLU_ERR_CSR;
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+            if (ci[p] < 0 || ci[p] >= n) return HYLU_ERR_CSR;
+            if (p > rp[i] && ci[p] <= ci[p - 1]) return HYLU_ERR_CSR;
+            if (!std::isfinite(v[p])) return HYLU_ERR_NONFINITE;
+        }
+    }
+    return HYLU_OK;
+}
+
+// symmetric adjacency of the pattern of M + M^T without the diagonal
+void symmetrize(int32_t n, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
+                std::vector<int64_t>& xadj, std::vector<int32_t>& adj)
+{
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int32_t i = 0; i < n; i++)
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++)
+            if (ci[p] != i) { cnt[i + 1]++; cnt[ci[p] + 1]++; }
+    for (int32_t i = 0; i < n; i++) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> tmp(cnt[n]);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int32_t i = 0; i < n; i++)
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++)
+            if (ci[p] != i) { tmp[fill[i]++] = ci[p]; tmp[fill[ci[p]]++] = i; }
+    xadj.assign(n + 1, 0);
+    adj.clear();
+    adj.reserve(tmp.size());
+    for (int32_t i = 0; i < n; i++) {
+        std::sort(tmp.begin() + cnt[i], tmp.begin() + cnt[i + 1]);
+        int32_t last = -1;
+        for (int64_t p = cnt[i]; p < cnt[i + 1]; p++)
+            if (tmp[p] != last) { adj.push_back(tmp[p]); last = tmp[p]; }
+        xadj[i + 1] = (int64_t)adj.size();
+    }
+}
+
+hylu_status ensure_workspace(hylu_handle h, int32_t nrhs)
+{
+    if (h->ws_nrhs >= nrhs) return HYLU_OK;
+    // captured solves refer to the old workspace
+    for (auto& kv : h->solve_graphs) { hipGraphExecDestroy(kv.second.exec); hipGraphDestroy(kv.second.graph); }
+    h->solve_graphs.clear();
+    size_t es = h->fp32 ? sizeof(float) : sizeof(double);
+    size_t nn = (size_t)h->n * nrhs;
+    h->d_y = dalloc(h, es * nn);
+    h->d_z = dalloc(h, es * nn);
+    h->d_r = (double*)dalloc(h, sizeof(double) * nn);
+    h->d_bc = (double*)dalloc(h, sizeof(double) * nn);
+    h->d_norms = (double*)dalloc(h, sizeof(double) * (4 * (size_t)nrhs + 8));
+    if (!h->d_y || !h->d_z || !h->d_r || !h->d_bc || !h->d_norms) return HYLU_ERR_OOM;
+    if (h->h_norms) hipHostFree(h->h_norms);
+    if (hipHostMalloc((void**)&h->h_norms, sizeof(double) * (4 * (size_t)nrhs + 8)) != hipSuccess) return HYLU_ERR_OOM;
+    h->ws_nrhs = nrhs;
+    return HYLU_OK;
+}
+
+// column lists of the T and L regions for the transposed solves (built on first use)
+hylu_status ensure_tlists(hylu_handle h)
+{
+    if (h->tlists) return HYLU_OK;
+    const Layout& L = h->lay;
+    const int32_t n = h->n;
+    std::vector<int64_t> uptr(n + 1, 0), lptr(n + 1, 0);
+    for (int32_t v = 0; v < L.nnodes; v++) {
+        const int32_t* c = L.cols.data() + L.coff[v];
+        for (int32_t t = 0; t < L.lw[v]; t++) lptr[c[t] + 1] += L.m[v];
+        for (int32_t t = L.lw[v] + L.m[v]; t < L.W[v]; t++) uptr[c[t] + 1] += L.m[v];
+    }
+    for (int32_t i = 0; i < n; i++) { uptr[i + 1] += uptr[i]; lptr[i + 1] += lptr[i]; }
+    std::vector<int64_t> uslot(uptr[n]), lslot(lptr[n]);
+    std::vector<int32_t> urow(uptr[n]), lrow(lptr[n]);
+    std::vector<int64_t> uf(uptr.begin(), uptr.end() - 1), lf(lptr.begin(), lptr.end() - 1);
+    for (int32_t v = 0; v < L.nnodes; v++) {
+        const int32_t* c = L.cols.data() + L.coff[v];
+        for (int32_t b = 0; b < L.m[v]; b++) {
+            int64_t base = L.voff[v] + (int64_t)b * L.W[v];
+            for (int32_t t = 0; t < L.lw[v]; t++) { int64_t q = lf[c[t]]++; lslot[q] = base + t; lrow[q] = L.r0[v] + b; }
+            for (int32_t t = L.lw[v] + L.m[v]; t < L.W[v]; t++) { int64_t q = uf[c[t]]++; uslot[q] = base + t; urow[q] = L.r0[v] + b; }
+        }
+    }
+    int64_t* p1; int64_t* p2; int32_t* p3; int64_t* p4; int64_t* p5; int32_t* p6;
+    UP(p1, uptr); UP(p2, uslot); UP(p3, urow); UP(p4, lptr); UP(p5, lslot); UP(p6, lrow);
+    h->D.ut_ptr = p1; h->D.ut_slot = p2; h->D.ut_row = p3;
+    h->D.lt_ptr = p4; h->D.lt_slot = p5; h->D.lt_row = p6;
+    // A^T for the transposed residual
+    const Csr& A = h->A;
+    std::vector<int64_t> tp(n + 1, 0), tq(A.nnz());
+    std::vector<int32_t> tc(A.nnz());
+    for (int64_t p = 0; p < A.nnz(); p++) tp[A.ci[p] + 1]++;
+    for (int32_t j = 0; j < n; j++) tp[j + 1] += tp[j];
+    std::vector<int64_t> f(tp.begin(), tp.end() - 1);
+    for (int32_t i = 0; i < n; i++)
+        for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++) { int64_t q = f[A.ci[p]]++; tc[q] = i; tq[q] = p; }
+    UP(h->d_atp, tp); UP(h->d_atc, tc); UP(h->d_atq, tq);
+    h->d_atv = (double*)dalloc(h, sizeof(double) * std::max<int64_t>(A.nnz(), 1));
+    if (!h->d_atv) return HYLU_ERR_OOM;
+    h->tlists = true;
+    return HYLU_OK;
+}
+
+// the level loop of the numerical factorisation
+hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipStream_t st)
+{
+    HIPCHK(launch_zero(h->d_pert, sizeof(int32_t), st));
+    HIPCHK(launch_zero(h->vals, h->lay.nvals * (h->fp32 ? 4 : 8), st));
+    HIPCHK(launch_scatter(h->fp32, d_val, h->d_amap, h->d_asr, h->d_asc, h->nnz, h->vals, h->d_aval, st));
+    const LevelTasks& T = h->ft;
+    int32_t nl = (int32_t)T.maxW.size();
+    for (int32_t l = 0; l < nl; l++) {
+        int64_t r0 = T.row_ptr[l], r1 = T.row_ptr[l + 1];
+        HIPCHK(launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.maxW[l], h->tau,
+                                  h->d_pert, st));
+        int64_t s0 = T.sn_ptr[l], s1 = T.sn_ptr[l + 1];
+        if (s1 > s0)
+            HIPCHK(launch_factor_snlu(h->fp32, h->D, h->vals, h->d_snodes + s0, (int32_t)(s1 - s0), T.maxm[l], h->tau,
+                                      h->d_pert, search ? 1 : 0, st));
+    }
+    return HYLU_OK;
+}
+
+// base solve in the factor precision: x = A^{-1} b (transpose 0) or A^{-T} b
+hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x, int64_t ldx, int32_t nrhs,
+                          int32_t transpose, int32_t accumulate, hipStream_t st)
+{
+    const Layout& L = h->lay;
+    const int32_t n = h->n;
+    if (!transpose) {
+        HIPCHK(launch_permute_in(h->fp32, n, nrhs, h->d_perm_r, h->d_dr, b, ldb, h->d_y, st));
+        for (size_t l = 0; l + 1 < L.lev_ptr[0].size(); l++)
+            HIPCHK(launch_lsolve(h->fp32, h->D, h->vals, h->d_lev[0] + L.lev_ptr[0][l],
+                                 (int32_t)(L.lev_ptr[0][l + 1] - L.lev_ptr[0][l]), h->d_y, nrhs, st));
+        for (size_t l = 0; l + 1 < L.lev_ptr[1].size(); l++)
+            HIPCHK(launch_usolve(h->fp32, h->D, h->vals, h->d_lev[1] + L.lev_ptr[1][l],
+                                 (int32_t)(L.lev_ptr[1][l + 1] - L.lev_ptr[1][l]), h->d_y, h->d_z, nrhs, st));
+        HIPCHK(launch_permute_out(h->fp32, n, nrhs, h->d_perm_c, h->d_dc, h->d_z, x, ldx, accumulate, st));
+    } else {
+        HIPCHK(launch_permute_in(h->fp32, n, nrhs, h->d_perm_c, h->d_dc, b, ldb, h->d_y, st));
+        for (size_t l = 0; l + 1 < L.lev_ptr[2].size(); l++)
+            HIPCHK(launch_utsolve(h->fp32, h->D, h->vals, h->d_lev[2] + L.lev_ptr[2][l],
+                                  (int32_t)(L.lev_ptr[2][l + 1] - L.lev_ptr[2][l]), h->d_y, h->d_z, nrhs, st));
+        for (size_t l = 0; l + 1 < L.lev_ptr[3].size(); l++)
+            HIPCHK(launch_ltsolve(h->fp32, h->D, h->vals, h->d_lev[3] + L.lev_ptr[3][l],
+                                  (int32_t)(L.lev_ptr[3][l + 1] - L.lev_ptr[3][l]), h->d_z, nrhs, st));
+        HIPCHK(launch_permute_out(h->fp32, n, nrhs, h->d_perm_r, h->d_dr, h->d_z, x, ldx, accumulate, st));
+    }
+    return HYLU_OK;
+}
+
+hylu_status run_graph(hylu_handle h, GraphEntry& g, bool fresh, hipStream_t st,
+                      const std::function<hylu_status(hipStream_t)>& body)
+{
+    if (fresh) {
+        HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        hylu_status s = body(h->cap_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
+        if (s != HYLU_OK) { if (graph) hipGraphDestroy(graph); return s; }
+        if (e != hipSuccess) { h->sticky_error = true; return HYLU_ERR_DEVICE; }
+        hipGraphExec_t exec = nullptr;
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(graph);
+            h->sticky_error = true;
+            return HYLU_ERR_DEVICE;
+        }
+        g.graph = graph;
+        g.exec = exec;
+    }
+    HIPCHK(hipGraphLaunch(g.exec, st));
+    return HYLU_OK;
+}
+
+// device tables of the layout, uploaded on the first factorisation so the
+// analysis itself needs no GPU
+hylu_status upload_device(hylu_handle h)
+{
+    const Layout& L = h->lay;
+    const Nodes& nd = h->nodes;
+    const Csr& A = h->A;
+    const LevelTasks& T = h->ft;
+    const int32_t n = h->n;
+    try {
+        if (hipGetDevice(&h->device) != hipSuccess) return HYLU_ERR_DEVICE;
+        if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) return HYLU_ERR_DEVICE;
+        if (!h->fact_done && hipEventCreateWithFlags(&h->fact_done, hipEventDisableTiming) != hipSuccess) return HYLU_ERR_DEVICE;
+        if (!h->h_pert && hipHostMalloc((void**)&h->h_pert, sizeof(int32_t)) != hipSuccess) return HYLU_ERR_OOM;
+        std::vector<EdgeDesc> ed(L.esrc.size());
+        for (int32_t v = 0; v < L.nnodes; v++)
+            for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
+                int32_t s = L.esrc[e];
+                EdgeDesc& d = ed[e];
+                d.uoff = L.voff[s] + L.lw[s];
+                d.roff = L.eroff[e];
+                d.Ws = L.W[s];
+                d.ms = L.m[s];
+                d.ws = L.W[s] - L.lw[s] - L.m[s];
+                d.lp = L.elpos[e];
+                d.r0s = L.r0[s];
+                d.pad = 0;
+            }
+        std::vector<double> asr(h->nnz), asc(h->nnz);
+        for (int32_t i = 0; i < n; i++)
+            for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++) { asr[p] = h->dr[i]; asc[p] = h->dc[A.ci[p]]; }
+        DevLayout& D = h->D;
+        D = DevLayout();
+        D.n = n; D.nnodes = L.nnodes;
+        int32_t *r0, *m, *lw, *W, *cols, *rel, *row_node, *pl, *qinv;
+        int64_t *voff, *coff, *eptr;
+        EdgeDesc* edges;
+        UP(r0, L.r0); UP(m, L.m); UP(lw, L.lw); UP(W, L.W); UP(voff, L.voff); UP(coff, L.coff);
+        UP(cols, L.cols); UP(eptr, L.eptr); UP(edges, ed); UP(rel, L.rel); UP(row_node, nd.of_row);
+        std::vector<int32_t> zeros(n, 0);
+        UP(pl, zeros); UP(qinv, zeros);
+        D.r0 = r0; D.m = m; D.lw = lw; D.W = W; D.voff = voff; D.coff = coff; D.cols = cols;
+        D.eptr = eptr; D.edges = edges; D.rel = rel; D.row_node = row_node; D.pl = pl; D.qinv = qinv;
+        UP(h->d_amap, L.amap); UP(h->d_asr, asr); UP(h->d_asc, asc);
+        UP(h->d_rows, T.rows); UP(h->d_snodes, T.snodes);
+        for (int g = 0; g < 4; g++) UP(h->d_lev[g], L.lev_nodes[g]);
+        UP(h->d_perm_r, h->perm_r); UP(h->d_perm_c, h->perm_c);
+        UP(h->d_dr, h->dr); UP(h->d_dc, h->dc);
+        UP(h->d_arp, A.rp); UP(h->d_aci, A.ci); UP(h->d_aval, A.v);
+        int32_t* pert;
+        std::vector<int32_t> one(2, 0);
+        UP(pert, one);
+        h->d_pert = pert;
+        h->vals = dalloc(h, (size_t)std::max<int64_t>(L.nvals, 1) * (h->fp32 ? 4 : 8));
+        if (!h->vals) return HYLU_ERR_OOM;
+        h->uploaded = true;
+    } catch (const std::bad_alloc&) {
+        return HYLU_ERR_OOM;
+    }
+    return HYLU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hylu_status hylu_default_options(hylu_options* o)
+{
+    if (!o) return HYLU_ERR_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->ordering = 0;
+    o->user_perm = nullptr;
+    o->static_pivot = 1;
+    o->precision = 0;
+    o->pivot_tau = 0.0;
+    o->ir_tol = 1e-12;
+    o->ir_maxit = 0;
+    o->sn_min = 2;
+    o->sn_max = 1 << 30;
+    o->kernel_mode = 0;
+    o->repeated = 1;
+    o->nd_leaf = 256;
+    o->amd_dense = 10.0;
+    return HYLU_OK;
+}
+
+const char* hylu_status_string(hylu_status s)
+{
+    switch (s) {
+    case HYLU_OK: return "ok";
+    case HYLU_ERR_ARG: return "invalid argument";
+    case HYLU_ERR_CSR: return "invalid CSR structure";
+    case HYLU_ERR_STRUCT_SINGULAR: return "structurally singular matrix";
+    case HYLU_ERR_NOT_ANALYZED: return "not analyzed";
+    case HYLU_ERR_NOT_FACTORIZED: return "not factorized";
+    case HYLU_ERR_OOM: return "out of memory";
+    case HYLU_ERR_DEVICE: return "device error";
+    case HYLU_ERR_NONFINITE: return "non-finite value";
+    case HYLU_ERR_INTERNAL: return "internal error";
+    case HYLU_WARN_IR_NOT_CONVERGED: return "refinement did not reach the tolerance";
+    }
+    return "unknown status";
+}
+
+hylu_status hylu_create(hylu_handle* out, const hylu_allocator* alloc)
+{
+    if (!out) return HYLU_ERR_ARG;
+    *out = nullptr;
+    hylu_handle h = new (std::nothrow) hylu_handle_s();
+    if (!h) return HYLU_ERR_OOM;
+    if (alloc) {
+        if (!alloc->alloc || !alloc->free) { delete h; return HYLU_ERR_ARG; }
+        h->alloc = *alloc;
+        h->has_alloc = true;
+    }
+    hylu_default_options(&h->opt);
+    *out = h;
+    return HYLU_OK;
+}
+
+hylu_status hylu_destroy(hylu_handle h)
+{
+    if (!h) return HYLU_ERR_ARG;
+    free_device(h);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    if (h->fact_done) hipEventDestroy(h->fact_done);
+    if (h->h_pert) hipHostFree(h->h_pert);
+    if (h->h_norms) hipHostFree(h->h_norms);
+    delete h;
+    return HYLU_OK;
+}
+
+hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const int32_t* col,
+                         const double* val, const hylu_options* opt_in)
+{
+    if (!h || n <= 0 || !row_ptr || !col || !val) return HYLU_ERR_ARG;
+    hylu_options opt;
+    if (opt_in) opt = *opt_in; else hylu_default_options(&opt);
+    if (opt.ordering < 0 || opt.ordering > 3 || (opt.ordering == 3 && !opt.user_perm)) return HYLU_ERR_ARG;
+    if (opt.precision < 0 || opt.precision > 1 || opt.kernel_mode < 0 || opt.kernel_mode > 2) return HYLU_ERR_ARG;
+    hylu_status st = validate_csr(n, row_ptr, col, val);
+    if (st != HYLU_OK) return st;
+    try {
+        free_device(h);
+        h->analyzed = h->factorized = h->uploaded = false;
+        h->sticky_error = false;
+        h->pert_known = false;
+        h->opt = opt;
+        h->n = n;
+        h->nnz = row_ptr[n];
+        h->fp32 = opt.precision == 1;
+        PhaseLog plog;
+        Csr& A = h->A;
+        A.n = n;
+        A.rp.assign(row_ptr, row_ptr + n + 1);
+        A.ci.assign(col, col + h->nnz);
+        A.v.assign(val, val + h->nnz);
+        // ---- static pivoting and scaling (Sec. 2.1)
+        std::vector<int32_t> match(n);
+        h->dr.assign(n, 1.0);
+        h->dc.assign(n, 1.0);
+        if (opt.static_pivot) {
+            if (!mc64_match_scale(A, match, h->dr, h->dc)) return HYLU_ERR_STRUCT_SINGULAR;
+        } else {
+            for (int32_t i = 0; i < n; i++) match[i] = i;
+            // a row or column without entries is singular in any case
+            std::vector<char> rowhas(n, 0), colhas(n, 0);
+            for (int32_t i = 0; i < n; i++)
+                for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++) { rowhas[i] = 1; colhas[A.ci[p]] = 1; }
+            for (int32_t i = 0; i < n; i++) if (!rowhas[i] || !colhas[i]) return HYLU_ERR_STRUCT_SINGULAR;
+        }
+        plog("matching");
+        // ---- fill-reducing ordering on the pattern of B0 + B0^T, B0 = matched A
+        std::vector<int32_t> q(n);
+        if (opt.ordering == 2) {
+            for (int32_t i = 0; i < n; i++) q[i] = i;
+        } else if (opt.ordering == 3) {
+            std::vector<char> seen(n, 0);
+            for (int32_t i = 0; i < n; i++) {
+                int32_t x = opt.user_perm[i];
+                if (x < 0 || x >= n || seen[x]) return HYLU_ERR_ARG;
+                seen[x] = 1;
+                q[i] = x;
+            }
+        } else {
+            std::vector<int64_t> b0p(n + 1, 0);
+            std::vector<int32_t> b0c;
+            b0c.reserve(h->nnz);
+            for (int32_t j = 0; j < n; j++) {
+                int32_t r = match[j];
+                for (int64_t p = A.rp[r]; p < A.rp[r + 1]; p++) b0c.push_back(A.ci[p]);
+                b0p[j + 1] = (int64_t)b0c.size();
+            }
+            std::vector<int64_t> xadj;
+            std::vector<int32_t> adj;
+            symmetrize(n, b0p, b0c, xadj, adj);
+            double ad = opt.amd_dense > 0 ? opt.amd_dense : 10.0;
+            q = opt.ordering == 0 ? amd_order(n, xadj, adj, ad) : nd_order(n, xadj, adj, std::max(opt.nd_leaf, 8), ad);
+            if ((int32_t)q.size() != n) return HYLU_ERR_INTERNAL;
+        }
+        plog("ordering");
+        h->perm_c = q;
+        h->perm_r.resize(n);
+        for (int32_t k = 0; k < n; k++) h->perm_r[k] = match[q[k]];
+        // ---- B = R A C (pattern, sorted) and the source position of each entry
+        std::vector<int32_t> pcinv(n);
+        for (int32_t k = 0; k < n; k++) pcinv[h->perm_c[k]] = k;
+        Csr B;
+        B.n = n;
+        B.rp.assign(n + 1, 0);
+        B.ci.resize(h->nnz);
+        std::vector<int64_t> bsrc(h->nnz);
+        {
+            std::vector<std::pair<int32_t, int64_t>> rowbuf;
+            int64_t q0 = 0;
+            for (int32_t i = 0; i < n; i++) {
+                int32_t r = h->perm_r[i];
+                rowbuf.clear();
+                for (int64_t p = A.rp[r]; p < A.rp[r + 1]; p++) rowbuf.push_back({pcinv[A.ci[p]], p});
+                std::sort(rowbuf.begin(), rowbuf.end());
+                for (auto& e : rowbuf) { B.ci[q0] = e.first; bsrc[q0] = e.second; q0++; }
+                B.rp[i + 1] = q0;
+            }
+        }
+        // ---- symbolic factorisation, flops, supernodes, levels (Sec. 2.1, 2.2, 2.2.1)
+        plog("permute");
+        if (!symbolic_factor(B, h->sym)) return HYLU_ERR_INTERNAL;
+        plog("symbolic");
+        int32_t sn_min = opt.sn_min, sn_max = opt.sn_max;
+        if (opt.kernel_mode == 1) sn_min = std::numeric_limits<int32_t>::max();
+        make_nodes(h->sym, sn_min, sn_max, h->nodes);
+        make_levels(h->sym, h->nodes);
+        plog("nodes");
+        std::string err;
+        if (!build_layout(B, h->sym, h->nodes, h->lay, bsrc, err)) {
+            std::fprintf(stderr, "hylu: %s\n", err.c_str());
+            return HYLU_ERR_INTERNAL;
+        }
+        plog("layout");
+        // ---- perturbation threshold
+        double bmax = 0.0;
+        for (int32_t i = 0; i < n; i++)
+            for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++)
+                bmax = std::max(bmax, std::fabs(h->dr[i] * A.v[p] * h->dc[A.ci[p]]));
+        double eps = h->fp32 ? (double)std::numeric_limits<float>::epsilon() : std::numeric_limits<double>::epsilon();
+        h->tau = (opt.pivot_tau > 0 ? opt.pivot_tau : std::sqrt(eps)) * (bmax > 0 ? bmax : 1.0);
+        // ---- level task lists of the factorisation
+        const Layout& L = h->lay;
+        const Nodes& nd = h->nodes;
+        LevelTasks& T = h->ft;
+        T = LevelTasks();
+        int32_t nl = nd.nlevels[0];
+        T.row_ptr.assign(1, 0); T.sn_ptr.assign(1, 0);
+        h->max_sn = 0;
+        for (int32_t l = 0; l < nl; l++) {
+            int32_t mw = 0, mm = 0;
+            for (int32_t t = L.lev_ptr[0][l]; t < L.lev_ptr[0][l + 1]; t++) {
+                int32_t v = L.lev_nodes[0][t];
+                for (int32_t r = L.r0[v]; r < L.r0[v] + L.m[v]; r++) T.rows.push_back(r);
+                mw = std::max(mw, L.W[v]);
+                if (nd.is_sn[v]) { T.snodes.push_back(v); mm = std::max(mm, L.m[v]); }
+            }
+            T.row_ptr.push_back((int64_t)T.rows.size());
+            T.sn_ptr.push_back((int64_t)T.snodes.size());
+            T.maxW.push_back(mw);
+            T.maxm.push_back(mm);
+            h->max_sn = std::max(h->max_sn, mm);
+        }
+        h->analyzed = true;
+    } catch (const std::bad_alloc&) {
+        return HYLU_ERR_OOM;
+    } catch (...) {
+        return HYLU_ERR_INTERNAL;
+    }
+    return HYLU_OK;
+}
+
+hylu_status hylu_factorize(hylu_handle h, const double* d_val, void* stream)
+{
+    if (!h || !d_val) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    if (h->sticky_error) return HYLU_ERR_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    if (!h->uploaded) {
+        hylu_status su = upload_device(h);
+        if (su != HYLU_OK) { free_device(h); return su; }
+    }
+    HIPCHK(launch_init_pivots(h->D, st));
+    hylu_status s = enqueue_factor(h, d_val, true, st);
+    if (s != HYLU_OK) return s;
+    HIPCHK(hipMemcpyAsync(h->h_pert, h->d_pert, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(h->fact_done, st));
+    h->pert_known = false;
+    h->factorized = true;
+    return HYLU_OK;
+}
+
+hylu_status hylu_refactor(hylu_handle h, const double* d_val, void* stream)
+{
+    if (!h || !d_val) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
+    if (h->sticky_error) return HYLU_ERR_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    auto it = h->refac_graphs.find(d_val);
+    bool fresh = it == h->refac_graphs.end();
+    GraphEntry& g = h->refac_graphs[d_val];
+    hylu_status s = run_graph(h, g, fresh, st, [&](hipStream_t cs) { return enqueue_factor(h, d_val, false, cs); });
+    if (s != HYLU_OK) { if (fresh) h->refac_graphs.erase(d_val); return s; }
+    HIPCHK(hipMemcpyAsync(h->h_pert, h->d_pert, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(h->fact_done, st));
+    h->pert_known = false;
+    return HYLU_OK;
+}
+
+hylu_status hylu_solve(hylu_handle h, const double* d_b, double* d_x, int32_t nrhs, int64_t ld, int32_t transpose,
+                       void* stream)
+{
+    if (!h || !d_b || !d_x || nrhs <= 0) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
+    if (h->sticky_error) return HYLU_ERR_DEVICE;
+    if (ld < h->n) return HYLU_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    hylu_status s = ensure_workspace(h, nrhs);
+    if (s != HYLU_OK) return s;
+    if (transpose) { s = ensure_tlists(h); if (s != HYLU_OK) return s; }
+    const int32_t n = h->n;
+    // does refinement run?  (perturbed pivots, or FP32 factors)
+    if (!h->pert_known) {
+        HIPCHK(hipEventSynchronize(h->fact_done));
+        h->last_pert = *h->h_pert;
+        h->pert_known = true;
+    }
+    bool refine = h->fp32 || h->last_pert > 0;
+    // b is needed after x is written when refining in place
+    const double* b = d_b;
+    bool bcopy = refine && d_b == d_x;
+    if (bcopy) {
+        for (int32_t k = 0; k < nrhs; k++)
+            HIPCHK(hipMemcpyAsync(h->d_bc + (size_t)k * n, d_b + (size_t)k * ld, sizeof(double) * n,
+                                  hipMemcpyDeviceToDevice, st));
+        b = h->d_bc;
+    }
+    int64_t ldb = bcopy ? n : ld;
+    auto key = std::make_tuple(b, d_x, nrhs, ld, transpose);
+    auto it = h->solve_graphs.find(key);
+    bool fresh = it == h->solve_graphs.end();
+    GraphEntry& g = h->solve_graphs[key];
+    s = run_graph(h, g, fresh, st, [&](hipStream_t cs) { return enqueue_solve(h, b, ldb, d_x, ld, nrhs, transpose, 0, cs); });
+    if (s != HYLU_OK) { if (fresh) h->solve_graphs.erase(key); return s; }
+    h->ir_iters = 0;
+    h->berr = 0.0;
+    if (!refine) return HYLU_OK;
+    // FP64 iterative refinement on the original matrix (Sec. 2.3)
+    const double* av = h->d_aval;
+    const int64_t* rp = h->d_arp;
+    const int32_t* ci = h->d_aci;
+    if (transpose) {
+        HIPCHK(launch_gather_values(h->nnz, h->d_atq, av, h->d_atv, st));
+        av = h->d_atv; rp = h->d_atp; ci = h->d_atc;
+    }
+    int32_t maxit = h->opt.ir_maxit > 0 ? h->opt.ir_maxit : (h->fp32 ? 30 : 10);
+    double tol = h->opt.ir_tol > 0 ? h->opt.ir_tol : 1e-12;
+    double eta_prev = std::numeric_limits<double>::infinity();
+    double eta = 0.0;
+    for (int32_t it2 = 0;; it2++) {
+        HIPCHK(launch_residual(n, nrhs, rp, ci, av, b, ldb, d_x, ld, h->d_r, st));
+        HIPCHK(launch_norms(n, nrhs, rp, av, h->d_r, d_x, ld, b, ldb, h->d_norms, st));
+        HIPCHK(hipMemcpyAsync(h->h_norms, h->d_norms, sizeof(double) * (4 * (size_t)nrhs + 1), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        eta = 0.0;
+        double anorm = h->h_norms[4 * nrhs];
+        for (int32_t k = 0; k < nrhs; k++) {
+            double den = anorm * h->h_norms[4 * k + 1] + h->h_norms[4 * k + 2];
+            double e = den > 0 ? h->h_norms[4 * k] / den : 0.0;
+            eta = std::max(eta, e);
+        }
+        if (eta <= tol || it2 >= maxit || eta > eta_prev / 2) break;
+        eta_prev = eta;
+        s = enqueue_solve(h, h->d_r, n, d_x, ld, nrhs, transpose, 1, st);
+        if (s != HYLU_OK) return s;
+        h->ir_iters++;
+    }
+    h->berr = eta;
+    return eta <= tol ? HYLU_OK : HYLU_WARN_IR_NOT_CONVERGED;
+}
+
+hylu_status hylu_grad_values(hylu_handle h, const double* d_lambda, const double* d_x, double* d_gval, void* stream)
+{
+    if (!h || !d_lambda || !d_x || !d_gval) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    if (h->sticky_error) return HYLU_ERR_DEVICE;
+    HIPCHK(launch_grad(h->n, h->d_arp, h->d_aci, d_lambda, d_x, d_gval, (hipStream_t)stream));
+    return HYLU_OK;
+}
+
+hylu_status hylu_get_info(hylu_handle h, hylu_info* o)
+{
+    if (!h || !o) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    std::memset(o, 0, sizeof(*o));
+    o->n = h->n;
+    o->nnz_a = h->nnz;
+    o->nnz_l = h->sym.nnz_l;
+    o->nnz_u = h->sym.nnz_u;
+    o->flops = h->sym.flops;
+    o->flops_padded = h->nodes.flops_padded;
+    o->factor_entries = h->lay.nvals;
+    o->n_nodes = h->nodes.count;
+    for (int32_t v = 0; v < h->nodes.count; v++)
+        if (h->nodes.is_sn[v]) {
+            int32_t m = h->nodes.ptr[v + 1] - h->nodes.ptr[v];
+            o->n_supernodes++;
+            o->rows_in_supernodes += m;
+            o->max_supernode = std::max(o->max_supernode, m);
+        }
+    for (int t = 0; t < 4; t++) o->n_levels[t] = h->nodes.nlevels[t];
+    if (h->factorized) {
+        if (!h->pert_known) {
+            if (hipEventSynchronize(h->fact_done) != hipSuccess) return HYLU_ERR_DEVICE;
+            h->last_pert = *h->h_pert;
+            h->pert_known = true;
+        }
+        o->n_perturbed = h->last_pert;
+    }
+    o->ir_iters = h->ir_iters;
+    o->berr = h->berr;
+    o->pivot_tau = h->tau;
+    return HYLU_OK;
+}
+
+hylu_status hylu_export_symbolic(hylu_handle h, const hylu_symbolic_view* v)
+{
+    if (!h || !v) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    const int32_t n = h->n, nn = h->nodes.count;
+    if (v->perm_r) std::memcpy(v->perm_r, h->perm_r.data(), sizeof(int32_t) * n);
+    if (v->perm_c) std::memcpy(v->perm_c, h->perm_c.data(), sizeof(int32_t) * n);
+    if (v->dr) std::memcpy(v->dr, h->dr.data(), sizeof(double) * n);
+    if (v->dc) std::memcpy(v->dc, h->dc.data(), sizeof(double) * n);
+    if (v->node_ptr) std::memcpy(v->node_ptr, h->nodes.ptr.data(), sizeof(int32_t) * (nn + 1));
+    if (v->is_sn) std::memcpy(v->is_sn, h->nodes.is_sn.data(), nn);
+    if (v->levels)
+        for (int t = 0; t < 4; t++) std::memcpy(v->levels + (size_t)t * nn, h->nodes.level[t].data(), sizeof(int32_t) * nn);
+    return HYLU_OK;
+}
+
+hylu_status hylu_export_sizes(hylu_handle h, int64_t* ncols_total)
+{
+    if (!h || !ncols_total) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    *ncols_total = (int64_t)h->lay.cols.size();
+    return HYLU_OK;
+}
+
+hylu_status hylu_export_factors(hylu_handle h, double* vals, int64_t* node_voff, int32_t* node_lw, int32_t* node_W,
+                                int64_t* node_coff, int32_t* cols, int32_t* piv)
+{
+    if (!h) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
+    const Layout& L = h->lay;
+    if (hipDeviceSynchronize() != hipSuccess) return HYLU_ERR_DEVICE;
+    if (vals) {
+        if (h->fp32) {
+            std::vector<float> tmp(L.nvals);
+            if (hipMemcpy(tmp.data(), h->vals, sizeof(float) * L.nvals, hipMemcpyDeviceToHost) != hipSuccess) return HYLU_ERR_DEVICE;
+            for (int64_t i = 0; i < L.nvals; i++) vals[i] = tmp[i];
+        } else if (hipMemcpy(vals, h->vals, sizeof(double) * L.nvals, hipMemcpyDeviceToHost) != hipSuccess) {
+            return HYLU_ERR_DEVICE;
+        }
+    }
+    if (node_voff) std::memcpy(node_voff, L.voff.data(), sizeof(int64_t) * (L.nnodes + 1));
+    if (node_lw) std::memcpy(node_lw, L.lw.data(), sizeof(int32_t) * L.nnodes);
+    if (node_W) std::memcpy(node_W, L.W.data(), sizeof(int32_t) * L.nnodes);
+    if (node_coff) std::memcpy(node_coff, L.coff.data(), sizeof(int64_t) * (L.nnodes + 1));
+    if (cols) std::memcpy(cols, L.cols.data(), sizeof(int32_t) * L.cols.size());
+    if (piv) {
+        std::vector<int32_t> pl(h->n);
+        if (hipMemcpy(pl.data(), h->D.pl, sizeof(int32_t) * h->n, hipMemcpyDeviceToHost) != hipSuccess) return HYLU_ERR_DEVICE;
+        for (int32_t v = 0; v < L.nnodes; v++)
+            for (int32_t a = 0; a < L.m[v]; a++) piv[L.r0[v] + a] = L.r0[v] + pl[L.r0[v] + a];
+    }
+    return HYLU_OK;
+}
+
+}  // extern "C"

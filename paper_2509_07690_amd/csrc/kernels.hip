@@ -1,0 +1,597 @@
+// gfx950 kernels of HYLU's numerical factorisation (Sec. 2.2) and
+// forward-backward substitution (Sec. 2.3).
+//
+// Storage (per node v with m rows, panel m x W, row-major):
+//   [ L region (lw) | diagonal block (m) | T (W - lw - m) ]
+// The diagonal block keeps its natural column order.  Row a of a supernode
+// pivots on block column pl[r0 + a] (the largest entry of its row in the
+// block, Sec. 2.2); its multiplier for an earlier row b of the same node is
+// stored at the pivot column of b, and its U values at the columns not yet
+// pivoted.  A target's L-region slots for a source node follow the same rule:
+// the multiplier of source row b sits at the slot of b's pivot column.  No
+// column is ever moved, so a level never waits on a permutation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace hylu {
+
+namespace {
+
+template <typename T> __device__ __forceinline__ T tabs(T x) { return x < T(0) ? -x : x; }
+
+// ----------------------------------------------------------------------------
+// value scatter: B = R A C into the panels (fill slots are zero)
+// ----------------------------------------------------------------------------
+
+__global__ void k_zero(uint64_t* __restrict__ p, int64_t n64)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n64; i += stride) p[i] = 0;
+}
+
+__global__ void k_zero_bytes(uint8_t* __restrict__ p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// also keeps a copy of A's values for the FP64 residual of the refinement
+template <typename T>
+__global__ void k_scatter(const double* __restrict__ aval, const int64_t* __restrict__ amap,
+                          const double* __restrict__ asr, const double* __restrict__ asc, int64_t nnz,
+                          T* __restrict__ vals, double* __restrict__ acopy)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz) {
+        double a = aval[p];
+        acopy[p] = a;
+        vals[amap[p]] = (T)((asr[p] * a) * asc[p]);
+    }
+}
+
+__global__ void k_init_pivots(int32_t n, const int32_t* __restrict__ row_node, const int32_t* __restrict__ r0,
+                              int32_t* __restrict__ pl, int32_t* __restrict__ qinv)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        // standalone rows pivot on their own column; supernode rows are set by the block LU
+        (void)row_node; (void)r0;
+        pl[i] = 0;
+        qinv[i] = i;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// row updates: one wavefront per target row.  Every source node (a standalone
+// row: row-row kernel; a supernode: sup-row kernel) is applied in ascending
+// order: the multipliers come from a triangular solve with the source block in
+// its pivot order, then the source's T part is subtracted through the relative
+// map.  The row's accumulator sits in LDS when it fits.
+// ----------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_factor_rows(DevLayout D, T* __restrict__ vals,
+                                                    const int32_t* __restrict__ rows, int32_t nrows,
+                                                    int32_t lds_cap, T tau, int32_t* __restrict__ pert)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* smem = reinterpret_cast<T*>(smem_raw);
+    const int lane = threadIdx.x;
+    const int t = blockIdx.x;
+    if (t >= nrows) return;
+    const int i = rows[t];
+    const int v = D.row_node[i];
+    const int W = D.W[v];
+    const int a = i - D.r0[v];
+    T* X = vals + D.voff[v] + (int64_t)a * W;
+    const bool in_lds = W <= lds_cap;
+    T* xs = in_lds ? smem : X;
+    if (in_lds) {
+        for (int j = lane; j < W; j += 64) xs[j] = X[j];
+    }
+    __syncthreads();
+    const int64_t e0 = D.eptr[v], e1 = D.eptr[v + 1];
+    for (int64_t e = e0; e < e1; e++) {
+        const EdgeDesc ed = D.edges[e];
+        const T* Us = vals + ed.uoff;                 // source row b, block column c at Us[b*Ws + c]
+        const int32_t* pls = D.pl + ed.r0s;
+        const int32_t* rl = D.rel + ed.roff;
+        const int lp = ed.lp, ms = ed.ms, Ws = ed.Ws, ws = ed.ws;
+        // multipliers: triangular solve with the source block in pivot order
+        for (int b = 0; b < ms; b++) {
+            const int pb = pls[b];
+            const T lb = xs[lp + pb] / Us[(int64_t)b * Ws + pb];
+            __syncthreads();
+            if (lane == 0) xs[lp + pb] = lb;
+            for (int bb = b + 1 + lane; bb < ms; bb += 64) {
+                const int pc = pls[bb];
+                xs[lp + pc] -= lb * Us[(int64_t)b * Ws + pc];
+            }
+            __syncthreads();
+        }
+        // update of the columns past the source block
+        for (int j = lane; j < ws; j += 64) {
+            T acc = T(0);
+            for (int b = 0; b < ms; b++) acc += xs[lp + pls[b]] * Us[(int64_t)b * Ws + ms + j];
+            xs[rl[j]] -= acc;
+        }
+        __syncthreads();
+    }
+    if (D.m[v] == 1 && lane == 0) {
+        // standalone row: no pivot search (Sec. 2.2), perturbation only
+        T d = xs[D.lw[v]];
+        if (tabs(d) < tau) {
+            xs[D.lw[v]] = d < T(0) ? -tau : tau;
+            atomicAdd(pert, 1);
+        }
+    }
+    __syncthreads();
+    if (in_lds) {
+        for (int j = lane; j < W; j += 64) X[j] = xs[j];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// internal factorisation of a supernode once every external update is in:
+// dense LU of the m x (m + w) block+T part, row by row, each row pivoting on
+// the largest entry among its block columns not yet taken (ties: lowest
+// column), perturbing small pivots, then eliminating the rows below.
+// ----------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_factor_snlu(DevLayout D, T* __restrict__ vals,
+                                                     const int32_t* __restrict__ nodes, int32_t count,
+                                                     T tau, int32_t* __restrict__ pert, int32_t search)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int v = nodes[blockIdx.x];
+    const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const int wc = W - lw;                     // block + T columns
+    T* P = vals + D.voff[v] + lw;              // row a, column c at P[a*W + c]
+    int32_t* pl = D.pl + r0;
+    T* lrow = reinterpret_cast<T*>(smem_raw);                       // m multipliers
+    uint8_t* taken = smem_raw + sizeof(T) * (size_t)m;             // m flags
+    __shared__ T red_v[256];
+    __shared__ int red_i[256];
+    __shared__ int s_p;
+    const int tid = threadIdx.x;
+    for (int c = tid; c < m; c += 256) taken[c] = 0;
+    __syncthreads();
+    for (int a = 0; a < m; a++) {
+        T* Pa = P + (int64_t)a * W;
+        int p;
+        if (search) {
+            T best = T(-1);
+            int bi = m;
+            for (int c = tid; c < m; c += 256) {
+                if (taken[c]) continue;
+                T x = tabs(Pa[c]);
+                if (x > best || (x == best && c < bi)) { best = x; bi = c; }
+            }
+            red_v[tid] = best; red_i[tid] = bi;
+            __syncthreads();
+            for (int s = 128; s > 0; s >>= 1) {
+                if (tid < s) {
+                    T x = red_v[tid + s]; int xi = red_i[tid + s];
+                    if (x > red_v[tid] || (x == red_v[tid] && xi < red_i[tid])) { red_v[tid] = x; red_i[tid] = xi; }
+                }
+                __syncthreads();
+            }
+            p = red_i[0];
+        } else {
+            p = pl[a];
+        }
+        if (tid == 0) {
+            T d = Pa[p];
+            if (tabs(d) < tau) {
+                Pa[p] = d < T(0) ? -tau : tau;
+                atomicAdd(pert, 1);
+            }
+            pl[a] = p;
+            D.qinv[r0 + p] = r0 + a;
+            taken[p] = 1;
+            s_p = p;
+        }
+        __syncthreads();
+        p = s_p;
+        const T d = Pa[p];
+        for (int r = a + 1 + tid; r < m; r += 256) {
+            T* Pr = P + (int64_t)r * W;
+            T l = Pr[p] / d;
+            Pr[p] = l;
+            lrow[r] = l;
+        }
+        __syncthreads();
+        const int rows_left = m - a - 1;
+        const int64_t total = (int64_t)rows_left * wc;
+        for (int64_t idx = tid; idx < total; idx += 256) {
+            int r = a + 1 + (int)(idx / wc);
+            int c = (int)(idx % wc);
+            if (c < m && taken[c]) continue;
+            P[(int64_t)r * W + c] -= lrow[r] * Pa[c];
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// triangular solves, one wavefront per node of a level
+// ----------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    return __shfl(x, 0, 64);
+}
+
+// forward: y_i = c_i - sum_k L(i,k) y_k (unit L), rows of a node in order
+template <typename T>
+__global__ __launch_bounds__(64) void k_lsolve(DevLayout D, const T* __restrict__ vals,
+                                               const int32_t* __restrict__ nodes, int32_t count,
+                                               T* __restrict__ y, int32_t nrhs)
+{
+    const int v = nodes[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const T* P = vals + D.voff[v];
+    const int32_t* cols = D.cols + D.coff[v];
+    const int32_t* pl = D.pl + r0;
+    const int n = D.n;
+    for (int r = 0; r < nrhs; r++) {
+        T* yr = y + (int64_t)r * n;
+        for (int a = 0; a < m; a++) {
+            const T* Pa = P + (int64_t)a * W;
+            T acc = T(0);
+            for (int t = lane; t < lw; t += 64) acc += Pa[t] * yr[D.qinv[cols[t]]];
+            for (int b = lane; b < a; b += 64) acc += Pa[lw + pl[b]] * yr[r0 + b];
+            acc = wave_sum(acc);
+            if (lane == 0) yr[r0 + a] -= acc;
+            __syncthreads();
+        }
+    }
+}
+
+// backward: x[piv a] = (y_a - sum_{j != piv a} U_st(a,j) x_j) / U_st(a, piv a)
+template <typename T>
+__global__ __launch_bounds__(64) void k_usolve(DevLayout D, const T* __restrict__ vals,
+                                               const int32_t* __restrict__ nodes, int32_t count,
+                                               const T* __restrict__ y, T* __restrict__ x, int32_t nrhs)
+{
+    const int v = nodes[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const int w = W - lw - m;
+    const T* P = vals + D.voff[v] + lw;
+    const int32_t* tc = D.cols + D.coff[v] + lw + m;
+    const int32_t* pl = D.pl + r0;
+    const int n = D.n;
+    for (int r = 0; r < nrhs; r++) {
+        const T* yr = y + (int64_t)r * n;
+        T* xr = x + (int64_t)r * n;
+        for (int a = m - 1; a >= 0; a--) {
+            const T* Pa = P + (int64_t)a * W;
+            T acc = T(0);
+            for (int t = lane; t < w; t += 64) acc += Pa[m + t] * xr[tc[t]];
+            for (int b = a + 1 + lane; b < m; b += 64) { int c = pl[b]; acc += Pa[c] * xr[r0 + c]; }
+            acc = wave_sum(acc);
+            if (lane == 0) { int c = pl[a]; xr[r0 + c] = (yr[r0 + a] - acc) / Pa[c]; }
+            __syncthreads();
+        }
+    }
+}
+
+// U_st^T w = h: w_a = (h[piv a] - sum_{k<a} U_st(k, piv a) w_k) / U_st(a, piv a)
+template <typename T>
+__global__ __launch_bounds__(64) void k_utsolve(DevLayout D, const T* __restrict__ vals,
+                                                const int32_t* __restrict__ nodes, int32_t count,
+                                                const T* __restrict__ h, T* __restrict__ w, int32_t nrhs)
+{
+    const int v = nodes[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const T* P = vals + D.voff[v] + lw;
+    const int32_t* pl = D.pl + r0;
+    const int n = D.n;
+    for (int r = 0; r < nrhs; r++) {
+        const T* hr = h + (int64_t)r * n;
+        T* wr = w + (int64_t)r * n;
+        for (int a = 0; a < m; a++) {
+            const int c = r0 + pl[a];
+            T acc = T(0);
+            for (int64_t q = D.ut_ptr[c] + lane; q < D.ut_ptr[c + 1]; q += 64) acc += vals[D.ut_slot[q]] * wr[D.ut_row[q]];
+            for (int b = lane; b < a; b += 64) acc += P[(int64_t)b * W + pl[a]] * wr[r0 + b];
+            acc = wave_sum(acc);
+            if (lane == 0) wr[r0 + a] = (hr[c] - acc) / P[(int64_t)a * W + pl[a]];
+            __syncthreads();
+        }
+    }
+}
+
+// L^T u = w in place: u_k = w_k - sum_{i>k} L(i,k) u_i, rows of a node in reverse
+template <typename T>
+__global__ __launch_bounds__(64) void k_ltsolve(DevLayout D, const T* __restrict__ vals,
+                                                const int32_t* __restrict__ nodes, int32_t count,
+                                                T* __restrict__ w, int32_t nrhs)
+{
+    const int v = nodes[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const T* P = vals + D.voff[v] + lw;
+    const int32_t* pl = D.pl + r0;
+    const int n = D.n;
+    for (int r = 0; r < nrhs; r++) {
+        T* wr = w + (int64_t)r * n;
+        for (int a = m - 1; a >= 0; a--) {
+            const int c = r0 + pl[a];          // L(i, r0+a) sits at the slot of column c
+            T acc = T(0);
+            for (int64_t q = D.lt_ptr[c] + lane; q < D.lt_ptr[c + 1]; q += 64) acc += vals[D.lt_slot[q]] * wr[D.lt_row[q]];
+            for (int b = a + 1 + lane; b < m; b += 64) acc += P[(int64_t)b * W + pl[a]] * wr[r0 + b];
+            acc = wave_sum(acc);
+            if (lane == 0) wr[r0 + a] -= acc;
+            __syncthreads();
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// permutation / scaling, FP64 residual and norms, gradient
+// ----------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_permute_in(int32_t n, int32_t nrhs, const int32_t* __restrict__ perm,
+                             const double* __restrict__ scale, const double* __restrict__ src, int64_t ld,
+                             T* __restrict__ dst)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * nrhs) return;
+    int r = (int)(idx / n), i = (int)(idx % n);
+    int o = perm[i];
+    dst[idx] = (T)(scale[o] * src[o + (int64_t)r * ld]);
+}
+
+template <typename T>
+__global__ void k_permute_out(int32_t n, int32_t nrhs, const int32_t* __restrict__ perm,
+                              const double* __restrict__ scale, const T* __restrict__ z, double* __restrict__ dst,
+                              int64_t ld, int32_t acc)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * nrhs) return;
+    int r = (int)(idx / n), j = (int)(idx % n);
+    int o = perm[j];
+    double val = scale[o] * (double)z[idx];
+    if (acc) dst[o + (int64_t)r * ld] += val; else dst[o + (int64_t)r * ld] = val;
+}
+
+__global__ void k_residual(int32_t n, int32_t nrhs, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const double* __restrict__ av, const double* __restrict__ b, int64_t ldb,
+                           const double* __restrict__ x, int64_t ldx, double* __restrict__ r)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * nrhs) return;
+    int k = (int)(idx / n), i = (int)(idx % n);
+    const double* xk = x + (int64_t)k * ldx;
+    double s = b[i + (int64_t)k * ldb];
+    for (int64_t p = rp[i]; p < rp[i + 1]; p++) s -= av[p] * xk[ci[p]];
+    r[idx] = s;
+}
+
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v)
+{
+    // non-negative doubles order like their bit patterns
+    atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ void k_norms(int32_t n, int32_t nrhs, const int64_t* __restrict__ rp, const double* __restrict__ av,
+                        const double* __restrict__ r, const double* __restrict__ x, int64_t ldx,
+                        const double* __restrict__ b, int64_t ldb, double* __restrict__ out)
+{
+    __shared__ double sm[4][256];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int k = 0; k <= nrhs; k++) {
+        double m0 = 0, m1 = 0, m2 = 0;
+        if (i < n) {
+            if (k < nrhs) {
+                m0 = fabs(r[i + (int64_t)k * n]);
+                m1 = fabs(x[i + (int64_t)k * ldx]);
+                m2 = fabs(b[i + (int64_t)k * ldb]);
+            } else {
+                for (int64_t p = rp[i]; p < rp[i + 1]; p++) m0 += fabs(av[p]);
+            }
+        }
+        sm[0][threadIdx.x] = m0; sm[1][threadIdx.x] = m1; sm[2][threadIdx.x] = m2;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (threadIdx.x < s)
+                for (int q = 0; q < 3; q++) sm[q][threadIdx.x] = fmax(sm[q][threadIdx.x], sm[q][threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (k < nrhs) {
+                atomic_max_nonneg(out + 4 * k + 0, sm[0][0]);
+                atomic_max_nonneg(out + 4 * k + 1, sm[1][0]);
+                atomic_max_nonneg(out + 4 * k + 2, sm[2][0]);
+            } else {
+                atomic_max_nonneg(out + 4 * nrhs, sm[0][0]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_gather(int64_t nnz, const int64_t* __restrict__ idx, const double* __restrict__ src,
+                         double* __restrict__ dst)
+{
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) dst[q] = src[idx[q]];
+}
+
+__global__ void k_grad(int32_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                       const double* __restrict__ lam, const double* __restrict__ x, double* __restrict__ g)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double li = lam[i];
+    for (int64_t p = rp[i]; p < rp[i + 1]; p++) g[p] = -li * x[ci[p]];
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st)
+{
+    if (bytes <= 0) return hipSuccess;
+    int64_t n64 = bytes / 8;
+    if (n64 > 0) {
+        unsigned g = (unsigned)std::min<int64_t>(nblk(n64, 256), 65536);
+        hipLaunchKernelGGL(k_zero, dim3(g), dim3(256), 0, st, (uint64_t*)p, n64);
+    }
+    int64_t rem = bytes - n64 * 8;
+    if (rem > 0) hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, st, (uint8_t*)p + n64 * 8, rem);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(bool fp32, const double* aval, const int64_t* amap, const double* asr,
+                          const double* asc, int64_t nnz, void* vals, double* acopy, hipStream_t st)
+{
+    if (nnz <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_scatter<float>, dim3(nblk(nnz, 256)), dim3(256), 0, st, aval, amap, asr, asc, nnz, (float*)vals, acopy);
+    else hipLaunchKernelGGL(k_scatter<double>, dim3(nblk(nnz, 256)), dim3(256), 0, st, aval, amap, asr, asc, nnz, (double*)vals, acopy);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_pivots, dim3(nblk(D.n, 256)), dim3(256), 0, st, D.n, D.row_node, D.r0, D.pl, D.qinv);
+    return hipGetLastError();
+}
+
+static const int32_t kRowLdsCap = 4096;   // row accumulator in LDS up to this width
+
+hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t nrows,
+                              int32_t maxW, double tau, int32_t* pert, hipStream_t st)
+{
+    if (nrows <= 0) return hipSuccess;
+    int32_t cap = std::min(maxW, kRowLdsCap);
+    if (fp32) {
+        size_t sh = sizeof(float) * (size_t)std::max(cap, 1);
+        hipLaunchKernelGGL(k_factor_rows<float>, dim3(nrows), dim3(64), sh, st, D, (float*)vals, rows, nrows, cap,
+                           (float)tau, pert);
+    } else {
+        size_t sh = sizeof(double) * (size_t)std::max(cap, 1);
+        hipLaunchKernelGGL(k_factor_rows<double>, dim3(nrows), dim3(64), sh, st, D, (double*)vals, rows, nrows, cap,
+                           tau, pert);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const int32_t* nodes, int32_t count,
+                              int32_t maxm, double tau, int32_t* pert, int32_t search, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    size_t sh = (size_t)maxm * ((fp32 ? sizeof(float) : sizeof(double)) + 1) + 16;
+    if (sh > 60 * 1024) return hipErrorInvalidValue;   // larger blocks need the tiled path
+    if (fp32) hipLaunchKernelGGL(k_factor_snlu<float>, dim3(count), dim3(256), sh, st, D, (float*)vals, nodes, count, (float)tau, pert, search);
+    else hipLaunchKernelGGL(k_factor_snlu<double>, dim3(count), dim3(256), sh, st, D, (double*)vals, nodes, count, tau, pert, search);
+    return hipGetLastError();
+}
+
+hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
+                         void* y, int32_t nrhs, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_lsolve<float>, dim3(count), dim3(64), 0, st, D, (const float*)vals, nodes, count, (float*)y, nrhs);
+    else hipLaunchKernelGGL(k_lsolve<double>, dim3(count), dim3(64), 0, st, D, (const double*)vals, nodes, count, (double*)y, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_usolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
+                         const void* y, void* x, int32_t nrhs, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_usolve<float>, dim3(count), dim3(64), 0, st, D, (const float*)vals, nodes, count, (const float*)y, (float*)x, nrhs);
+    else hipLaunchKernelGGL(k_usolve<double>, dim3(count), dim3(64), 0, st, D, (const double*)vals, nodes, count, (const double*)y, (double*)x, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_utsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
+                          const void* h, void* w, int32_t nrhs, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_utsolve<float>, dim3(count), dim3(64), 0, st, D, (const float*)vals, nodes, count, (const float*)h, (float*)w, nrhs);
+    else hipLaunchKernelGGL(k_utsolve<double>, dim3(count), dim3(64), 0, st, D, (const double*)vals, nodes, count, (const double*)h, (double*)w, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_ltsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
+                          void* w, int32_t nrhs, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_ltsolve<float>, dim3(count), dim3(64), 0, st, D, (const float*)vals, nodes, count, (float*)w, nrhs);
+    else hipLaunchKernelGGL(k_ltsolve<double>, dim3(count), dim3(64), 0, st, D, (const double*)vals, nodes, count, (double*)w, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_in(bool fp32, int32_t n, int32_t nrhs, const int32_t* perm, const double* scale,
+                             const double* src, int64_t ld, void* dst, hipStream_t st)
+{
+    int64_t tot = (int64_t)n * nrhs;
+    if (tot <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_permute_in<float>, dim3(nblk(tot, 256)), dim3(256), 0, st, n, nrhs, perm, scale, src, ld, (float*)dst);
+    else hipLaunchKernelGGL(k_permute_in<double>, dim3(nblk(tot, 256)), dim3(256), 0, st, n, nrhs, perm, scale, src, ld, (double*)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_out(bool fp32, int32_t n, int32_t nrhs, const int32_t* perm, const double* scale,
+                              const void* z, double* dst, int64_t ld, int32_t accumulate, hipStream_t st)
+{
+    int64_t tot = (int64_t)n * nrhs;
+    if (tot <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_permute_out<float>, dim3(nblk(tot, 256)), dim3(256), 0, st, n, nrhs, perm, scale, (const float*)z, dst, ld, accumulate);
+    else hipLaunchKernelGGL(k_permute_out<double>, dim3(nblk(tot, 256)), dim3(256), 0, st, n, nrhs, perm, scale, (const double*)z, dst, ld, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(int32_t n, int32_t nrhs, const int64_t* rp, const int32_t* ci, const double* av,
+                           const double* b, int64_t ldb, const double* x, int64_t ldx, double* r, hipStream_t st)
+{
+    int64_t tot = (int64_t)n * nrhs;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_residual, dim3(nblk(tot, 256)), dim3(256), 0, st, n, nrhs, rp, ci, av, b, ldb, x, ldx, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_norms(int32_t n, int32_t nrhs, const int64_t* rp, const double* av, const double* r,
+                        const double* x, int64_t ldx, const double* b, int64_t ldb, double* out, hipStream_t st)
+{
+    hipError_t e = launch_zero(out, sizeof(double) * (4 * (size_t)nrhs + 1), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_norms, dim3(nblk(n, 256)), dim3(256), 0, st, n, nrhs, rp, av, r, x, ldx, b, ldb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_values(int64_t nnz, const int64_t* idx, const double* src, double* dst, hipStream_t st)
+{
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3(nblk(nnz, 256)), dim3(256), 0, st, nnz, idx, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(int32_t n, const int64_t* rp, const int32_t* ci, const double* lam, const double* x,
+                       double* g, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_grad, dim3(nblk(n, 256)), dim3(256), 0, st, n, rp, ci, lam, x, g);
+    return hipGetLastError();
+}
+
+}  // namespace hylu

@@ -1,0 +1,81 @@
+// Launch interface of the gfx950 kernels (HYLU numerical factorisation and
+// substitution).  All pointers are device pointers; every launcher enqueues on
+// `stream` and returns the hipError_t of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hylu {
+
+// Per-edge descriptor: target node t takes source node s.  Precomputed so a
+// kernel reads one 48-byte record per source instead of chasing node arrays.
+struct EdgeDesc {
+    int64_t uoff;   // value offset of the source's diagonal block (voff[s] + lw[s])
+    int64_t roff;   // offset of the relative map of the source's T into the target
+    int32_t Ws;     // source panel width
+    int32_t ms;     // source rows
+    int32_t ws;     // source T width
+    int32_t lp;     // slot of the source's first column in the target's L region
+    int32_t r0s;    // first row of the source (pivot table offset)
+    int32_t pad;
+};
+
+// Device view of the panel layout.
+struct DevLayout {
+    int32_t n, nnodes;
+    const int32_t* r0;
+    const int32_t* m;
+    const int32_t* lw;
+    const int32_t* W;
+    const int64_t* voff;
+    const int64_t* coff;
+    const int32_t* cols;
+    const int64_t* eptr;
+    const EdgeDesc* edges;
+    const int32_t* rel;
+    const int32_t* row_node;
+    int32_t* pl;            // per row: natural local block column of its pivot
+    int32_t* qinv;          // per column: row whose pivot is this column
+    // column lists for the transposed solves: entries of other nodes' panels
+    const int64_t* ut_ptr;  // per column (n+1): T-region entries in that column
+    const int64_t* ut_slot;
+    const int32_t* ut_row;
+    const int64_t* lt_ptr;  // per column (n+1): L-region entries in that column
+    const int64_t* lt_slot;
+    const int32_t* lt_row;
+};
+
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+hipError_t launch_scatter(bool fp32, const double* aval, const int64_t* amap, const double* asr,
+                          const double* asc, int64_t nnz, void* vals, double* acopy, hipStream_t st);
+hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st);
+hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t nrows,
+                              int32_t maxW, double tau, int32_t* pert, hipStream_t st);
+hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const int32_t* nodes, int32_t count,
+                              int32_t maxm, double tau, int32_t* pert, int32_t search, hipStream_t st);
+hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
+                         void* y, int32_t nrhs, hipStream_t st);
+hipError_t launch_usolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
+                         const void* y, void* x, int32_t nrhs, hipStream_t st);
+hipError_t launch_utsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
+                          const void* h, void* w, int32_t nrhs, hipStream_t st);
+hipError_t launch_ltsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
+                          void* w, int32_t nrhs, hipStream_t st);
+// c[i + r n] = scale[perm[i]] * src[perm[i] + r ld]  (gather, into the factor precision)
+hipError_t launch_permute_in(bool fp32, int32_t n, int32_t nrhs, const int32_t* perm, const double* scale,
+                             const double* src, int64_t ld, void* dst, hipStream_t st);
+// dst[perm[j] + r ld] (+)= scale[perm[j]] * z[j + r n]  (scatter from the factor precision)
+hipError_t launch_permute_out(bool fp32, int32_t n, int32_t nrhs, const int32_t* perm, const double* scale,
+                              const void* z, double* dst, int64_t ld, int32_t accumulate, hipStream_t st);
+// r = b - op(A) x (FP64), op = A (CSR) or A^T (via the column copy)
+hipError_t launch_residual(int32_t n, int32_t nrhs, const int64_t* rp, const int32_t* ci, const double* av,
+                           const double* b, int64_t ldb, const double* x, int64_t ldx, double* r, hipStream_t st);
+// per-RHS maxima: out[4 r + 0] = max|r|, +1 max|x|, +2 max|b|; out[4 nrhs] = max row abs sum of A
+hipError_t launch_norms(int32_t n, int32_t nrhs, const int64_t* rp, const double* av, const double* r,
+                        const double* x, int64_t ldx, const double* b, int64_t ldb, double* out, hipStream_t st);
+hipError_t launch_gather_values(int64_t nnz, const int64_t* idx, const double* src, double* dst, hipStream_t st);
+hipError_t launch_grad(int32_t n, const int64_t* rp, const int32_t* ci, const double* lam, const double* x,
+                       double* g, hipStream_t st);
+
+}  // namespace hylu

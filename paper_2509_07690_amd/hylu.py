@@ -1,0 +1,275 @@
+"""Python binding of libhylu.so (HYLU numerical factorisation on MI355X).
+
+Argument marshalling only: every step of the factorisation and substitution
+runs in the library's gfx950 kernels.  PyTorch supplies device memory and the
+current stream.  If the library was not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhylu.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2509_07690_amd.build_lib` "
+                      "or __graft_entry__.build() (there is no CPU fallback)")
+
+_lib = C.CDLL(LIB_PATH)
+
+OK = 0
+WARN_IR_NOT_CONVERGED = 1
+
+
+class Options(C.Structure):
+    _fields_ = [("ordering", C.c_int32), ("user_perm", C.c_void_p), ("static_pivot", C.c_int32),
+                ("precision", C.c_int32), ("pivot_tau", C.c_double), ("ir_tol", C.c_double),
+                ("ir_maxit", C.c_int32), ("sn_min", C.c_int32), ("sn_max", C.c_int32),
+                ("kernel_mode", C.c_int32), ("repeated", C.c_int32), ("nd_leaf", C.c_int32),
+                ("amd_dense", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz_a", C.c_int64), ("nnz_l", C.c_int64), ("nnz_u", C.c_int64),
+                ("flops", C.c_uint64), ("flops_padded", C.c_uint64), ("factor_entries", C.c_int64),
+                ("n_nodes", C.c_int32), ("n_supernodes", C.c_int32), ("rows_in_supernodes", C.c_int32),
+                ("max_supernode", C.c_int32), ("n_levels", C.c_int32 * 4), ("n_perturbed", C.c_int32),
+                ("ir_iters", C.c_int32), ("berr", C.c_double), ("pivot_tau", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["n_levels"] = list(self.n_levels)
+        return d
+
+
+class SymbolicView(C.Structure):
+    _fields_ = [("perm_r", C.c_void_p), ("perm_c", C.c_void_p), ("dr", C.c_void_p), ("dc", C.c_void_p),
+                ("node_ptr", C.c_void_p), ("is_sn", C.c_void_p), ("levels", C.c_void_p)]
+
+
+_P = C.c_void_p
+_sigs = {
+    "hylu_default_options": [_P],
+    "hylu_status_string": [C.c_int],
+    "hylu_create": [_P, _P],
+    "hylu_destroy": [_P],
+    "hylu_analyze": [_P, C.c_int32, _P, _P, _P, _P],
+    "hylu_factorize": [_P, _P, _P],
+    "hylu_refactor": [_P, _P, _P],
+    "hylu_solve": [_P, _P, _P, C.c_int32, C.c_int64, C.c_int32, _P],
+    "hylu_grad_values": [_P, _P, _P, _P, _P],
+    "hylu_get_info": [_P, _P],
+    "hylu_export_symbolic": [_P, _P],
+    "hylu_export_factors": [_P, _P, _P, _P, _P, _P, _P, _P],
+    "hylu_export_sizes": [_P, _P],
+}
+for _name, _args in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.hylu_status_string.restype = C.c_char_p
+
+EXPORTED = tuple(_sigs)
+
+
+class HyluError(RuntimeError):
+    def __init__(self, code, what):
+        msg = _lib.hylu_status_string(code).decode()
+        super().__init__(f"{what}: {msg} ({code})")
+        self.code = code
+
+
+def _chk(rc, what, allow_warn=False):
+    if rc == OK or (allow_warn and rc == WARN_IR_NOT_CONVERGED):
+        return rc
+    raise HyluError(rc, what)
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"expected a contiguous {dtype} CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+ORDERINGS = {"amd": 0, "nd": 1, "natural": 2, "user": 3}
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    _chk(_lib.hylu_default_options(C.byref(o)), "default_options")
+    for k, v in kw.items():
+        if k == "ordering" and isinstance(v, str):
+            v = ORDERINGS[v]
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": 0, "fp32": 1}[v]
+        setattr(o, k, v)
+    return o
+
+
+class Handle:
+    """One sparsity pattern: analyze once, factorize / refactor / solve many times.
+
+    row_ptr, col, val are host arrays (CSR, 0-based, sorted unique columns).
+    Keyword options follow hylu_options (ordering="amd"|"nd"|"natural"|"user",
+    precision="fp64"|"fp32", static_pivot, sn_min, sn_max, kernel_mode, ...).
+    """
+
+    def __init__(self, row_ptr, col, val, user_perm=None, **opts):
+        self.h = C.c_void_p()
+        _chk(_lib.hylu_create(C.byref(self.h), None), "create")
+        rp = _np(row_ptr, np.int64)
+        ci = _np(col, np.int32)
+        va = _np(val, np.float64)
+        self.n = rp.size - 1
+        self.nnz = int(rp[-1])
+        self._perm = None
+        if user_perm is not None:
+            self._perm = _np(user_perm, np.int32)
+            opts["ordering"] = 3
+            opts["user_perm"] = self._perm.ctypes.data
+        self.opts = default_options(**opts)
+        _chk(_lib.hylu_analyze(self.h, self.n, _ptr(rp), _ptr(ci), _ptr(va), C.byref(self.opts)), "analyze")
+        self.row_ptr, self.col = rp, ci
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            _lib.hylu_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- numerical phases (device tensors) --------------------------------
+    def factorize(self, values, stream=None):
+        import torch
+        _chk(_lib.hylu_factorize(self.h, _dev_ptr(values, torch.float64), _stream(stream)), "factorize")
+
+    def refactor(self, values, stream=None):
+        import torch
+        _chk(_lib.hylu_refactor(self.h, _dev_ptr(values, torch.float64), _stream(stream)), "refactor")
+
+    def solve(self, b, out=None, transpose=False, stream=None):
+        """b: (n,) or (n, k) float64 CUDA tensor (column-major for k > 1 means
+        b.t().contiguous() layout; pass a tensor of shape (k, n) via solve_cols)."""
+        import torch
+        if b.dim() == 1:
+            x = torch.empty_like(b) if out is None else out
+            rc = _lib.hylu_solve(self.h, _dev_ptr(b, torch.float64), _dev_ptr(x, torch.float64), 1, self.n,
+                                 1 if transpose else 0, _stream(stream))
+            _chk(rc, "solve", allow_warn=True)
+            return x
+        return self.solve_cols(b.t().contiguous(), transpose=transpose, stream=stream).t()
+
+    def solve_cols(self, bt, out=None, transpose=False, stream=None):
+        """bt: (k, n) float64 CUDA tensor, i.e. k right-hand sides stored
+        column-major as the C ABI expects; returns (k, n)."""
+        import torch
+        k, n = bt.shape
+        assert n == self.n
+        x = torch.empty_like(bt) if out is None else out
+        rc = _lib.hylu_solve(self.h, _dev_ptr(bt, torch.float64), _dev_ptr(x, torch.float64), k, n,
+                             1 if transpose else 0, _stream(stream))
+        _chk(rc, "solve", allow_warn=True)
+        return x
+
+    def grad_values(self, lam, x, out=None, stream=None):
+        import torch
+        g = torch.empty(self.nnz, dtype=torch.float64, device=lam.device) if out is None else out
+        _chk(_lib.hylu_grad_values(self.h, _dev_ptr(lam, torch.float64), _dev_ptr(x, torch.float64),
+                                   _dev_ptr(g, torch.float64), _stream(stream)), "grad_values")
+        return g
+
+    # ---- inspection -------------------------------------------------------
+    def info(self) -> dict:
+        inf = Info()
+        _chk(_lib.hylu_get_info(self.h, C.byref(inf)), "get_info")
+        return inf.as_dict()
+
+    def symbolic(self) -> dict:
+        inf = self.info()
+        n, nn = self.n, inf["n_nodes"]
+        out = {"perm_r": np.empty(n, np.int32), "perm_c": np.empty(n, np.int32), "dr": np.empty(n),
+               "dc": np.empty(n), "node_ptr": np.empty(nn + 1, np.int32), "is_sn": np.empty(nn, np.uint8),
+               "levels": np.empty(4 * nn, np.int32)}
+        v = SymbolicView(*[C.c_void_p(out[k].ctypes.data) for k in
+                           ("perm_r", "perm_c", "dr", "dc", "node_ptr", "is_sn", "levels")])
+        _chk(_lib.hylu_export_symbolic(self.h, C.byref(v)), "export_symbolic")
+        out["levels"] = out["levels"].reshape(4, nn)
+        return out
+
+    def factors_raw(self) -> dict:
+        inf = self.info()
+        nn = inf["n_nodes"]
+        nc = C.c_int64()
+        _chk(_lib.hylu_export_sizes(self.h, C.byref(nc)), "export_sizes")
+        out = {"vals": np.empty(inf["factor_entries"]), "voff": np.empty(nn + 1, np.int64),
+               "lw": np.empty(nn, np.int32), "W": np.empty(nn, np.int32), "coff": np.empty(nn + 1, np.int64),
+               "cols": np.empty(nc.value, np.int32), "piv": np.empty(self.n, np.int32)}
+        _chk(_lib.hylu_export_factors(self.h, *[C.c_void_p(out[k].ctypes.data) for k in
+                                                 ("vals", "voff", "lw", "W", "coff", "cols", "piv")]),
+             "export_factors")
+        return out
+
+
+def factors_as_rows(h: Handle):
+    """Panel export converted to the oracle's row conventions.
+
+    Returns (L, U, piv) where L = (Lrow, Lkey, Lval) lists every stored
+    multiplier with its row i and source row k (padding included), U = (Urow,
+    Ucol, Uval) every stored entry of U_st (B = L * U_st) with its row and
+    column, and piv[i] is the column of row i's pivot.
+    """
+    raw = h.factors_raw()
+    sym = h.symbolic()
+    ptr = sym["node_ptr"].astype(np.int64)
+    piv = raw["piv"].astype(np.int64)
+    n = h.n
+    qinv = np.empty(n, np.int64)
+    qinv[piv] = np.arange(n)
+    m = np.diff(ptr)
+    lw = raw["lw"].astype(np.int64)
+    W = raw["W"].astype(np.int64)
+    nn = m.size
+    # per stored value: node, row within node, position within row
+    sizes = m * W
+    node_of_val = np.repeat(np.arange(nn), sizes)
+    off = raw["voff"][:-1].astype(np.int64)
+    local = np.arange(raw["vals"].size, dtype=np.int64) - off[node_of_val]
+    Wv = W[node_of_val]
+    a = local // Wv
+    t = local % Wv
+    row = ptr[node_of_val] + a
+    col = raw["cols"][raw["coff"][:-1][node_of_val] + t].astype(np.int64)
+    lwv = lw[node_of_val]
+    mv = m[node_of_val]
+    in_L = t < lwv
+    in_B = (t >= lwv) & (t < lwv + mv)
+    # a block column belongs to L for row i if an earlier row of the node pivoted on it
+    pivot_row = qinv[col]                     # row whose pivot is this column (block columns)
+    block_L = in_B & (pivot_row < row)
+    is_L = in_L | block_L
+    Lrow, Lkey, Lval = row[is_L], qinv[col[is_L]], raw["vals"][is_L]
+    Urow, Ucol, Uval = row[~is_L], col[~is_L], raw["vals"][~is_L]
+    return (Lrow, Lkey, Lval), (Urow, Ucol, Uval), piv

@@ -1,0 +1,173 @@
+"""HIP path against the CPU oracle, through the C ABI (needs an MI355X).
+
+Tolerances: FP64 factors within 1e-11 of the oracle (normwise, relative to the
+largest entry); solutions within 1e-10 normwise relative difference; backward
+error at most 1e-12 (FP64 and FP32 with refinement); integer factors bit-exact.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2509_07690_amd import synth  # noqa: E402
+from parity import oracle_for, compare_factors, rel_diff  # noqa: E402
+
+TAU64 = np.sqrt(np.finfo(np.float64).eps)
+
+
+@pytest.fixture(scope="module")
+def hylu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_07690_amd import hylu as H
+    return H
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def run_case(hylu, A, b, opts=None, sn=(2, 1 << 30), exact=False, tol=1e-11):
+    opts = dict(opts or {})
+    print(f"[case] n={A.n} nnz={A.nnz} opts={opts}", flush=True)
+    h = hylu.Handle(A.row_ptr, A.col, A.val, **opts)
+    o, sym = oracle_for(h, A, *sn)
+    vals = dev(A.val)
+    h.factorize(vals)
+    torch.cuda.synchronize()
+    o.numeric(h.info()["pivot_tau"])
+    assert h.info()["n_perturbed"] == o.sizes()["n_perturbed"]
+    compare_factors(h, o, tol=tol, exact=exact)
+    x = h.solve(dev(b)).cpu().numpy()
+    xo = o.solve(b)
+    eta, _ = o.backward_error(b, x)
+    return h, o, x, xo, eta
+
+
+def test_random_small(hylu):
+    for seed in range(4):
+        rng = np.random.default_rng(seed)
+        n = 300
+        M = rng.random((n, n)) < 0.015
+        np.fill_diagonal(M, True)
+        D = np.where(M, rng.standard_normal((n, n)), 0.0)
+        A = synth.csr_from_dense(D)
+        b = rng.standard_normal(n)
+        h, o, x, xo, eta = run_case(hylu, A, b)
+        assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
+
+
+def test_dense_block_pivoting(hylu):
+    rng = np.random.default_rng(11)
+    n = 70
+    D = rng.standard_normal((n, n))
+    A = synth.csr_from_dense(D)
+    b = rng.standard_normal(n)
+    h, o, x, xo, eta = run_case(hylu, A, b, opts=dict(static_pivot=0, ordering="natural"))
+    assert h.info()["max_supernode"] == n
+    assert not np.array_equal(h.symbolic()["perm_r"], None)
+    assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
+
+
+def _integer_case(n, density, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.random((n, n)) < density
+    np.fill_diagonal(M, True)
+    # close the structure (dense boolean elimination)
+    for k in range(n):
+        rows = np.nonzero(M[k + 1:, k])[0] + k + 1
+        if rows.size:
+            M[np.ix_(rows, np.arange(k + 1, n))] |= M[k, k + 1:]
+    L = np.where(np.tril(M, -1), rng.choice([-2, -1, 1, 2], (n, n)), 0).astype(np.int64) + np.eye(n, dtype=np.int64)
+    U = np.where(np.triu(M, 1), rng.integers(-3, 4, (n, n)), 0).astype(np.int64)
+    U[np.arange(n), np.arange(n)] = rng.choice([-1, 1], n) * 2 ** rng.integers(2, 5, n)
+    Aint = L @ U
+    r, c = np.nonzero(M)
+    return synth.csr_from_coo(n, r, c, Aint[r, c].astype(np.float64)), L, U
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_integer_factors_bit_exact(hylu, seed):
+    A, L, U = _integer_case([40, 90, 150][seed], [0.1, 0.04, 0.02][seed], 700 + seed)
+    b = np.arange(A.n, dtype=np.float64)
+    h, o, x, xo, eta = run_case(hylu, A, b, opts=dict(static_pivot=0, ordering="natural"), exact=True)
+
+
+@pytest.mark.parametrize("ordering", ["amd", "nd"])
+def test_config0_factor_solve(hylu, ordering):
+    w = synth.config(0)
+    h, o, x, xo, eta = run_case(hylu, w.A, w.b[:, 0], opts=dict(ordering=ordering))
+    assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
+    assert np.abs(x - w.x_true[:, 0]).max() < 1e-10
+
+
+def test_config0_refactor_and_transpose(hylu):
+    w = synth.config(0)
+    A = w.A
+    h = hylu.Handle(A.row_ptr, A.col, A.val)
+    o, sym = oracle_for(h, A)
+    h.factorize(dev(A.val))
+    torch.cuda.synchronize()
+    piv = hylu.factors_as_rows(h)[2]
+    for seed in (5, 6):
+        A2 = synth.grid_values(A, seed, 4.0)
+        v2 = dev(A2.val)
+        h.refactor(v2)
+        torch.cuda.synchronize()
+        o.set_values(A2.val)
+        o.numeric(h.info()["pivot_tau"], piv=piv)
+        compare_factors(h, o)
+        b = A2.matvec(w.x_true[:, 0])
+        x = h.solve(dev(b)).cpu().numpy()
+        assert rel_diff(x, o.solve(b)) <= 1e-10 and o.backward_error(b, x)[0] <= 1e-12
+        g = np.random.default_rng(seed).uniform(-1, 1, A.n)
+        lam = h.solve(dev(g), transpose=True).cpu().numpy()
+        lo = o.solve_transposed(g)
+        assert rel_diff(lam, lo) <= 1e-10
+
+
+def test_multiple_rhs(hylu):
+    w = synth.config(0)
+    A = w.A
+    h = hylu.Handle(A.row_ptr, A.col, A.val)
+    o, _ = oracle_for(h, A)
+    h.factorize(dev(A.val))
+    o.numeric(h.info()["pivot_tau"])
+    B = np.random.default_rng(3).uniform(-1, 1, (A.n, 5))
+    X = h.solve_cols(dev(B.T.copy())).cpu().numpy().T
+    for k in range(5):
+        assert rel_diff(X[:, k], o.solve(B[:, k])) <= 1e-10
+
+
+def test_fp32_with_refinement(hylu):
+    w = synth.config(0)
+    A = w.A
+    h = hylu.Handle(A.row_ptr, A.col, A.val, precision="fp32")
+    o, _ = oracle_for(h, A)
+    h.factorize(dev(A.val))
+    o.numeric(TAU64)
+    b = w.b[:, 0]
+    x = h.solve(dev(b)).cpu().numpy()
+    eta, _ = o.backward_error(b, x)
+    inf = h.info()
+    print("fp32+IR iterations", inf["ir_iters"], "eta", eta, "diff", rel_diff(x, o.solve(b)))
+    assert eta <= 1e-12 and rel_diff(x, o.solve(b)) <= 1e-10 and inf["ir_iters"] >= 1
+
+
+def test_perturbation_triggers_refinement(hylu):
+    A = synth.csr_from_dense(np.array([[0.0, 1.0], [1.0, 1.0]]))
+    h = hylu.Handle(A.row_ptr, A.col, A.val, static_pivot=0, ordering="natural", sn_min=3)
+    h.factorize(dev(A.val))
+    b = np.array([1.0, 3.0])
+    x = h.solve(dev(b)).cpu().numpy()
+    inf = h.info()
+    assert inf["n_perturbed"] == 1 and inf["ir_iters"] >= 1
+    np.testing.assert_allclose(x, [2.0, 1.0], rtol=1e-12)
+
+
+@pytest.mark.parametrize("m", [0, 1])
+def test_batch_members(hylu, m):
+    w = synth.batch_member(m)
+    h, o, x, xo, eta = run_case(hylu, w.A, w.b[:, 0])
+    assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
