@@ -68,6 +68,9 @@ typedef struct {
     int32_t repeated;      /* reserved: the relative-index maps are always precomputed */
     int32_t nd_leaf;       /* nested dissection: parts up to this size are ordered by AMD (default 256) */
     double amd_dense;      /* AMD: rows with more than max(16, amd_dense*sqrt(n)) entries are ordered last */
+    double dense_tail;     /* factor the trailing block of at least this density densely (0: never; default 0.5) */
+    int32_t tail_min;      /* smallest dense tail in rows (default 64) */
+    int32_t tail_max;      /* largest dense tail in rows (default 32768) */
 } hylu_options;
 
 /* Optional device allocator (e.g. the PyTorch caching allocator).  alloc
@@ -90,6 +93,9 @@ typedef struct {
     int32_t ir_iters;                 /* refinement steps of the last solve */
     double berr;                      /* normwise backward error of the last solve (if refined) */
     double pivot_tau;                 /* absolute perturbation threshold used */
+    int32_t tail_rows;                /* rows of the dense tail (0: none) */
+    int32_t tail_panels;              /* row panels of the dense tail */
+    uint64_t flops_issued;            /* flops the kernels issue (padding, dense tail included) */
 } hylu_info;
 
 /* Analysis export for checking: every array is host memory the caller

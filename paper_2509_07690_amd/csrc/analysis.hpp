@@ -93,12 +93,27 @@ struct Layout {
     std::vector<int32_t> rel;           // relative positions, concatenated
     // value map: entry q of B (CSR order of A) lands in slot amap[p]
     std::vector<int64_t> amap;          // per A entry p -> value slot
-    // level lists (node ids sorted by level, then index) for the 4 graphs
-    std::vector<int32_t> lev_ptr[4], lev_nodes[4];
-    uint64_t flops_kernel = 0;          // multiply-adds actually issued by the kernels (x2) + divisions
+    // dense tail: rows [t0, n) factored as one dense block (same factors: the
+    // padding stays exactly zero and each row still pivots inside its node)
+    int32_t tail_node0 = 0, t0 = 0, mT = 0;
+    std::vector<int32_t> lext;          // per node: width of the L part from sources outside the tail
+    std::vector<int64_t> trow;          // per tail row: value offset of its dense part (column t0)
+    std::vector<int32_t> tlo, thi;      // per tail row: tail-local block range of its node
+    struct Panel { int32_t p0, p1, c0, c1, cg0; };
+    std::vector<Panel> panels;          // row panels of the dense tail LU
+    // execution level lists (node ids by level, then index):
+    // 0 factor updates (every node; tail nodes take their outside sources only)
+    // 1 U solve, 2 U^T solve, 3 L^T solve, 4 L solve (nodes before the tail)
+    std::vector<int32_t> xlev_ptr[5], xlev_nodes[5];
+    uint64_t flops_kernel = 0;          // flops the kernels issue (padding and dense tail included)
 };
 
-bool build_layout(const Csr& b, const Symbolic& s, const Nodes& nd, Layout& L,
-                  const std::vector<int64_t>& bsrc, std::string& err);
+// First node of the dense tail: the smallest node start t such that the exact
+// factors restricted to rows and columns [t, n) have at least `density` of
+// their entries nonzero (and at least min_rows rows); nd.count if none.
+int32_t choose_tail(const Symbolic& s, const Nodes& nd, double density, int32_t min_rows, int32_t max_rows);
+
+bool build_layout(const Csr& b, const Symbolic& s, const Nodes& nd, int32_t tail_node0, int32_t panel_rows,
+                  Layout& L, const std::vector<int64_t>& bsrc, std::string& err);
 
 }  // namespace hylu

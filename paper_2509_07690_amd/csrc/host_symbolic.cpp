@@ -222,48 +222,82 @@ void make_levels(const Symbolic& s, Nodes& nd)
     }
 }
 
-bool build_layout(const Csr& b, const Symbolic& s, const Nodes& nd, Layout& L,
-                  const std::vector<int64_t>& bsrc, std::string& err)
+int32_t choose_tail(const Symbolic& s, const Nodes& nd, double density, int32_t min_rows, int32_t max_rows)
+{
+    const int32_t n = s.n;
+    if (density <= 0.0 || n == 0) return nd.count;
+    // entries of L and U with min(row, col) = t
+    std::vector<int64_t> diff(n + 1, 0);
+    for (int64_t t = 0; t < s.lp[n]; t++) { diff[s.lint[2 * t]]++; diff[s.lint[2 * t + 1] + 1]--; }
+    std::vector<double> cnt(n);
+    int64_t acc = 0;
+    for (int32_t k = 0; k < n; k++) { acc += diff[k]; cnt[k] = (double)acc + 1.0 + (double)s.ucount[k]; }
+    double suf = 0.0;
+    int32_t best = n;
+    for (int32_t t = n - 1; t >= 0; t--) {
+        suf += cnt[t];
+        double m = (double)(n - t);
+        if (n - t > max_rows) break;
+        if (suf >= density * m * m && n - t >= min_rows) best = t;
+    }
+    if (best >= n) return nd.count;
+    return nd.of_row[best];
+}
+
+bool build_layout(const Csr& b, const Symbolic& s, const Nodes& nd, int32_t tail_node0, int32_t panel_rows,
+                  Layout& L, const std::vector<int64_t>& bsrc, std::string& err)
 {
     const int32_t n = s.n, nn = nd.count;
     L = Layout();
     L.n = n; L.nnodes = nn;
-    L.r0.resize(nn); L.m.resize(nn); L.lw.resize(nn); L.W.resize(nn);
+    L.tail_node0 = tail_node0;
+    L.t0 = tail_node0 < nn ? nd.ptr[tail_node0] : n;
+    L.mT = n - L.t0;
+    const int32_t t0 = L.t0;
+    L.r0.resize(nn); L.m.resize(nn); L.lw.resize(nn); L.W.resize(nn); L.lext.resize(nn);
     L.voff.resize(nn + 1); L.coff.resize(nn + 1);
     L.eptr.assign(nn + 1, 0);
-    std::vector<int32_t> stamp(nn, -1), srcs, lcols;
-    std::vector<int32_t> pos_of;      // scratch: column -> position in the current node (via stamp)
+    std::vector<int32_t> stamp(nn, -1), srcs;
     std::vector<int32_t> colstamp(n, -1), colpos(n, 0);
+    std::vector<int32_t> flev(nn, 0);
     int64_t voff = 0;
     for (int32_t v = 0; v < nn; v++) {
+        const bool tail = v >= tail_node0;
         int32_t v0 = nd.ptr[v], v1 = nd.ptr[v + 1], m = v1 - v0;
         // source nodes: union over the node's rows of the nodes covering L(i,:)
+        // (for a tail node only those before the tail: the rest is dense)
         srcs.clear();
         for (int32_t i = v0; i < v1; i++)
             for (int64_t t = s.lp[i]; t < s.lp[i + 1]; t++) {
                 int32_t lo = s.lint[2 * t], hi = s.lint[2 * t + 1];
                 for (int32_t u = nd.of_row[lo]; u <= nd.of_row[hi]; u++) {
-                    if (u == v || stamp[u] == v) continue;
-                    if (!nd.is_sn[u] && !(nd.ptr[u] >= lo && nd.ptr[u] <= hi)) continue;
+                    if (u == v || stamp[u] == v || (tail && u >= tail_node0)) continue;
                     stamp[u] = v;
                     srcs.push_back(u);
                 }
             }
         std::sort(srcs.begin(), srcs.end());
-        // column list: source rows | block | columns past the block
+        // column list: source rows | block | columns past the block; a tail node
+        // lists its outside sources, then every column of the tail
         L.coff[v] = (int64_t)L.cols.size();
         for (int32_t u : srcs)
             for (int32_t k = nd.ptr[u]; k < nd.ptr[u + 1]; k++) L.cols.push_back(k);
-        int32_t lw = (int32_t)(L.cols.size() - L.coff[v]);
-        for (int32_t k = v0; k < v1; k++) L.cols.push_back(k);
-        const int32_t* up; int64_t ul;
-        row_upper(s, v1 - 1, up, ul);
-        for (int64_t t = 0; t < ul; t++) L.cols.push_back(up[t]);
+        int32_t lext = (int32_t)(L.cols.size() - L.coff[v]);
+        int32_t lw;
+        if (tail) {
+            for (int32_t k = t0; k < n; k++) L.cols.push_back(k);
+            lw = lext + (v0 - t0);
+        } else {
+            lw = lext;
+            for (int32_t k = v0; k < v1; k++) L.cols.push_back(k);
+            const int32_t* up; int64_t ul;
+            row_upper(s, v1 - 1, up, ul);
+            for (int64_t t = 0; t < ul; t++) L.cols.push_back(up[t]);
+        }
         int32_t W = (int32_t)(L.cols.size() - L.coff[v]);
-        L.r0[v] = v0; L.m[v] = m; L.lw[v] = lw; L.W[v] = W;
+        L.r0[v] = v0; L.m[v] = m; L.lw[v] = lw; L.W[v] = W; L.lext[v] = lext;
         L.voff[v] = voff;
         voff += (int64_t)m * W;
-        // positions of the node's columns
         for (int32_t t = 0; t < W; t++) { int32_t c = L.cols[L.coff[v] + t]; colstamp[c] = v; colpos[c] = t; }
         // edges with relative maps of the source's T into this node
         int32_t lpos = 0;
@@ -279,20 +313,19 @@ bool build_layout(const Csr& b, const Symbolic& s, const Nodes& nd, Layout& L,
                 int32_t c = uu[t];
                 if (colstamp[c] != v) { err = "layout: source column outside target structure"; return false; }
                 L.rel.push_back(colpos[c]);
-                L.flops_kernel += 2 * (uint64_t)m * mu;
             }
-            L.flops_kernel += (uint64_t)m * mu * mu;    // the triangular solve with the source block
+            L.flops_kernel += (uint64_t)m * mu * (mu + 2 * (uint64_t)uul);
+            flev[v] = std::max(flev[v], flev[u] + 1);
         }
         L.eptr[v + 1] = (int64_t)L.esrc.size();
-        if (nd.is_sn[v]) L.flops_kernel += (uint64_t)m * m * (uint64_t)(m + W - lw) ;
+        if (nd.is_sn[v] && !tail) L.flops_kernel += (uint64_t)m * m * (uint64_t)(2 * (W - lw) - m);
         // value map for B's entries of these rows
+        if (L.amap.empty()) L.amap.assign(bsrc.size(), -1);
         for (int32_t i = v0; i < v1; i++)
             for (int64_t q = b.rp[i]; q < b.rp[i + 1]; q++) {
                 int32_t c = b.ci[q];
                 if (colstamp[c] != v) { err = "layout: entry of B outside the structure"; return false; }
-                int64_t slot = L.voff[v] + (int64_t)(i - v0) * W + colpos[c];
-                if (L.amap.empty()) L.amap.assign(bsrc.size(), -1);
-                L.amap[bsrc[q]] = slot;
+                L.amap[bsrc[q]] = L.voff[v] + (int64_t)(i - v0) * W + colpos[c];
             }
     }
     L.voff[nn] = voff;
@@ -305,19 +338,79 @@ bool build_layout(const Csr& b, const Symbolic& s, const Nodes& nd, Layout& L,
         for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
             int32_t s2 = L.esrc[e];
             int32_t ws2 = L.W[s2] - L.lw[s2] - L.m[s2];
-            if (L.elpos[e] + L.m[s2] > L.lw[v]) { err = "layout: source block outside the L region"; return false; }
+            if (L.elpos[e] + L.m[s2] > L.lext[v]) { err = "layout: source block outside the L region"; return false; }
             for (int32_t t = 0; t < ws2; t++)
                 if (L.rel[L.eroff[e] + t] < 0 || L.rel[L.eroff[e] + t] >= L.W[v]) { err = "layout: relative index out of range"; return false; }
         }
-    // level lists
-    for (int g = 0; g < 4; g++) {
-        int32_t nl = nd.nlevels[g];
-        L.lev_ptr[g].assign(nl + 1, 0);
-        for (int32_t v = 0; v < nn; v++) L.lev_ptr[g][nd.level[g][v] + 1]++;
-        for (int32_t l = 0; l < nl; l++) L.lev_ptr[g][l + 1] += L.lev_ptr[g][l];
-        L.lev_nodes[g].resize(nn);
-        std::vector<int32_t> fill(L.lev_ptr[g].begin(), L.lev_ptr[g].end() - 1);
-        for (int32_t v = 0; v < nn; v++) L.lev_nodes[g][fill[nd.level[g][v]]++] = v;
+    // ---- dense tail tables
+    const int32_t mT = L.mT;
+    if (mT > 0) {
+        L.trow.resize(mT); L.tlo.resize(mT); L.thi.resize(mT);
+        for (int32_t v = tail_node0; v < nn; v++)
+            for (int32_t a = 0; a < L.m[v]; a++) {
+                int32_t r = L.r0[v] + a - t0;
+                L.trow[r] = L.voff[v] + (int64_t)a * L.W[v] + L.lext[v];
+                L.tlo[r] = L.r0[v] - t0;
+                L.thi[r] = L.r0[v] + L.m[v] - t0;
+            }
+        // panels: whole nodes up to panel_rows rows; a larger node is cut into
+        // chunks that share its block as pivot window
+        int32_t NB = std::max(panel_rows, 1);
+        int32_t cp0 = -1, cp1 = -1;
+        auto flush = [&]() { if (cp0 >= 0) L.panels.push_back({cp0, cp1, cp0, cp1, cp1}); cp0 = cp1 = -1; };
+        for (int32_t v = tail_node0; v < nn; v++) {
+            int32_t a0 = L.r0[v] - t0, m = L.m[v];
+            if (m > NB) {
+                flush();
+                for (int32_t k = 0; k < m; k += NB)
+                    L.panels.push_back({a0 + k, std::min(a0 + k + NB, a0 + m), a0, a0 + m, a0});
+            } else {
+                if (cp0 >= 0 && cp1 - cp0 + m > NB) flush();
+                if (cp0 < 0) cp0 = a0;
+                cp1 = a0 + m;
+            }
+        }
+        flush();
+        L.flops_kernel += (uint64_t)(2.0 * (double)mT * mT * mT / 3.0);
+    }
+    // ---- execution level lists
+    std::vector<int32_t> lv[5];
+    for (int g = 0; g < 5; g++) lv[g].assign(nn, -1);
+    for (int32_t v = 0; v < nn; v++) lv[0][v] = flev[v];
+    for (int32_t v = 0; v < tail_node0; v++) lv[4][v] = flev[v];
+    // backward solve: the tail is solved first, so only nodes before it order the rest
+    for (int32_t v = tail_node0 - 1; v >= 0; v--) {
+        int32_t l = 0;
+        const int32_t* tc = L.cols.data() + L.coff[v] + L.lw[v] + L.m[v];
+        for (int32_t t = 0; t < L.W[v] - L.lw[v] - L.m[v]; t++) {
+            int32_t u = nd.of_row[tc[t]];
+            if (u < tail_node0) l = std::max(l, lv[1][u] + 1);
+        }
+        lv[1][v] = l;
+    }
+    for (int32_t v = 0; v < tail_node0; v++) lv[2][v] = std::max(lv[2][v], 0);
+    for (int32_t v = 0; v < tail_node0; v++) {
+        const int32_t* tc = L.cols.data() + L.coff[v] + L.lw[v] + L.m[v];
+        for (int32_t t = 0; t < L.W[v] - L.lw[v] - L.m[v]; t++) {
+            int32_t u = nd.of_row[tc[t]];
+            if (u < tail_node0) lv[2][u] = std::max(lv[2][u], lv[2][v] + 1);
+        }
+    }
+    for (int32_t v = 0; v < tail_node0; v++) lv[3][v] = std::max(lv[3][v], 0);
+    for (int32_t v = tail_node0 - 1; v >= 0; v--)
+        for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
+            int32_t u = L.esrc[e];
+            lv[3][u] = std::max(lv[3][u], lv[3][v] + 1);
+        }
+    for (int g = 0; g < 5; g++) {
+        int32_t nl = 0;
+        for (int32_t v = 0; v < nn; v++) nl = std::max(nl, lv[g][v] + 1);
+        L.xlev_ptr[g].assign(nl + 1, 0);
+        for (int32_t v = 0; v < nn; v++) if (lv[g][v] >= 0) L.xlev_ptr[g][lv[g][v] + 1]++;
+        for (int32_t l = 0; l < nl; l++) L.xlev_ptr[g][l + 1] += L.xlev_ptr[g][l];
+        L.xlev_nodes[g].resize(L.xlev_ptr[g][nl]);
+        std::vector<int32_t> fill(L.xlev_ptr[g].begin(), L.xlev_ptr[g].end() - 1);
+        for (int32_t v = 0; v < nn; v++) if (lv[g][v] >= 0) L.xlev_nodes[g][fill[lv[g][v]]++] = v;
     }
     return true;
 }

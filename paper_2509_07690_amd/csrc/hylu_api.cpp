@@ -69,7 +69,8 @@ struct hylu_handle_s {
     int64_t* d_amap = nullptr;
     double *d_asr = nullptr, *d_asc = nullptr;
     int32_t *d_rows = nullptr, *d_snodes = nullptr;
-    int32_t* d_lev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t* d_lev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    TailView TV{};
     int32_t *d_perm_r = nullptr, *d_perm_c = nullptr;
     double *d_dr = nullptr, *d_dc = nullptr;
     int64_t* d_arp = nullptr;
@@ -225,10 +226,13 @@ hylu_status ensure_tlists(hylu_handle h)
     const Layout& L = h->lay;
     const int32_t n = h->n;
     std::vector<int64_t> uptr(n + 1, 0), lptr(n + 1, 0);
+    // entries of the dense tail are handled by the tail kernels
+    auto lend = [&](int32_t v) { return v >= L.tail_node0 ? L.lext[v] : L.lw[v]; };
+    auto ubeg = [&](int32_t v) { return v >= L.tail_node0 ? L.W[v] : L.lw[v] + L.m[v]; };
     for (int32_t v = 0; v < L.nnodes; v++) {
         const int32_t* c = L.cols.data() + L.coff[v];
-        for (int32_t t = 0; t < L.lw[v]; t++) lptr[c[t] + 1] += L.m[v];
-        for (int32_t t = L.lw[v] + L.m[v]; t < L.W[v]; t++) uptr[c[t] + 1] += L.m[v];
+        for (int32_t t = 0; t < lend(v); t++) lptr[c[t] + 1] += L.m[v];
+        for (int32_t t = ubeg(v); t < L.W[v]; t++) uptr[c[t] + 1] += L.m[v];
     }
     for (int32_t i = 0; i < n; i++) { uptr[i + 1] += uptr[i]; lptr[i + 1] += lptr[i]; }
     std::vector<int64_t> uslot(uptr[n]), lslot(lptr[n]);
@@ -238,8 +242,8 @@ hylu_status ensure_tlists(hylu_handle h)
         const int32_t* c = L.cols.data() + L.coff[v];
         for (int32_t b = 0; b < L.m[v]; b++) {
             int64_t base = L.voff[v] + (int64_t)b * L.W[v];
-            for (int32_t t = 0; t < L.lw[v]; t++) { int64_t q = lf[c[t]]++; lslot[q] = base + t; lrow[q] = L.r0[v] + b; }
-            for (int32_t t = L.lw[v] + L.m[v]; t < L.W[v]; t++) { int64_t q = uf[c[t]]++; uslot[q] = base + t; urow[q] = L.r0[v] + b; }
+            for (int32_t t = 0; t < lend(v); t++) { int64_t q = lf[c[t]]++; lslot[q] = base + t; lrow[q] = L.r0[v] + b; }
+            for (int32_t t = ubeg(v); t < L.W[v]; t++) { int64_t q = uf[c[t]]++; uslot[q] = base + t; urow[q] = L.r0[v] + b; }
         }
     }
     int64_t* p1; int64_t* p2; int32_t* p3; int64_t* p4; int64_t* p5; int32_t* p6;
@@ -268,6 +272,7 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
     HIPCHK(launch_zero(h->d_pert, sizeof(int32_t), st));
     HIPCHK(launch_zero(h->vals, h->lay.nvals * (h->fp32 ? 4 : 8), st));
     HIPCHK(launch_scatter(h->fp32, d_val, h->d_amap, h->d_asr, h->d_asc, h->nnz, h->vals, h->d_aval, st));
+    if (search) HIPCHK(launch_tail_init(h->TV, st));
     const LevelTasks& T = h->ft;
     int32_t nl = (int32_t)T.maxW.size();
     for (int32_t l = 0; l < nl; l++) {
@@ -279,6 +284,13 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
             HIPCHK(launch_factor_snlu(h->fp32, h->D, h->vals, h->d_snodes + s0, (int32_t)(s1 - s0), T.maxm[l], h->tau,
                                       h->d_pert, search ? 1 : 0, st));
     }
+    // dense tail: blocked right-looking LU, one row panel at a time
+    for (const Layout::Panel& P : h->lay.panels) {
+        HIPCHK(launch_tail_panel(h->fp32, h->D, h->TV, h->vals, P.p0, P.p1, P.c0, P.c1, h->tau, h->d_pert,
+                                 search ? 1 : 0, st));
+        HIPCHK(launch_tail_trsm(h->fp32, h->TV, h->vals, P.p0, P.p1, P.c1, st));
+        HIPCHK(launch_tail_gemm(h->fp32, h->TV, h->vals, P.p0, P.p1, P.cg0, st));
+    }
     return HYLU_OK;
 }
 
@@ -288,24 +300,41 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
 {
     const Layout& L = h->lay;
     const int32_t n = h->n;
+    const bool f = h->fp32;
+    auto levels = [&](int g, auto&& fn) -> hylu_status {
+        for (size_t l = 0; l + 1 < L.xlev_ptr[g].size(); l++) {
+            int32_t a = L.xlev_ptr[g][l], c = L.xlev_ptr[g][l + 1] - a;
+            if (c > 0) HIPCHK(fn(h->d_lev[g] + a, c));
+        }
+        return HYLU_OK;
+    };
+    hylu_status s;
     if (!transpose) {
-        HIPCHK(launch_permute_in(h->fp32, n, nrhs, h->d_perm_r, h->d_dr, b, ldb, h->d_y, st));
-        for (size_t l = 0; l + 1 < L.lev_ptr[0].size(); l++)
-            HIPCHK(launch_lsolve(h->fp32, h->D, h->vals, h->d_lev[0] + L.lev_ptr[0][l],
-                                 (int32_t)(L.lev_ptr[0][l + 1] - L.lev_ptr[0][l]), h->d_y, nrhs, st));
-        for (size_t l = 0; l + 1 < L.lev_ptr[1].size(); l++)
-            HIPCHK(launch_usolve(h->fp32, h->D, h->vals, h->d_lev[1] + L.lev_ptr[1][l],
-                                 (int32_t)(L.lev_ptr[1][l + 1] - L.lev_ptr[1][l]), h->d_y, h->d_z, nrhs, st));
-        HIPCHK(launch_permute_out(h->fp32, n, nrhs, h->d_perm_c, h->d_dc, h->d_z, x, ldx, accumulate, st));
+        HIPCHK(launch_permute_in(f, n, nrhs, h->d_perm_r, h->d_dr, b, ldb, h->d_y, st));
+        s = levels(4, [&](const int32_t* nodes, int32_t c) { return launch_lsolve(f, h->D, h->vals, nodes, c, h->d_y, nrhs, st); });
+        if (s != HYLU_OK) return s;
+        if (L.mT > 0) {
+            HIPCHK(launch_tail_lext(f, h->D, h->vals, L.tail_node0, L.t0, h->d_y, nrhs, st));
+            for (const Layout::Panel& P : L.panels) HIPCHK(launch_tail_fwd(f, h->TV, h->vals, P.p0, P.p1, n, h->d_y, nrhs, st));
+            for (size_t k = L.panels.size(); k-- > 0;)
+                HIPCHK(launch_tail_bwd(f, h->TV, h->vals, L.panels[k].p0, L.panels[k].p1, n, h->d_y, h->d_z, nrhs, st));
+        }
+        s = levels(1, [&](const int32_t* nodes, int32_t c) { return launch_usolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, st); });
+        if (s != HYLU_OK) return s;
+        HIPCHK(launch_permute_out(f, n, nrhs, h->d_perm_c, h->d_dc, h->d_z, x, ldx, accumulate, st));
     } else {
-        HIPCHK(launch_permute_in(h->fp32, n, nrhs, h->d_perm_c, h->d_dc, b, ldb, h->d_y, st));
-        for (size_t l = 0; l + 1 < L.lev_ptr[2].size(); l++)
-            HIPCHK(launch_utsolve(h->fp32, h->D, h->vals, h->d_lev[2] + L.lev_ptr[2][l],
-                                  (int32_t)(L.lev_ptr[2][l + 1] - L.lev_ptr[2][l]), h->d_y, h->d_z, nrhs, st));
-        for (size_t l = 0; l + 1 < L.lev_ptr[3].size(); l++)
-            HIPCHK(launch_ltsolve(h->fp32, h->D, h->vals, h->d_lev[3] + L.lev_ptr[3][l],
-                                  (int32_t)(L.lev_ptr[3][l + 1] - L.lev_ptr[3][l]), h->d_z, nrhs, st));
-        HIPCHK(launch_permute_out(h->fp32, n, nrhs, h->d_perm_r, h->d_dr, h->d_z, x, ldx, accumulate, st));
+        HIPCHK(launch_permute_in(f, n, nrhs, h->d_perm_c, h->d_dc, b, ldb, h->d_y, st));
+        s = levels(2, [&](const int32_t* nodes, int32_t c) { return launch_utsolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, st); });
+        if (s != HYLU_OK) return s;
+        if (L.mT > 0) {
+            HIPCHK(launch_tail_utext(f, h->D, h->TV, h->vals, h->d_y, h->d_z, nrhs, st));
+            for (const Layout::Panel& P : L.panels) HIPCHK(launch_tail_ut(f, h->TV, h->vals, P.p0, P.p1, n, h->d_y, h->d_z, nrhs, st));
+            for (size_t k = L.panels.size(); k-- > 0;)
+                HIPCHK(launch_tail_lt(f, h->TV, h->vals, L.panels[k].p0, L.panels[k].p1, n, h->d_z, nrhs, st));
+        }
+        s = levels(3, [&](const int32_t* nodes, int32_t c) { return launch_ltsolve(f, h->D, h->vals, nodes, c, h->d_z, nrhs, st); });
+        if (s != HYLU_OK) return s;
+        HIPCHK(launch_permute_out(f, n, nrhs, h->d_perm_r, h->d_dr, h->d_z, x, ldx, accumulate, st));
     }
     return HYLU_OK;
 }
@@ -366,7 +395,7 @@ hylu_status upload_device(hylu_handle h)
             for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++) { asr[p] = h->dr[i]; asc[p] = h->dc[A.ci[p]]; }
         DevLayout& D = h->D;
         D = DevLayout();
-        D.n = n; D.nnodes = L.nnodes;
+        D.n = n; D.nnodes = L.nnodes; D.tail_node0 = L.tail_node0;
         int32_t *r0, *m, *lw, *W, *cols, *rel, *row_node, *pl, *qinv;
         int64_t *voff, *coff, *eptr;
         EdgeDesc* edges;
@@ -378,7 +407,16 @@ hylu_status upload_device(hylu_handle h)
         D.eptr = eptr; D.edges = edges; D.rel = rel; D.row_node = row_node; D.pl = pl; D.qinv = qinv;
         UP(h->d_amap, L.amap); UP(h->d_asr, asr); UP(h->d_asc, asc);
         UP(h->d_rows, T.rows); UP(h->d_snodes, T.snodes);
-        for (int g = 0; g < 4; g++) UP(h->d_lev[g], L.lev_nodes[g]);
+        for (int g = 0; g < 5; g++) UP(h->d_lev[g], L.xlev_nodes[g]);
+        {
+            TailView& TVw = h->TV;
+            TVw = TailView();
+            TVw.mT = L.mT; TVw.t0 = L.t0;
+            int64_t* trow; int32_t *tlo, *thi, *tpiv, *tstep;
+            std::vector<int32_t> zt(std::max(L.mT, 1), 0);
+            UP(trow, L.trow); UP(tlo, L.tlo); UP(thi, L.thi); UP(tpiv, zt); UP(tstep, zt);
+            TVw.trow = trow; TVw.tlo = tlo; TVw.thi = thi; TVw.tpiv = tpiv; TVw.tstep = tstep;
+        }
         UP(h->d_perm_r, h->perm_r); UP(h->d_perm_c, h->perm_c);
         UP(h->d_dr, h->dr); UP(h->d_dc, h->dc);
         UP(h->d_arp, A.rp); UP(h->d_aci, A.ci); UP(h->d_aval, A.v);
@@ -416,6 +454,9 @@ hylu_status hylu_default_options(hylu_options* o)
     o->repeated = 1;
     o->nd_leaf = 256;
     o->amd_dense = 10.0;
+    o->dense_tail = 0.5;
+    o->tail_min = 64;
+    o->tail_max = 32768;
     return HYLU_OK;
 }
 
@@ -567,7 +608,9 @@ hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const
         make_levels(h->sym, h->nodes);
         plog("nodes");
         std::string err;
-        if (!build_layout(B, h->sym, h->nodes, h->lay, bsrc, err)) {
+        int32_t tail_node0 = choose_tail(h->sym, h->nodes, opt.dense_tail, std::max(opt.tail_min, 1),
+                                         opt.tail_max > 0 ? opt.tail_max : 32768);
+        if (!build_layout(B, h->sym, h->nodes, tail_node0, 64, h->lay, bsrc, err)) {
             std::fprintf(stderr, "hylu: %s\n", err.c_str());
             return HYLU_ERR_INTERNAL;
         }
@@ -584,16 +627,16 @@ hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const
         const Nodes& nd = h->nodes;
         LevelTasks& T = h->ft;
         T = LevelTasks();
-        int32_t nl = nd.nlevels[0];
+        int32_t nl = (int32_t)L.xlev_ptr[0].size() - 1;
         T.row_ptr.assign(1, 0); T.sn_ptr.assign(1, 0);
         h->max_sn = 0;
         for (int32_t l = 0; l < nl; l++) {
             int32_t mw = 0, mm = 0;
-            for (int32_t t = L.lev_ptr[0][l]; t < L.lev_ptr[0][l + 1]; t++) {
-                int32_t v = L.lev_nodes[0][t];
+            for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) {
+                int32_t v = L.xlev_nodes[0][t];
                 for (int32_t r = L.r0[v]; r < L.r0[v] + L.m[v]; r++) T.rows.push_back(r);
                 mw = std::max(mw, L.W[v]);
-                if (nd.is_sn[v]) { T.snodes.push_back(v); mm = std::max(mm, L.m[v]); }
+                if (nd.is_sn[v] && v < L.tail_node0) { T.snodes.push_back(v); mm = std::max(mm, L.m[v]); }
             }
             T.row_ptr.push_back((int64_t)T.rows.size());
             T.sn_ptr.push_back((int64_t)T.snodes.size());
@@ -601,6 +644,7 @@ hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const
             T.maxm.push_back(mm);
             h->max_sn = std::max(h->max_sn, mm);
         }
+        plog("tasks");
         h->analyzed = true;
     } catch (const std::bad_alloc&) {
         return HYLU_ERR_OOM;
@@ -762,6 +806,9 @@ hylu_status hylu_get_info(hylu_handle h, hylu_info* o)
     o->ir_iters = h->ir_iters;
     o->berr = h->berr;
     o->pivot_tau = h->tau;
+    o->tail_rows = h->lay.mT;
+    o->tail_panels = (int32_t)h->lay.panels.size();
+    o->flops_issued = h->lay.flops_kernel;
     return HYLU_OK;
 }
 

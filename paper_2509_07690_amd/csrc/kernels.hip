@@ -122,7 +122,7 @@ __global__ __launch_bounds__(64) void k_factor_rows(DevLayout D, T* __restrict__
         }
         __syncthreads();
     }
-    if (D.m[v] == 1 && lane == 0) {
+    if (D.m[v] == 1 && v < D.tail_node0 && lane == 0) {
         // standalone row: no pivot search (Sec. 2.2), perturbation only
         T d = xs[D.lw[v]];
         if (tabs(d) < tau) {
@@ -440,6 +440,320 @@ __global__ void k_grad(int32_t n, const int64_t* __restrict__ rp, const int32_t*
     for (int64_t p = rp[i]; p < rp[i + 1]; p++) g[p] = -li * x[ci[p]];
 }
 
+// ----------------------------------------------------------------------------
+// dense tail: blocked right-looking LU of the trailing block [t0, n) with the
+// same pivot rule (each row searches only its own node's block columns, a
+// standalone row keeps its diagonal).  A column c is still unpivoted at row a
+// iff tstep[c] > a.  Per row panel [p0, p1):
+//   k_tail_panel: the panel rows on their pivot window [c0, c1) (one block);
+//   k_tail_trsm:  the panel rows' U right of the window (column-parallel)
+//                 and the trailing rows' multipliers (row-parallel);
+//   k_tail_gemm:  the trailing update of every still-unpivoted column.
+// ----------------------------------------------------------------------------
+
+constexpr int kNB = 64;   // panel rows
+
+__global__ void k_tail_init(int32_t mT, int32_t* __restrict__ tstep)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < mT) tstep[c] = 0x7fffffff;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tail_panel(DevLayout D, TailView TV, T* __restrict__ vals, int p0, int p1,
+                                                    int c0, int c1, T tau, int32_t* __restrict__ pert, int search)
+{
+    __shared__ T lrow[kNB];
+    __shared__ T red_v[256];
+    __shared__ int red_i[256];
+    __shared__ int s_p;
+    const int tid = threadIdx.x;
+    const int wc = c1 - c0;
+    for (int a = p0; a < p1; a++) {
+        T* Xa = vals + TV.trow[a];
+        const int lo = TV.tlo[a], hi = TV.thi[a];
+        int p;
+        if (!search) {
+            p = TV.tpiv[a];
+        } else if (hi - lo == 1) {
+            p = a;
+        } else {
+            T best = T(-1);
+            int bi = hi;
+            for (int c = lo + tid; c < hi; c += 256) {
+                if (TV.tstep[c] <= a) continue;
+                T x = tabs(Xa[c]);
+                if (x > best || (x == best && c < bi)) { best = x; bi = c; }
+            }
+            red_v[tid] = best; red_i[tid] = bi;
+            __syncthreads();
+            for (int s = 128; s > 0; s >>= 1) {
+                if (tid < s) {
+                    T x = red_v[tid + s]; int xi = red_i[tid + s];
+                    if (x > red_v[tid] || (x == red_v[tid] && xi < red_i[tid])) { red_v[tid] = x; red_i[tid] = xi; }
+                }
+                __syncthreads();
+            }
+            p = red_i[0];
+        }
+        if (tid == 0) {
+            T d = Xa[p];
+            if (tabs(d) < tau) {
+                Xa[p] = d < T(0) ? -tau : tau;
+                atomicAdd(pert, 1);
+            }
+            TV.tpiv[a] = p;
+            TV.tstep[p] = a;
+            D.pl[TV.t0 + a] = p - lo;
+            D.qinv[TV.t0 + p] = TV.t0 + a;
+            s_p = p;
+        }
+        __syncthreads();
+        p = s_p;
+        const T d = Xa[p];
+        for (int r = a + 1 + tid; r < p1; r += 256) {
+            T* Xr = vals + TV.trow[r];
+            T l = Xr[p] / d;
+            Xr[p] = l;
+            lrow[r - p0] = l;
+        }
+        __syncthreads();
+        const int rows_left = p1 - a - 1;
+        for (int idx = tid; idx < rows_left * wc; idx += 256) {
+            int r = a + 1 + idx / wc;
+            int c = c0 + idx % wc;
+            if (TV.tstep[c] <= a) continue;
+            vals[TV.trow[r] + c] -= lrow[r - p0] * Xa[c];
+        }
+        __syncthreads();
+    }
+}
+
+// blocks [0, nA): panel rows' U for columns >= c1 (one thread per column);
+// blocks [nA, ...): trailing rows' multipliers (one thread per row)
+template <typename T>
+__global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ vals, int p0, int p1, int c1, int nA)
+{
+    __shared__ T M[kNB][kNB + 1];       // M[i][j] = X_{p0+i}[tpiv[p0+j]]
+    __shared__ int64_t rowoff[kNB];
+    __shared__ int piv[kNB];
+    const int np = p1 - p0, tid = threadIdx.x;
+    for (int i = tid; i < np; i += 64) { rowoff[i] = TV.trow[p0 + i]; piv[i] = TV.tpiv[p0 + i]; }
+    __syncthreads();
+    for (int idx = tid; idx < np * np; idx += 64) { int i = idx / np, j = idx % np; M[i][j] = vals[rowoff[i] + piv[j]]; }
+    __syncthreads();
+    if ((int)blockIdx.x < nA) {
+        const int c = c1 + blockIdx.x * 64 + tid;
+        if (c >= TV.mT) return;
+        T colv[kNB];
+#pragma unroll
+        for (int a = 0; a < kNB; a++) {
+            if (a < np) {
+                T acc = vals[rowoff[a] + c];
+#pragma unroll
+                for (int b = 0; b < a; b++) acc -= M[a][b] * colv[b];
+                colv[a] = acc;
+                vals[rowoff[a] + c] = acc;
+            }
+        }
+    } else {
+        const int r = p1 + (blockIdx.x - nA) * 64 + tid;
+        if (r >= TV.mT) return;
+        T* Xr = vals + TV.trow[r];
+        T y[kNB];
+#pragma unroll
+        for (int b = 0; b < kNB; b++) y[b] = b < np ? Xr[piv[b]] : T(0);
+#pragma unroll
+        for (int b = 0; b < kNB; b++) {
+            if (b < np) {
+                const T l = y[b] / M[b][b];
+                y[b] = l;
+#pragma unroll
+                for (int bb = b + 1; bb < kNB; bb++) y[bb] -= l * M[b][bb];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < kNB; b++) if (b < np) Xr[piv[b]] = y[b];
+    }
+}
+
+// trailing update X[r][c] -= sum_b X[r][tpiv[p0+b]] X[p0+b][c], r >= p1,
+// c >= cg0 still unpivoted after the panel; 64 x 64 tile per block
+template <typename T>
+__global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ vals, int p0, int p1, int cg0)
+{
+    __shared__ T As[kNB][kNB + 1];
+    __shared__ T Bs[kNB][kNB + 1];
+    __shared__ int64_t rowA[kNB];
+    __shared__ int pivs[kNB];
+    const int np = p1 - p0, mT = TV.mT, tid = threadIdx.x;
+    const int rt = p1 + blockIdx.y * 64, ct = cg0 + blockIdx.x * 64;
+    for (int i = tid; i < 64; i += 256) {
+        int row = rt + i;
+        rowA[i] = row < mT ? TV.trow[row] : -1;
+        if (i < np) pivs[i] = TV.tpiv[p0 + i];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 64 * kNB; idx += 256) {
+        int r = idx / kNB, b = idx % kNB;
+        As[r][b] = (rowA[r] >= 0 && b < np) ? vals[rowA[r] + pivs[b]] : T(0);
+    }
+    for (int idx = tid; idx < kNB * 64; idx += 256) {
+        int b = idx / 64, c = idx % 64, col = ct + c;
+        Bs[b][c] = (b < np && col < mT) ? vals[TV.trow[p0 + b] + col] : T(0);
+    }
+    __syncthreads();
+    const int tx = tid % 16, ty = tid / 16;
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = T(0);
+    for (int b = 0; b < np; b++) {
+        T av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) { av[i] = As[ty * 4 + i][b]; bv[i] = Bs[b][tx * 4 + i]; }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[i][j] += av[i] * bv[j];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        int r = ty * 4 + i;
+        if (rowA[r] < 0) continue;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            int col = ct + tx * 4 + j;
+            if (col < mT && TV.tstep[col] >= p1) vals[rowA[r] + col] -= acc[i][j];
+        }
+    }
+}
+
+// ---- dense tail solves (tail-local row/column a is global t0 + a)
+
+// forward, outside part: y_i -= sum over the L columns from outside the tail
+template <typename T>
+__global__ __launch_bounds__(256) void k_tail_lext(DevLayout D, const T* __restrict__ vals, int t0, T* __restrict__ y,
+                                                   int nrhs)
+{
+    const int lane = threadIdx.x & 63;
+    const int i = t0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= D.n) return;
+    const int v = D.row_node[i];
+    const int W = D.W[v];
+    const T* P = vals + D.voff[v] + (int64_t)(i - D.r0[v]) * W;
+    const int32_t* cols = D.cols + D.coff[v];
+    // outside sources come first in the column list and are the only columns < t0
+    for (int r = 0; r < nrhs; r++) {
+        T* yr = y + (int64_t)r * D.n;
+        T acc = T(0);
+        for (int t = lane; t < W && cols[t] < t0; t += 64) acc += P[t] * yr[D.qinv[cols[t]]];
+        acc = wave_sum(acc);
+        if (lane == 0) yr[i] -= acc;
+    }
+}
+
+// U^T, outside part: h[c] -= sum_k U_st(k, c) w_k over rows k before the tail
+template <typename T>
+__global__ __launch_bounds__(256) void k_tail_utext(DevLayout D, TailView TV, const T* __restrict__ vals,
+                                                    T* __restrict__ h, const T* __restrict__ w, int nrhs)
+{
+    const int lane = threadIdx.x & 63;
+    const int c = TV.t0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= D.n) return;
+    for (int r = 0; r < nrhs; r++) {
+        const T* wr = w + (int64_t)r * D.n;
+        T acc = T(0);
+        for (int64_t q = D.ut_ptr[c] + lane; q < D.ut_ptr[c + 1]; q += 64) acc += vals[D.ut_slot[q]] * wr[D.ut_row[q]];
+        acc = wave_sum(acc);
+        if (lane == 0) h[(int64_t)r * D.n + c] -= acc;
+    }
+}
+
+// mode 0 forward (L, ascending), 1 backward (U, descending),
+// 2 U^T (ascending), 3 L^T (descending): the panel's own triangle, one wave
+template <typename T>
+__global__ __launch_bounds__(64) void k_tail_tri(TailView TV, const T* __restrict__ vals, int p0, int p1, int n,
+                                                 T* __restrict__ y, T* __restrict__ x, int nrhs, int mode)
+{
+    const int lane = threadIdx.x;
+    const int np = p1 - p0;
+    const int t0 = TV.t0;
+    const int b = p0 + lane;
+    const int64_t rowb = lane < np ? TV.trow[b] : 0;
+    const int pivb = lane < np ? TV.tpiv[b] : 0;
+    for (int r = 0; r < nrhs; r++) {
+        T* yr = y + (int64_t)r * n + t0;
+        T* xr = x + (int64_t)r * n + t0;
+        for (int s = 0; s < np; s++) {
+            const int a = (mode == 1 || mode == 3) ? p1 - 1 - s : p0 + s;
+            const int64_t rowa = TV.trow[a];
+            const int piva = TV.tpiv[a];
+            T acc = T(0);
+            if (mode == 0) {            // L(a,b) = X_a[piv b], b < a
+                if (b < a && lane < np) acc = vals[rowa + pivb] * yr[b];
+            } else if (mode == 1) {     // U_st(a, piv b), b > a
+                if (b > a && lane < np) acc = vals[rowa + pivb] * xr[pivb];
+            } else if (mode == 2) {     // U_st(b, piv a), b < a
+                if (b < a && lane < np) acc = vals[rowb + piva] * xr[b];
+            } else {                    // L(b, a) = X_b[piv a], b > a
+                if (b > a && lane < np) acc = vals[rowb + piva] * xr[b];
+            }
+            acc = wave_sum(acc);
+            if (lane == 0) {
+                if (mode == 0) yr[a] -= acc;
+                else if (mode == 1) xr[piva] = (yr[a] - acc) / vals[rowa + piva];
+                else if (mode == 2) xr[a] = (yr[piva] - acc) / vals[rowa + piva];
+                else xr[a] -= acc;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// the panel's contribution to the rest of the tail, one wavefront per row or
+// column: mode 0 rows r >= p1: y_r -= sum_b X_r[piv b] y_b
+//         mode 1 rows r < p0:  y_r -= sum_b X_r[piv b] x[piv b]
+//         mode 2 columns c:     h_c -= sum_b X_b[c] w_b  (c pivoted after p1)
+//         mode 3 rows a < p0:  w_a -= sum_b X_b[piv a] u_b
+template <typename T>
+__global__ __launch_bounds__(256) void k_tail_gemv(TailView TV, const T* __restrict__ vals, int p0, int p1, int n,
+                                                   T* __restrict__ y, T* __restrict__ x, int nrhs, int mode,
+                                                   int first, int count)
+{
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= count) return;
+    const int e = first + k;              // row or column index, tail-local
+    const int np = p1 - p0;
+    const int t0 = TV.t0;
+    const int b = p0 + lane;
+    T coef = T(0);
+    if (lane < np) {
+        if (mode == 0 || mode == 1) coef = vals[TV.trow[e] + TV.tpiv[b]];
+        else if (mode == 2) coef = vals[TV.trow[b] + e];
+        else coef = vals[TV.trow[b] + TV.tpiv[e]];
+    }
+    if (mode == 2 && TV.tstep[e] < p1) return;
+    for (int r = 0; r < nrhs; r++) {
+        T* yr = y + (int64_t)r * n + t0;
+        T* xr = x + (int64_t)r * n + t0;
+        T v = T(0);
+        if (lane < np) {
+            if (mode == 0) v = yr[b];
+            else if (mode == 1) v = xr[TV.tpiv[b]];
+            else v = xr[b];
+        }
+        T acc = wave_sum(coef * v);
+        if (lane == 0) {
+            if (mode == 0 || mode == 1) yr[e] -= acc;
+            else if (mode == 2) yr[e] -= acc;
+            else xr[e] -= acc;
+        }
+    }
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -592,6 +906,104 @@ hipError_t launch_grad(int32_t n, const int64_t* rp, const int32_t* ci, const do
 {
     hipLaunchKernelGGL(k_grad, dim3(nblk(n, 256)), dim3(256), 0, st, n, rp, ci, lam, x, g);
     return hipGetLastError();
+}
+
+hipError_t launch_tail_init(const TailView& T, hipStream_t st)
+{
+    if (T.mT <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tail_init, dim3(nblk(T.mT, 256)), dim3(256), 0, st, T.mT, T.tstep);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, void* vals, int32_t p0, int32_t p1,
+                             int32_t c0, int32_t c1, double tau, int32_t* pert, int32_t search, hipStream_t st)
+{
+    if (p1 - p0 > kNB || p1 <= p0) return hipErrorInvalidValue;
+    if (fp32) hipLaunchKernelGGL(k_tail_panel<float>, dim3(1), dim3(256), 0, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
+    else hipLaunchKernelGGL(k_tail_panel<double>, dim3(1), dim3(256), 0, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_trsm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t c1, hipStream_t st)
+{
+    int nA = (int)nblk(std::max(T.mT - c1, 0), 64);
+    int nB = (int)nblk(std::max(T.mT - p1, 0), 64);
+    if (nA + nB == 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_tail_trsm<float>, dim3(nA + nB), dim3(64), 0, st, T, (float*)vals, p0, p1, c1, nA);
+    else hipLaunchKernelGGL(k_tail_trsm<double>, dim3(nA + nB), dim3(64), 0, st, T, (double*)vals, p0, p1, c1, nA);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_gemm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t cg0, hipStream_t st)
+{
+    int gx = (int)nblk(std::max(T.mT - cg0, 0), 64), gy = (int)nblk(std::max(T.mT - p1, 0), 64);
+    if (gx == 0 || gy == 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(gx, gy), dim3(256), 0, st, T, (float*)vals, p0, p1, cg0);
+    else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(gx, gy), dim3(256), 0, st, T, (double*)vals, p0, p1, cg0);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_lext(bool fp32, const DevLayout& D, const void* vals, int32_t tail_node0, int32_t t0,
+                            void* y, int32_t nrhs, hipStream_t st)
+{
+    (void)tail_node0;
+    int mT = D.n - t0;
+    if (mT <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_tail_lext<float>, dim3(nblk(mT, 4)), dim3(256), 0, st, D, (const float*)vals, t0, (float*)y, nrhs);
+    else hipLaunchKernelGGL(k_tail_lext<double>, dim3(nblk(mT, 4)), dim3(256), 0, st, D, (const double*)vals, t0, (double*)y, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_utext(bool fp32, const DevLayout& D, const TailView& T, const void* vals, void* h,
+                             const void* w, int32_t nrhs, hipStream_t st)
+{
+    if (T.mT <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_tail_utext<float>, dim3(nblk(T.mT, 4)), dim3(256), 0, st, D, T, (const float*)vals, (float*)h, (const float*)w, nrhs);
+    else hipLaunchKernelGGL(k_tail_utext<double>, dim3(nblk(T.mT, 4)), dim3(256), 0, st, D, T, (const double*)vals, (double*)h, (const double*)w, nrhs);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t tail_step(const TailView& TV, const T* vals, int32_t p0, int32_t p1, int32_t n, T* y, T* x,
+                            int32_t nrhs, int mode, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tail_tri<T>, dim3(1), dim3(64), 0, st, TV, vals, p0, p1, n, y, x, nrhs, mode);
+    int first, count;
+    if (mode == 0) { first = p1; count = TV.mT - p1; }
+    else if (mode == 2) { first = 0; count = TV.mT; }
+    else { first = 0; count = p0; }
+    if (count > 0)
+        hipLaunchKernelGGL(k_tail_gemv<T>, dim3(nblk(count, 4)), dim3(256), 0, st, TV, vals, p0, p1, n, y, x, nrhs, mode,
+                           first, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_fwd(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
+                           void* y, int32_t nrhs, hipStream_t st)
+{
+    if (fp32) return tail_step<float>(T, (const float*)vals, p0, p1, n, (float*)y, (float*)y, nrhs, 0, st);
+    return tail_step<double>(T, (const double*)vals, p0, p1, n, (double*)y, (double*)y, nrhs, 0, st);
+}
+
+hipError_t launch_tail_bwd(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
+                           void* y, void* x, int32_t nrhs, hipStream_t st)
+{
+    if (fp32) return tail_step<float>(T, (const float*)vals, p0, p1, n, (float*)y, (float*)x, nrhs, 1, st);
+    return tail_step<double>(T, (const double*)vals, p0, p1, n, (double*)y, (double*)x, nrhs, 1, st);
+}
+
+hipError_t launch_tail_ut(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
+                          void* h, void* w, int32_t nrhs, hipStream_t st)
+{
+    if (fp32) return tail_step<float>(T, (const float*)vals, p0, p1, n, (float*)h, (float*)w, nrhs, 2, st);
+    return tail_step<double>(T, (const double*)vals, p0, p1, n, (double*)h, (double*)w, nrhs, 2, st);
+}
+
+hipError_t launch_tail_lt(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
+                          void* w, int32_t nrhs, hipStream_t st)
+{
+    if (fp32) return tail_step<float>(T, (const float*)vals, p0, p1, n, (float*)w, (float*)w, nrhs, 3, st);
+    return tail_step<double>(T, (const double*)vals, p0, p1, n, (double*)w, (double*)w, nrhs, 3, st);
 }
 
 }  // namespace hylu

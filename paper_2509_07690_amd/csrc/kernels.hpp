@@ -24,6 +24,7 @@ struct EdgeDesc {
 // Device view of the panel layout.
 struct DevLayout {
     int32_t n, nnodes;
+    int32_t tail_node0;     // nodes from here on belong to the dense tail
     const int32_t* r0;
     const int32_t* m;
     const int32_t* lw;
@@ -46,7 +47,36 @@ struct DevLayout {
     const int32_t* lt_row;
 };
 
+// Dense tail: rows and columns [t0, n) of the factors as one dense block whose
+// rows live inside their nodes' panels (row a starts at vals + trow[a]).
+struct TailView {
+    int32_t mT, t0;
+    const int64_t* trow;    // value offset of tail row a's dense part
+    const int32_t* tlo;     // tail-local block range of row a's node: its pivot window
+    const int32_t* thi;
+    int32_t* tpiv;          // tail-local column of row a's pivot
+    int32_t* tstep;         // per tail column: the tail row that pivots it (INT32_MAX before)
+};
+
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+hipError_t launch_tail_init(const TailView& T, hipStream_t st);
+hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, void* vals, int32_t p0, int32_t p1,
+                             int32_t c0, int32_t c1, double tau, int32_t* pert, int32_t search, hipStream_t st);
+hipError_t launch_tail_trsm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t c1, hipStream_t st);
+hipError_t launch_tail_gemm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t cg0, hipStream_t st);
+// dense tail solves; y/x/h/w are the solve work vectors (n x nrhs, factor precision)
+hipError_t launch_tail_lext(bool fp32, const DevLayout& D, const void* vals, int32_t tail_node0, int32_t t0,
+                            void* y, int32_t nrhs, hipStream_t st);
+hipError_t launch_tail_utext(bool fp32, const DevLayout& D, const TailView& T, const void* vals, void* h,
+                             const void* w, int32_t nrhs, hipStream_t st);
+hipError_t launch_tail_fwd(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
+                           void* y, int32_t nrhs, hipStream_t st);
+hipError_t launch_tail_bwd(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
+                           void* y, void* x, int32_t nrhs, hipStream_t st);
+hipError_t launch_tail_ut(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
+                          void* h, void* w, int32_t nrhs, hipStream_t st);
+hipError_t launch_tail_lt(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
+                          void* w, int32_t nrhs, hipStream_t st);
 hipError_t launch_scatter(bool fp32, const double* aval, const int64_t* amap, const double* asr,
                           const double* asc, int64_t nnz, void* vals, double* acopy, hipStream_t st);
 hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st);

@@ -30,7 +30,8 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("pivot_tau", C.c_double), ("ir_tol", C.c_double),
                 ("ir_maxit", C.c_int32), ("sn_min", C.c_int32), ("sn_max", C.c_int32),
                 ("kernel_mode", C.c_int32), ("repeated", C.c_int32), ("nd_leaf", C.c_int32),
-                ("amd_dense", C.c_double)]
+                ("amd_dense", C.c_double), ("dense_tail", C.c_double), ("tail_min", C.c_int32),
+                ("tail_max", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -38,7 +39,8 @@ class Info(C.Structure):
                 ("flops", C.c_uint64), ("flops_padded", C.c_uint64), ("factor_entries", C.c_int64),
                 ("n_nodes", C.c_int32), ("n_supernodes", C.c_int32), ("rows_in_supernodes", C.c_int32),
                 ("max_supernode", C.c_int32), ("n_levels", C.c_int32 * 4), ("n_perturbed", C.c_int32),
-                ("ir_iters", C.c_int32), ("berr", C.c_double), ("pivot_tau", C.c_double)]
+                ("ir_iters", C.c_int32), ("berr", C.c_double), ("pivot_tau", C.c_double),
+                ("tail_rows", C.c_int32), ("tail_panels", C.c_int32), ("flops_issued", C.c_uint64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -45,7 +45,8 @@ def run_case(hylu, A, b, opts=None, sn=(2, 1 << 30), exact=False, tol=1e-11):
     return h, o, x, xo, eta
 
 
-def test_random_small(hylu):
+@pytest.mark.parametrize("tail", [0.0, 0.5])
+def test_random_small(hylu, tail):
     for seed in range(4):
         rng = np.random.default_rng(seed)
         n = 300
@@ -54,8 +55,9 @@ def test_random_small(hylu):
         D = np.where(M, rng.standard_normal((n, n)), 0.0)
         A = synth.csr_from_dense(D)
         b = rng.standard_normal(n)
-        h, o, x, xo, eta = run_case(hylu, A, b)
+        h, o, x, xo, eta = run_case(hylu, A, b, opts=dict(dense_tail=tail))
         assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
+        assert (h.info()["tail_rows"] > 0) == (tail > 0)
 
 
 def test_dense_block_pivoting(hylu):
@@ -94,18 +96,20 @@ def test_integer_factors_bit_exact(hylu, seed):
     h, o, x, xo, eta = run_case(hylu, A, b, opts=dict(static_pivot=0, ordering="natural"), exact=True)
 
 
-@pytest.mark.parametrize("ordering", ["amd", "nd"])
-def test_config0_factor_solve(hylu, ordering):
+@pytest.mark.parametrize("ordering,tail", [("amd", 0.5), ("nd", 0.5), ("amd", 0.0), ("amd", 0.05)])
+def test_config0_factor_solve(hylu, ordering, tail):
     w = synth.config(0)
-    h, o, x, xo, eta = run_case(hylu, w.A, w.b[:, 0], opts=dict(ordering=ordering))
+    h, o, x, xo, eta = run_case(hylu, w.A, w.b[:, 0], opts=dict(ordering=ordering, dense_tail=tail))
+    print("tail rows", h.info()["tail_rows"], "panels", h.info()["tail_panels"])
     assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
     assert np.abs(x - w.x_true[:, 0]).max() < 1e-10
 
 
-def test_config0_refactor_and_transpose(hylu):
+@pytest.mark.parametrize("tail", [0.0, 0.3])
+def test_config0_refactor_and_transpose(hylu, tail):
     w = synth.config(0)
     A = w.A
-    h = hylu.Handle(A.row_ptr, A.col, A.val)
+    h = hylu.Handle(A.row_ptr, A.col, A.val, dense_tail=tail)
     o, sym = oracle_for(h, A)
     h.factorize(dev(A.val))
     torch.cuda.synchronize()
