@@ -165,6 +165,23 @@ hylu_status hylu_export_factors(hylu_handle h, double* vals, int64_t* node_voff,
                                 int32_t* node_W, int64_t* node_coff, int32_t* cols, int32_t* piv);
 hylu_status hylu_export_sizes(hylu_handle h, int64_t* ncols_total);
 
+/* Per-kernel-class measurement of one refactorisation + solve, run eagerly
+ * (not from the graph) with a pair of HIP events around every launch on
+ * `stream`.  For every class: launches, summed device time, and the
+ * algorithmic bytes and flops of those launches (computed on the host from the
+ * layout: values and indices each launch must read or write once, flops of
+ * the entries it updates).  d_b, d_x: one right-hand side (device).  Returns
+ * the number of classes written (at most max_classes) in *count. */
+typedef struct {
+    char name[32];
+    int32_t launches;
+    double ms;
+    double bytes;
+    double flops;
+} hylu_kernel_stats;
+hylu_status hylu_profile(hylu_handle h, const double* d_val, const double* d_b, double* d_x, void* stream,
+                         hylu_kernel_stats* stats, int32_t max_classes, int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

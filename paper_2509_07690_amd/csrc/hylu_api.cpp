@@ -32,6 +32,21 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
 };
 
+// per-launch timing used by hylu_profile: when active, every launch of the
+// factor and solve sequences is bracketed by events and attributed to a class
+struct Profiler {
+    bool on = false;
+    hipStream_t st = nullptr;
+    struct Rec { int cls; hipEvent_t a, b; double bytes, flops; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    hipEvent_t ev() {
+        if (used == pool.size()) { hipEvent_t e; if (hipEventCreate(&e) != hipSuccess) return nullptr; pool.push_back(e); }
+        return pool[used++];
+    }
+};
+
 struct LevelTasks {
     std::vector<int64_t> row_ptr;     // per level into rows
     std::vector<int32_t> maxW;        // per level
@@ -99,7 +114,14 @@ struct hylu_handle_s {
     // last solve
     int32_t ir_iters = 0;
     double berr = 0.0;
+    // measurement
+    Profiler prof;
+    std::vector<double> lvl_bytes, lvl_flops;   // per factor level: row-kernel traffic and flops
 };
+
+static const char* kClassNames[] = {"rows", "snlu", "tail_panel", "tail_trsm", "tail_gemm", "lsolve", "usolve",
+                                    "tail_solve", "scatter", "other_solve"};
+enum { C_ROWS, C_SNLU, C_PANEL, C_TRSM, C_GEMM, C_LSOLVE, C_USOLVE, C_TSOLVE, C_SCATTER, C_OSOLVE, C_N };
 
 namespace {
 
@@ -115,6 +137,14 @@ struct PhaseLog {
 };
 
 #define HIPCHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { h->sticky_error = true; return HYLU_ERR_DEVICE; } } while (0)
+
+// launch `x` and, when profiling, bracket it with events attributed to class `c`
+#define LAUNCH(c, by, fl, x) do {                                                          \
+        hipEvent_t ea_ = nullptr, eb_ = nullptr;                                            \
+        if (h->prof.on) { ea_ = h->prof.ev(); eb_ = h->prof.ev(); HIPCHK(hipEventRecord(ea_, st)); } \
+        HIPCHK(x);                                                                          \
+        if (h->prof.on) { HIPCHK(hipEventRecord(eb_, st)); h->prof.recs.push_back({(c), ea_, eb_, (double)(by), (double)(fl)}); } \
+    } while (0)
 
 void* dalloc(hylu_handle h, size_t bytes)
 {
@@ -269,27 +299,41 @@ hylu_status ensure_tlists(hylu_handle h)
 // the level loop of the numerical factorisation
 hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipStream_t st)
 {
+    const double es = h->fp32 ? 4.0 : 8.0;
     HIPCHK(launch_zero(h->d_pert, sizeof(int32_t), st));
-    HIPCHK(launch_zero(h->vals, h->lay.nvals * (h->fp32 ? 4 : 8), st));
-    HIPCHK(launch_scatter(h->fp32, d_val, h->d_amap, h->d_asr, h->d_asc, h->nnz, h->vals, h->d_aval, st));
+    LAUNCH(C_SCATTER, es * h->lay.nvals, 0, launch_zero(h->vals, h->lay.nvals * (h->fp32 ? 4 : 8), st));
+    LAUNCH(C_SCATTER, 40.0 * h->nnz, 2.0 * h->nnz,
+           launch_scatter(h->fp32, d_val, h->d_amap, h->d_asr, h->d_asc, h->nnz, h->vals, h->d_aval, st));
     if (search) HIPCHK(launch_tail_init(h->TV, st));
     const LevelTasks& T = h->ft;
     int32_t nl = (int32_t)T.maxW.size();
     for (int32_t l = 0; l < nl; l++) {
         int64_t r0 = T.row_ptr[l], r1 = T.row_ptr[l + 1];
-        HIPCHK(launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.maxW[l], h->tau,
-                                  h->d_pert, st));
+        LAUNCH(C_ROWS, h->lvl_bytes[l] * es / 8.0, h->lvl_flops[l],
+               launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.maxW[l], h->tau, h->d_pert, st));
         int64_t s0 = T.sn_ptr[l], s1 = T.sn_ptr[l + 1];
-        if (s1 > s0)
-            HIPCHK(launch_factor_snlu(h->fp32, h->D, h->vals, h->d_snodes + s0, (int32_t)(s1 - s0), T.maxm[l], h->tau,
-                                      h->d_pert, search ? 1 : 0, st));
+        if (s1 > s0) {
+            double by = 0, fl = 0;
+            for (int64_t q = s0; q < s1; q++) {
+                int32_t v = T.snodes[q];
+                double m = h->lay.m[v], wc = h->lay.W[v] - h->lay.lw[v];
+                by += 2.0 * es * m * wc;
+                fl += m * m * (2.0 * wc - m);
+            }
+            LAUNCH(C_SNLU, by, fl, launch_factor_snlu(h->fp32, h->D, h->vals, h->d_snodes + s0, (int32_t)(s1 - s0), T.maxm[l],
+                                                      h->tau, h->d_pert, search ? 1 : 0, st));
+        }
     }
     // dense tail: blocked right-looking LU, one row panel at a time
+    const double mT = h->lay.mT;
     for (const Layout::Panel& P : h->lay.panels) {
-        HIPCHK(launch_tail_panel(h->fp32, h->D, h->TV, h->vals, P.p0, P.p1, P.c0, P.c1, h->tau, h->d_pert,
-                                 search ? 1 : 0, st));
-        HIPCHK(launch_tail_trsm(h->fp32, h->TV, h->vals, P.p0, P.p1, P.c1, st));
-        HIPCHK(launch_tail_gemm(h->fp32, h->TV, h->vals, P.p0, P.p1, P.cg0, st));
+        const double np = P.p1 - P.p0, wc = P.c1 - P.c0, rows = mT - P.p1, colsA = mT - P.c1, colsG = mT - P.cg0;
+        LAUNCH(C_PANEL, 2.0 * es * np * wc, np * np * wc,
+               launch_tail_panel(h->fp32, h->D, h->TV, h->vals, P.p0, P.p1, P.c0, P.c1, h->tau, h->d_pert, search ? 1 : 0, st));
+        LAUNCH(C_TRSM, es * (2.0 * np * colsA + 3.0 * np * rows + np * np), np * np * (colsA + rows),
+               launch_tail_trsm(h->fp32, h->TV, h->vals, P.p0, P.p1, P.c1, st));
+        LAUNCH(C_GEMM, es * (2.0 * rows * colsG + np * (rows + colsG)), 2.0 * np * rows * colsG,
+               launch_tail_gemm(h->fp32, h->TV, h->vals, P.p0, P.p1, P.cg0, st));
     }
     return HYLU_OK;
 }
@@ -304,7 +348,8 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
     auto levels = [&](int g, auto&& fn) -> hylu_status {
         for (size_t l = 0; l + 1 < L.xlev_ptr[g].size(); l++) {
             int32_t a = L.xlev_ptr[g][l], c = L.xlev_ptr[g][l + 1] - a;
-            if (c > 0) HIPCHK(fn(h->d_lev[g] + a, c));
+            int cls = g == 4 ? C_LSOLVE : g == 1 ? C_USOLVE : C_OSOLVE;
+            if (c > 0) LAUNCH(cls, 0, 0, fn(h->d_lev[g] + a, c));
         }
         return HYLU_OK;
     };
@@ -314,10 +359,10 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
         s = levels(4, [&](const int32_t* nodes, int32_t c) { return launch_lsolve(f, h->D, h->vals, nodes, c, h->d_y, nrhs, st); });
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
-            HIPCHK(launch_tail_lext(f, h->D, h->vals, L.tail_node0, L.t0, h->d_y, nrhs, st));
-            for (const Layout::Panel& P : L.panels) HIPCHK(launch_tail_fwd(f, h->TV, h->vals, P.p0, P.p1, n, h->d_y, nrhs, st));
+            LAUNCH(C_TSOLVE, 0, 0, launch_tail_lext(f, h->D, h->vals, L.tail_node0, L.t0, h->d_y, nrhs, st));
+            for (const Layout::Panel& P : L.panels) LAUNCH(C_TSOLVE, 0, 0, launch_tail_fwd(f, h->TV, h->vals, P.p0, P.p1, n, h->d_y, nrhs, st));
             for (size_t k = L.panels.size(); k-- > 0;)
-                HIPCHK(launch_tail_bwd(f, h->TV, h->vals, L.panels[k].p0, L.panels[k].p1, n, h->d_y, h->d_z, nrhs, st));
+                LAUNCH(C_TSOLVE, 0, 0, launch_tail_bwd(f, h->TV, h->vals, L.panels[k].p0, L.panels[k].p1, n, h->d_y, h->d_z, nrhs, st));
         }
         s = levels(1, [&](const int32_t* nodes, int32_t c) { return launch_usolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, st); });
         if (s != HYLU_OK) return s;
@@ -327,10 +372,10 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
         s = levels(2, [&](const int32_t* nodes, int32_t c) { return launch_utsolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, st); });
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
-            HIPCHK(launch_tail_utext(f, h->D, h->TV, h->vals, h->d_y, h->d_z, nrhs, st));
-            for (const Layout::Panel& P : L.panels) HIPCHK(launch_tail_ut(f, h->TV, h->vals, P.p0, P.p1, n, h->d_y, h->d_z, nrhs, st));
+            LAUNCH(C_TSOLVE, 0, 0, launch_tail_utext(f, h->D, h->TV, h->vals, h->d_y, h->d_z, nrhs, st));
+            for (const Layout::Panel& P : L.panels) LAUNCH(C_TSOLVE, 0, 0, launch_tail_ut(f, h->TV, h->vals, P.p0, P.p1, n, h->d_y, h->d_z, nrhs, st));
             for (size_t k = L.panels.size(); k-- > 0;)
-                HIPCHK(launch_tail_lt(f, h->TV, h->vals, L.panels[k].p0, L.panels[k].p1, n, h->d_z, nrhs, st));
+                LAUNCH(C_TSOLVE, 0, 0, launch_tail_lt(f, h->TV, h->vals, L.panels[k].p0, L.panels[k].p1, n, h->d_z, nrhs, st));
         }
         s = levels(3, [&](const int32_t* nodes, int32_t c) { return launch_ltsolve(f, h->D, h->vals, nodes, c, h->d_z, nrhs, st); });
         if (s != HYLU_OK) return s;
@@ -416,6 +461,8 @@ hylu_status upload_device(hylu_handle h)
             std::vector<int32_t> zt(std::max(L.mT, 1), 0);
             UP(trow, L.trow); UP(tlo, L.tlo); UP(thi, L.thi); UP(tpiv, zt); UP(tstep, zt);
             TVw.trow = trow; TVw.tlo = tlo; TVw.thi = thi; TVw.tpiv = tpiv; TVw.tstep = tstep;
+            TVw.lbuf = dalloc(h, (size_t)64 * std::max(L.mT, 1) * (h->fp32 ? 4 : 8));
+            if (!TVw.lbuf) return HYLU_ERR_OOM;
         }
         UP(h->d_perm_r, h->perm_r); UP(h->d_perm_c, h->perm_c);
         UP(h->d_dr, h->dr); UP(h->d_dc, h->dc);
@@ -498,6 +545,7 @@ hylu_status hylu_destroy(hylu_handle h)
 {
     if (!h) return HYLU_ERR_ARG;
     free_device(h);
+    for (hipEvent_t e : h->prof.pool) hipEventDestroy(e);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     if (h->fact_done) hipEventDestroy(h->fact_done);
     if (h->h_pert) hipHostFree(h->h_pert);
@@ -644,6 +692,22 @@ hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const
             T.maxm.push_back(mm);
             h->max_sn = std::max(h->max_sn, mm);
         }
+        // algorithmic traffic and flops of every row-kernel launch (8-byte values)
+        h->lvl_bytes.assign(nl, 0.0);
+        h->lvl_flops.assign(nl, 0.0);
+        for (int32_t l = 0; l < nl; l++)
+            for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) {
+                int32_t v = L.xlev_nodes[0][t];
+                double m = L.m[v], by = 16.0 * L.W[v], fl = 0;
+                for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
+                    int32_t u = L.esrc[e];
+                    double ms = L.m[u], ws = L.W[u] - L.lw[u] - L.m[u];
+                    by += 8.0 * ms * (ms + ws) + 4.0 * ws + 48.0;
+                    fl += ms * (ms + 2.0 * ws);
+                }
+                h->lvl_bytes[l] += m * by;
+                h->lvl_flops[l] += m * fl;
+            }
         plog("tasks");
         h->analyzed = true;
     } catch (const std::bad_alloc&) {
@@ -825,6 +889,44 @@ hylu_status hylu_export_symbolic(hylu_handle h, const hylu_symbolic_view* v)
     if (v->is_sn) std::memcpy(v->is_sn, h->nodes.is_sn.data(), nn);
     if (v->levels)
         for (int t = 0; t < 4; t++) std::memcpy(v->levels + (size_t)t * nn, h->nodes.level[t].data(), sizeof(int32_t) * nn);
+    return HYLU_OK;
+}
+
+hylu_status hylu_profile(hylu_handle h, const double* d_val, const double* d_b, double* d_x, void* stream,
+                         hylu_kernel_stats* stats, int32_t max_classes, int32_t* count)
+{
+    if (!h || !d_val || !d_b || !d_x || !stats || !count || max_classes <= 0) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
+    if (h->sticky_error) return HYLU_ERR_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    hylu_status s = ensure_workspace(h, 1);
+    if (s != HYLU_OK) return s;
+    h->prof.on = true;
+    h->prof.recs.clear();
+    h->prof.used = 0;
+    s = enqueue_factor(h, d_val, false, st);
+    if (s == HYLU_OK) s = enqueue_solve(h, d_b, h->n, d_x, h->n, 1, 0, 0, st);
+    h->prof.on = false;
+    if (s != HYLU_OK) return s;
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<hylu_kernel_stats> acc(C_N);
+    for (int c = 0; c < C_N; c++) { std::memset(&acc[c], 0, sizeof(acc[c])); std::snprintf(acc[c].name, 32, "%s", kClassNames[c]); }
+    for (const Profiler::Rec& r : h->prof.recs) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        acc[r.cls].launches++;
+        acc[r.cls].ms += ms;
+        acc[r.cls].bytes += r.bytes;
+        acc[r.cls].flops += r.flops;
+    }
+    int32_t k = 0;
+    for (int c = 0; c < C_N && k < max_classes; c++)
+        if (acc[c].launches > 0) stats[k++] = acc[c];
+    *count = k;
+    h->pert_known = false;
+    HIPCHK(hipMemcpyAsync(h->h_pert, h->d_pert, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(h->fact_done, st));
     return HYLU_OK;
 }
 

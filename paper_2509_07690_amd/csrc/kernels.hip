@@ -23,6 +23,8 @@ namespace {
 
 template <typename T> __device__ __forceinline__ T tabs(T x) { return x < T(0) ? -x : x; }
 
+constexpr int kStage = 1024;   // staged source entries per batch (values + relative indices)
+
 // ----------------------------------------------------------------------------
 // value scatter: B = R A C into the panels (fill slots are zero)
 // ----------------------------------------------------------------------------
@@ -74,14 +76,79 @@ __global__ void k_init_pivots(int32_t n, const int32_t* __restrict__ row_node, c
 // map.  The row's accumulator sits in LDS when it fits.
 // ----------------------------------------------------------------------------
 
-template <typename T>
-__global__ __launch_bounds__(64) void k_factor_rows(DevLayout D, T* __restrict__ vals,
+// a source with its own pivot order (a supernode; also a standalone source too
+// large for the stage): triangular solve with its block in pivot order, then
+// the update of the columns past the block.  The pivot order, and the block
+// when small, are first copied to LDS; the update reads the source rows with
+// independent loads (unrolled over source rows).
+template <typename T, int NT>
+__device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ vals, T* xs, const EdgeDesc& ed,
+                                    int tid, T* sbuf, int32_t* ibuf)
+{
+    const T* Us = vals + ed.uoff;
+    const int32_t* rl = D.rel + ed.roff;
+    const int lp = ed.lp, ms = ed.ms, Ws = ed.Ws, ws = ed.ws;
+    const bool pl_lds = ms <= kStage;
+    const bool blk_lds = ms * ms <= kStage;
+    const int32_t* pls = pl_lds ? ibuf : D.pl + ed.r0s;
+    if (pl_lds) for (int b = tid; b < ms; b += NT) ibuf[b] = D.pl[ed.r0s + b];
+    if (blk_lds)
+        for (int idx = tid; idx < ms * ms; idx += NT) sbuf[idx] = Us[(int64_t)(idx / ms) * Ws + idx % ms];
+    __syncthreads();
+    for (int b = 0; b < ms; b++) {
+        const int pb = pls[b];
+        const T ub = blk_lds ? sbuf[b * ms + pb] : Us[(int64_t)b * Ws + pb];
+        const T lb = xs[lp + pb] / ub;
+        __syncthreads();
+        if (tid == 0) xs[lp + pb] = lb;
+        for (int bb = b + 1 + tid; bb < ms; bb += NT) {
+            const int pc = pls[bb];
+            xs[lp + pc] -= lb * (blk_lds ? sbuf[b * ms + pc] : Us[(int64_t)b * Ws + pc]);
+        }
+        __syncthreads();
+    }
+    const T* Ut = Us + ms;
+    for (int j = tid; j < ws; j += NT) {
+        T acc0 = T(0), acc1 = T(0);
+        int b = 0;
+        for (; b + 4 <= ms; b += 4) {
+            const T u0 = Ut[(int64_t)(b + 0) * Ws + j];
+            const T u1 = Ut[(int64_t)(b + 1) * Ws + j];
+            const T u2 = Ut[(int64_t)(b + 2) * Ws + j];
+            const T u3 = Ut[(int64_t)(b + 3) * Ws + j];
+            acc0 += xs[lp + pls[b + 0]] * u0;
+            acc1 += xs[lp + pls[b + 1]] * u1;
+            acc0 += xs[lp + pls[b + 2]] * u2;
+            acc1 += xs[lp + pls[b + 3]] * u3;
+        }
+        for (; b < ms; b++) acc0 += xs[lp + pls[b]] * Ut[(int64_t)b * Ws + j];
+        xs[rl[j]] -= acc0 + acc1;
+    }
+    __syncthreads();
+}
+
+// row updates: one block of NT threads per target row.  Every source node (a
+// standalone row: row-row kernel; a supernode: sup-row kernel) is applied in
+// ascending order.  Standalone sources are staged in batches in LDS (pivot,
+// the source's U values and their relative positions in the target), then
+// applied one after the other from LDS.  The row's accumulator sits in LDS
+// when it fits.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__ vals,
                                                     const int32_t* __restrict__ rows, int32_t nrows,
                                                     int32_t lds_cap, T tau, int32_t* __restrict__ pert)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* smem = reinterpret_cast<T*>(smem_raw);
-    const int lane = threadIdx.x;
+    T* sval = reinterpret_cast<T*>(smem_raw);                                   // kStage
+    int32_t* sidx = reinterpret_cast<int32_t*>(sval + kStage);                 // kStage
+    int32_t* eoff = sidx + kStage;                                              // 65 (padded to 66)
+    int32_t* elp = eoff + 66;                                                   // 64
+    int64_t* eu = reinterpret_cast<int64_t*>(elp + 64);                         // 64, 8-byte aligned
+    int64_t* er = eu + 64;                                                      // 64
+    T* xsl = reinterpret_cast<T*>(er + 64);                                     // lds_cap
+    __shared__ int s_nb, s_total;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int t = blockIdx.x;
     if (t >= nrows) return;
     const int i = rows[t];
@@ -90,39 +157,73 @@ __global__ __launch_bounds__(64) void k_factor_rows(DevLayout D, T* __restrict__
     const int a = i - D.r0[v];
     T* X = vals + D.voff[v] + (int64_t)a * W;
     const bool in_lds = W <= lds_cap;
-    T* xs = in_lds ? smem : X;
+    T* xs = in_lds ? xsl : X;
     if (in_lds) {
-        for (int j = lane; j < W; j += 64) xs[j] = X[j];
+        for (int j = tid; j < W; j += NT) xs[j] = X[j];
     }
     __syncthreads();
-    const int64_t e0 = D.eptr[v], e1 = D.eptr[v + 1];
-    for (int64_t e = e0; e < e1; e++) {
-        const EdgeDesc ed = D.edges[e];
-        const T* Us = vals + ed.uoff;                 // source row b, block column c at Us[b*Ws + c]
-        const int32_t* pls = D.pl + ed.r0s;
-        const int32_t* rl = D.rel + ed.roff;
-        const int lp = ed.lp, ms = ed.ms, Ws = ed.Ws, ws = ed.ws;
-        // multipliers: triangular solve with the source block in pivot order
-        for (int b = 0; b < ms; b++) {
-            const int pb = pls[b];
-            const T lb = xs[lp + pb] / Us[(int64_t)b * Ws + pb];
-            __syncthreads();
-            if (lane == 0) xs[lp + pb] = lb;
-            for (int bb = b + 1 + lane; bb < ms; bb += 64) {
-                const int pc = pls[bb];
-                xs[lp + pc] -= lb * Us[(int64_t)b * Ws + pc];
+    const int64_t e1 = D.eptr[v + 1];
+    int64_t e = D.eptr[v];
+    while (e < e1) {
+        // wave 0 plans a batch: one descriptor per lane; standalone sources are staged
+        if (tid < 64) {
+            const int64_t my = e + lane;
+            EdgeDesc ed;
+            int cost = 0x3fffffff;
+            if (my < e1) {
+                ed = D.edges[my];
+                if (ed.ms == 1) cost = ed.ws + 1;
             }
-            __syncthreads();
-        }
-        // update of the columns past the source block
-        for (int j = lane; j < ws; j += 64) {
-            T acc = T(0);
-            for (int b = 0; b < ms; b++) acc += xs[lp + pls[b]] * Us[(int64_t)b * Ws + ms + j];
-            xs[rl[j]] -= acc;
+            int pre = cost;
+            for (int off = 1; off < 64; off <<= 1) {
+                int o = __shfl_up(pre, off, 64);
+                if (lane >= off) pre = (pre > 0x3fffffff - o) ? 0x3fffffff : pre + o;
+            }
+            const unsigned long long fits = __ballot(pre <= kStage && my < e1);
+            const int nb = (fits == ~0ull) ? 64 : __builtin_ctzll(~fits);
+            if (lane < nb) {
+                eoff[lane] = pre - cost;
+                elp[lane] = ed.lp;
+                eu[lane] = ed.uoff;
+                er[lane] = ed.roff;
+            }
+            if (lane == 0) {
+                s_nb = nb;
+                s_total = nb > 0 ? 0 : -1;
+            }
+            if (nb > 0 && lane == nb - 1) { eoff[nb] = pre; s_total = pre; }
         }
         __syncthreads();
+        const int nb = s_nb, total = s_total;
+        if (nb == 0) {
+            // a supernode source (or an oversized standalone one)
+            const EdgeDesc e0 = D.edges[e];
+            apply_source_direct<T, NT>(D, vals, xs, e0, tid, sval, sidx);
+            e += 1;
+            continue;
+        }
+        for (int idx = tid; idx < total; idx += NT) {
+            int lo = 0, hi = nb - 1;                 // edge j with eoff[j] <= idx < eoff[j+1]
+            while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (eoff[mid] <= idx) lo = mid; else hi = mid - 1; }
+            const int tt = idx - eoff[lo];
+            sval[idx] = vals[eu[lo] + tt];           // pivot, then the T values
+            if (tt > 0) sidx[idx] = D.rel[er[lo] + tt - 1];
+        }
+        __syncthreads();
+        // sequential part: every source needs the multipliers of the earlier ones
+        for (int j = 0; j < nb; j++) {
+            const int off = eoff[j];
+            const int ws = eoff[j + 1] - off - 1;
+            const int lp = elp[j];
+            const T l = xs[lp] / sval[off];
+            if (NT > 64) __syncthreads();
+            for (int q = tid; q < ws; q += NT) xs[sidx[off + 1 + q]] -= l * sval[off + 1 + q];
+            if (tid == 0) xs[lp] = l;
+            __syncthreads();
+        }
+        e += nb;
     }
-    if (D.m[v] == 1 && v < D.tail_node0 && lane == 0) {
+    if (D.m[v] == 1 && v < D.tail_node0 && tid == 0) {
         // standalone row: no pivot search (Sec. 2.2), perturbation only
         T d = xs[D.lw[v]];
         if (tabs(d) < tau) {
@@ -132,7 +233,7 @@ __global__ __launch_bounds__(64) void k_factor_rows(DevLayout D, T* __restrict__
     }
     __syncthreads();
     if (in_lds) {
-        for (int j = lane; j < W; j += 64) X[j] = xs[j];
+        for (int j = tid; j < W; j += NT) X[j] = xs[j];
     }
 }
 
@@ -459,18 +560,36 @@ __global__ void k_tail_init(int32_t mT, int32_t* __restrict__ tstep)
     if (c < mT) tstep[c] = 0x7fffffff;
 }
 
-template <typename T>
+// panel factorisation; with stage = true the panel's pivot window lives in LDS
+// (np x wc values and the window's tstep entries), else it is updated in place
+template <typename T, bool stage>
 __global__ __launch_bounds__(256) void k_tail_panel(DevLayout D, TailView TV, T* __restrict__ vals, int p0, int p1,
                                                     int c0, int c1, T tau, int32_t* __restrict__ pert, int search)
 {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ T lrow[kNB];
     __shared__ T red_v[256];
     __shared__ int red_i[256];
     __shared__ int s_p;
+    __shared__ int64_t rowoff[kNB];
     const int tid = threadIdx.x;
-    const int wc = c1 - c0;
+    const int wc = c1 - c0, np = p1 - p0;
+    T* Xw = reinterpret_cast<T*>(smem_raw);                         // np x wc (stage only)
+    int* tsw = reinterpret_cast<int*>(Xw + (stage ? np * wc : 0));  // wc (stage only)
+    for (int r = tid; r < np; r += 256) rowoff[r] = TV.trow[p0 + r];
+    __syncthreads();
+    if (stage) {
+        for (int idx = tid; idx < np * wc; idx += 256) {
+            int r = idx / wc, c = idx % wc;
+            Xw[idx] = vals[rowoff[r] + c0 + c];
+        }
+        for (int c = tid; c < wc; c += 256) tsw[c] = TV.tstep[c0 + c];
+        __syncthreads();
+    }
+    // element (panel row r, tail column c) and the step that pivots column c
+    auto X = [&](int r, int c) -> T& { return stage ? Xw[(r - p0) * wc + (c - c0)] : vals[rowoff[r - p0] + c]; };
+    auto step = [&](int c) -> int { return stage ? tsw[c - c0] : TV.tstep[c]; };
     for (int a = p0; a < p1; a++) {
-        T* Xa = vals + TV.trow[a];
         const int lo = TV.tlo[a], hi = TV.thi[a];
         int p;
         if (!search) {
@@ -481,15 +600,15 @@ __global__ __launch_bounds__(256) void k_tail_panel(DevLayout D, TailView TV, T*
             T best = T(-1);
             int bi = hi;
             for (int c = lo + tid; c < hi; c += 256) {
-                if (TV.tstep[c] <= a) continue;
-                T x = tabs(Xa[c]);
+                if (step(c) <= a) continue;
+                T x = tabs(X(a, c));
                 if (x > best || (x == best && c < bi)) { best = x; bi = c; }
             }
             red_v[tid] = best; red_i[tid] = bi;
             __syncthreads();
-            for (int s = 128; s > 0; s >>= 1) {
-                if (tid < s) {
-                    T x = red_v[tid + s]; int xi = red_i[tid + s];
+            for (int s2 = 128; s2 > 0; s2 >>= 1) {
+                if (tid < s2) {
+                    T x = red_v[tid + s2]; int xi = red_i[tid + s2];
                     if (x > red_v[tid] || (x == red_v[tid] && xi < red_i[tid])) { red_v[tid] = x; red_i[tid] = xi; }
                 }
                 __syncthreads();
@@ -497,24 +616,24 @@ __global__ __launch_bounds__(256) void k_tail_panel(DevLayout D, TailView TV, T*
             p = red_i[0];
         }
         if (tid == 0) {
-            T d = Xa[p];
+            T d = X(a, p);
             if (tabs(d) < tau) {
-                Xa[p] = d < T(0) ? -tau : tau;
+                X(a, p) = d < T(0) ? -tau : tau;
                 atomicAdd(pert, 1);
             }
             TV.tpiv[a] = p;
             TV.tstep[p] = a;
+            if (stage) tsw[p - c0] = a;
             D.pl[TV.t0 + a] = p - lo;
             D.qinv[TV.t0 + p] = TV.t0 + a;
             s_p = p;
         }
         __syncthreads();
         p = s_p;
-        const T d = Xa[p];
+        const T d = X(a, p);
         for (int r = a + 1 + tid; r < p1; r += 256) {
-            T* Xr = vals + TV.trow[r];
-            T l = Xr[p] / d;
-            Xr[p] = l;
+            T l = X(r, p) / d;
+            X(r, p) = l;
             lrow[r - p0] = l;
         }
         __syncthreads();
@@ -522,11 +641,104 @@ __global__ __launch_bounds__(256) void k_tail_panel(DevLayout D, TailView TV, T*
         for (int idx = tid; idx < rows_left * wc; idx += 256) {
             int r = a + 1 + idx / wc;
             int c = c0 + idx % wc;
-            if (TV.tstep[c] <= a) continue;
-            vals[TV.trow[r] + c] -= lrow[r - p0] * Xa[c];
+            if (step(c) <= a) continue;
+            X(r, c) -= lrow[r - p0] * X(a, c);
         }
         __syncthreads();
     }
+    if (stage) {
+        for (int idx = tid; idx < np * wc; idx += 256) {
+            int r = idx / wc, c = idx % wc;
+            vals[rowoff[r] + c0 + c] = Xw[idx];
+        }
+    }
+}
+
+// panel factorisation with the window in LDS (4 wavefronts): rows are staged
+// with coalesced loads, wave 0 searches the pivot with a wave reduction, the
+// elimination gives each wave every fourth remaining row, lanes over columns
+template <typename T>
+__global__ __launch_bounds__(256) void k_tail_panel_lds(DevLayout D, TailView TV, T* __restrict__ vals, int p0, int p1,
+                                                        int c0, int c1, T tau, int32_t* __restrict__ pert, int search)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ T lrow[kNB];
+    __shared__ int64_t rowoff[kNB];
+    __shared__ int s_p;
+    __shared__ T s_d;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wc = c1 - c0, np = p1 - p0;
+    T* Xw = reinterpret_cast<T*>(smem_raw);          // np x wc
+    int* tsw = reinterpret_cast<int*>(Xw + np * wc); // wc
+    if (tid < np) rowoff[tid] = TV.trow[p0 + tid];
+    for (int c = tid; c < wc; c += 256) tsw[c] = TV.tstep[c0 + c];
+    __syncthreads();
+#pragma unroll 4
+    for (int r = wv; r < np; r += 4)
+        for (int c = lane; c < wc; c += 64) Xw[r * wc + c] = vals[rowoff[r] + c0 + c];
+    __syncthreads();
+    for (int ar = 0; ar < np; ar++) {
+        const int a = p0 + ar;
+        T* Xa = Xw + ar * wc;
+        if (wv == 0) {
+            const int lo = TV.tlo[a], hi = TV.thi[a];
+            int p;
+            if (!search) {
+                p = TV.tpiv[a];
+            } else if (hi - lo == 1) {
+                p = a;
+            } else {
+                T best = T(-1);
+                int bi = 0x7fffffff;
+                for (int c = lo + lane; c < hi; c += 64) {
+                    if (tsw[c - c0] <= a) continue;
+                    T x = tabs(Xa[c - c0]);
+                    if (x > best || (x == best && c < bi)) { best = x; bi = c; }
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    T ob = __shfl_xor(best, off, 64);
+                    int oi = __shfl_xor(bi, off, 64);
+                    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+                }
+                p = bi;
+            }
+            if (lane == 0) {
+                const int pc = p - c0;
+                T d = Xa[pc];
+                if (tabs(d) < tau) {
+                    d = d < T(0) ? -tau : tau;
+                    Xa[pc] = d;
+                    atomicAdd(pert, 1);
+                }
+                TV.tpiv[a] = p;
+                TV.tstep[p] = a;
+                tsw[pc] = a;
+                D.pl[TV.t0 + a] = p - lo;
+                D.qinv[TV.t0 + p] = TV.t0 + a;
+                s_p = pc;
+                s_d = d;
+            }
+        }
+        __syncthreads();
+        const int pc = s_p;
+        const T d = s_d;
+        if (tid < np - ar - 1) {
+            T* Xr = Xw + (ar + 1 + tid) * wc;
+            T l = Xr[pc] / d;
+            Xr[pc] = l;
+            lrow[ar + 1 + tid] = l;
+        }
+        __syncthreads();
+        for (int c = lane; c < wc; c += 64) {
+            if (tsw[c] <= a) continue;
+            const T u = Xa[c];
+            for (int r = ar + 1 + wv; r < np; r += 4) Xw[r * wc + c] -= lrow[r] * u;
+        }
+        __syncthreads();
+    }
+#pragma unroll 4
+    for (int r = wv; r < np; r += 4)
+        for (int c = lane; c < wc; c += 64) vals[rowoff[r] + c0 + c] = Xw[r * wc + c];
 }
 
 // blocks [0, nA): panel rows' U for columns >= c1 (one thread per column);
@@ -572,60 +784,93 @@ __global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ v
                 for (int bb = b + 1; bb < kNB; bb++) y[bb] -= l * M[b][bb];
             }
         }
+        T* lb = reinterpret_cast<T*>(TV.lbuf);
 #pragma unroll
-        for (int b = 0; b < kNB; b++) if (b < np) Xr[piv[b]] = y[b];
+        for (int b = 0; b < kNB; b++) {
+            if (b < np) Xr[piv[b]] = y[b];
+            lb[(int64_t)b * TV.mT + r] = b < np ? y[b] : T(0);   // k-major copy for the trailing update
+        }
     }
 }
 
-// trailing update X[r][c] -= sum_b X[r][tpiv[p0+b]] X[p0+b][c], r >= p1,
-// c >= cg0 still unpivoted after the panel; 64 x 64 tile per block
+// trailing update X[r][c] -= sum_b L[r][b] X[p0+b][c] for r >= p1 and the
+// columns c >= cg0 still unpivoted after the panel, on 16x16x4 MFMA tiles.
+// One wavefront computes a 64 x 64 tile as 4 x 4 blocks; operand fragments
+// are loaded straight from global memory (lbuf is k-major, the panel rows are
+// row-major, so 16 lanes read 16 consecutive values).
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    // output item v of lane l: row (l / 16) + 4 v, column l % 16
+    static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <> struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    // output item v of lane l: row 4 (l / 16) + v, column l % 16
+    static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ vals, int p0, int p1, int cg0)
+__global__ __launch_bounds__(64) void k_tail_gemm(TailView TV, T* __restrict__ vals, int p0, int p1, int cg0)
 {
-    __shared__ T As[kNB][kNB + 1];
-    __shared__ T Bs[kNB][kNB + 1];
-    __shared__ int64_t rowA[kNB];
-    __shared__ int pivs[kNB];
-    const int np = p1 - p0, mT = TV.mT, tid = threadIdx.x;
-    const int rt = p1 + blockIdx.y * 64, ct = cg0 + blockIdx.x * 64;
-    for (int i = tid; i < 64; i += 256) {
-        int row = rt + i;
-        rowA[i] = row < mT ? TV.trow[row] : -1;
-        if (i < np) pivs[i] = TV.tpiv[p0 + i];
-    }
-    __syncthreads();
-    for (int idx = tid; idx < 64 * kNB; idx += 256) {
-        int r = idx / kNB, b = idx % kNB;
-        As[r][b] = (rowA[r] >= 0 && b < np) ? vals[rowA[r] + pivs[b]] : T(0);
-    }
-    for (int idx = tid; idx < kNB * 64; idx += 256) {
-        int b = idx / 64, c = idx % 64, col = ct + c;
-        Bs[b][c] = (b < np && col < mT) ? vals[TV.trow[p0 + b] + col] : T(0);
-    }
-    __syncthreads();
-    const int tx = tid % 16, ty = tid / 16;
-    T acc[4][4];
+    typedef typename Mfma<T>::v4 v4;
+    const int lane = threadIdx.x;
+    const int np = p1 - p0, mT = TV.mT;
+    const int r0 = p1 + blockIdx.y * 64, c0 = cg0 + blockIdx.x * 64;
+    const T* lb = reinterpret_cast<const T*>(TV.lbuf);
+    const int li = lane & 15, lk = lane >> 4;      // fragment row/column and k within a 4-step
+    int64_t brow[kNB / 4];                          // panel row offsets this lane reads, per k-step
+    v4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = T(0);
-    for (int b = 0; b < np; b++) {
-        T av[4], bv[4];
+        for (int j = 0; j < 4; j++) acc[i][j] = v4{T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int i = 0; i < 4; i++) { av[i] = As[ty * 4 + i][b]; bv[i] = Bs[b][tx * 4 + i]; }
+    for (int ks = 0; ks < kNB / 4; ks++) {
+        const int k = ks * 4 + lk;
+        brow[ks] = k < np ? TV.trow[p0 + k] : -1;
+    }
+    const int nks = (np + 3) / 4;
+    T af[4], bf[4], an[4], bn[4];
+    auto load = [&](int ks, T* A, T* B) {
+        const int k = ks * 4 + lk;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int r = r0 + 16 * i + li;
+            A[i] = (k < np && r < mT) ? lb[(int64_t)k * mT + r] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int c = c0 + 16 * j + li;
+            B[j] = (brow[ks] >= 0 && c < mT) ? vals[brow[ks] + c] : T(0);
+        }
+    };
+    load(0, af, bf);
+#pragma unroll
+    for (int ks = 0; ks < kNB / 4; ks++) {
+        if (ks >= nks) break;
+        if (ks + 1 < nks) load(ks + 1, an, bn);
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
-            for (int j = 0; j < 4; j++) acc[i][j] += av[i] * bv[j];
+            for (int j = 0; j < 4; j++) acc[i][j] = Mfma<T>::mma(af[i], bf[j], acc[i][j]);
+#pragma unroll
+        for (int q = 0; q < 4; q++) { af[q] = an[q]; bf[q] = bn[q]; }
     }
 #pragma unroll
     for (int i = 0; i < 4; i++) {
-        int r = ty * 4 + i;
-        if (rowA[r] < 0) continue;
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            int col = ct + tx * 4 + j;
-            if (col < mT && TV.tstep[col] >= p1) vals[rowA[r] + col] -= acc[i][j];
+        for (int v = 0; v < 4; v++) {
+            const int r = r0 + 16 * i + Mfma<T>::row(lane, v);
+            if (r >= mT) continue;
+            T* Xr = vals + TV.trow[r];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int c = c0 + 16 * j + li;
+                if (c < mT && TV.tstep[c] >= p1) Xr[c] -= acc[i][j][v];
+            }
         }
     }
 }
@@ -672,43 +917,64 @@ __global__ __launch_bounds__(256) void k_tail_utext(DevLayout D, TailView TV, co
 }
 
 // mode 0 forward (L, ascending), 1 backward (U, descending),
-// 2 U^T (ascending), 3 L^T (descending): the panel's own triangle, one wave
+// 2 U^T (ascending), 3 L^T (descending): the panel's own triangle, one wave;
+// M[i][j] = X_{p0+i}[tpiv[p0+j]] holds L below and U_st on/above the diagonal
 template <typename T>
 __global__ __launch_bounds__(64) void k_tail_tri(TailView TV, const T* __restrict__ vals, int p0, int p1, int n,
                                                  T* __restrict__ y, T* __restrict__ x, int nrhs, int mode)
 {
+    __shared__ T M[kNB][kNB + 1];
+    __shared__ int piv[kNB];
+    __shared__ int64_t ro[kNB];
+    __shared__ T v[kNB];
     const int lane = threadIdx.x;
     const int np = p1 - p0;
     const int t0 = TV.t0;
-    const int b = p0 + lane;
-    const int64_t rowb = lane < np ? TV.trow[b] : 0;
-    const int pivb = lane < np ? TV.tpiv[b] : 0;
+    if (lane < np) { piv[lane] = TV.tpiv[p0 + lane]; ro[lane] = TV.trow[p0 + lane]; }
+    __syncthreads();
+    if (np == kNB) {
+        const int pc = piv[lane];
+        T tmp[kNB];
+#pragma unroll
+        for (int i = 0; i < kNB; i++) tmp[i] = vals[ro[i] + pc];
+#pragma unroll
+        for (int i = 0; i < kNB; i++) M[i][lane] = tmp[i];
+    } else if (lane < np) {
+        const int pc = piv[lane];
+        for (int i = 0; i < np; i++) M[i][lane] = vals[ro[i] + pc];
+    }
+    __syncthreads();
     for (int r = 0; r < nrhs; r++) {
         T* yr = y + (int64_t)r * n + t0;
         T* xr = x + (int64_t)r * n + t0;
-        for (int s = 0; s < np; s++) {
-            const int a = (mode == 1 || mode == 3) ? p1 - 1 - s : p0 + s;
-            const int64_t rowa = TV.trow[a];
-            const int piva = TV.tpiv[a];
+        if (lane < np) {
+            if (mode == 0 || mode == 1) v[lane] = yr[p0 + lane];
+            else if (mode == 2) v[lane] = yr[piv[lane]];
+            else v[lane] = xr[p0 + lane];
+        }
+        __syncthreads();
+        for (int s2 = 0; s2 < np; s2++) {
+            const int a = (mode == 1 || mode == 3) ? np - 1 - s2 : s2;
             T acc = T(0);
-            if (mode == 0) {            // L(a,b) = X_a[piv b], b < a
-                if (b < a && lane < np) acc = vals[rowa + pivb] * yr[b];
-            } else if (mode == 1) {     // U_st(a, piv b), b > a
-                if (b > a && lane < np) acc = vals[rowa + pivb] * xr[pivb];
-            } else if (mode == 2) {     // U_st(b, piv a), b < a
-                if (b < a && lane < np) acc = vals[rowb + piva] * xr[b];
-            } else {                    // L(b, a) = X_b[piv a], b > a
-                if (b > a && lane < np) acc = vals[rowb + piva] * xr[b];
+            if (lane < np) {
+                if (mode == 0 && lane < a) acc = M[a][lane] * v[lane];
+                else if (mode == 1 && lane > a) acc = M[a][lane] * v[lane];
+                else if (mode == 2 && lane < a) acc = M[lane][a] * v[lane];
+                else if (mode == 3 && lane > a) acc = M[lane][a] * v[lane];
             }
             acc = wave_sum(acc);
             if (lane == 0) {
-                if (mode == 0) yr[a] -= acc;
-                else if (mode == 1) xr[piva] = (yr[a] - acc) / vals[rowa + piva];
-                else if (mode == 2) xr[a] = (yr[piva] - acc) / vals[rowa + piva];
-                else xr[a] -= acc;
+                if (mode == 0 || mode == 3) v[a] -= acc;
+                else v[a] = (v[a] - acc) / M[a][a];
             }
             __syncthreads();
         }
+        if (lane < np) {
+            if (mode == 0) yr[p0 + lane] = v[lane];
+            else if (mode == 1) xr[piv[lane]] = v[lane];
+            else xr[p0 + lane] = v[lane];
+        }
+        __syncthreads();
     }
 }
 
@@ -797,14 +1063,16 @@ hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const i
 {
     if (nrows <= 0) return hipSuccess;
     int32_t cap = std::min(maxW, kRowLdsCap);
+    size_t fixed = (size_t)kStage * 4 + 129 * 4 + 4 + 128 * 8;   // indices, edge tables (8-byte aligned)
+    const bool wide = maxW > 1024;                                 // 4 waves per row for long rows
     if (fp32) {
-        size_t sh = sizeof(float) * (size_t)std::max(cap, 1);
-        hipLaunchKernelGGL(k_factor_rows<float>, dim3(nrows), dim3(64), sh, st, D, (float*)vals, rows, nrows, cap,
-                           (float)tau, pert);
+        size_t sh = sizeof(float) * (kStage + (size_t)std::max(cap, 1)) + fixed;
+        if (wide) hipLaunchKernelGGL((k_factor_rows<float, 256>), dim3(nrows), dim3(256), sh, st, D, (float*)vals, rows, nrows, cap, (float)tau, pert);
+        else hipLaunchKernelGGL((k_factor_rows<float, 64>), dim3(nrows), dim3(64), sh, st, D, (float*)vals, rows, nrows, cap, (float)tau, pert);
     } else {
-        size_t sh = sizeof(double) * (size_t)std::max(cap, 1);
-        hipLaunchKernelGGL(k_factor_rows<double>, dim3(nrows), dim3(64), sh, st, D, (double*)vals, rows, nrows, cap,
-                           tau, pert);
+        size_t sh = sizeof(double) * (kStage + (size_t)std::max(cap, 1)) + fixed;
+        if (wide) hipLaunchKernelGGL((k_factor_rows<double, 256>), dim3(nrows), dim3(256), sh, st, D, (double*)vals, rows, nrows, cap, tau, pert);
+        else hipLaunchKernelGGL((k_factor_rows<double, 64>), dim3(nrows), dim3(64), sh, st, D, (double*)vals, rows, nrows, cap, tau, pert);
     }
     return hipGetLastError();
 }
@@ -919,8 +1187,15 @@ hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, v
                              int32_t c0, int32_t c1, double tau, int32_t* pert, int32_t search, hipStream_t st)
 {
     if (p1 - p0 > kNB || p1 <= p0) return hipErrorInvalidValue;
-    if (fp32) hipLaunchKernelGGL(k_tail_panel<float>, dim3(1), dim3(256), 0, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
-    else hipLaunchKernelGGL(k_tail_panel<double>, dim3(1), dim3(256), 0, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+    size_t es = fp32 ? sizeof(float) : sizeof(double);
+    size_t sh = (size_t)(p1 - p0) * (c1 - c0) * es + (size_t)(c1 - c0) * 4;
+    if (sh <= 48 * 1024) {
+        if (fp32) hipLaunchKernelGGL(k_tail_panel_lds<float>, dim3(1), dim3(256), sh, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
+        else hipLaunchKernelGGL(k_tail_panel_lds<double>, dim3(1), dim3(256), sh, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+    } else {
+        if (fp32) hipLaunchKernelGGL((k_tail_panel<float, false>), dim3(1), dim3(256), 0, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
+        else hipLaunchKernelGGL((k_tail_panel<double, false>), dim3(1), dim3(256), 0, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+    }
     return hipGetLastError();
 }
 
@@ -938,8 +1213,8 @@ hipError_t launch_tail_gemm(bool fp32, const TailView& T, void* vals, int32_t p0
 {
     int gx = (int)nblk(std::max(T.mT - cg0, 0), 64), gy = (int)nblk(std::max(T.mT - p1, 0), 64);
     if (gx == 0 || gy == 0) return hipSuccess;
-    if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(gx, gy), dim3(256), 0, st, T, (float*)vals, p0, p1, cg0);
-    else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(gx, gy), dim3(256), 0, st, T, (double*)vals, p0, p1, cg0);
+    if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(gx, gy), dim3(64), 0, st, T, (float*)vals, p0, p1, cg0);
+    else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(gx, gy), dim3(64), 0, st, T, (double*)vals, p0, p1, cg0);
     return hipGetLastError();
 }
 

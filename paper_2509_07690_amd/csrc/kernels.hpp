@@ -56,6 +56,7 @@ struct TailView {
     const int32_t* thi;
     int32_t* tpiv;          // tail-local column of row a's pivot
     int32_t* tstep;         // per tail column: the tail row that pivots it (INT32_MAX before)
+    void* lbuf;             // kNB x mT workspace: the current panel's multipliers, transposed
 };
 
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);

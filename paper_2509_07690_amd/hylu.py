@@ -48,6 +48,11 @@ class Info(C.Structure):
         return d
 
 
+class KernelStats(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int32), ("ms", C.c_double), ("bytes", C.c_double),
+                ("flops", C.c_double)]
+
+
 class SymbolicView(C.Structure):
     _fields_ = [("perm_r", C.c_void_p), ("perm_c", C.c_void_p), ("dr", C.c_void_p), ("dc", C.c_void_p),
                 ("node_ptr", C.c_void_p), ("is_sn", C.c_void_p), ("levels", C.c_void_p)]
@@ -68,6 +73,7 @@ _sigs = {
     "hylu_export_symbolic": [_P, _P],
     "hylu_export_factors": [_P, _P, _P, _P, _P, _P, _P, _P],
     "hylu_export_sizes": [_P, _P],
+    "hylu_profile": [_P, _P, _P, _P, _P, _P, C.c_int32, _P],
 }
 for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
@@ -202,6 +208,17 @@ class Handle:
         _chk(_lib.hylu_grad_values(self.h, _dev_ptr(lam, torch.float64), _dev_ptr(x, torch.float64),
                                    _dev_ptr(g, torch.float64), _stream(stream)), "grad_values")
         return g
+
+    def profile(self, values, b, x, stream=None):
+        """Per-kernel-class device time (HIP events around every launch of one
+        eager refactorisation + solve) with algorithmic bytes and flops."""
+        import torch
+        arr = (KernelStats * 16)()
+        cnt = C.c_int32()
+        _chk(_lib.hylu_profile(self.h, _dev_ptr(values, torch.float64), _dev_ptr(b, torch.float64),
+                               _dev_ptr(x, torch.float64), _stream(stream), arr, 16, C.byref(cnt)), "profile")
+        return [{"name": arr[i].name.decode(), "launches": arr[i].launches, "ms": arr[i].ms,
+                 "bytes": arr[i].bytes, "flops": arr[i].flops} for i in range(cnt.value)]
 
     # ---- inspection -------------------------------------------------------
     def info(self) -> dict:

@@ -1,0 +1,128 @@
+"""C ABI and host analysis on the CPU (no kernel is launched).
+
+* every function declared in include/hylu.h is exported by libhylu.so;
+* the library's analysis (matching, ordering, symbolic structure, flop count,
+  supernode partition, the four level sets) against the oracle, bit-exact;
+* the matching's product against brute force on tiny matrices;
+* error paths forced from the host.
+"""
+import ctypes as C
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_07690_amd import synth
+
+hylu = pytest.importorskip("paper_2509_07690_amd.hylu")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_every_declared_symbol_is_exported():
+    hdr = open(os.path.join(ROOT, "include", "hylu.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    names = set(re.findall(r"\b(hylu_[a-z_]+)\s*\(", hdr))
+    assert len(names) >= 14
+    lib = C.CDLL(hylu.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _check_against_oracle(A, sn=(2, 1 << 30), **opts):
+    h = hylu.Handle(A.row_ptr, A.col, A.val, sn_min=sn[0], sn_max=sn[1], **opts)
+    inf, sym = h.info(), h.symbolic()
+    o = oracle.Oracle(A.n, A.row_ptr, A.col, A.val, sym["perm_r"], sym["perm_c"], sym["dr"], sym["dc"])
+    if opts.get("static_pivot", 1):
+        assert o.check_matching()
+    o.analyse(*sn)
+    s = o.sizes()
+    assert inf["flops"] == s["flops"]
+    assert inf["nnz_l"] == s["nnz_l"] and inf["nnz_u"] == s["nnz_u"]
+    ptr, isn = o.partition_arrays()
+    assert np.array_equal(ptr, sym["node_ptr"]) and np.array_equal(isn, sym["is_sn"])
+    assert np.array_equal(o.level_arrays(), sym["levels"])
+    assert sorted(sym["perm_c"]) == list(range(A.n))
+    return h
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_analysis_random(seed):
+    rng = np.random.default_rng(seed)
+    n = 300
+    M = rng.random((n, n)) < 0.012
+    np.fill_diagonal(M, True)
+    D = np.where(M, rng.standard_normal((n, n)), 0.0)
+    _check_against_oracle(synth.csr_from_dense(D))
+    _check_against_oracle(synth.csr_from_dense(D), sn=(3, 8), ordering="nd")
+
+
+@pytest.mark.parametrize("ordering", ["amd", "nd", "natural"])
+def test_analysis_config0(ordering):
+    A = synth.config(0).A
+    _check_against_oracle(A, ordering=ordering)
+
+
+def test_analysis_batch_members_and_small_circuit():
+    for m in (0, 1):
+        _check_against_oracle(synth.batch_member(m).A)
+    _check_against_oracle(synth.circuit_powerlaw(20000).A, amd_dense=0.1)
+
+
+def test_analysis_small_3d_grids():
+    _check_against_oracle(synth.convdiff3d_7pt(10).A, ordering="nd")
+    _check_against_oracle(synth.convdiff3d_27pt(8, nrhs=1).A, ordering="nd")
+
+
+def test_analysis_user_perm_and_kernel_modes():
+    A = synth.config(0).A
+    q = np.random.default_rng(1).permutation(A.n).astype(np.int32)
+    h = hylu.Handle(A.row_ptr, A.col, A.val, user_perm=q, static_pivot=0)
+    assert np.array_equal(h.symbolic()["perm_c"], q)
+    h = hylu.Handle(A.row_ptr, A.col, A.val, kernel_mode=1)
+    assert h.info()["n_supernodes"] == 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_matching_maximises_the_product(seed):
+    rng = np.random.default_rng(40 + seed)
+    n = 6
+    M = rng.random((n, n)) < 0.6
+    M[np.arange(n), rng.permutation(n)] = True           # at least one perfect matching
+    D = np.where(M, rng.uniform(0.1, 10.0, (n, n)) * rng.choice([-1, 1], (n, n)), 0.0)
+    A = synth.csr_from_coo(n, *np.nonzero(M), D[M])
+    h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="natural")
+    sym = h.symbolic()
+    got = np.prod([abs(D[sym["perm_r"][j], sym["perm_c"][j]]) for j in range(n)])
+    best = max(np.prod([abs(D[p[j], j]) for j in range(n)]) for p in itertools.permutations(range(n)))
+    assert got == pytest.approx(best, rel=1e-12)
+    o = oracle.Oracle(A.n, A.row_ptr, A.col, A.val, sym["perm_r"], sym["perm_c"], sym["dr"], sym["dc"])
+    assert o.check_matching()
+
+
+def _code(fn):
+    with pytest.raises(hylu.HyluError) as e:
+        fn()
+    return e.value.code
+
+
+def test_error_paths():
+    rp = np.array([0, 2, 3], np.int64)
+    assert _code(lambda: hylu.Handle(rp, np.array([1, 0, 1], np.int32), np.ones(3))) == -2      # unsorted
+    assert _code(lambda: hylu.Handle(rp, np.array([0, 0, 1], np.int32), np.ones(3))) == -2      # duplicate
+    assert _code(lambda: hylu.Handle(rp, np.array([0, 5, 1], np.int32), np.ones(3))) == -2      # out of range
+    assert _code(lambda: hylu.Handle(rp, np.array([0, 1, 1], np.int32), np.array([1, np.nan, 1]))) == -8
+    # structurally singular: column 1 empty
+    assert _code(lambda: hylu.Handle(np.array([0, 1, 2], np.int64), np.array([0, 0], np.int32), np.ones(2))) == -3
+    h = hylu.Handle(np.array([0, 1, 2], np.int64), np.array([0, 1], np.int32), np.ones(2))
+    lib = hylu._lib
+    # a solve before any factorisation fails without touching the device
+    assert lib.hylu_solve(h.h, C.c_void_p(8), C.c_void_p(8), 1, 2, 0, None) == -5
+    assert lib.hylu_refactor(h.h, C.c_void_p(8), None) == -5
+    h2 = C.c_void_p()
+    assert lib.hylu_create(C.byref(h2), None) == 0
+    assert lib.hylu_factorize(h2, C.c_void_p(8), None) == -4
+    assert lib.hylu_destroy(h2) == 0
+    assert lib.hylu_solve(None, None, None, 1, 1, 0, None) == -1
