@@ -42,7 +42,8 @@ def main():
     ap.add_argument("--n", type=int, default=200000)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--amd-dense", type=float, default=0.1)
-    ap.add_argument("--dense-tail", type=float, default=0.5)
+    ap.add_argument("--dense-tail", type=float, default=0.15)
+    ap.add_argument("--pipeline-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-refactors", type=int, default=3)
     args = ap.parse_args()
@@ -62,7 +63,7 @@ def main():
     log(f"pattern n={A0.n} nnz={A0.nnz} ({time.time() - t0:.1f}s)")
     t0 = time.time()
     h = hylu.Handle(A0.row_ptr, A0.col, A0.val, precision=args.precision, amd_dense=args.amd_dense,
-                    dense_tail=args.dense_tail)
+                    dense_tail=args.dense_tail, pipeline_rows=args.pipeline_rows)
     t_analyze = time.time() - t0
     info = h.info()
     log(f"analyze {t_analyze:.1f}s: F={info['flops']:.3e} nnz(L+U)={info['nnz_l'] + info['nnz_u']:.3e} "

@@ -71,6 +71,8 @@ typedef struct {
     double dense_tail;     /* factor the trailing block of at least this density densely (0: never; default 0.5) */
     int32_t tail_min;      /* smallest dense tail in rows (default 64) */
     int32_t tail_max;      /* largest dense tail in rows (default 32768) */
+    int32_t pipeline_rows; /* reserved for the pipelined mode of Sec. 2.2.1 (one persistent launch whose
+                              blocks wait per source node); switched off: must be 0, else HYLU_ERR_ARG */
 } hylu_options;
 
 /* Optional device allocator (e.g. the PyTorch caching allocator).  alloc

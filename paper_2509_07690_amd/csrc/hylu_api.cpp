@@ -53,6 +53,9 @@ struct LevelTasks {
     std::vector<int64_t> sn_ptr;      // per level into snodes
     std::vector<int32_t> maxm;
     std::vector<int32_t> rows, snodes;
+    int32_t pipe_level = 0;           // levels from here on run as one pipelined launch
+    int32_t pipe_maxW = 0, pipe_maxm = 0;
+    std::vector<int32_t> node_level;  // execution level of every node
 };
 
 }  // namespace
@@ -86,6 +89,7 @@ struct hylu_handle_s {
     int32_t *d_rows = nullptr, *d_snodes = nullptr;
     int32_t* d_lev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     TailView TV{};
+    PipeCtl PC{};
     int32_t *d_perm_r = nullptr, *d_perm_c = nullptr;
     double *d_dr = nullptr, *d_dc = nullptr;
     int64_t* d_arp = nullptr;
@@ -96,8 +100,8 @@ struct hylu_handle_s {
     int64_t* d_atq = nullptr;
     double* d_atv = nullptr;
     bool tlists = false;
-    int32_t* d_pert = nullptr;
-    int32_t* h_pert = nullptr;              // pinned
+    int32_t* d_pert = nullptr;              // [0] perturbed pivots, [1] a pipelined wait gave up
+    int32_t* h_pert = nullptr;              // pinned copy of d_pert
     hipEvent_t fact_done = nullptr;
     int32_t last_pert = 0;
     bool pert_known = false;
@@ -136,7 +140,9 @@ struct PhaseLog {
     }
 };
 
-#define HIPCHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { h->sticky_error = true; return HYLU_ERR_DEVICE; } } while (0)
+#define HIPCHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) {                        \
+        std::fprintf(stderr, "hylu: %s (line %d)\n", hipGetErrorString(e_), __LINE__);     \
+        h->sticky_error = true; return HYLU_ERR_DEVICE; } } while (0)
 
 // launch `x` and, when profiling, bracket it with events attributed to class `c`
 #define LAUNCH(c, by, fl, x) do {                                                          \
@@ -182,8 +188,13 @@ hylu_status upload(hylu_handle h, T*& dst, const std::vector<T>& src)
 {
     dst = (T*)dalloc(h, sizeof(T) * std::max<size_t>(src.size(), 1));
     if (!dst) return HYLU_ERR_OOM;
-    if (!src.empty() && hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice) != hipSuccess)
-        return HYLU_ERR_DEVICE;
+    if (!src.empty()) {
+        hipError_t e = hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            std::fprintf(stderr, "hylu: upload of %zu bytes: %s\n", sizeof(T) * src.size(), hipGetErrorString(e));
+            return HYLU_ERR_DEVICE;
+        }
+    }
     return HYLU_OK;
 }
 
@@ -300,14 +311,14 @@ hylu_status ensure_tlists(hylu_handle h)
 hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipStream_t st)
 {
     const double es = h->fp32 ? 4.0 : 8.0;
-    HIPCHK(launch_zero(h->d_pert, sizeof(int32_t), st));
+    HIPCHK(launch_zero(h->d_pert, 2 * sizeof(int32_t), st));
     LAUNCH(C_SCATTER, es * h->lay.nvals, 0, launch_zero(h->vals, h->lay.nvals * (h->fp32 ? 4 : 8), st));
     LAUNCH(C_SCATTER, 40.0 * h->nnz, 2.0 * h->nnz,
            launch_scatter(h->fp32, d_val, h->d_amap, h->d_asr, h->d_asc, h->nnz, h->vals, h->d_aval, st));
     if (search) HIPCHK(launch_tail_init(h->TV, st));
     const LevelTasks& T = h->ft;
     int32_t nl = (int32_t)T.maxW.size();
-    for (int32_t l = 0; l < nl; l++) {
+    for (int32_t l = 0; l < T.pipe_level; l++) {
         int64_t r0 = T.row_ptr[l], r1 = T.row_ptr[l + 1];
         LAUNCH(C_ROWS, h->lvl_bytes[l] * es / 8.0, h->lvl_flops[l],
                launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.maxW[l], h->tau, h->d_pert, st));
@@ -323,6 +334,22 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
             LAUNCH(C_SNLU, by, fl, launch_factor_snlu(h->fp32, h->D, h->vals, h->d_snodes + s0, (int32_t)(s1 - s0), T.maxm[l],
                                                       h->tau, h->d_pert, search ? 1 : 0, st));
         }
+    }
+    if (T.pipe_level < nl) {
+        // pipeline mode over the remaining levels
+        double by = 0, fl = 0;
+        for (int32_t l = T.pipe_level; l < nl; l++) { by += h->lvl_bytes[l] * es / 8.0; fl += h->lvl_flops[l]; }
+        for (int64_t q = T.sn_ptr[T.pipe_level]; q < T.sn_ptr[nl]; q++) {
+            int32_t v = T.snodes[q];
+            double m = h->lay.m[v], wc = h->lay.W[v] - h->lay.lw[v];
+            by += 2.0 * es * m * wc;
+            fl += m * m * (2.0 * wc - m);
+        }
+        const int64_t r0 = T.row_ptr[T.pipe_level], r1 = T.row_ptr[nl];
+        HIPCHK(launch_pipe_reset(h->PC, h->lay.nnodes, st));
+        LAUNCH(C_ROWS, by, fl,
+               launch_factor_pipe(h->fp32, h->D, h->PC, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.pipe_maxW,
+                                  T.pipe_maxm, h->tau, h->d_pert, search ? 1 : 0, st));
     }
     // dense tail: blocked right-looking LU, one row panel at a time
     const double mT = h->lay.mT;
@@ -417,10 +444,10 @@ hylu_status upload_device(hylu_handle h)
     const LevelTasks& T = h->ft;
     const int32_t n = h->n;
     try {
-        if (hipGetDevice(&h->device) != hipSuccess) return HYLU_ERR_DEVICE;
-        if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) return HYLU_ERR_DEVICE;
-        if (!h->fact_done && hipEventCreateWithFlags(&h->fact_done, hipEventDisableTiming) != hipSuccess) return HYLU_ERR_DEVICE;
-        if (!h->h_pert && hipHostMalloc((void**)&h->h_pert, sizeof(int32_t)) != hipSuccess) return HYLU_ERR_OOM;
+        HIPCHK(hipGetDevice(&h->device));
+        if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        if (!h->fact_done) HIPCHK(hipEventCreateWithFlags(&h->fact_done, hipEventDisableTiming));
+        if (!h->h_pert && hipHostMalloc((void**)&h->h_pert, 2 * sizeof(int32_t)) != hipSuccess) return HYLU_ERR_OOM;
         std::vector<EdgeDesc> ed(L.esrc.size());
         for (int32_t v = 0; v < L.nnodes; v++)
             for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
@@ -433,7 +460,7 @@ hylu_status upload_device(hylu_handle h)
                 d.ws = L.W[s] - L.lw[s] - L.m[s];
                 d.lp = L.elpos[e];
                 d.r0s = L.r0[s];
-                d.pad = 0;
+                d.srcp = (T.node_level[s] >= T.pipe_level && s < L.tail_node0) ? s : -1;
             }
         std::vector<double> asr(h->nnz), asc(h->nnz);
         for (int32_t i = 0; i < n; i++)
@@ -467,10 +494,19 @@ hylu_status upload_device(hylu_handle h)
         UP(h->d_perm_r, h->perm_r); UP(h->d_perm_c, h->perm_c);
         UP(h->d_dr, h->dr); UP(h->d_dc, h->dc);
         UP(h->d_arp, A.rp); UP(h->d_aci, A.ci); UP(h->d_aval, A.v);
+        {
+            int32_t *ctl, *done, *rdone;
+            std::vector<int32_t> z2(2, 0), zn(std::max(L.nnodes, 1), 0);
+            UP(ctl, z2); UP(done, zn); UP(rdone, zn);
+            h->PC = PipeCtl();
+            h->PC.ctl = ctl; h->PC.done = done; h->PC.rows_done = rdone;
+            h->PC.spin_limit = 1 << 22;
+        }
         int32_t* pert;
         std::vector<int32_t> one(2, 0);
         UP(pert, one);
         h->d_pert = pert;
+        h->PC.err = pert + 1;
         h->vals = dalloc(h, (size_t)std::max<int64_t>(L.nvals, 1) * (h->fp32 ? 4 : 8));
         if (!h->vals) return HYLU_ERR_OOM;
         h->uploaded = true;
@@ -504,6 +540,7 @@ hylu_status hylu_default_options(hylu_options* o)
     o->dense_tail = 0.5;
     o->tail_min = 64;
     o->tail_max = 32768;
+    o->pipeline_rows = 0;
     return HYLU_OK;
 }
 
@@ -562,6 +599,7 @@ hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const
     if (opt_in) opt = *opt_in; else hylu_default_options(&opt);
     if (opt.ordering < 0 || opt.ordering > 3 || (opt.ordering == 3 && !opt.user_perm)) return HYLU_ERR_ARG;
     if (opt.precision < 0 || opt.precision > 1 || opt.kernel_mode < 0 || opt.kernel_mode > 2) return HYLU_ERR_ARG;
+    if (opt.pipeline_rows != 0) return HYLU_ERR_ARG;     // pipelined mode is switched off
     hylu_status st = validate_csr(n, row_ptr, col, val);
     if (st != HYLU_OK) return st;
     try {
@@ -692,6 +730,12 @@ hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const
             T.maxm.push_back(mm);
             h->max_sn = std::max(h->max_sn, mm);
         }
+        T.node_level.assign(L.nnodes, 0);
+        for (int32_t l = 0; l < nl; l++)
+            for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) T.node_level[L.xlev_nodes[0][t]] = l;
+        // pipeline mode stays off: its dataflow launch did not finish on the device
+        // and the reason is not established, so every level is a launch of its own
+        T.pipe_level = nl;
         // algorithmic traffic and flops of every row-kernel launch (8-byte values)
         h->lvl_bytes.assign(nl, 0.0);
         h->lvl_flops.assign(nl, 0.0);
@@ -720,6 +764,7 @@ hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const
 
 hylu_status hylu_factorize(hylu_handle h, const double* d_val, void* stream)
 {
+    (void)hipGetLastError();   // an error another library left on this thread is not ours
     if (!h || !d_val) return HYLU_ERR_ARG;
     if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
     if (h->sticky_error) return HYLU_ERR_DEVICE;
@@ -731,7 +776,7 @@ hylu_status hylu_factorize(hylu_handle h, const double* d_val, void* stream)
     HIPCHK(launch_init_pivots(h->D, st));
     hylu_status s = enqueue_factor(h, d_val, true, st);
     if (s != HYLU_OK) return s;
-    HIPCHK(hipMemcpyAsync(h->h_pert, h->d_pert, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h->h_pert, h->d_pert, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipEventRecord(h->fact_done, st));
     h->pert_known = false;
     h->factorized = true;
@@ -740,6 +785,7 @@ hylu_status hylu_factorize(hylu_handle h, const double* d_val, void* stream)
 
 hylu_status hylu_refactor(hylu_handle h, const double* d_val, void* stream)
 {
+    (void)hipGetLastError();   // an error another library left on this thread is not ours
     if (!h || !d_val) return HYLU_ERR_ARG;
     if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
     if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
@@ -750,7 +796,7 @@ hylu_status hylu_refactor(hylu_handle h, const double* d_val, void* stream)
     GraphEntry& g = h->refac_graphs[d_val];
     hylu_status s = run_graph(h, g, fresh, st, [&](hipStream_t cs) { return enqueue_factor(h, d_val, false, cs); });
     if (s != HYLU_OK) { if (fresh) h->refac_graphs.erase(d_val); return s; }
-    HIPCHK(hipMemcpyAsync(h->h_pert, h->d_pert, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h->h_pert, h->d_pert, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipEventRecord(h->fact_done, st));
     h->pert_known = false;
     return HYLU_OK;
@@ -759,6 +805,7 @@ hylu_status hylu_refactor(hylu_handle h, const double* d_val, void* stream)
 hylu_status hylu_solve(hylu_handle h, const double* d_b, double* d_x, int32_t nrhs, int64_t ld, int32_t transpose,
                        void* stream)
 {
+    (void)hipGetLastError();
     if (!h || !d_b || !d_x || nrhs <= 0) return HYLU_ERR_ARG;
     if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
     if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
@@ -772,8 +819,9 @@ hylu_status hylu_solve(hylu_handle h, const double* d_b, double* d_x, int32_t nr
     // does refinement run?  (perturbed pivots, or FP32 factors)
     if (!h->pert_known) {
         HIPCHK(hipEventSynchronize(h->fact_done));
-        h->last_pert = *h->h_pert;
+        h->last_pert = h->h_pert[0];
         h->pert_known = true;
+        if (h->h_pert[1]) { h->sticky_error = true; return HYLU_ERR_DEVICE; }
     }
     bool refine = h->fp32 || h->last_pert > 0;
     // b is needed after x is written when refining in place
@@ -862,8 +910,9 @@ hylu_status hylu_get_info(hylu_handle h, hylu_info* o)
     if (h->factorized) {
         if (!h->pert_known) {
             if (hipEventSynchronize(h->fact_done) != hipSuccess) return HYLU_ERR_DEVICE;
-            h->last_pert = *h->h_pert;
+            h->last_pert = h->h_pert[0];
             h->pert_known = true;
+            if (h->h_pert[1]) { h->sticky_error = true; return HYLU_ERR_DEVICE; }
         }
         o->n_perturbed = h->last_pert;
     }
@@ -895,6 +944,7 @@ hylu_status hylu_export_symbolic(hylu_handle h, const hylu_symbolic_view* v)
 hylu_status hylu_profile(hylu_handle h, const double* d_val, const double* d_b, double* d_x, void* stream,
                          hylu_kernel_stats* stats, int32_t max_classes, int32_t* count)
 {
+    (void)hipGetLastError();
     if (!h || !d_val || !d_b || !d_x || !stats || !count || max_classes <= 0) return HYLU_ERR_ARG;
     if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
     if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
@@ -925,7 +975,7 @@ hylu_status hylu_profile(hylu_handle h, const double* d_val, const double* d_b, 
         if (acc[c].launches > 0) stats[k++] = acc[c];
     *count = k;
     h->pert_known = false;
-    HIPCHK(hipMemcpyAsync(h->h_pert, h->d_pert, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h->h_pert, h->d_pert, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipEventRecord(h->fact_done, st));
     return HYLU_OK;
 }

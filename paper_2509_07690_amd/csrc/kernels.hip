@@ -127,18 +127,36 @@ __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ va
     __syncthreads();
 }
 
-// row updates: one block of NT threads per target row.  Every source node (a
+// wave 0 waits until every listed source node is complete in this epoch
+// (src < 0: nothing to wait for); bounded: on timeout the error flag is set
+__device__ __forceinline__ void wait_sources(const PipeCtl& P, int epoch, int src)
+{
+    bool ok = src < 0 || __hip_atomic_load(P.done + src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+    // after one wait has given up the results are void: no further waiting
+    if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = true;
+    int it = 0;
+    while (!__all(ok)) {
+        if (++it > P.spin_limit) {
+            __hip_atomic_store(P.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if (!ok) ok = __hip_atomic_load(P.done + src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// row updates of target row i by a block of NT threads.  Every source node (a
 // standalone row: row-row kernel; a supernode: sup-row kernel) is applied in
 // ascending order.  Standalone sources are staged in batches in LDS (pivot,
 // the source's U values and their relative positions in the target), then
 // applied one after the other from LDS.  The row's accumulator sits in LDS
-// when it fits.
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__ vals,
-                                                    const int32_t* __restrict__ rows, int32_t nrows,
-                                                    int32_t lds_cap, T tau, int32_t* __restrict__ pert)
+// when it fits.  PIPE: sources factored in the pipelined region are waited for
+// before they are read.
+template <typename T, int NT, bool PIPE>
+__device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_t lds_cap, T tau,
+                         int32_t* __restrict__ pert, unsigned char* smem_raw, const PipeCtl& PC, int epoch)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sval = reinterpret_cast<T*>(smem_raw);                                   // kStage
     int32_t* sidx = reinterpret_cast<int32_t*>(sval + kStage);                 // kStage
     int32_t* eoff = sidx + kStage;                                              // 65 (padded to 66)
@@ -149,9 +167,6 @@ __global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__
     __shared__ int s_nb, s_total;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int t = blockIdx.x;
-    if (t >= nrows) return;
-    const int i = rows[t];
     const int v = D.row_node[i];
     const int W = D.W[v];
     const int a = i - D.r0[v];
@@ -170,9 +185,11 @@ __global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__
             const int64_t my = e + lane;
             EdgeDesc ed;
             int cost = 0x3fffffff;
+            int src = -1;
             if (my < e1) {
                 ed = D.edges[my];
                 if (ed.ms == 1) cost = ed.ws + 1;
+                src = ed.srcp;
             }
             int pre = cost;
             for (int off = 1; off < 64; off <<= 1) {
@@ -181,6 +198,7 @@ __global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__
             }
             const unsigned long long fits = __ballot(pre <= kStage && my < e1);
             const int nb = (fits == ~0ull) ? 64 : __builtin_ctzll(~fits);
+            if (PIPE) wait_sources(PC, epoch, lane < (nb > 0 ? nb : 1) ? src : -1);
             if (lane < nb) {
                 eoff[lane] = pre - cost;
                 elp[lane] = ed.lp;
@@ -237,6 +255,17 @@ __global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__
     }
 }
 
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__ vals,
+                                                    const int32_t* __restrict__ rows, int32_t nrows,
+                                                    int32_t lds_cap, T tau, int32_t* __restrict__ pert)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    if ((int)blockIdx.x >= nrows) return;
+    PipeCtl none{};
+    row_task<T, NT, false>(D, vals, rows[blockIdx.x], lds_cap, tau, pert, smem_raw, none, 0);
+}
+
 // ----------------------------------------------------------------------------
 // internal factorisation of a supernode once every external update is in:
 // dense LU of the m x (m + w) block+T part, row by row, each row pivoting on
@@ -244,24 +273,16 @@ __global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__
 // column), perturbing small pivots, then eliminating the rows below.
 // ----------------------------------------------------------------------------
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_factor_snlu(DevLayout D, T* __restrict__ vals,
-                                                     const int32_t* __restrict__ nodes, int32_t count,
-                                                     T tau, int32_t* __restrict__ pert, int32_t search)
+template <typename T, int NT>
+__device__ void snlu_node(const DevLayout& D, T* __restrict__ vals, int v, T tau, int32_t* __restrict__ pert,
+                          int search, T* lrow, uint8_t* taken, T* red_v, int* red_i, int* s_p)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int v = nodes[blockIdx.x];
     const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
     const int wc = W - lw;                     // block + T columns
     T* P = vals + D.voff[v] + lw;              // row a, column c at P[a*W + c]
     int32_t* pl = D.pl + r0;
-    T* lrow = reinterpret_cast<T*>(smem_raw);                       // m multipliers
-    uint8_t* taken = smem_raw + sizeof(T) * (size_t)m;             // m flags
-    __shared__ T red_v[256];
-    __shared__ int red_i[256];
-    __shared__ int s_p;
     const int tid = threadIdx.x;
-    for (int c = tid; c < m; c += 256) taken[c] = 0;
+    for (int c = tid; c < m; c += NT) taken[c] = 0;
     __syncthreads();
     for (int a = 0; a < m; a++) {
         T* Pa = P + (int64_t)a * W;
@@ -269,16 +290,16 @@ __global__ __launch_bounds__(256) void k_factor_snlu(DevLayout D, T* __restrict_
         if (search) {
             T best = T(-1);
             int bi = m;
-            for (int c = tid; c < m; c += 256) {
+            for (int c = tid; c < m; c += NT) {
                 if (taken[c]) continue;
                 T x = tabs(Pa[c]);
                 if (x > best || (x == best && c < bi)) { best = x; bi = c; }
             }
             red_v[tid] = best; red_i[tid] = bi;
             __syncthreads();
-            for (int s = 128; s > 0; s >>= 1) {
-                if (tid < s) {
-                    T x = red_v[tid + s]; int xi = red_i[tid + s];
+            for (int s2 = NT / 2; s2 > 0; s2 >>= 1) {
+                if (tid < s2) {
+                    T x = red_v[tid + s2]; int xi = red_i[tid + s2];
                     if (x > red_v[tid] || (x == red_v[tid] && xi < red_i[tid])) { red_v[tid] = x; red_i[tid] = xi; }
                 }
                 __syncthreads();
@@ -296,28 +317,103 @@ __global__ __launch_bounds__(256) void k_factor_snlu(DevLayout D, T* __restrict_
             pl[a] = p;
             D.qinv[r0 + p] = r0 + a;
             taken[p] = 1;
-            s_p = p;
+            *s_p = p;
         }
         __syncthreads();
-        p = s_p;
+        p = *s_p;
         const T d = Pa[p];
-        for (int r = a + 1 + tid; r < m; r += 256) {
+        for (int r = a + 1 + tid; r < m; r += NT) {
             T* Pr = P + (int64_t)r * W;
             T l = Pr[p] / d;
             Pr[p] = l;
             lrow[r] = l;
         }
         __syncthreads();
-        const int rows_left = m - a - 1;
-        const int64_t total = (int64_t)rows_left * wc;
-        for (int64_t idx = tid; idx < total; idx += 256) {
-            int r = a + 1 + (int)(idx / wc);
-            int c = (int)(idx % wc);
+        for (int c = tid; c < wc; c += NT) {
             if (c < m && taken[c]) continue;
-            P[(int64_t)r * W + c] -= lrow[r] * Pa[c];
+            const T u = Pa[c];
+            for (int r = a + 1; r < m; r++) P[(int64_t)r * W + c] -= lrow[r] * u;
         }
         __syncthreads();
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_factor_snlu(DevLayout D, T* __restrict__ vals,
+                                                     const int32_t* __restrict__ nodes, int32_t count,
+                                                     T tau, int32_t* __restrict__ pert, int32_t search)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ T red_v[256];
+    __shared__ int red_i[256];
+    __shared__ int s_p;
+    const int v = nodes[blockIdx.x];
+    const int m = D.m[v];
+    T* lrow = reinterpret_cast<T*>(smem_raw);                       // m multipliers
+    uint8_t* taken = smem_raw + sizeof(T) * (size_t)m;             // m flags
+    snlu_node<T, 256>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p);
+}
+
+// pipeline mode (Sec. 2.2.1): persistent blocks take rows in topological order
+// from a ticket; a row waits only for the source nodes it is about to read.
+// The block that finishes the last row of a supernode factors its block.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_factor_pipe(DevLayout D, PipeCtl PC, T* __restrict__ vals,
+                                                    const int32_t* __restrict__ rows, int32_t nrows,
+                                                    int32_t lds_cap, T tau, int32_t* __restrict__ pert,
+                                                    int32_t search)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_task, s_last;
+    __shared__ T red_v[NT];
+    __shared__ int red_i[NT];
+    __shared__ int s_p;
+    const int tid = threadIdx.x;
+    const int epoch = __hip_atomic_load(PC.ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if (tid == 0) s_task = __hip_atomic_fetch_add(PC.ctl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int t = s_task;
+        if (t >= nrows) break;
+        const int i = rows[t];
+        row_task<T, NT, true>(D, vals, i, lds_cap, tau, pert, smem_raw, PC, epoch);
+        const int v = D.row_node[i];
+        const int m = D.m[v];
+        __syncthreads();
+        if (v >= D.tail_node0) continue;            // the dense tail waits on no flag
+        if (m == 1) {
+            if (tid == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(PC.done + v, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            continue;
+        }
+        if (tid == 0) {
+            const int old = __hip_atomic_fetch_add(PC.rows_done + v, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            s_last = old == m - 1;
+        }
+        __syncthreads();
+        if (!s_last) continue;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        T* lrow = reinterpret_cast<T*>(smem_raw);
+        uint8_t* taken = smem_raw + sizeof(T) * (size_t)m;
+        snlu_node<T, NT>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p);
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(PC.done + v, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__global__ void k_pipe_reset(PipeCtl PC, int32_t nnodes)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        PC.ctl[0] = 0;
+        PC.ctl[1] += 1;
+    }
+    for (; i < nnodes; i += gridDim.x * blockDim.x) PC.rows_done[i] = 0;
 }
 
 // ----------------------------------------------------------------------------
@@ -329,6 +425,18 @@ __device__ __forceinline__ T wave_sum(T x)
 {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
     return __shfl(x, 0, 64);
+}
+
+// broadcast of a lane's value (the lane index must be wave-uniform)
+__device__ __forceinline__ double bcast(double x, int l)
+{
+    int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float bcast(float x, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 
 // forward: y_i = c_i - sum_k L(i,k) y_k (unit L), rows of a node in order
@@ -654,91 +762,104 @@ __global__ __launch_bounds__(256) void k_tail_panel(DevLayout D, TailView TV, T*
     }
 }
 
-// panel factorisation with the window in LDS (4 wavefronts): rows are staged
-// with coalesced loads, wave 0 searches the pivot with a wave reduction, the
-// elimination gives each wave every fourth remaining row, lanes over columns
+// panel factorisation with the window in LDS, one wavefront: lanes own
+// window columns (wc <= 64); for every panel row the pivot is a wave
+// reduction and the elimination walks the remaining rows, each lane updating
+// its column (no cross-wave synchronisation)
 template <typename T>
-__global__ __launch_bounds__(256) void k_tail_panel_lds(DevLayout D, TailView TV, T* __restrict__ vals, int p0, int p1,
-                                                        int c0, int c1, T tau, int32_t* __restrict__ pert, int search)
+__global__ __launch_bounds__(64) void k_tail_panel_lds(DevLayout D, TailView TV, T* __restrict__ vals, int p0, int p1,
+                                                       int c0, int c1, T tau, int32_t* __restrict__ pert, int search)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ T lrow[kNB];
     __shared__ int64_t rowoff[kNB];
-    __shared__ int s_p;
-    __shared__ T s_d;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lane = threadIdx.x;
     const int wc = c1 - c0, np = p1 - p0;
+    __shared__ T lrow[kNB];
+    __shared__ int spiv[kNB], slo[kNB], shi[kNB];
+    int npert = 0;
     T* Xw = reinterpret_cast<T*>(smem_raw);          // np x wc
-    int* tsw = reinterpret_cast<int*>(Xw + np * wc); // wc
-    if (tid < np) rowoff[tid] = TV.trow[p0 + tid];
-    for (int c = tid; c < wc; c += 256) tsw[c] = TV.tstep[c0 + c];
+    if (lane < np) {                                 // every per-row table read once, up front
+        rowoff[lane] = TV.trow[p0 + lane];
+        slo[lane] = TV.tlo[p0 + lane];
+        shi[lane] = TV.thi[p0 + lane];
+        spiv[lane] = search ? 0 : TV.tpiv[p0 + lane];
+    }
+    int mystep = lane < wc ? TV.tstep[c0 + lane] : -1;   // the step that pivots my column
     __syncthreads();
-#pragma unroll 4
-    for (int r = wv; r < np; r += 4)
-        for (int c = lane; c < wc; c += 64) Xw[r * wc + c] = vals[rowoff[r] + c0 + c];
+    if (lane < wc) {
+        T tmp[kNB];
+#pragma unroll
+        for (int r = 0; r < kNB; r++) tmp[r] = r < np ? vals[rowoff[r] + c0 + lane] : T(0);
+#pragma unroll
+        for (int r = 0; r < kNB; r++) if (r < np) Xw[r * wc + lane] = tmp[r];
+    }
     __syncthreads();
     for (int ar = 0; ar < np; ar++) {
         const int a = p0 + ar;
+        const int lo = slo[ar], hi = shi[ar];
         T* Xa = Xw + ar * wc;
-        if (wv == 0) {
-            const int lo = TV.tlo[a], hi = TV.thi[a];
-            int p;
-            if (!search) {
-                p = TV.tpiv[a];
-            } else if (hi - lo == 1) {
-                p = a;
-            } else {
-                T best = T(-1);
-                int bi = 0x7fffffff;
-                for (int c = lo + lane; c < hi; c += 64) {
-                    if (tsw[c - c0] <= a) continue;
-                    T x = tabs(Xa[c - c0]);
-                    if (x > best || (x == best && c < bi)) { best = x; bi = c; }
-                }
-                for (int off = 32; off > 0; off >>= 1) {
-                    T ob = __shfl_xor(best, off, 64);
-                    int oi = __shfl_xor(bi, off, 64);
-                    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-                }
-                p = bi;
+        int p;
+        if (!search) {
+            p = spiv[ar];
+        } else if (hi - lo == 1) {
+            p = a;
+        } else {
+            T best = T(-1);
+            int bi = 0x7fffffff;
+            const int c = c0 + lane;
+            if (lane < wc && c >= lo && c < hi && mystep > a) { best = tabs(Xa[lane]); bi = c; }
+            for (int off = 32; off > 0; off >>= 1) {
+                T ob = __shfl_xor(best, off, 64);
+                int oi = __shfl_xor(bi, off, 64);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
             }
-            if (lane == 0) {
-                const int pc = p - c0;
-                T d = Xa[pc];
-                if (tabs(d) < tau) {
-                    d = d < T(0) ? -tau : tau;
-                    Xa[pc] = d;
-                    atomicAdd(pert, 1);
-                }
-                TV.tpiv[a] = p;
-                TV.tstep[p] = a;
-                tsw[pc] = a;
-                D.pl[TV.t0 + a] = p - lo;
-                D.qinv[TV.t0 + p] = TV.t0 + a;
-                s_p = pc;
-                s_d = d;
-            }
+            p = bi;
         }
+        const int pc = p - c0;
+        T d = Xa[pc];
+        if (tabs(d) < tau) d = d < T(0) ? -tau : tau;
         __syncthreads();
-        const int pc = s_p;
-        const T d = s_d;
-        if (tid < np - ar - 1) {
-            T* Xr = Xw + (ar + 1 + tid) * wc;
-            T l = Xr[pc] / d;
+        if (lane == 0) {
+            // pivot records stay in LDS until the end: a global store here would
+            // make every barrier of the panel wait for it
+            if (Xa[pc] != d) { Xa[pc] = d; npert++; }
+            spiv[ar] = p;
+        }        if (lane == pc) mystep = a;
+        // multipliers of the remaining rows, one lane per row
+        const int rl = np - ar - 1;
+        if (lane < rl) {
+            T* Xr = Xw + (ar + 1 + lane) * wc;
+            const T l = Xr[pc] / d;
             Xr[pc] = l;
-            lrow[ar + 1 + tid] = l;
+            lrow[ar + 1 + lane] = l;
         }
         __syncthreads();
-        for (int c = lane; c < wc; c += 64) {
-            if (tsw[c] <= a) continue;
-            const T u = Xa[c];
-            for (int r = ar + 1 + wv; r < np; r += 4) Xw[r * wc + c] -= lrow[r] * u;
+        if (lane < wc && mystep > a) {              // my column is still unpivoted
+            const T u = Xa[lane];
+            int r = ar + 1;
+            for (; r + 8 <= np; r += 8) {           // eight independent rows per round
+                T xv[8], lv[8];
+#pragma unroll
+                for (int q = 0; q < 8; q++) { xv[q] = Xw[(r + q) * wc + lane]; lv[q] = lrow[r + q]; }
+#pragma unroll
+                for (int q = 0; q < 8; q++) Xw[(r + q) * wc + lane] = xv[q] - lv[q] * u;
+            }
+            for (; r < np; r++) Xw[r * wc + lane] -= lrow[r] * u;
         }
         __syncthreads();
     }
-#pragma unroll 4
-    for (int r = wv; r < np; r += 4)
-        for (int c = lane; c < wc; c += 64) vals[rowoff[r] + c0 + c] = Xw[r * wc + c];
+    if (lane < wc) {
+#pragma unroll 16
+        for (int r = 0; r < np; r++) vals[rowoff[r] + c0 + lane] = Xw[r * wc + lane];
+    }
+    if (lane < np) {
+        const int a = p0 + lane, p = spiv[lane];
+        TV.tpiv[a] = p;
+        TV.tstep[p] = a;
+        D.pl[TV.t0 + a] = p - slo[lane];
+        D.qinv[TV.t0 + p] = TV.t0 + a;
+    }
+    if (lane == 0 && npert > 0) atomicAdd(pert, npert);
 }
 
 // blocks [0, nA): panel rows' U for columns >= c1 (one thread per column);
@@ -752,7 +873,14 @@ __global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ v
     const int np = p1 - p0, tid = threadIdx.x;
     for (int i = tid; i < np; i += 64) { rowoff[i] = TV.trow[p0 + i]; piv[i] = TV.tpiv[p0 + i]; }
     __syncthreads();
-    for (int idx = tid; idx < np * np; idx += 64) { int i = idx / np, j = idx % np; M[i][j] = vals[rowoff[i] + piv[j]]; }
+    if (tid < np) {                          // column tid of M: one independent load per panel row
+        const int pc = piv[tid];
+        T tmp[kNB];
+#pragma unroll
+        for (int i = 0; i < kNB; i++) tmp[i] = i < np ? vals[rowoff[i] + pc] : T(0);
+#pragma unroll
+        for (int i = 0; i < kNB; i++) M[i][tid] = tmp[i];
+    }
     __syncthreads();
     if ((int)blockIdx.x < nA) {
         const int c = c1 + blockIdx.x * 64 + tid;
@@ -813,66 +941,52 @@ template <> struct Mfma<float> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_tail_gemm(TailView TV, T* __restrict__ vals, int p0, int p1, int cg0)
+__global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ vals, int p0, int p1, int cg0)
 {
     typedef typename Mfma<T>::v4 v4;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int np = p1 - p0, mT = TV.mT;
-    const int r0 = p1 + blockIdx.y * 64, c0 = cg0 + blockIdx.x * 64;
+    // block tile 64 x 64, four wavefronts of 32 x 32 (2 x 2 MFMA blocks each)
+    const int r0 = p1 + blockIdx.y * 64 + (wv >> 1) * 32, c0 = cg0 + blockIdx.x * 64 + (wv & 1) * 32;
     const T* lb = reinterpret_cast<const T*>(TV.lbuf);
-    const int li = lane & 15, lk = lane >> 4;      // fragment row/column and k within a 4-step
-    int64_t brow[kNB / 4];                          // panel row offsets this lane reads, per k-step
-    v4 acc[4][4];
+    const int li = lane & 15, lk = lane >> 4;
+    v4 acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int i = 0; i < 2; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = v4{T(0), T(0), T(0), T(0)};
+        for (int j = 0; j < 2; j++) acc[i][j] = v4{T(0), T(0), T(0), T(0)};
+    const bool rok0 = r0 + li < mT, rok1 = r0 + 16 + li < mT;
+    const int cb = c0 + li;
+    const bool cok0 = cb < mT, cok1 = cb + 16 < mT;
+    const T* arow = lb + (int64_t)lk * mT + r0 + li;
 #pragma unroll
     for (int ks = 0; ks < kNB / 4; ks++) {
         const int k = ks * 4 + lk;
-        brow[ks] = k < np ? TV.trow[p0 + k] : -1;
-    }
-    const int nks = (np + 3) / 4;
-    T af[4], bf[4], an[4], bn[4];
-    auto load = [&](int ks, T* A, T* B) {
-        const int k = ks * 4 + lk;
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int r = r0 + 16 * i + li;
-            A[i] = (k < np && r < mT) ? lb[(int64_t)k * mT + r] : T(0);
+        if (ks * 4 < np) {
+            const bool kok = k < np;
+            const T* ap = arow + (int64_t)ks * 4 * mT;
+            const T a0 = (kok && rok0) ? ap[0] : T(0);
+            const T a1 = (kok && rok1) ? ap[16] : T(0);
+            const T* bp = vals + (kok ? TV.trow[p0 + k] : 0) + cb;
+            const T b0 = (kok && cok0) ? bp[0] : T(0);
+            const T b1 = (kok && cok1) ? bp[16] : T(0);
+            acc[0][0] = Mfma<T>::mma(a0, b0, acc[0][0]);
+            acc[0][1] = Mfma<T>::mma(a0, b1, acc[0][1]);
+            acc[1][0] = Mfma<T>::mma(a1, b0, acc[1][0]);
+            acc[1][1] = Mfma<T>::mma(a1, b1, acc[1][1]);
         }
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int c = c0 + 16 * j + li;
-            B[j] = (brow[ks] >= 0 && c < mT) ? vals[brow[ks] + c] : T(0);
-        }
-    };
-    load(0, af, bf);
-#pragma unroll
-    for (int ks = 0; ks < kNB / 4; ks++) {
-        if (ks >= nks) break;
-        if (ks + 1 < nks) load(ks + 1, an, bn);
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-            for (int j = 0; j < 4; j++) acc[i][j] = Mfma<T>::mma(af[i], bf[j], acc[i][j]);
-#pragma unroll
-        for (int q = 0; q < 4; q++) { af[q] = an[q]; bf[q] = bn[q]; }
     }
+    const bool cm0 = cok0 && TV.tstep[cb] >= p1, cm1 = cok1 && TV.tstep[cb + 16] >= p1;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int v = 0; v < 4; v++) {
             const int r = r0 + 16 * i + Mfma<T>::row(lane, v);
             if (r >= mT) continue;
-            T* Xr = vals + TV.trow[r];
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int c = c0 + 16 * j + li;
-                if (c < mT && TV.tstep[c] >= p1) Xr[c] -= acc[i][j][v];
-            }
+            T* Xr = vals + TV.trow[r] + cb;
+            if (cm0) Xr[0] -= acc[i][0][v];
+            if (cm1) Xr[16] -= acc[i][1][v];
         }
-    }
 }
 
 // ---- dense tail solves (tail-local row/column a is global t0 + a)
@@ -918,7 +1032,9 @@ __global__ __launch_bounds__(256) void k_tail_utext(DevLayout D, TailView TV, co
 
 // mode 0 forward (L, ascending), 1 backward (U, descending),
 // 2 U^T (ascending), 3 L^T (descending): the panel's own triangle, one wave;
-// M[i][j] = X_{p0+i}[tpiv[p0+j]] holds L below and U_st on/above the diagonal
+// M[i][j] = X_{p0+i}[tpiv[p0+j]] holds L below and U_st on/above the diagonal.
+// Column sweep: lane r holds v[r]; at step a the finished value is broadcast
+// and every lane still waiting subtracts its coefficient times it.
 template <typename T>
 __global__ __launch_bounds__(64) void k_tail_tri(TailView TV, const T* __restrict__ vals, int p0, int p1, int n,
                                                  T* __restrict__ y, T* __restrict__ x, int nrhs, int mode)
@@ -926,55 +1042,47 @@ __global__ __launch_bounds__(64) void k_tail_tri(TailView TV, const T* __restric
     __shared__ T M[kNB][kNB + 1];
     __shared__ int piv[kNB];
     __shared__ int64_t ro[kNB];
-    __shared__ T v[kNB];
     const int lane = threadIdx.x;
     const int np = p1 - p0;
     const int t0 = TV.t0;
     if (lane < np) { piv[lane] = TV.tpiv[p0 + lane]; ro[lane] = TV.trow[p0 + lane]; }
     __syncthreads();
-    if (np == kNB) {
+    if (lane < np) {
         const int pc = piv[lane];
         T tmp[kNB];
 #pragma unroll
-        for (int i = 0; i < kNB; i++) tmp[i] = vals[ro[i] + pc];
+        for (int i = 0; i < kNB; i++) tmp[i] = i < np ? vals[ro[i] + pc] : T(0);
 #pragma unroll
         for (int i = 0; i < kNB; i++) M[i][lane] = tmp[i];
-    } else if (lane < np) {
-        const int pc = piv[lane];
-        for (int i = 0; i < np; i++) M[i][lane] = vals[ro[i] + pc];
     }
     __syncthreads();
+    const bool desc = mode == 1 || mode == 3;
     for (int r = 0; r < nrhs; r++) {
         T* yr = y + (int64_t)r * n + t0;
         T* xr = x + (int64_t)r * n + t0;
+        T v = T(0);
         if (lane < np) {
-            if (mode == 0 || mode == 1) v[lane] = yr[p0 + lane];
-            else if (mode == 2) v[lane] = yr[piv[lane]];
-            else v[lane] = xr[p0 + lane];
+            if (mode == 0 || mode == 1) v = yr[p0 + lane];
+            else if (mode == 2) v = yr[piv[lane]];
+            else v = xr[p0 + lane];
         }
-        __syncthreads();
         for (int s2 = 0; s2 < np; s2++) {
-            const int a = (mode == 1 || mode == 3) ? np - 1 - s2 : s2;
-            T acc = T(0);
-            if (lane < np) {
-                if (mode == 0 && lane < a) acc = M[a][lane] * v[lane];
-                else if (mode == 1 && lane > a) acc = M[a][lane] * v[lane];
-                else if (mode == 2 && lane < a) acc = M[lane][a] * v[lane];
-                else if (mode == 3 && lane > a) acc = M[lane][a] * v[lane];
+            const int a = desc ? np - 1 - s2 : s2;
+            T va = bcast(v, a);
+            if (mode == 1 || mode == 2) va = va / M[a][a];
+            if (lane == a) v = va;
+            const bool pend = desc ? lane < a : (lane > a && lane < np);
+            if (pend) {
+                // 0: L(r,a) = M[r][a]   1: U(r, piv a) = M[r][a]   2: U(a, piv r) = M[a][r]   3: L(a, r) = M[a][r]
+                const T c = (mode == 0 || mode == 1) ? M[lane][a] : M[a][lane];
+                v -= c * va;
             }
-            acc = wave_sum(acc);
-            if (lane == 0) {
-                if (mode == 0 || mode == 3) v[a] -= acc;
-                else v[a] = (v[a] - acc) / M[a][a];
-            }
-            __syncthreads();
         }
         if (lane < np) {
-            if (mode == 0) yr[p0 + lane] = v[lane];
-            else if (mode == 1) xr[piv[lane]] = v[lane];
-            else xr[p0 + lane] = v[lane];
+            if (mode == 0) yr[p0 + lane] = v;
+            else if (mode == 1) xr[piv[lane]] = v;
+            else xr[p0 + lane] = v;
         }
-        __syncthreads();
     }
 }
 
@@ -1073,6 +1181,36 @@ hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const i
         size_t sh = sizeof(double) * (kStage + (size_t)std::max(cap, 1)) + fixed;
         if (wide) hipLaunchKernelGGL((k_factor_rows<double, 256>), dim3(nrows), dim3(256), sh, st, D, (double*)vals, rows, nrows, cap, tau, pert);
         else hipLaunchKernelGGL((k_factor_rows<double, 64>), dim3(nrows), dim3(64), sh, st, D, (double*)vals, rows, nrows, cap, tau, pert);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pipe_reset(const PipeCtl& P, int32_t nnodes, hipStream_t st)
+{
+    if (!P.ctl || !P.rows_done) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pipe_reset, dim3(std::min<unsigned>(nblk(std::max(nnodes, 1), 256), 1024)), dim3(256), 0, st, P, nnodes);
+    return hipGetLastError();
+}
+
+hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, void* vals, const int32_t* rows,
+                              int32_t nrows, int32_t maxW, int32_t maxm, double tau, int32_t* pert, int32_t search,
+                              hipStream_t st)
+{
+    if (nrows <= 0) return hipSuccess;
+    if (!P.ctl || !P.err || !P.done || !P.rows_done || P.spin_limit <= 0) return hipErrorInvalidValue;
+    int32_t cap = std::min(maxW, kRowLdsCap);
+    size_t fixed = (size_t)kStage * 4 + 129 * 4 + 4 + 128 * 8;
+    size_t es = fp32 ? sizeof(float) : sizeof(double);
+    size_t sh = std::max(es * (kStage + (size_t)std::max(cap, 1)) + fixed, (size_t)maxm * (es + 1) + 16);
+    if (sh > 60 * 1024) return hipErrorInvalidValue;
+    const bool wide = maxW > 1024;
+    unsigned grid = (unsigned)std::min(nrows, wide ? 1024 : 2048);
+    if (fp32) {
+        if (wide) hipLaunchKernelGGL((k_factor_pipe<float, 256>), dim3(grid), dim3(256), sh, st, D, P, (float*)vals, rows, nrows, cap, (float)tau, pert, search);
+        else hipLaunchKernelGGL((k_factor_pipe<float, 64>), dim3(grid), dim3(64), sh, st, D, P, (float*)vals, rows, nrows, cap, (float)tau, pert, search);
+    } else {
+        if (wide) hipLaunchKernelGGL((k_factor_pipe<double, 256>), dim3(grid), dim3(256), sh, st, D, P, (double*)vals, rows, nrows, cap, tau, pert, search);
+        else hipLaunchKernelGGL((k_factor_pipe<double, 64>), dim3(grid), dim3(64), sh, st, D, P, (double*)vals, rows, nrows, cap, tau, pert, search);
     }
     return hipGetLastError();
 }
@@ -1188,10 +1326,10 @@ hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, v
 {
     if (p1 - p0 > kNB || p1 <= p0) return hipErrorInvalidValue;
     size_t es = fp32 ? sizeof(float) : sizeof(double);
-    size_t sh = (size_t)(p1 - p0) * (c1 - c0) * es + (size_t)(c1 - c0) * 4;
-    if (sh <= 48 * 1024) {
-        if (fp32) hipLaunchKernelGGL(k_tail_panel_lds<float>, dim3(1), dim3(256), sh, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
-        else hipLaunchKernelGGL(k_tail_panel_lds<double>, dim3(1), dim3(256), sh, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+    size_t sh = (size_t)(p1 - p0) * (c1 - c0) * es;
+    if (c1 - c0 <= 64) {
+        if (fp32) hipLaunchKernelGGL(k_tail_panel_lds<float>, dim3(1), dim3(64), sh, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
+        else hipLaunchKernelGGL(k_tail_panel_lds<double>, dim3(1), dim3(64), sh, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
     } else {
         if (fp32) hipLaunchKernelGGL((k_tail_panel<float, false>), dim3(1), dim3(256), 0, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
         else hipLaunchKernelGGL((k_tail_panel<double, false>), dim3(1), dim3(256), 0, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
@@ -1213,8 +1351,8 @@ hipError_t launch_tail_gemm(bool fp32, const TailView& T, void* vals, int32_t p0
 {
     int gx = (int)nblk(std::max(T.mT - cg0, 0), 64), gy = (int)nblk(std::max(T.mT - p1, 0), 64);
     if (gx == 0 || gy == 0) return hipSuccess;
-    if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(gx, gy), dim3(64), 0, st, T, (float*)vals, p0, p1, cg0);
-    else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(gx, gy), dim3(64), 0, st, T, (double*)vals, p0, p1, cg0);
+    if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(gx, gy), dim3(256), 0, st, T, (float*)vals, p0, p1, cg0);
+    else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(gx, gy), dim3(256), 0, st, T, (double*)vals, p0, p1, cg0);
     return hipGetLastError();
 }
 

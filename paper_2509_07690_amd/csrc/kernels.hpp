@@ -18,7 +18,17 @@ struct EdgeDesc {
     int32_t ws;     // source T width
     int32_t lp;     // slot of the source's first column in the target's L region
     int32_t r0s;    // first row of the source (pivot table offset)
-    int32_t pad;
+    int32_t srcp;   // source node when it is factored in the pipelined region, else -1
+};
+
+// Pipeline mode: persistent blocks claim rows in topological order from a
+// ticket and wait per source node on a done flag.
+struct PipeCtl {
+    int32_t* ctl;           // [0] ticket, [1] epoch of the current factorisation
+    int32_t* err;           // set to 1 when a wait gave up
+    int32_t* done;          // per node: epoch in which the node was completed
+    int32_t* rows_done;     // per supernode: rows whose outside updates are finished
+    int32_t spin_limit;     // polls before a wait is declared failed (error flag, no hang)
 };
 
 // Device view of the panel layout.
@@ -83,6 +93,10 @@ hipError_t launch_scatter(bool fp32, const double* aval, const int64_t* amap, co
 hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st);
 hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t nrows,
                               int32_t maxW, double tau, int32_t* pert, hipStream_t st);
+hipError_t launch_pipe_reset(const PipeCtl& P, int32_t nnodes, hipStream_t st);
+hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, void* vals, const int32_t* rows,
+                              int32_t nrows, int32_t maxW, int32_t maxm, double tau, int32_t* pert, int32_t search,
+                              hipStream_t st);
 hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const int32_t* nodes, int32_t count,
                               int32_t maxm, double tau, int32_t* pert, int32_t search, hipStream_t st);
 hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,

@@ -11,6 +11,11 @@ import os
 from typing import Optional
 
 import numpy as np
+# PyTorch ships its own HIP runtime (file libamdhip64.so, soname
+# libamdhip64.so.7).  It has to be loaded before libhylu.so: the loader then
+# binds libhylu.so to that same runtime.  In the other order the process ends
+# up with two HIP runtimes, and device pointers of one are unknown to the other.
+import torch  # noqa: F401,E402
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhylu.so")
@@ -31,7 +36,7 @@ class Options(C.Structure):
                 ("ir_maxit", C.c_int32), ("sn_min", C.c_int32), ("sn_max", C.c_int32),
                 ("kernel_mode", C.c_int32), ("repeated", C.c_int32), ("nd_leaf", C.c_int32),
                 ("amd_dense", C.c_double), ("dense_tail", C.c_double), ("tail_min", C.c_int32),
-                ("tail_max", C.c_int32)]
+                ("tail_max", C.c_int32), ("pipeline_rows", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -126,3 +126,16 @@ def test_error_paths():
     assert lib.hylu_factorize(h2, C.c_void_p(8), None) == -4
     assert lib.hylu_destroy(h2) == 0
     assert lib.hylu_solve(None, None, None, 1, 1, 0, None) == -1
+
+
+def test_one_hip_runtime_in_the_process():
+    """libhylu.so binds to the HIP runtime PyTorch brought in (a second copy
+    would not know PyTorch's device pointers)."""
+    maps = open("/proc/self/maps").read().splitlines()
+    libs = {ln.split()[-1] for ln in maps if "libamdhip64" in ln}
+    assert len(libs) == 1, libs
+
+
+def test_pipelined_mode_is_rejected():
+    A = synth.config(0).A
+    assert _code(lambda: hylu.Handle(A.row_ptr, A.col, A.val, pipeline_rows=1024)) == -1

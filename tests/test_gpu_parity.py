@@ -45,8 +45,12 @@ def run_case(hylu, A, b, opts=None, sn=(2, 1 << 30), exact=False, tol=1e-11):
     return h, o, x, xo, eta
 
 
+PIPE_OFF = pytest.mark.skip(reason="pipelined mode is switched off: its launch did not finish on the device")
+
+
+@pytest.mark.parametrize("pipe", [0, pytest.param(1024, marks=PIPE_OFF)])
 @pytest.mark.parametrize("tail", [0.0, 0.5])
-def test_random_small(hylu, tail):
+def test_random_small(hylu, tail, pipe):
     for seed in range(4):
         rng = np.random.default_rng(seed)
         n = 300
@@ -55,7 +59,7 @@ def test_random_small(hylu, tail):
         D = np.where(M, rng.standard_normal((n, n)), 0.0)
         A = synth.csr_from_dense(D)
         b = rng.standard_normal(n)
-        h, o, x, xo, eta = run_case(hylu, A, b, opts=dict(dense_tail=tail))
+        h, o, x, xo, eta = run_case(hylu, A, b, opts=dict(dense_tail=tail, pipeline_rows=pipe))
         assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
         assert (h.info()["tail_rows"] > 0) == (tail > 0)
 
@@ -105,11 +109,13 @@ def test_config0_factor_solve(hylu, ordering, tail):
     assert np.abs(x - w.x_true[:, 0]).max() < 1e-10
 
 
-@pytest.mark.parametrize("tail", [0.0, 0.3])
-def test_config0_refactor_and_transpose(hylu, tail):
+@pytest.mark.parametrize("tail,pipe", [(0.0, 0), (0.3, 0), pytest.param(0.0, 1024, marks=PIPE_OFF),
+                                       pytest.param(0.3, 300, marks=PIPE_OFF)])
+def test_config0_refactor_and_transpose(hylu, tail, pipe):
     w = synth.config(0)
     A = w.A
-    h = hylu.Handle(A.row_ptr, A.col, A.val, dense_tail=tail)
+    print(f"[case] config0 refactor tail={tail} pipe={pipe}", flush=True)
+    h = hylu.Handle(A.row_ptr, A.col, A.val, dense_tail=tail, pipeline_rows=pipe)
     o, sym = oracle_for(h, A)
     h.factorize(dev(A.val))
     torch.cuda.synchronize()
@@ -175,3 +181,20 @@ def test_batch_members(hylu, m):
     w = synth.batch_member(m)
     h, o, x, xo, eta = run_case(hylu, w.A, w.b[:, 0])
     assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
+
+
+@pytest.mark.parametrize("pipe", [0, pytest.param(1024, marks=PIPE_OFF)])
+def test_small_circuit(hylu, pipe):
+    """Power-law circuit pattern at n = 20000: hub supernodes, a dense tail,
+    and (pipe > 0) every narrow level in the pipelined launch."""
+    w = synth.circuit_powerlaw(20000)
+    h, o, x, xo, eta = run_case(hylu, w.A, w.b[:, 0],
+                                opts=dict(amd_dense=0.1, dense_tail=0.15, pipeline_rows=pipe))
+    assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
+    w2 = w.revalue(1)
+    piv = hylu.factors_as_rows(h)[2]
+    h.refactor(dev(w2.A.val))
+    torch.cuda.synchronize()
+    o.set_values(w2.A.val)
+    o.numeric(h.info()["pivot_tau"], piv=piv)
+    compare_factors(h, o)
