@@ -46,10 +46,16 @@ def main():
     ap.add_argument("--pipeline-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-refactors", type=int, default=3)
+    ap.add_argument("--workload", default="circuit", choices=["circuit", "batch", "grid27", "adjoint"],
+                    help="circuit (default): the headline line; the others print their own line")
+    ap.add_argument("--members", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload != "circuit":
+        {"batch": bench_batch, "grid27": bench_grid27, "adjoint": bench_adjoint}[args.workload](args)
+        return
 
     import torch
     from paper_2509_07690_amd import synth, hylu
@@ -151,6 +157,127 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def _timed(fn, steps, warmup):
+    """Runs fn() warmup times, then times `steps` calls between two device
+    synchronisations; returns ms per call."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def _line(metric, value, unit, args, dtype, config, **extra):
+    out = {"metric": metric, "value": round(value, 4), "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(value, 4), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out))
+
+
+def bench_batch(args):
+    """The uneven batch: `members` matrices (even: local circuits n ~ U{2000..
+    50000}; odd: 9-point grids, side ~ U{32..160}) on one handle; a step
+    refactorises every member with its fresh values (one graph) and solves one
+    right-hand side each.  Launch shapes come from the autotuner (untimed)."""
+    import torch
+    from paper_2509_07690_amd import synth, hylu
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    ws = [synth.batch_member(m) for m in range(args.members)]
+    a0 = [w.extra["analyze_values"] for w in ws]
+    log(f"members {len(ws)} n={sum(w.A.n for w in ws)} ({time.time() - t0:.1f}s)")
+    t0 = time.time()
+    hb = hylu.Handle.batch([(a.row_ptr, a.col, a.val) for a in a0], precision=args.precision)
+    t_an = time.time() - t0
+    inf = hb.info()
+    log(f"analyze {t_an:.1f}s F={inf['flops']:.3e} levels={inf['n_levels']}")
+    v0 = torch.from_numpy(np.concatenate([a.val for a in a0])).to(dev)
+    v1 = torch.from_numpy(np.concatenate([w.A.val for w in ws])).to(dev)
+    b = torch.from_numpy(np.concatenate([w.b[:, 0] for w in ws])).to(dev)
+    x = torch.empty_like(b)
+    hb.factorize(v0)
+    t_def, t_tuned = hb.autotune(v1, reps=2)
+    log(f"autotune: level time {t_def:.2f} ms with built-in shapes, {t_tuned:.2f} ms tuned")
+
+    def step():
+        hb.refactor(v1)
+        hb.solve(b, out=x)
+    ms = _timed(step, args.steps, args.warmup)
+    t_ref = _timed(lambda: hb.refactor(v1), args.steps, 1)
+    roff, _ = hb.offsets()
+    xs = x.cpu().numpy()
+    err = max(float(np.abs(xs[roff[k]:roff[k + 1]] - w.x_true[:, 0]).max()) for k, w in enumerate(ws))
+    info = hb.info()
+    _line(f"batch refactor+solve ms ({len(ws)} uneven matrices, one handle)", ms, "ms", args,
+          "f64" if args.precision == "fp64" else "f32+f64ir",
+          {"workload": f"uneven batch of {len(ws)}: circuits n~U[2000,50000] + 9-pt grids side~U[32,160]",
+           "members": len(ws), "n_total": hb.n, "nnz_total": hb.nnz, "precision": args.precision},
+          refactor_ms=round(t_ref, 4), factor_gflops=round(info["flops"] / (t_ref * 1e-3) / 1e9, 3),
+          flops=info["flops"], autotune_level_ms={"builtin": round(t_def, 3), "tuned": round(t_tuned, 3)},
+          max_abs_err_vs_x_true=err, ir_iters=info["ir_iters"], berr=info["berr"], analyze_s=round(t_an, 2))
+
+
+def bench_grid27(args):
+    """27-point 3D convection-diffusion on side^3 (ND ordering), 8 RHS."""
+    import torch
+    from paper_2509_07690_amd import synth, hylu
+    side = args.n if args.n != 200000 else 64
+    w = synth.convdiff3d_27pt(side)
+    A = w.A
+    t0 = time.time()
+    h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd", precision=args.precision, dense_tail=args.dense_tail)
+    t_an = time.time() - t0
+    v = torch.from_numpy(A.val).cuda()
+    B = torch.from_numpy(np.ascontiguousarray(w.b.T)).cuda()       # (8, n): column-major RHS
+    X = torch.empty_like(B)
+    h.factorize(v)
+    ms = _timed(lambda: (h.refactor(v), h.solve_cols(B, out=X)), args.steps, args.warmup)
+    t_ref = _timed(lambda: h.refactor(v), args.steps, 1)
+    info = h.info()
+    err = float(np.abs(X.cpu().numpy().T - w.x_true).max())
+    _line(f"refactor+solve ms (27-pt grid {side}^3, 8 rhs)", ms, "ms", args,
+          "f64" if args.precision == "fp64" else "f32+f64ir",
+          {"workload": f"convdiff3d_27pt side={side} n={A.n} nnz={A.nnz}, 8 rhs", "precision": args.precision},
+          refactor_ms=round(t_ref, 4), factor_gflops=round(info["flops"] / (t_ref * 1e-3) / 1e9, 3),
+          flops=info["flops"], max_abs_err_vs_x_true=err, ir_iters=info["ir_iters"], berr=info["berr"],
+          analyze_s=round(t_an, 2), tail_rows=info["tail_rows"])
+
+
+def bench_adjoint(args):
+    """x = A^{-1} b and the gradient of 0.5||x - x_target||^2 with respect to
+    the values of A and b, on the 7-point grid side^3 (ND): forward
+    (refactor + solve) and backward (transposed solve + pattern gradient)."""
+    import torch
+    from paper_2509_07690_amd import synth, hylu
+    side = args.n if args.n != 200000 else 48
+    w = synth.convdiff3d_7pt(side)
+    A = w.A
+    h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd", dense_tail=args.dense_tail)
+    v = torch.from_numpy(A.val).cuda()
+    b = torch.from_numpy(np.ascontiguousarray(w.b[:, 0])).cuda()
+    xt = torch.from_numpy(w.extra["x_target"]).cuda()
+    h.factorize(v)
+
+    def fwd():
+        return hylu.sparse_solve(h, v, b)
+
+    def fwd_bwd():
+        vv = v.clone().requires_grad_()
+        bb = b.clone().requires_grad_()
+        x = hylu.sparse_solve(h, vv, bb)
+        (0.5 * ((x - xt) ** 2).sum()).backward()
+    t_f = _timed(fwd, args.steps, args.warmup)
+    t_fb = _timed(fwd_bwd, args.steps, args.warmup)
+    _line(f"adjoint forward+backward ms (7-pt grid {side}^3)", t_fb, "ms", args, "f64",
+          {"workload": f"convdiff3d_7pt side={side} n={A.n} nnz={A.nnz}, loss 0.5||x-x_target||^2"},
+          forward_ms=round(t_f, 4), backward_ms=round(t_fb - t_f, 4), flops=h.info()["flops"])
 
 
 def cpu_baseline(A0, base, h, nref, first):

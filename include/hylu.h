@@ -71,6 +71,9 @@ typedef struct {
     double dense_tail;     /* factor the trailing block of at least this density densely (0: never; default 0.5) */
     int32_t tail_min;      /* smallest dense tail in rows (default 64) */
     int32_t tail_max;      /* largest dense tail in rows (default 32768) */
+    int32_t sn_dense;      /* supernodes outside the dense tail with at least this many rows are factored by
+                              the blocked panel / TRSM / MFMA-GEMM kernels instead of one workgroup each
+                              (0: never; default 128) */
     int32_t pipeline_rows; /* reserved for the pipelined mode of Sec. 2.2.1 (one persistent launch whose
                               blocks wait per source node); switched off: must be 0, else HYLU_ERR_ARG */
 } hylu_options;
@@ -126,13 +129,34 @@ hylu_status hylu_destroy(hylu_handle h);
 hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const int32_t* col,
                          const double* val, const hylu_options* opt);
 
+/* Batched analysis of `count` matrices of uneven sizes on one handle.  The
+ * handle's matrix is their block diagonal: member k owns rows and columns
+ * [row_off[k], row_off[k+1]) and values [nnz_off[k], nnz_off[k+1]) in member
+ * order (hylu_batch_offsets), so hylu_factorize / hylu_refactor take the
+ * members' value arrays back to back and hylu_solve their right-hand sides
+ * back to back.  Every member is matched, scaled and ordered on its own (on
+ * host threads); the structural analysis then runs once on the union, so the
+ * members' levels share every launch and one refactorisation of the whole
+ * batch replays as one HIP graph.  opt->ordering 3 (user) is rejected and
+ * dense_tail is not used.  Iterative refinement stops on the largest
+ * backward error over the members and right-hand sides.  n, row_ptr, col,
+ * val: host arrays of count entries, each pointing at a member's host CSR. */
+hylu_status hylu_analyze_batch(hylu_handle h, int32_t count, const int32_t* n, const int64_t* const* row_ptr,
+                               const int32_t* const* col, const double* const* val, const hylu_options* opt);
+
+/* Member layout of a batched handle (one member after hylu_analyze):
+ * *count, and row_off / nnz_off of count+1 entries each (host; may be null). */
+hylu_status hylu_batch_offsets(hylu_handle h, int32_t* count, int64_t* row_off, int64_t* nnz_off);
+
 /* Numerical factorisation with pivot search (Sec. 2.2).  d_val: device,
  * nnz float64 values in the CSR order given to hylu_analyze. */
 hylu_status hylu_factorize(hylu_handle h, const double* d_val, void* stream);
 
 /* Refactorisation with new values on the same pattern, reusing the pivot
  * order of the last hylu_factorize (the repeated-solve scenario, Sec. 3.2).
- * Perturbation stays active.  The level sequence is replayed as a HIP graph. */
+ * Perturbation stays active.  The level sequence is replayed as a HIP graph,
+ * one per d_val address (at most 16 are kept; the cache is emptied, after a
+ * device synchronisation, when a 17th address arrives). */
 hylu_status hylu_refactor(hylu_handle h, const double* d_val, void* stream);
 
 /* Forward-backward substitution (Sec. 2.3): solves A x = b (transpose = 0) or
@@ -141,7 +165,8 @@ hylu_status hylu_refactor(hylu_handle h, const double* d_val, void* stream);
  * refinement in FP64 runs when a pivot was perturbed or precision = 1; its
  * residual uses the handle's copy of the values of the last (re)factorisation.
  * Synchronises the stream when refinement runs (the stopping test
- * reads the backward error on the host). */
+ * reads the backward error on the host).  Graphs are cached per
+ * (d_b, d_x, nrhs, ld, transpose) like those of hylu_refactor. */
 hylu_status hylu_solve(hylu_handle h, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
                        int32_t transpose, void* stream);
 
@@ -166,6 +191,18 @@ hylu_status hylu_export_symbolic(hylu_handle h, const hylu_symbolic_view* v);
 hylu_status hylu_export_factors(hylu_handle h, double* vals, int64_t* node_voff, int32_t* node_lw,
                                 int32_t* node_W, int64_t* node_coff, int32_t* cols, int32_t* piv);
 hylu_status hylu_export_sizes(hylu_handle h, int64_t* ncols_total);
+
+/* Autotuner of the factorisation's launch shapes: for every level, the threads
+ * given to one target row (64, 128 or 256) and to one supernode's internal
+ * LU (64 or 256).  Runs `reps` rounds of three complete refactorisations with
+ * d_val (each trial gives every level one shape; every shape computes
+ * bit-identical factors), times each level's launches with HIP events on
+ * `stream`, keeps the fastest shape per level and drops the refactorisation
+ * graphs captured before.  Leaves the factors of d_val.  ms_default /
+ * ms_tuned (host, may be null): summed level times with the built-in shapes
+ * and with the chosen ones.  Needs a prior hylu_factorize (pivot order). */
+hylu_status hylu_autotune(hylu_handle h, const double* d_val, void* stream, int32_t reps, double* ms_default,
+                          double* ms_tuned);
 
 /* Per-kernel-class measurement of one refactorisation + solve, run eagerly
  * (not from the graph) with a pair of HIP events around every launch on

@@ -80,6 +80,9 @@ void make_levels(const Symbolic& s, Nodes& nd);
 // with one shared sorted column list.  The L region holds the multipliers for
 // whole source nodes (one slot per source row), the diagonal block holds the
 // node's own L\U in pivoted column order, T the columns of U past the block.
+// rows per factorisation panel inside a node wider than one panel
+constexpr int32_t kWideChunk = 16;
+
 struct Layout {
     int32_t n = 0, nnodes = 0;
     std::vector<int32_t> r0, m, lw, W;  // per node
@@ -101,6 +104,7 @@ struct Layout {
     std::vector<int32_t> tlo, thi;      // per tail row: tail-local block range of its node
     struct Panel { int32_t p0, p1, c0, c1, cg0; };
     std::vector<Panel> panels;          // row panels of the dense tail LU
+    std::vector<Panel> spanels;         // row panels of the dense tail solves (whole nodes or 64-row chunks)
     // execution level lists (node ids by level, then index):
     // 0 factor updates (every node; tail nodes take their outside sources only)
     // 1 U solve, 2 U^T solve, 3 L^T solve, 4 L solve (nodes before the tail)

@@ -354,23 +354,31 @@ bool build_layout(const Csr& b, const Symbolic& s, const Nodes& nd, int32_t tail
                 L.thi[r] = L.r0[v] + L.m[v] - t0;
             }
         // panels: whole nodes up to panel_rows rows; a larger node is cut into
-        // chunks that share its block as pivot window
-        int32_t NB = std::max(panel_rows, 1);
-        int32_t cp0 = -1, cp1 = -1;
-        auto flush = [&]() { if (cp0 >= 0) L.panels.push_back({cp0, cp1, cp0, cp1, cp1}); cp0 = cp1 = -1; };
-        for (int32_t v = tail_node0; v < nn; v++) {
-            int32_t a0 = L.r0[v] - t0, m = L.m[v];
-            if (m > NB) {
-                flush();
-                for (int32_t k = 0; k < m; k += NB)
-                    L.panels.push_back({a0 + k, std::min(a0 + k + NB, a0 + m), a0, a0 + m, a0});
-            } else {
-                if (cp0 >= 0 && cp1 - cp0 + m > NB) flush();
-                if (cp0 < 0) cp0 = a0;
-                cp1 = a0 + m;
+        // chunks that share its block as pivot window.  The factorisation cuts
+        // such nodes into chunks of kWideChunk rows: the panel kernel of a wide
+        // window runs on one workgroup and its traffic grows with the chunk
+        // height, while the trailing update runs chip-wide.  The solves keep
+        // panel_rows-row chunks.
+        const int32_t NB = std::max(panel_rows, 1);
+        auto build = [&](std::vector<Layout::Panel>& out, int32_t chunk) {
+            int32_t cp0 = -1, cp1 = -1;
+            auto flush = [&]() { if (cp0 >= 0) out.push_back({cp0, cp1, cp0, cp1, cp1}); cp0 = cp1 = -1; };
+            for (int32_t v = tail_node0; v < nn; v++) {
+                int32_t a0 = L.r0[v] - t0, m = L.m[v];
+                if (m > NB) {
+                    flush();
+                    for (int32_t k = 0; k < m; k += chunk)
+                        out.push_back({a0 + k, std::min(a0 + k + chunk, a0 + m), a0, a0 + m, a0});
+                } else {
+                    if (cp0 >= 0 && cp1 - cp0 + m > NB) flush();
+                    if (cp0 < 0) cp0 = a0;
+                    cp1 = a0 + m;
+                }
             }
-        }
-        flush();
+            flush();
+        };
+        build(L.panels, std::min(NB, kWideChunk));
+        build(L.spanels, NB);
         L.flops_kernel += (uint64_t)(2.0 * (double)mT * mT * mT / 3.0);
     }
     // ---- execution level lists

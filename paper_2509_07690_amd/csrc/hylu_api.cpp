@@ -14,7 +14,10 @@
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <tuple>
+#include <atomic>
+#include <array>
 #include <vector>
 
 #include <chrono>
@@ -53,6 +56,8 @@ struct LevelTasks {
     std::vector<int64_t> sn_ptr;      // per level into snodes
     std::vector<int32_t> maxm;
     std::vector<int32_t> rows, snodes;
+    std::vector<int32_t> row_nt, sn_nt;  // per level: threads per row / per supernode (0: built-in rule)
+    int32_t tune_rows = 0, tune_sn = 0;  // when nonzero, every level uses this (autotuner trials)
     int32_t pipe_level = 0;           // levels from here on run as one pipelined launch
     int32_t pipe_maxW = 0, pipe_maxm = 0;
     std::vector<int32_t> node_level;  // execution level of every node
@@ -90,6 +95,13 @@ struct hylu_handle_s {
     int32_t* d_lev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     TailView TV{};
     PipeCtl PC{};
+    // large supernodes outside the tail, factored by the blocked dense kernels
+    struct DenseSn { int32_t v, level; TailView TV; std::vector<Layout::Panel> panels; };
+    std::vector<DenseSn> dsn;
+    std::vector<int32_t> dsn_ptr;           // per factor level into dsn
+    static constexpr int kSide = 4;         // side streams for independent supernodes of a level
+    hipStream_t side[kSide] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[kSide] = {nullptr, nullptr, nullptr, nullptr};
     int32_t *d_perm_r = nullptr, *d_perm_c = nullptr;
     double *d_dr = nullptr, *d_dc = nullptr;
     int64_t* d_arp = nullptr;
@@ -112,6 +124,9 @@ struct hylu_handle_s {
     double* d_bc = nullptr;                 // copy of b when refining in place
     double* d_norms = nullptr;
     double* h_norms = nullptr;              // pinned
+    // batch of matrices on one handle (block diagonal); one member otherwise
+    std::vector<int64_t> member_row_off{0}, member_nnz_off{0};
+    int32_t* d_seg = nullptr;               // member of every row (null for one member)
     // graphs
     std::map<const double*, GraphEntry> refac_graphs;
     std::map<std::tuple<const double*, double*, int32_t, int64_t, int32_t>, GraphEntry> solve_graphs;
@@ -252,10 +267,11 @@ hylu_status ensure_workspace(hylu_handle h, int32_t nrhs)
     h->d_z = dalloc(h, es * nn);
     h->d_r = (double*)dalloc(h, sizeof(double) * nn);
     h->d_bc = (double*)dalloc(h, sizeof(double) * nn);
-    h->d_norms = (double*)dalloc(h, sizeof(double) * (4 * (size_t)nrhs + 8));
+    const size_t nseg = h->member_row_off.size() - 1;
+    h->d_norms = (double*)dalloc(h, sizeof(double) * 4 * ((size_t)nrhs + 1) * nseg);
     if (!h->d_y || !h->d_z || !h->d_r || !h->d_bc || !h->d_norms) return HYLU_ERR_OOM;
     if (h->h_norms) hipHostFree(h->h_norms);
-    if (hipHostMalloc((void**)&h->h_norms, sizeof(double) * (4 * (size_t)nrhs + 8)) != hipSuccess) return HYLU_ERR_OOM;
+    if (hipHostMalloc((void**)&h->h_norms, sizeof(double) * 4 * ((size_t)nrhs + 1) * nseg) != hipSuccess) return HYLU_ERR_OOM;
     h->ws_nrhs = nrhs;
     return HYLU_OK;
 }
@@ -307,6 +323,58 @@ hylu_status ensure_tlists(hylu_handle h)
     return HYLU_OK;
 }
 
+// blocked right-looking LU of a dense view, one row panel at a time
+hylu_status enqueue_dense(hylu_handle h, const TailView& TV, const std::vector<Layout::Panel>& panels, bool search,
+                          hipStream_t st)
+{
+    const double es = h->fp32 ? 4.0 : 8.0;
+    const double mT = TV.mT, nc = TV.nc;
+    for (const Layout::Panel& P : panels) {
+        const double np = P.p1 - P.p0, wc = P.c1 - P.c0, rows = mT - P.p1, colsA = nc - P.c1, colsG = nc - P.cg0;
+        LAUNCH(C_PANEL, 2.0 * es * np * wc, np * np * wc,
+               launch_tail_panel(h->fp32, h->D, TV, h->vals, P.p0, P.p1, P.c0, P.c1, h->tau, h->d_pert, search ? 1 : 0, st));
+        LAUNCH(C_TRSM, es * (2.0 * np * colsA + 3.0 * np * rows + np * np), np * np * (colsA + rows),
+               launch_tail_trsm(h->fp32, TV, h->vals, P.p0, P.p1, P.c1, st));
+        LAUNCH(C_GEMM, es * (2.0 * rows * colsG + np * (rows + colsG)), 2.0 * np * rows * colsG,
+               launch_tail_gemm(h->fp32, TV, h->vals, P.p0, P.p1, P.cg0, st));
+    }
+    return HYLU_OK;
+}
+
+// the large supernodes of level l, spread over the side streams (forked from
+// and joined back into st; under capture they become parallel graph branches)
+hylu_status enqueue_level_dense(hylu_handle h, int32_t l, bool search, hipStream_t st)
+{
+    const int32_t d0 = h->dsn_ptr[l], d1 = h->dsn_ptr[l + 1];
+    if (d1 == d0) return HYLU_OK;
+    if (h->prof.on || d1 - d0 == 1) {          // one supernode, or measuring: stay on st
+        for (int32_t q = d0; q < d1; q++) {
+            if (search) HIPCHK(launch_tail_init(h->dsn[q].TV, st));
+            hylu_status s = enqueue_dense(h, h->dsn[q].TV, h->dsn[q].panels, search, st);
+            if (s != HYLU_OK) return s;
+        }
+        return HYLU_OK;
+    }
+    const int k = std::min<int>(hylu_handle_s::kSide, d1 - d0);
+    HIPCHK(hipEventRecord(h->ev_fork, st));
+    for (int j = 0; j < k; j++) HIPCHK(hipStreamWaitEvent(h->side[j], h->ev_fork, 0));
+    // largest first, each to the least loaded stream
+    std::vector<double> load(k, 0.0);
+    for (int32_t q = d0; q < d1; q++) {
+        int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        const TailView& TV = h->dsn[q].TV;
+        load[j] += (double)TV.mT * TV.mT * TV.nc;
+        if (search) HIPCHK(launch_tail_init(TV, h->side[j]));
+        hylu_status s = enqueue_dense(h, TV, h->dsn[q].panels, search, h->side[j]);
+        if (s != HYLU_OK) return s;
+    }
+    for (int j = 0; j < k; j++) {
+        HIPCHK(hipEventRecord(h->ev_join[j], h->side[j]));
+        HIPCHK(hipStreamWaitEvent(st, h->ev_join[j], 0));
+    }
+    return HYLU_OK;
+}
+
 // the level loop of the numerical factorisation
 hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipStream_t st)
 {
@@ -321,7 +389,8 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
     for (int32_t l = 0; l < T.pipe_level; l++) {
         int64_t r0 = T.row_ptr[l], r1 = T.row_ptr[l + 1];
         LAUNCH(C_ROWS, h->lvl_bytes[l] * es / 8.0, h->lvl_flops[l],
-               launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.maxW[l], h->tau, h->d_pert, st));
+               launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.maxW[l], h->tau, h->d_pert,
+                                  T.tune_rows ? T.tune_rows : T.row_nt[l], st));
         int64_t s0 = T.sn_ptr[l], s1 = T.sn_ptr[l + 1];
         if (s1 > s0) {
             double by = 0, fl = 0;
@@ -332,8 +401,11 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
                 fl += m * m * (2.0 * wc - m);
             }
             LAUNCH(C_SNLU, by, fl, launch_factor_snlu(h->fp32, h->D, h->vals, h->d_snodes + s0, (int32_t)(s1 - s0), T.maxm[l],
-                                                      h->tau, h->d_pert, search ? 1 : 0, st));
+                                                      h->tau, h->d_pert, search ? 1 : 0,
+                                                      T.tune_sn ? T.tune_sn : T.sn_nt[l], st));
         }
+        hylu_status sd = enqueue_level_dense(h, l, search, st);
+        if (sd != HYLU_OK) return sd;
     }
     if (T.pipe_level < nl) {
         // pipeline mode over the remaining levels
@@ -352,17 +424,7 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
                                   T.pipe_maxm, h->tau, h->d_pert, search ? 1 : 0, st));
     }
     // dense tail: blocked right-looking LU, one row panel at a time
-    const double mT = h->lay.mT;
-    for (const Layout::Panel& P : h->lay.panels) {
-        const double np = P.p1 - P.p0, wc = P.c1 - P.c0, rows = mT - P.p1, colsA = mT - P.c1, colsG = mT - P.cg0;
-        LAUNCH(C_PANEL, 2.0 * es * np * wc, np * np * wc,
-               launch_tail_panel(h->fp32, h->D, h->TV, h->vals, P.p0, P.p1, P.c0, P.c1, h->tau, h->d_pert, search ? 1 : 0, st));
-        LAUNCH(C_TRSM, es * (2.0 * np * colsA + 3.0 * np * rows + np * np), np * np * (colsA + rows),
-               launch_tail_trsm(h->fp32, h->TV, h->vals, P.p0, P.p1, P.c1, st));
-        LAUNCH(C_GEMM, es * (2.0 * rows * colsG + np * (rows + colsG)), 2.0 * np * rows * colsG,
-               launch_tail_gemm(h->fp32, h->TV, h->vals, P.p0, P.p1, P.cg0, st));
-    }
-    return HYLU_OK;
+    return enqueue_dense(h, h->TV, h->lay.panels, search, st);
 }
 
 // base solve in the factor precision: x = A^{-1} b (transpose 0) or A^{-T} b
@@ -387,9 +449,9 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
             LAUNCH(C_TSOLVE, 0, 0, launch_tail_lext(f, h->D, h->vals, L.tail_node0, L.t0, h->d_y, nrhs, st));
-            for (const Layout::Panel& P : L.panels) LAUNCH(C_TSOLVE, 0, 0, launch_tail_fwd(f, h->TV, h->vals, P.p0, P.p1, n, h->d_y, nrhs, st));
-            for (size_t k = L.panels.size(); k-- > 0;)
-                LAUNCH(C_TSOLVE, 0, 0, launch_tail_bwd(f, h->TV, h->vals, L.panels[k].p0, L.panels[k].p1, n, h->d_y, h->d_z, nrhs, st));
+            for (const Layout::Panel& P : L.spanels) LAUNCH(C_TSOLVE, 0, 0, launch_tail_fwd(f, h->TV, h->vals, P.p0, P.p1, n, h->d_y, nrhs, st));
+            for (size_t k = L.spanels.size(); k-- > 0;)
+                LAUNCH(C_TSOLVE, 0, 0, launch_tail_bwd(f, h->TV, h->vals, L.spanels[k].p0, L.spanels[k].p1, n, h->d_y, h->d_z, nrhs, st));
         }
         s = levels(1, [&](const int32_t* nodes, int32_t c) { return launch_usolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, st); });
         if (s != HYLU_OK) return s;
@@ -400,9 +462,9 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
             LAUNCH(C_TSOLVE, 0, 0, launch_tail_utext(f, h->D, h->TV, h->vals, h->d_y, h->d_z, nrhs, st));
-            for (const Layout::Panel& P : L.panels) LAUNCH(C_TSOLVE, 0, 0, launch_tail_ut(f, h->TV, h->vals, P.p0, P.p1, n, h->d_y, h->d_z, nrhs, st));
-            for (size_t k = L.panels.size(); k-- > 0;)
-                LAUNCH(C_TSOLVE, 0, 0, launch_tail_lt(f, h->TV, h->vals, L.panels[k].p0, L.panels[k].p1, n, h->d_z, nrhs, st));
+            for (const Layout::Panel& P : L.spanels) LAUNCH(C_TSOLVE, 0, 0, launch_tail_ut(f, h->TV, h->vals, P.p0, P.p1, n, h->d_y, h->d_z, nrhs, st));
+            for (size_t k = L.spanels.size(); k-- > 0;)
+                LAUNCH(C_TSOLVE, 0, 0, launch_tail_lt(f, h->TV, h->vals, L.spanels[k].p0, L.spanels[k].p1, n, h->d_z, nrhs, st));
         }
         s = levels(3, [&](const int32_t* nodes, int32_t c) { return launch_ltsolve(f, h->D, h->vals, nodes, c, h->d_z, nrhs, st); });
         if (s != HYLU_OK) return s;
@@ -432,6 +494,20 @@ hylu_status run_graph(hylu_handle h, GraphEntry& g, bool fresh, hipStream_t st,
     }
     HIPCHK(hipGraphLaunch(g.exec, st));
     return HYLU_OK;
+}
+
+// Graphs are cached per buffer address.  Callers that hand in fresh buffers on
+// every call (autograd, allocators without reuse) would grow the cache without
+// bound, so past a fixed size it is emptied after the device has drained.
+constexpr size_t kGraphCache = 16;
+
+template <typename Map>
+void trim_graphs(Map& m)
+{
+    if (m.size() < kGraphCache) return;
+    hipDeviceSynchronize();
+    for (auto& kv : m) { hipGraphExecDestroy(kv.second.exec); hipGraphDestroy(kv.second.graph); }
+    m.clear();
 }
 
 // device tables of the layout, uploaded on the first factorisation so the
@@ -483,7 +559,7 @@ hylu_status upload_device(hylu_handle h)
         {
             TailView& TVw = h->TV;
             TVw = TailView();
-            TVw.mT = L.mT; TVw.t0 = L.t0;
+            TVw.mT = L.mT; TVw.t0 = L.t0; TVw.nc = L.mT;
             int64_t* trow; int32_t *tlo, *thi, *tpiv, *tstep;
             std::vector<int32_t> zt(std::max(L.mT, 1), 0);
             UP(trow, L.trow); UP(tlo, L.tlo); UP(thi, L.thi); UP(tpiv, zt); UP(tstep, zt);
@@ -491,9 +567,38 @@ hylu_status upload_device(hylu_handle h)
             TVw.lbuf = dalloc(h, (size_t)64 * std::max(L.mT, 1) * (h->fp32 ? 4 : 8));
             if (!TVw.lbuf) return HYLU_ERR_OOM;
         }
+        for (hylu_handle_s::DenseSn& q : h->dsn) {
+            const int32_t v = q.v, m = L.m[v], nc = L.W[v] - L.lw[v];
+            std::vector<int64_t> tr(m);
+            std::vector<int32_t> lo(m, 0), hi(m, m), z(std::max(m, nc), 0);
+            for (int32_t a = 0; a < m; a++) tr[a] = L.voff[v] + (int64_t)a * L.W[v] + L.lw[v];
+            int64_t* trow; int32_t *tlo, *thi, *tpiv, *tstep;
+            UP(trow, tr); UP(tlo, lo); UP(thi, hi);
+            std::vector<int32_t> zm(m, 0), zc(nc, 0);
+            UP(tpiv, zm); UP(tstep, zc);
+            q.TV = TailView();
+            q.TV.mT = m; q.TV.nc = nc; q.TV.t0 = L.r0[v];
+            q.TV.trow = trow; q.TV.tlo = tlo; q.TV.thi = thi; q.TV.tpiv = tpiv; q.TV.tstep = tstep;
+            q.TV.lbuf = dalloc(h, (size_t)64 * m * (h->fp32 ? 4 : 8));
+            if (!q.TV.lbuf) return HYLU_ERR_OOM;
+        }
+        if (!h->dsn.empty() && !h->side[0]) {
+            for (int j = 0; j < hylu_handle_s::kSide; j++) {
+                HIPCHK(hipStreamCreateWithFlags(&h->side[j], hipStreamNonBlocking));
+                HIPCHK(hipEventCreateWithFlags(&h->ev_join[j], hipEventDisableTiming));
+            }
+            HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        }
         UP(h->d_perm_r, h->perm_r); UP(h->d_perm_c, h->perm_c);
         UP(h->d_dr, h->dr); UP(h->d_dc, h->dc);
         UP(h->d_arp, A.rp); UP(h->d_aci, A.ci); UP(h->d_aval, A.v);
+        h->d_seg = nullptr;
+        if (h->member_row_off.size() > 2) {
+            std::vector<int32_t> seg(n);
+            for (size_t k = 0; k + 1 < h->member_row_off.size(); k++)
+                for (int64_t i = h->member_row_off[k]; i < h->member_row_off[k + 1]; i++) seg[i] = (int32_t)k;
+            UP(h->d_seg, seg);
+        }
         {
             int32_t *ctl, *done, *rdone;
             std::vector<int32_t> z2(2, 0), zn(std::max(L.nnodes, 1), 0);
@@ -513,6 +618,179 @@ hylu_status upload_device(hylu_handle h)
     } catch (const std::bad_alloc&) {
         return HYLU_ERR_OOM;
     }
+    return HYLU_OK;
+}
+
+// static pivoting and scaling (Sec. 2.1), then the fill-reducing ordering of
+// the matched pattern: B = R A C with R = P_r D_r, C = D_c P_c
+hylu_status order_matrix(const Csr& A, const hylu_options& opt, std::vector<int32_t>& perm_r,
+                         std::vector<int32_t>& perm_c, std::vector<double>& dr, std::vector<double>& dc)
+{
+    const int32_t n = A.n;
+    // ---- static pivoting and scaling (Sec. 2.1)
+    std::vector<int32_t> match(n);
+    dr.assign(n, 1.0);
+    dc.assign(n, 1.0);
+    if (opt.static_pivot) {
+        if (!mc64_match_scale(A, match, dr, dc)) return HYLU_ERR_STRUCT_SINGULAR;
+    } else {
+        for (int32_t i = 0; i < n; i++) match[i] = i;
+        // a row or column without entries is singular in any case
+        std::vector<char> rowhas(n, 0), colhas(n, 0);
+        for (int32_t i = 0; i < n; i++)
+            for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++) { rowhas[i] = 1; colhas[A.ci[p]] = 1; }
+        for (int32_t i = 0; i < n; i++) if (!rowhas[i] || !colhas[i]) return HYLU_ERR_STRUCT_SINGULAR;
+    }
+    // ---- fill-reducing ordering on the pattern of B0 + B0^T, B0 = matched A
+    std::vector<int32_t> q(n);
+    if (opt.ordering == 2) {
+        for (int32_t i = 0; i < n; i++) q[i] = i;
+    } else if (opt.ordering == 3) {
+        std::vector<char> seen(n, 0);
+        for (int32_t i = 0; i < n; i++) {
+            int32_t x = opt.user_perm[i];
+            if (x < 0 || x >= n || seen[x]) return HYLU_ERR_ARG;
+            seen[x] = 1;
+            q[i] = x;
+        }
+    } else {
+        std::vector<int64_t> b0p(n + 1, 0);
+        std::vector<int32_t> b0c;
+        b0c.reserve(A.rp[n]);
+        for (int32_t j = 0; j < n; j++) {
+            int32_t r = match[j];
+            for (int64_t p = A.rp[r]; p < A.rp[r + 1]; p++) b0c.push_back(A.ci[p]);
+            b0p[j + 1] = (int64_t)b0c.size();
+        }
+        std::vector<int64_t> xadj;
+        std::vector<int32_t> adj;
+        symmetrize(n, b0p, b0c, xadj, adj);
+        double ad = opt.amd_dense > 0 ? opt.amd_dense : 10.0;
+        q = opt.ordering == 0 ? amd_order(n, xadj, adj, ad) : nd_order(n, xadj, adj, std::max(opt.nd_leaf, 8), ad);
+        if ((int32_t)q.size() != n) return HYLU_ERR_INTERNAL;
+    }
+    perm_c = q;
+    perm_r.resize(n);
+    for (int32_t k = 0; k < n; k++) perm_r[k] = match[q[k]];
+    return HYLU_OK;
+}
+
+// everything after the permutations and scalings: B = R A C, symbolic
+// factorisation, supernodes, levels, dense tail, panel layout, task lists
+hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
+{
+    const int32_t n = h->n;
+    const hylu_options& opt = h->opt;
+    const Csr& A = h->A;
+    // ---- B = R A C (pattern, sorted) and the source position of each entry
+    std::vector<int32_t> pcinv(n);
+    for (int32_t k = 0; k < n; k++) pcinv[h->perm_c[k]] = k;
+    Csr B;
+    B.n = n;
+    B.rp.assign(n + 1, 0);
+    B.ci.resize(h->nnz);
+    std::vector<int64_t> bsrc(h->nnz);
+    {
+        std::vector<std::pair<int32_t, int64_t>> rowbuf;
+        int64_t q0 = 0;
+        for (int32_t i = 0; i < n; i++) {
+            int32_t r = h->perm_r[i];
+            rowbuf.clear();
+            for (int64_t p = A.rp[r]; p < A.rp[r + 1]; p++) rowbuf.push_back({pcinv[A.ci[p]], p});
+            std::sort(rowbuf.begin(), rowbuf.end());
+            for (auto& e : rowbuf) { B.ci[q0] = e.first; bsrc[q0] = e.second; q0++; }
+            B.rp[i + 1] = q0;
+        }
+    }
+    // ---- symbolic factorisation, flops, supernodes, levels (Sec. 2.1, 2.2, 2.2.1)
+    plog("permute");
+    if (!symbolic_factor(B, h->sym)) return HYLU_ERR_INTERNAL;
+    plog("symbolic");
+    int32_t sn_min = opt.sn_min, sn_max = opt.sn_max;
+    if (opt.kernel_mode == 1) sn_min = std::numeric_limits<int32_t>::max();
+    make_nodes(h->sym, sn_min, sn_max, h->nodes);
+    make_levels(h->sym, h->nodes);
+    plog("nodes");
+    std::string err;
+    int32_t tail_node0 = choose_tail(h->sym, h->nodes, opt.dense_tail, std::max(opt.tail_min, 1),
+                                     opt.tail_max > 0 ? opt.tail_max : 32768);
+    if (!build_layout(B, h->sym, h->nodes, tail_node0, 64, h->lay, bsrc, err)) {
+        std::fprintf(stderr, "hylu: %s\n", err.c_str());
+        return HYLU_ERR_INTERNAL;
+    }
+    plog("layout");
+    // ---- perturbation threshold
+    double bmax = 0.0;
+    for (int32_t i = 0; i < n; i++)
+        for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++)
+            bmax = std::max(bmax, std::fabs(h->dr[i] * A.v[p] * h->dc[A.ci[p]]));
+    double eps = h->fp32 ? (double)std::numeric_limits<float>::epsilon() : std::numeric_limits<double>::epsilon();
+    h->tau = (opt.pivot_tau > 0 ? opt.pivot_tau : std::sqrt(eps)) * (bmax > 0 ? bmax : 1.0);
+    // ---- level task lists of the factorisation
+    const Layout& L = h->lay;
+    const Nodes& nd = h->nodes;
+    LevelTasks& T = h->ft;
+    T = LevelTasks();
+    int32_t nl = (int32_t)L.xlev_ptr[0].size() - 1;
+    T.row_ptr.assign(1, 0); T.sn_ptr.assign(1, 0);
+    h->max_sn = 0;
+    h->dsn.clear();
+    h->dsn_ptr.assign(1, 0);
+    const int32_t big = opt.sn_dense > 0 ? opt.sn_dense : std::numeric_limits<int32_t>::max();
+    for (int32_t l = 0; l < nl; l++) {
+        int32_t mw = 0, mm = 0;
+        for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) {
+            int32_t v = L.xlev_nodes[0][t];
+            for (int32_t r = L.r0[v]; r < L.r0[v] + L.m[v]; r++) T.rows.push_back(r);
+            mw = std::max(mw, L.W[v]);
+            if (!nd.is_sn[v] || v >= L.tail_node0) continue;
+            if (L.m[v] >= big) {
+                // blocked LU on the supernode's panel: kWideChunk-row panels, the
+                // whole block as pivot window, T columns updated by TRSM/GEMM
+                hylu_handle_s::DenseSn q;
+                q.v = v;
+                q.level = l;
+                for (int32_t k = 0; k < L.m[v]; k += kWideChunk)
+                    q.panels.push_back({k, std::min(k + kWideChunk, L.m[v]), 0, L.m[v], 0});
+                h->dsn.push_back(std::move(q));
+            } else {
+                T.snodes.push_back(v);
+                mm = std::max(mm, L.m[v]);
+            }
+        }
+        h->dsn_ptr.push_back((int32_t)h->dsn.size());
+        T.row_ptr.push_back((int64_t)T.rows.size());
+        T.sn_ptr.push_back((int64_t)T.snodes.size());
+        T.maxW.push_back(mw);
+        T.maxm.push_back(mm);
+        h->max_sn = std::max(h->max_sn, mm);
+    }
+    T.row_nt.assign(nl, 0);
+    T.sn_nt.assign(nl, 0);
+    T.node_level.assign(L.nnodes, 0);
+    for (int32_t l = 0; l < nl; l++)
+        for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) T.node_level[L.xlev_nodes[0][t]] = l;
+    // pipeline mode stays off: its dataflow launch did not finish on the device
+    // and the reason is not established, so every level is a launch of its own
+    T.pipe_level = nl;
+    // algorithmic traffic and flops of every row-kernel launch (8-byte values)
+    h->lvl_bytes.assign(nl, 0.0);
+    h->lvl_flops.assign(nl, 0.0);
+    for (int32_t l = 0; l < nl; l++)
+        for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) {
+            int32_t v = L.xlev_nodes[0][t];
+            double m = L.m[v], by = 16.0 * L.W[v], fl = 0;
+            for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
+                int32_t u = L.esrc[e];
+                double ms = L.m[u], ws = L.W[u] - L.lw[u] - L.m[u];
+                by += 8.0 * ms * (ms + ws) + 4.0 * ws + 48.0;
+                fl += ms * (ms + 2.0 * ws);
+            }
+            h->lvl_bytes[l] += m * by;
+            h->lvl_flops[l] += m * fl;
+        }
+    plog("tasks");
+    h->analyzed = true;
     return HYLU_OK;
 }
 
@@ -540,6 +818,7 @@ hylu_status hylu_default_options(hylu_options* o)
     o->dense_tail = 0.5;
     o->tail_min = 64;
     o->tail_max = 32768;
+    o->sn_dense = 128;
     o->pipeline_rows = 0;
     return HYLU_OK;
 }
@@ -587,6 +866,11 @@ hylu_status hylu_destroy(hylu_handle h)
     if (h->fact_done) hipEventDestroy(h->fact_done);
     if (h->h_pert) hipHostFree(h->h_pert);
     if (h->h_norms) hipHostFree(h->h_norms);
+    for (int j = 0; j < hylu_handle_s::kSide; j++) {
+        if (h->side[j]) hipStreamDestroy(h->side[j]);
+        if (h->ev_join[j]) hipEventDestroy(h->ev_join[j]);
+    }
+    if (h->ev_fork) hipEventDestroy(h->ev_fork);
     delete h;
     return HYLU_OK;
 }
@@ -617,148 +901,132 @@ hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const
         A.rp.assign(row_ptr, row_ptr + n + 1);
         A.ci.assign(col, col + h->nnz);
         A.v.assign(val, val + h->nnz);
-        // ---- static pivoting and scaling (Sec. 2.1)
-        std::vector<int32_t> match(n);
-        h->dr.assign(n, 1.0);
-        h->dc.assign(n, 1.0);
-        if (opt.static_pivot) {
-            if (!mc64_match_scale(A, match, h->dr, h->dc)) return HYLU_ERR_STRUCT_SINGULAR;
-        } else {
-            for (int32_t i = 0; i < n; i++) match[i] = i;
-            // a row or column without entries is singular in any case
-            std::vector<char> rowhas(n, 0), colhas(n, 0);
-            for (int32_t i = 0; i < n; i++)
-                for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++) { rowhas[i] = 1; colhas[A.ci[p]] = 1; }
-            for (int32_t i = 0; i < n; i++) if (!rowhas[i] || !colhas[i]) return HYLU_ERR_STRUCT_SINGULAR;
-        }
-        plog("matching");
-        // ---- fill-reducing ordering on the pattern of B0 + B0^T, B0 = matched A
-        std::vector<int32_t> q(n);
-        if (opt.ordering == 2) {
-            for (int32_t i = 0; i < n; i++) q[i] = i;
-        } else if (opt.ordering == 3) {
-            std::vector<char> seen(n, 0);
-            for (int32_t i = 0; i < n; i++) {
-                int32_t x = opt.user_perm[i];
-                if (x < 0 || x >= n || seen[x]) return HYLU_ERR_ARG;
-                seen[x] = 1;
-                q[i] = x;
-            }
-        } else {
-            std::vector<int64_t> b0p(n + 1, 0);
-            std::vector<int32_t> b0c;
-            b0c.reserve(h->nnz);
-            for (int32_t j = 0; j < n; j++) {
-                int32_t r = match[j];
-                for (int64_t p = A.rp[r]; p < A.rp[r + 1]; p++) b0c.push_back(A.ci[p]);
-                b0p[j + 1] = (int64_t)b0c.size();
-            }
-            std::vector<int64_t> xadj;
-            std::vector<int32_t> adj;
-            symmetrize(n, b0p, b0c, xadj, adj);
-            double ad = opt.amd_dense > 0 ? opt.amd_dense : 10.0;
-            q = opt.ordering == 0 ? amd_order(n, xadj, adj, ad) : nd_order(n, xadj, adj, std::max(opt.nd_leaf, 8), ad);
-            if ((int32_t)q.size() != n) return HYLU_ERR_INTERNAL;
-        }
-        plog("ordering");
-        h->perm_c = q;
-        h->perm_r.resize(n);
-        for (int32_t k = 0; k < n; k++) h->perm_r[k] = match[q[k]];
-        // ---- B = R A C (pattern, sorted) and the source position of each entry
-        std::vector<int32_t> pcinv(n);
-        for (int32_t k = 0; k < n; k++) pcinv[h->perm_c[k]] = k;
-        Csr B;
-        B.n = n;
-        B.rp.assign(n + 1, 0);
-        B.ci.resize(h->nnz);
-        std::vector<int64_t> bsrc(h->nnz);
+        h->member_row_off = {0, (int64_t)n};
+        h->member_nnz_off = {0, h->nnz};
         {
-            std::vector<std::pair<int32_t, int64_t>> rowbuf;
-            int64_t q0 = 0;
-            for (int32_t i = 0; i < n; i++) {
-                int32_t r = h->perm_r[i];
-                rowbuf.clear();
-                for (int64_t p = A.rp[r]; p < A.rp[r + 1]; p++) rowbuf.push_back({pcinv[A.ci[p]], p});
-                std::sort(rowbuf.begin(), rowbuf.end());
-                for (auto& e : rowbuf) { B.ci[q0] = e.first; bsrc[q0] = e.second; q0++; }
-                B.rp[i + 1] = q0;
-            }
+            hylu_status so = order_matrix(A, opt, h->perm_r, h->perm_c, h->dr, h->dc);
+            if (so != HYLU_OK) return so;
         }
-        // ---- symbolic factorisation, flops, supernodes, levels (Sec. 2.1, 2.2, 2.2.1)
-        plog("permute");
-        if (!symbolic_factor(B, h->sym)) return HYLU_ERR_INTERNAL;
-        plog("symbolic");
-        int32_t sn_min = opt.sn_min, sn_max = opt.sn_max;
-        if (opt.kernel_mode == 1) sn_min = std::numeric_limits<int32_t>::max();
-        make_nodes(h->sym, sn_min, sn_max, h->nodes);
-        make_levels(h->sym, h->nodes);
-        plog("nodes");
-        std::string err;
-        int32_t tail_node0 = choose_tail(h->sym, h->nodes, opt.dense_tail, std::max(opt.tail_min, 1),
-                                         opt.tail_max > 0 ? opt.tail_max : 32768);
-        if (!build_layout(B, h->sym, h->nodes, tail_node0, 64, h->lay, bsrc, err)) {
-            std::fprintf(stderr, "hylu: %s\n", err.c_str());
-            return HYLU_ERR_INTERNAL;
-        }
-        plog("layout");
-        // ---- perturbation threshold
-        double bmax = 0.0;
-        for (int32_t i = 0; i < n; i++)
-            for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++)
-                bmax = std::max(bmax, std::fabs(h->dr[i] * A.v[p] * h->dc[A.ci[p]]));
-        double eps = h->fp32 ? (double)std::numeric_limits<float>::epsilon() : std::numeric_limits<double>::epsilon();
-        h->tau = (opt.pivot_tau > 0 ? opt.pivot_tau : std::sqrt(eps)) * (bmax > 0 ? bmax : 1.0);
-        // ---- level task lists of the factorisation
-        const Layout& L = h->lay;
-        const Nodes& nd = h->nodes;
-        LevelTasks& T = h->ft;
-        T = LevelTasks();
-        int32_t nl = (int32_t)L.xlev_ptr[0].size() - 1;
-        T.row_ptr.assign(1, 0); T.sn_ptr.assign(1, 0);
-        h->max_sn = 0;
-        for (int32_t l = 0; l < nl; l++) {
-            int32_t mw = 0, mm = 0;
-            for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) {
-                int32_t v = L.xlev_nodes[0][t];
-                for (int32_t r = L.r0[v]; r < L.r0[v] + L.m[v]; r++) T.rows.push_back(r);
-                mw = std::max(mw, L.W[v]);
-                if (nd.is_sn[v] && v < L.tail_node0) { T.snodes.push_back(v); mm = std::max(mm, L.m[v]); }
-            }
-            T.row_ptr.push_back((int64_t)T.rows.size());
-            T.sn_ptr.push_back((int64_t)T.snodes.size());
-            T.maxW.push_back(mw);
-            T.maxm.push_back(mm);
-            h->max_sn = std::max(h->max_sn, mm);
-        }
-        T.node_level.assign(L.nnodes, 0);
-        for (int32_t l = 0; l < nl; l++)
-            for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) T.node_level[L.xlev_nodes[0][t]] = l;
-        // pipeline mode stays off: its dataflow launch did not finish on the device
-        // and the reason is not established, so every level is a launch of its own
-        T.pipe_level = nl;
-        // algorithmic traffic and flops of every row-kernel launch (8-byte values)
-        h->lvl_bytes.assign(nl, 0.0);
-        h->lvl_flops.assign(nl, 0.0);
-        for (int32_t l = 0; l < nl; l++)
-            for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) {
-                int32_t v = L.xlev_nodes[0][t];
-                double m = L.m[v], by = 16.0 * L.W[v], fl = 0;
-                for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
-                    int32_t u = L.esrc[e];
-                    double ms = L.m[u], ws = L.W[u] - L.lw[u] - L.m[u];
-                    by += 8.0 * ms * (ms + ws) + 4.0 * ws + 48.0;
-                    fl += ms * (ms + 2.0 * ws);
-                }
-                h->lvl_bytes[l] += m * by;
-                h->lvl_flops[l] += m * fl;
-            }
-        plog("tasks");
-        h->analyzed = true;
+        plog("matching and ordering");
+        hylu_status s2 = analyze_structure(h, plog);
+        if (s2 != HYLU_OK) return s2;
     } catch (const std::bad_alloc&) {
         return HYLU_ERR_OOM;
     } catch (...) {
         return HYLU_ERR_INTERNAL;
     }
+    return HYLU_OK;
+}
+
+hylu_status hylu_analyze_batch(hylu_handle h, int32_t count, const int32_t* n_k, const int64_t* const* row_ptr_k,
+                               const int32_t* const* col_k, const double* const* val_k, const hylu_options* opt_in)
+{
+    if (!h || count <= 0 || !n_k || !row_ptr_k || !col_k || !val_k) return HYLU_ERR_ARG;
+    hylu_options opt;
+    if (opt_in) opt = *opt_in; else hylu_default_options(&opt);
+    if (opt.ordering < 0 || opt.ordering > 2) return HYLU_ERR_ARG;    // no user permutation for a batch
+    if (opt.precision < 0 || opt.precision > 1 || opt.kernel_mode < 0 || opt.kernel_mode > 2) return HYLU_ERR_ARG;
+    if (opt.pipeline_rows != 0) return HYLU_ERR_ARG;
+    opt.dense_tail = 0.0;   // members are independent: the levels of all of them share the launches instead
+    int64_t ntot = 0, nnztot = 0;
+    for (int32_t k = 0; k < count; k++) {
+        if (n_k[k] <= 0 || !row_ptr_k[k] || !col_k[k] || !val_k[k]) return HYLU_ERR_ARG;
+        hylu_status st = validate_csr(n_k[k], row_ptr_k[k], col_k[k], val_k[k]);
+        if (st != HYLU_OK) return st;
+        ntot += n_k[k];
+        nnztot += row_ptr_k[k][n_k[k]];
+    }
+    if (ntot > std::numeric_limits<int32_t>::max()) return HYLU_ERR_ARG;
+    try {
+        free_device(h);
+        h->analyzed = h->factorized = h->uploaded = false;
+        h->sticky_error = false;
+        h->pert_known = false;
+        h->opt = opt;
+        h->n = (int32_t)ntot;
+        h->nnz = nnztot;
+        h->fp32 = opt.precision == 1;
+        PhaseLog plog;
+        h->member_row_off.assign(count + 1, 0);
+        h->member_nnz_off.assign(count + 1, 0);
+        for (int32_t k = 0; k < count; k++) {
+            h->member_row_off[k + 1] = h->member_row_off[k] + n_k[k];
+            h->member_nnz_off[k + 1] = h->member_nnz_off[k] + row_ptr_k[k][n_k[k]];
+        }
+        // the block-diagonal union
+        Csr& A = h->A;
+        A.n = (int32_t)ntot;
+        A.rp.assign(ntot + 1, 0);
+        A.ci.resize(nnztot);
+        A.v.resize(nnztot);
+        for (int32_t k = 0; k < count; k++) {
+            const int64_t r0 = h->member_row_off[k], q0 = h->member_nnz_off[k];
+            for (int32_t i = 0; i < n_k[k]; i++) A.rp[r0 + i + 1] = q0 + row_ptr_k[k][i + 1];
+            for (int64_t p = 0; p < row_ptr_k[k][n_k[k]]; p++) {
+                A.ci[q0 + p] = (int32_t)(col_k[k][p] + r0);
+                A.v[q0 + p] = val_k[k][p];
+            }
+        }
+        // every member matched, scaled and ordered on its own, on host threads
+        h->perm_r.assign(ntot, 0);
+        h->perm_c.assign(ntot, 0);
+        h->dr.assign(ntot, 1.0);
+        h->dc.assign(ntot, 1.0);
+        std::vector<hylu_status> res(count, HYLU_OK);
+        std::atomic<int32_t> next{0};
+        auto worker = [&]() {
+            for (;;) {
+                const int32_t k = next.fetch_add(1);
+                if (k >= count) return;
+                try {
+                    Csr M;
+                    M.n = n_k[k];
+                    M.rp.assign(row_ptr_k[k], row_ptr_k[k] + n_k[k] + 1);
+                    M.ci.assign(col_k[k], col_k[k] + M.rp[M.n]);
+                    M.v.assign(val_k[k], val_k[k] + M.rp[M.n]);
+                    std::vector<int32_t> pr, pc;
+                    std::vector<double> dr, dc;
+                    res[k] = order_matrix(M, opt, pr, pc, dr, dc);
+                    if (res[k] != HYLU_OK) continue;
+                    const int64_t r0 = h->member_row_off[k];
+                    for (int32_t i = 0; i < M.n; i++) {
+                        h->perm_r[r0 + i] = (int32_t)(pr[i] + r0);
+                        h->perm_c[r0 + i] = (int32_t)(pc[i] + r0);
+                        h->dr[r0 + i] = dr[i];
+                        h->dc[r0 + i] = dc[i];
+                    }
+                } catch (const std::bad_alloc&) {
+                    res[k] = HYLU_ERR_OOM;
+                } catch (...) {
+                    res[k] = HYLU_ERR_INTERNAL;
+                }
+            }
+        };
+        unsigned nth = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16u));
+        nth = std::min<unsigned>(nth, (unsigned)count);
+        std::vector<std::thread> pool;
+        for (unsigned t = 1; t < nth; t++) pool.emplace_back(worker);
+        worker();
+        for (auto& t : pool) t.join();
+        for (int32_t k = 0; k < count; k++) if (res[k] != HYLU_OK) return res[k];
+        plog("matching and ordering (members)");
+        hylu_status s2 = analyze_structure(h, plog);
+        if (s2 != HYLU_OK) return s2;
+    } catch (const std::bad_alloc&) {
+        return HYLU_ERR_OOM;
+    } catch (...) {
+        return HYLU_ERR_INTERNAL;
+    }
+    return HYLU_OK;
+}
+
+hylu_status hylu_batch_offsets(hylu_handle h, int32_t* count, int64_t* row_off, int64_t* nnz_off)
+{
+    if (!h || !count) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    *count = (int32_t)h->member_row_off.size() - 1;
+    if (row_off) std::memcpy(row_off, h->member_row_off.data(), sizeof(int64_t) * h->member_row_off.size());
+    if (nnz_off) std::memcpy(nnz_off, h->member_nnz_off.data(), sizeof(int64_t) * h->member_nnz_off.size());
     return HYLU_OK;
 }
 
@@ -791,6 +1059,7 @@ hylu_status hylu_refactor(hylu_handle h, const double* d_val, void* stream)
     if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
     if (h->sticky_error) return HYLU_ERR_DEVICE;
     hipStream_t st = (hipStream_t)stream;
+    if (h->refac_graphs.find(d_val) == h->refac_graphs.end()) trim_graphs(h->refac_graphs);
     auto it = h->refac_graphs.find(d_val);
     bool fresh = it == h->refac_graphs.end();
     GraphEntry& g = h->refac_graphs[d_val];
@@ -835,6 +1104,7 @@ hylu_status hylu_solve(hylu_handle h, const double* d_b, double* d_x, int32_t nr
     }
     int64_t ldb = bcopy ? n : ld;
     auto key = std::make_tuple(b, d_x, nrhs, ld, transpose);
+    if (h->solve_graphs.find(key) == h->solve_graphs.end()) trim_graphs(h->solve_graphs);
     auto it = h->solve_graphs.find(key);
     bool fresh = it == h->solve_graphs.end();
     GraphEntry& g = h->solve_graphs[key];
@@ -857,15 +1127,21 @@ hylu_status hylu_solve(hylu_handle h, const double* d_b, double* d_x, int32_t nr
     double eta = 0.0;
     for (int32_t it2 = 0;; it2++) {
         HIPCHK(launch_residual(n, nrhs, rp, ci, av, b, ldb, d_x, ld, h->d_r, st));
-        HIPCHK(launch_norms(n, nrhs, rp, av, h->d_r, d_x, ld, b, ldb, h->d_norms, st));
-        HIPCHK(hipMemcpyAsync(h->h_norms, h->d_norms, sizeof(double) * (4 * (size_t)nrhs + 1), hipMemcpyDeviceToHost, st));
+        const int32_t nseg = (int32_t)h->member_row_off.size() - 1;
+        HIPCHK(launch_norms(n, nrhs, rp, av, h->d_r, d_x, ld, b, ldb, h->d_seg, nseg, h->d_norms, st));
+        HIPCHK(hipMemcpyAsync(h->h_norms, h->d_norms, sizeof(double) * 4 * ((size_t)nrhs + 1) * nseg,
+                              hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        // normwise backward error of every right-hand side of every member
         eta = 0.0;
-        double anorm = h->h_norms[4 * nrhs];
-        for (int32_t k = 0; k < nrhs; k++) {
-            double den = anorm * h->h_norms[4 * k + 1] + h->h_norms[4 * k + 2];
-            double e = den > 0 ? h->h_norms[4 * k] / den : 0.0;
-            eta = std::max(eta, e);
+        for (int32_t sg = 0; sg < nseg; sg++) {
+            double anorm = h->h_norms[4 * ((size_t)nrhs * nseg + sg)];
+            for (int32_t k = 0; k < nrhs; k++) {
+                const double* q = h->h_norms + 4 * ((size_t)k * nseg + sg);
+                double den = anorm * q[1] + q[2];
+                double e = den > 0 ? q[0] / den : 0.0;
+                eta = std::max(eta, e);
+            }
         }
         if (eta <= tol || it2 >= maxit || eta > eta_prev / 2) break;
         eta_prev = eta;
@@ -938,6 +1214,79 @@ hylu_status hylu_export_symbolic(hylu_handle h, const hylu_symbolic_view* v)
     if (v->is_sn) std::memcpy(v->is_sn, h->nodes.is_sn.data(), nn);
     if (v->levels)
         for (int t = 0; t < 4; t++) std::memcpy(v->levels + (size_t)t * nn, h->nodes.level[t].data(), sizeof(int32_t) * nn);
+    return HYLU_OK;
+}
+
+hylu_status hylu_autotune(hylu_handle h, const double* d_val, void* stream, int32_t reps, double* ms_default,
+                          double* ms_tuned)
+{
+    (void)hipGetLastError();
+    if (!h || !d_val) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
+    if (h->sticky_error) return HYLU_ERR_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    LevelTasks& T = h->ft;
+    const int32_t nl = (int32_t)T.maxW.size();
+    static const int32_t kRowNT[3] = {64, 128, 256};
+    static const int32_t kSnNT[3] = {64, 256, 256};
+    // best[l][t]: shortest time of level l's row launch (snlu launch) under trial t
+    std::vector<std::array<double, 3>> trow(nl), tsn(nl);
+    for (auto& a : trow) a.fill(std::numeric_limits<double>::infinity());
+    for (auto& a : tsn) a.fill(std::numeric_limits<double>::infinity());
+    std::vector<int32_t> sn_levels;
+    for (int32_t l = 0; l < T.pipe_level; l++) if (T.sn_ptr[l + 1] > T.sn_ptr[l]) sn_levels.push_back(l);
+    reps = std::max(reps, 1);
+    hylu_status s = HYLU_OK;
+    for (int32_t rep = 0; rep < reps && s == HYLU_OK; rep++)
+        for (int t = 0; t < 3 && s == HYLU_OK; t++) {
+            T.tune_rows = kRowNT[t];
+            T.tune_sn = kSnNT[t];
+            h->prof.on = true;
+            h->prof.recs.clear();
+            h->prof.used = 0;
+            s = enqueue_factor(h, d_val, false, st);
+            h->prof.on = false;
+            if (s != HYLU_OK) break;
+            if (hipStreamSynchronize(st) != hipSuccess) { s = HYLU_ERR_DEVICE; break; }
+            int32_t lr = 0;
+            size_t ls = 0;
+            for (const Profiler::Rec& r : h->prof.recs) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) { s = HYLU_ERR_DEVICE; break; }
+                if (r.cls == C_ROWS && lr < T.pipe_level) { trow[lr][t] = std::min(trow[lr][t], (double)ms); lr++; }
+                else if (r.cls == C_SNLU && ls < sn_levels.size()) {
+                    tsn[sn_levels[ls]][t] = std::min(tsn[sn_levels[ls]][t], (double)ms);
+                    ls++;
+                }
+            }
+        }
+    T.tune_rows = T.tune_sn = 0;
+    if (s != HYLU_OK) { h->sticky_error = true; return s; }
+    double before = 0.0, after = 0.0;
+    for (int32_t l = 0; l < T.pipe_level; l++) {
+        const int def = T.maxW[l] > 1024 ? 2 : 0;
+        int best = 0;
+        for (int t = 1; t < 3; t++) if (trow[l][t] < trow[l][best]) best = t;
+        T.row_nt[l] = kRowNT[best];
+        before += trow[l][def];
+        after += trow[l][best];
+        if (T.sn_ptr[l + 1] > T.sn_ptr[l]) {
+            const int sb = tsn[l][0] < std::min(tsn[l][1], tsn[l][2]) ? 0 : 1;
+            T.sn_nt[l] = kSnNT[sb];
+            before += std::min(tsn[l][1], tsn[l][2]);
+            after += std::min(tsn[l][sb], sb ? tsn[l][2] : tsn[l][0]);
+        }
+    }
+    // graphs captured with the old choices are stale
+    for (auto& kv : h->refac_graphs) { hipGraphExecDestroy(kv.second.exec); hipGraphDestroy(kv.second.graph); }
+    h->refac_graphs.clear();
+    if (ms_default) *ms_default = before;
+    if (ms_tuned) *ms_tuned = after;
+    // every trial was a complete refactorisation of d_val with identical results
+    h->pert_known = false;
+    HIPCHK(hipMemcpyAsync(h->h_pert, h->d_pert, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(h->fact_done, st));
     return HYLU_OK;
 }
 

@@ -22,6 +22,13 @@ namespace hylu {
 namespace {
 
 template <typename T> __device__ __forceinline__ T tabs(T x) { return x < T(0) ? -x : x; }
+// magnitude for the pivot search: a NaN ranks above every number, so a search
+// over a non-empty set of columns always returns one of them
+template <typename T> __device__ __forceinline__ T pmag(T x)
+{
+    const T y = tabs(x);
+    return y == y ? y : static_cast<T>(__builtin_huge_valf());
+}
 
 constexpr int kStage = 1024;   // staged source entries per batch (values + relative indices)
 
@@ -292,7 +299,7 @@ __device__ void snlu_node(const DevLayout& D, T* __restrict__ vals, int v, T tau
             int bi = m;
             for (int c = tid; c < m; c += NT) {
                 if (taken[c]) continue;
-                T x = tabs(Pa[c]);
+                T x = pmag(Pa[c]);
                 if (x > best || (x == best && c < bi)) { best = x; bi = c; }
             }
             red_v[tid] = best; red_i[tid] = bi;
@@ -338,20 +345,20 @@ __device__ void snlu_node(const DevLayout& D, T* __restrict__ vals, int v, T tau
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_factor_snlu(DevLayout D, T* __restrict__ vals,
-                                                     const int32_t* __restrict__ nodes, int32_t count,
-                                                     T tau, int32_t* __restrict__ pert, int32_t search)
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_factor_snlu(DevLayout D, T* __restrict__ vals,
+                                                    const int32_t* __restrict__ nodes, int32_t count,
+                                                    T tau, int32_t* __restrict__ pert, int32_t search)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ T red_v[256];
-    __shared__ int red_i[256];
+    __shared__ T red_v[NT];
+    __shared__ int red_i[NT];
     __shared__ int s_p;
     const int v = nodes[blockIdx.x];
     const int m = D.m[v];
     T* lrow = reinterpret_cast<T*>(smem_raw);                       // m multipliers
     uint8_t* taken = smem_raw + sizeof(T) * (size_t)m;             // m flags
-    snlu_node<T, 256>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p);
+    snlu_node<T, NT>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p);
 }
 
 // pipeline mode (Sec. 2.2.1): persistent blocks take rows in topological order
@@ -596,12 +603,22 @@ __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v)
     atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
+// maxima per right-hand side and per segment of rows (the members of a
+// batch; one segment when seg is null): out[4 (k nseg + s) + q] for q = 0 |r|,
+// 1 |x|, 2 |b|; out[4 (nrhs nseg + s)] = largest row abs sum of A in segment s
 __global__ void k_norms(int32_t n, int32_t nrhs, const int64_t* __restrict__ rp, const double* __restrict__ av,
                         const double* __restrict__ r, const double* __restrict__ x, int64_t ldx,
-                        const double* __restrict__ b, int64_t ldb, double* __restrict__ out)
+                        const double* __restrict__ b, int64_t ldb, const int32_t* __restrict__ seg, int32_t nseg,
+                        double* __restrict__ out)
 {
-    __shared__ double sm[4][256];
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double sm[3][256];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int first = blockIdx.x * blockDim.x;
+    const int last = min(first + (int)blockDim.x, n) - 1;
+    // a block whose rows all lie in one segment reduces in LDS first
+    const int s_first = seg ? seg[first] : 0;
+    const bool uniform = !seg || seg[last] == s_first;
+    const int si = (i < n && seg) ? seg[i] : 0;
     for (int k = 0; k <= nrhs; k++) {
         double m0 = 0, m1 = 0, m2 = 0;
         if (i < n) {
@@ -613,20 +630,29 @@ __global__ void k_norms(int32_t n, int32_t nrhs, const int64_t* __restrict__ rp,
                 for (int64_t p = rp[i]; p < rp[i + 1]; p++) m0 += fabs(av[p]);
             }
         }
+        double* o = out + 4 * ((int64_t)k * nseg);
+        if (!uniform) {
+            if (i < n) {
+                atomic_max_nonneg(o + 4 * si + 0, m0);
+                if (k < nrhs) {
+                    atomic_max_nonneg(o + 4 * si + 1, m1);
+                    atomic_max_nonneg(o + 4 * si + 2, m2);
+                }
+            }
+            continue;
+        }
         sm[0][threadIdx.x] = m0; sm[1][threadIdx.x] = m1; sm[2][threadIdx.x] = m2;
         __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (threadIdx.x < s)
-                for (int q = 0; q < 3; q++) sm[q][threadIdx.x] = fmax(sm[q][threadIdx.x], sm[q][threadIdx.x + s]);
+        for (int st = 128; st > 0; st >>= 1) {
+            if (threadIdx.x < st)
+                for (int q = 0; q < 3; q++) sm[q][threadIdx.x] = fmax(sm[q][threadIdx.x], sm[q][threadIdx.x + st]);
             __syncthreads();
         }
         if (threadIdx.x == 0) {
+            atomic_max_nonneg(o + 4 * s_first + 0, sm[0][0]);
             if (k < nrhs) {
-                atomic_max_nonneg(out + 4 * k + 0, sm[0][0]);
-                atomic_max_nonneg(out + 4 * k + 1, sm[1][0]);
-                atomic_max_nonneg(out + 4 * k + 2, sm[2][0]);
-            } else {
-                atomic_max_nonneg(out + 4 * nrhs, sm[0][0]);
+                atomic_max_nonneg(o + 4 * s_first + 1, sm[1][0]);
+                atomic_max_nonneg(o + 4 * s_first + 2, sm[2][0]);
             }
         }
         __syncthreads();
@@ -709,7 +735,7 @@ __global__ __launch_bounds__(256) void k_tail_panel(DevLayout D, TailView TV, T*
             int bi = hi;
             for (int c = lo + tid; c < hi; c += 256) {
                 if (step(c) <= a) continue;
-                T x = tabs(X(a, c));
+                T x = pmag(X(a, c));
                 if (x > best || (x == best && c < bi)) { best = x; bi = c; }
             }
             red_v[tid] = best; red_i[tid] = bi;
@@ -762,6 +788,119 @@ __global__ __launch_bounds__(256) void k_tail_panel(DevLayout D, TailView TV, T*
     }
 }
 
+// panel factorisation for a wide pivot window (wc > 64) on one workgroup of
+// NT threads.  Thread t owns window columns t, t+NT, ...; per panel row the
+// pivot is a block argmax over the unpivoted window columns (ties: lowest
+// column), the multipliers of the later panel rows are formed by one thread
+// each, and every thread eliminates its own columns down the panel.  The next
+// row's candidate is taken while that row is updated, so each step makes one
+// pass.  The window's pivot steps sit in LDS; STAGE also stages the window.
+template <typename T, int NT, bool STAGE>
+__global__ __launch_bounds__(NT) void k_tail_panel_wide(DevLayout D, TailView TV, T* __restrict__ vals, int p0,
+                                                        int p1, int c0, int c1, T tau, int32_t* __restrict__ pert,
+                                                        int search)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int64_t rowoff[kNB];
+    __shared__ T lrow[kNB];
+    __shared__ T red_v[NT / 64];
+    __shared__ int red_i[NT / 64];
+    __shared__ int s_p;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wc = c1 - c0, np = p1 - p0;
+    int* tsw = reinterpret_cast<int*>(smem_raw);                              // wc: step pivoting the column
+    T* Xs = reinterpret_cast<T*>(smem_raw + (((size_t)wc * 4 + 15) & ~(size_t)15));   // STAGE: np x wc
+    for (int r = tid; r < np; r += NT) rowoff[r] = TV.trow[p0 + r];
+    for (int c = tid; c < wc; c += NT) tsw[c] = TV.tstep[c0 + c];
+    __syncthreads();
+    if (STAGE) {
+        for (int r = 0; r < np; r++)
+            for (int c = tid; c < wc; c += NT) Xs[r * wc + c] = vals[rowoff[r] + c0 + c];
+        __syncthreads();
+    }
+    auto X = [&](int r, int c) -> T& {   // panel-local row r, window-local column c
+        return STAGE ? Xs[r * wc + c] : vals[rowoff[r] + c0 + c];
+    };
+    // candidate of panel row 0
+    T cv = T(-1);
+    int ci = wc;
+    if (search) {
+        const int lo0 = TV.tlo[p0] - c0, hi0 = TV.thi[p0] - c0;
+        for (int c = tid; c < wc; c += NT) {
+            if (tsw[c] <= p0 || c < lo0 || c >= hi0) continue;
+            const T x = pmag(X(0, c));
+            if (x > cv) { cv = x; ci = c; }     // ascending c: the first maximum is the lowest column
+        }
+    }
+    for (int a = 0; a < np; a++) {
+        const int ga = p0 + a;
+        const int lo = TV.tlo[ga], hi = TV.thi[ga];
+        int p;
+        if (!search) {
+            p = TV.tpiv[ga] - c0;
+        } else if (hi - lo == 1) {
+            p = lo - c0;
+        } else {
+            // block argmax of (cv, ci): larger value, then lower column
+            T bv = cv;
+            int bi = ci;
+            for (int off = 32; off > 0; off >>= 1) {
+                const T ov = __shfl_xor(bv, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+            }
+            if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
+            __syncthreads();
+            if (tid == 0) {
+                for (int w = 1; w < NT / 64; w++)
+                    if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) { bv = red_v[w]; bi = red_i[w]; }
+                s_p = bi;
+            }
+            __syncthreads();
+            p = s_p;
+        }
+        if (tid == 0) {
+            T d = X(a, p);
+            if (tabs(d) < tau) {
+                X(a, p) = d < T(0) ? -tau : tau;
+                atomicAdd(pert, 1);
+            }
+            TV.tpiv[ga] = c0 + p;
+            TV.tstep[c0 + p] = ga;
+            tsw[p] = ga;
+            D.pl[TV.t0 + ga] = c0 + p - lo;
+            D.qinv[TV.t0 + c0 + p] = TV.t0 + ga;
+        }
+        __syncthreads();
+        const T d = X(a, p);
+        if (tid > a && tid < np) {
+            const T l = X(tid, p) / d;
+            X(tid, p) = l;
+            lrow[tid] = l;
+        }
+        __syncthreads();
+        cv = T(-1);
+        ci = wc;
+        const int nlo = a + 1 < np ? TV.tlo[ga + 1] - c0 : 0, nhi = a + 1 < np ? TV.thi[ga + 1] - c0 : 0;
+        for (int c = tid; c < wc; c += NT) {
+            if (tsw[c] <= ga) continue;             // pivoted (this step's pivot included)
+            const T u = X(a, c);
+            if (a + 1 < np) {
+                const T x1 = X(a + 1, c) - lrow[a + 1] * u;
+                X(a + 1, c) = x1;
+                if (pmag(x1) > cv && c >= nlo && c < nhi) { cv = pmag(x1); ci = c; }
+            }
+#pragma unroll 4
+            for (int r = a + 2; r < np; r++) X(r, c) -= lrow[r] * u;
+        }
+        __syncthreads();
+    }
+    if (STAGE) {
+        for (int r = 0; r < np; r++)
+            for (int c = tid; c < wc; c += NT) vals[rowoff[r] + c0 + c] = Xs[r * wc + c];
+    }
+}
+
 // panel factorisation with the window in LDS, one wavefront: lanes own
 // window columns (wc <= 64); for every panel row the pivot is a wave
 // reduction and the elimination walks the remaining rows, each lane updating
@@ -807,7 +946,7 @@ __global__ __launch_bounds__(64) void k_tail_panel_lds(DevLayout D, TailView TV,
             T best = T(-1);
             int bi = 0x7fffffff;
             const int c = c0 + lane;
-            if (lane < wc && c >= lo && c < hi && mystep > a) { best = tabs(Xa[lane]); bi = c; }
+            if (lane < wc && c >= lo && c < hi && mystep > a) { best = pmag(Xa[lane]); bi = c; }
             for (int off = 32; off > 0; off >>= 1) {
                 T ob = __shfl_xor(best, off, 64);
                 int oi = __shfl_xor(bi, off, 64);
@@ -884,7 +1023,7 @@ __global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ v
     __syncthreads();
     if ((int)blockIdx.x < nA) {
         const int c = c1 + blockIdx.x * 64 + tid;
-        if (c >= TV.mT) return;
+        if (c >= TV.nc) return;
         T colv[kNB];
 #pragma unroll
         for (int a = 0; a < kNB; a++) {
@@ -945,7 +1084,7 @@ __global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ 
 {
     typedef typename Mfma<T>::v4 v4;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int np = p1 - p0, mT = TV.mT;
+    const int np = p1 - p0, mT = TV.mT, nc = TV.nc;
     // block tile 64 x 64, four wavefronts of 32 x 32 (2 x 2 MFMA blocks each)
     const int r0 = p1 + blockIdx.y * 64 + (wv >> 1) * 32, c0 = cg0 + blockIdx.x * 64 + (wv & 1) * 32;
     const T* lb = reinterpret_cast<const T*>(TV.lbuf);
@@ -957,7 +1096,7 @@ __global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ 
         for (int j = 0; j < 2; j++) acc[i][j] = v4{T(0), T(0), T(0), T(0)};
     const bool rok0 = r0 + li < mT, rok1 = r0 + 16 + li < mT;
     const int cb = c0 + li;
-    const bool cok0 = cb < mT, cok1 = cb + 16 < mT;
+    const bool cok0 = cb < nc, cok1 = cb + 16 < nc;
     const T* arow = lb + (int64_t)lk * mT + r0 + li;
 #pragma unroll
     for (int ks = 0; ks < kNB / 4; ks++) {
@@ -1167,21 +1306,27 @@ hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st)
 static const int32_t kRowLdsCap = 4096;   // row accumulator in LDS up to this width
 
 hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t nrows,
-                              int32_t maxW, double tau, int32_t* pert, hipStream_t st)
+                              int32_t maxW, double tau, int32_t* pert, int32_t nt, hipStream_t st)
 {
     if (nrows <= 0) return hipSuccess;
     int32_t cap = std::min(maxW, kRowLdsCap);
     size_t fixed = (size_t)kStage * 4 + 129 * 4 + 4 + 128 * 8;   // indices, edge tables (8-byte aligned)
-    const bool wide = maxW > 1024;                                 // 4 waves per row for long rows
+    if (nt == 0) nt = maxW > 1024 ? 256 : 64;                      // default: 4 waves per row for long rows
+    const size_t sh = (fp32 ? sizeof(float) : sizeof(double)) * (kStage + (size_t)std::max(cap, 1)) + fixed;
+    const dim3 g(nrows);
+#define ROWS_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_rows<TT, NTT>), g, dim3(NTT), sh, st, D, (TT*)vals, rows, nrows, cap, (TT)tau, pert)
     if (fp32) {
-        size_t sh = sizeof(float) * (kStage + (size_t)std::max(cap, 1)) + fixed;
-        if (wide) hipLaunchKernelGGL((k_factor_rows<float, 256>), dim3(nrows), dim3(256), sh, st, D, (float*)vals, rows, nrows, cap, (float)tau, pert);
-        else hipLaunchKernelGGL((k_factor_rows<float, 64>), dim3(nrows), dim3(64), sh, st, D, (float*)vals, rows, nrows, cap, (float)tau, pert);
+        if (nt == 256) ROWS_LAUNCH(float, 256);
+        else if (nt == 128) ROWS_LAUNCH(float, 128);
+        else if (nt == 64) ROWS_LAUNCH(float, 64);
+        else return hipErrorInvalidValue;
     } else {
-        size_t sh = sizeof(double) * (kStage + (size_t)std::max(cap, 1)) + fixed;
-        if (wide) hipLaunchKernelGGL((k_factor_rows<double, 256>), dim3(nrows), dim3(256), sh, st, D, (double*)vals, rows, nrows, cap, tau, pert);
-        else hipLaunchKernelGGL((k_factor_rows<double, 64>), dim3(nrows), dim3(64), sh, st, D, (double*)vals, rows, nrows, cap, tau, pert);
+        if (nt == 256) ROWS_LAUNCH(double, 256);
+        else if (nt == 128) ROWS_LAUNCH(double, 128);
+        else if (nt == 64) ROWS_LAUNCH(double, 64);
+        else return hipErrorInvalidValue;
     }
+#undef ROWS_LAUNCH
     return hipGetLastError();
 }
 
@@ -1216,13 +1361,20 @@ hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, v
 }
 
 hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const int32_t* nodes, int32_t count,
-                              int32_t maxm, double tau, int32_t* pert, int32_t search, hipStream_t st)
+                              int32_t maxm, double tau, int32_t* pert, int32_t search, int32_t nt, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
     size_t sh = (size_t)maxm * ((fp32 ? sizeof(float) : sizeof(double)) + 1) + 16;
     if (sh > 60 * 1024) return hipErrorInvalidValue;   // larger blocks need the tiled path
-    if (fp32) hipLaunchKernelGGL(k_factor_snlu<float>, dim3(count), dim3(256), sh, st, D, (float*)vals, nodes, count, (float)tau, pert, search);
-    else hipLaunchKernelGGL(k_factor_snlu<double>, dim3(count), dim3(256), sh, st, D, (double*)vals, nodes, count, tau, pert, search);
+    if (nt == 0) nt = 256;
+    if (nt != 64 && nt != 256) return hipErrorInvalidValue;
+    if (fp32) {
+        if (nt == 64) hipLaunchKernelGGL((k_factor_snlu<float, 64>), dim3(count), dim3(64), sh, st, D, (float*)vals, nodes, count, (float)tau, pert, search);
+        else hipLaunchKernelGGL((k_factor_snlu<float, 256>), dim3(count), dim3(256), sh, st, D, (float*)vals, nodes, count, (float)tau, pert, search);
+    } else {
+        if (nt == 64) hipLaunchKernelGGL((k_factor_snlu<double, 64>), dim3(count), dim3(64), sh, st, D, (double*)vals, nodes, count, tau, pert, search);
+        else hipLaunchKernelGGL((k_factor_snlu<double, 256>), dim3(count), dim3(256), sh, st, D, (double*)vals, nodes, count, tau, pert, search);
+    }
     return hipGetLastError();
 }
 
@@ -1292,11 +1444,12 @@ hipError_t launch_residual(int32_t n, int32_t nrhs, const int64_t* rp, const int
 }
 
 hipError_t launch_norms(int32_t n, int32_t nrhs, const int64_t* rp, const double* av, const double* r,
-                        const double* x, int64_t ldx, const double* b, int64_t ldb, double* out, hipStream_t st)
+                        const double* x, int64_t ldx, const double* b, int64_t ldb, const int32_t* seg,
+                        int32_t nseg, double* out, hipStream_t st)
 {
-    hipError_t e = launch_zero(out, sizeof(double) * (4 * (size_t)nrhs + 1), st);
+    hipError_t e = launch_zero(out, sizeof(double) * 4 * ((size_t)nrhs + 1) * (size_t)nseg, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_norms, dim3(nblk(n, 256)), dim3(256), 0, st, n, nrhs, rp, av, r, x, ldx, b, ldb, out);
+    hipLaunchKernelGGL(k_norms, dim3(nblk(n, 256)), dim3(256), 0, st, n, nrhs, rp, av, r, x, ldx, b, ldb, seg, nseg, out);
     return hipGetLastError();
 }
 
@@ -1317,7 +1470,7 @@ hipError_t launch_grad(int32_t n, const int64_t* rp, const int32_t* ci, const do
 hipError_t launch_tail_init(const TailView& T, hipStream_t st)
 {
     if (T.mT <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tail_init, dim3(nblk(T.mT, 256)), dim3(256), 0, st, T.mT, T.tstep);
+    hipLaunchKernelGGL(k_tail_init, dim3(nblk(T.nc, 256)), dim3(256), 0, st, T.nc, T.tstep);
     return hipGetLastError();
 }
 
@@ -1331,15 +1484,26 @@ hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, v
         if (fp32) hipLaunchKernelGGL(k_tail_panel_lds<float>, dim3(1), dim3(64), sh, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
         else hipLaunchKernelGGL(k_tail_panel_lds<double>, dim3(1), dim3(64), sh, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
     } else {
-        if (fp32) hipLaunchKernelGGL((k_tail_panel<float, false>), dim3(1), dim3(256), 0, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
-        else hipLaunchKernelGGL((k_tail_panel<double, false>), dim3(1), dim3(256), 0, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+        // wide window: steps in LDS, the window itself too when it fits
+        const size_t tsz = ((size_t)(c1 - c0) * 4 + 15) & ~(size_t)15;
+        const size_t stg = tsz + sh;
+        if (stg <= 60 * 1024) {
+            if (fp32) hipLaunchKernelGGL((k_tail_panel_wide<float, 256, true>), dim3(1), dim3(256), stg, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
+            else hipLaunchKernelGGL((k_tail_panel_wide<double, 256, true>), dim3(1), dim3(256), stg, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+        } else if (tsz <= 60 * 1024) {
+            if (fp32) hipLaunchKernelGGL((k_tail_panel_wide<float, 1024, false>), dim3(1), dim3(1024), tsz, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
+            else hipLaunchKernelGGL((k_tail_panel_wide<double, 1024, false>), dim3(1), dim3(1024), tsz, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+        } else {
+            if (fp32) hipLaunchKernelGGL((k_tail_panel<float, false>), dim3(1), dim3(256), 0, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
+            else hipLaunchKernelGGL((k_tail_panel<double, false>), dim3(1), dim3(256), 0, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+        }
     }
     return hipGetLastError();
 }
 
 hipError_t launch_tail_trsm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t c1, hipStream_t st)
 {
-    int nA = (int)nblk(std::max(T.mT - c1, 0), 64);
+    int nA = (int)nblk(std::max(T.nc - c1, 0), 64);
     int nB = (int)nblk(std::max(T.mT - p1, 0), 64);
     if (nA + nB == 0) return hipSuccess;
     if (fp32) hipLaunchKernelGGL(k_tail_trsm<float>, dim3(nA + nB), dim3(64), 0, st, T, (float*)vals, p0, p1, c1, nA);
@@ -1349,7 +1513,7 @@ hipError_t launch_tail_trsm(bool fp32, const TailView& T, void* vals, int32_t p0
 
 hipError_t launch_tail_gemm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t cg0, hipStream_t st)
 {
-    int gx = (int)nblk(std::max(T.mT - cg0, 0), 64), gy = (int)nblk(std::max(T.mT - p1, 0), 64);
+    int gx = (int)nblk(std::max(T.nc - cg0, 0), 64), gy = (int)nblk(std::max(T.mT - p1, 0), 64);
     if (gx == 0 || gy == 0) return hipSuccess;
     if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(gx, gy), dim3(256), 0, st, T, (float*)vals, p0, p1, cg0);
     else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(gx, gy), dim3(256), 0, st, T, (double*)vals, p0, p1, cg0);

@@ -58,9 +58,12 @@ struct DevLayout {
 };
 
 // Dense tail: rows and columns [t0, n) of the factors as one dense block whose
-// rows live inside their nodes' panels (row a starts at vals + trow[a]).
+// rows live inside their nodes' panels (row a starts at vals + trow[a]).  The
+// same view describes a large supernode factored by the same blocked kernels:
+// its m rows, its block plus T columns, pivot windows its whole block.
 struct TailView {
     int32_t mT, t0;
+    int32_t nc;             // columns (>= mT): a supernode's block plus its T columns; mT for the tail
     const int64_t* trow;    // value offset of tail row a's dense part
     const int32_t* tlo;     // tail-local block range of row a's node: its pivot window
     const int32_t* thi;
@@ -91,14 +94,16 @@ hipError_t launch_tail_lt(bool fp32, const TailView& T, const void* vals, int32_
 hipError_t launch_scatter(bool fp32, const double* aval, const int64_t* amap, const double* asr,
                           const double* asc, int64_t nnz, void* vals, double* acopy, hipStream_t st);
 hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st);
+// nt: threads per row (64, 128 or 256; 0 picks by the widest row of the launch)
 hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t nrows,
-                              int32_t maxW, double tau, int32_t* pert, hipStream_t st);
+                              int32_t maxW, double tau, int32_t* pert, int32_t nt, hipStream_t st);
 hipError_t launch_pipe_reset(const PipeCtl& P, int32_t nnodes, hipStream_t st);
 hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, void* vals, const int32_t* rows,
                               int32_t nrows, int32_t maxW, int32_t maxm, double tau, int32_t* pert, int32_t search,
                               hipStream_t st);
+// nt: threads per supernode (64 or 256; 0 = 256)
 hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const int32_t* nodes, int32_t count,
-                              int32_t maxm, double tau, int32_t* pert, int32_t search, hipStream_t st);
+                              int32_t maxm, double tau, int32_t* pert, int32_t search, int32_t nt, hipStream_t st);
 hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
                          void* y, int32_t nrhs, hipStream_t st);
 hipError_t launch_usolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
@@ -116,9 +121,12 @@ hipError_t launch_permute_out(bool fp32, int32_t n, int32_t nrhs, const int32_t*
 // r = b - op(A) x (FP64), op = A (CSR) or A^T (via the column copy)
 hipError_t launch_residual(int32_t n, int32_t nrhs, const int64_t* rp, const int32_t* ci, const double* av,
                            const double* b, int64_t ldb, const double* x, int64_t ldx, double* r, hipStream_t st);
-// per-RHS maxima: out[4 r + 0] = max|r|, +1 max|x|, +2 max|b|; out[4 nrhs] = max row abs sum of A
+// per-RHS, per-segment maxima (segments: the members of a batch, seg[row] ->
+// member, or one segment when seg is null): out[4 (r nseg + s) + 0] = max|r|,
+// +1 max|x|, +2 max|b|; out[4 (nrhs nseg + s)] = max row abs sum of A
 hipError_t launch_norms(int32_t n, int32_t nrhs, const int64_t* rp, const double* av, const double* r,
-                        const double* x, int64_t ldx, const double* b, int64_t ldb, double* out, hipStream_t st);
+                        const double* x, int64_t ldx, const double* b, int64_t ldb, const int32_t* seg,
+                        int32_t nseg, double* out, hipStream_t st);
 hipError_t launch_gather_values(int64_t nnz, const int64_t* idx, const double* src, double* dst, hipStream_t st);
 hipError_t launch_grad(int32_t n, const int64_t* rp, const int32_t* ci, const double* lam, const double* x,
                        double* g, hipStream_t st);

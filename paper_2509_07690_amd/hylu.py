@@ -36,7 +36,8 @@ class Options(C.Structure):
                 ("ir_maxit", C.c_int32), ("sn_min", C.c_int32), ("sn_max", C.c_int32),
                 ("kernel_mode", C.c_int32), ("repeated", C.c_int32), ("nd_leaf", C.c_int32),
                 ("amd_dense", C.c_double), ("dense_tail", C.c_double), ("tail_min", C.c_int32),
-                ("tail_max", C.c_int32), ("pipeline_rows", C.c_int32)]
+                ("tail_max", C.c_int32), ("sn_dense", C.c_int32),
+                ("pipeline_rows", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -148,6 +149,7 @@ class Handle:
 
     def __init__(self, row_ptr, col, val, user_perm=None, **opts):
         self.h = C.c_void_p()
+        self.fact_id = 0          # bumped by every (re)factorisation
         _chk(_lib.hylu_create(C.byref(self.h), None), "create")
         rp = _np(row_ptr, np.int64)
         ci = _np(col, np.int32)
@@ -162,6 +164,41 @@ class Handle:
         self.opts = default_options(**opts)
         _chk(_lib.hylu_analyze(self.h, self.n, _ptr(rp), _ptr(ci), _ptr(va), C.byref(self.opts)), "analyze")
         self.row_ptr, self.col = rp, ci
+
+    @classmethod
+    def batch(cls, members, **opts):
+        """One handle for a batch of matrices of uneven sizes (block diagonal;
+        see hylu_analyze_batch).  members: sequence of (row_ptr, col, val)
+        host CSR triples.  Values and right-hand sides are passed back to back
+        in member order; `offsets()` gives the row and value ranges."""
+        self = cls.__new__(cls)
+        self.h = C.c_void_p()
+        self.fact_id = 0
+        self._perm = None
+        _chk(_lib.hylu_create(C.byref(self.h), None), "create")
+        mats = [(_np(rp, np.int64), _np(ci, np.int32), _np(va, np.float64)) for rp, ci, va in members]
+        k = len(mats)
+        ns = (C.c_int32 * k)(*[m[0].size - 1 for m in mats])
+        rps = (C.c_void_p * k)(*[m[0].ctypes.data for m in mats])
+        cis = (C.c_void_p * k)(*[m[1].ctypes.data for m in mats])
+        vas = (C.c_void_p * k)(*[m[2].ctypes.data for m in mats])
+        self.opts = default_options(**opts)
+        _chk(_lib.hylu_analyze_batch(self.h, k, ns, rps, cis, vas, C.byref(self.opts)), "analyze_batch")
+        roff, qoff = self.offsets()
+        self.n, self.nnz = int(roff[-1]), int(qoff[-1])
+        self.row_ptr = np.concatenate([[0]] + [m[0][1:] + q for m, q in zip(mats, qoff[:-1])]).astype(np.int64)
+        self.col = np.concatenate([m[1] + r for m, r in zip(mats, roff[:-1])]).astype(np.int32)
+        return self
+
+    def offsets(self):
+        """(row_off, nnz_off): member k owns rows row_off[k]:row_off[k+1] and
+        values nnz_off[k]:nnz_off[k+1]."""
+        cnt = C.c_int32()
+        _chk(_lib.hylu_batch_offsets(self.h, C.byref(cnt), None, None), "batch_offsets")
+        ro = np.empty(cnt.value + 1, np.int64)
+        qo = np.empty(cnt.value + 1, np.int64)
+        _chk(_lib.hylu_batch_offsets(self.h, C.byref(cnt), _ptr(ro), _ptr(qo)), "batch_offsets")
+        return ro, qo
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:
@@ -178,10 +215,12 @@ class Handle:
     def factorize(self, values, stream=None):
         import torch
         _chk(_lib.hylu_factorize(self.h, _dev_ptr(values, torch.float64), _stream(stream)), "factorize")
+        self.fact_id += 1
 
     def refactor(self, values, stream=None):
         import torch
         _chk(_lib.hylu_refactor(self.h, _dev_ptr(values, torch.float64), _stream(stream)), "refactor")
+        self.fact_id += 1
 
     def solve(self, b, out=None, transpose=False, stream=None):
         """b: (n,) or (n, k) float64 CUDA tensor (column-major for k > 1 means
@@ -206,6 +245,16 @@ class Handle:
                              1 if transpose else 0, _stream(stream))
         _chk(rc, "solve", allow_warn=True)
         return x
+
+    def autotune(self, values, reps=2, stream=None):
+        """Pick per-level thread counts by timing (hylu_autotune); returns the
+        summed level times (ms) with the built-in and with the chosen shapes."""
+        import torch
+        before, after = C.c_double(), C.c_double()
+        _chk(_lib.hylu_autotune(self.h, _dev_ptr(values, torch.float64), _stream(stream), int(reps),
+                                C.byref(before), C.byref(after)), "autotune")
+        self.fact_id += 1
+        return before.value, after.value
 
     def grad_values(self, lam, x, out=None, stream=None):
         import torch
@@ -255,6 +304,57 @@ class Handle:
                                                  ("vals", "voff", "lw", "W", "coff", "cols", "piv")]),
              "export_factors")
         return out
+
+
+class SparseSolve(torch.autograd.Function):
+    """x = A(val)^{-1} b on the handle's pattern, with a hand-written adjoint.
+
+    forward: (re)factorise with `val` (the first call factorises with pivot
+    search, later ones reuse that pivot order) and solve.
+    backward: lambda = A^{-T} dL/dx by the transposed solve on the same
+    factors; dL/db = lambda and dL/dval[p] = -lambda[row p] * x[col p], the
+    gradient of x = A^{-1} b restricted to the stored pattern.  If the handle
+    was refactorised with other values in between, it is refactorised with
+    this call's values first.  b is (n,) or (n, k); val is (nnz,).
+    """
+
+    @staticmethod
+    def forward(ctx, val, b, handle):
+        val = val.detach().contiguous()
+        if handle.fact_id == 0:
+            handle.factorize(val)
+        else:
+            handle.refactor(val)
+        x = handle.solve(b.detach().contiguous())
+        ctx.handle = handle
+        ctx.fact_id = handle.fact_id
+        ctx.save_for_backward(val, x)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        val, x = ctx.saved_tensors
+        h = ctx.handle
+        if h.fact_id != ctx.fact_id:
+            h.refactor(val)
+        lam = h.solve(gx.contiguous(), transpose=True)
+        gval = gb = None
+        if ctx.needs_input_grad[0]:
+            if x.dim() == 1:
+                gval = h.grad_values(lam, x)
+            else:
+                lc, xc = lam.t().contiguous(), x.t().contiguous()
+                gval = h.grad_values(lc[0], xc[0])
+                for k in range(1, xc.shape[0]):
+                    gval += h.grad_values(lc[k], xc[k])
+        if ctx.needs_input_grad[1]:
+            gb = lam
+        return gval, gb, None
+
+
+def sparse_solve(handle: Handle, val, b):
+    """Differentiable x = A(val)^{-1} b (see SparseSolve)."""
+    return SparseSolve.apply(val, b, handle)
 
 
 def factors_as_rows(h: Handle):

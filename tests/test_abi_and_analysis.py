@@ -139,3 +139,34 @@ def test_one_hip_runtime_in_the_process():
 def test_pipelined_mode_is_rejected():
     A = synth.config(0).A
     assert _code(lambda: hylu.Handle(A.row_ptr, A.col, A.val, pipeline_rows=1024)) == -1
+
+
+def test_batch_analysis_matches_members_and_oracle():
+    """Batched analysis: every member's permutations and scalings equal its own
+    single-matrix analysis (shifted by the member's offset), and the structure
+    of the union (flops, partition, levels) matches the oracle bit-exactly."""
+    members = [synth.batch_member(m).A for m in (0, 1, 2, 3)]
+    hb = hylu.Handle.batch([(a.row_ptr, a.col, a.val) for a in members])
+    roff, qoff = hb.offsets()
+    assert list(np.diff(roff)) == [a.n for a in members]
+    assert list(np.diff(qoff)) == [a.nnz for a in members]
+    sym = hb.symbolic()
+    for k, a in enumerate(members):
+        hs = hylu.Handle(a.row_ptr, a.col, a.val)
+        ss = hs.symbolic()
+        sl = slice(roff[k], roff[k + 1])
+        assert np.array_equal(sym["perm_r"][sl] - roff[k], ss["perm_r"])
+        assert np.array_equal(sym["perm_c"][sl] - roff[k], ss["perm_c"])
+        assert np.array_equal(sym["dr"][sl], ss["dr"]) and np.array_equal(sym["dc"][sl], ss["dc"])
+    U = synth.Csr(hb.n, hb.row_ptr, hb.col, np.concatenate([a.val for a in members]))
+    o = oracle.Oracle(U.n, U.row_ptr, U.col, U.val, sym["perm_r"], sym["perm_c"], sym["dr"], sym["dc"])
+    assert o.check_matching()
+    o.analyse()
+    inf = hb.info()
+    assert inf["flops"] == o.sizes()["flops"] and inf["tail_rows"] == 0
+    ptr, isn = o.partition_arrays()
+    assert np.array_equal(ptr, sym["node_ptr"]) and np.array_equal(isn, sym["is_sn"])
+    assert np.array_equal(o.level_arrays(), sym["levels"])
+    # the levels of the union are the members' levels side by side
+    assert inf["n_levels"][0] == max(hylu.Handle(a.row_ptr, a.col, a.val, dense_tail=0).info()["n_levels"][0]
+                                     for a in members)
