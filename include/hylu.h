@@ -74,6 +74,10 @@ typedef struct {
     int32_t sn_dense;      /* supernodes outside the dense tail with at least this many rows are factored by
                               the blocked panel / TRSM / MFMA-GEMM kernels instead of one workgroup each
                               (0: never; default 128) */
+    int32_t sn_tile;       /* supernodes outside the dense tail with at least this many rows take their
+                              updates from earlier nodes by 16-row tiles (MFMA for supernode sources) instead
+                              of one row per workgroup (0: never; default 0: on the 3D grids measured so far
+                              the per-tile triangular solves make it slower than the row kernel) */
     int32_t pipeline_rows; /* reserved for the pipelined mode of Sec. 2.2.1 (one persistent launch whose
                               blocks wait per source node); switched off: must be 0, else HYLU_ERR_ARG */
 } hylu_options;

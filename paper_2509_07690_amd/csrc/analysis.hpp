@@ -82,6 +82,8 @@ void make_levels(const Symbolic& s, Nodes& nd);
 // node's own L\U in pivoted column order, T the columns of U past the block.
 // rows per factorisation panel inside a node wider than one panel
 constexpr int32_t kWideChunk = 16;
+// rows per tile of the supernode-target update kernel
+constexpr int32_t kTileRowsHost = 16;
 
 struct Layout {
     int32_t n = 0, nnodes = 0;

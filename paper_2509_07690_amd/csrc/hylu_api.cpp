@@ -57,6 +57,8 @@ struct LevelTasks {
     std::vector<int32_t> maxm;
     std::vector<int32_t> rows, snodes;
     std::vector<int32_t> row_nt, sn_nt;  // per level: threads per row / per supernode (0: built-in rule)
+    std::vector<int64_t> tile_ptr;        // per level into tiles (pairs: node, first local row)
+    std::vector<int32_t> tiles;
     int32_t tune_rows = 0, tune_sn = 0;  // when nonzero, every level uses this (autotuner trials)
     int32_t pipe_level = 0;           // levels from here on run as one pipelined launch
     int32_t pipe_maxW = 0, pipe_maxm = 0;
@@ -91,14 +93,15 @@ struct hylu_handle_s {
     void* vals = nullptr;                   // factor panels (double or float)
     int64_t* d_amap = nullptr;
     double *d_asr = nullptr, *d_asc = nullptr;
-    int32_t *d_rows = nullptr, *d_snodes = nullptr;
+    int32_t *d_rows = nullptr, *d_snodes = nullptr, *d_tiles = nullptr;
     int32_t* d_lev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     TailView TV{};
     PipeCtl PC{};
     // large supernodes outside the tail, factored by the blocked dense kernels
-    struct DenseSn { int32_t v, level; TailView TV; std::vector<Layout::Panel> panels; };
+    struct DenseSn { int32_t v, level; TailView TV; std::vector<Layout::Panel> panels, spanels; };
     std::vector<DenseSn> dsn;
     std::vector<int32_t> dsn_ptr;           // per factor level into dsn
+    std::vector<std::vector<int32_t>> dsn_l, dsn_u;   // per L-solve / U-solve level: dsn indices
     static constexpr int kSide = 4;         // side streams for independent supernodes of a level
     hipStream_t side[kSide] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_join[kSide] = {nullptr, nullptr, nullptr, nullptr};
@@ -136,11 +139,12 @@ struct hylu_handle_s {
     // measurement
     Profiler prof;
     std::vector<double> lvl_bytes, lvl_flops;   // per factor level: row-kernel traffic and flops
+    std::vector<double> tile_bytes, tile_flops; // per factor level: tile-kernel traffic and flops
 };
 
 static const char* kClassNames[] = {"rows", "snlu", "tail_panel", "tail_trsm", "tail_gemm", "lsolve", "usolve",
-                                    "tail_solve", "scatter", "other_solve"};
-enum { C_ROWS, C_SNLU, C_PANEL, C_TRSM, C_GEMM, C_LSOLVE, C_USOLVE, C_TSOLVE, C_SCATTER, C_OSOLVE, C_N };
+                                    "tail_solve", "scatter", "other_solve", "sup_tile"};
+enum { C_ROWS, C_SNLU, C_PANEL, C_TRSM, C_GEMM, C_LSOLVE, C_USOLVE, C_TSOLVE, C_SCATTER, C_OSOLVE, C_TILE, C_N };
 
 namespace {
 
@@ -391,6 +395,10 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
         LAUNCH(C_ROWS, h->lvl_bytes[l] * es / 8.0, h->lvl_flops[l],
                launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.maxW[l], h->tau, h->d_pert,
                                   T.tune_rows ? T.tune_rows : T.row_nt[l], st));
+        if (T.tile_ptr[l + 1] > T.tile_ptr[l])
+            LAUNCH(C_TILE, h->tile_bytes[l] * es / 8.0, h->tile_flops[l],
+                   launch_factor_tile(h->fp32, h->D, h->vals, h->d_tiles + 2 * T.tile_ptr[l],
+                                      (int32_t)(T.tile_ptr[l + 1] - T.tile_ptr[l]), st));
         int64_t s0 = T.sn_ptr[l], s1 = T.sn_ptr[l + 1];
         if (s1 > s0) {
             double by = 0, fl = 0;
@@ -434,11 +442,28 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
     const Layout& L = h->lay;
     const int32_t n = h->n;
     const bool f = h->fp32;
+    // level launches of solve graph g; after each level, its large supernodes
+    // (forward and backward solves) through the dense-view kernels
     auto levels = [&](int g, auto&& fn) -> hylu_status {
         for (size_t l = 0; l + 1 < L.xlev_ptr[g].size(); l++) {
             int32_t a = L.xlev_ptr[g][l], c = L.xlev_ptr[g][l + 1] - a;
             int cls = g == 4 ? C_LSOLVE : g == 1 ? C_USOLVE : C_OSOLVE;
             if (c > 0) LAUNCH(cls, 0, 0, fn(h->d_lev[g] + a, c));
+            const std::vector<std::vector<int32_t>>* dl = g == 4 ? &h->dsn_l : g == 1 ? &h->dsn_u : nullptr;
+            if (!dl || l >= dl->size()) continue;
+            for (int32_t q : (*dl)[l]) {
+                const hylu_handle_s::DenseSn& d = h->dsn[q];
+                if (g == 4) {
+                    LAUNCH(cls, 0, 0, launch_sn_lext(f, h->D, d.TV, h->vals, d.v, h->d_y, nrhs, st));
+                    for (const Layout::Panel& P : d.spanels)
+                        LAUNCH(cls, 0, 0, launch_tail_fwd(f, d.TV, h->vals, P.p0, P.p1, n, h->d_y, nrhs, st));
+                } else {
+                    LAUNCH(cls, 0, 0, launch_sn_utext(f, h->D, d.TV, h->vals, d.v, h->d_y, h->d_z, nrhs, st));
+                    for (size_t k = d.spanels.size(); k-- > 0;)
+                        LAUNCH(cls, 0, 0, launch_tail_bwd(f, d.TV, h->vals, d.spanels[k].p0, d.spanels[k].p1, n,
+                                                          h->d_y, h->d_z, nrhs, st));
+                }
+            }
         }
         return HYLU_OK;
     };
@@ -554,7 +579,7 @@ hylu_status upload_device(hylu_handle h)
         D.r0 = r0; D.m = m; D.lw = lw; D.W = W; D.voff = voff; D.coff = coff; D.cols = cols;
         D.eptr = eptr; D.edges = edges; D.rel = rel; D.row_node = row_node; D.pl = pl; D.qinv = qinv;
         UP(h->d_amap, L.amap); UP(h->d_asr, asr); UP(h->d_asc, asc);
-        UP(h->d_rows, T.rows); UP(h->d_snodes, T.snodes);
+        UP(h->d_rows, T.rows); UP(h->d_snodes, T.snodes); UP(h->d_tiles, T.tiles);
         for (int g = 0; g < 5; g++) UP(h->d_lev[g], L.xlev_nodes[g]);
         {
             TailView& TVw = h->TV;
@@ -581,6 +606,13 @@ hylu_status upload_device(hylu_handle h)
             q.TV.trow = trow; q.TV.tlo = tlo; q.TV.thi = thi; q.TV.tpiv = tpiv; q.TV.tstep = tstep;
             q.TV.lbuf = dalloc(h, (size_t)64 * m * (h->fp32 ? 4 : 8));
             if (!q.TV.lbuf) return HYLU_ERR_OOM;
+        }
+        if (!h->dsn.empty()) {
+            std::vector<uint8_t> fl(L.nnodes, 0);
+            for (const hylu_handle_s::DenseSn& q : h->dsn) fl[q.v] = 1;
+            uint8_t* d_fl;
+            UP(d_fl, fl);
+            h->D.dense_sn = d_fl;
         }
         if (!h->dsn.empty() && !h->side[0]) {
             for (int j = 0; j < hylu_handle_s::kSide; j++) {
@@ -737,12 +769,19 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     h->dsn.clear();
     h->dsn_ptr.assign(1, 0);
     const int32_t big = opt.sn_dense > 0 ? opt.sn_dense : std::numeric_limits<int32_t>::max();
+    const int32_t tile_min = opt.sn_tile > 0 ? opt.sn_tile : std::numeric_limits<int32_t>::max();
+    T.tile_ptr.assign(1, 0);
     for (int32_t l = 0; l < nl; l++) {
         int32_t mw = 0, mm = 0;
         for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) {
             int32_t v = L.xlev_nodes[0][t];
-            for (int32_t r = L.r0[v]; r < L.r0[v] + L.m[v]; r++) T.rows.push_back(r);
-            mw = std::max(mw, L.W[v]);
+            if (nd.is_sn[v] && v < L.tail_node0 && L.m[v] >= tile_min) {
+                // outside updates of a large supernode target by 16-row tiles
+                for (int32_t a = 0; a < L.m[v]; a += kTileRowsHost) { T.tiles.push_back(v); T.tiles.push_back(a); }
+            } else {
+                for (int32_t r = L.r0[v]; r < L.r0[v] + L.m[v]; r++) T.rows.push_back(r);
+                mw = std::max(mw, L.W[v]);
+            }
             if (!nd.is_sn[v] || v >= L.tail_node0) continue;
             if (L.m[v] >= big) {
                 // blocked LU on the supernode's panel: kWideChunk-row panels, the
@@ -752,6 +791,8 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 q.level = l;
                 for (int32_t k = 0; k < L.m[v]; k += kWideChunk)
                     q.panels.push_back({k, std::min(k + kWideChunk, L.m[v]), 0, L.m[v], 0});
+                for (int32_t k = 0; k < L.m[v]; k += 64)
+                    q.spanels.push_back({k, std::min(k + 64, L.m[v]), 0, L.m[v], 0});
                 h->dsn.push_back(std::move(q));
             } else {
                 T.snodes.push_back(v);
@@ -760,6 +801,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         }
         h->dsn_ptr.push_back((int32_t)h->dsn.size());
         T.row_ptr.push_back((int64_t)T.rows.size());
+        T.tile_ptr.push_back((int64_t)T.tiles.size() / 2);
         T.sn_ptr.push_back((int64_t)T.snodes.size());
         T.maxW.push_back(mw);
         T.maxm.push_back(mm);
@@ -770,24 +812,47 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     T.node_level.assign(L.nnodes, 0);
     for (int32_t l = 0; l < nl; l++)
         for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) T.node_level[L.xlev_nodes[0][t]] = l;
+    // the large supernodes' places in the L-solve and U-solve level sequences
+    {
+        std::vector<int32_t> dix(L.nnodes, -1);
+        for (size_t q = 0; q < h->dsn.size(); q++) dix[h->dsn[q].v] = (int32_t)q;
+        for (int g : {4, 1}) {
+            auto& out = g == 4 ? h->dsn_l : h->dsn_u;
+            out.assign(L.xlev_ptr[g].size() > 0 ? L.xlev_ptr[g].size() - 1 : 0, {});
+            for (size_t l = 0; l + 1 < L.xlev_ptr[g].size(); l++)
+                for (int32_t t = L.xlev_ptr[g][l]; t < L.xlev_ptr[g][l + 1]; t++)
+                    if (dix[L.xlev_nodes[g][t]] >= 0) out[l].push_back(dix[L.xlev_nodes[g][t]]);
+        }
+    }
     // pipeline mode stays off: its dataflow launch did not finish on the device
     // and the reason is not established, so every level is a launch of its own
     T.pipe_level = nl;
-    // algorithmic traffic and flops of every row-kernel launch (8-byte values)
+    // algorithmic traffic and flops of every row-kernel and tile launch
+    // (8-byte values): the row or tile is read and written once, each source's
+    // panel is read once per row (row kernel) or once per tile
     h->lvl_bytes.assign(nl, 0.0);
     h->lvl_flops.assign(nl, 0.0);
+    h->tile_bytes.assign(nl, 0.0);
+    h->tile_flops.assign(nl, 0.0);
     for (int32_t l = 0; l < nl; l++)
         for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) {
             int32_t v = L.xlev_nodes[0][t];
-            double m = L.m[v], by = 16.0 * L.W[v], fl = 0;
+            const bool tiled = nd.is_sn[v] && v < L.tail_node0 && L.m[v] >= tile_min;
+            double m = L.m[v], by = 16.0 * L.W[v], src = 0, fl = 0;
             for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
                 int32_t u = L.esrc[e];
                 double ms = L.m[u], ws = L.W[u] - L.lw[u] - L.m[u];
-                by += 8.0 * ms * (ms + ws) + 4.0 * ws + 48.0;
+                src += 8.0 * ms * (ms + ws) + 4.0 * ws + 48.0;
                 fl += ms * (ms + 2.0 * ws);
             }
-            h->lvl_bytes[l] += m * by;
-            h->lvl_flops[l] += m * fl;
+            if (tiled) {
+                double ntile = std::ceil(m / kTileRowsHost);
+                h->tile_bytes[l] += m * by + ntile * src;
+                h->tile_flops[l] += m * fl;
+            } else {
+                h->lvl_bytes[l] += m * (by + src);
+                h->lvl_flops[l] += m * fl;
+            }
         }
     plog("tasks");
     h->analyzed = true;
@@ -819,6 +884,7 @@ hylu_status hylu_default_options(hylu_options* o)
     o->tail_min = 64;
     o->tail_max = 32768;
     o->sn_dense = 128;
+    o->sn_tile = 0;
     o->pipeline_rows = 0;
     return HYLU_OK;
 }

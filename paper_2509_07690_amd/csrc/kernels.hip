@@ -453,6 +453,7 @@ __global__ __launch_bounds__(64) void k_lsolve(DevLayout D, const T* __restrict_
                                                T* __restrict__ y, int32_t nrhs)
 {
     const int v = nodes[blockIdx.x];
+    if (D.dense_sn && D.dense_sn[v]) return;     // solved by the dense-view kernels
     const int lane = threadIdx.x;
     const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
     const T* P = vals + D.voff[v];
@@ -480,6 +481,7 @@ __global__ __launch_bounds__(64) void k_usolve(DevLayout D, const T* __restrict_
                                                const T* __restrict__ y, T* __restrict__ x, int32_t nrhs)
 {
     const int v = nodes[blockIdx.x];
+    if (D.dense_sn && D.dense_sn[v]) return;     // solved by the dense-view kernels
     const int lane = threadIdx.x;
     const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
     const int w = W - lw - m;
@@ -1128,6 +1130,130 @@ __global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ 
         }
 }
 
+// ---- row tiles of supernode targets (sup-sup on MFMA)
+//
+// One workgroup takes kTileRows consecutive rows of a target supernode and
+// applies every source in ascending order, as the row kernel does for one
+// row, so each source's panel is read once per tile instead of once per row.
+// Standalone source: multipliers l_r = X[r][lp] / pivot, then a rank-1 update
+// through the relative map, each wavefront on its own four rows.  Supernode source s (ms rows): the tile's block
+// columns of s are solved against U_ss in s's pivot order (TRSM, staged in
+// LDS when ms <= kTileMs), then X[:, rel(T_s)] -= L (tile x ms) * U_s,T on
+// 16x16x4 MFMA, 16-column blocks per wavefront, scattered through rel.
+constexpr int kTileRows = 16;
+constexpr int kTileMs = 448;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_factor_tile(DevLayout D, T* __restrict__ vals,
+                                                     const int32_t* __restrict__ tiles, int32_t ntiles)
+{
+    typedef typename Mfma<T>::v4 v4;
+    __shared__ T Xs[kTileRows][kTileMs + 1];
+    __shared__ int pls[kTileMs];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int v = tiles[2 * blockIdx.x], a0 = tiles[2 * blockIdx.x + 1];
+    const int m = D.m[v], W = D.W[v];
+    const int R = min(kTileRows, m - a0);
+    T* X0 = vals + D.voff[v] + (int64_t)a0 * W;
+    const int64_t e1 = D.eptr[v + 1];
+    for (int64_t e = D.eptr[v]; e < e1; e++) {
+        const EdgeDesc ed = D.edges[e];
+        const T* Us = vals + ed.uoff;
+        const int32_t* rl = D.rel + ed.roff;
+        const int lp = ed.lp, ms = ed.ms, Ws = ed.Ws, ws = ed.ws;
+        if (ms == 1) {
+            // standalone source: wavefront w updates rows w, w+4, w+8, w+12 on
+            // its own, so runs of standalone sources need no block barrier
+            for (int r = wv; r < R; r += 4) {
+                T* Xr = X0 + (int64_t)r * W;
+                const T l = Xr[lp] / Us[0];
+                for (int j = lane; j < ws; j += 64) Xr[rl[j]] -= l * Us[1 + j];
+                if (lane == 0) Xr[lp] = l;
+            }
+            __threadfence_block();
+            continue;
+        }
+        __syncthreads();     // the standalone updates of every wavefront are in
+        const int32_t* plg = D.pl + ed.r0s;
+        const bool in_lds = ms <= kTileMs;
+        // the tile's block columns of s in s's pivot order: XP(r, b) = X[r][lp + pl_b]
+        if (in_lds) {
+            for (int b = tid; b < ms; b += 256) pls[b] = plg[b];
+            __syncthreads();
+            for (int idx = tid; idx < kTileRows * ms; idx += 256) {
+                const int r = idx / ms, c = idx - (idx / ms) * ms;
+                Xs[r][c] = r < R ? X0[(int64_t)r * W + lp + pls[c]] : T(0);
+            }
+        }
+        __syncthreads();
+        auto PL = [&](int b) -> int { return in_lds ? pls[b] : plg[b]; };
+        auto XP = [&](int r, int b) -> T& { return in_lds ? Xs[r][b] : X0[(int64_t)r * W + lp + PL(b)]; };
+        // L = XP U_pp^{-1}, U_pp(b, b') = U(b, pl_b') upper triangular in pivot
+        // order; blocked by 16 columns on wavefront 0: the block's update from
+        // the solved columns on MFMA, then its 16 x 16 triangle, one lane per row
+        if (wv == 0) {
+            const int li = lane & 15;
+            for (int kb0 = 0; kb0 < ms; kb0 += 16) {
+                const int nb = min(16, ms - kb0);
+                if (kb0 > 0) {
+                    v4 acc = v4{T(0), T(0), T(0), T(0)};
+                    const int bc = kb0 + li;
+                    const int pc = bc < ms ? PL(bc) : 0;
+                    for (int k0 = 0; k0 < kb0; k0 += 4) {
+                        const int k = k0 + (lane >> 4);
+                        const T av = li < R ? XP(li, k) : T(0);
+                        const T bv = bc < ms ? Us[(int64_t)k * Ws + pc] : T(0);
+                        acc = Mfma<T>::mma(av, bv, acc);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const int r = Mfma<T>::row(lane, q);
+                        if (r < R && bc < ms) XP(r, bc) -= acc[q];
+                    }
+                    __threadfence_block();
+                }
+                if (lane < R) {
+                    for (int b = kb0; b < kb0 + nb; b++) {
+                        const T l = XP(lane, b) / Us[(int64_t)b * Ws + PL(b)];
+                        XP(lane, b) = l;
+                        for (int b2 = b + 1; b2 < kb0 + nb; b2++) XP(lane, b2) -= l * Us[(int64_t)b * Ws + PL(b2)];
+                    }
+                }
+                __threadfence_block();
+            }
+        }
+        __syncthreads();
+        if (in_lds) {
+            for (int idx = tid; idx < R * ms; idx += 256) {
+                const int r = idx / ms, c = idx - (idx / ms) * ms;
+                X0[(int64_t)r * W + lp + pls[c]] = Xs[r][c];
+            }
+        }
+        // X[:, rel(T_s)] -= L * U_s,T  (A: tile rows x source rows, B: source rows x T)
+        const T* Ut = Us + ms;
+        const int li = lane & 15, lk = lane >> 4;
+        for (int j0 = wv * 16; j0 < ws; j0 += 64) {
+            v4 acc = v4{T(0), T(0), T(0), T(0)};
+            const int jc = j0 + li;
+            for (int k0 = 0; k0 < ms; k0 += 4) {
+                const int k = k0 + lk;
+                const T a = (k < ms && li < R) ? XP(li, k) : T(0);
+                const T bv = (k < ms && jc < ws) ? Ut[(int64_t)k * Ws + jc] : T(0);
+                acc = Mfma<T>::mma(a, bv, acc);
+            }
+            if (jc < ws) {
+                const int c = rl[jc];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int r = Mfma<T>::row(lane, q);
+                    if (r < R) X0[(int64_t)r * W + c] -= acc[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---- dense tail solves (tail-local row/column a is global t0 + a)
 
 // forward, outside part: y_i -= sum over the L columns from outside the tail
@@ -1267,6 +1393,31 @@ __global__ __launch_bounds__(256) void k_tail_gemv(TailView TV, const T* __restr
     }
 }
 
+// one wavefront per row of a large supernode: the gathers outside its block
+template <typename T>
+__global__ __launch_bounds__(256) void k_sn_ext(DevLayout D, const T* __restrict__ vals, int v,
+                                                T* __restrict__ y, const T* __restrict__ x, int nrhs, int upper)
+{
+    const int lane = threadIdx.x & 63;
+    const int m = D.m[v];
+    const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (a >= m) return;
+    const int W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const T* Pa = vals + D.voff[v] + (int64_t)a * W;
+    const int32_t* cols = D.cols + D.coff[v];
+    const int n = D.n;
+    const int t0 = upper ? lw + m : 0, t1 = upper ? W : lw;
+    for (int r = 0; r < nrhs; r++) {
+        T* yr = y + (int64_t)r * n;
+        const T* xr = upper ? x + (int64_t)r * n : nullptr;
+        T acc = T(0);
+        if (upper) for (int t = t0 + lane; t < t1; t += 64) acc += Pa[t] * xr[cols[t]];
+        else for (int t = t0 + lane; t < t1; t += 64) acc += Pa[t] * yr[D.qinv[cols[t]]];
+        acc = wave_sum(acc);
+        if (lane == 0) yr[r0 + a] -= acc;
+    }
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -1285,6 +1436,33 @@ hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st)
     }
     int64_t rem = bytes - n64 * 8;
     if (rem > 0) hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, st, (uint8_t*)p + n64 * 8, rem);
+    return hipGetLastError();
+}
+
+hipError_t launch_factor_tile(bool fp32, const DevLayout& D, void* vals, const int32_t* tiles, int32_t ntiles,
+                              hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_factor_tile<float>, dim3(ntiles), dim3(256), 0, st, D, (float*)vals, tiles, ntiles);
+    else hipLaunchKernelGGL(k_factor_tile<double>, dim3(ntiles), dim3(256), 0, st, D, (double*)vals, tiles, ntiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_sn_lext(bool fp32, const DevLayout& D, const TailView& TV, const void* vals, int32_t v, void* y,
+                          int32_t nrhs, hipStream_t st)
+{
+    if (TV.mT <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_sn_ext<float>, dim3(nblk(TV.mT, 4)), dim3(256), 0, st, D, (const float*)vals, v, (float*)y, (const float*)nullptr, nrhs, 0);
+    else hipLaunchKernelGGL(k_sn_ext<double>, dim3(nblk(TV.mT, 4)), dim3(256), 0, st, D, (const double*)vals, v, (double*)y, (const double*)nullptr, nrhs, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_sn_utext(bool fp32, const DevLayout& D, const TailView& TV, const void* vals, int32_t v, void* y,
+                           const void* x, int32_t nrhs, hipStream_t st)
+{
+    if (TV.mT <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_sn_ext<float>, dim3(nblk(TV.mT, 4)), dim3(256), 0, st, D, (const float*)vals, v, (float*)y, (const float*)x, nrhs, 1);
+    else hipLaunchKernelGGL(k_sn_ext<double>, dim3(nblk(TV.mT, 4)), dim3(256), 0, st, D, (const double*)vals, v, (double*)y, (const double*)x, nrhs, 1);
     return hipGetLastError();
 }
 

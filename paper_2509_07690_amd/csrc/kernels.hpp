@@ -52,6 +52,7 @@ struct DevLayout {
     const int64_t* ut_ptr;  // per column (n+1): T-region entries in that column
     const int64_t* ut_slot;
     const int32_t* ut_row;
+    const uint8_t* dense_sn;  // per node: 1 when the forward / backward solves take it by the dense-view kernels
     const int64_t* lt_ptr;  // per column (n+1): L-region entries in that column
     const int64_t* lt_slot;
     const int32_t* lt_row;
@@ -91,12 +92,22 @@ hipError_t launch_tail_ut(bool fp32, const TailView& T, const void* vals, int32_
                           void* h, void* w, int32_t nrhs, hipStream_t st);
 hipError_t launch_tail_lt(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
                           void* w, int32_t nrhs, hipStream_t st);
+// one large supernode's rows (dense view TV, node v): forward, the L-region
+// gather y_i -= sum_{t < lw} L(i, t) y[source of t]; backward, the T-region
+// gather y_i -= sum_{t in T} U(i, t) x[column t] (before its block panels)
+hipError_t launch_sn_lext(bool fp32, const DevLayout& D, const TailView& TV, const void* vals, int32_t v, void* y,
+                          int32_t nrhs, hipStream_t st);
+hipError_t launch_sn_utext(bool fp32, const DevLayout& D, const TailView& TV, const void* vals, int32_t v, void* y,
+                           const void* x, int32_t nrhs, hipStream_t st);
 hipError_t launch_scatter(bool fp32, const double* aval, const int64_t* amap, const double* asr,
                           const double* asc, int64_t nnz, void* vals, double* acopy, hipStream_t st);
 hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st);
 // nt: threads per row (64, 128 or 256; 0 picks by the widest row of the launch)
 hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t nrows,
                               int32_t maxW, double tau, int32_t* pert, int32_t nt, hipStream_t st);
+// row tiles (16 rows) of supernode targets: tiles = pairs (node, first local row)
+hipError_t launch_factor_tile(bool fp32, const DevLayout& D, void* vals, const int32_t* tiles, int32_t ntiles,
+                              hipStream_t st);
 hipError_t launch_pipe_reset(const PipeCtl& P, int32_t nnodes, hipStream_t st);
 hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, void* vals, const int32_t* rows,
                               int32_t nrows, int32_t maxW, int32_t maxm, double tau, int32_t* pert, int32_t search,

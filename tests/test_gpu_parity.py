@@ -104,10 +104,13 @@ def test_integer_factors_bit_exact(hylu, seed):
     h, o, x, xo, eta = run_case(hylu, A, b, opts=dict(static_pivot=0, ordering="natural"), exact=True)
 
 
-@pytest.mark.parametrize("ordering,tail", [("amd", 0.5), ("nd", 0.5), ("amd", 0.0), ("amd", 0.05)])
-def test_config0_factor_solve(hylu, ordering, tail):
+@pytest.mark.parametrize("ordering,tail,tile", [("amd", 0.5, 16), ("nd", 0.5, 16), ("amd", 0.0, 16), ("amd", 0.05, 16),
+                                               ("nd", 0.0, 2), ("nd", 0.0, 0)])
+def test_config0_factor_solve(hylu, ordering, tail, tile):
+    """tile: supernode targets of at least this many rows take their updates
+    by 16-row tiles (2: every supernode; 0: the row kernel only)."""
     w = synth.config(0)
-    h, o, x, xo, eta = run_case(hylu, w.A, w.b[:, 0], opts=dict(ordering=ordering, dense_tail=tail))
+    h, o, x, xo, eta = run_case(hylu, w.A, w.b[:, 0], opts=dict(ordering=ordering, dense_tail=tail, sn_tile=tile))
     print("tail rows", h.info()["tail_rows"], "panels", h.info()["tail_panels"])
     assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
     assert np.abs(x - w.x_true[:, 0]).max() < 1e-10
@@ -204,8 +207,9 @@ def test_small_circuit(hylu, pipe):
     compare_factors(h, o)
 
 
-@pytest.mark.parametrize("side,sn_dense,tail", [(12, 16, 0.0), (16, 32, 0.15), (16, 2, 0.0)])
-def test_grid3d_blocked_supernodes(hylu, side, sn_dense, tail):
+@pytest.mark.parametrize("side,sn_dense,tail,tile", [(12, 16, 0.0, 16), (16, 32, 0.15, 16), (16, 2, 0.0, 2),
+                                                    (16, 128, 0.0, 0)])
+def test_grid3d_blocked_supernodes(hylu, side, sn_dense, tail, tile):
     """7-point 3D grid (ND): supernodes of at least sn_dense rows go through
     the blocked panel / TRSM / MFMA-GEMM kernels on side streams.  Pivots and
     structure bit-exact; L and U are not diagonally dominant here (growth
@@ -214,8 +218,8 @@ def test_grid3d_blocked_supernodes(hylu, side, sn_dense, tail):
     refactorisation through the graph; the solve against the oracle."""
     w = synth.convdiff3d_7pt(side)
     A = w.A
-    h, o, x, xo, eta = run_case(hylu, A, w.b[:, 0], opts=dict(ordering="nd", sn_dense=sn_dense, dense_tail=tail),
-                                tol="derived")
+    h, o, x, xo, eta = run_case(hylu, A, w.b[:, 0], opts=dict(ordering="nd", sn_dense=sn_dense, dense_tail=tail,
+                                                              sn_tile=tile), tol="derived")
     print("residual ratios (device, oracle):", compare_backward_stability(h, o))
     assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
     A2 = synth.grid_values(A, 77, 4.0)
