@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -46,7 +47,7 @@ def main():
     ap.add_argument("--pipeline-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-refactors", type=int, default=3)
-    ap.add_argument("--workload", default="circuit", choices=["circuit", "batch", "grid27", "adjoint"],
+    ap.add_argument("--workload", default="circuit", choices=["circuit", "batch", "grid27", "adjoint", "copy"],
                     help="circuit (default): the headline line; the others print their own line")
     ap.add_argument("--members", type=int, default=256)
     ap.add_argument("--sn-tile", type=int, default=0)
@@ -55,7 +56,8 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.workload != "circuit":
-        {"batch": bench_batch, "grid27": bench_grid27, "adjoint": bench_adjoint}[args.workload](args)
+        {"batch": bench_batch, "grid27": bench_grid27, "adjoint": bench_adjoint,
+         "copy": bench_copy}[args.workload](args)
         return
 
     import torch
@@ -122,6 +124,11 @@ def main():
         ach = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roof = {"kernel": dom["name"], "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None}
+        tr = _row_traffic() if dom["name"] == "rows" else None
+        if tr is not None:
+            # measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)
+            roof["traffic"] = round(tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"])
+            roof["algorithmic_bytes_per_launch"] = round(dom["bytes"] / max(dom["launches"], 1))
     roof["launches"] = dom["launches"]
     roof["avg_launch_us"] = round(dom["ms"] * 1e3 / max(dom["launches"], 1), 3)
     kernels = {k["name"]: {"launches": k["launches"], "ms": round(k["ms"], 4),
@@ -158,6 +165,51 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def bench_copy(args):
+    """A plain device copy of 1 GiB (3 times): the reference that scales the
+    HBM counters (FETCH_SIZE, WRITE_SIZE) to bytes."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                      "copies": 3}))
+
+
+ROW_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "circuit_n200000_rows_hbm_traffic.md")
+
+
+def _row_kernel_source_hash():
+    """Hash of the row kernel's source (the source application, the row task
+    and its launch kernel): counter figures taken for another version of the
+    kernel are not reported."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2509_07690_amd", "csrc", "kernels.hip")).read()
+    a = src.index("__device__ void apply_source_direct(")
+    b = src.index("// internal factorisation of a supernode")
+    return hashlib.sha1(src[a:b].encode()).hexdigest()[:16]
+
+
+def _row_traffic():
+    """Measured HBM bytes per row-kernel launch from the committed counter
+    profile, when it was taken for the current kernel source; else None."""
+    try:
+        txt = open(ROW_TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_json: (\{.*\})", txt)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("source_hash") != _row_kernel_source_hash():
+        return None
+    return d
 
 
 def _timed(fn, steps, warmup):

@@ -59,7 +59,8 @@ typedef struct {
     const int32_t* user_perm; /* host, n entries, new -> old; read by hylu_analyze only */
     int32_t static_pivot;  /* 1: maximum-product matching + scaling (Sec. 2.1); 0: identity, unit scaling */
     int32_t precision;     /* 0: FP64 factors; 1: FP32 factors + FP64 iterative refinement */
-    double pivot_tau;      /* perturbation threshold relative to max|B|; <= 0: sqrt(eps) of the factor precision */
+    double pivot_tau;      /* perturbation threshold relative to max|B|; <= 0: sqrt(eps) of FP64 (1.49e-8), for
+                              FP32 factors too */
     double ir_tol;         /* target normwise backward error of refinement (default 1e-12) */
     int32_t ir_maxit;      /* refinement iteration cap (default 10 for FP64, 30 for FP32) */
     int32_t sn_min;        /* shortest run of rows kept as a supernode (default 2) */

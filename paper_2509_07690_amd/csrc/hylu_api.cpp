@@ -756,7 +756,10 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     for (int32_t i = 0; i < n; i++)
         for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++)
             bmax = std::max(bmax, std::fabs(h->dr[i] * A.v[p] * h->dc[A.ci[p]]));
-    double eps = h->fp32 ? (double)std::numeric_limits<float>::epsilon() : std::numeric_limits<double>::epsilon();
+    // the threshold belongs to the FP64 problem: FP32 factors perturb the same
+    // pivots as FP64 ones (sqrt of the FP32 epsilon, 3.45e-4, would replace
+    // pivots that FP32 represents well and stall the refinement)
+    double eps = std::numeric_limits<double>::epsilon();
     h->tau = (opt.pivot_tau > 0 ? opt.pivot_tau : std::sqrt(eps)) * (bmax > 0 ? bmax : 1.0);
     // ---- level task lists of the factorisation
     const Layout& L = h->lay;

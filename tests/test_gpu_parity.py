@@ -230,3 +230,23 @@ def test_grid3d_blocked_supernodes(hylu, side, sn_dense, tail, tile):
     o.numeric(h.info()["pivot_tau"], piv=piv)
     compare_factors(h, o, tol="derived")
     compare_backward_stability(h, o)
+
+
+def test_fp32_refactor_fresh_values_full_circuit(hylu):
+    """Circuit n = 200000, FP32 factors: refactorisations with fresh value sets
+    on the first factorisation's pivot order converge under FP64 refinement
+    to a backward error of at most 1e-10 (the FP64 perturbation threshold
+    leaves these pivots alone)."""
+    base = synth.circuit_powerlaw(200000)
+    A = base.A
+    h = hylu.Handle(A.row_ptr, A.col, A.val, precision="fp32", amd_dense=0.1, dense_tail=0.15)
+    h.factorize(dev(A.val))
+    for r in (1, 3):
+        w = base.revalue(r)
+        h.refactor(dev(w.A.val))
+        x = h.solve(dev(w.b[:, 0])).cpu().numpy()
+        ok = __import__("oracle").Oracle(A.n, A.row_ptr, A.col, w.A.val, *[np.arange(A.n, dtype=np.int32)] * 2,
+                                         np.ones(A.n), np.ones(A.n))
+        eta, _ = ok.backward_error(w.b[:, 0], x)
+        print(f"refactor {r}: eta {eta:.2e} ir {h.info()['ir_iters']} perturbed {h.info()['n_perturbed']}")
+        assert eta <= 1e-10 and np.abs(x - w.x_true[:, 0]).max() <= 1e-9
