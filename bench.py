@@ -124,7 +124,7 @@ def main():
         ach = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roof = {"kernel": dom["name"], "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None}
-        tr = _row_traffic() if dom["name"] == "rows" else None
+        tr = _row_traffic() if dom["name"] == "rows" and args.precision == "fp64" else None
         if tr is not None:
             # measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)
             roof["traffic"] = round(tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"])
