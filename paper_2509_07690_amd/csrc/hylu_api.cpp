@@ -328,19 +328,47 @@ hylu_status ensure_tlists(hylu_handle h)
 }
 
 // blocked right-looking LU of a dense view, one row panel at a time
+constexpr int32_t kGroupMinRows = 2048;
 hylu_status enqueue_dense(hylu_handle h, const TailView& TV, const std::vector<Layout::Panel>& panels, bool search,
                           hipStream_t st)
 {
     const double es = h->fp32 ? 4.0 : 8.0;
     const double mT = TV.mT, nc = TV.nc;
-    for (const Layout::Panel& P : panels) {
-        const double np = P.p1 - P.p0, wc = P.c1 - P.c0, rows = mT - P.p1, colsA = nc - P.c1, colsG = nc - P.cg0;
-        LAUNCH(C_PANEL, 2.0 * es * np * wc, np * np * wc,
-               launch_tail_panel(h->fp32, h->D, TV, h->vals, P.p0, P.p1, P.c0, P.c1, h->tau, h->d_pert, search ? 1 : 0, st));
-        LAUNCH(C_TRSM, es * (2.0 * np * colsA + 3.0 * np * rows + np * np), np * np * (colsA + rows),
-               launch_tail_trsm(h->fp32, TV, h->vals, P.p0, P.p1, P.c1, st));
-        LAUNCH(C_GEMM, es * (2.0 * rows * colsG + np * (rows + colsG)), 2.0 * np * rows * colsG,
-               launch_tail_gemm(h->fp32, TV, h->vals, P.p0, P.p1, P.cg0, st));
+    auto gemm = [&](int32_t kb0, int32_t K, int32_t rb, int32_t re, int32_t cg0, int32_t mstep, int32_t gp0,
+                    int32_t gnp) -> hylu_status {
+        const double rows = re - rb, cols = gnp > 0 ? gnp : nc - cg0;
+        if (K <= 0 || rows <= 0 || cols <= 0) return HYLU_OK;
+        LAUNCH(C_GEMM, es * (2.0 * rows * cols + K * (rows + cols)), 2.0 * K * rows * cols,
+               launch_tail_gemm(h->fp32, TV, h->vals, kb0, K, rb, re, cg0, mstep, gp0, gnp, st));
+        return HYLU_OK;
+    };
+    // groups of up to kGroup panels: left-looking inside the group, one
+    // trailing update per group
+    for (size_t i = 0; i < panels.size();) {
+        // grouping pays where the trailing matrix is large; near the end its
+        // extra launches cost more than the saved passes
+        const bool big = TV.mT - panels[i].p1 >= kGroupMinRows;
+        const size_t g1 = std::min(i + (size_t)(big ? kGroup : 1), panels.size());
+        const int32_t kb0 = panels[i].p0, cg = panels[i].cg0;
+        int32_t kof = 0;
+        for (size_t j = i; j < g1; j++) {
+            const Layout::Panel& P = panels[j];
+            hylu_status s = gemm(kb0, kof, P.p0, P.p1, cg, P.p0, 0, 0);   // this panel's rows, from the group so far
+            if (s != HYLU_OK) return s;
+            const double np = P.p1 - P.p0, wc = P.c1 - P.c0, rows = mT - P.p1, colsA = nc - P.c1;
+            LAUNCH(C_PANEL, 2.0 * es * np * wc, np * np * wc,
+                   launch_tail_panel(h->fp32, h->D, TV, h->vals, P.p0, P.p1, P.c0, P.c1, h->tau, h->d_pert, search ? 1 : 0, st));
+            // the rows below at this panel's pivot columns, from the group so far
+            s = gemm(kb0, kof, P.p1, TV.mT, 0, 0, P.p0, P.p1 - P.p0);
+            if (s != HYLU_OK) return s;
+            LAUNCH(C_TRSM, es * (2.0 * np * colsA + 3.0 * np * rows + np * np), np * np * (colsA + rows),
+                   launch_tail_trsm(h->fp32, TV, h->vals, P.p0, P.p1, P.c1, kb0, kof, st));
+            kof += P.p1 - P.p0;
+        }
+        const Layout::Panel& Q = panels[g1 - 1];
+        hylu_status s = gemm(kb0, kof, Q.p1, TV.mT, cg, Q.p1, 0, 0);   // everything below the group
+        if (s != HYLU_OK) return s;
+        i = g1;
     }
     return HYLU_OK;
 }
@@ -589,7 +617,7 @@ hylu_status upload_device(hylu_handle h)
             std::vector<int32_t> zt(std::max(L.mT, 1), 0);
             UP(trow, L.trow); UP(tlo, L.tlo); UP(thi, L.thi); UP(tpiv, zt); UP(tstep, zt);
             TVw.trow = trow; TVw.tlo = tlo; TVw.thi = thi; TVw.tpiv = tpiv; TVw.tstep = tstep;
-            TVw.lbuf = dalloc(h, (size_t)64 * std::max(L.mT, 1) * (h->fp32 ? 4 : 8));
+            TVw.lbuf = dalloc(h, (size_t)64 * kGroup * std::max(L.mT, 1) * (h->fp32 ? 4 : 8));
             if (!TVw.lbuf) return HYLU_ERR_OOM;
         }
         for (hylu_handle_s::DenseSn& q : h->dsn) {
@@ -604,7 +632,7 @@ hylu_status upload_device(hylu_handle h)
             q.TV = TailView();
             q.TV.mT = m; q.TV.nc = nc; q.TV.t0 = L.r0[v];
             q.TV.trow = trow; q.TV.tlo = tlo; q.TV.thi = thi; q.TV.tpiv = tpiv; q.TV.tstep = tstep;
-            q.TV.lbuf = dalloc(h, (size_t)64 * m * (h->fp32 ? 4 : 8));
+            q.TV.lbuf = dalloc(h, (size_t)64 * kGroup * m * (h->fp32 ? 4 : 8));
             if (!q.TV.lbuf) return HYLU_ERR_OOM;
         }
         if (!h->dsn.empty()) {

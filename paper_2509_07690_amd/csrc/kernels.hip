@@ -1006,7 +1006,8 @@ __global__ __launch_bounds__(64) void k_tail_panel_lds(DevLayout D, TailView TV,
 // blocks [0, nA): panel rows' U for columns >= c1 (one thread per column);
 // blocks [nA, ...): trailing rows' multipliers (one thread per row)
 template <typename T>
-__global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ vals, int p0, int p1, int c1, int nA)
+__global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ vals, int p0, int p1, int c1, int nA,
+                                                  int kb0, int kof)
 {
     __shared__ T M[kNB][kNB + 1];       // M[i][j] = X_{p0+i}[tpiv[p0+j]]
     __shared__ int64_t rowoff[kNB];
@@ -1041,6 +1042,7 @@ __global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ v
         const int r = p1 + (blockIdx.x - nA) * 64 + tid;
         if (r >= TV.mT) return;
         T* Xr = vals + TV.trow[r];
+        T* lb = reinterpret_cast<T*>(TV.lbuf);
         T y[kNB];
 #pragma unroll
         for (int b = 0; b < kNB; b++) y[b] = b < np ? Xr[piv[b]] : T(0);
@@ -1053,20 +1055,19 @@ __global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ v
                 for (int bb = b + 1; bb < kNB; bb++) y[bb] -= l * M[b][bb];
             }
         }
-        T* lb = reinterpret_cast<T*>(TV.lbuf);
 #pragma unroll
         for (int b = 0; b < kNB; b++) {
             if (b < np) Xr[piv[b]] = y[b];
-            lb[(int64_t)b * TV.mT + r] = b < np ? y[b] : T(0);   // k-major copy for the trailing update
+            lb[(int64_t)(kof + b) * TV.mT + r] = b < np ? y[b] : T(0);   // k-major copy for the trailing update
         }
     }
 }
 
-// trailing update X[r][c] -= sum_b L[r][b] X[p0+b][c] for r >= p1 and the
-// columns c >= cg0 still unpivoted after the panel, on 16x16x4 MFMA tiles.
-// One wavefront computes a 64 x 64 tile as 4 x 4 blocks; operand fragments
-// are loaded straight from global memory (lbuf is k-major, the panel rows are
-// row-major, so 16 lanes read 16 consecutive values).
+// trailing update X[r][c] -= sum_k L[r][k] X[kb0+k][c] on 16x16x4 MFMA tiles:
+// a workgroup computes a 64 x 64 tile (four wavefronts of 32 x 32); operand
+// fragments come straight from global memory (lbuf is k-major, the panel rows
+// row-major, so 16 lanes read 16 consecutive values); the outputs are read
+// before the K loop.
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {
     typedef double v4 __attribute__((ext_vector_type(4)));
@@ -1082,51 +1083,88 @@ template <> struct Mfma<float> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ vals, int p0, int p1, int cg0)
+__global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ vals, int kb0, int K, int rb, int re,
+                                                   int cg0, int mstep, int gx, int gy, int swz, int gp0, int gnp)
 {
     typedef typename Mfma<T>::v4 v4;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int np = p1 - p0, mT = TV.mT, nc = TV.nc;
+    const int mT = re, nc = TV.nc, lds = TV.mT;
+    // tile of this workgroup.  Workgroups go to the 8 XCDs round robin by
+    // index; with swz each XCD takes a quarter of the tile rows and half of
+    // the tile columns, so the operand tiles it reads fit its own L2.
+    int tx, ty;
+    {
+        const int L = blockIdx.x;
+        if (swz) {
+            const int xcd = L & 7, k = L >> 3;
+            const int rb0 = (xcd >> 1) * gy / 4, rb1 = ((xcd >> 1) + 1) * gy / 4;
+            const int cb0 = (xcd & 1) * gx / 2, cb1 = ((xcd & 1) + 1) * gx / 2;
+            const int nr = rb1 - rb0, ncl = cb1 - cb0;
+            if (k >= nr * ncl) return;
+            ty = rb0 + k / ncl;
+            tx = cb0 + k % ncl;
+        } else {
+            if (L >= gx * gy) return;
+            ty = L / gx;
+            tx = L % gx;
+        }
+    }
     // block tile 64 x 64, four wavefronts of 32 x 32 (2 x 2 MFMA blocks each)
-    const int r0 = p1 + blockIdx.y * 64 + (wv >> 1) * 32, c0 = cg0 + blockIdx.x * 64 + (wv & 1) * 32;
+    const int r0 = rb + ty * 64 + (wv >> 1) * 32, c0 = cg0 + tx * 64 + (wv & 1) * 32;
     const T* lb = reinterpret_cast<const T*>(TV.lbuf);
     const int li = lane & 15, lk = lane >> 4;
+    const bool rok0 = r0 + li < mT, rok1 = r0 + 16 + li < mT;
+    // gnp > 0: the columns are the pivot columns of panel rows gp0.., in order
+    int cb = c0 + li, cb1 = cb + 16;
+    bool cok0 = cb < nc, cok1 = cb1 < nc;
+    if (gnp > 0) {
+        cok0 = cb < gnp;
+        cok1 = cb1 < gnp;
+        cb = cok0 ? TV.tpiv[gp0 + cb] : 0;
+        cb1 = cok1 ? TV.tpiv[gp0 + cb1] : 0;
+    }
+    const bool cm0 = cok0 && (gnp > 0 || TV.tstep[cb] >= mstep), cm1 = cok1 && (gnp > 0 || TV.tstep[cb1] >= mstep);
+    // the output values are read before the K loop so their latency overlaps it
+    T cold[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int r = r0 + 16 * i + Mfma<T>::row(lane, v);
+            const T* Xr = vals + (r < mT ? TV.trow[r] : 0);
+            cold[i][0][v] = (r < mT && cm0) ? Xr[cb] : T(0);
+            cold[i][1][v] = (r < mT && cm1) ? Xr[cb1] : T(0);
+        }
     v4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = v4{T(0), T(0), T(0), T(0)};
-    const bool rok0 = r0 + li < mT, rok1 = r0 + 16 + li < mT;
-    const int cb = c0 + li;
-    const bool cok0 = cb < nc, cok1 = cb + 16 < nc;
-    const T* arow = lb + (int64_t)lk * mT + r0 + li;
-#pragma unroll
-    for (int ks = 0; ks < kNB / 4; ks++) {
+    const T* arow = lb + (int64_t)lk * lds + r0 + li;
+#pragma unroll 4
+    for (int ks = 0; ks * 4 < K; ks++) {
         const int k = ks * 4 + lk;
-        if (ks * 4 < np) {
-            const bool kok = k < np;
-            const T* ap = arow + (int64_t)ks * 4 * mT;
-            const T a0 = (kok && rok0) ? ap[0] : T(0);
-            const T a1 = (kok && rok1) ? ap[16] : T(0);
-            const T* bp = vals + (kok ? TV.trow[p0 + k] : 0) + cb;
-            const T b0 = (kok && cok0) ? bp[0] : T(0);
-            const T b1 = (kok && cok1) ? bp[16] : T(0);
-            acc[0][0] = Mfma<T>::mma(a0, b0, acc[0][0]);
-            acc[0][1] = Mfma<T>::mma(a0, b1, acc[0][1]);
-            acc[1][0] = Mfma<T>::mma(a1, b0, acc[1][0]);
-            acc[1][1] = Mfma<T>::mma(a1, b1, acc[1][1]);
-        }
+        const bool kok = k < K;
+        const T* ap = arow + (int64_t)ks * 4 * lds;
+        const T a0 = (kok && rok0) ? ap[0] : T(0);
+        const T a1 = (kok && rok1) ? ap[16] : T(0);
+        const T* bp = vals + (kok ? TV.trow[kb0 + k] : 0);
+        const T b0 = (kok && cok0) ? bp[cb] : T(0);
+        const T b1 = (kok && cok1) ? bp[cb1] : T(0);
+        acc[0][0] = Mfma<T>::mma(a0, b0, acc[0][0]);
+        acc[0][1] = Mfma<T>::mma(a0, b1, acc[0][1]);
+        acc[1][0] = Mfma<T>::mma(a1, b0, acc[1][0]);
+        acc[1][1] = Mfma<T>::mma(a1, b1, acc[1][1]);
     }
-    const bool cm0 = cok0 && TV.tstep[cb] >= p1, cm1 = cok1 && TV.tstep[cb + 16] >= p1;
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int v = 0; v < 4; v++) {
             const int r = r0 + 16 * i + Mfma<T>::row(lane, v);
             if (r >= mT) continue;
-            T* Xr = vals + TV.trow[r] + cb;
-            if (cm0) Xr[0] -= acc[i][0][v];
-            if (cm1) Xr[16] -= acc[i][1][v];
+            T* Xr = vals + TV.trow[r];
+            if (cm0) Xr[cb] = cold[i][0][v] - acc[i][0][v];
+            if (cm1) Xr[cb1] = cold[i][1][v] - acc[i][1][v];
         }
 }
 
@@ -1679,22 +1717,29 @@ hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, v
     return hipGetLastError();
 }
 
-hipError_t launch_tail_trsm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t c1, hipStream_t st)
+hipError_t launch_tail_trsm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t c1, int32_t kb0,
+                            int32_t kof, hipStream_t st)
 {
     int nA = (int)nblk(std::max(T.nc - c1, 0), 64);
     int nB = (int)nblk(std::max(T.mT - p1, 0), 64);
     if (nA + nB == 0) return hipSuccess;
-    if (fp32) hipLaunchKernelGGL(k_tail_trsm<float>, dim3(nA + nB), dim3(64), 0, st, T, (float*)vals, p0, p1, c1, nA);
-    else hipLaunchKernelGGL(k_tail_trsm<double>, dim3(nA + nB), dim3(64), 0, st, T, (double*)vals, p0, p1, c1, nA);
+    if (kof < 0 || kof + (p1 - p0) > kNB * kGroup) return hipErrorInvalidValue;
+    if (fp32) hipLaunchKernelGGL(k_tail_trsm<float>, dim3(nA + nB), dim3(64), 0, st, T, (float*)vals, p0, p1, c1, nA, kb0, kof);
+    else hipLaunchKernelGGL(k_tail_trsm<double>, dim3(nA + nB), dim3(64), 0, st, T, (double*)vals, p0, p1, c1, nA, kb0, kof);
     return hipGetLastError();
 }
 
-hipError_t launch_tail_gemm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t cg0, hipStream_t st)
+hipError_t launch_tail_gemm(bool fp32, const TailView& T, void* vals, int32_t kb0, int32_t K, int32_t rb, int32_t re,
+                            int32_t cg0, int32_t mstep, int32_t gp0, int32_t gnp, hipStream_t st)
 {
-    int gx = (int)nblk(std::max(T.nc - cg0, 0), 64), gy = (int)nblk(std::max(T.mT - p1, 0), 64);
-    if (gx == 0 || gy == 0) return hipSuccess;
-    if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(gx, gy), dim3(256), 0, st, T, (float*)vals, p0, p1, cg0);
-    else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(gx, gy), dim3(256), 0, st, T, (double*)vals, p0, p1, cg0);
+    int gx = gnp > 0 ? (int)nblk(gnp, 64) : (int)nblk(std::max(T.nc - cg0, 0), 64);
+    int gy = (int)nblk(std::max(re - rb, 0), 64);
+    if (gx == 0 || gy == 0 || K <= 0) return hipSuccess;
+    if (K > kNB * kGroup || re > T.mT || gnp > kNB) return hipErrorInvalidValue;
+    const int swz = gy >= 8 && gx >= 4;
+    const unsigned grid = swz ? 8u * (unsigned)((gy + 3) / 4) * (unsigned)((gx + 1) / 2) : (unsigned)(gx * gy);
+    if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(grid), dim3(256), 0, st, T, (float*)vals, kb0, K, rb, re, cg0, mstep, gx, gy, swz, gp0, gnp);
+    else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(grid), dim3(256), 0, st, T, (double*)vals, kb0, K, rb, re, cg0, mstep, gx, gy, swz, gp0, gnp);
     return hipGetLastError();
 }
 

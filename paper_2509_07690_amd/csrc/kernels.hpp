@@ -77,8 +77,22 @@ hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_tail_init(const TailView& T, hipStream_t st);
 hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, void* vals, int32_t p0, int32_t p1,
                              int32_t c0, int32_t c1, double tau, int32_t* pert, int32_t search, hipStream_t st);
-hipError_t launch_tail_trsm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t c1, hipStream_t st);
-hipError_t launch_tail_gemm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t cg0, hipStream_t st);
+// panels are processed in groups of up to kGroup: the rows of a group take the
+// group's earlier panels left-looking, the rows below the group take the whole
+// group in one trailing update (K up to kGroup * 64), so the trailing matrix is
+// read and written once per group instead of once per panel.  lbuf holds
+// kGroup * 64 rows (k-major), panel j of a group at rows kof..kof+np.
+constexpr int kGroup = 4;
+// panel [p0, p1): U right of the window, and the multipliers of the rows
+// below (their pivot columns already carry the group's earlier panels),
+// written to lbuf rows kof.. (kb0: first panel row of the group, unused here)
+hipError_t launch_tail_trsm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t c1, int32_t kb0,
+                            int32_t kof, hipStream_t st);
+// rows [rb, re): X[r][c] -= sum_{k < K} lbuf[k][r] X[kb0 + k][c] over the
+// columns from cg0 still unpivoted before step mstep, or (gnp > 0) over the
+// pivot columns of panel rows gp0 .. gp0+gnp
+hipError_t launch_tail_gemm(bool fp32, const TailView& T, void* vals, int32_t kb0, int32_t K, int32_t rb, int32_t re,
+                            int32_t cg0, int32_t mstep, int32_t gp0, int32_t gnp, hipStream_t st);
 // dense tail solves; y/x/h/w are the solve work vectors (n x nrhs, factor precision)
 hipError_t launch_tail_lext(bool fp32, const DevLayout& D, const void* vals, int32_t tail_node0, int32_t t0,
                             void* y, int32_t nrhs, hipStream_t st);
