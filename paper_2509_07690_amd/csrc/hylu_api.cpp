@@ -794,7 +794,23 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     const Nodes& nd = h->nodes;
     LevelTasks& T = h->ft;
     T = LevelTasks();
-    int32_t nl = (int32_t)L.xlev_ptr[0].size() - 1;
+    // factor levels; the dense tail's rows take their outside updates in one
+    // extra level after all others: nothing outside the tail depends on them,
+    // so they need not sit on the chain of narrow levels
+    std::vector<std::vector<int32_t>> lvnodes;
+    {
+        const int32_t nx = (int32_t)L.xlev_ptr[0].size() - 1;
+        lvnodes.resize(nx);
+        std::vector<int32_t> tailn;
+        for (int32_t l = 0; l < nx; l++)
+            for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) {
+                const int32_t v = L.xlev_nodes[0][t];
+                (v >= L.tail_node0 ? tailn : lvnodes[l]).push_back(v);
+            }
+        while (!lvnodes.empty() && lvnodes.back().empty()) lvnodes.pop_back();
+        if (!tailn.empty()) lvnodes.push_back(std::move(tailn));
+    }
+    int32_t nl = (int32_t)lvnodes.size();
     T.row_ptr.assign(1, 0); T.sn_ptr.assign(1, 0);
     h->max_sn = 0;
     h->dsn.clear();
@@ -804,8 +820,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     T.tile_ptr.assign(1, 0);
     for (int32_t l = 0; l < nl; l++) {
         int32_t mw = 0, mm = 0;
-        for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) {
-            int32_t v = L.xlev_nodes[0][t];
+        for (int32_t v : lvnodes[l]) {
             if (nd.is_sn[v] && v < L.tail_node0 && L.m[v] >= tile_min) {
                 // outside updates of a large supernode target by 16-row tiles
                 for (int32_t a = 0; a < L.m[v]; a += kTileRowsHost) { T.tiles.push_back(v); T.tiles.push_back(a); }
@@ -842,7 +857,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     T.sn_nt.assign(nl, 0);
     T.node_level.assign(L.nnodes, 0);
     for (int32_t l = 0; l < nl; l++)
-        for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) T.node_level[L.xlev_nodes[0][t]] = l;
+        for (int32_t v : lvnodes[l]) T.node_level[v] = l;
     // the large supernodes' places in the L-solve and U-solve level sequences
     {
         std::vector<int32_t> dix(L.nnodes, -1);
@@ -866,8 +881,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     h->tile_bytes.assign(nl, 0.0);
     h->tile_flops.assign(nl, 0.0);
     for (int32_t l = 0; l < nl; l++)
-        for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) {
-            int32_t v = L.xlev_nodes[0][t];
+        for (int32_t v : lvnodes[l]) {
             const bool tiled = nd.is_sn[v] && v < L.tail_node0 && L.m[v] >= tile_min;
             double m = L.m[v], by = 16.0 * L.W[v], src = 0, fl = 0;
             for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
