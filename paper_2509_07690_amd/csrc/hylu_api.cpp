@@ -796,16 +796,24 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     T = LevelTasks();
     // factor levels; the dense tail's rows take their outside updates in one
     // extra level after all others: nothing outside the tail depends on them,
-    // so they need not sit on the chain of narrow levels
+    // so they need not sit on the chain of narrow levels (nor need the other
+    // nodes that feed nobody)
     std::vector<std::vector<int32_t>> lvnodes;
     {
         const int32_t nx = (int32_t)L.xlev_ptr[0].size() - 1;
         lvnodes.resize(nx);
         std::vector<int32_t> tailn;
+        // a node no other node takes updates from can run as late as the tail
+        // rows do; with a tail present such nodes join that final level
+        std::vector<char> feeds(L.nnodes, 0);
+        for (int32_t v = 0; v < L.nnodes; v++)
+            for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) feeds[L.esrc[e]] = 1;
+        const bool tail = L.tail_node0 < L.nnodes;
         for (int32_t l = 0; l < nx; l++)
             for (int32_t t = L.xlev_ptr[0][l]; t < L.xlev_ptr[0][l + 1]; t++) {
                 const int32_t v = L.xlev_nodes[0][t];
-                (v >= L.tail_node0 ? tailn : lvnodes[l]).push_back(v);
+                const bool late = v >= L.tail_node0 || (tail && l > 0 && !feeds[v]);
+                (late ? tailn : lvnodes[l]).push_back(v);
             }
         while (!lvnodes.empty() && lvnodes.back().empty()) lvnodes.pop_back();
         if (!tailn.empty()) lvnodes.push_back(std::move(tailn));
