@@ -1003,6 +1003,116 @@ __global__ __launch_bounds__(64) void k_tail_panel_lds(DevLayout D, TailView TV,
     if (lane == 0 && npert > 0) atomicAdd(pert, npert);
 }
 
+// the same panel factorisation on four wavefronts: rows are dealt to the
+// wavefronts round robin for the multipliers and the elimination; wavefront
+// 0 takes the pivot search
+template <typename T>
+__global__ __launch_bounds__(256) void k_tail_panel_lds4(DevLayout D, TailView TV, T* __restrict__ vals, int p0,
+                                                         int p1, int c0, int c1, T tau, int32_t* __restrict__ pert,
+                                                         int search)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int64_t rowoff[kNB];
+    __shared__ T lrow[kNB];
+    __shared__ int spiv[kNB], slo[kNB], shi[kNB];
+    __shared__ int s_p;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wc = c1 - c0, np = p1 - p0;
+    int npert = 0;
+    T* Xw = reinterpret_cast<T*>(smem_raw);          // np x wc
+    if (tid < np) {
+        rowoff[tid] = TV.trow[p0 + tid];
+        slo[tid] = TV.tlo[p0 + tid];
+        shi[tid] = TV.thi[p0 + tid];
+        spiv[tid] = search ? 0 : TV.tpiv[p0 + tid];
+    }
+    int mystep = lane < wc ? TV.tstep[c0 + lane] : -1;   // the step that pivots my column
+    __syncthreads();
+    if (lane < wc) {
+        T tmp[kNB / 4];
+#pragma unroll
+        for (int q = 0; q < kNB / 4; q++) {
+            const int r = wv + 4 * q;
+            tmp[q] = r < np ? vals[rowoff[r] + c0 + lane] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < kNB / 4; q++) {
+            const int r = wv + 4 * q;
+            if (r < np) Xw[r * wc + lane] = tmp[q];
+        }
+    }
+    __syncthreads();
+    for (int ar = 0; ar < np; ar++) {
+        const int a = p0 + ar;
+        const int lo = slo[ar], hi = shi[ar];
+        T* Xa = Xw + ar * wc;
+        int p;
+        if (!search) {
+            p = spiv[ar];
+        } else if (hi - lo == 1) {
+            p = a;
+        } else {
+            if (wv == 0) {
+                T best = T(-1);
+                int bi = 0x7fffffff;
+                const int c = c0 + lane;
+                if (lane < wc && c >= lo && c < hi && mystep > a) { best = pmag(Xa[lane]); bi = c; }
+                for (int off = 32; off > 0; off >>= 1) {
+                    T ob = __shfl_xor(best, off, 64);
+                    int oi = __shfl_xor(bi, off, 64);
+                    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+                }
+                if (lane == 0) s_p = bi;
+            }
+            __syncthreads();
+            p = s_p;
+        }
+        const int pc = p - c0;
+        T d = Xa[pc];
+        if (tabs(d) < tau) d = d < T(0) ? -tau : tau;
+        if (lane == pc) mystep = a;
+        // multipliers of the remaining rows, one thread per row
+        const int rl = np - ar - 1;
+        if (tid < rl) {
+            T* Xr = Xw + (ar + 1 + tid) * wc;
+            const T l = Xr[pc] / d;
+            Xr[pc] = l;
+            lrow[ar + 1 + tid] = l;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            if (Xa[pc] != d) { Xa[pc] = d; npert++; }
+            spiv[ar] = p;
+        }
+        if (lane < wc && mystep > a) {              // my column is still unpivoted
+            const T u = Xa[lane];
+            // rows ar+1.. dealt round robin: this wavefront takes r = wv mod 4
+            int r = ar + 1 + ((wv - (ar + 1)) & 3);
+            for (; r + 12 < np; r += 16) {
+                const T x0 = Xw[r * wc + lane], x1 = Xw[(r + 4) * wc + lane];
+                const T x2 = Xw[(r + 8) * wc + lane], x3 = Xw[(r + 12) * wc + lane];
+                Xw[r * wc + lane] = x0 - lrow[r] * u;
+                Xw[(r + 4) * wc + lane] = x1 - lrow[r + 4] * u;
+                Xw[(r + 8) * wc + lane] = x2 - lrow[r + 8] * u;
+                Xw[(r + 12) * wc + lane] = x3 - lrow[r + 12] * u;
+            }
+            for (; r < np; r += 4) Xw[r * wc + lane] -= lrow[r] * u;
+        }
+        __syncthreads();
+    }
+    if (lane < wc) {
+        for (int r = wv; r < np; r += 4) vals[rowoff[r] + c0 + lane] = Xw[r * wc + lane];
+    }
+    if (tid < np) {
+        const int a = p0 + tid, p = spiv[tid];
+        TV.tpiv[a] = p;
+        TV.tstep[p] = a;
+        D.pl[TV.t0 + a] = p - slo[tid];
+        D.qinv[TV.t0 + p] = TV.t0 + a;
+    }
+    if (tid == 0 && npert > 0) atomicAdd(pert, npert);
+}
+
 // blocks [0, nA): panel rows' U for columns >= c1 (one thread per column);
 // blocks [nA, ...): trailing rows' multipliers (one thread per row)
 template <typename T>
@@ -1697,8 +1807,8 @@ hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, v
     size_t es = fp32 ? sizeof(float) : sizeof(double);
     size_t sh = (size_t)(p1 - p0) * (c1 - c0) * es;
     if (c1 - c0 <= 64) {
-        if (fp32) hipLaunchKernelGGL(k_tail_panel_lds<float>, dim3(1), dim3(64), sh, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
-        else hipLaunchKernelGGL(k_tail_panel_lds<double>, dim3(1), dim3(64), sh, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+        if (fp32) hipLaunchKernelGGL(k_tail_panel_lds4<float>, dim3(1), dim3(256), sh, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
+        else hipLaunchKernelGGL(k_tail_panel_lds4<double>, dim3(1), dim3(256), sh, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
     } else {
         // wide window: steps in LDS, the window itself too when it fits
         const size_t tsz = ((size_t)(c1 - c0) * 4 + 15) & ~(size_t)15;
