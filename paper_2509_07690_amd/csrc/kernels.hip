@@ -1003,13 +1003,13 @@ __global__ __launch_bounds__(64) void k_tail_panel_lds(DevLayout D, TailView TV,
     if (lane == 0 && npert > 0) atomicAdd(pert, npert);
 }
 
-// the same panel factorisation on four wavefronts: rows are dealt to the
+// the same panel factorisation on NW wavefronts: rows are dealt to the
 // wavefronts round robin for the multipliers and the elimination; wavefront
 // 0 takes the pivot search
-template <typename T>
-__global__ __launch_bounds__(256) void k_tail_panel_lds4(DevLayout D, TailView TV, T* __restrict__ vals, int p0,
-                                                         int p1, int c0, int c1, T tau, int32_t* __restrict__ pert,
-                                                         int search)
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_tail_panel_lds4(DevLayout D, TailView TV, T* __restrict__ vals, int p0,
+                                                             int p1, int c0, int c1, T tau, int32_t* __restrict__ pert,
+                                                             int search)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int64_t rowoff[kNB];
@@ -1029,15 +1029,15 @@ __global__ __launch_bounds__(256) void k_tail_panel_lds4(DevLayout D, TailView T
     int mystep = lane < wc ? TV.tstep[c0 + lane] : -1;   // the step that pivots my column
     __syncthreads();
     if (lane < wc) {
-        T tmp[kNB / 4];
+        T tmp[kNB / NW];
 #pragma unroll
-        for (int q = 0; q < kNB / 4; q++) {
-            const int r = wv + 4 * q;
+        for (int q = 0; q < kNB / NW; q++) {
+            const int r = wv + NW * q;
             tmp[q] = r < np ? vals[rowoff[r] + c0 + lane] : T(0);
         }
 #pragma unroll
-        for (int q = 0; q < kNB / 4; q++) {
-            const int r = wv + 4 * q;
+        for (int q = 0; q < kNB / NW; q++) {
+            const int r = wv + NW * q;
             if (r < np) Xw[r * wc + lane] = tmp[q];
         }
     }
@@ -1086,22 +1086,22 @@ __global__ __launch_bounds__(256) void k_tail_panel_lds4(DevLayout D, TailView T
         }
         if (lane < wc && mystep > a) {              // my column is still unpivoted
             const T u = Xa[lane];
-            // rows ar+1.. dealt round robin: this wavefront takes r = wv mod 4
-            int r = ar + 1 + ((wv - (ar + 1)) & 3);
-            for (; r + 12 < np; r += 16) {
-                const T x0 = Xw[r * wc + lane], x1 = Xw[(r + 4) * wc + lane];
-                const T x2 = Xw[(r + 8) * wc + lane], x3 = Xw[(r + 12) * wc + lane];
+            // rows ar+1.. dealt round robin: this wavefront takes r = wv mod NW
+            int r = ar + 1 + ((wv - (ar + 1)) & (NW - 1));
+            for (; r + 3 * NW < np; r += 4 * NW) {
+                const T x0 = Xw[r * wc + lane], x1 = Xw[(r + NW) * wc + lane];
+                const T x2 = Xw[(r + 2 * NW) * wc + lane], x3 = Xw[(r + 3 * NW) * wc + lane];
                 Xw[r * wc + lane] = x0 - lrow[r] * u;
-                Xw[(r + 4) * wc + lane] = x1 - lrow[r + 4] * u;
-                Xw[(r + 8) * wc + lane] = x2 - lrow[r + 8] * u;
-                Xw[(r + 12) * wc + lane] = x3 - lrow[r + 12] * u;
+                Xw[(r + NW) * wc + lane] = x1 - lrow[r + NW] * u;
+                Xw[(r + 2 * NW) * wc + lane] = x2 - lrow[r + 2 * NW] * u;
+                Xw[(r + 3 * NW) * wc + lane] = x3 - lrow[r + 3 * NW] * u;
             }
-            for (; r < np; r += 4) Xw[r * wc + lane] -= lrow[r] * u;
+            for (; r < np; r += NW) Xw[r * wc + lane] -= lrow[r] * u;
         }
         __syncthreads();
     }
     if (lane < wc) {
-        for (int r = wv; r < np; r += 4) vals[rowoff[r] + c0 + lane] = Xw[r * wc + lane];
+        for (int r = wv; r < np; r += NW) vals[rowoff[r] + c0 + lane] = Xw[r * wc + lane];
     }
     if (tid < np) {
         const int a = p0 + tid, p = spiv[tid];
@@ -1807,8 +1807,8 @@ hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, v
     size_t es = fp32 ? sizeof(float) : sizeof(double);
     size_t sh = (size_t)(p1 - p0) * (c1 - c0) * es;
     if (c1 - c0 <= 64) {
-        if (fp32) hipLaunchKernelGGL(k_tail_panel_lds4<float>, dim3(1), dim3(256), sh, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
-        else hipLaunchKernelGGL(k_tail_panel_lds4<double>, dim3(1), dim3(256), sh, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+        if (fp32) hipLaunchKernelGGL((k_tail_panel_lds4<float, 8>), dim3(1), dim3(512), sh, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
+        else hipLaunchKernelGGL((k_tail_panel_lds4<double, 8>), dim3(1), dim3(512), sh, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
     } else {
         // wide window: steps in LDS, the window itself too when it fits
         const size_t tsz = ((size_t)(c1 - c0) * 4 + 15) & ~(size_t)15;
