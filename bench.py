@@ -124,11 +124,11 @@ def main():
         ach = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roof = {"kernel": dom["name"], "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None}
-        tr = _row_traffic() if dom["name"] == "rows" and args.precision == "fp64" else None
-        if tr is not None:
-            # measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)
-            roof["traffic"] = round(tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"])
-            roof["algorithmic_bytes_per_launch"] = round(dom["bytes"] / max(dom["launches"], 1))
+    tr = _traffic(dom["name"]) if args.precision == "fp64" else None
+    if tr is not None:
+        # measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)
+        roof["traffic"] = round(tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"])
+        roof["algorithmic_bytes_per_launch"] = round(dom["bytes"] / max(dom["launches"], 1))
     roof["launches"] = dom["launches"]
     roof["avg_launch_us"] = round(dom["ms"] * 1e3 / max(dom["launches"], 1), 3)
     kernels = {k["name"]: {"launches": k["launches"], "ms": round(k["ms"], 4),
@@ -182,32 +182,39 @@ def bench_copy(args):
                       "copies": 3}))
 
 
-ROW_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "circuit_n200000_rows_hbm_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "circuit_n200000_hbm_traffic.md")
+# kernel class -> (kernel family, first and last marker of its source in kernels.hip)
+TRAFFIC_SOURCES = {
+    "rows": ("k_factor_rows", "__device__ void apply_source_direct(", "// internal factorisation of a supernode"),
+    "tail_gemm": ("k_tail_gemm", "template <typename T> struct Mfma;", "// ---- row tiles of supernode targets"),
+}
 
 
-def _row_kernel_source_hash():
-    """Hash of the row kernel's source (the source application, the row task
-    and its launch kernel): counter figures taken for another version of the
-    kernel are not reported."""
+def _kernel_source_hash(cls):
+    """Hash of a kernel class's source text: counter figures taken for
+    another version of the kernel are not reported."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_2509_07690_amd", "csrc", "kernels.hip")).read()
-    a = src.index("__device__ void apply_source_direct(")
-    b = src.index("// internal factorisation of a supernode")
+    _, first, last = TRAFFIC_SOURCES[cls]
+    a = src.index(first)
+    b = src.index(last, a)
     return hashlib.sha1(src[a:b].encode()).hexdigest()[:16]
 
 
-def _row_traffic():
-    """Measured HBM bytes per row-kernel launch from the committed counter
-    profile, when it was taken for the current kernel source; else None."""
+def _traffic(cls):
+    """Measured HBM bytes per launch of a kernel class from the committed
+    counter profile, when it was taken for the current kernel source."""
+    if cls not in TRAFFIC_SOURCES:
+        return None
     try:
-        txt = open(ROW_TRAFFIC_PROFILE).read()
+        txt = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
     m = re.search(r"traffic_json: (\{.*\})", txt)
     if not m:
         return None
-    d = json.loads(m.group(1))
-    if d.get("source_hash") != _row_kernel_source_hash():
+    d = json.loads(m.group(1)).get(cls)
+    if not d or d.get("source_hash") != _kernel_source_hash(cls):
         return None
     return d
 
