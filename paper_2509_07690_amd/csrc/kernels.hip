@@ -903,109 +903,10 @@ __global__ __launch_bounds__(NT) void k_tail_panel_wide(DevLayout D, TailView TV
     }
 }
 
-// panel factorisation with the window in LDS, one wavefront: lanes own
-// window columns (wc <= 64); for every panel row the pivot is a wave
-// reduction and the elimination walks the remaining rows, each lane updating
-// its column (no cross-wave synchronisation)
-template <typename T>
-__global__ __launch_bounds__(64) void k_tail_panel_lds(DevLayout D, TailView TV, T* __restrict__ vals, int p0, int p1,
-                                                       int c0, int c1, T tau, int32_t* __restrict__ pert, int search)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int64_t rowoff[kNB];
-    const int lane = threadIdx.x;
-    const int wc = c1 - c0, np = p1 - p0;
-    __shared__ T lrow[kNB];
-    __shared__ int spiv[kNB], slo[kNB], shi[kNB];
-    int npert = 0;
-    T* Xw = reinterpret_cast<T*>(smem_raw);          // np x wc
-    if (lane < np) {                                 // every per-row table read once, up front
-        rowoff[lane] = TV.trow[p0 + lane];
-        slo[lane] = TV.tlo[p0 + lane];
-        shi[lane] = TV.thi[p0 + lane];
-        spiv[lane] = search ? 0 : TV.tpiv[p0 + lane];
-    }
-    int mystep = lane < wc ? TV.tstep[c0 + lane] : -1;   // the step that pivots my column
-    __syncthreads();
-    if (lane < wc) {
-        T tmp[kNB];
-#pragma unroll
-        for (int r = 0; r < kNB; r++) tmp[r] = r < np ? vals[rowoff[r] + c0 + lane] : T(0);
-#pragma unroll
-        for (int r = 0; r < kNB; r++) if (r < np) Xw[r * wc + lane] = tmp[r];
-    }
-    __syncthreads();
-    for (int ar = 0; ar < np; ar++) {
-        const int a = p0 + ar;
-        const int lo = slo[ar], hi = shi[ar];
-        T* Xa = Xw + ar * wc;
-        int p;
-        if (!search) {
-            p = spiv[ar];
-        } else if (hi - lo == 1) {
-            p = a;
-        } else {
-            T best = T(-1);
-            int bi = 0x7fffffff;
-            const int c = c0 + lane;
-            if (lane < wc && c >= lo && c < hi && mystep > a) { best = pmag(Xa[lane]); bi = c; }
-            for (int off = 32; off > 0; off >>= 1) {
-                T ob = __shfl_xor(best, off, 64);
-                int oi = __shfl_xor(bi, off, 64);
-                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-            }
-            p = bi;
-        }
-        const int pc = p - c0;
-        T d = Xa[pc];
-        if (tabs(d) < tau) d = d < T(0) ? -tau : tau;
-        __syncthreads();
-        if (lane == 0) {
-            // pivot records stay in LDS until the end: a global store here would
-            // make every barrier of the panel wait for it
-            if (Xa[pc] != d) { Xa[pc] = d; npert++; }
-            spiv[ar] = p;
-        }        if (lane == pc) mystep = a;
-        // multipliers of the remaining rows, one lane per row
-        const int rl = np - ar - 1;
-        if (lane < rl) {
-            T* Xr = Xw + (ar + 1 + lane) * wc;
-            const T l = Xr[pc] / d;
-            Xr[pc] = l;
-            lrow[ar + 1 + lane] = l;
-        }
-        __syncthreads();
-        if (lane < wc && mystep > a) {              // my column is still unpivoted
-            const T u = Xa[lane];
-            int r = ar + 1;
-            for (; r + 8 <= np; r += 8) {           // eight independent rows per round
-                T xv[8], lv[8];
-#pragma unroll
-                for (int q = 0; q < 8; q++) { xv[q] = Xw[(r + q) * wc + lane]; lv[q] = lrow[r + q]; }
-#pragma unroll
-                for (int q = 0; q < 8; q++) Xw[(r + q) * wc + lane] = xv[q] - lv[q] * u;
-            }
-            for (; r < np; r++) Xw[r * wc + lane] -= lrow[r] * u;
-        }
-        __syncthreads();
-    }
-    if (lane < wc) {
-#pragma unroll 16
-        for (int r = 0; r < np; r++) vals[rowoff[r] + c0 + lane] = Xw[r * wc + lane];
-    }
-    if (lane < np) {
-        const int a = p0 + lane, p = spiv[lane];
-        TV.tpiv[a] = p;
-        TV.tstep[p] = a;
-        D.pl[TV.t0 + a] = p - slo[lane];
-        D.qinv[TV.t0 + p] = TV.t0 + a;
-    }
-    if (lane == 0 && npert > 0) atomicAdd(pert, npert);
-}
-
-// the same panel factorisation on NW wavefronts: rows are dealt to the
-// wavefronts round robin for the multipliers and the elimination; wavefront
-// 0 takes the pivot search
+// panel factorisation with the window (<= 64 columns) in LDS: lanes own
+// window columns; for every panel row the pivot is a wave reduction on
+// wavefront 0, the multipliers are formed one thread per row, and NW
+// wavefronts share the elimination, the rows dealt round robin.
 template <typename T, int NW>
 __global__ __launch_bounds__(64 * NW) void k_tail_panel_lds4(DevLayout D, TailView TV, T* __restrict__ vals, int p0,
                                                              int p1, int c0, int c1, T tau, int32_t* __restrict__ pert,
