@@ -271,6 +271,8 @@ def bench_batch(args):
         hb.solve(b, out=x)
     ms = _timed(step, args.steps, args.warmup)
     t_ref = _timed(lambda: hb.refactor(v1), args.steps, 1)
+    prof = hb.profile(v1, b, torch.empty_like(b))
+    kernels = {k["name"]: {"launches": k["launches"], "ms": round(k["ms"], 3)} for k in prof}
     roff, _ = hb.offsets()
     xs = x.cpu().numpy()
     err = max(float(np.abs(xs[roff[k]:roff[k + 1]] - w.x_true[:, 0]).max()) for k, w in enumerate(ws))
@@ -281,7 +283,8 @@ def bench_batch(args):
            "members": len(ws), "n_total": hb.n, "nnz_total": hb.nnz, "precision": args.precision},
           refactor_ms=round(t_ref, 4), factor_gflops=round(info["flops"] / (t_ref * 1e-3) / 1e9, 3),
           flops=info["flops"], autotune_level_ms={"builtin": round(t_def, 3), "tuned": round(t_tuned, 3)},
-          max_abs_err_vs_x_true=err, ir_iters=info["ir_iters"], berr=info["berr"], analyze_s=round(t_an, 2))
+          max_abs_err_vs_x_true=err, ir_iters=info["ir_iters"], berr=info["berr"], analyze_s=round(t_an, 2),
+          kernels=kernels)
 
 
 def bench_grid27(args):

@@ -102,6 +102,7 @@ struct hylu_handle_s {
     std::vector<DenseSn> dsn;
     std::vector<int32_t> dsn_ptr;           // per factor level into dsn
     std::vector<std::vector<int32_t>> dsn_l, dsn_u;   // per L-solve / U-solve level: dsn indices
+    std::vector<int32_t> lsolve_sn;         // per L-solve level: 1 if it has a supernode for k_lsolve_sn
     static constexpr int kSide = 4;         // side streams for independent supernodes of a level
     hipStream_t side[kSide] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_join[kSide] = {nullptr, nullptr, nullptr, nullptr};
@@ -329,6 +330,9 @@ hylu_status ensure_tlists(hylu_handle h)
 
 // blocked right-looking LU of a dense view, one row panel at a time
 constexpr int32_t kGroupMinRows = 2048;
+// supernodes of at least this many rows (and at most 64) take the
+// four-wavefront forward-solve kernel
+constexpr int32_t kLsolveSnMin = 8;
 hylu_status enqueue_dense(hylu_handle h, const TailView& TV, const std::vector<Layout::Panel>& panels, bool search,
                           hipStream_t st)
 {
@@ -476,7 +480,7 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
         for (size_t l = 0; l + 1 < L.xlev_ptr[g].size(); l++) {
             int32_t a = L.xlev_ptr[g][l], c = L.xlev_ptr[g][l + 1] - a;
             int cls = g == 4 ? C_LSOLVE : g == 1 ? C_USOLVE : C_OSOLVE;
-            if (c > 0) LAUNCH(cls, 0, 0, fn(h->d_lev[g] + a, c));
+            if (c > 0) LAUNCH(cls, 0, 0, fn(h->d_lev[g] + a, c, l));
             const std::vector<std::vector<int32_t>>* dl = g == 4 ? &h->dsn_l : g == 1 ? &h->dsn_u : nullptr;
             if (!dl || l >= dl->size()) continue;
             for (int32_t q : (*dl)[l]) {
@@ -498,7 +502,10 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
     hylu_status s;
     if (!transpose) {
         HIPCHK(launch_permute_in(f, n, nrhs, h->d_perm_r, h->d_dr, b, ldb, h->d_y, st));
-        s = levels(4, [&](const int32_t* nodes, int32_t c) { return launch_lsolve(f, h->D, h->vals, nodes, c, h->d_y, nrhs, st); });
+        s = levels(4, [&](const int32_t* nodes, int32_t c, size_t l) {
+            const int32_t with = l < h->lsolve_sn.size() ? h->lsolve_sn[l] : 0;
+            return launch_lsolve(f, h->D, h->vals, nodes, c, h->d_y, nrhs, kLsolveSnMin, with, st);
+        });
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
             LAUNCH(C_TSOLVE, 0, 0, launch_tail_lext(f, h->D, h->vals, L.tail_node0, L.t0, h->d_y, nrhs, st));
@@ -506,12 +513,12 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
             for (size_t k = L.spanels.size(); k-- > 0;)
                 LAUNCH(C_TSOLVE, 0, 0, launch_tail_bwd(f, h->TV, h->vals, L.spanels[k].p0, L.spanels[k].p1, n, h->d_y, h->d_z, nrhs, st));
         }
-        s = levels(1, [&](const int32_t* nodes, int32_t c) { return launch_usolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, st); });
+        s = levels(1, [&](const int32_t* nodes, int32_t c, size_t) { return launch_usolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, st); });
         if (s != HYLU_OK) return s;
         HIPCHK(launch_permute_out(f, n, nrhs, h->d_perm_c, h->d_dc, h->d_z, x, ldx, accumulate, st));
     } else {
         HIPCHK(launch_permute_in(f, n, nrhs, h->d_perm_c, h->d_dc, b, ldb, h->d_y, st));
-        s = levels(2, [&](const int32_t* nodes, int32_t c) { return launch_utsolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, st); });
+        s = levels(2, [&](const int32_t* nodes, int32_t c, size_t) { return launch_utsolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, st); });
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
             LAUNCH(C_TSOLVE, 0, 0, launch_tail_utext(f, h->D, h->TV, h->vals, h->d_y, h->d_z, nrhs, st));
@@ -519,7 +526,7 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
             for (size_t k = L.spanels.size(); k-- > 0;)
                 LAUNCH(C_TSOLVE, 0, 0, launch_tail_lt(f, h->TV, h->vals, L.spanels[k].p0, L.spanels[k].p1, n, h->d_z, nrhs, st));
         }
-        s = levels(3, [&](const int32_t* nodes, int32_t c) { return launch_ltsolve(f, h->D, h->vals, nodes, c, h->d_z, nrhs, st); });
+        s = levels(3, [&](const int32_t* nodes, int32_t c, size_t) { return launch_ltsolve(f, h->D, h->vals, nodes, c, h->d_z, nrhs, st); });
         if (s != HYLU_OK) return s;
         HIPCHK(launch_permute_out(f, n, nrhs, h->d_perm_r, h->d_dr, h->d_z, x, ldx, accumulate, st));
     }
@@ -866,6 +873,13 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     T.node_level.assign(L.nnodes, 0);
     for (int32_t l = 0; l < nl; l++)
         for (int32_t v : lvnodes[l]) T.node_level[v] = l;
+    // L-solve levels with a supernode of kLsolveSnMin..64 rows
+    h->lsolve_sn.assign(L.xlev_ptr[4].size() > 0 ? L.xlev_ptr[4].size() - 1 : 0, 0);
+    for (size_t l = 0; l + 1 < L.xlev_ptr[4].size(); l++)
+        for (int32_t t = L.xlev_ptr[4][l]; t < L.xlev_ptr[4][l + 1]; t++) {
+            const int32_t m = L.m[L.xlev_nodes[4][t]];
+            if (m >= kLsolveSnMin && m <= 64) h->lsolve_sn[l] = 1;
+        }
     // the large supernodes' places in the L-solve and U-solve level sequences
     {
         std::vector<int32_t> dix(L.nnodes, -1);

@@ -31,6 +31,7 @@ template <typename T> __device__ __forceinline__ T pmag(T x)
 }
 
 constexpr int kStage = 1024;   // staged source entries per batch (values + relative indices)
+constexpr int kSnSolveRows = 64;   // largest supernode of the four-wavefront forward solve
 
 // ----------------------------------------------------------------------------
 // value scatter: B = R A C into the panels (fill slots are zero)
@@ -450,12 +451,13 @@ __device__ __forceinline__ float bcast(float x, int l)
 template <typename T>
 __global__ __launch_bounds__(64) void k_lsolve(DevLayout D, const T* __restrict__ vals,
                                                const int32_t* __restrict__ nodes, int32_t count,
-                                               T* __restrict__ y, int32_t nrhs)
+                                               T* __restrict__ y, int32_t nrhs, int32_t sn_min)
 {
     const int v = nodes[blockIdx.x];
     if (D.dense_sn && D.dense_sn[v]) return;     // solved by the dense-view kernels
     const int lane = threadIdx.x;
     const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    if (sn_min > 0 && m >= sn_min && m <= kSnSolveRows) return;   // solved by k_lsolve_sn
     const T* P = vals + D.voff[v];
     const int32_t* cols = D.cols + D.coff[v];
     const int32_t* pl = D.pl + r0;
@@ -471,6 +473,54 @@ __global__ __launch_bounds__(64) void k_lsolve(DevLayout D, const T* __restrict_
             if (lane == 0) yr[r0 + a] -= acc;
             __syncthreads();
         }
+    }
+}
+
+// forward solve of a supernode with at least sn_min rows on four wavefronts:
+// the rows' gathers over the L region are independent and run first, spread
+// over the wavefronts; the unit-lower block (row a's multiplier for an earlier
+// row b at b's pivot column) is then swept column by column on wavefront 0,
+// one lane per row, with the block staged in LDS
+template <typename T>
+__global__ __launch_bounds__(256) void k_lsolve_sn(DevLayout D, const T* __restrict__ vals,
+                                                   const int32_t* __restrict__ nodes, int32_t count,
+                                                   T* __restrict__ y, int32_t nrhs, int32_t sn_min)
+{
+    __shared__ T Lb[kSnSolveRows][kSnSolveRows + 1];   // Lb[r][b] = L(r, b), b < r
+    __shared__ T ys[kSnSolveRows];
+    const int v = nodes[blockIdx.x];
+    if (D.dense_sn && D.dense_sn[v]) return;
+    const int m = D.m[v];
+    if (m < sn_min || m > kSnSolveRows) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const T* P = vals + D.voff[v];
+    const int32_t* cols = D.cols + D.coff[v];
+    const int32_t* pl = D.pl + r0;
+    const int n = D.n;
+    for (int idx = tid; idx < m * m; idx += 256) {
+        const int r = idx / m, b = idx - (idx / m) * m;
+        Lb[r][b] = b < r ? P[(int64_t)r * W + lw + pl[b]] : T(0);
+    }
+    for (int r = 0; r < nrhs; r++) {
+        T* yr = y + (int64_t)r * n;
+        for (int a = wv; a < m; a += 4) {
+            const T* Pa = P + (int64_t)a * W;
+            T acc = T(0);
+            for (int t = lane; t < lw; t += 64) acc += Pa[t] * yr[D.qinv[cols[t]]];
+            acc = wave_sum(acc);
+            if (lane == 0) ys[a] = yr[r0 + a] - acc;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            T va = lane < m ? ys[lane] : T(0);
+            for (int b = 0; b < m; b++) {
+                const T yb = bcast(va, b);
+                if (lane > b && lane < m) va -= Lb[lane][b] * yb;
+            }
+            if (lane < m) yr[r0 + lane] = va;
+        }
+        __syncthreads();
     }
 }
 
@@ -1606,11 +1656,16 @@ hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const i
 }
 
 hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
-                         void* y, int32_t nrhs, hipStream_t st)
+                         void* y, int32_t nrhs, int32_t sn_min, int32_t with_sn, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    if (fp32) hipLaunchKernelGGL(k_lsolve<float>, dim3(count), dim3(64), 0, st, D, (const float*)vals, nodes, count, (float*)y, nrhs);
-    else hipLaunchKernelGGL(k_lsolve<double>, dim3(count), dim3(64), 0, st, D, (const double*)vals, nodes, count, (double*)y, nrhs);
+    if (!with_sn || sn_min > kSnSolveRows) sn_min = 0;    // every node by k_lsolve
+    if (fp32) hipLaunchKernelGGL(k_lsolve<float>, dim3(count), dim3(64), 0, st, D, (const float*)vals, nodes, count, (float*)y, nrhs, sn_min);
+    else hipLaunchKernelGGL(k_lsolve<double>, dim3(count), dim3(64), 0, st, D, (const double*)vals, nodes, count, (double*)y, nrhs, sn_min);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || sn_min <= 0) return e;
+    if (fp32) hipLaunchKernelGGL(k_lsolve_sn<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (float*)y, nrhs, sn_min);
+    else hipLaunchKernelGGL(k_lsolve_sn<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (double*)y, nrhs, sn_min);
     return hipGetLastError();
 }
 

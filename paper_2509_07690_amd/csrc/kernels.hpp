@@ -129,8 +129,10 @@ hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, v
 // nt: threads per supernode (64 or 256; 0 = 256)
 hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const int32_t* nodes, int32_t count,
                               int32_t maxm, double tau, int32_t* pert, int32_t search, int32_t nt, hipStream_t st);
+// forward L solve of a level's nodes; supernodes of sn_min..64 rows (sn_min > 0)
+// go to a four-wavefront kernel, launched when with_sn says the level has one
 hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
-                         void* y, int32_t nrhs, hipStream_t st);
+                         void* y, int32_t nrhs, int32_t sn_min, int32_t with_sn, hipStream_t st);
 hipError_t launch_usolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
                          const void* y, void* x, int32_t nrhs, hipStream_t st);
 hipError_t launch_utsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
