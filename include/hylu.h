@@ -74,7 +74,7 @@ typedef struct {
     int32_t tail_max;      /* largest dense tail in rows (default 32768) */
     int32_t sn_dense;      /* supernodes outside the dense tail with at least this many rows are factored by
                               the blocked panel / TRSM / MFMA-GEMM kernels instead of one workgroup each
-                              (0: never; default 128) */
+                              (0: never; default 64) */
     int32_t sn_tile;       /* supernodes outside the dense tail with at least this many rows take their
                               updates from earlier nodes by 16-row tiles (MFMA for supernode sources) instead
                               of one row per workgroup (0: never; default 0: on the 3D grids measured so far

@@ -950,7 +950,7 @@ hylu_status hylu_default_options(hylu_options* o)
     o->dense_tail = 0.5;
     o->tail_min = 64;
     o->tail_max = 32768;
-    o->sn_dense = 128;
+    o->sn_dense = 64;
     o->sn_tile = 0;
     o->pipeline_rows = 0;
     return HYLU_OK;
