@@ -52,6 +52,7 @@ def main():
     ap.add_argument("--members", type=int, default=256)
     ap.add_argument("--sn-tile", type=int, default=0)
     ap.add_argument("--sn-dense", type=int, default=64)
+    ap.add_argument("--sn-inverse", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -73,7 +74,8 @@ def main():
     log(f"pattern n={A0.n} nnz={A0.nnz} ({time.time() - t0:.1f}s)")
     t0 = time.time()
     h = hylu.Handle(A0.row_ptr, A0.col, A0.val, precision=args.precision, amd_dense=args.amd_dense,
-                    dense_tail=args.dense_tail, pipeline_rows=args.pipeline_rows, sn_dense=args.sn_dense)
+                    dense_tail=args.dense_tail, pipeline_rows=args.pipeline_rows, sn_dense=args.sn_dense,
+                    sn_inverse=args.sn_inverse)
     t_analyze = time.time() - t0
     info = h.info()
     log(f"analyze {t_analyze:.1f}s: F={info['flops']:.3e} nnz(L+U)={info['nnz_l'] + info['nnz_u']:.3e} "
@@ -255,7 +257,8 @@ def bench_batch(args):
     a0 = [w.extra["analyze_values"] for w in ws]
     log(f"members {len(ws)} n={sum(w.A.n for w in ws)} ({time.time() - t0:.1f}s)")
     t0 = time.time()
-    hb = hylu.Handle.batch([(a.row_ptr, a.col, a.val) for a in a0], precision=args.precision, sn_dense=args.sn_dense)
+    hb = hylu.Handle.batch([(a.row_ptr, a.col, a.val) for a in a0], precision=args.precision, sn_dense=args.sn_dense,
+                            sn_inverse=args.sn_inverse)
     t_an = time.time() - t0
     inf = hb.info()
     log(f"analyze {t_an:.1f}s F={inf['flops']:.3e} levels={inf['n_levels']}")
@@ -297,7 +300,7 @@ def bench_grid27(args):
     A = w.A
     t0 = time.time()
     h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd", precision=args.precision, dense_tail=args.dense_tail,
-                    sn_tile=args.sn_tile, sn_dense=args.sn_dense)
+                    sn_tile=args.sn_tile, sn_dense=args.sn_dense, sn_inverse=args.sn_inverse)
     t_an = time.time() - t0
     log(f"analyze {t_an:.1f}s F={h.info()['flops']:.3e} tail={h.info()['tail_rows']}")
     v = torch.from_numpy(A.val).cuda()
@@ -334,7 +337,8 @@ def bench_adjoint(args):
     side = args.n if args.n != 200000 else 48
     w = synth.convdiff3d_7pt(side)
     A = w.A
-    h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd", dense_tail=args.dense_tail, sn_dense=args.sn_dense)
+    h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd", dense_tail=args.dense_tail, sn_dense=args.sn_dense,
+                      sn_inverse=args.sn_inverse)
     v = torch.from_numpy(A.val).cuda()
     b = torch.from_numpy(np.ascontiguousarray(w.b[:, 0])).cuda()
     xt = torch.from_numpy(w.extra["x_target"]).cuda()

@@ -79,6 +79,9 @@ typedef struct {
                               updates from earlier nodes by 16-row tiles (MFMA for supernode sources) instead
                               of one row per workgroup (0: never; default 0: on the 3D grids measured so far
                               the per-tile triangular solves make it slower than the row kernel) */
+    int32_t sn_inverse;    /* 1: after its LU, each supernode outside the dense tail with at most 256 rows keeps
+                              the inverse of its block in pivot order, and target rows form their multipliers
+                              for it as one product with that inverse instead of a triangular solve (default 1) */
     int32_t pipeline_rows; /* reserved for the pipelined mode of Sec. 2.2.1 (one persistent launch whose
                               blocks wait per source node); switched off: must be 0, else HYLU_ERR_ARG */
 } hylu_options;

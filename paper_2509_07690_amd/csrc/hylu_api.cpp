@@ -103,6 +103,13 @@ struct hylu_handle_s {
     std::vector<int32_t> dsn_ptr;           // per factor level into dsn
     std::vector<std::vector<int32_t>> dsn_l, dsn_u;   // per L-solve / U-solve level: dsn indices
     std::vector<int32_t> lsolve_sn;         // per L-solve level: 1 if it has a supernode for k_lsolve_sn
+    std::vector<int64_t> inv_off;           // per node: offset of its block inverse, or -1
+    int64_t inv_total = 0;
+    std::vector<int64_t> inv_ptr;           // per factor level into inv_nodes
+    std::vector<int32_t> inv_nodes, inv_maxm;
+    int64_t* d_inv_off = nullptr;
+    int32_t* d_inv_nodes = nullptr;
+    void* d_uinv = nullptr;
     static constexpr int kSide = 4;         // side streams for independent supernodes of a level
     hipStream_t side[kSide] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_join[kSide] = {nullptr, nullptr, nullptr, nullptr};
@@ -446,6 +453,11 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
         }
         hylu_status sd = enqueue_level_dense(h, l, search, st);
         if (sd != HYLU_OK) return sd;
+        if (h->inv_ptr[l + 1] > h->inv_ptr[l])
+            LAUNCH(C_SNLU, 0.0, 0.0,
+                   launch_sn_inverse(h->fp32, h->D, h->vals, h->d_inv_nodes + h->inv_ptr[l],
+                                     (int32_t)(h->inv_ptr[l + 1] - h->inv_ptr[l]), h->inv_maxm[l], h->d_inv_off,
+                                     h->d_uinv, st));
     }
     if (T.pipe_level < nl) {
         // pipeline mode over the remaining levels
@@ -597,6 +609,7 @@ hylu_status upload_device(hylu_handle h)
                 d.lp = L.elpos[e];
                 d.r0s = L.r0[s];
                 d.srcp = (T.node_level[s] >= T.pipe_level && s < L.tail_node0) ? s : -1;
+                d.ioff = h->inv_off[s];
             }
         std::vector<double> asr(h->nnz), asc(h->nnz);
         for (int32_t i = 0; i < n; i++)
@@ -615,6 +628,10 @@ hylu_status upload_device(hylu_handle h)
         D.eptr = eptr; D.edges = edges; D.rel = rel; D.row_node = row_node; D.pl = pl; D.qinv = qinv;
         UP(h->d_amap, L.amap); UP(h->d_asr, asr); UP(h->d_asc, asc);
         UP(h->d_rows, T.rows); UP(h->d_snodes, T.snodes); UP(h->d_tiles, T.tiles);
+        UP(h->d_inv_off, h->inv_off); UP(h->d_inv_nodes, h->inv_nodes);
+        h->d_uinv = dalloc(h, (size_t)std::max<int64_t>(h->inv_total, 1) * (h->fp32 ? 4 : 8));
+        if (!h->d_uinv) return HYLU_ERR_OOM;
+        D.uinv = h->d_uinv;
         for (int g = 0; g < 5; g++) UP(h->d_lev[g], L.xlev_nodes[g]);
         {
             TailView& TVw = h->TV;
@@ -873,6 +890,26 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     T.node_level.assign(L.nnodes, 0);
     for (int32_t l = 0; l < nl; l++)
         for (int32_t v : lvnodes[l]) T.node_level[v] = l;
+    // block inverses of the supernodes outside the tail with 2..kInvMax rows,
+    // computed in the level of their factorisation
+    h->inv_off.assign(L.nnodes, -1);
+    h->inv_total = 0;
+    h->inv_ptr.assign(1, 0);
+    h->inv_nodes.clear();
+    h->inv_maxm.clear();
+    for (int32_t l = 0; l < nl; l++) {
+        int32_t mm = 0;
+        if (opt.sn_inverse)
+            for (int32_t v : lvnodes[l]) {
+                if (!nd.is_sn[v] || v >= L.tail_node0 || L.m[v] < 2 || L.m[v] > kInvMax) continue;
+                h->inv_off[v] = h->inv_total;
+                h->inv_total += (int64_t)L.m[v] * L.m[v];
+                h->inv_nodes.push_back(v);
+                mm = std::max(mm, L.m[v]);
+            }
+        h->inv_ptr.push_back((int64_t)h->inv_nodes.size());
+        h->inv_maxm.push_back(mm);
+    }
     // L-solve levels with a supernode of kLsolveSnMin..64 rows
     h->lsolve_sn.assign(L.xlev_ptr[4].size() > 0 ? L.xlev_ptr[4].size() - 1 : 0, 0);
     for (size_t l = 0; l + 1 < L.xlev_ptr[4].size(); l++)
@@ -952,6 +989,7 @@ hylu_status hylu_default_options(hylu_options* o)
     o->tail_max = 32768;
     o->sn_dense = 64;
     o->sn_tile = 0;
+    o->sn_inverse = 1;
     o->pipeline_rows = 0;
     return HYLU_OK;
 }

@@ -97,9 +97,28 @@ __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ va
     const int32_t* rl = D.rel + ed.roff;
     const int lp = ed.lp, ms = ed.ms, Ws = ed.Ws, ws = ed.ws;
     const bool pl_lds = ms <= kStage;
-    const bool blk_lds = ms * ms <= kStage;
     const int32_t* pls = pl_lds ? ibuf : D.pl + ed.r0s;
     if (pl_lds) for (int b = tid; b < ms; b += NT) ibuf[b] = D.pl[ed.r0s + b];
+    if (ed.ioff >= 0 && ms <= kStage) {
+        // multipliers from the inverse: l_c = sum_{b <= c} x_p[b] Uinv[b][c],
+        // every c at once (x_p staged in LDS first)
+        const T* Ui = reinterpret_cast<const T*>(D.uinv) + ed.ioff;
+        __syncthreads();
+        for (int b = tid; b < ms; b += NT) sbuf[b] = xs[lp + pls[b]];
+        __syncthreads();
+        for (int c = tid; c < ms; c += NT) {
+            T acc0 = T(0), acc1 = T(0);
+            int b = 0;
+            for (; b + 2 <= c + 1; b += 2) {
+                acc0 += sbuf[b] * Ui[(int64_t)b * ms + c];
+                acc1 += sbuf[b + 1] * Ui[(int64_t)(b + 1) * ms + c];
+            }
+            if (b <= c) acc0 += sbuf[b] * Ui[(int64_t)b * ms + c];
+            xs[lp + pls[c]] = acc0 + acc1;
+        }
+        __syncthreads();
+    } else {
+    const bool blk_lds = ms * ms <= kStage;
     if (blk_lds)
         for (int idx = tid; idx < ms * ms; idx += NT) sbuf[idx] = Us[(int64_t)(idx / ms) * Ws + idx % ms];
     __syncthreads();
@@ -114,6 +133,7 @@ __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ va
             xs[lp + pc] -= lb * (blk_lds ? sbuf[b * ms + pc] : Us[(int64_t)b * Ws + pc]);
         }
         __syncthreads();
+    }
     }
     const T* Ut = Us + ms;
     for (int j = tid; j < ws; j += NT) {
@@ -272,6 +292,45 @@ __global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__
     if ((int)blockIdx.x >= nrows) return;
     PipeCtl none{};
     row_task<T, NT, false>(D, vals, rows[blockIdx.x], lds_cap, tau, pert, smem_raw, none, 0);
+}
+
+// ----------------------------------------------------------------------------
+// inverse of a supernode's block in pivot order, once its LU is complete: one
+// workgroup per supernode, thread j solving U_pp x = e_j by back substitution
+// for column j of the inverse (U_pp staged in LDS when it fits)
+template <typename T>
+__global__ __launch_bounds__(256) void k_sn_inverse(DevLayout D, const T* __restrict__ vals,
+                                                    const int32_t* __restrict__ nodes, const int64_t* __restrict__ inv_off,
+                                                    T* __restrict__ uinv, int32_t lds_m)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int pls[kInvMax];
+    const int v = nodes[blockIdx.x];
+    const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const T* P = vals + D.voff[v] + lw;
+    T* X = uinv + inv_off[v];
+    const int tid = threadIdx.x;
+    for (int b = tid; b < m; b += 256) pls[b] = D.pl[r0 + b];
+    __syncthreads();
+    const bool in_lds = m <= lds_m;
+    T* Us = reinterpret_cast<T*>(smem_raw);          // m x m, Us[i*m + k] = U_pp(i, k)
+    if (in_lds) {
+        for (int idx = tid; idx < m * m; idx += 256) {
+            const int i = idx / m, k = idx - (idx / m) * m;
+            Us[idx] = k >= i ? P[(int64_t)i * W + pls[k]] : T(0);
+        }
+        __syncthreads();
+    }
+    auto U = [&](int i, int k) -> T { return in_lds ? Us[i * m + k] : P[(int64_t)i * W + pls[k]]; };
+    for (int j = tid; j < m; j += 256) {
+        for (int i = j + 1; i < m; i++) X[(int64_t)i * m + j] = T(0);
+        X[(int64_t)j * m + j] = T(1) / U(j, j);
+        for (int i = j - 1; i >= 0; i--) {
+            T acc = T(0);
+            for (int k = i + 1; k <= j; k++) acc += U(i, k) * X[(int64_t)k * m + j];
+            X[(int64_t)i * m + j] = -acc / U(i, i);
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -1634,6 +1693,19 @@ hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, v
         if (wide) hipLaunchKernelGGL((k_factor_pipe<double, 256>), dim3(grid), dim3(256), sh, st, D, P, (double*)vals, rows, nrows, cap, tau, pert, search);
         else hipLaunchKernelGGL((k_factor_pipe<double, 64>), dim3(grid), dim3(64), sh, st, D, P, (double*)vals, rows, nrows, cap, tau, pert, search);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_sn_inverse(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
+                             int32_t maxm, const int64_t* inv_off, void* uinv, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    if (maxm > kInvMax) return hipErrorInvalidValue;
+    const size_t es = fp32 ? sizeof(float) : sizeof(double);
+    const int lds_m = std::min(maxm, fp32 ? 180 : 128);    // m x m block staged in LDS up to this m
+    const size_t sh = (size_t)lds_m * lds_m * es;
+    if (fp32) hipLaunchKernelGGL(k_sn_inverse<float>, dim3(count), dim3(256), sh, st, D, (const float*)vals, nodes, inv_off, (float*)uinv, lds_m);
+    else hipLaunchKernelGGL(k_sn_inverse<double>, dim3(count), dim3(256), sh, st, D, (const double*)vals, nodes, inv_off, (double*)uinv, lds_m);
     return hipGetLastError();
 }
 

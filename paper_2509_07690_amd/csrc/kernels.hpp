@@ -19,7 +19,15 @@ struct EdgeDesc {
     int32_t lp;     // slot of the source's first column in the target's L region
     int32_t r0s;    // first row of the source (pivot table offset)
     int32_t srcp;   // source node when it is factored in the pipelined region, else -1
+    int64_t ioff;   // offset of the inverse of the source's block in pivot order, or -1
 };
+
+// Inverse of a supernode's block in pivot order: with U_pp(b, b') = U(b, pl_b')
+// (upper triangular), Uinv = U_pp^{-1} is stored row-major (m x m) at
+// uinv + inv_off[v]; a target row's multipliers for the supernode are then
+// l = x_p Uinv (x_p: the row's entries at the source's pivot columns in pivot
+// order) with no sequential dependency.
+constexpr int32_t kInvMax = 256;   // largest supernode given an inverse
 
 // Pipeline mode: persistent blocks claim rows in topological order from a
 // ticket and wait per source node on a done flag.
@@ -46,6 +54,7 @@ struct DevLayout {
     const EdgeDesc* edges;
     const int32_t* rel;
     const int32_t* row_node;
+    const void* uinv;       // inverses of the supernode blocks (factor precision), see EdgeDesc::ioff
     int32_t* pl;            // per row: natural local block column of its pivot
     int32_t* qinv;          // per column: row whose pivot is this column
     // column lists for the transposed solves: entries of other nodes' panels
@@ -127,6 +136,9 @@ hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, v
                               int32_t nrows, int32_t maxW, int32_t maxm, double tau, int32_t* pert, int32_t search,
                               hipStream_t st);
 // nt: threads per supernode (64 or 256; 0 = 256)
+// inverses of the blocks of the listed supernodes (each 2 <= m <= kInvMax)
+hipError_t launch_sn_inverse(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
+                             int32_t maxm, const int64_t* inv_off, void* uinv, hipStream_t st);
 hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const int32_t* nodes, int32_t count,
                               int32_t maxm, double tau, int32_t* pert, int32_t search, int32_t nt, hipStream_t st);
 // forward L solve of a level's nodes; supernodes of sn_min..64 rows (sn_min > 0)

@@ -99,9 +99,13 @@ def _integer_case(n, density, seed):
 
 @pytest.mark.parametrize("seed", range(3))
 def test_integer_factors_bit_exact(hylu, seed):
+    """Integer L and U with power-of-two pivots: every intermediate of the
+    substitution is a small dyadic number, so the factors are exact.  The
+    block-inverse form of the sup-row update rounds the inverse's entries,
+    so it is off here (sn_inverse=0); it is compared at tolerance elsewhere."""
     A, L, U = _integer_case([40, 90, 150][seed], [0.1, 0.04, 0.02][seed], 700 + seed)
     b = np.arange(A.n, dtype=np.float64)
-    h, o, x, xo, eta = run_case(hylu, A, b, opts=dict(static_pivot=0, ordering="natural"), exact=True)
+    h, o, x, xo, eta = run_case(hylu, A, b, opts=dict(static_pivot=0, ordering="natural", sn_inverse=0), exact=True)
 
 
 @pytest.mark.parametrize("ordering,tail,tile", [("amd", 0.5, 16), ("nd", 0.5, 16), ("amd", 0.0, 16), ("amd", 0.05, 16),
@@ -207,19 +211,20 @@ def test_small_circuit(hylu, pipe):
     compare_factors(h, o)
 
 
-@pytest.mark.parametrize("side,sn_dense,tail,tile", [(12, 16, 0.0, 16), (16, 32, 0.15, 16), (16, 2, 0.0, 2),
-                                                    (16, 128, 0.0, 0)])
-def test_grid3d_blocked_supernodes(hylu, side, sn_dense, tail, tile):
+@pytest.mark.parametrize("side,sn_dense,tail,tile,inv", [(12, 16, 0.0, 16, 1), (16, 32, 0.15, 16, 1), (16, 2, 0.0, 2, 1),
+                                                        (16, 128, 0.0, 0, 1), (16, 128, 0.0, 0, 0), (16, 64, 0.0, 0, 0)])
+def test_grid3d_blocked_supernodes(hylu, side, sn_dense, tail, tile, inv):
     """7-point 3D grid (ND): supernodes of at least sn_dense rows go through
     the blocked panel / TRSM / MFMA-GEMM kernels on side streams.  Pivots and
     structure bit-exact; L and U are not diagonally dominant here (growth
     ~1e3 in each), so the entries are compared with a growth-derived tolerance
     and the device factors must reproduce B as closely as the oracle's do;
-    refactorisation through the graph; the solve against the oracle."""
+    refactorisation through the graph; the solve against the oracle.  inv:
+    sup-row multipliers from the block inverse (1) or by substitution (0)."""
     w = synth.convdiff3d_7pt(side)
     A = w.A
     h, o, x, xo, eta = run_case(hylu, A, w.b[:, 0], opts=dict(ordering="nd", sn_dense=sn_dense, dense_tail=tail,
-                                                              sn_tile=tile), tol="derived")
+                                                              sn_tile=tile, sn_inverse=inv), tol="derived")
     print("residual ratios (device, oracle):", compare_backward_stability(h, o))
     assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
     A2 = synth.grid_values(A, 77, 4.0)
