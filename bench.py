@@ -53,6 +53,7 @@ def main():
     ap.add_argument("--sn-tile", type=int, default=0)
     ap.add_argument("--sn-dense", type=int, default=64)
     ap.add_argument("--sn-inverse", type=int, default=1)
+    ap.add_argument("--tail-sparse", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -75,7 +76,7 @@ def main():
     t0 = time.time()
     h = hylu.Handle(A0.row_ptr, A0.col, A0.val, precision=args.precision, amd_dense=args.amd_dense,
                     dense_tail=args.dense_tail, pipeline_rows=args.pipeline_rows, sn_dense=args.sn_dense,
-                    sn_inverse=args.sn_inverse)
+                    sn_inverse=args.sn_inverse, tail_sparse=args.tail_sparse)
     t_analyze = time.time() - t0
     info = h.info()
     log(f"analyze {t_analyze:.1f}s: F={info['flops']:.3e} nnz(L+U)={info['nnz_l'] + info['nnz_u']:.3e} "
@@ -300,7 +301,8 @@ def bench_grid27(args):
     A = w.A
     t0 = time.time()
     h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd", precision=args.precision, dense_tail=args.dense_tail,
-                    sn_tile=args.sn_tile, sn_dense=args.sn_dense, sn_inverse=args.sn_inverse)
+                    sn_tile=args.sn_tile, sn_dense=args.sn_dense, sn_inverse=args.sn_inverse,
+                    tail_sparse=args.tail_sparse)
     t_an = time.time() - t0
     log(f"analyze {t_an:.1f}s F={h.info()['flops']:.3e} tail={h.info()['tail_rows']}")
     v = torch.from_numpy(A.val).cuda()
@@ -338,7 +340,7 @@ def bench_adjoint(args):
     w = synth.convdiff3d_7pt(side)
     A = w.A
     h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd", dense_tail=args.dense_tail, sn_dense=args.sn_dense,
-                      sn_inverse=args.sn_inverse)
+                      sn_inverse=args.sn_inverse, tail_sparse=args.tail_sparse)
     v = torch.from_numpy(A.val).cuda()
     b = torch.from_numpy(np.ascontiguousarray(w.b[:, 0])).cuda()
     xt = torch.from_numpy(w.extra["x_target"]).cuda()

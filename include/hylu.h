@@ -82,6 +82,8 @@ typedef struct {
     int32_t sn_inverse;    /* 1: after its LU, each supernode outside the dense tail with at most 256 rows keeps
                               the inverse of its block in pivot order, and target rows form their multipliers
                               for it as one product with that inverse instead of a triangular solve (default 1) */
+    int32_t tail_sparse;   /* 1: the dense tail's trailing updates and triangular solves skip the 64 x 64 blocks
+                              that are zero by structure (same factors to the bit; default 1) */
     int32_t pipeline_rows; /* reserved for the pipelined mode of Sec. 2.2.1 (one persistent launch whose
                               blocks wait per source node); switched off: must be 0, else HYLU_ERR_ARG */
 } hylu_options;

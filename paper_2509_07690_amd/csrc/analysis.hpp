@@ -122,4 +122,21 @@ int32_t choose_tail(const Symbolic& s, const Nodes& nd, double density, int32_t 
 bool build_layout(const Csr& b, const Symbolic& s, const Nodes& nd, int32_t tail_node0, int32_t panel_rows,
                   Layout& L, const std::vector<int64_t>& bsrc, std::string& err);
 
+// Structural block masks of the dense tail over its factorisation panels
+// (L.panels).  lbits: per tail row, the panels whose pivot columns the row has
+// L entries in; ubits: per tail column, the panels with a row that has a U
+// entry in that column.  Node-padded (a row with an entry anywhere in a node's
+// block counts for every panel of that node; a row's U covers its whole
+// block), so every entry outside the masks stays exactly zero through the
+// dense factorisation whatever pivots the blocks take: the trailing updates
+// and triangular solves of those blocks can be skipped with no change to any
+// result.  words: 64-bit words per row / column.
+struct TailMasks {
+    int32_t words = 0;
+    std::vector<uint64_t> lbits, ubits;
+    bool lbit(int32_t a, int32_t j) const { return (lbits[(size_t)a * words + (j >> 6)] >> (j & 63)) & 1; }
+    bool ubit(int32_t c, int32_t j) const { return (ubits[(size_t)c * words + (j >> 6)] >> (j & 63)) & 1; }
+};
+void tail_masks(const Symbolic& s, const Nodes& nd, const Layout& L, TailMasks& M);
+
 }  // namespace hylu

@@ -244,6 +244,52 @@ int32_t choose_tail(const Symbolic& s, const Nodes& nd, double density, int32_t 
     return nd.of_row[best];
 }
 
+void tail_masks(const Symbolic& s, const Nodes& nd, const Layout& L, TailMasks& M)
+{
+    const int32_t mT = L.mT, t0 = L.t0, np = (int32_t)L.panels.size();
+    M = TailMasks();
+    if (mT <= 0 || np == 0) return;
+    const int32_t wd = (np + 63) / 64;
+    M.words = wd;
+    M.lbits.assign((size_t)mT * wd, 0);
+    M.ubits.assign((size_t)mT * wd, 0);
+    // panels whose pivot window holds tail-local column c: [pf[c], pl[c]]
+    // (one panel, or every chunk of a node cut into chunks)
+    std::vector<int32_t> pf(mT, np), pl(mT, -1), prow(mT, 0);
+    for (int32_t j = 0; j < np; j++) {
+        const Layout::Panel& P = L.panels[j];
+        for (int32_t c = P.c0; c < P.c1; c++) { pf[c] = std::min(pf[c], j); pl[c] = std::max(pl[c], j); }
+        for (int32_t a = P.p0; a < P.p1; a++) prow[a] = j;
+    }
+    auto set_range = [&](uint64_t* w, int32_t j0, int32_t j1) {      // bits j0..j1 inclusive
+        for (int32_t j = j0; j <= j1;) {
+            if ((j & 63) == 0 && j + 63 <= j1) { w[j >> 6] = ~0ull; j += 64; }
+            else { w[j >> 6] |= 1ull << (j & 63); j++; }
+        }
+    };
+    for (int32_t a = 0; a < mT; a++) {
+        const int32_t i = t0 + a;
+        const int32_t v = nd.of_row[i];
+        const int32_t b0 = nd.ptr[v] - t0, b1 = nd.ptr[v + 1] - t0;
+        uint64_t* lw = M.lbits.data() + (size_t)a * wd;
+        // L entries in the tail (intervals of strictly-lower columns), widened
+        // to whole windows; the row's own node counts whole
+        for (int64_t t = s.lp[i]; t < s.lp[i + 1]; t++) {
+            int32_t lo = std::max(s.lint[2 * t], t0), hi = s.lint[2 * t + 1];
+            if (hi < lo) continue;
+            set_range(lw, pf[lo - t0], pl[hi - t0]);
+        }
+        set_range(lw, pf[b0], pl[b1 - 1]);
+        // U entries: the whole block and the strict upper structure
+        const int32_t j = prow[a];
+        const uint64_t bit = 1ull << (j & 63);
+        for (int32_t c = b0; c < b1; c++) M.ubits[(size_t)c * wd + (j >> 6)] |= bit;
+        const int32_t* up; int64_t ul;
+        row_upper(s, i, up, ul);
+        for (int64_t t = 0; t < ul; t++) M.ubits[(size_t)(up[t] - t0) * wd + (j >> 6)] |= bit;
+    }
+}
+
 bool build_layout(const Csr& b, const Symbolic& s, const Nodes& nd, int32_t tail_node0, int32_t panel_rows,
                   Layout& L, const std::vector<int64_t>& bsrc, std::string& err)
 {

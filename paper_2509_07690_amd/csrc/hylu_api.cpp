@@ -65,6 +65,16 @@ struct LevelTasks {
     std::vector<int32_t> node_level;  // execution level of every node
 };
 
+// one launch of the blocked dense LU of a view (a large supernode or the tail)
+struct DenseOp {
+    int32_t kind = 0;                 // 0 panel, 1 TRSM, 2 trailing GEMM
+    int32_t a[8] = {};                // panel: p0 p1 c0 c1 | TRSM: p0 p1 c1 kb0 kof | GEMM: kb0 K rb re cg0 mstep gp0 gnp
+    int32_t kb[kGroup + 1] = {};      // GEMM: K offsets of the group's panels
+    int64_t list = -1;                // offset of its tile / block list; -1: every tile
+    int32_t count = 0;
+    double elems = 0.0, flops = 0.0;  // algorithmic traffic (values) and flops
+};
+
 }  // namespace
 
 struct hylu_handle_s {
@@ -98,7 +108,11 @@ struct hylu_handle_s {
     TailView TV{};
     PipeCtl PC{};
     // large supernodes outside the tail, factored by the blocked dense kernels
-    struct DenseSn { int32_t v, level; TailView TV; std::vector<Layout::Panel> panels, spanels; };
+    struct DenseSn { int32_t v, level; TailView TV; std::vector<Layout::Panel> panels, spanels; std::vector<DenseOp> ops; };
+    std::vector<DenseOp> tail_ops;          // the dense tail's launches, block-sparse when its masks are known
+    std::vector<uint32_t> tail_list;        // their tile / block lists
+    uint32_t* d_tail_list = nullptr;
+    double tail_flops = 0.0;
     std::vector<DenseSn> dsn;
     std::vector<int32_t> dsn_ptr;           // per factor level into dsn
     std::vector<std::vector<int32_t>> dsn_l, dsn_u;   // per L-solve / U-solve level: dsn indices
@@ -340,46 +354,175 @@ constexpr int32_t kGroupMinRows = 2048;
 // supernodes of at least this many rows (and at most 64) take the
 // four-wavefront forward-solve kernel
 constexpr int32_t kLsolveSnMin = 8;
-hylu_status enqueue_dense(hylu_handle h, const TailView& TV, const std::vector<Layout::Panel>& panels, bool search,
-                          hipStream_t st)
+// The launch sequence of a view: groups of up to kGroup panels (left-looking
+// inside the group, one trailing update per group).  With the tail's masks M
+// every GEMM gets the list of its tiles that have a nonzero product, each with
+// the group panels that contribute, in XCD order, and every TRSM the list of
+// its blocks that hold entries (row blocks without multipliers only write
+// zeros to lbuf); the rest is exactly zero and is skipped.
+void plan_dense(const std::vector<Layout::Panel>& panels, int32_t mT, int32_t nc, const TailMasks* M,
+                std::vector<DenseOp>& ops, std::vector<uint32_t>& lists)
 {
-    const double es = h->fp32 ? 4.0 : 8.0;
-    const double mT = TV.mT, nc = TV.nc;
-    auto gemm = [&](int32_t kb0, int32_t K, int32_t rb, int32_t re, int32_t cg0, int32_t mstep, int32_t gp0,
-                    int32_t gnp) -> hylu_status {
-        const double rows = re - rb, cols = gnp > 0 ? gnp : nc - cg0;
-        if (K <= 0 || rows <= 0 || cols <= 0) return HYLU_OK;
-        LAUNCH(C_GEMM, es * (2.0 * rows * cols + K * (rows + cols)), 2.0 * K * rows * cols,
-               launch_tail_gemm(h->fp32, TV, h->vals, kb0, K, rb, re, cg0, mstep, gp0, gnp, st));
-        return HYLU_OK;
+    ops.clear();
+    const int32_t wd = M ? M->words : 0;
+    auto bits = [&](const std::vector<uint64_t>& v, int32_t row, int32_t g0, int32_t nk) -> uint32_t {
+        const uint64_t* w = v.data() + (size_t)row * wd;
+        const int32_t q = g0 >> 6, o = g0 & 63;
+        uint64_t x = w[q] >> o;
+        if (o && q + 1 < wd) x |= w[q + 1] << (64 - o);
+        return (uint32_t)(x & ((1ull << nk) - 1));
     };
-    // groups of up to kGroup panels: left-looking inside the group, one
-    // trailing update per group
+    auto gemm = [&](int32_t g0, int32_t nk, const int32_t* kofs, int32_t kb0, int32_t rb, int32_t re, int32_t cg0,
+                    int32_t mstep, int32_t gp0, int32_t gnp, int32_t w0, int32_t w1) {
+        const int32_t K = kofs[nk];
+        const int32_t rows = re - rb, cols = gnp > 0 ? gnp : nc - cg0;
+        if (K <= 0 || rows <= 0 || cols <= 0) return;
+        DenseOp o;
+        o.kind = 2;
+        const int32_t a[8] = {kb0, K, rb, re, cg0, mstep, gp0, gnp};
+        std::copy(a, a + 8, o.a);
+        for (int j = 0; j <= kGroup; j++) o.kb[j] = j <= nk ? kofs[j] : K;
+        const int32_t gy = (rows + 63) / 64, gx = gnp > 0 ? 1 : (cols + 63) / 64;
+        if (!M || gx > 4095 || gy > 65535) {
+            o.elems = 2.0 * rows * cols + (double)K * (rows + cols);
+            o.flops = 2.0 * K * rows * (double)cols;
+            ops.push_back(o);
+            return;
+        }
+        std::vector<uint32_t> rm(gy, 0), cm(gx, 0);
+        for (int32_t r = rb; r < re; r++) rm[(r - rb) >> 6] |= bits(M->lbits, r, g0, nk);
+        if (gnp > 0) {
+            for (int32_t c = w0; c < w1; c++) cm[0] |= bits(M->ubits, c, g0, nk);
+        } else {
+            for (int32_t c = cg0; c < nc; c++) cm[(c - cg0) >> 6] |= bits(M->ubits, c, g0, nk);
+        }
+        std::vector<uint32_t> t;
+        for (int32_t ty = 0; ty < gy; ty++)
+            for (int32_t tx = 0; tx < gx; tx++) {
+                const uint32_t m = rm[ty] & cm[tx];
+                if (!m) continue;
+                t.push_back(((uint32_t)ty << 16) | ((uint32_t)tx << 4) | m);
+                double ka = 0;
+                for (int j = 0; j < nk; j++)
+                    if ((m >> j) & 1) ka += kofs[j + 1] - kofs[j];
+                const double tr = std::min(64, rows - 64 * ty), tc = std::min(64, cols - 64 * tx);
+                o.flops += 2.0 * tr * tc * ka;
+                o.elems += 2.0 * tr * tc + ka * (tr + tc);
+            }
+        if (t.empty()) return;                     // every product is zero
+        // XCD order: workgroup i runs on XCD i % 8; split the row-major tiles
+        // into four bands of rows, each into two halves of columns, with equal
+        // counts, and give each of the eight parts one XCD
+        std::vector<uint32_t> out;
+        if (t.size() >= 32) {
+            const size_t n = t.size();
+            std::vector<std::vector<uint32_t>> part(8);
+            for (int b = 0; b < 4; b++) {
+                std::vector<uint32_t> band(t.begin() + n * b / 4, t.begin() + n * (b + 1) / 4);
+                std::stable_sort(band.begin(), band.end(), [](uint32_t x, uint32_t y) {
+                    return ((x >> 4) & 0xFFF) < ((y >> 4) & 0xFFF);
+                });
+                const size_t h2 = band.size() / 2;
+                part[2 * b].assign(band.begin(), band.begin() + h2);
+                part[2 * b + 1].assign(band.begin() + h2, band.end());
+            }
+            size_t len = 0;
+            for (auto& q : part) len = std::max(len, q.size());
+            out.assign(8 * len, kTileNone);
+            for (int c = 0; c < 8; c++)
+                for (size_t i = 0; i < part[c].size(); i++) out[i * 8 + c] = part[c][i];
+        } else {
+            out = t;
+        }
+        o.list = (int64_t)lists.size();
+        o.count = (int32_t)out.size();
+        lists.insert(lists.end(), out.begin(), out.end());
+        ops.push_back(o);
+    };
+    auto trsm = [&](int32_t j, const Layout::Panel& P, int32_t kb0, int32_t kof) {
+        DenseOp o;
+        o.kind = 1;
+        const int32_t a[5] = {P.p0, P.p1, P.c1, kb0, kof};
+        std::copy(a, a + 5, o.a);
+        const double np = P.p1 - P.p0;
+        const int32_t colsA = std::max(nc - P.c1, 0), rows = std::max(mT - P.p1, 0);
+        const int32_t nA = (colsA + 63) / 64, nB = (rows + 63) / 64;
+        if (!M) {
+            o.elems = 2.0 * np * colsA + 3.0 * np * rows + np * np;
+            o.flops = np * np * ((double)colsA + rows);
+            ops.push_back(o);
+            return;
+        }
+        std::vector<uint32_t> bl;
+        double ca = 0, rr = 0;
+        for (int32_t b = 0; b < nA; b++) {
+            const int32_t c0 = P.c1 + 64 * b, c1 = std::min(nc, c0 + 64);
+            bool any = false;
+            for (int32_t c = c0; c < c1 && !any; c++) any = M->ubit(c, j);
+            if (any) { bl.push_back((uint32_t)b); ca += c1 - c0; }
+        }
+        for (int32_t b = 0; b < nB; b++) {
+            const int32_t r0 = P.p1 + 64 * b, r1 = std::min(mT, r0 + 64);
+            bool any = false;
+            for (int32_t r = r0; r < r1 && !any; r++) any = M->lbit(r, j);
+            if (any) { bl.push_back((uint32_t)(nA + b)); rr += r1 - r0; }
+            else bl.push_back((uint32_t)(nA + b) | (uint32_t)kTrsmZero);
+        }
+        o.elems = 2.0 * np * ca + 3.0 * np * rr + np * np + np * (rows - rr);
+        o.flops = np * np * (ca + rr);
+        o.list = (int64_t)lists.size();
+        o.count = (int32_t)bl.size();
+        lists.insert(lists.end(), bl.begin(), bl.end());
+        ops.push_back(o);
+    };
     for (size_t i = 0; i < panels.size();) {
         // grouping pays where the trailing matrix is large; near the end its
         // extra launches cost more than the saved passes
-        const bool big = TV.mT - panels[i].p1 >= kGroupMinRows;
+        const bool big = mT - panels[i].p1 >= kGroupMinRows;
         const size_t g1 = std::min(i + (size_t)(big ? kGroup : 1), panels.size());
         const int32_t kb0 = panels[i].p0, cg = panels[i].cg0;
-        int32_t kof = 0;
+        int32_t kofs[kGroup + 1] = {0, 0, 0, 0, 0};
         for (size_t j = i; j < g1; j++) {
             const Layout::Panel& P = panels[j];
-            hylu_status s = gemm(kb0, kof, P.p0, P.p1, cg, P.p0, 0, 0);   // this panel's rows, from the group so far
-            if (s != HYLU_OK) return s;
-            const double np = P.p1 - P.p0, wc = P.c1 - P.c0, rows = mT - P.p1, colsA = nc - P.c1;
-            LAUNCH(C_PANEL, 2.0 * es * np * wc, np * np * wc,
-                   launch_tail_panel(h->fp32, h->D, TV, h->vals, P.p0, P.p1, P.c0, P.c1, h->tau, h->d_pert, search ? 1 : 0, st));
+            const int32_t nk = (int32_t)(j - i);
+            // this panel's rows, from the group so far
+            gemm((int32_t)i, nk, kofs, kb0, P.p0, P.p1, cg, P.p0, 0, 0, 0, 0);
+            DenseOp o;
+            o.kind = 0;
+            const int32_t a[4] = {P.p0, P.p1, P.c0, P.c1};
+            std::copy(a, a + 4, o.a);
+            o.elems = 2.0 * (P.p1 - P.p0) * (P.c1 - P.c0);
+            o.flops = (double)(P.p1 - P.p0) * (P.p1 - P.p0) * (P.c1 - P.c0);
+            ops.push_back(o);
             // the rows below at this panel's pivot columns, from the group so far
-            s = gemm(kb0, kof, P.p1, TV.mT, 0, 0, P.p0, P.p1 - P.p0);
-            if (s != HYLU_OK) return s;
-            LAUNCH(C_TRSM, es * (2.0 * np * colsA + 3.0 * np * rows + np * np), np * np * (colsA + rows),
-                   launch_tail_trsm(h->fp32, TV, h->vals, P.p0, P.p1, P.c1, kb0, kof, st));
-            kof += P.p1 - P.p0;
+            gemm((int32_t)i, nk, kofs, kb0, P.p1, mT, 0, 0, P.p0, P.p1 - P.p0, P.c0, P.c1);
+            trsm((int32_t)j, P, kb0, kofs[nk]);
+            kofs[nk + 1] = kofs[nk] + (P.p1 - P.p0);
         }
         const Layout::Panel& Q = panels[g1 - 1];
-        hylu_status s = gemm(kb0, kof, Q.p1, TV.mT, cg, Q.p1, 0, 0);   // everything below the group
-        if (s != HYLU_OK) return s;
+        gemm((int32_t)i, (int32_t)(g1 - i), kofs, kb0, Q.p1, mT, cg, Q.p1, 0, 0, 0, 0);   // everything below the group
         i = g1;
+    }
+}
+
+hylu_status enqueue_dense(hylu_handle h, const TailView& TV, const std::vector<DenseOp>& ops, const uint32_t* d_list,
+                          bool search, hipStream_t st)
+{
+    const double es = h->fp32 ? 4.0 : 8.0;
+    for (const DenseOp& o : ops) {
+        const int32_t* a = o.a;
+        if (o.kind == 0) {
+            LAUNCH(C_PANEL, es * o.elems, o.flops,
+                   launch_tail_panel(h->fp32, h->D, TV, h->vals, a[0], a[1], a[2], a[3], h->tau, h->d_pert, search ? 1 : 0, st));
+        } else if (o.kind == 1) {
+            const int32_t* bl = o.list >= 0 ? reinterpret_cast<const int32_t*>(d_list + o.list) : nullptr;
+            LAUNCH(C_TRSM, es * o.elems, o.flops,
+                   launch_tail_trsm(h->fp32, TV, h->vals, a[0], a[1], a[2], a[3], a[4], bl, o.count, st));
+        } else {
+            const uint32_t* tl = o.list >= 0 ? d_list + o.list : nullptr;
+            LAUNCH(C_GEMM, es * o.elems, o.flops,
+                   launch_tail_gemm(h->fp32, TV, h->vals, a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], tl, o.count, o.kb, st));
+        }
     }
     return HYLU_OK;
 }
@@ -393,7 +536,7 @@ hylu_status enqueue_level_dense(hylu_handle h, int32_t l, bool search, hipStream
     if (h->prof.on || d1 - d0 == 1) {          // one supernode, or measuring: stay on st
         for (int32_t q = d0; q < d1; q++) {
             if (search) HIPCHK(launch_tail_init(h->dsn[q].TV, st));
-            hylu_status s = enqueue_dense(h, h->dsn[q].TV, h->dsn[q].panels, search, st);
+            hylu_status s = enqueue_dense(h, h->dsn[q].TV, h->dsn[q].ops, nullptr, search, st);
             if (s != HYLU_OK) return s;
         }
         return HYLU_OK;
@@ -408,7 +551,7 @@ hylu_status enqueue_level_dense(hylu_handle h, int32_t l, bool search, hipStream
         const TailView& TV = h->dsn[q].TV;
         load[j] += (double)TV.mT * TV.mT * TV.nc;
         if (search) HIPCHK(launch_tail_init(TV, h->side[j]));
-        hylu_status s = enqueue_dense(h, TV, h->dsn[q].panels, search, h->side[j]);
+        hylu_status s = enqueue_dense(h, TV, h->dsn[q].ops, nullptr, search, h->side[j]);
         if (s != HYLU_OK) return s;
     }
     for (int j = 0; j < k; j++) {
@@ -476,7 +619,7 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
                                   T.pipe_maxm, h->tau, h->d_pert, search ? 1 : 0, st));
     }
     // dense tail: blocked right-looking LU, one row panel at a time
-    return enqueue_dense(h, h->TV, h->lay.panels, search, st);
+    return enqueue_dense(h, h->TV, h->tail_ops, h->d_tail_list, search, st);
 }
 
 // base solve in the factor precision: x = A^{-1} b (transpose 0) or A^{-T} b
@@ -629,6 +772,7 @@ hylu_status upload_device(hylu_handle h)
         UP(h->d_amap, L.amap); UP(h->d_asr, asr); UP(h->d_asc, asc);
         UP(h->d_rows, T.rows); UP(h->d_snodes, T.snodes); UP(h->d_tiles, T.tiles);
         UP(h->d_inv_off, h->inv_off); UP(h->d_inv_nodes, h->inv_nodes);
+        UP(h->d_tail_list, h->tail_list);
         h->d_uinv = dalloc(h, (size_t)std::max<int64_t>(h->inv_total, 1) * (h->fp32 ? 4 : 8));
         if (!h->d_uinv) return HYLU_ERR_OOM;
         D.uinv = h->d_uinv;
@@ -871,6 +1015,8 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                     q.panels.push_back({k, std::min(k + kWideChunk, L.m[v]), 0, L.m[v], 0});
                 for (int32_t k = 0; k < L.m[v]; k += 64)
                     q.spanels.push_back({k, std::min(k + 64, L.m[v]), 0, L.m[v], 0});
+                std::vector<uint32_t> none;
+                plan_dense(q.panels, L.m[v], L.W[v] - L.lw[v], nullptr, q.ops, none);
                 h->dsn.push_back(std::move(q));
             } else {
                 T.snodes.push_back(v);
@@ -885,6 +1031,17 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         T.maxm.push_back(mm);
         h->max_sn = std::max(h->max_sn, mm);
     }
+    // the dense tail's launches, block-sparse by its structural masks
+    h->tail_ops.clear();
+    h->tail_list.clear();
+    h->tail_flops = 0.0;
+    if (L.mT > 0) {
+        TailMasks M;
+        if (opt.tail_sparse) tail_masks(h->sym, nd, L, M);
+        plan_dense(L.panels, L.mT, L.mT, opt.tail_sparse ? &M : nullptr, h->tail_ops, h->tail_list);
+        for (const DenseOp& o : h->tail_ops) h->tail_flops += o.flops;
+    }
+    plog("tail plan");
     T.row_nt.assign(nl, 0);
     T.sn_nt.assign(nl, 0);
     T.node_level.assign(L.nnodes, 0);
@@ -990,6 +1147,7 @@ hylu_status hylu_default_options(hylu_options* o)
     o->sn_dense = 64;
     o->sn_tile = 0;
     o->sn_inverse = 1;
+    o->tail_sparse = 1;
     o->pipeline_rows = 0;
     return HYLU_OK;
 }
@@ -1368,7 +1526,9 @@ hylu_status hylu_get_info(hylu_handle h, hylu_info* o)
     o->pivot_tau = h->tau;
     o->tail_rows = h->lay.mT;
     o->tail_panels = (int32_t)h->lay.panels.size();
-    o->flops_issued = h->lay.flops_kernel;
+    // the dense tail counts with the products its block-sparse plan issues
+    const double mT = h->lay.mT;
+    o->flops_issued = h->lay.flops_kernel - (uint64_t)(2.0 * mT * mT * mT / 3.0) + (uint64_t)h->tail_flops;
     return HYLU_OK;
 }
 

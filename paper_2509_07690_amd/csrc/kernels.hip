@@ -1127,12 +1127,27 @@ __global__ __launch_bounds__(64 * NW) void k_tail_panel_lds4(DevLayout D, TailVi
 // blocks [nA, ...): trailing rows' multipliers (one thread per row)
 template <typename T>
 __global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ vals, int p0, int p1, int c1, int nA,
-                                                  int kb0, int kof)
+                                                  int kb0, int kof, const int32_t* __restrict__ bl)
 {
     __shared__ T M[kNB][kNB + 1];       // M[i][j] = X_{p0+i}[tpiv[p0+j]]
     __shared__ int64_t rowoff[kNB];
     __shared__ int piv[kNB];
     const int np = p1 - p0, tid = threadIdx.x;
+    // block list (structurally sparse tail): column blocks of U that hold
+    // entries, and every row block, flagged when its multipliers are all zero
+    int blk = blockIdx.x;
+    if (bl) {
+        const int e = bl[blockIdx.x];
+        blk = e & ~kTrsmZero;
+        if (e & kTrsmZero) {
+            const int r = p1 + (blk - nA) * 64 + tid;
+            if (r < TV.mT) {
+                T* lb = reinterpret_cast<T*>(TV.lbuf);
+                for (int b = 0; b < np; b++) lb[(int64_t)(kof + b) * TV.mT + r] = T(0);
+            }
+            return;
+        }
+    }
     for (int i = tid; i < np; i += 64) { rowoff[i] = TV.trow[p0 + i]; piv[i] = TV.tpiv[p0 + i]; }
     __syncthreads();
     if (tid < np) {                          // column tid of M: one independent load per panel row
@@ -1144,8 +1159,8 @@ __global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ v
         for (int i = 0; i < kNB; i++) M[i][tid] = tmp[i];
     }
     __syncthreads();
-    if ((int)blockIdx.x < nA) {
-        const int c = c1 + blockIdx.x * 64 + tid;
+    if (blk < nA) {
+        const int c = c1 + blk * 64 + tid;
         if (c >= TV.nc) return;
         T colv[kNB];
 #pragma unroll
@@ -1159,7 +1174,7 @@ __global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ v
             }
         }
     } else {
-        const int r = p1 + (blockIdx.x - nA) * 64 + tid;
+        const int r = p1 + (blk - nA) * 64 + tid;
         if (r >= TV.mT) return;
         T* Xr = vals + TV.trow[r];
         T* lb = reinterpret_cast<T*>(TV.lbuf);
@@ -1204,18 +1219,28 @@ template <> struct Mfma<float> {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ vals, int kb0, int K, int rb, int re,
-                                                   int cg0, int mstep, int gx, int gy, int swz, int gp0, int gnp)
+                                                   int cg0, int mstep, int gx, int gy, int swz, int gp0, int gnp,
+                                                   const uint32_t* __restrict__ tl, int kb1, int kb2, int kb3)
 {
     typedef typename Mfma<T>::v4 v4;
+    static_assert(kGroup == 4, "the K ranges below assume four panels per group");
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int mT = re, nc = TV.nc, lds = TV.mT;
     // tile of this workgroup.  Workgroups go to the 8 XCDs round robin by
     // index; with swz each XCD takes a quarter of the tile rows and half of
-    // the tile columns, so the operand tiles it reads fit its own L2.
-    int tx, ty;
+    // the tile columns, so the operand tiles it reads fit its own L2.  With a
+    // tile list (structurally sparse tail) the list is already in that order
+    // and each entry carries the group panels whose products are nonzero.
+    int tx, ty, pmask = 0xF;
     {
         const int L = blockIdx.x;
-        if (swz) {
+        if (tl) {
+            const uint32_t e = tl[L];
+            if (e == kTileNone) return;
+            ty = (int)(e >> 16);
+            tx = (int)((e >> 4) & 0xFFF);
+            pmask = (int)(e & 0xF);
+        } else if (swz) {
             const int xcd = L & 7, k = L >> 3;
             const int rb0 = (xcd >> 1) * gy / 4, rb1 = ((xcd >> 1) + 1) * gy / 4;
             const int cb0 = (xcd & 1) * gx / 2, cb1 = ((xcd & 1) + 1) * gx / 2;
@@ -1261,20 +1286,32 @@ __global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ 
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = v4{T(0), T(0), T(0), T(0)};
     const T* arow = lb + (int64_t)lk * lds + r0 + li;
+    // K in the group's panel ranges [kbnd[j], kbnd[j+1]) whose bit is set, in
+    // steps of 4 from 0 as in the dense sweep, so the products summed are the
+    // same: a skipped step has only exact zeros (rows without L entries in the
+    // panel, or columns without U entries)
+    const int kbnd[kGroup + 1] = {0, kb1, kb2, kb3, K};
+    int next = 0;
+#pragma unroll
+    for (int j = 0; j < kGroup; j++) {
+        if (!((pmask >> j) & 1)) continue;
+        const int ks1 = (kbnd[j + 1] + 3) >> 2;
 #pragma unroll 4
-    for (int ks = 0; ks * 4 < K; ks++) {
-        const int k = ks * 4 + lk;
-        const bool kok = k < K;
-        const T* ap = arow + (int64_t)ks * 4 * lds;
-        const T a0 = (kok && rok0) ? ap[0] : T(0);
-        const T a1 = (kok && rok1) ? ap[16] : T(0);
-        const T* bp = vals + (kok ? TV.trow[kb0 + k] : 0);
-        const T b0 = (kok && cok0) ? bp[cb] : T(0);
-        const T b1 = (kok && cok1) ? bp[cb1] : T(0);
-        acc[0][0] = Mfma<T>::mma(a0, b0, acc[0][0]);
-        acc[0][1] = Mfma<T>::mma(a0, b1, acc[0][1]);
-        acc[1][0] = Mfma<T>::mma(a1, b0, acc[1][0]);
-        acc[1][1] = Mfma<T>::mma(a1, b1, acc[1][1]);
+        for (int ks = max(kbnd[j] >> 2, next); ks < ks1; ks++) {
+            const int k = ks * 4 + lk;
+            const bool kok = k < K;
+            const T* ap = arow + (int64_t)ks * 4 * lds;
+            const T a0 = (kok && rok0) ? ap[0] : T(0);
+            const T a1 = (kok && rok1) ? ap[16] : T(0);
+            const T* bp = vals + (kok ? TV.trow[kb0 + k] : 0);
+            const T b0 = (kok && cok0) ? bp[cb] : T(0);
+            const T b1 = (kok && cok1) ? bp[cb1] : T(0);
+            acc[0][0] = Mfma<T>::mma(a0, b0, acc[0][0]);
+            acc[0][1] = Mfma<T>::mma(a0, b1, acc[0][1]);
+            acc[1][0] = Mfma<T>::mma(a1, b0, acc[1][0]);
+            acc[1][1] = Mfma<T>::mma(a1, b1, acc[1][1]);
+        }
+        next = max(next, ks1);
     }
 #pragma unroll
     for (int i = 0; i < 2; i++)
@@ -1856,28 +1893,39 @@ hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, v
 }
 
 hipError_t launch_tail_trsm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t c1, int32_t kb0,
-                            int32_t kof, hipStream_t st)
+                            int32_t kof, const int32_t* blocks, int32_t nblocks, hipStream_t st)
 {
     int nA = (int)nblk(std::max(T.nc - c1, 0), 64);
     int nB = (int)nblk(std::max(T.mT - p1, 0), 64);
-    if (nA + nB == 0) return hipSuccess;
+    const int grid = blocks ? nblocks : nA + nB;
+    if (grid <= 0) return hipSuccess;
     if (kof < 0 || kof + (p1 - p0) > kNB * kGroup) return hipErrorInvalidValue;
-    if (fp32) hipLaunchKernelGGL(k_tail_trsm<float>, dim3(nA + nB), dim3(64), 0, st, T, (float*)vals, p0, p1, c1, nA, kb0, kof);
-    else hipLaunchKernelGGL(k_tail_trsm<double>, dim3(nA + nB), dim3(64), 0, st, T, (double*)vals, p0, p1, c1, nA, kb0, kof);
+    if (fp32) hipLaunchKernelGGL(k_tail_trsm<float>, dim3(grid), dim3(64), 0, st, T, (float*)vals, p0, p1, c1, nA, kb0, kof, blocks);
+    else hipLaunchKernelGGL(k_tail_trsm<double>, dim3(grid), dim3(64), 0, st, T, (double*)vals, p0, p1, c1, nA, kb0, kof, blocks);
     return hipGetLastError();
 }
 
 hipError_t launch_tail_gemm(bool fp32, const TailView& T, void* vals, int32_t kb0, int32_t K, int32_t rb, int32_t re,
-                            int32_t cg0, int32_t mstep, int32_t gp0, int32_t gnp, hipStream_t st)
+                            int32_t cg0, int32_t mstep, int32_t gp0, int32_t gnp, const uint32_t* tiles,
+                            int32_t ntiles, const int32_t* kbnd, hipStream_t st)
 {
     int gx = gnp > 0 ? (int)nblk(gnp, 64) : (int)nblk(std::max(T.nc - cg0, 0), 64);
     int gy = (int)nblk(std::max(re - rb, 0), 64);
     if (gx == 0 || gy == 0 || K <= 0) return hipSuccess;
     if (K > kNB * kGroup || re > T.mT || gnp > kNB) return hipErrorInvalidValue;
+    int kb1 = K, kb2 = K, kb3 = K;
+    if (kbnd) {
+        kb1 = kbnd[1]; kb2 = kbnd[2]; kb3 = kbnd[3];
+        if (kbnd[0] != 0 || kb1 < 0 || kb1 > kb2 || kb2 > kb3 || kb3 > K) return hipErrorInvalidValue;
+    }
     const int swz = gy >= 8 && gx >= 4;
-    const unsigned grid = swz ? 8u * (unsigned)((gy + 3) / 4) * (unsigned)((gx + 1) / 2) : (unsigned)(gx * gy);
-    if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(grid), dim3(256), 0, st, T, (float*)vals, kb0, K, rb, re, cg0, mstep, gx, gy, swz, gp0, gnp);
-    else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(grid), dim3(256), 0, st, T, (double*)vals, kb0, K, rb, re, cg0, mstep, gx, gy, swz, gp0, gnp);
+    unsigned grid = swz ? 8u * (unsigned)((gy + 3) / 4) * (unsigned)((gx + 1) / 2) : (unsigned)(gx * gy);
+    if (tiles) {
+        if (ntiles <= 0) return hipSuccess;
+        grid = (unsigned)ntiles;
+    }
+    if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(grid), dim3(256), 0, st, T, (float*)vals, kb0, K, rb, re, cg0, mstep, gx, gy, swz, gp0, gnp, tiles, kb1, kb2, kb3);
+    else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(grid), dim3(256), 0, st, T, (double*)vals, kb0, K, rb, re, cg0, mstep, gx, gy, swz, gp0, gnp, tiles, kb1, kb2, kb3);
     return hipGetLastError();
 }
 

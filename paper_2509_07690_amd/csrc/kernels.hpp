@@ -95,13 +95,22 @@ constexpr int kGroup = 4;
 // panel [p0, p1): U right of the window, and the multipliers of the rows
 // below (their pivot columns already carry the group's earlier panels),
 // written to lbuf rows kof.. (kb0: first panel row of the group, unused here)
+// blocks (optional, device): the blocks to run, indices into [0, nA + nB) with
+// nA = column blocks of U right of the window, nB = row blocks below the panel;
+// a row block flagged kTrsmZero only writes zero multipliers to lbuf
+constexpr int32_t kTrsmZero = 1 << 30;
 hipError_t launch_tail_trsm(bool fp32, const TailView& T, void* vals, int32_t p0, int32_t p1, int32_t c1, int32_t kb0,
-                            int32_t kof, hipStream_t st);
+                            int32_t kof, const int32_t* blocks, int32_t nblocks, hipStream_t st);
 // rows [rb, re): X[r][c] -= sum_{k < K} lbuf[k][r] X[kb0 + k][c] over the
 // columns from cg0 still unpivoted before step mstep, or (gnp > 0) over the
-// pivot columns of panel rows gp0 .. gp0+gnp
+// pivot columns of panel rows gp0 .. gp0+gnp.  tiles (optional, device):
+// ntiles entries (ty << 16) | (tx << 4) | panel mask, or kTileNone; kbnd
+// (host, optional): the K offsets 0 <= kbnd[1] <= kbnd[2] <= kbnd[3] <= K of
+// the group's panels the mask bits stand for.
+constexpr uint32_t kTileNone = 0xFFFFFFFFu;
 hipError_t launch_tail_gemm(bool fp32, const TailView& T, void* vals, int32_t kb0, int32_t K, int32_t rb, int32_t re,
-                            int32_t cg0, int32_t mstep, int32_t gp0, int32_t gnp, hipStream_t st);
+                            int32_t cg0, int32_t mstep, int32_t gp0, int32_t gnp, const uint32_t* tiles,
+                            int32_t ntiles, const int32_t* kbnd, hipStream_t st);
 // dense tail solves; y/x/h/w are the solve work vectors (n x nrhs, factor precision)
 hipError_t launch_tail_lext(bool fp32, const DevLayout& D, const void* vals, int32_t tail_node0, int32_t t0,
                             void* y, int32_t nrhs, hipStream_t st);

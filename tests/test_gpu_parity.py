@@ -255,3 +255,43 @@ def test_fp32_refactor_fresh_values_full_circuit(hylu):
         eta, _ = ok.backward_error(w.b[:, 0], x)
         print(f"refactor {r}: eta {eta:.2e} ir {h.info()['ir_iters']} perturbed {h.info()['n_perturbed']}")
         assert eta <= 1e-10 and np.abs(x - w.x_true[:, 0]).max() <= 1e-9
+
+
+@pytest.mark.parametrize("case", ["config0_amd", "config0_nd", "circuit", "grid3d", "circuit_fp32"])
+def test_sparse_tail_bit_identical(hylu, case):
+    """The block-sparse dense tail skips only 64 x 64 products and triangular
+    solves that are exactly zero by structure, and sums the rest in the dense
+    order: its factors, pivots and solution equal the dense tail's to the bit,
+    on a first factorisation (pivot search) and a refactorisation."""
+    if case.startswith("config0"):
+        w = synth.config(0)
+        A, b, A2 = w.A, w.b[:, 0], synth.config(0).A
+        A2 = type(A2)(A2.n, A2.row_ptr, A2.col, A2.val * (1.0 + 0.1 * np.sin(np.arange(A2.nnz))))
+        opts = dict(ordering=case.split("_")[1], dense_tail=0.3)
+    elif case.startswith("circuit"):
+        w = synth.circuit_powerlaw(20000)
+        A, b, A2 = w.A, w.b[:, 0], w.revalue(1).A
+        opts = dict(amd_dense=0.1, dense_tail=0.05)
+        if case.endswith("fp32"):
+            opts["precision"] = "fp32"
+    else:
+        w = synth.convdiff3d_7pt(16)
+        A, b, A2 = w.A, w.b[:, 0], synth.grid_values(w.A, 5, 4.0)
+        opts = dict(ordering="nd", dense_tail=0.05, sn_dense=32)
+    out = []
+    for sparse in (0, 1):
+        print(f"[case] {case} tail_sparse={sparse} n={A.n}", flush=True)
+        h = hylu.Handle(A.row_ptr, A.col, A.val, tail_sparse=sparse, **opts)
+        assert h.info()["tail_rows"] > 0
+        h.factorize(dev(A.val))
+        x = h.solve(dev(b)).cpu().numpy()
+        f1 = h.factors_raw()
+        h.refactor(dev(A2.val))
+        torch.cuda.synchronize()
+        f2 = h.factors_raw()
+        out.append((h.info()["flops_issued"], f1, f2, x))
+    assert out[1][0] < out[0][0]
+    for k in ("vals", "piv"):
+        assert np.array_equal(out[0][1][k], out[1][1][k]), k
+        assert np.array_equal(out[0][2][k], out[1][2][k]), k
+    assert np.array_equal(out[0][3], out[1][3])
