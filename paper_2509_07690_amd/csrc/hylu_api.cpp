@@ -112,6 +112,8 @@ struct hylu_handle_s {
     std::vector<DenseOp> tail_ops;          // the dense tail's launches, block-sparse when its masks are known
     std::vector<uint32_t> tail_list;        // their tile / block lists
     uint32_t* d_tail_list = nullptr;
+    int32_t* d_tsp = nullptr;               // the tail's solve panels (p0, p1 pairs)
+    void* d_tinv = nullptr;                 // inverses of their diagonal blocks (L and U, 64 x 64 each)
     double tail_flops = 0.0;
     std::vector<DenseSn> dsn;
     std::vector<int32_t> dsn_ptr;           // per factor level into dsn
@@ -618,8 +620,14 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
                launch_factor_pipe(h->fp32, h->D, h->PC, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.pipe_maxW,
                                   T.pipe_maxm, h->tau, h->d_pert, search ? 1 : 0, st));
     }
-    // dense tail: blocked right-looking LU, one row panel at a time
-    return enqueue_dense(h, h->TV, h->tail_ops, h->d_tail_list, search, st);
+    // dense tail: blocked right-looking LU, one row panel at a time, then the
+    // inverses of the solve panels' diagonal blocks
+    hylu_status sd = enqueue_dense(h, h->TV, h->tail_ops, h->d_tail_list, search, st);
+    if (sd != HYLU_OK || h->lay.mT == 0) return sd;
+    const double ns = (double)h->lay.spanels.size();
+    LAUNCH(C_PANEL, es * ns * 3.0 * kNB * kNB, ns * 2.0 * kNB * kNB * kNB / 3.0,
+           launch_tail_dinv(h->fp32, h->TV, h->vals, h->d_tsp, (int32_t)h->lay.spanels.size(), h->d_tinv, st));
+    return HYLU_OK;
 }
 
 // base solve in the factor precision: x = A^{-1} b (transpose 0) or A^{-T} b
@@ -664,9 +672,24 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
             LAUNCH(C_TSOLVE, 0, 0, launch_tail_lext(f, h->D, h->vals, L.tail_node0, L.t0, h->d_y, nrhs, st));
-            for (const Layout::Panel& P : L.spanels) LAUNCH(C_TSOLVE, 0, 0, launch_tail_fwd(f, h->TV, h->vals, P.p0, P.p1, n, h->d_y, nrhs, st));
-            for (size_t k = L.spanels.size(); k-- > 0;)
-                LAUNCH(C_TSOLVE, 0, 0, launch_tail_bwd(f, h->TV, h->vals, L.spanels[k].p0, L.spanels[k].p1, n, h->d_y, h->d_z, nrhs, st));
+            // one launch per solve panel: its contribution to the rows after it
+            // and the next panel's diagonal solve (with the block inverses)
+            const std::vector<Layout::Panel>& SP = L.spanels;
+            const int32_t ns = (int32_t)SP.size();
+            const size_t es = f ? 4 : 8;
+            auto inv = [&](int32_t k, int kind) {
+                return (const void*)((const char*)h->d_tinv + ((size_t)2 * k + kind) * kNB * kNB * es);
+            };
+            LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, 0, 0, SP[0].p0, SP[0].p1, inv(0, 0), n, h->d_y,
+                                                    h->d_y, nrhs, 0, st));
+            for (int32_t k = 0; k + 1 < ns; k++)
+                LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, SP[k].p0, SP[k].p1, SP[k + 1].p0, SP[k + 1].p1,
+                                                        inv(k + 1, 0), n, h->d_y, h->d_y, nrhs, 0, st));
+            LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, 0, 0, SP[ns - 1].p0, SP[ns - 1].p1, inv(ns - 1, 1), n,
+                                                    h->d_y, h->d_z, nrhs, 1, st));
+            for (int32_t k = ns - 1; k > 0; k--)
+                LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, SP[k].p0, SP[k].p1, SP[k - 1].p0, SP[k - 1].p1,
+                                                        inv(k - 1, 1), n, h->d_y, h->d_z, nrhs, 1, st));
         }
         s = levels(1, [&](const int32_t* nodes, int32_t c, size_t) { return launch_usolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, st); });
         if (s != HYLU_OK) return s;
@@ -773,6 +796,13 @@ hylu_status upload_device(hylu_handle h)
         UP(h->d_rows, T.rows); UP(h->d_snodes, T.snodes); UP(h->d_tiles, T.tiles);
         UP(h->d_inv_off, h->inv_off); UP(h->d_inv_nodes, h->inv_nodes);
         UP(h->d_tail_list, h->tail_list);
+        {
+            std::vector<int32_t> sp;
+            for (const Layout::Panel& P : L.spanels) { sp.push_back(P.p0); sp.push_back(P.p1); }
+            UP(h->d_tsp, sp);
+            h->d_tinv = dalloc(h, (size_t)std::max<size_t>(L.spanels.size(), 1) * 2 * kNB * kNB * (h->fp32 ? 4 : 8));
+            if (!h->d_tinv) return HYLU_ERR_OOM;
+        }
         h->d_uinv = dalloc(h, (size_t)std::max<int64_t>(h->inv_total, 1) * (h->fp32 ? 4 : 8));
         if (!h->d_uinv) return HYLU_ERR_OOM;
         D.uinv = h->d_uinv;

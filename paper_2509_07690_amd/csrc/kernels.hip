@@ -797,7 +797,6 @@ __global__ void k_grad(int32_t n, const int64_t* __restrict__ rp, const int32_t*
 //   k_tail_gemm:  the trailing update of every still-unpivoted column.
 // ----------------------------------------------------------------------------
 
-constexpr int kNB = 64;   // panel rows
 
 __global__ void k_tail_init(int32_t mT, int32_t* __restrict__ tstep)
 {
@@ -1546,6 +1545,141 @@ __global__ __launch_bounds__(64) void k_tail_tri(TailView TV, const T* __restric
     }
 }
 
+// inverses of the diagonal blocks of the solve panels: for panel s = [p0, p1)
+// with M[i][j] = X_{p0+i}[tpiv[p0+j]] (L strictly below the diagonal, U_st on
+// and above it, both in pivot order), kind 0 writes (I + L)^-1 and kind 1
+// U^-1, column-major 64 x 64 at out + (2 s + kind) * 64 * 64.  Thread j
+// substitutes for column j.
+template <typename T>
+__global__ __launch_bounds__(64) void k_tail_dinv(TailView TV, const T* __restrict__ vals, const int32_t* __restrict__ sp,
+                                                  T* __restrict__ out)
+{
+    __shared__ T M[kNB][kNB + 1];
+    __shared__ T X[kNB][kNB + 1];
+    __shared__ int piv[kNB];
+    __shared__ int64_t ro[kNB];
+    const int s = blockIdx.x >> 1, kind = blockIdx.x & 1;
+    const int p0 = sp[2 * s], np = sp[2 * s + 1] - p0;
+    const int lane = threadIdx.x;
+    if (lane < np) { piv[lane] = TV.tpiv[p0 + lane]; ro[lane] = TV.trow[p0 + lane]; }
+    __syncthreads();
+    if (lane < np) {
+        const int pc = piv[lane];
+        T tmp[kNB];
+#pragma unroll
+        for (int i = 0; i < kNB; i++) tmp[i] = i < np ? vals[ro[i] + pc] : T(0);
+#pragma unroll
+        for (int i = 0; i < kNB; i++) M[i][lane] = tmp[i];
+    }
+    __syncthreads();
+    const int j = lane;
+    for (int i = 0; i < kNB; i++) X[i][j] = T(0);
+    if (j < np) {
+        if (kind == 0) {
+            X[j][j] = T(1);
+            for (int i = j + 1; i < np; i++) {
+                T acc = T(0);
+                for (int k = j; k < i; k++) acc += M[i][k] * X[k][j];
+                X[i][j] = -acc;
+            }
+        } else {
+            X[j][j] = T(1) / M[j][j];
+            for (int i = j - 1; i >= 0; i--) {
+                T acc = T(0);
+                for (int k = i + 1; k <= j; k++) acc += M[i][k] * X[k][j];
+                X[i][j] = -acc / M[i][i];
+            }
+        }
+    }
+    __syncthreads();
+    T* O = out + ((int64_t)2 * s + kind) * kNB * kNB;
+    for (int idx = lane; idx < kNB * kNB; idx += 64) O[idx] = X[idx & (kNB - 1)][idx >> 6];
+}
+
+// one launch per solve panel of the tail: the rows past the next panel take
+// the current panel [p0, p1)'s contribution (one wavefront per row, as
+// k_tail_gemv), and workgroup 0 brings the next panel [q0, q1)'s rows up to
+// date and solves its diagonal block with its inverse inv (column-major).
+// mode 0: forward with L, ascending, y in place; mode 1: backward with U,
+// descending, the solution to x at the pivot columns.  p0 == p1: the next
+// panel's diagonal solve only.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restrict__ vals, int p0, int p1, int q0, int q1,
+                                                   const T* __restrict__ inv, int n, T* __restrict__ y,
+                                                   T* __restrict__ x, int nrhs, int mode, int first, int count)
+{
+    __shared__ T ys[kNB];
+    __shared__ T part[4][kNB];
+    __shared__ int64_t rowq[kNB];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int np = p1 - p0, nq = q1 - q0, t0 = TV.t0;
+    const int b = p0 + lane;
+    const int pb = lane < np ? TV.tpiv[b] : 0;
+    if (blockIdx.x == 0) {
+        // every load of a phase is issued before its first use: wavefront w
+        // takes the next panel's rows w, w+4, ..; the inverse's columns are
+        // split the same way and the four partial sums combined in LDS
+        const int t = threadIdx.x;
+        if (t < nq) rowq[t] = TV.trow[q0 + t];
+        __syncthreads();
+        T c[kNB / 4];
+#pragma unroll
+        for (int q = 0; q < kNB / 4; q++) {
+            const int i = wv + 4 * q;
+            c[q] = (i < nq && lane < np) ? vals[rowq[i] + pb] : T(0);
+        }
+        for (int r = 0; r < nrhs; r++) {
+            T* yr = y + (int64_t)r * n + t0;
+            T* xr = x + (int64_t)r * n + t0;
+            const T v = lane < np ? (mode == 0 ? yr[b] : xr[pb]) : T(0);
+            if (t < nq) ys[t] = yr[q0 + t];
+            __syncthreads();
+            if (np > 0) {
+#pragma unroll
+                for (int q = 0; q < kNB / 4; q++) {
+                    const int i = wv + 4 * q;
+                    if (i >= nq) break;
+                    const T acc = wave_sum(c[q] * v);
+                    if (lane == 0) ys[i] -= acc;
+                }
+            }
+            __syncthreads();
+            T iv[kNB / 4];
+#pragma unroll
+            for (int q = 0; q < kNB / 4; q++) {
+                const int jj = wv + 4 * q;
+                iv[q] = (jj < nq && lane < nq) ? inv[jj * kNB + lane] : T(0);
+            }
+            T acc = T(0);
+#pragma unroll
+            for (int q = 0; q < kNB / 4; q++) {
+                const int jj = wv + 4 * q;
+                if (jj < nq) acc += iv[q] * ys[jj];
+            }
+            part[wv][lane] = acc;
+            __syncthreads();
+            if (t < nq) {
+                const T o = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
+                if (mode == 0) yr[q0 + t] = o;
+                else xr[TV.tpiv[q0 + t]] = o;
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    const int k = (blockIdx.x - 1) * 4 + wv;
+    if (k >= count) return;
+    const int e = first + k;
+    const T coef = lane < np ? vals[TV.trow[e] + pb] : T(0);
+    for (int r = 0; r < nrhs; r++) {
+        T* yr = y + (int64_t)r * n + t0;
+        const T* xr = x + (int64_t)r * n + t0;
+        const T v = lane < np ? (mode == 0 ? yr[b] : xr[pb]) : T(0);
+        const T acc = wave_sum(coef * v);
+        if (lane == 0) yr[e] -= acc;
+    }
+}
+
 // the panel's contribution to the rest of the tail, one wavefront per row or
 // column: mode 0 rows r >= p1: y_r -= sum_b X_r[piv b] y_b
 //         mode 1 rows r < p0:  y_r -= sum_b X_r[piv b] x[piv b]
@@ -1983,6 +2117,35 @@ hipError_t launch_tail_ut(bool fp32, const TailView& T, const void* vals, int32_
 {
     if (fp32) return tail_step<float>(T, (const float*)vals, p0, p1, n, (float*)h, (float*)w, nrhs, 2, st);
     return tail_step<double>(T, (const double*)vals, p0, p1, n, (double*)h, (double*)w, nrhs, 2, st);
+}
+
+hipError_t launch_tail_dinv(bool fp32, const TailView& T, const void* vals, const int32_t* spanels, int32_t nsp,
+                            void* out, hipStream_t st)
+{
+    if (nsp <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_tail_dinv<float>, dim3(2 * nsp), dim3(64), 0, st, T, (const float*)vals, spanels, (float*)out);
+    else hipLaunchKernelGGL(k_tail_dinv<double>, dim3(2 * nsp), dim3(64), 0, st, T, (const double*)vals, spanels, (double*)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_step(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t q0, int32_t q1,
+                            const void* inv, int32_t n, void* y, void* x, int32_t nrhs, int32_t mode, hipStream_t st)
+{
+    const int np = p1 - p0, nq = q1 - q0;
+    if (np < 0 || np > kNB || nq <= 0 || nq > kNB || (mode != 0 && mode != 1)) return hipErrorInvalidValue;
+    if (np > 0 && (mode == 0 ? q0 != p1 : q1 != p0)) return hipErrorInvalidValue;
+    if (q0 < 0 || q1 > T.mT) return hipErrorInvalidValue;
+    int first = 0, count = 0;
+    if (np > 0) {
+        if (mode == 0) { first = q1; count = T.mT - q1; }
+        else { first = 0; count = q0; }
+    }
+    const unsigned grid = 1u + nblk(count, 4);
+    if (fp32) hipLaunchKernelGGL(k_tail_step<float>, dim3(grid), dim3(256), 0, st, T, (const float*)vals, p0, p1, q0, q1,
+                                 (const float*)inv, n, (float*)y, (float*)x, nrhs, mode, first, count);
+    else hipLaunchKernelGGL(k_tail_step<double>, dim3(grid), dim3(256), 0, st, T, (const double*)vals, p0, p1, q0, q1,
+                            (const double*)inv, n, (double*)y, (double*)x, nrhs, mode, first, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_tail_lt(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,

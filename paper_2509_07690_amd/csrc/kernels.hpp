@@ -91,6 +91,7 @@ hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, v
 // group in one trailing update (K up to kGroup * 64), so the trailing matrix is
 // read and written once per group instead of once per panel.  lbuf holds
 // kGroup * 64 rows (k-major), panel j of a group at rows kof..kof+np.
+constexpr int kNB = 64;      // rows of a dense-view panel (solves) and of its diagonal block
 constexpr int kGroup = 4;
 // panel [p0, p1): U right of the window, and the multipliers of the rows
 // below (their pivot columns already carry the group's earlier panels),
@@ -116,6 +117,16 @@ hipError_t launch_tail_lext(bool fp32, const DevLayout& D, const void* vals, int
                             void* y, int32_t nrhs, hipStream_t st);
 hipError_t launch_tail_utext(bool fp32, const DevLayout& D, const TailView& T, const void* vals, void* h,
                              const void* w, int32_t nrhs, hipStream_t st);
+// inverses of the diagonal blocks of the nsp solve panels (spanels: device
+// pairs p0, p1): (I + L)^-1 and U^-1 in pivot order, 64 x 64 column-major each,
+// panel s's at out + (2 s + {0, 1}) * 64 * 64 values
+hipError_t launch_tail_dinv(bool fp32, const TailView& T, const void* vals, const int32_t* spanels, int32_t nsp,
+                            void* out, hipStream_t st);
+// one step of the tail's forward (mode 0) or backward (mode 1) solve: the
+// contribution of panel [p0, p1) to every row still to come, and the diagonal
+// solve of the next panel [q0, q1) (adjacent to it) with its inverse inv
+hipError_t launch_tail_step(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t q0, int32_t q1,
+                            const void* inv, int32_t n, void* y, void* x, int32_t nrhs, int32_t mode, hipStream_t st);
 hipError_t launch_tail_fwd(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
                            void* y, int32_t nrhs, hipStream_t st);
 hipError_t launch_tail_bwd(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
