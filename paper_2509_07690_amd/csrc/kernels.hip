@@ -1122,6 +1122,62 @@ __global__ __launch_bounds__(64 * NW) void k_tail_panel_lds4(DevLayout D, TailVi
     if (tid == 0 && npert > 0) atomicAdd(pert, npert);
 }
 
+// value of v in lane l (l the same in every lane), all lanes active
+__device__ __forceinline__ double rlane(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float rlane(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+
+// refactorisation of a panel whose pivot window is its own rows (pivots
+// known): one wavefront, lane r holding row r of the window in registers in
+// pivot order.  At step a every lane reads row a's values by readlane (all
+// lanes active) and the rows below form their multiplier and update their
+// copy: the operations of k_tail_panel_lds4 in the same order, without a
+// block barrier per step.
+template <typename T>
+__global__ __launch_bounds__(64) void k_tail_panel_reg(DevLayout D, TailView TV, T* __restrict__ vals, int p0, int p1,
+                                                       T tau, int32_t* __restrict__ pert)
+{
+    const int lane = threadIdx.x;
+    const int np = p1 - p0;
+    const bool mine = lane < np;
+    const int64_t ro = mine ? TV.trow[p0 + lane] : 0;
+    T x[kNB];
+#pragma unroll
+    for (int j = 0; j < kNB; j++) x[j] = (mine && j < np) ? vals[ro + TV.tpiv[p0 + j]] : T(0);
+    int npert = 0;
+#pragma unroll
+    for (int a = 0; a < kNB; a++) {
+        if (a < np) {
+            T d = rlane(x[a], a);
+            if (tabs(d) < tau) d = d < T(0) ? -tau : tau;
+            if (lane == a && x[a] != d) { x[a] = d; npert++; }
+            const bool act = mine && lane > a;
+            T l = T(0);
+            if (act) l = x[a] / d;
+#pragma unroll
+            for (int j = a + 1; j < kNB; j++) {
+                const T u = rlane(x[j], a);
+                if (act) x[j] -= l * u;
+            }
+            if (act) x[a] = l;
+        }
+    }
+    if (mine) {
+#pragma unroll
+        for (int j = 0; j < kNB; j++)
+            if (j < np) vals[ro + TV.tpiv[p0 + j]] = x[j];
+        const int a = p0 + lane, p = TV.tpiv[a];
+        TV.tstep[p] = a;
+        D.pl[TV.t0 + a] = p - TV.tlo[a];
+        D.qinv[TV.t0 + p] = TV.t0 + a;
+    }
+    if (npert > 0) atomicAdd(pert, npert);
+}
+
 // blocks [0, nA): panel rows' U for columns >= c1 (one thread per column);
 // blocks [nA, ...): trailing rows' multipliers (one thread per row)
 template <typename T>
@@ -2005,7 +2061,10 @@ hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, v
     if (p1 - p0 > kNB || p1 <= p0) return hipErrorInvalidValue;
     size_t es = fp32 ? sizeof(float) : sizeof(double);
     size_t sh = (size_t)(p1 - p0) * (c1 - c0) * es;
-    if (c1 - c0 <= 64) {
+    if (!search && c0 == p0 && c1 == p1) {
+        if (fp32) hipLaunchKernelGGL(k_tail_panel_reg<float>, dim3(1), dim3(64), 0, st, D, T, (float*)vals, p0, p1, (float)tau, pert);
+        else hipLaunchKernelGGL(k_tail_panel_reg<double>, dim3(1), dim3(64), 0, st, D, T, (double*)vals, p0, p1, tau, pert);
+    } else if (c1 - c0 <= 64) {
         if (fp32) hipLaunchKernelGGL((k_tail_panel_lds4<float, 8>), dim3(1), dim3(512), sh, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
         else hipLaunchKernelGGL((k_tail_panel_lds4<double, 8>), dim3(1), dim3(512), sh, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
     } else {
