@@ -54,6 +54,7 @@ def main():
     ap.add_argument("--sn-dense", type=int, default=64)
     ap.add_argument("--sn-inverse", type=int, default=1)
     ap.add_argument("--tail-sparse", type=int, default=1)
+    ap.add_argument("--side-rows", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -76,7 +77,8 @@ def main():
     t0 = time.time()
     h = hylu.Handle(A0.row_ptr, A0.col, A0.val, precision=args.precision, amd_dense=args.amd_dense,
                     dense_tail=args.dense_tail, pipeline_rows=args.pipeline_rows, sn_dense=args.sn_dense,
-                    sn_inverse=args.sn_inverse, tail_sparse=args.tail_sparse)
+                    sn_inverse=args.sn_inverse, tail_sparse=args.tail_sparse,
+                    side_rows=args.side_rows)
     t_analyze = time.time() - t0
     info = h.info()
     log(f"analyze {t_analyze:.1f}s: F={info['flops']:.3e} nnz(L+U)={info['nnz_l'] + info['nnz_u']:.3e} "

@@ -57,6 +57,8 @@ struct LevelTasks {
     std::vector<int32_t> maxm;
     std::vector<int32_t> rows, snodes;
     std::vector<int32_t> row_nt, sn_nt;  // per level: threads per row / per supernode (0: built-in rule)
+    std::vector<int32_t> row_stage;      // per level: source entries staged per batch by the row kernel
+    std::vector<int32_t> row_cap;        // per level: widest row whose accumulator sits in LDS
     std::vector<int64_t> tile_ptr;        // per level into tiles (pairs: node, first local row)
     std::vector<int32_t> tiles;
     int32_t tune_rows = 0, tune_sn = 0;  // when nonzero, every level uses this (autotuner trials)
@@ -353,6 +355,11 @@ hylu_status ensure_tlists(hylu_handle h)
 
 // blocked right-looking LU of a dense view, one row panel at a time
 constexpr int32_t kGroupMinRows = 2048;
+// a factor level of fewer rows than this counts as narrow: deferred rows may
+// join its launch on the CUs it leaves idle
+constexpr int32_t kSideNarrowRows = 256;
+// row accumulators in LDS: up to this width by default, wider in narrow levels
+constexpr int32_t kRowCapSmall = 4096, kRowCapBig = 10240;
 // supernodes of at least this many rows (and at most 64) take the
 // four-wavefront forward-solve kernel
 constexpr int32_t kLsolveSnMin = 8;
@@ -578,7 +585,7 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
         int64_t r0 = T.row_ptr[l], r1 = T.row_ptr[l + 1];
         LAUNCH(C_ROWS, h->lvl_bytes[l] * es / 8.0, h->lvl_flops[l],
                launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.maxW[l], h->tau, h->d_pert,
-                                  T.tune_rows ? T.tune_rows : T.row_nt[l], st));
+                                  T.tune_rows ? T.tune_rows : T.row_nt[l], T.row_stage[l], T.row_cap[l], st));
         if (T.tile_ptr[l + 1] > T.tile_ptr[l])
             LAUNCH(C_TILE, h->tile_bytes[l] * es / 8.0, h->tile_flops[l],
                    launch_factor_tile(h->fp32, h->D, h->vals, h->d_tiles + 2 * T.tile_ptr[l],
@@ -997,6 +1004,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     // so they need not sit on the chain of narrow levels (nor need the other
     // nodes that feed nobody)
     std::vector<std::vector<int32_t>> lvnodes;
+    std::vector<std::pair<int32_t, int32_t>> late_nodes;      // (level by its sources, node) of the deferred ones
     {
         const int32_t nx = (int32_t)L.xlev_ptr[0].size() - 1;
         lvnodes.resize(nx);
@@ -1012,11 +1020,52 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 const int32_t v = L.xlev_nodes[0][t];
                 const bool late = v >= L.tail_node0 || (tail && l > 0 && !feeds[v]);
                 (late ? tailn : lvnodes[l]).push_back(v);
+                if (late) late_nodes.push_back({l, v});
             }
         while (!lvnodes.empty() && lvnodes.back().empty()) lvnodes.pop_back();
         if (!tailn.empty()) lvnodes.push_back(std::move(tailn));
+        else late_nodes.clear();
     }
     int32_t nl = (int32_t)lvnodes.size();
+    // deferred standalone rows and tail rows join the launches of the narrow
+    // levels (fewer than kSideNarrowRows rows) once their sources are
+    // complete: one row per idle CU, and only where the level's own longest
+    // row is estimated to take at least as long (sources applied one after
+    // the other, plus the update volume), so the level does not get longer.
+    // The rest stay in the final level.
+    if (opt.side_rows && !late_nodes.empty()) {
+        const int32_t nmain = nl - 1;
+        auto cost = [&](int32_t v) {
+            double c = 0;
+            for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
+                const int32_t u = L.esrc[e];
+                c += 1.0 + (double)L.m[u] * (L.W[u] - L.lw[u]) / 2048.0;
+            }
+            return L.W[v] > kRowCapBig ? 3.0 * c : c;    // accumulator in global memory
+        };
+        std::vector<int64_t> nrow(nmain, 0), room(nmain, 0);
+        std::vector<double> lmax(nmain, 0.0);
+        for (int32_t l = 0; l < nmain; l++)
+            for (int32_t v : lvnodes[l]) { nrow[l] += L.m[v]; lmax[l] = std::max(lmax[l], cost(v)); }
+        for (int32_t l = 0; l < nmain; l++) room[l] = nrow[l] < kSideNarrowRows ? kSideNarrowRows - nrow[l] : 0;
+        std::vector<char> moved(L.nnodes, 0);
+        std::vector<std::pair<int32_t, int32_t>> order(late_nodes);
+        std::sort(order.begin(), order.end());
+        for (const auto& q : order) {
+            const int32_t v = q.second;
+            if (!(L.m[v] == 1 || v >= L.tail_node0)) continue;
+            const double c = cost(v);
+            for (int32_t l = std::max(q.first, 0); l < nmain; l++) {
+                if (room[l] < L.m[v] || lmax[l] < c) continue;
+                lvnodes[l].push_back(v);
+                room[l] -= L.m[v];
+                moved[v] = 1;
+                break;
+            }
+        }
+        auto& fin = lvnodes[nl - 1];
+        fin.erase(std::remove_if(fin.begin(), fin.end(), [&](int32_t v) { return moved[v] != 0; }), fin.end());
+    }
     T.row_ptr.assign(1, 0); T.sn_ptr.assign(1, 0);
     h->max_sn = 0;
     h->dsn.clear();
@@ -1073,6 +1122,21 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     }
     plog("tail plan");
     T.row_nt.assign(nl, 0);
+    // a level of few rows runs one row per CU at most: its rows may take
+    // the large staging buffer, so wide standalone sources are loaded in
+    // batches rather than one after the other
+    // and hold wider rows in LDS (first the row, then as large a stage as fits)
+    T.row_stage.assign(nl, kStageSmall);
+    T.row_cap.assign(nl, kRowCapSmall);
+    for (int32_t l = 0; l < nl; l++) {
+        if (T.row_ptr[l + 1] - T.row_ptr[l] > kSideNarrowRows) continue;
+        const int32_t cap = std::min(std::max(T.maxW[l], kRowCapSmall), kRowCapBig);
+        int32_t stage = kStageMax;
+        while (stage > kStageSmall && factor_rows_lds(h->fp32, stage, cap) > kLdsMax) stage -= 256;
+        if (factor_rows_lds(h->fp32, stage, cap) > kLdsMax) continue;
+        T.row_stage[l] = stage;
+        T.row_cap[l] = cap;
+    }
     T.sn_nt.assign(nl, 0);
     T.node_level.assign(L.nnodes, 0);
     for (int32_t l = 0; l < nl; l++)
@@ -1178,6 +1242,7 @@ hylu_status hylu_default_options(hylu_options* o)
     o->sn_tile = 0;
     o->sn_inverse = 1;
     o->tail_sparse = 1;
+    o->side_rows = 1;
     o->pipeline_rows = 0;
     return HYLU_OK;
 }

@@ -30,7 +30,7 @@ template <typename T> __device__ __forceinline__ T pmag(T x)
     return y == y ? y : static_cast<T>(__builtin_huge_valf());
 }
 
-constexpr int kStage = 1024;   // staged source entries per batch (values + relative indices)
+constexpr int kStage = 1024;   // staged source entries per batch (values + relative indices), default
 constexpr int kSnSolveRows = 64;   // largest supernode of the four-wavefront forward solve
 
 // ----------------------------------------------------------------------------
@@ -91,15 +91,15 @@ __global__ void k_init_pivots(int32_t n, const int32_t* __restrict__ row_node, c
 // independent loads (unrolled over source rows).
 template <typename T, int NT>
 __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ vals, T* xs, const EdgeDesc& ed,
-                                    int tid, T* sbuf, int32_t* ibuf)
+                                    int tid, T* sbuf, int32_t* ibuf, int stage)
 {
     const T* Us = vals + ed.uoff;
     const int32_t* rl = D.rel + ed.roff;
     const int lp = ed.lp, ms = ed.ms, Ws = ed.Ws, ws = ed.ws;
-    const bool pl_lds = ms <= kStage;
+    const bool pl_lds = ms <= stage;
     const int32_t* pls = pl_lds ? ibuf : D.pl + ed.r0s;
     if (pl_lds) for (int b = tid; b < ms; b += NT) ibuf[b] = D.pl[ed.r0s + b];
-    if (ed.ioff >= 0 && ms <= kStage) {
+    if (ed.ioff >= 0 && ms <= stage) {
         // multipliers from the inverse: l_c = sum_{b <= c} x_p[b] Uinv[b][c],
         // every c at once (x_p staged in LDS first)
         const T* Ui = reinterpret_cast<const T*>(D.uinv) + ed.ioff;
@@ -118,7 +118,7 @@ __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ va
         }
         __syncthreads();
     } else {
-    const bool blk_lds = ms * ms <= kStage;
+    const bool blk_lds = ms * ms <= stage;
     if (blk_lds)
         for (int idx = tid; idx < ms * ms; idx += NT) sbuf[idx] = Us[(int64_t)(idx / ms) * Ws + idx % ms];
     __syncthreads();
@@ -183,11 +183,11 @@ __device__ __forceinline__ void wait_sources(const PipeCtl& P, int epoch, int sr
 // before they are read.
 template <typename T, int NT, bool PIPE>
 __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_t lds_cap, T tau,
-                         int32_t* __restrict__ pert, unsigned char* smem_raw, const PipeCtl& PC, int epoch)
+                         int32_t* __restrict__ pert, unsigned char* smem_raw, const PipeCtl& PC, int epoch, int stage)
 {
-    T* sval = reinterpret_cast<T*>(smem_raw);                                   // kStage
-    int32_t* sidx = reinterpret_cast<int32_t*>(sval + kStage);                 // kStage
-    int32_t* eoff = sidx + kStage;                                              // 65 (padded to 66)
+    T* sval = reinterpret_cast<T*>(smem_raw);                                   // stage
+    int32_t* sidx = reinterpret_cast<int32_t*>(sval + stage);                  // stage
+    int32_t* eoff = sidx + stage;                                               // 65 (padded to 66)
     int32_t* elp = eoff + 66;                                                   // 64
     int64_t* eu = reinterpret_cast<int64_t*>(elp + 64);                         // 64, 8-byte aligned
     int64_t* er = eu + 64;                                                      // 64
@@ -224,7 +224,7 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
                 int o = __shfl_up(pre, off, 64);
                 if (lane >= off) pre = (pre > 0x3fffffff - o) ? 0x3fffffff : pre + o;
             }
-            const unsigned long long fits = __ballot(pre <= kStage && my < e1);
+            const unsigned long long fits = __ballot(pre <= stage && my < e1);
             const int nb = (fits == ~0ull) ? 64 : __builtin_ctzll(~fits);
             if (PIPE) wait_sources(PC, epoch, lane < (nb > 0 ? nb : 1) ? src : -1);
             if (lane < nb) {
@@ -244,7 +244,7 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
         if (nb == 0) {
             // a supernode source (or an oversized standalone one)
             const EdgeDesc e0 = D.edges[e];
-            apply_source_direct<T, NT>(D, vals, xs, e0, tid, sval, sidx);
+            apply_source_direct<T, NT>(D, vals, xs, e0, tid, sval, sidx, stage);
             e += 1;
             continue;
         }
@@ -286,12 +286,12 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__ vals,
                                                     const int32_t* __restrict__ rows, int32_t nrows,
-                                                    int32_t lds_cap, T tau, int32_t* __restrict__ pert)
+                                                    int32_t lds_cap, T tau, int32_t* __restrict__ pert, int32_t stage)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if ((int)blockIdx.x >= nrows) return;
     PipeCtl none{};
-    row_task<T, NT, false>(D, vals, rows[blockIdx.x], lds_cap, tau, pert, smem_raw, none, 0);
+    row_task<T, NT, false>(D, vals, rows[blockIdx.x], lds_cap, tau, pert, smem_raw, none, 0, stage);
 }
 
 // ----------------------------------------------------------------------------
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(NT) void k_factor_pipe(DevLayout D, PipeCtl PC, T* 
         const int t = s_task;
         if (t >= nrows) break;
         const int i = rows[t];
-        row_task<T, NT, true>(D, vals, i, lds_cap, tau, pert, smem_raw, PC, epoch);
+        row_task<T, NT, true>(D, vals, i, lds_cap, tau, pert, smem_raw, PC, epoch, kStage);
         const int v = D.row_node[i];
         const int m = D.m[v];
         __syncthreads();
@@ -1868,16 +1868,24 @@ hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st)
 
 static const int32_t kRowLdsCap = 4096;   // row accumulator in LDS up to this width
 
+size_t factor_rows_lds(bool fp32, int32_t stage, int32_t cap)
+{
+    const size_t fixed = (size_t)stage * 4 + 129 * 4 + 4 + 128 * 8;   // indices, edge tables (8-byte aligned)
+    return (fp32 ? sizeof(float) : sizeof(double)) * ((size_t)stage + (size_t)std::max(cap, 1)) + fixed;
+}
+
 hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t nrows,
-                              int32_t maxW, double tau, int32_t* pert, int32_t nt, hipStream_t st)
+                              int32_t maxW, double tau, int32_t* pert, int32_t nt, int32_t stage, int32_t lds_cap,
+                              hipStream_t st)
 {
     if (nrows <= 0) return hipSuccess;
-    int32_t cap = std::min(maxW, kRowLdsCap);
-    size_t fixed = (size_t)kStage * 4 + 129 * 4 + 4 + 128 * 8;   // indices, edge tables (8-byte aligned)
+    if (stage < kStage || stage > kStageMax || stage % 64) return hipErrorInvalidValue;
+    const int32_t cap = std::min(maxW, lds_cap > 0 ? lds_cap : kRowLdsCap);
     if (nt == 0) nt = maxW > 1024 ? 256 : 64;                      // default: 4 waves per row for long rows
-    const size_t sh = (fp32 ? sizeof(float) : sizeof(double)) * (kStage + (size_t)std::max(cap, 1)) + fixed;
+    const size_t sh = factor_rows_lds(fp32, stage, cap);
+    if (sh > kLdsMax) return hipErrorInvalidValue;
     const dim3 g(nrows);
-#define ROWS_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_rows<TT, NTT>), g, dim3(NTT), sh, st, D, (TT*)vals, rows, nrows, cap, (TT)tau, pert)
+#define ROWS_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_rows<TT, NTT>), g, dim3(NTT), sh, st, D, (TT*)vals, rows, nrows, cap, (TT)tau, pert, stage)
     if (fp32) {
         if (nt == 256) ROWS_LAUNCH(float, 256);
         else if (nt == 128) ROWS_LAUNCH(float, 128);

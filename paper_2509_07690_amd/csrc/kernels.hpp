@@ -146,8 +146,17 @@ hipError_t launch_scatter(bool fp32, const double* aval, const int64_t* amap, co
                           const double* asc, int64_t nnz, void* vals, double* acopy, hipStream_t st);
 hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st);
 // nt: threads per row (64, 128 or 256; 0 picks by the widest row of the launch)
+// stage: source entries staged per batch in LDS (a multiple of 64, from
+// kStageSmall to kStageMax); lds_cap: the row accumulator sits in LDS for rows
+// up to this width (0: the default 4096).  Levels of few rows run one row per
+// CU and may take a large stage and cap; factor_rows_lds gives the LDS bytes
+// of a choice (at most kLdsMax).
+constexpr int32_t kStageSmall = 1024, kStageMax = 8192;
+constexpr size_t kLdsMax = 160 * 1024;
+size_t factor_rows_lds(bool fp32, int32_t stage, int32_t cap);
 hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t nrows,
-                              int32_t maxW, double tau, int32_t* pert, int32_t nt, hipStream_t st);
+                              int32_t maxW, double tau, int32_t* pert, int32_t nt, int32_t stage, int32_t lds_cap,
+                              hipStream_t st);
 // row tiles (16 rows) of supernode targets: tiles = pairs (node, first local row)
 hipError_t launch_factor_tile(bool fp32, const DevLayout& D, void* vals, const int32_t* tiles, int32_t ntiles,
                               hipStream_t st);

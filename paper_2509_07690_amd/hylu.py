@@ -37,7 +37,7 @@ class Options(C.Structure):
                 ("kernel_mode", C.c_int32), ("repeated", C.c_int32), ("nd_leaf", C.c_int32),
                 ("amd_dense", C.c_double), ("dense_tail", C.c_double), ("tail_min", C.c_int32),
                 ("tail_max", C.c_int32), ("sn_dense", C.c_int32),
-                ("sn_tile", C.c_int32), ("sn_inverse", C.c_int32), ("tail_sparse", C.c_int32),
+                ("sn_tile", C.c_int32), ("sn_inverse", C.c_int32), ("tail_sparse", C.c_int32), ("side_rows", C.c_int32),
                 ("pipeline_rows", C.c_int32)]
 
 
