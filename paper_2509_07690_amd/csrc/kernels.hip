@@ -138,7 +138,19 @@ __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ va
     const T* Ut = Us + ms;
     for (int j = tid; j < ws; j += NT) {
         T acc0 = T(0), acc1 = T(0);
+        const int rj = rl[j];
         int b = 0;
+        // sixteen loads in flight per step
+        for (; b + 16 <= ms; b += 16) {
+            T u[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) u[k] = Ut[(int64_t)(b + k) * Ws + j];
+#pragma unroll
+            for (int k = 0; k < 16; k += 2) {
+                acc0 += xs[lp + pls[b + k]] * u[k];
+                acc1 += xs[lp + pls[b + k + 1]] * u[k + 1];
+            }
+        }
         for (; b + 4 <= ms; b += 4) {
             const T u0 = Ut[(int64_t)(b + 0) * Ws + j];
             const T u1 = Ut[(int64_t)(b + 1) * Ws + j];
@@ -150,7 +162,7 @@ __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ va
             acc1 += xs[lp + pls[b + 3]] * u3;
         }
         for (; b < ms; b++) acc0 += xs[lp + pls[b]] * Ut[(int64_t)b * Ws + j];
-        xs[rl[j]] -= acc0 + acc1;
+        xs[rj] -= acc0 + acc1;
     }
     __syncthreads();
 }
@@ -202,7 +214,15 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
     const bool in_lds = W <= lds_cap;
     T* xs = in_lds ? xsl : X;
     if (in_lds) {
-        for (int j = tid; j < W; j += NT) xs[j] = X[j];
+        // eight loads per thread in flight before their LDS stores (a wave
+        // issues in order and would otherwise wait on every load)
+        for (int j0 = tid; j0 < W; j0 += 8 * NT) {
+            T t[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) { const int j = j0 + u * NT; t[u] = j < W ? X[j] : T(0); }
+#pragma unroll
+            for (int u = 0; u < 8; u++) { const int j = j0 + u * NT; if (j < W) xs[j] = t[u]; }
+        }
     }
     __syncthreads();
     const int64_t e1 = D.eptr[v + 1];
@@ -248,12 +268,29 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
             e += 1;
             continue;
         }
-        for (int idx = tid; idx < total; idx += NT) {
-            int lo = 0, hi = nb - 1;                 // edge j with eoff[j] <= idx < eoff[j+1]
-            while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (eoff[mid] <= idx) lo = mid; else hi = mid - 1; }
-            const int tt = idx - eoff[lo];
-            sval[idx] = vals[eu[lo] + tt];           // pivot, then the T values
-            if (tt > 0) sidx[idx] = D.rel[er[lo] + tt - 1];
+        // eight entries per thread at a time: their loads are all issued
+        // before the first LDS store
+        for (int i0 = tid; i0 < total; i0 += 8 * NT) {
+            T sv[8];
+            int32_t si[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int idx = i0 + u * NT;
+                sv[u] = T(0);
+                si[u] = 0;
+                if (idx < total) {
+                    int lo = 0, hi = nb - 1;         // edge j with eoff[j] <= idx < eoff[j+1]
+                    while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (eoff[mid] <= idx) lo = mid; else hi = mid - 1; }
+                    const int tt = idx - eoff[lo];
+                    sv[u] = vals[eu[lo] + tt];       // pivot, then the T values
+                    if (tt > 0) si[u] = D.rel[er[lo] + tt - 1];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int idx = i0 + u * NT;
+                if (idx < total) { sval[idx] = sv[u]; sidx[idx] = si[u]; }
+            }
         }
         __syncthreads();
         // sequential part: every source needs the multipliers of the earlier ones
@@ -263,7 +300,23 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
             const int lp = elp[j];
             const T l = xs[lp] / sval[off];
             if (NT > 64) __syncthreads();
-            for (int q = tid; q < ws; q += NT) xs[sidx[off + 1 + q]] -= l * sval[off + 1 + q];
+            // the accumulator values first, then the updates (distinct
+            // positions within one source)
+            for (int q0 = tid; q0 < ws; q0 += 4 * NT) {
+                T xv[4];
+                int ix[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int q = q0 + u * NT;
+                    ix[u] = q < ws ? sidx[off + 1 + q] : 0;
+                    xv[u] = q < ws ? xs[ix[u]] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int q = q0 + u * NT;
+                    if (q < ws) xs[ix[u]] = xv[u] - l * sval[off + 1 + q];
+                }
+            }
             if (tid == 0) xs[lp] = l;
             __syncthreads();
         }
