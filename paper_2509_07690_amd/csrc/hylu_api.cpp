@@ -165,6 +165,8 @@ struct hylu_handle_s {
     // measurement
     Profiler prof;
     std::vector<double> lvl_bytes, lvl_flops;   // per factor level: row-kernel traffic and flops
+    std::vector<int32_t> pert_rows;              // standalone rows without sources: pivot check only
+    int32_t* d_pert_rows = nullptr;
     std::vector<double> tile_bytes, tile_flops; // per factor level: tile-kernel traffic and flops
 };
 
@@ -579,6 +581,10 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
     LAUNCH(C_SCATTER, 40.0 * h->nnz, 2.0 * h->nnz,
            launch_scatter(h->fp32, d_val, h->d_amap, h->d_asr, h->d_asc, h->nnz, h->vals, h->d_aval, st));
     if (search) HIPCHK(launch_tail_init(h->TV, st));
+    if (!h->pert_rows.empty())
+        LAUNCH(C_SCATTER, 2.0 * es * h->pert_rows.size(), 0.0,
+               launch_perturb_rows(h->fp32, h->D, h->vals, h->d_pert_rows, (int32_t)h->pert_rows.size(), h->tau,
+                                   h->d_pert, st));
     const LevelTasks& T = h->ft;
     int32_t nl = (int32_t)T.maxW.size();
     for (int32_t l = 0; l < T.pipe_level; l++) {
@@ -803,6 +809,7 @@ hylu_status upload_device(hylu_handle h)
         UP(h->d_rows, T.rows); UP(h->d_snodes, T.snodes); UP(h->d_tiles, T.tiles);
         UP(h->d_inv_off, h->inv_off); UP(h->d_inv_nodes, h->inv_nodes);
         UP(h->d_tail_list, h->tail_list);
+        UP(h->d_pert_rows, h->pert_rows);
         {
             std::vector<int32_t> sp;
             for (const Layout::Panel& P : L.spanels) { sp.push_back(P.p0); sp.push_back(P.p1); }
@@ -1073,10 +1080,15 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     const int32_t big = opt.sn_dense > 0 ? opt.sn_dense : std::numeric_limits<int32_t>::max();
     const int32_t tile_min = opt.sn_tile > 0 ? opt.sn_tile : std::numeric_limits<int32_t>::max();
     T.tile_ptr.assign(1, 0);
+    h->pert_rows.clear();
     for (int32_t l = 0; l < nl; l++) {
         int32_t mw = 0, mm = 0;
         for (int32_t v : lvnodes[l]) {
-            if (nd.is_sn[v] && v < L.tail_node0 && L.m[v] >= tile_min) {
+            if (L.eptr[v + 1] == L.eptr[v]) {
+                // no sources: nothing to apply; a standalone row outside the
+                // tail only has its pivot checked (one small launch for all)
+                if (L.m[v] == 1 && v < L.tail_node0) h->pert_rows.push_back(L.r0[v]);
+            } else if (nd.is_sn[v] && v < L.tail_node0 && L.m[v] >= tile_min) {
                 // outside updates of a large supernode target by 16-row tiles
                 for (int32_t a = 0; a < L.m[v]; a += kTileRowsHost) { T.tiles.push_back(v); T.tiles.push_back(a); }
             } else {
@@ -1192,6 +1204,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     h->tile_flops.assign(nl, 0.0);
     for (int32_t l = 0; l < nl; l++)
         for (int32_t v : lvnodes[l]) {
+            if (L.eptr[v + 1] == L.eptr[v]) continue;
             const bool tiled = nd.is_sn[v] && v < L.tail_node0 && L.m[v] >= tile_min;
             double m = L.m[v], by = 16.0 * L.W[v], src = 0, fl = 0;
             for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {

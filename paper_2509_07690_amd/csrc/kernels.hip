@@ -347,6 +347,23 @@ __global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__
     row_task<T, NT, false>(D, vals, rows[blockIdx.x], lds_cap, tau, pert, smem_raw, none, 0, stage);
 }
 
+// standalone rows without sources: their pivot is checked (and perturbed)
+// in place, one thread per row
+template <typename T>
+__global__ __launch_bounds__(256) void k_perturb_rows(DevLayout D, T* __restrict__ vals, const int32_t* __restrict__ rows,
+                                                      int32_t count, T tau, int32_t* __restrict__ pert)
+{
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= count) return;
+    const int v = D.row_node[rows[q]];
+    T* d = vals + D.voff[v] + D.lw[v];
+    const T x = *d;
+    if (tabs(x) < tau) {
+        *d = x < T(0) ? -tau : tau;
+        atomicAdd(pert, 1);
+    }
+}
+
 // ----------------------------------------------------------------------------
 // inverse of a supernode's block in pivot order, once its LU is complete: one
 // workgroup per supernode, thread j solving U_pp x = e_j by back substitution
@@ -1951,6 +1968,15 @@ hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const i
         else return hipErrorInvalidValue;
     }
 #undef ROWS_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_perturb_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t count,
+                               double tau, int32_t* pert, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_perturb_rows<float>, dim3(nblk(count, 256)), dim3(256), 0, st, D, (float*)vals, rows, count, (float)tau, pert);
+    else hipLaunchKernelGGL(k_perturb_rows<double>, dim3(nblk(count, 256)), dim3(256), 0, st, D, (double*)vals, rows, count, tau, pert);
     return hipGetLastError();
 }
 

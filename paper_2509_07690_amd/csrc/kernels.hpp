@@ -154,6 +154,9 @@ hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st);
 constexpr int32_t kStageSmall = 1024, kStageMax = 8192;
 constexpr size_t kLdsMax = 160 * 1024;
 size_t factor_rows_lds(bool fp32, int32_t stage, int32_t cap);
+// pivot check (perturbation) of standalone rows that take no updates
+hipError_t launch_perturb_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t count,
+                               double tau, int32_t* pert, hipStream_t st);
 hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t nrows,
                               int32_t maxW, double tau, int32_t* pert, int32_t nt, int32_t stage, int32_t lds_cap,
                               hipStream_t st);
