@@ -121,6 +121,7 @@ struct hylu_handle_s {
     std::vector<int32_t> dsn_ptr;           // per factor level into dsn
     std::vector<std::vector<int32_t>> dsn_l, dsn_u;   // per L-solve / U-solve level: dsn indices
     std::vector<int32_t> lsolve_sn;         // per L-solve level: 1 if it has a supernode for k_lsolve_sn
+    std::vector<int32_t> usolve_sn;         // per U-solve level: 1 if it has a supernode for k_usolve_sn
     std::vector<int64_t> inv_off;           // per node: offset of its block inverse, or -1
     int64_t inv_total = 0;
     std::vector<int64_t> inv_ptr;           // per factor level into inv_nodes
@@ -704,7 +705,10 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
                 LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, SP[k].p0, SP[k].p1, SP[k - 1].p0, SP[k - 1].p1,
                                                         inv(k - 1, 1), n, h->d_y, h->d_z, nrhs, 1, st));
         }
-        s = levels(1, [&](const int32_t* nodes, int32_t c, size_t) { return launch_usolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, st); });
+        s = levels(1, [&](const int32_t* nodes, int32_t c, size_t l) {
+            const int32_t with = l < h->usolve_sn.size() ? h->usolve_sn[l] : 0;
+            return launch_usolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, kLsolveSnMin, with, st);
+        });
         if (s != HYLU_OK) return s;
         HIPCHK(launch_permute_out(f, n, nrhs, h->d_perm_c, h->d_dc, h->d_z, x, ldx, accumulate, st));
     } else {
@@ -1179,6 +1183,12 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         for (int32_t t = L.xlev_ptr[4][l]; t < L.xlev_ptr[4][l + 1]; t++) {
             const int32_t m = L.m[L.xlev_nodes[4][t]];
             if (m >= kLsolveSnMin && m <= 64) h->lsolve_sn[l] = 1;
+        }
+    h->usolve_sn.assign(L.xlev_ptr[1].size() > 0 ? L.xlev_ptr[1].size() - 1 : 0, 0);
+    for (size_t l = 0; l + 1 < L.xlev_ptr[1].size(); l++)
+        for (int32_t t = L.xlev_ptr[1][l]; t < L.xlev_ptr[1][l + 1]; t++) {
+            const int32_t m = L.m[L.xlev_nodes[1][t]];
+            if (m >= kLsolveSnMin && m <= 64) h->usolve_sn[l] = 1;
         }
     // the large supernodes' places in the L-solve and U-solve level sequences
     {

@@ -576,6 +576,56 @@ __device__ __forceinline__ float bcast(float x, int l)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 
+// sum over t = lane, lane + 64, .. < len of P[t] * y[qinv[cols[t]]]: four
+// entries per lane at a time, each dependent load issued for all four before
+// the next (a wave waits on a load at its first use)
+template <typename T, int S = 64>
+__device__ __forceinline__ T gather_lq(const T* __restrict__ P, const int32_t* __restrict__ cols,
+                                       const int32_t* __restrict__ qinv, const T* __restrict__ y, int len, int lane)
+{
+    T acc = T(0);
+    for (int t0 = lane; t0 < len; t0 += 4 * S) {
+        int c[4];
+        T p[4], x[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int t = t0 + S * u;
+            c[u] = t < len ? cols[t] : 0;
+            p[u] = t < len ? P[t] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) c[u] = t0 + S * u < len ? qinv[c[u]] : 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) x[u] = t0 + S * u < len ? y[c[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; u++) acc += p[u] * x[u];
+    }
+    return acc;
+}
+
+// the same with a direct index: P[t] * x[cols[t]]
+template <typename T, int S = 64>
+__device__ __forceinline__ T gather_x(const T* __restrict__ P, const int32_t* __restrict__ cols, const T* __restrict__ x,
+                                      int len, int lane)
+{
+    T acc = T(0);
+    for (int t0 = lane; t0 < len; t0 += 4 * S) {
+        int c[4];
+        T p[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int t = t0 + S * u;
+            c[u] = t < len ? cols[t] : 0;
+            p[u] = t < len ? P[t] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) xv[u] = t0 + S * u < len ? x[c[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; u++) acc += p[u] * xv[u];
+    }
+    return acc;
+}
+
 // forward: y_i = c_i - sum_k L(i,k) y_k (unit L), rows of a node in order
 template <typename T>
 __global__ __launch_bounds__(64) void k_lsolve(DevLayout D, const T* __restrict__ vals,
@@ -595,8 +645,7 @@ __global__ __launch_bounds__(64) void k_lsolve(DevLayout D, const T* __restrict_
         T* yr = y + (int64_t)r * n;
         for (int a = 0; a < m; a++) {
             const T* Pa = P + (int64_t)a * W;
-            T acc = T(0);
-            for (int t = lane; t < lw; t += 64) acc += Pa[t] * yr[D.qinv[cols[t]]];
+            T acc = gather_lq(Pa, cols, D.qinv, yr, lw, lane);
             for (int b = lane; b < a; b += 64) acc += Pa[lw + pl[b]] * yr[r0 + b];
             acc = wave_sum(acc);
             if (lane == 0) yr[r0 + a] -= acc;
@@ -635,8 +684,7 @@ __global__ __launch_bounds__(256) void k_lsolve_sn(DevLayout D, const T* __restr
         T* yr = y + (int64_t)r * n;
         for (int a = wv; a < m; a += 4) {
             const T* Pa = P + (int64_t)a * W;
-            T acc = T(0);
-            for (int t = lane; t < lw; t += 64) acc += Pa[t] * yr[D.qinv[cols[t]]];
+            T acc = gather_lq(Pa, cols, D.qinv, yr, lw, lane);
             acc = wave_sum(acc);
             if (lane == 0) ys[a] = yr[r0 + a] - acc;
         }
@@ -653,16 +701,19 @@ __global__ __launch_bounds__(256) void k_lsolve_sn(DevLayout D, const T* __restr
     }
 }
 
-// backward: x[piv a] = (y_a - sum_{j != piv a} U_st(a,j) x_j) / U_st(a, piv a)
+// backward: x[piv a] = (y_a - sum_{j != piv a} U_st(a,j) x_j) / U_st(a, piv a);
+// the four wavefronts of the workgroup share each row's gather
 template <typename T>
-__global__ __launch_bounds__(64) void k_usolve(DevLayout D, const T* __restrict__ vals,
-                                               const int32_t* __restrict__ nodes, int32_t count,
-                                               const T* __restrict__ y, T* __restrict__ x, int32_t nrhs)
+__global__ __launch_bounds__(256) void k_usolve(DevLayout D, const T* __restrict__ vals,
+                                                const int32_t* __restrict__ nodes, int32_t count,
+                                                const T* __restrict__ y, T* __restrict__ x, int32_t nrhs, int32_t sn_min)
 {
+    __shared__ T part[4];
     const int v = nodes[blockIdx.x];
     if (D.dense_sn && D.dense_sn[v]) return;     // solved by the dense-view kernels
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    if (sn_min > 0 && m >= sn_min && m <= kSnSolveRows) return;   // solved by k_usolve_sn
     const int w = W - lw - m;
     const T* P = vals + D.voff[v] + lw;
     const int32_t* tc = D.cols + D.coff[v] + lw + m;
@@ -673,13 +724,70 @@ __global__ __launch_bounds__(64) void k_usolve(DevLayout D, const T* __restrict_
         T* xr = x + (int64_t)r * n;
         for (int a = m - 1; a >= 0; a--) {
             const T* Pa = P + (int64_t)a * W;
-            T acc = T(0);
-            for (int t = lane; t < w; t += 64) acc += Pa[m + t] * xr[tc[t]];
-            for (int b = a + 1 + lane; b < m; b += 64) { int c = pl[b]; acc += Pa[c] * xr[r0 + c]; }
+            T acc = gather_x<T, 256>(Pa + m, tc, xr, w, tid);
+            for (int b = a + 1 + tid; b < m; b += 256) { int c = pl[b]; acc += Pa[c] * xr[r0 + c]; }
             acc = wave_sum(acc);
-            if (lane == 0) { int c = pl[a]; xr[r0 + c] = (yr[r0 + a] - acc) / Pa[c]; }
+            if (lane == 0) part[wv] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                const int c = pl[a];
+                xr[r0 + c] = (yr[r0 + a] - ((part[0] + part[1]) + (part[2] + part[3]))) / Pa[c];
+            }
             __syncthreads();
         }
+    }
+}
+
+// backward solve of a supernode with sn_min..64 rows on four wavefronts: the
+// rows' gathers over the shared T columns do not depend on the block and run
+// first, spread over the wavefronts; the block (U_st(a, piv b), b >= a, in
+// pivot order, staged in LDS) is then swept column by column from the last
+// one on wavefront 0, one lane per row
+template <typename T>
+__global__ __launch_bounds__(256) void k_usolve_sn(DevLayout D, const T* __restrict__ vals,
+                                                   const int32_t* __restrict__ nodes, int32_t count,
+                                                   const T* __restrict__ y, T* __restrict__ x, int32_t nrhs,
+                                                   int32_t sn_min)
+{
+    __shared__ T Ub[kSnSolveRows][kSnSolveRows + 1];
+    __shared__ T ys[kSnSolveRows];
+    __shared__ int pls[kSnSolveRows];
+    const int v = nodes[blockIdx.x];
+    if (D.dense_sn && D.dense_sn[v]) return;
+    const int m = D.m[v];
+    if (m < sn_min || m > kSnSolveRows) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const int w = W - lw - m;
+    const T* P = vals + D.voff[v] + lw;
+    const int32_t* tc = D.cols + D.coff[v] + lw + m;
+    const int n = D.n;
+    if (tid < m) pls[tid] = D.pl[r0 + tid];
+    __syncthreads();
+    for (int idx = tid; idx < m * m; idx += 256) {
+        const int a = idx / m, b = idx - (idx / m) * m;
+        Ub[a][b] = b >= a ? P[(int64_t)a * W + pls[b]] : T(0);
+    }
+    for (int r = 0; r < nrhs; r++) {
+        const T* yr = y + (int64_t)r * n;
+        T* xr = x + (int64_t)r * n;
+        for (int a = wv; a < m; a += 4) {
+            T acc = gather_x(P + (int64_t)a * W + m, tc, xr, w, lane);
+            acc = wave_sum(acc);
+            if (lane == 0) ys[a] = yr[r0 + a] - acc;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            T va = lane < m ? ys[lane] : T(0);
+            T xv = T(0);
+            for (int b = m - 1; b >= 0; b--) {
+                const T xb = bcast(va, b) / Ub[b][b];
+                if (lane == b) xv = xb;
+                if (lane < b) va -= Ub[lane][b] * xb;
+            }
+            if (lane < m) xr[r0 + pls[lane]] = xv;
+        }
+        __syncthreads();
     }
 }
 
@@ -1748,11 +1856,12 @@ __global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restr
         const int t = threadIdx.x;
         if (t < nq) rowq[t] = TV.trow[q0 + t];
         __syncthreads();
-        T c[kNB / 4];
+        T c[kNB / 4], iv[kNB / 4];
 #pragma unroll
         for (int q = 0; q < kNB / 4; q++) {
             const int i = wv + 4 * q;
             c[q] = (i < nq && lane < np) ? vals[rowq[i] + pb] : T(0);
+            iv[q] = (i < nq && lane < nq) ? inv[i * kNB + lane] : T(0);
         }
         for (int r = 0; r < nrhs; r++) {
             T* yr = y + (int64_t)r * n + t0;
@@ -1770,12 +1879,6 @@ __global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restr
                 }
             }
             __syncthreads();
-            T iv[kNB / 4];
-#pragma unroll
-            for (int q = 0; q < kNB / 4; q++) {
-                const int jj = wv + 4 * q;
-                iv[q] = (jj < nq && lane < nq) ? inv[jj * kNB + lane] : T(0);
-            }
             T acc = T(0);
 #pragma unroll
             for (int q = 0; q < kNB / 4; q++) {
@@ -2056,11 +2159,16 @@ hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const 
 }
 
 hipError_t launch_usolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
-                         const void* y, void* x, int32_t nrhs, hipStream_t st)
+                         const void* y, void* x, int32_t nrhs, int32_t sn_min, int32_t with_sn, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    if (fp32) hipLaunchKernelGGL(k_usolve<float>, dim3(count), dim3(64), 0, st, D, (const float*)vals, nodes, count, (const float*)y, (float*)x, nrhs);
-    else hipLaunchKernelGGL(k_usolve<double>, dim3(count), dim3(64), 0, st, D, (const double*)vals, nodes, count, (const double*)y, (double*)x, nrhs);
+    if (!with_sn || sn_min > kSnSolveRows) sn_min = 0;    // every node by k_usolve
+    if (fp32) hipLaunchKernelGGL(k_usolve<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (const float*)y, (float*)x, nrhs, sn_min);
+    else hipLaunchKernelGGL(k_usolve<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (const double*)y, (double*)x, nrhs, sn_min);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || sn_min <= 0) return e;
+    if (fp32) hipLaunchKernelGGL(k_usolve_sn<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (const float*)y, (float*)x, nrhs, sn_min);
+    else hipLaunchKernelGGL(k_usolve_sn<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (const double*)y, (double*)x, nrhs, sn_min);
     return hipGetLastError();
 }
 

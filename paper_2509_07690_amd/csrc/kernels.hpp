@@ -178,7 +178,7 @@ hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const i
 hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
                          void* y, int32_t nrhs, int32_t sn_min, int32_t with_sn, hipStream_t st);
 hipError_t launch_usolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
-                         const void* y, void* x, int32_t nrhs, hipStream_t st);
+                         const void* y, void* x, int32_t nrhs, int32_t sn_min, int32_t with_sn, hipStream_t st);
 hipError_t launch_utsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
                           const void* h, void* w, int32_t nrhs, hipStream_t st);
 hipError_t launch_ltsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
