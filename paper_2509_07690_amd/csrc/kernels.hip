@@ -109,6 +109,17 @@ __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ va
         for (int c = tid; c < ms; c += NT) {
             T acc0 = T(0), acc1 = T(0);
             int b = 0;
+            // sixteen loads in flight per step
+            for (; b + 16 <= c + 1; b += 16) {
+                T u[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) u[k] = Ui[(int64_t)(b + k) * ms + c];
+#pragma unroll
+                for (int k = 0; k < 16; k += 2) {
+                    acc0 += sbuf[b + k] * u[k];
+                    acc1 += sbuf[b + k + 1] * u[k + 1];
+                }
+            }
             for (; b + 2 <= c + 1; b += 2) {
                 acc0 += sbuf[b] * Ui[(int64_t)b * ms + c];
                 acc1 += sbuf[b + 1] * Ui[(int64_t)(b + 1) * ms + c];
@@ -1487,6 +1498,11 @@ __global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ 
             tx = L % gx;
         }
     }
+    // value offsets of the K panel rows, staged once (the B operand's row
+    // pointers would otherwise be a dependent load in every K step)
+    __shared__ int64_t trk[kNB * kGroup];
+    for (int k = threadIdx.x; k < K; k += 256) trk[k] = TV.trow[kb0 + k];
+    __syncthreads();
     // block tile 64 x 64, four wavefronts of 32 x 32 (2 x 2 MFMA blocks each)
     const int r0 = rb + ty * 64 + (wv >> 1) * 32, c0 = cg0 + tx * 64 + (wv & 1) * 32;
     const T* lb = reinterpret_cast<const T*>(TV.lbuf);
@@ -1536,7 +1552,7 @@ __global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ 
             const T* ap = arow + (int64_t)ks * 4 * lds;
             const T a0 = (kok && rok0) ? ap[0] : T(0);
             const T a1 = (kok && rok1) ? ap[16] : T(0);
-            const T* bp = vals + (kok ? TV.trow[kb0 + k] : 0);
+            const T* bp = vals + (kok ? trk[k] : 0);
             const T b0 = (kok && cok0) ? bp[cb] : T(0);
             const T b1 = (kok && cok1) ? bp[cb1] : T(0);
             acc[0][0] = Mfma<T>::mma(a0, b0, acc[0][0]);
