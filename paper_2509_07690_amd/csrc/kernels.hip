@@ -1540,27 +1540,38 @@ __global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ 
     // same: a skipped step has only exact zeros (rows without L entries in the
     // panel, or columns without U entries)
     const int kbnd[kGroup + 1] = {0, kb1, kb2, kb3, K};
-    int next = 0;
+    unsigned long long kact = 0;          // bit ks: K step [4 ks, 4 ks + 4) is summed
 #pragma unroll
     for (int j = 0; j < kGroup; j++) {
         if (!((pmask >> j) & 1)) continue;
-        const int ks1 = (kbnd[j + 1] + 3) >> 2;
-#pragma unroll 4
-        for (int ks = max(kbnd[j] >> 2, next); ks < ks1; ks++) {
-            const int k = ks * 4 + lk;
-            const bool kok = k < K;
+        const int s0 = kbnd[j] >> 2, s1 = (kbnd[j + 1] + 3) >> 2;
+        if (s1 > s0) kact |= (s1 - s0 >= 64 ? ~0ull : ((1ull << (s1 - s0)) - 1)) << s0;
+    }
+    // eight K steps per round, all their loads issued before the first MFMA;
+    // a step outside the summed ones within a round contributes exact zeros
+    const int nks = (K + 3) >> 2;
+    for (int c0 = 0; c0 < nks; c0 += 8) {
+        const unsigned cm = (unsigned)(kact >> c0) & 0xFFu;
+        if (!cm) continue;
+        T a0[8], a1[8], b0[8], b1[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int ks = c0 + u, k = ks * 4 + lk;
+            const bool kok = ((cm >> u) & 1u) && k < K;
             const T* ap = arow + (int64_t)ks * 4 * lds;
-            const T a0 = (kok && rok0) ? ap[0] : T(0);
-            const T a1 = (kok && rok1) ? ap[16] : T(0);
+            a0[u] = (kok && rok0) ? ap[0] : T(0);
+            a1[u] = (kok && rok1) ? ap[16] : T(0);
             const T* bp = vals + (kok ? trk[k] : 0);
-            const T b0 = (kok && cok0) ? bp[cb] : T(0);
-            const T b1 = (kok && cok1) ? bp[cb1] : T(0);
-            acc[0][0] = Mfma<T>::mma(a0, b0, acc[0][0]);
-            acc[0][1] = Mfma<T>::mma(a0, b1, acc[0][1]);
-            acc[1][0] = Mfma<T>::mma(a1, b0, acc[1][0]);
-            acc[1][1] = Mfma<T>::mma(a1, b1, acc[1][1]);
+            b0[u] = (kok && cok0) ? bp[cb] : T(0);
+            b1[u] = (kok && cok1) ? bp[cb1] : T(0);
         }
-        next = max(next, ks1);
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            acc[0][0] = Mfma<T>::mma(a0[u], b0[u], acc[0][0]);
+            acc[0][1] = Mfma<T>::mma(a0[u], b1[u], acc[0][1]);
+            acc[1][0] = Mfma<T>::mma(a1[u], b0[u], acc[1][0]);
+            acc[1][1] = Mfma<T>::mma(a1[u], b1[u], acc[1][1]);
+        }
     }
 #pragma unroll
     for (int i = 0; i < 2; i++)
