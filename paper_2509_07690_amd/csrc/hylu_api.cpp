@@ -61,6 +61,7 @@ struct LevelTasks {
     std::vector<int32_t> row_cap;        // per level: widest row whose accumulator sits in LDS
     std::vector<int64_t> tile_ptr;        // per level into tiles (pairs: node, first local row)
     std::vector<int32_t> tiles;
+    std::vector<int64_t> rrange;          // per entry of rows: its first and one-past-last source
     int32_t tune_rows = 0, tune_sn = 0;  // when nonzero, every level uses this (autotuner trials)
     int32_t pipe_level = 0;           // levels from here on run as one pipelined launch
     int32_t pipe_maxW = 0, pipe_maxm = 0;
@@ -106,6 +107,7 @@ struct hylu_handle_s {
     int64_t* d_amap = nullptr;
     double *d_asr = nullptr, *d_asc = nullptr;
     int32_t *d_rows = nullptr, *d_snodes = nullptr, *d_tiles = nullptr;
+    int64_t* d_rrange = nullptr;
     int32_t* d_lev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     TailView TV{};
     PipeCtl PC{};
@@ -591,7 +593,8 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
     for (int32_t l = 0; l < T.pipe_level; l++) {
         int64_t r0 = T.row_ptr[l], r1 = T.row_ptr[l + 1];
         LAUNCH(C_ROWS, h->lvl_bytes[l] * es / 8.0, h->lvl_flops[l],
-               launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.maxW[l], h->tau, h->d_pert,
+               launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, h->d_rrange + 2 * r0, (int32_t)(r1 - r0),
+                                  T.maxW[l], h->tau, h->d_pert,
                                   T.tune_rows ? T.tune_rows : T.row_nt[l], T.row_stage[l], T.row_cap[l], st));
         if (T.tile_ptr[l + 1] > T.tile_ptr[l])
             LAUNCH(C_TILE, h->tile_bytes[l] * es / 8.0, h->tile_flops[l],
@@ -811,6 +814,7 @@ hylu_status upload_device(hylu_handle h)
         D.eptr = eptr; D.edges = edges; D.rel = rel; D.row_node = row_node; D.pl = pl; D.qinv = qinv;
         UP(h->d_amap, L.amap); UP(h->d_asr, asr); UP(h->d_asc, asc);
         UP(h->d_rows, T.rows); UP(h->d_snodes, T.snodes); UP(h->d_tiles, T.tiles);
+        UP(h->d_rrange, T.rrange);
         UP(h->d_inv_off, h->inv_off); UP(h->d_inv_nodes, h->inv_nodes);
         UP(h->d_tail_list, h->tail_list);
         UP(h->d_pert_rows, h->pert_rows);
@@ -1038,6 +1042,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         else late_nodes.clear();
     }
     int32_t nl = (int32_t)lvnodes.size();
+    std::vector<std::vector<std::array<int64_t, 3>>> lvpieces(nl);   // per level: (row, first, end source)
     // deferred standalone rows and tail rows join the launches of the narrow
     // levels (fewer than kSideNarrowRows rows) once their sources are
     // complete: one row per idle CU, and only where the level's own longest
@@ -1074,6 +1079,42 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 break;
             }
         }
+        // a tail node too long for any narrow level takes its sources in
+        // pieces: in order, each piece in a later narrow level than the one
+        // before, once its sources are complete and while its estimated cost
+        // stays within the level's; the rest in the final level
+        std::vector<int32_t> lev_of(L.nnodes, -1);
+        for (int32_t l = 0; l < nmain; l++)
+            for (int32_t v : lvnodes[l]) lev_of[v] = l;
+        for (const auto& q : order) {
+            const int32_t v = q.second;
+            if (moved[v] || v < L.tail_node0 || L.eptr[v + 1] == L.eptr[v]) continue;
+            // (pieces are held to half the level's estimate: a piece also
+            // loads and stores the whole row)
+            const double mult = 2.0 * (L.W[v] > kRowCapBig ? 3.0 : 1.0);
+            int64_t e = L.eptr[v];
+            const int64_t e1 = L.eptr[v + 1];
+            std::vector<std::array<int64_t, 3>> pieces;     // (level, first, end)
+            for (int32_t l = std::max(q.first, 0); l < nmain && e < e1; l++) {
+                if (room[l] < L.m[v]) continue;
+                const int64_t e0 = e;
+                double c = 0;
+                while (e < e1) {
+                    const int32_t u = L.esrc[e];
+                    if (lev_of[u] < 0 || lev_of[u] >= l) break;
+                    const double cu = mult * (1.0 + (double)L.m[u] * (L.W[u] - L.lw[u]) / 2048.0);
+                    if (c + cu > lmax[l]) break;
+                    c += cu;
+                    e++;
+                }
+                if (e > e0) { pieces.push_back({l, e0, e}); room[l] -= L.m[v]; }
+            }
+            if (pieces.empty()) continue;
+            if (e < e1) pieces.push_back({nl - 1, e, e1});
+            for (const auto& pc : pieces)
+                for (int32_t r = L.r0[v]; r < L.r0[v] + L.m[v]; r++) lvpieces[pc[0]].push_back({r, pc[1], pc[2]});
+            moved[v] = 1;
+        }
         auto& fin = lvnodes[nl - 1];
         fin.erase(std::remove_if(fin.begin(), fin.end(), [&](int32_t v) { return moved[v] != 0; }), fin.end());
     }
@@ -1084,6 +1125,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     const int32_t big = opt.sn_dense > 0 ? opt.sn_dense : std::numeric_limits<int32_t>::max();
     const int32_t tile_min = opt.sn_tile > 0 ? opt.sn_tile : std::numeric_limits<int32_t>::max();
     T.tile_ptr.assign(1, 0);
+    T.rrange.clear();
     h->pert_rows.clear();
     for (int32_t l = 0; l < nl; l++) {
         int32_t mw = 0, mm = 0;
@@ -1096,7 +1138,11 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 // outside updates of a large supernode target by 16-row tiles
                 for (int32_t a = 0; a < L.m[v]; a += kTileRowsHost) { T.tiles.push_back(v); T.tiles.push_back(a); }
             } else {
-                for (int32_t r = L.r0[v]; r < L.r0[v] + L.m[v]; r++) T.rows.push_back(r);
+                for (int32_t r = L.r0[v]; r < L.r0[v] + L.m[v]; r++) {
+                    T.rows.push_back(r);
+                    T.rrange.push_back(L.eptr[v]);
+                    T.rrange.push_back(L.eptr[v + 1]);
+                }
                 mw = std::max(mw, L.W[v]);
             }
             if (!nd.is_sn[v] || v >= L.tail_node0) continue;
@@ -1117,6 +1163,12 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 T.snodes.push_back(v);
                 mm = std::max(mm, L.m[v]);
             }
+        }
+        for (const auto& pc : lvpieces[l]) {
+            T.rows.push_back((int32_t)pc[0]);
+            T.rrange.push_back(pc[1]);
+            T.rrange.push_back(pc[2]);
+            mw = std::max(mw, L.W[nd.of_row[pc[0]]]);
         }
         h->dsn_ptr.push_back((int32_t)h->dsn.size());
         T.row_ptr.push_back((int64_t)T.rows.size());
@@ -1231,6 +1283,19 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 h->lvl_bytes[l] += m * (by + src);
                 h->lvl_flops[l] += m * fl;
             }
+        }
+    for (int32_t l = 0; l < nl; l++)
+        for (const auto& pc : lvpieces[l]) {
+            const int32_t v = nd.of_row[pc[0]];
+            double src = 0, fl = 0;
+            for (int64_t e = pc[1]; e < pc[2]; e++) {
+                int32_t u = L.esrc[e];
+                double ms = L.m[u], ws = L.W[u] - L.lw[u] - L.m[u];
+                src += 8.0 * ms * (ms + ws) + 4.0 * ws + 48.0;
+                fl += ms * (ms + 2.0 * ws);
+            }
+            h->lvl_bytes[l] += 16.0 * L.W[v] + src;
+            h->lvl_flops[l] += fl;
         }
     plog("tasks");
     h->analyzed = true;

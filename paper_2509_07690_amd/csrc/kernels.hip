@@ -206,7 +206,8 @@ __device__ __forceinline__ void wait_sources(const PipeCtl& P, int epoch, int sr
 // before they are read.
 template <typename T, int NT, bool PIPE>
 __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_t lds_cap, T tau,
-                         int32_t* __restrict__ pert, unsigned char* smem_raw, const PipeCtl& PC, int epoch, int stage)
+                         int32_t* __restrict__ pert, unsigned char* smem_raw, const PipeCtl& PC, int epoch, int stage,
+                         int64_t eb = -1, int64_t ee = -1)
 {
     T* sval = reinterpret_cast<T*>(smem_raw);                                   // stage
     int32_t* sidx = reinterpret_cast<int32_t*>(sval + stage);                  // stage
@@ -236,8 +237,11 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
         }
     }
     __syncthreads();
-    const int64_t e1 = D.eptr[v + 1];
-    int64_t e = D.eptr[v];
+    // the sources [eb, ee) of the row's list (all of them by default: a long
+    // row may take its sources in several launches, in order)
+    const int64_t eall = D.eptr[v + 1];
+    const int64_t e1 = ee >= 0 ? ee : eall;
+    int64_t e = eb >= 0 ? eb : D.eptr[v];
     while (e < e1) {
         // wave 0 plans a batch: one descriptor per lane; standalone sources are staged
         if (tid < 64) {
@@ -333,7 +337,7 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
         }
         e += nb;
     }
-    if (D.m[v] == 1 && v < D.tail_node0 && tid == 0) {
+    if (D.m[v] == 1 && v < D.tail_node0 && e1 == eall && tid == 0) {
         // standalone row: no pivot search (Sec. 2.2), perturbation only
         T d = xs[D.lw[v]];
         if (tabs(d) < tau) {
@@ -349,13 +353,15 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
 
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__ vals,
-                                                    const int32_t* __restrict__ rows, int32_t nrows,
-                                                    int32_t lds_cap, T tau, int32_t* __restrict__ pert, int32_t stage)
+                                                    const int32_t* __restrict__ rows, const int64_t* __restrict__ ranges,
+                                                    int32_t nrows, int32_t lds_cap, T tau, int32_t* __restrict__ pert,
+                                                    int32_t stage)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if ((int)blockIdx.x >= nrows) return;
     PipeCtl none{};
-    row_task<T, NT, false>(D, vals, rows[blockIdx.x], lds_cap, tau, pert, smem_raw, none, 0, stage);
+    const int64_t eb = ranges ? ranges[2 * blockIdx.x] : -1, ee = ranges ? ranges[2 * blockIdx.x + 1] : -1;
+    row_task<T, NT, false>(D, vals, rows[blockIdx.x], lds_cap, tau, pert, smem_raw, none, 0, stage, eb, ee);
 }
 
 // standalone rows without sources: their pivot is checked (and perturbed)
@@ -2074,9 +2080,9 @@ size_t factor_rows_lds(bool fp32, int32_t stage, int32_t cap)
     return (fp32 ? sizeof(float) : sizeof(double)) * ((size_t)stage + (size_t)std::max(cap, 1)) + fixed;
 }
 
-hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t nrows,
-                              int32_t maxW, double tau, int32_t* pert, int32_t nt, int32_t stage, int32_t lds_cap,
-                              hipStream_t st)
+hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, const int64_t* ranges,
+                              int32_t nrows, int32_t maxW, double tau, int32_t* pert, int32_t nt, int32_t stage,
+                              int32_t lds_cap, hipStream_t st)
 {
     if (nrows <= 0) return hipSuccess;
     if (stage < kStage || stage > kStageMax || stage % 64) return hipErrorInvalidValue;
@@ -2085,7 +2091,7 @@ hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const i
     const size_t sh = factor_rows_lds(fp32, stage, cap);
     if (sh > kLdsMax) return hipErrorInvalidValue;
     const dim3 g(nrows);
-#define ROWS_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_rows<TT, NTT>), g, dim3(NTT), sh, st, D, (TT*)vals, rows, nrows, cap, (TT)tau, pert, stage)
+#define ROWS_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_rows<TT, NTT>), g, dim3(NTT), sh, st, D, (TT*)vals, rows, ranges, nrows, cap, (TT)tau, pert, stage)
     if (fp32) {
         if (nt == 256) ROWS_LAUNCH(float, 256);
         else if (nt == 128) ROWS_LAUNCH(float, 128);

@@ -149,17 +149,22 @@ hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st);
 // stage: source entries staged per batch in LDS (a multiple of 64, from
 // kStageSmall to kStageMax); lds_cap: the row accumulator sits in LDS for rows
 // up to this width (0: the default 4096).  Levels of few rows run one row per
-// CU and may take a large stage and cap; factor_rows_lds gives the LDS bytes
-// of a choice (at most kLdsMax).
+// CU and may take a large stage and cap; factor_rows_lds gives the dynamic
+// LDS bytes of a choice, at most kLdsMax: the 160 KiB a workgroup may hold
+// less 1 KiB for the kernel's static LDS and its alignment (a dispatch that
+// asks for more than the device allows is refused by the queue).
 constexpr int32_t kStageSmall = 1024, kStageMax = 8192;
-constexpr size_t kLdsMax = 160 * 1024;
+constexpr size_t kLdsMax = 160 * 1024 - 1024;
 size_t factor_rows_lds(bool fp32, int32_t stage, int32_t cap);
 // pivot check (perturbation) of standalone rows that take no updates
 hipError_t launch_perturb_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t count,
                                double tau, int32_t* pert, hipStream_t st);
-hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, int32_t nrows,
-                              int32_t maxW, double tau, int32_t* pert, int32_t nt, int32_t stage, int32_t lds_cap,
-                              hipStream_t st);
+// ranges (optional, device): per row, the first and one-past-last index of
+// the sources it takes in this launch (a long row's sources may be split over
+// several launches, in order); null: every source
+hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, const int64_t* ranges,
+                              int32_t nrows, int32_t maxW, double tau, int32_t* pert, int32_t nt, int32_t stage,
+                              int32_t lds_cap, hipStream_t st);
 // row tiles (16 rows) of supernode targets: tiles = pairs (node, first local row)
 hipError_t launch_factor_tile(bool fp32, const DevLayout& D, void* vals, const int32_t* tiles, int32_t ntiles,
                               hipStream_t st);
