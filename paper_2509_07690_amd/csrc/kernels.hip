@@ -643,6 +643,36 @@ __device__ __forceinline__ T gather_x(const T* __restrict__ P, const int32_t* __
     return acc;
 }
 
+// sum over q = q0 + lane, .. < q1 (stride S) of vals[slot[q]] * w[row[q]],
+// four entries per lane at a time with their dependent loads issued together
+template <typename T, int S>
+__device__ __forceinline__ T gather_sr(const T* __restrict__ vals, const int64_t* __restrict__ slot,
+                                       const int32_t* __restrict__ row, const T* __restrict__ w, int64_t q0, int64_t q1,
+                                       int lane)
+{
+    T acc = T(0);
+    for (int64_t b = q0 + lane; b < q1; b += 4 * S) {
+        int64_t sl[4];
+        int32_t rw[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int64_t q = b + S * u;
+            sl[u] = q < q1 ? slot[q] : 0;
+            rw[u] = q < q1 ? row[q] : 0;
+        }
+        T p[4], x[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const bool ok = b + S * u < q1;
+            p[u] = ok ? vals[sl[u]] : T(0);
+            x[u] = ok ? w[rw[u]] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) acc += p[u] * x[u];
+    }
+    return acc;
+}
+
 // forward: y_i = c_i - sum_k L(i,k) y_k (unit L), rows of a node in order
 template <typename T>
 __global__ __launch_bounds__(64) void k_lsolve(DevLayout D, const T* __restrict__ vals,
@@ -810,12 +840,13 @@ __global__ __launch_bounds__(256) void k_usolve_sn(DevLayout D, const T* __restr
 
 // U_st^T w = h: w_a = (h[piv a] - sum_{k<a} U_st(k, piv a) w_k) / U_st(a, piv a)
 template <typename T>
-__global__ __launch_bounds__(64) void k_utsolve(DevLayout D, const T* __restrict__ vals,
-                                                const int32_t* __restrict__ nodes, int32_t count,
-                                                const T* __restrict__ h, T* __restrict__ w, int32_t nrhs)
+__global__ __launch_bounds__(256) void k_utsolve(DevLayout D, const T* __restrict__ vals,
+                                                 const int32_t* __restrict__ nodes, int32_t count,
+                                                 const T* __restrict__ h, T* __restrict__ w, int32_t nrhs)
 {
+    __shared__ T part[4];
     const int v = nodes[blockIdx.x];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
     const T* P = vals + D.voff[v] + lw;
     const int32_t* pl = D.pl + r0;
@@ -825,11 +856,13 @@ __global__ __launch_bounds__(64) void k_utsolve(DevLayout D, const T* __restrict
         T* wr = w + (int64_t)r * n;
         for (int a = 0; a < m; a++) {
             const int c = r0 + pl[a];
-            T acc = T(0);
-            for (int64_t q = D.ut_ptr[c] + lane; q < D.ut_ptr[c + 1]; q += 64) acc += vals[D.ut_slot[q]] * wr[D.ut_row[q]];
-            for (int b = lane; b < a; b += 64) acc += P[(int64_t)b * W + pl[a]] * wr[r0 + b];
+            T acc = gather_sr<T, 256>(vals, D.ut_slot, D.ut_row, wr, D.ut_ptr[c], D.ut_ptr[c + 1], tid);
+            for (int b = tid; b < a; b += 256) acc += P[(int64_t)b * W + pl[a]] * wr[r0 + b];
             acc = wave_sum(acc);
-            if (lane == 0) wr[r0 + a] = (hr[c] - acc) / P[(int64_t)a * W + pl[a]];
+            if (lane == 0) part[wv] = acc;
+            __syncthreads();
+            if (tid == 0)
+                wr[r0 + a] = (hr[c] - ((part[0] + part[1]) + (part[2] + part[3]))) / P[(int64_t)a * W + pl[a]];
             __syncthreads();
         }
     }
@@ -837,12 +870,13 @@ __global__ __launch_bounds__(64) void k_utsolve(DevLayout D, const T* __restrict
 
 // L^T u = w in place: u_k = w_k - sum_{i>k} L(i,k) u_i, rows of a node in reverse
 template <typename T>
-__global__ __launch_bounds__(64) void k_ltsolve(DevLayout D, const T* __restrict__ vals,
-                                                const int32_t* __restrict__ nodes, int32_t count,
-                                                T* __restrict__ w, int32_t nrhs)
+__global__ __launch_bounds__(256) void k_ltsolve(DevLayout D, const T* __restrict__ vals,
+                                                 const int32_t* __restrict__ nodes, int32_t count,
+                                                 T* __restrict__ w, int32_t nrhs)
 {
+    __shared__ T part[4];
     const int v = nodes[blockIdx.x];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
     const T* P = vals + D.voff[v] + lw;
     const int32_t* pl = D.pl + r0;
@@ -851,11 +885,12 @@ __global__ __launch_bounds__(64) void k_ltsolve(DevLayout D, const T* __restrict
         T* wr = w + (int64_t)r * n;
         for (int a = m - 1; a >= 0; a--) {
             const int c = r0 + pl[a];          // L(i, r0+a) sits at the slot of column c
-            T acc = T(0);
-            for (int64_t q = D.lt_ptr[c] + lane; q < D.lt_ptr[c + 1]; q += 64) acc += vals[D.lt_slot[q]] * wr[D.lt_row[q]];
-            for (int b = a + 1 + lane; b < m; b += 64) acc += P[(int64_t)b * W + pl[a]] * wr[r0 + b];
+            T acc = gather_sr<T, 256>(vals, D.lt_slot, D.lt_row, wr, D.lt_ptr[c], D.lt_ptr[c + 1], tid);
+            for (int b = a + 1 + tid; b < m; b += 256) acc += P[(int64_t)b * W + pl[a]] * wr[r0 + b];
             acc = wave_sum(acc);
-            if (lane == 0) wr[r0 + a] -= acc;
+            if (lane == 0) part[wv] = acc;
+            __syncthreads();
+            if (tid == 0) wr[r0 + a] -= (part[0] + part[1]) + (part[2] + part[3]);
             __syncthreads();
         }
     }
@@ -2209,8 +2244,8 @@ hipError_t launch_utsolve(bool fp32, const DevLayout& D, const void* vals, const
                           const void* h, void* w, int32_t nrhs, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    if (fp32) hipLaunchKernelGGL(k_utsolve<float>, dim3(count), dim3(64), 0, st, D, (const float*)vals, nodes, count, (const float*)h, (float*)w, nrhs);
-    else hipLaunchKernelGGL(k_utsolve<double>, dim3(count), dim3(64), 0, st, D, (const double*)vals, nodes, count, (const double*)h, (double*)w, nrhs);
+    if (fp32) hipLaunchKernelGGL(k_utsolve<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (const float*)h, (float*)w, nrhs);
+    else hipLaunchKernelGGL(k_utsolve<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (const double*)h, (double*)w, nrhs);
     return hipGetLastError();
 }
 
@@ -2218,8 +2253,8 @@ hipError_t launch_ltsolve(bool fp32, const DevLayout& D, const void* vals, const
                           void* w, int32_t nrhs, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    if (fp32) hipLaunchKernelGGL(k_ltsolve<float>, dim3(count), dim3(64), 0, st, D, (const float*)vals, nodes, count, (float*)w, nrhs);
-    else hipLaunchKernelGGL(k_ltsolve<double>, dim3(count), dim3(64), 0, st, D, (const double*)vals, nodes, count, (double*)w, nrhs);
+    if (fp32) hipLaunchKernelGGL(k_ltsolve<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (float*)w, nrhs);
+    else hipLaunchKernelGGL(k_ltsolve<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (double*)w, nrhs);
     return hipGetLastError();
 }
 
