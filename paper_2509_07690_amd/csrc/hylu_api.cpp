@@ -1204,6 +1204,8 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         if (factor_rows_lds(h->fp32, stage, cap) > kLdsMax) continue;
         T.row_stage[l] = stage;
         T.row_cap[l] = cap;
+        // one long row per CU: eight wavefronts share its staging and updates
+        if (T.maxW[l] > 1024) T.row_nt[l] = 512;
     }
     T.sn_nt.assign(nl, 0);
     T.node_level.assign(L.nnodes, 0);

@@ -313,8 +313,10 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
             const int off = eoff[j];
             const int ws = eoff[j + 1] - off - 1;
             const int lp = elp[j];
+            // every thread forms l; the multiplier is stored after the barrier
+            // below (no later source of the batch touches this position: its
+            // columns lie right of its own pivot, so right of this one)
             const T l = xs[lp] / sval[off];
-            if (NT > 64) __syncthreads();
             // the accumulator values first, then the updates (distinct
             // positions within one source)
             for (int q0 = tid; q0 < ws; q0 += 4 * NT) {
@@ -332,9 +334,10 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
                     if (q < ws) xs[ix[u]] = xv[u] - l * sval[off + 1 + q];
                 }
             }
-            if (tid == 0) xs[lp] = l;
             __syncthreads();
+            if (tid == 0) xs[lp] = l;
         }
+        __syncthreads();
         e += nb;
     }
     if (D.m[v] == 1 && v < D.tail_node0 && e1 == eall && tid == 0) {
@@ -2128,12 +2131,14 @@ hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const i
     const dim3 g(nrows);
 #define ROWS_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_rows<TT, NTT>), g, dim3(NTT), sh, st, D, (TT*)vals, rows, ranges, nrows, cap, (TT)tau, pert, stage)
     if (fp32) {
-        if (nt == 256) ROWS_LAUNCH(float, 256);
+        if (nt == 512) ROWS_LAUNCH(float, 512);
+        else if (nt == 256) ROWS_LAUNCH(float, 256);
         else if (nt == 128) ROWS_LAUNCH(float, 128);
         else if (nt == 64) ROWS_LAUNCH(float, 64);
         else return hipErrorInvalidValue;
     } else {
-        if (nt == 256) ROWS_LAUNCH(double, 256);
+        if (nt == 512) ROWS_LAUNCH(double, 512);
+        else if (nt == 256) ROWS_LAUNCH(double, 256);
         else if (nt == 128) ROWS_LAUNCH(double, 128);
         else if (nt == 64) ROWS_LAUNCH(double, 64);
         else return hipErrorInvalidValue;
