@@ -1205,7 +1205,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         T.row_stage[l] = stage;
         T.row_cap[l] = cap;
         // one long row per CU: eight wavefronts share its staging and updates
-        if (T.maxW[l] > 1024) T.row_nt[l] = 512;
+        if (T.maxW[l] > 1024) T.row_nt[l] = 1024;
     }
     T.sn_nt.assign(nl, 0);
     T.node_level.assign(L.nnodes, 0);

@@ -2131,13 +2131,15 @@ hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const i
     const dim3 g(nrows);
 #define ROWS_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_rows<TT, NTT>), g, dim3(NTT), sh, st, D, (TT*)vals, rows, ranges, nrows, cap, (TT)tau, pert, stage)
     if (fp32) {
-        if (nt == 512) ROWS_LAUNCH(float, 512);
+        if (nt == 1024) ROWS_LAUNCH(float, 1024);
+        else if (nt == 512) ROWS_LAUNCH(float, 512);
         else if (nt == 256) ROWS_LAUNCH(float, 256);
         else if (nt == 128) ROWS_LAUNCH(float, 128);
         else if (nt == 64) ROWS_LAUNCH(float, 64);
         else return hipErrorInvalidValue;
     } else {
-        if (nt == 512) ROWS_LAUNCH(double, 512);
+        if (nt == 1024) ROWS_LAUNCH(double, 1024);
+        else if (nt == 512) ROWS_LAUNCH(double, 512);
         else if (nt == 256) ROWS_LAUNCH(double, 256);
         else if (nt == 128) ROWS_LAUNCH(double, 128);
         else if (nt == 64) ROWS_LAUNCH(double, 64);
