@@ -206,8 +206,8 @@ hylu_status hylu_export_factors(hylu_handle h, double* vals, int64_t* node_voff,
 hylu_status hylu_export_sizes(hylu_handle h, int64_t* ncols_total);
 
 /* Autotuner of the factorisation's launch shapes: for every level, the threads
- * given to one target row (64, 128 or 256) and to one supernode's internal
- * LU (64 or 256).  Runs `reps` rounds of three complete refactorisations with
+ * given to one target row (64, 128, 256 or 1024) and to one supernode's
+ * internal LU (64 or 256).  Runs `reps` rounds of four complete refactorisations with
  * d_val (each trial gives every level one shape; every shape computes
  * bit-identical factors), times each level's launches with HIP events on
  * `stream`, keeps the fastest shape per level and drops the refactorisation

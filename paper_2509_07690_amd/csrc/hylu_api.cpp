@@ -1744,10 +1744,11 @@ hylu_status hylu_autotune(hylu_handle h, const double* d_val, void* stream, int3
     hipStream_t st = (hipStream_t)stream;
     LevelTasks& T = h->ft;
     const int32_t nl = (int32_t)T.maxW.size();
-    static const int32_t kRowNT[3] = {64, 128, 256};
-    static const int32_t kSnNT[3] = {64, 256, 256};
+    constexpr int kTrials = 4;
+    static const int32_t kRowNT[kTrials] = {64, 128, 256, 1024};
+    static const int32_t kSnNT[kTrials] = {64, 256, 256, 256};
     // best[l][t]: shortest time of level l's row launch (snlu launch) under trial t
-    std::vector<std::array<double, 3>> trow(nl), tsn(nl);
+    std::vector<std::array<double, kTrials>> trow(nl), tsn(nl);
     for (auto& a : trow) a.fill(std::numeric_limits<double>::infinity());
     for (auto& a : tsn) a.fill(std::numeric_limits<double>::infinity());
     std::vector<int32_t> sn_levels;
@@ -1755,7 +1756,7 @@ hylu_status hylu_autotune(hylu_handle h, const double* d_val, void* stream, int3
     reps = std::max(reps, 1);
     hylu_status s = HYLU_OK;
     for (int32_t rep = 0; rep < reps && s == HYLU_OK; rep++)
-        for (int t = 0; t < 3 && s == HYLU_OK; t++) {
+        for (int t = 0; t < kTrials && s == HYLU_OK; t++) {
             T.tune_rows = kRowNT[t];
             T.tune_sn = kSnNT[t];
             h->prof.on = true;
@@ -1781,17 +1782,21 @@ hylu_status hylu_autotune(hylu_handle h, const double* d_val, void* stream, int3
     if (s != HYLU_OK) { h->sticky_error = true; return s; }
     double before = 0.0, after = 0.0;
     for (int32_t l = 0; l < T.pipe_level; l++) {
-        const int def = T.maxW[l] > 1024 ? 2 : 0;
+        // the built-in shape: 1024 threads for long rows of narrow levels, 256
+        // for other long rows, 64 otherwise
+        const bool narrow = T.row_ptr[l + 1] - T.row_ptr[l] <= kSideNarrowRows;
+        const int def = T.maxW[l] > 1024 ? (narrow ? 3 : 2) : 0;
         int best = 0;
-        for (int t = 1; t < 3; t++) if (trow[l][t] < trow[l][best]) best = t;
+        for (int t = 1; t < kTrials; t++) if (trow[l][t] < trow[l][best]) best = t;
         T.row_nt[l] = kRowNT[best];
         before += trow[l][def];
         after += trow[l][best];
         if (T.sn_ptr[l + 1] > T.sn_ptr[l]) {
-            const int sb = tsn[l][0] < std::min(tsn[l][1], tsn[l][2]) ? 0 : 1;
+            const double t256 = std::min(std::min(tsn[l][1], tsn[l][2]), tsn[l][3]);
+            const int sb = tsn[l][0] < t256 ? 0 : 1;
             T.sn_nt[l] = kSnNT[sb];
-            before += std::min(tsn[l][1], tsn[l][2]);
-            after += std::min(tsn[l][sb], sb ? tsn[l][2] : tsn[l][0]);
+            before += t256;
+            after += sb ? t256 : tsn[l][0];
         }
     }
     // graphs captured with the old choices are stale
