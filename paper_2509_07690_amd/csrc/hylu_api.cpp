@@ -359,7 +359,7 @@ hylu_status ensure_tlists(hylu_handle h)
 }
 
 // blocked right-looking LU of a dense view, one row panel at a time
-constexpr int32_t kGroupMinRows = 2048;
+constexpr int32_t kGroupMinRows = 1 << 30;
 // a factor level of fewer rows than this counts as narrow: deferred rows may
 // join its launch on the CUs it leaves idle
 constexpr int32_t kSideNarrowRows = 256;
