@@ -359,7 +359,9 @@ hylu_status ensure_tlists(hylu_handle h)
 }
 
 // blocked right-looking LU of a dense view, one row panel at a time
-constexpr int32_t kGroupMinRows = 1 << 30;
+constexpr int32_t kGroupMinRows = 2048;
+// a block-sparse tail of at least this many rows still takes panel groups
+constexpr int32_t kGroupTailRows = 16384;
 // a factor level of fewer rows than this counts as narrow: deferred rows may
 // join its launch on the CUs it leaves idle
 constexpr int32_t kSideNarrowRows = 256;
@@ -374,7 +376,7 @@ constexpr int32_t kLsolveSnMin = 8;
 // the group panels that contribute, in XCD order, and every TRSM the list of
 // its blocks that hold entries (row blocks without multipliers only write
 // zeros to lbuf); the rest is exactly zero and is skipped.
-void plan_dense(const std::vector<Layout::Panel>& panels, int32_t mT, int32_t nc, const TailMasks* M,
+void plan_dense(const std::vector<Layout::Panel>& panels, int32_t mT, int32_t nc, const TailMasks* M, bool group,
                 std::vector<DenseOp>& ops, std::vector<uint32_t>& lists)
 {
     ops.clear();
@@ -490,9 +492,10 @@ void plan_dense(const std::vector<Layout::Panel>& panels, int32_t mT, int32_t nc
         ops.push_back(o);
     };
     for (size_t i = 0; i < panels.size();) {
-        // grouping pays where the trailing matrix is large; near the end its
-        // extra launches cost more than the saved passes
-        const bool big = mT - panels[i].p1 >= kGroupMinRows;
+        // grouping pays where the trailing matrix is large and mostly dense;
+        // near the end, or where block sparsity leaves small per-panel
+        // updates, its extra launches cost more than the saved passes
+        const bool big = group && mT - panels[i].p1 >= kGroupMinRows;
         const size_t g1 = std::min(i + (size_t)(big ? kGroup : 1), panels.size());
         const int32_t kb0 = panels[i].p0, cg = panels[i].cg0;
         int32_t kofs[kGroup + 1] = {0, 0, 0, 0, 0};
@@ -1157,7 +1160,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 for (int32_t k = 0; k < L.m[v]; k += 64)
                     q.spanels.push_back({k, std::min(k + 64, L.m[v]), 0, L.m[v], 0});
                 std::vector<uint32_t> none;
-                plan_dense(q.panels, L.m[v], L.W[v] - L.lw[v], nullptr, q.ops, none);
+                plan_dense(q.panels, L.m[v], L.W[v] - L.lw[v], nullptr, true, q.ops, none);
                 h->dsn.push_back(std::move(q));
             } else {
                 T.snodes.push_back(v);
@@ -1185,8 +1188,20 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     if (L.mT > 0) {
         TailMasks M;
         if (opt.tail_sparse) tail_masks(h->sym, nd, L, M);
-        plan_dense(L.panels, L.mT, L.mT, opt.tail_sparse ? &M : nullptr, h->tail_ops, h->tail_list);
+        // panel groups for a large tail (each pass over its trailing matrix
+        // is costly: 27-point 64^3, 32786 rows, 4.68 vs 4.89 s) or where the
+        // plan keeps more than half of the dense work; not for a small sparse
+        // tail (circuit, 8315 rows: 29.4 vs 30.7 ms)
+        const TailMasks* Mp = opt.tail_sparse ? &M : nullptr;
+        plan_dense(L.panels, L.mT, L.mT, Mp, Mp == nullptr || L.mT >= kGroupTailRows, h->tail_ops, h->tail_list);
         for (const DenseOp& o : h->tail_ops) h->tail_flops += o.flops;
+        const double mTd = L.mT, dense_flops = 2.0 * mTd * mTd * mTd / 3.0;
+        if (Mp && L.mT < kGroupTailRows && h->tail_flops > 0.5 * dense_flops) {
+            h->tail_list.clear();
+            h->tail_flops = 0.0;
+            plan_dense(L.panels, L.mT, L.mT, Mp, true, h->tail_ops, h->tail_list);
+            for (const DenseOp& o : h->tail_ops) h->tail_flops += o.flops;
+        }
     }
     plog("tail plan");
     T.row_nt.assign(nl, 0);
