@@ -1187,21 +1187,24 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     h->tail_flops = 0.0;
     if (L.mT > 0) {
         TailMasks M;
-        if (opt.tail_sparse) tail_masks(h->sym, nd, L, M);
+        tail_masks(h->sym, nd, L, M);
         // panel groups for a large tail (each pass over its trailing matrix
         // is costly: 27-point 64^3, 32786 rows, 4.68 vs 4.89 s) or where the
-        // plan keeps more than half of the dense work; not for a small sparse
-        // tail (circuit, 8315 rows: 29.4 vs 30.7 ms)
-        const TailMasks* Mp = opt.tail_sparse ? &M : nullptr;
-        plan_dense(L.panels, L.mT, L.mT, Mp, Mp == nullptr || L.mT >= kGroupTailRows, h->tail_ops, h->tail_list);
-        for (const DenseOp& o : h->tail_ops) h->tail_flops += o.flops;
-        const double mTd = L.mT, dense_flops = 2.0 * mTd * mTd * mTd / 3.0;
-        if (Mp && L.mT < kGroupTailRows && h->tail_flops > 0.5 * dense_flops) {
-            h->tail_list.clear();
-            h->tail_flops = 0.0;
-            plan_dense(L.panels, L.mT, L.mT, Mp, true, h->tail_ops, h->tail_list);
-            for (const DenseOp& o : h->tail_ops) h->tail_flops += o.flops;
+        // block-sparse plan keeps more than half of the dense work; not for a
+        // small sparse tail (circuit, 8315 rows: 29.4 vs 30.7 ms).  The choice
+        // does not depend on tail_sparse, so both plans sum in the same order.
+        bool group = L.mT >= kGroupTailRows;
+        if (!group) {
+            std::vector<DenseOp> probe;
+            std::vector<uint32_t> plist;
+            plan_dense(L.panels, L.mT, L.mT, &M, false, probe, plist);
+            double fl = 0.0;
+            for (const DenseOp& o : probe) fl += o.flops;
+            const double mTd = L.mT;
+            group = fl > 0.5 * (2.0 * mTd * mTd * mTd / 3.0);
         }
+        plan_dense(L.panels, L.mT, L.mT, opt.tail_sparse ? &M : nullptr, group, h->tail_ops, h->tail_list);
+        for (const DenseOp& o : h->tail_ops) h->tail_flops += o.flops;
     }
     plog("tail plan");
     T.row_nt.assign(nl, 0);
