@@ -170,3 +170,27 @@ def test_batch_analysis_matches_members_and_oracle():
     # the levels of the union are the members' levels side by side
     assert inf["n_levels"][0] == max(hylu.Handle(a.row_ptr, a.col, a.val, dense_tail=0).info()["n_levels"][0]
                                      for a in members)
+
+
+def test_default_options_and_schedule_options_leave_the_analysis_alone():
+    """Defaults as documented in include/hylu.h; the options that only change
+    how the numerical work is launched (block-sparse tail, deferred-row
+    placement, block inverses) leave the symbolic result unchanged, and the
+    block-sparse tail issues fewer flops than the dense one."""
+    o = hylu.default_options()
+    assert (o.sn_dense, o.sn_tile, o.sn_inverse, o.tail_sparse, o.side_rows, o.pipeline_rows) == (64, 0, 1, 1, 1, 0)
+    A = synth.circuit_powerlaw(20000).A
+    ref = None
+    for opts in ({}, dict(tail_sparse=0), dict(side_rows=0), dict(sn_inverse=0)):
+        h = hylu.Handle(A.row_ptr, A.col, A.val, amd_dense=0.1, dense_tail=0.05, **opts)
+        sy, inf = h.symbolic(), h.info()
+        assert inf["tail_rows"] > 0
+        key = (inf["flops"], inf["nnz_l"], inf["nnz_u"], inf["n_supernodes"], inf["tail_rows"])
+        if ref is None:
+            ref, sy0, issued = key, sy, inf["flops_issued"]
+        else:
+            assert key == ref
+            for k in ("perm_r", "perm_c", "node_ptr", "levels"):
+                assert np.array_equal(sy[k], sy0[k]), k
+            if opts.get("tail_sparse") == 0:
+                assert inf["flops_issued"] > issued
