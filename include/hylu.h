@@ -84,9 +84,10 @@ typedef struct {
                               for it as one product with that inverse instead of a triangular solve (default 1) */
     int32_t tail_sparse;   /* 1: the dense tail's trailing updates and triangular solves skip the 64 x 64 blocks
                               that are zero by structure (same factors to the bit; default 1) */
-    int32_t side_rows;     /* 1: deferred standalone rows and tail rows whose sources are complete early take their
-                              updates on a second stream beside the narrow levels instead of in the final level
-                              (same factors; default 1) */
+    int32_t side_rows;     /* 1: deferred standalone rows and tail rows whose sources are complete early join the
+                              launches of the factor levels with fewer than 256 rows (a long tail row in pieces
+                              over several of them, its sources in order) instead of waiting for the final level;
+                              0: all of them in the final level (same factors either way; default 1) */
     int32_t pipeline_rows; /* reserved for the pipelined mode of Sec. 2.2.1 (one persistent launch whose
                               blocks wait per source node); switched off: must be 0, else HYLU_ERR_ARG */
 } hylu_options;
