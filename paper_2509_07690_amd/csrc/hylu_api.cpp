@@ -112,7 +112,14 @@ struct hylu_handle_s {
     TailView TV{};
     PipeCtl PC{};
     // large supernodes outside the tail, factored by the blocked dense kernels
-    struct DenseSn { int32_t v, level; TailView TV; std::vector<Layout::Panel> panels, spanels; std::vector<DenseOp> ops; };
+    struct DenseSn {
+        int32_t v, level;
+        TailView TV;
+        std::vector<Layout::Panel> panels, spanels;
+        std::vector<DenseOp> ops;
+        int32_t* d_sp = nullptr;            // solve panels (p0, p1 pairs)
+        void* d_inv = nullptr;              // inverses of their diagonal blocks (L and U, 64 x 64 each)
+    };
     std::vector<DenseOp> tail_ops;          // the dense tail's launches, block-sparse when its masks are known
     std::vector<uint32_t> tail_list;        // their tile / block lists
     uint32_t* d_tail_list = nullptr;
@@ -546,14 +553,26 @@ hylu_status enqueue_dense(hylu_handle h, const TailView& TV, const std::vector<D
 
 // the large supernodes of level l, spread over the side streams (forked from
 // and joined back into st; under capture they become parallel graph branches)
+// a large supernode's blocked LU, then the inverses of its solve panels'
+// diagonal blocks (used by its forward and backward solve steps)
+hylu_status enqueue_dsn(hylu_handle h, const hylu_handle_s::DenseSn& q, bool search, hipStream_t st)
+{
+    if (search) HIPCHK(launch_tail_init(q.TV, st));
+    hylu_status s = enqueue_dense(h, q.TV, q.ops, nullptr, search, st);
+    if (s != HYLU_OK) return s;
+    const double ns = (double)q.spanels.size();
+    LAUNCH(C_PANEL, (h->fp32 ? 4.0 : 8.0) * ns * 3.0 * kNB * kNB, ns * 2.0 * kNB * kNB * kNB / 3.0,
+           launch_tail_dinv(h->fp32, q.TV, h->vals, q.d_sp, (int32_t)q.spanels.size(), q.d_inv, st));
+    return HYLU_OK;
+}
+
 hylu_status enqueue_level_dense(hylu_handle h, int32_t l, bool search, hipStream_t st)
 {
     const int32_t d0 = h->dsn_ptr[l], d1 = h->dsn_ptr[l + 1];
     if (d1 == d0) return HYLU_OK;
     if (h->prof.on || d1 - d0 == 1) {          // one supernode, or measuring: stay on st
         for (int32_t q = d0; q < d1; q++) {
-            if (search) HIPCHK(launch_tail_init(h->dsn[q].TV, st));
-            hylu_status s = enqueue_dense(h, h->dsn[q].TV, h->dsn[q].ops, nullptr, search, st);
+            hylu_status s = enqueue_dsn(h, h->dsn[q], search, st);
             if (s != HYLU_OK) return s;
         }
         return HYLU_OK;
@@ -567,8 +586,7 @@ hylu_status enqueue_level_dense(hylu_handle h, int32_t l, bool search, hipStream
         int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         const TailView& TV = h->dsn[q].TV;
         load[j] += (double)TV.mT * TV.mT * TV.nc;
-        if (search) HIPCHK(launch_tail_init(TV, h->side[j]));
-        hylu_status s = enqueue_dense(h, TV, h->dsn[q].ops, nullptr, search, h->side[j]);
+        hylu_status s = enqueue_dsn(h, h->dsn[q], search, h->side[j]);
         if (s != HYLU_OK) return s;
     }
     for (int j = 0; j < k; j++) {
@@ -668,15 +686,27 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
             if (!dl || l >= dl->size()) continue;
             for (int32_t q : (*dl)[l]) {
                 const hylu_handle_s::DenseSn& d = h->dsn[q];
+                // one launch per solve panel with the diagonal blocks' inverses
+                const std::vector<Layout::Panel>& SP = d.spanels;
+                const int32_t ns = (int32_t)SP.size();
+                const size_t esz = f ? 4 : 8;
+                auto inv = [&](int32_t k, int kind) {
+                    return (const void*)((const char*)d.d_inv + ((size_t)2 * k + kind) * kNB * kNB * esz);
+                };
                 if (g == 4) {
                     LAUNCH(cls, 0, 0, launch_sn_lext(f, h->D, d.TV, h->vals, d.v, h->d_y, nrhs, st));
-                    for (const Layout::Panel& P : d.spanels)
-                        LAUNCH(cls, 0, 0, launch_tail_fwd(f, d.TV, h->vals, P.p0, P.p1, n, h->d_y, nrhs, st));
+                    LAUNCH(cls, 0, 0, launch_tail_step(f, d.TV, h->vals, 0, 0, SP[0].p0, SP[0].p1, inv(0, 0), n, h->d_y,
+                                                       h->d_y, nrhs, 0, st));
+                    for (int32_t k = 0; k + 1 < ns; k++)
+                        LAUNCH(cls, 0, 0, launch_tail_step(f, d.TV, h->vals, SP[k].p0, SP[k].p1, SP[k + 1].p0,
+                                                           SP[k + 1].p1, inv(k + 1, 0), n, h->d_y, h->d_y, nrhs, 0, st));
                 } else {
                     LAUNCH(cls, 0, 0, launch_sn_utext(f, h->D, d.TV, h->vals, d.v, h->d_y, h->d_z, nrhs, st));
-                    for (size_t k = d.spanels.size(); k-- > 0;)
-                        LAUNCH(cls, 0, 0, launch_tail_bwd(f, d.TV, h->vals, d.spanels[k].p0, d.spanels[k].p1, n,
-                                                          h->d_y, h->d_z, nrhs, st));
+                    LAUNCH(cls, 0, 0, launch_tail_step(f, d.TV, h->vals, 0, 0, SP[ns - 1].p0, SP[ns - 1].p1,
+                                                       inv(ns - 1, 1), n, h->d_y, h->d_z, nrhs, 1, st));
+                    for (int32_t k = ns - 1; k > 0; k--)
+                        LAUNCH(cls, 0, 0, launch_tail_step(f, d.TV, h->vals, SP[k].p0, SP[k].p1, SP[k - 1].p0,
+                                                           SP[k - 1].p1, inv(k - 1, 1), n, h->d_y, h->d_z, nrhs, 1, st));
                 }
             }
         }
@@ -857,6 +887,11 @@ hylu_status upload_device(hylu_handle h)
             q.TV.trow = trow; q.TV.tlo = tlo; q.TV.thi = thi; q.TV.tpiv = tpiv; q.TV.tstep = tstep;
             q.TV.lbuf = dalloc(h, (size_t)64 * kGroup * m * (h->fp32 ? 4 : 8));
             if (!q.TV.lbuf) return HYLU_ERR_OOM;
+            std::vector<int32_t> sp;
+            for (const Layout::Panel& P : q.spanels) { sp.push_back(P.p0); sp.push_back(P.p1); }
+            UP(q.d_sp, sp);
+            q.d_inv = dalloc(h, std::max<size_t>(q.spanels.size(), 1) * 2 * kNB * kNB * (h->fp32 ? 4 : 8));
+            if (!q.d_inv) return HYLU_ERR_OOM;
         }
         if (!h->dsn.empty()) {
             std::vector<uint8_t> fl(L.nnodes, 0);
