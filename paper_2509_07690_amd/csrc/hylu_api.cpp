@@ -753,9 +753,24 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
             LAUNCH(C_TSOLVE, 0, 0, launch_tail_utext(f, h->D, h->TV, h->vals, h->d_y, h->d_z, nrhs, st));
-            for (const Layout::Panel& P : L.spanels) LAUNCH(C_TSOLVE, 0, 0, launch_tail_ut(f, h->TV, h->vals, P.p0, P.p1, n, h->d_y, h->d_z, nrhs, st));
-            for (size_t k = L.spanels.size(); k-- > 0;)
-                LAUNCH(C_TSOLVE, 0, 0, launch_tail_lt(f, h->TV, h->vals, L.spanels[k].p0, L.spanels[k].p1, n, h->d_z, nrhs, st));
+            // U^T ascending, then L^T descending: one launch per solve panel
+            // with the transposed inverses of the diagonal blocks
+            const std::vector<Layout::Panel>& SP = L.spanels;
+            const int32_t ns = (int32_t)SP.size();
+            const size_t esz = f ? 4 : 8;
+            auto inv = [&](int32_t k, int kind) {
+                return (const void*)((const char*)h->d_tinv + ((size_t)2 * k + kind) * kNB * kNB * esz);
+            };
+            LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, 0, 0, SP[0].p0, SP[0].p1, inv(0, 1), n, h->d_y,
+                                                    h->d_z, nrhs, 2, st));
+            for (int32_t k = 0; k + 1 < ns; k++)
+                LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, SP[k].p0, SP[k].p1, SP[k + 1].p0, SP[k + 1].p1,
+                                                        inv(k + 1, 1), n, h->d_y, h->d_z, nrhs, 2, st));
+            LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, 0, 0, SP[ns - 1].p0, SP[ns - 1].p1, inv(ns - 1, 0), n,
+                                                    h->d_z, h->d_z, nrhs, 3, st));
+            for (int32_t k = ns - 1; k > 0; k--)
+                LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, SP[k].p0, SP[k].p1, SP[k - 1].p0, SP[k - 1].p1,
+                                                        inv(k - 1, 0), n, h->d_z, h->d_z, nrhs, 3, st));
         }
         s = levels(3, [&](const int32_t* nodes, int32_t c, size_t) { return launch_ltsolve(f, h->D, h->vals, nodes, c, h->d_z, nrhs, st); });
         if (s != HYLU_OK) return s;

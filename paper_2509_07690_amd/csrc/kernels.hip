@@ -1901,13 +1901,15 @@ __global__ __launch_bounds__(64) void k_tail_dinv(TailView TV, const T* __restri
     for (int idx = lane; idx < kNB * kNB; idx += 64) O[idx] = X[idx & (kNB - 1)][idx >> 6];
 }
 
-// one launch per solve panel of the tail: the rows past the next panel take
-// the current panel [p0, p1)'s contribution (one wavefront per row, as
-// k_tail_gemv), and workgroup 0 brings the next panel [q0, q1)'s rows up to
-// date and solves its diagonal block with its inverse inv (column-major).
-// mode 0: forward with L, ascending, y in place; mode 1: backward with U,
-// descending, the solution to x at the pivot columns.  p0 == p1: the next
-// panel's diagonal solve only.
+// one launch per solve panel of a dense view: the targets past the next panel
+// take the current panel [p0, p1)'s contribution (one wavefront each, as
+// k_tail_gemv), and workgroup 0 brings the next panel [q0, q1)'s targets up to
+// date and solves its diagonal block with its inverse inv (column-major;
+// transposed for modes 2 and 3).  mode 0: L, ascending, y in place; mode 1: U,
+// descending, the solution to x at the pivot columns; mode 2: U^T, ascending,
+// h in y, w to x; mode 3: L^T, descending, w in place in x.  A target is a row
+// (modes 0, 1, 3) or a column (mode 2: only those pivoted after the next
+// panel).  p0 == p1: the next panel's diagonal solve only.
 template <typename T>
 __global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restrict__ vals, int p0, int p1, int q0, int q1,
                                                    const T* __restrict__ inv, int n, T* __restrict__ y,
@@ -1918,27 +1920,31 @@ __global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restr
     __shared__ int64_t rowq[kNB];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int np = p1 - p0, nq = q1 - q0, t0 = TV.t0;
+    const bool tr = mode >= 2;
     const int b = p0 + lane;
     const int pb = lane < np ? TV.tpiv[b] : 0;
+    const int64_t rb = (tr && lane < np) ? TV.trow[b] : 0;    // row b of the current panel
+    // coefficient of target e for the current panel's lane b:
+    //   modes 0, 1: X_e[piv b];  mode 2: X_b[e];  mode 3: X_b[piv e]
     if (blockIdx.x == 0) {
         // every load of a phase is issued before its first use: wavefront w
-        // takes the next panel's rows w, w+4, ..; the inverse's columns are
+        // takes the next panel's targets w, w+4, ..; the inverse's columns are
         // split the same way and the four partial sums combined in LDS
         const int t = threadIdx.x;
-        if (t < nq) rowq[t] = TV.trow[q0 + t];
+        if (t < nq) rowq[t] = mode <= 1 ? TV.trow[q0 + t] : (int64_t)TV.tpiv[q0 + t];
         __syncthreads();
         T c[kNB / 4], iv[kNB / 4];
 #pragma unroll
         for (int q = 0; q < kNB / 4; q++) {
             const int i = wv + 4 * q;
-            c[q] = (i < nq && lane < np) ? vals[rowq[i] + pb] : T(0);
-            iv[q] = (i < nq && lane < nq) ? inv[i * kNB + lane] : T(0);
+            c[q] = (i < nq && lane < np) ? (mode <= 1 ? vals[rowq[i] + pb] : vals[rb + rowq[i]]) : T(0);
+            iv[q] = (i < nq && lane < nq) ? (tr ? inv[lane * kNB + i] : inv[i * kNB + lane]) : T(0);
         }
         for (int r = 0; r < nrhs; r++) {
             T* yr = y + (int64_t)r * n + t0;
             T* xr = x + (int64_t)r * n + t0;
-            const T v = lane < np ? (mode == 0 ? yr[b] : xr[pb]) : T(0);
-            if (t < nq) ys[t] = yr[q0 + t];
+            const T v = lane < np ? (mode == 0 ? yr[b] : mode == 1 ? xr[pb] : xr[b]) : T(0);
+            if (t < nq) ys[t] = mode <= 1 ? yr[q0 + t] : mode == 2 ? yr[rowq[t]] : xr[q0 + t];
             __syncthreads();
             if (np > 0) {
 #pragma unroll
@@ -1961,7 +1967,8 @@ __global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restr
             if (t < nq) {
                 const T o = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
                 if (mode == 0) yr[q0 + t] = o;
-                else xr[TV.tpiv[q0 + t]] = o;
+                else if (mode == 1) xr[TV.tpiv[q0 + t]] = o;
+                else xr[q0 + t] = o;
             }
             __syncthreads();
         }
@@ -1970,13 +1977,22 @@ __global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restr
     const int k = (blockIdx.x - 1) * 4 + wv;
     if (k >= count) return;
     const int e = first + k;
-    const T coef = lane < np ? vals[TV.trow[e] + pb] : T(0);
+    if (mode == 2 && TV.tstep[e] < q1) return;             // a column solved at or before the next panel
+    T coef = T(0);
+    if (lane < np) {
+        if (mode <= 1) coef = vals[TV.trow[e] + pb];
+        else if (mode == 2) coef = vals[rb + e];
+        else coef = vals[rb + TV.tpiv[e]];
+    }
     for (int r = 0; r < nrhs; r++) {
         T* yr = y + (int64_t)r * n + t0;
-        const T* xr = x + (int64_t)r * n + t0;
-        const T v = lane < np ? (mode == 0 ? yr[b] : xr[pb]) : T(0);
+        T* xr = x + (int64_t)r * n + t0;
+        const T v = lane < np ? (mode == 0 ? yr[b] : mode == 1 ? xr[pb] : xr[b]) : T(0);
         const T acc = wave_sum(coef * v);
-        if (lane == 0) yr[e] -= acc;
+        if (lane == 0) {
+            if (mode == 3) xr[e] -= acc;
+            else yr[e] -= acc;
+        }
     }
 }
 
@@ -2461,12 +2477,15 @@ hipError_t launch_tail_step(bool fp32, const TailView& T, const void* vals, int3
                             const void* inv, int32_t n, void* y, void* x, int32_t nrhs, int32_t mode, hipStream_t st)
 {
     const int np = p1 - p0, nq = q1 - q0;
-    if (np < 0 || np > kNB || nq <= 0 || nq > kNB || (mode != 0 && mode != 1)) return hipErrorInvalidValue;
-    if (np > 0 && (mode == 0 ? q0 != p1 : q1 != p0)) return hipErrorInvalidValue;
+    if (np < 0 || np > kNB || nq <= 0 || nq > kNB || mode < 0 || mode > 3) return hipErrorInvalidValue;
+    const bool asc = mode == 0 || mode == 2;
+    if (np > 0 && (asc ? q0 != p1 : q1 != p0)) return hipErrorInvalidValue;
     if (q0 < 0 || q1 > T.mT) return hipErrorInvalidValue;
+    if (mode == 2 && T.nc != T.mT) return hipErrorInvalidValue;   // columns of the tail only
     int first = 0, count = 0;
     if (np > 0) {
         if (mode == 0) { first = q1; count = T.mT - q1; }
+        else if (mode == 2) { first = 0; count = T.mT; }
         else { first = 0; count = q0; }
     }
     const unsigned grid = 1u + nblk(count, 4);

@@ -122,9 +122,11 @@ hipError_t launch_tail_utext(bool fp32, const DevLayout& D, const TailView& T, c
 // panel s's at out + (2 s + {0, 1}) * 64 * 64 values
 hipError_t launch_tail_dinv(bool fp32, const TailView& T, const void* vals, const int32_t* spanels, int32_t nsp,
                             void* out, hipStream_t st);
-// one step of the tail's forward (mode 0) or backward (mode 1) solve: the
-// contribution of panel [p0, p1) to every row still to come, and the diagonal
-// solve of the next panel [q0, q1) (adjacent to it) with its inverse inv
+// one step of a dense view's forward (mode 0, L) or backward (mode 1, U) solve,
+// or of the transposed ones (mode 2, U^T ascending; mode 3, L^T descending;
+// the tail only): the contribution of panel [p0, p1) to every target still to
+// come, and the diagonal solve of the next panel [q0, q1) (adjacent to it)
+// with its inverse inv (L's for modes 0 and 3, U's for 1 and 2)
 hipError_t launch_tail_step(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t q0, int32_t q1,
                             const void* inv, int32_t n, void* y, void* x, int32_t nrhs, int32_t mode, hipStream_t st);
 hipError_t launch_tail_fwd(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
