@@ -1794,62 +1794,6 @@ __global__ __launch_bounds__(256) void k_tail_utext(DevLayout D, TailView TV, co
     }
 }
 
-// mode 0 forward (L, ascending), 1 backward (U, descending),
-// 2 U^T (ascending), 3 L^T (descending): the panel's own triangle, one wave;
-// M[i][j] = X_{p0+i}[tpiv[p0+j]] holds L below and U_st on/above the diagonal.
-// Column sweep: lane r holds v[r]; at step a the finished value is broadcast
-// and every lane still waiting subtracts its coefficient times it.
-template <typename T>
-__global__ __launch_bounds__(64) void k_tail_tri(TailView TV, const T* __restrict__ vals, int p0, int p1, int n,
-                                                 T* __restrict__ y, T* __restrict__ x, int nrhs, int mode)
-{
-    __shared__ T M[kNB][kNB + 1];
-    __shared__ int piv[kNB];
-    __shared__ int64_t ro[kNB];
-    const int lane = threadIdx.x;
-    const int np = p1 - p0;
-    const int t0 = TV.t0;
-    if (lane < np) { piv[lane] = TV.tpiv[p0 + lane]; ro[lane] = TV.trow[p0 + lane]; }
-    __syncthreads();
-    if (lane < np) {
-        const int pc = piv[lane];
-        T tmp[kNB];
-#pragma unroll
-        for (int i = 0; i < kNB; i++) tmp[i] = i < np ? vals[ro[i] + pc] : T(0);
-#pragma unroll
-        for (int i = 0; i < kNB; i++) M[i][lane] = tmp[i];
-    }
-    __syncthreads();
-    const bool desc = mode == 1 || mode == 3;
-    for (int r = 0; r < nrhs; r++) {
-        T* yr = y + (int64_t)r * n + t0;
-        T* xr = x + (int64_t)r * n + t0;
-        T v = T(0);
-        if (lane < np) {
-            if (mode == 0 || mode == 1) v = yr[p0 + lane];
-            else if (mode == 2) v = yr[piv[lane]];
-            else v = xr[p0 + lane];
-        }
-        for (int s2 = 0; s2 < np; s2++) {
-            const int a = desc ? np - 1 - s2 : s2;
-            T va = bcast(v, a);
-            if (mode == 1 || mode == 2) va = va / M[a][a];
-            if (lane == a) v = va;
-            const bool pend = desc ? lane < a : (lane > a && lane < np);
-            if (pend) {
-                // 0: L(r,a) = M[r][a]   1: U(r, piv a) = M[r][a]   2: U(a, piv r) = M[a][r]   3: L(a, r) = M[a][r]
-                const T c = (mode == 0 || mode == 1) ? M[lane][a] : M[a][lane];
-                v -= c * va;
-            }
-        }
-        if (lane < np) {
-            if (mode == 0) yr[p0 + lane] = v;
-            else if (mode == 1) xr[piv[lane]] = v;
-            else xr[p0 + lane] = v;
-        }
-    }
-}
-
 // inverses of the diagonal blocks of the solve panels: for panel s = [p0, p1)
 // with M[i][j] = X_{p0+i}[tpiv[p0+j]] (L strictly below the diagonal, U_st on
 // and above it, both in pivot order), kind 0 writes (I + L)^-1 and kind 1
@@ -1902,8 +1846,8 @@ __global__ __launch_bounds__(64) void k_tail_dinv(TailView TV, const T* __restri
 }
 
 // one launch per solve panel of a dense view: the targets past the next panel
-// take the current panel [p0, p1)'s contribution (one wavefront each, as
-// k_tail_gemv), and workgroup 0 brings the next panel [q0, q1)'s targets up to
+// take the current panel [p0, p1)'s contribution (one wavefront each, its
+// lanes over the panel's 64 columns), and workgroup 0 brings the next panel [q0, q1)'s targets up to
 // date and solves its diagonal block with its inverse inv (column-major;
 // transposed for modes 2 and 3).  mode 0: L, ascending, y in place; mode 1: U,
 // descending, the solution to x at the pivot columns; mode 2: U^T, ascending,
@@ -1992,48 +1936,6 @@ __global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restr
         if (lane == 0) {
             if (mode == 3) xr[e] -= acc;
             else yr[e] -= acc;
-        }
-    }
-}
-
-// the panel's contribution to the rest of the tail, one wavefront per row or
-// column: mode 0 rows r >= p1: y_r -= sum_b X_r[piv b] y_b
-//         mode 1 rows r < p0:  y_r -= sum_b X_r[piv b] x[piv b]
-//         mode 2 columns c:     h_c -= sum_b X_b[c] w_b  (c pivoted after p1)
-//         mode 3 rows a < p0:  w_a -= sum_b X_b[piv a] u_b
-template <typename T>
-__global__ __launch_bounds__(256) void k_tail_gemv(TailView TV, const T* __restrict__ vals, int p0, int p1, int n,
-                                                   T* __restrict__ y, T* __restrict__ x, int nrhs, int mode,
-                                                   int first, int count)
-{
-    const int lane = threadIdx.x & 63;
-    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (k >= count) return;
-    const int e = first + k;              // row or column index, tail-local
-    const int np = p1 - p0;
-    const int t0 = TV.t0;
-    const int b = p0 + lane;
-    T coef = T(0);
-    if (lane < np) {
-        if (mode == 0 || mode == 1) coef = vals[TV.trow[e] + TV.tpiv[b]];
-        else if (mode == 2) coef = vals[TV.trow[b] + e];
-        else coef = vals[TV.trow[b] + TV.tpiv[e]];
-    }
-    if (mode == 2 && TV.tstep[e] < p1) return;
-    for (int r = 0; r < nrhs; r++) {
-        T* yr = y + (int64_t)r * n + t0;
-        T* xr = x + (int64_t)r * n + t0;
-        T v = T(0);
-        if (lane < np) {
-            if (mode == 0) v = yr[b];
-            else if (mode == 1) v = xr[TV.tpiv[b]];
-            else v = xr[b];
-        }
-        T acc = wave_sum(coef * v);
-        if (lane == 0) {
-            if (mode == 0 || mode == 1) yr[e] -= acc;
-            else if (mode == 2) yr[e] -= acc;
-            else xr[e] -= acc;
         }
     }
 }
@@ -2428,42 +2330,6 @@ hipError_t launch_tail_utext(bool fp32, const DevLayout& D, const TailView& T, c
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t tail_step(const TailView& TV, const T* vals, int32_t p0, int32_t p1, int32_t n, T* y, T* x,
-                            int32_t nrhs, int mode, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_tail_tri<T>, dim3(1), dim3(64), 0, st, TV, vals, p0, p1, n, y, x, nrhs, mode);
-    int first, count;
-    if (mode == 0) { first = p1; count = TV.mT - p1; }
-    else if (mode == 2) { first = 0; count = TV.mT; }
-    else { first = 0; count = p0; }
-    if (count > 0)
-        hipLaunchKernelGGL(k_tail_gemv<T>, dim3(nblk(count, 4)), dim3(256), 0, st, TV, vals, p0, p1, n, y, x, nrhs, mode,
-                           first, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_tail_fwd(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
-                           void* y, int32_t nrhs, hipStream_t st)
-{
-    if (fp32) return tail_step<float>(T, (const float*)vals, p0, p1, n, (float*)y, (float*)y, nrhs, 0, st);
-    return tail_step<double>(T, (const double*)vals, p0, p1, n, (double*)y, (double*)y, nrhs, 0, st);
-}
-
-hipError_t launch_tail_bwd(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
-                           void* y, void* x, int32_t nrhs, hipStream_t st)
-{
-    if (fp32) return tail_step<float>(T, (const float*)vals, p0, p1, n, (float*)y, (float*)x, nrhs, 1, st);
-    return tail_step<double>(T, (const double*)vals, p0, p1, n, (double*)y, (double*)x, nrhs, 1, st);
-}
-
-hipError_t launch_tail_ut(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
-                          void* h, void* w, int32_t nrhs, hipStream_t st)
-{
-    if (fp32) return tail_step<float>(T, (const float*)vals, p0, p1, n, (float*)h, (float*)w, nrhs, 2, st);
-    return tail_step<double>(T, (const double*)vals, p0, p1, n, (double*)h, (double*)w, nrhs, 2, st);
-}
-
 hipError_t launch_tail_dinv(bool fp32, const TailView& T, const void* vals, const int32_t* spanels, int32_t nsp,
                             void* out, hipStream_t st)
 {
@@ -2494,13 +2360,6 @@ hipError_t launch_tail_step(bool fp32, const TailView& T, const void* vals, int3
     else hipLaunchKernelGGL(k_tail_step<double>, dim3(grid), dim3(256), 0, st, T, (const double*)vals, p0, p1, q0, q1,
                             (const double*)inv, n, (double*)y, (double*)x, nrhs, mode, first, count);
     return hipGetLastError();
-}
-
-hipError_t launch_tail_lt(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
-                          void* w, int32_t nrhs, hipStream_t st)
-{
-    if (fp32) return tail_step<float>(T, (const float*)vals, p0, p1, n, (float*)w, (float*)w, nrhs, 3, st);
-    return tail_step<double>(T, (const double*)vals, p0, p1, n, (double*)w, (double*)w, nrhs, 3, st);
 }
 
 }  // namespace hylu

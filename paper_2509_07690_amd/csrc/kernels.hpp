@@ -129,14 +129,6 @@ hipError_t launch_tail_dinv(bool fp32, const TailView& T, const void* vals, cons
 // with its inverse inv (L's for modes 0 and 3, U's for 1 and 2)
 hipError_t launch_tail_step(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t q0, int32_t q1,
                             const void* inv, int32_t n, void* y, void* x, int32_t nrhs, int32_t mode, hipStream_t st);
-hipError_t launch_tail_fwd(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
-                           void* y, int32_t nrhs, hipStream_t st);
-hipError_t launch_tail_bwd(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
-                           void* y, void* x, int32_t nrhs, hipStream_t st);
-hipError_t launch_tail_ut(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
-                          void* h, void* w, int32_t nrhs, hipStream_t st);
-hipError_t launch_tail_lt(bool fp32, const TailView& T, const void* vals, int32_t p0, int32_t p1, int32_t n,
-                          void* w, int32_t nrhs, hipStream_t st);
 // one large supernode's rows (dense view TV, node v): forward, the L-region
 // gather y_i -= sum_{t < lw} L(i, t) y[source of t]; backward, the T-region
 // gather y_i -= sum_{t in T} U(i, t) x[column t] (before its block panels)
