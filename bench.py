@@ -373,7 +373,7 @@ def cpu_baseline(A0, base, h, nref, first):
     t = time.perf_counter()
     o.analyse()
     t_sym = time.perf_counter() - t
-    tau = h.info()["pivot_tau"]
+    tau = o.pivot_tau()                 # from the oracle's own B (analysed values)
     o.numeric(tau)
     piv = o.factors()[-1]
     times = []

@@ -46,6 +46,8 @@ def _load():
         lib.orc_check_matching.argtypes = [P, C.c_double]
         lib.orc_partition.argtypes = [P, C.c_int32, C.c_int32]
         lib.orc_numeric.argtypes = [P, C.c_double, C.c_int, P]
+        lib.orc_pivot_tau.argtypes = [P, C.c_double]
+        lib.orc_pivot_tau.restype = C.c_double
         lib.orc_solve.argtypes = [P, P, P]
         lib.orc_solve_transposed.argtypes = [P, P, P]
         lib.orc_residual.argtypes = [P, P, P, P]
@@ -133,6 +135,11 @@ class Oracle:
 
     def analyse(self, sn_min=2, sn_max=1 << 30):
         return self.symbolic().partition(sn_min, sn_max).levels()
+
+    def pivot_tau(self, rel=float(np.sqrt(np.finfo(np.float64).eps))):
+        """Perturbation threshold rel * max|B| from the oracle's own B (the
+        values it holds now: take it before set_values for a refactorisation)."""
+        return float(self.lib.orc_pivot_tau(self.h, float(rel)))
 
     def numeric(self, tau, piv=None):
         pv = _c(piv, np.int32)

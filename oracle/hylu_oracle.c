@@ -468,6 +468,20 @@ int orc_levels(orc *o)
 /* and pivot perturbation (Sec. 2.2)                                         */
 /* ------------------------------------------------------------------------ */
 
+/* Perturbation threshold of Sec. 2.2 (the paper names the technique, not its
+ * value): rel * max |b_ij| over this oracle's own B, 1 when B is all zero.
+ * With rel = sqrt(eps) and B scaled to max |b_ij| = 1 by the static pivoting
+ * this is the usual tiny-pivot replacement level.  Read on the values B holds
+ * when it is called: for a refactorisation the threshold of the analysed
+ * values is taken before orc_set_values. */
+double orc_pivot_tau(const orc *o, double rel)
+{
+    double m = 0.0;
+    for (int64_t q = 0; q < o->brp[o->n]; q++)
+        if (fabs(o->bv[q]) > m) m = fabs(o->bv[q]);
+    return rel * (m > 0 ? m : 1.0);
+}
+
 /* pivot_search = 1: choose pivots; 0: reuse piv_in (refactorisation). */
 int orc_numeric(orc *o, double tau, int pivot_search, const int32_t *piv_in)
 {

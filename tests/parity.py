@@ -5,11 +5,22 @@ import oracle
 
 
 def oracle_for(h, A, sn_min=2, sn_max=1 << 30):
-    """The oracle on A with the permutations and scalings the library chose."""
+    """The oracle on A (the analysed values) with the permutations and
+    scalings the library chose.  o.tau is the perturbation threshold the
+    oracle computes from its own B; it must equal the library's."""
     sym = h.symbolic()
     o = oracle.Oracle(A.n, A.row_ptr, A.col, A.val, sym["perm_r"], sym["perm_c"], sym["dr"], sym["dc"])
     o.analyse(sn_min, sn_max)
+    o.tau = checked_tau(h, o)
     return o, sym
+
+
+def checked_tau(h, o):
+    """tau = sqrt(eps) max|B| of the oracle's B (the analysed values), checked
+    against the threshold the library reports."""
+    tau = o.pivot_tau()
+    assert tau == h.info()["pivot_tau"], (tau, h.info()["pivot_tau"])
+    return tau
 
 
 def _match(gkey, gval, okey, oval):

@@ -47,7 +47,7 @@ def test_gradient_against_oracle_and_fd(hylu, side):
     h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd")
     loss, x, gval, gb = _loss_grad(hylu, h, A, b, xt)
     o, _ = oracle_for(h, A)
-    o.numeric(h.info()["pivot_tau"])
+    o.numeric(o.tau)
     xo = o.solve(b)
     lam = o.solve_transposed(xo - xt)
     go = o.gradient_values(lam, xo)
@@ -95,7 +95,7 @@ def test_gradient_multi_rhs_and_refactor_between(hylu):
     loss = 0.5 * ((X - dev(T)) ** 2).sum()
     loss.backward()
     o, _ = oracle_for(h, A)
-    o.numeric(h.info()["pivot_tau"], piv=hylu.factors_as_rows(h)[2])   # pivots of the first factorisation
+    o.numeric(o.tau, piv=hylu.factors_as_rows(h)[2])   # pivots of the first factorisation
     g = np.zeros(A.nnz)
     for k in range(3):
         xk = o.solve(B[:, k])

@@ -16,7 +16,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2509_07690_amd import synth  # noqa: E402
-from parity import compare_factors, rel_diff  # noqa: E402
+from parity import checked_tau, compare_factors, rel_diff  # noqa: E402
 import oracle  # noqa: E402
 
 MEMBERS = range(8)
@@ -46,9 +46,12 @@ def _union(hb, vals):
 
 
 def _oracle(hb, U):
+    """The oracle on the union with the analysed values U; o.tau from its own
+    B, checked against the library's threshold."""
     sym = hb.symbolic()
     o = oracle.Oracle(U.n, U.row_ptr, U.col, U.val, sym["perm_r"], sym["perm_c"], sym["dr"], sym["dc"])
     o.analyse()
+    o.tau = checked_tau(hb, o)
     return o
 
 
@@ -62,7 +65,7 @@ def test_batch_factor_and_solve(hylu, batch, precision):
     hb.factorize(dev(U0.val))
     torch.cuda.synchronize()
     o = _oracle(hb, U0)
-    tau = hb.info()["pivot_tau"] if precision == "fp64" else np.sqrt(np.finfo(np.float64).eps)
+    tau = o.tau
     o.numeric(tau)
     if precision == "fp64":
         compare_factors(hb, o)
@@ -109,6 +112,7 @@ def test_autotune_keeps_factors(hylu, batch):
     piv = hylu.factors_as_rows(hb)[2]
     hb.refactor(dev(U1.val))
     torch.cuda.synchronize()
-    o = _oracle(hb, U1)
-    o.numeric(hb.info()["pivot_tau"], piv=piv)
+    o = _oracle(hb, U0)
+    o.set_values(U1.val)
+    o.numeric(o.tau, piv=piv)
     compare_factors(hb, o)

@@ -50,7 +50,7 @@ def test_circuit_full_factors_and_solution(hylu):
     x = h.solve(dev(w.b[:, 0])).cpu().numpy()
     o, _ = oracle_for(h, A)
     o.set_values(w.A.val)
-    o.numeric(h.info()["pivot_tau"], piv=piv)
+    o.numeric(o.tau, piv=piv)
     compare_factors(h, o)
     xo = o.solve(w.b[:, 0])
     assert rel_diff(x, xo) <= 1e-10

@@ -36,7 +36,7 @@ def run_case(hylu, A, b, opts=None, sn=(2, 1 << 30), exact=False, tol=1e-11):
     vals = dev(A.val)
     h.factorize(vals)
     torch.cuda.synchronize()
-    o.numeric(h.info()["pivot_tau"])
+    o.numeric(o.tau)
     assert h.info()["n_perturbed"] == o.sizes()["n_perturbed"]
     compare_factors(h, o, tol=tol, exact=exact)
     x = h.solve(dev(b)).cpu().numpy()
@@ -137,7 +137,7 @@ def test_config0_refactor_and_transpose(hylu, tail, pipe):
         h.refactor(v2)
         torch.cuda.synchronize()
         o.set_values(A2.val)
-        o.numeric(h.info()["pivot_tau"], piv=piv)
+        o.numeric(o.tau, piv=piv)
         compare_factors(h, o)
         b = A2.matvec(w.x_true[:, 0])
         x = h.solve(dev(b)).cpu().numpy()
@@ -154,7 +154,7 @@ def test_multiple_rhs(hylu):
     h = hylu.Handle(A.row_ptr, A.col, A.val)
     o, _ = oracle_for(h, A)
     h.factorize(dev(A.val))
-    o.numeric(h.info()["pivot_tau"])
+    o.numeric(o.tau)
     B = np.random.default_rng(3).uniform(-1, 1, (A.n, 5))
     X = h.solve_cols(dev(B.T.copy())).cpu().numpy().T
     for k in range(5):
@@ -167,7 +167,7 @@ def test_fp32_with_refinement(hylu):
     h = hylu.Handle(A.row_ptr, A.col, A.val, precision="fp32")
     o, _ = oracle_for(h, A)
     h.factorize(dev(A.val))
-    o.numeric(TAU64)
+    o.numeric(o.tau)
     b = w.b[:, 0]
     x = h.solve(dev(b)).cpu().numpy()
     eta, _ = o.backward_error(b, x)
@@ -207,7 +207,7 @@ def test_small_circuit(hylu, pipe):
     h.refactor(dev(w2.A.val))
     torch.cuda.synchronize()
     o.set_values(w2.A.val)
-    o.numeric(h.info()["pivot_tau"], piv=piv)
+    o.numeric(o.tau, piv=piv)
     compare_factors(h, o)
 
 
@@ -232,7 +232,7 @@ def test_grid3d_blocked_supernodes(hylu, side, sn_dense, tail, tile, inv):
     h.refactor(dev(A2.val))
     torch.cuda.synchronize()
     o.set_values(A2.val)
-    o.numeric(h.info()["pivot_tau"], piv=piv)
+    o.numeric(o.tau, piv=piv)
     compare_factors(h, o, tol="derived")
     compare_backward_stability(h, o)
 

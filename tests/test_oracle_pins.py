@@ -473,3 +473,113 @@ def test_pivot_tie_takes_lowest_column():
     L, Ust, piv = unpack_factors(o, 2)
     assert list(piv) == [0, 1]
     assert np.array_equal(L, [[1, 0], [1, 1]]) and np.array_equal(Ust, [[1, 1], [0, 1]])
+
+
+# ---------------------------------------------------------------------------
+# backward error, value reload and perturbation threshold against their
+# definitions, computed here without the oracle
+# ---------------------------------------------------------------------------
+
+def _dense_eta(D, b, x):
+    """Normwise backward error max|b - Dx| / (max_i sum_j |D_ij| max|x| + max|b|)
+    and the paper's accuracy measure sum|Dx - b| / sum|b| (Sec. 3.3)."""
+    r = b - D @ x
+    eta = np.abs(r).max() / (np.abs(D).sum(axis=1).max() * np.abs(x).max() + np.abs(b).max())
+    return eta, np.abs(r).sum() / np.abs(b).sum()
+
+
+@pytest.mark.parametrize("case", ["A_x_term", "b_term", "balanced"])
+def test_backward_error_against_dense_definition(case):
+    """Cases where each term of the denominator dominates, on a matrix whose
+    largest row sum differs from its largest column sum (a transposed norm, a
+    dropped ||b|| or ||A|| ||x|| term, or a 1-norm for an infinity norm each
+    change the value by far more than the tolerance)."""
+    n = 60
+    rng = np.random.default_rng(31)
+    D = np.where(random_mask(n, 0.1, 31), rng.uniform(-1, 1, (n, n)), 0.0)
+    D[7, ::2] = 4.0                                   # one heavy row
+    A = synth.csr_from_dense(D)
+    assert np.abs(D).sum(axis=1).max() > 1.5 * np.abs(D).sum(axis=0).max()
+    scale_x, scale_b = {"A_x_term": (1e3, 1e-3), "b_term": (1e-6, 1e2), "balanced": (1.0, 100.0)}[case]
+    x = scale_x * rng.uniform(-1, 1, n)
+    b = scale_b * rng.uniform(-1, 1, n)
+    eta, r1 = oracle_of(A).backward_error(b, x)
+    eta_d, r1_d = _dense_eta(D, b, x)
+    assert abs(eta - eta_d) <= 1e-13 * eta_d and abs(r1 - r1_d) <= 1e-13 * r1_d
+    # the terms really differ in size where they are meant to
+    ax = np.abs(D).sum(axis=1).max() * np.abs(x).max()
+    bx = np.abs(b).max()
+    assert {"A_x_term": ax > 1e5 * bx, "b_term": bx > 1e5 * ax, "balanced": 0.1 < ax / bx < 10}[case]
+
+
+def test_backward_error_exact_integers():
+    """Integer A, x and b: the residual and both norms are exact, so the
+    backward error is the correctly rounded quotient of two integers."""
+    from fractions import Fraction
+    n = 25
+    rng = np.random.default_rng(32)
+    D = np.where(random_mask(n, 0.2, 32), rng.integers(-9, 10, (n, n)), 0).astype(np.float64)
+    A = synth.csr_from_dense(D)
+    x = rng.integers(-50, 51, n).astype(np.float64)
+    b = rng.integers(-70, 71, n).astype(np.float64)
+    eta, r1 = oracle_of(A).backward_error(b, x)
+    Di = D.astype(np.int64)
+    r = b.astype(np.int64) - Di @ x.astype(np.int64)
+    den = int(np.abs(Di).sum(axis=1).max()) * int(np.abs(x).max()) + int(np.abs(b).max())
+    assert eta == float(Fraction(int(np.abs(r).max()), den))
+    assert r1 == float(Fraction(int(np.abs(r).sum()), int(np.abs(b).sum())))
+
+
+def test_set_values_matches_fresh_oracle():
+    """The repeated-solve path (Sec. 3.2): new values on the same pattern
+    through set_values give B, factors and solutions bit-identical to an
+    oracle created with those values, with and without the pivot search, and
+    B equals R A C formed here from the new values."""
+    n = 60
+    A, D, q, dr, dc = _perm_case(n, 77)
+    rng = np.random.default_rng(78)
+    v1 = A.val * rng.uniform(0.5, 1.5, A.nnz)
+    o = oracle_of(A, perm_r=q, perm_c=q, dr=dr, dc=dc).analyse().numeric(TAU64)
+    piv = o.factors()[-1]
+    o.set_values(v1)
+    A1 = synth.Csr(A.n, A.row_ptr, A.col, v1)
+    f = oracle_of(A1, perm_r=q, perm_c=q, dr=dr, dc=dc).analyse()
+    for a, c in zip(o.B(), f.B()):
+        assert np.array_equal(a, c)
+    rp, ci, bv = o.B()
+    rows = A.rows()
+    Bd = np.zeros((n, n))
+    Bd[rows, A.col] = (dr[rows] * v1) * dc[A.col]
+    qinv = np.argsort(q)
+    assert np.array_equal(bv, Bd[np.ix_(q, q)][np.repeat(np.arange(n), np.diff(rp)), ci])
+    assert np.array_equal(np.sort(qinv[A.col]), np.sort(ci))
+    o.numeric(TAU64, piv=piv)
+    f.numeric(TAU64, piv=piv)
+    for a, c in zip(o.factors(), f.factors()):
+        assert np.array_equal(a, c)
+    o.numeric(TAU64)
+    f.numeric(TAU64)
+    for a, c in zip(o.factors(), f.factors()):
+        assert np.array_equal(a, c)
+    b = rng.uniform(-1, 1, n)
+    assert np.array_equal(o.solve(b), f.solve(b))
+    np.testing.assert_allclose(o.solve(b), np.linalg.solve(_dense(A1), b), rtol=1e-11, atol=1e-12)
+
+
+def _dense(A):
+    D = np.zeros((A.n, A.n))
+    D[A.rows(), A.col] = A.val
+    return D
+
+
+def test_pivot_tau_from_own_B():
+    """tau = sqrt(eps) max|B| with B = R A C formed here; exactly sqrt(eps)
+    when the scaling leaves a unit maximum; the rel argument scales it."""
+    n = 40
+    A, D, q, dr, dc = _perm_case(n, 91)
+    o = oracle_of(A, perm_r=q, perm_c=q, dr=dr, dc=dc)
+    bmax = np.abs((dr[:, None] * D) * dc[None, :]).max()
+    assert o.pivot_tau() == TAU64 * bmax
+    assert o.pivot_tau(1e-3) == 1e-3 * bmax
+    Dn = D / np.abs(D).max()
+    assert oracle_of(synth.csr_from_dense(Dn)).pivot_tau() == TAU64
