@@ -46,6 +46,9 @@ def main():
     ap.add_argument("--dense-tail", type=float, default=0.15)
     ap.add_argument("--pipeline-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 + refinement leg of the headline")
+    ap.add_argument("--value-sets", type=int, default=100,
+                    help="value sets of the circuit workload (the workload refactorises each once)")
     ap.add_argument("--cpu-sample-refactors", type=int, default=3)
     ap.add_argument("--workload", default="circuit", choices=["circuit", "batch", "grid27", "adjoint", "copy"],
                     help="circuit (default): the headline line; the others print their own line")
@@ -69,20 +72,21 @@ def main():
 
     dev = torch.device("cuda:0")
     t0 = time.time()
-    pat = synth.circuit_powerlaw_pattern(args.n, 100)
-    nsets = args.warmup + args.steps
     base = synth.circuit_powerlaw(args.n)  # refactor 0 values define the analysis
     A0 = base.A
     log(f"pattern n={A0.n} nnz={A0.nnz} ({time.time() - t0:.1f}s)")
+    opts = dict(amd_dense=args.amd_dense, dense_tail=args.dense_tail, pipeline_rows=args.pipeline_rows,
+                sn_dense=args.sn_dense, sn_inverse=args.sn_inverse, tail_sparse=args.tail_sparse,
+                side_rows=args.side_rows)
     t0 = time.time()
-    h = hylu.Handle(A0.row_ptr, A0.col, A0.val, precision=args.precision, amd_dense=args.amd_dense,
-                    dense_tail=args.dense_tail, pipeline_rows=args.pipeline_rows, sn_dense=args.sn_dense,
-                    sn_inverse=args.sn_inverse, tail_sparse=args.tail_sparse,
-                    side_rows=args.side_rows)
+    h = hylu.Handle(A0.row_ptr, A0.col, A0.val, precision=args.precision, **opts)
     t_analyze = time.time() - t0
     info = h.info()
     log(f"analyze {t_analyze:.1f}s: F={info['flops']:.3e} nnz(L+U)={info['nnz_l'] + info['nnz_u']:.3e} "
         f"supernodes={info['n_supernodes']} levels={info['n_levels']} tail={info['tail_rows']}")
+    # the workload's value sets (one per refactorisation), resident in HBM
+    nsets = max(args.value_sets, args.warmup + args.steps)
+    t0 = time.time()
     vals, bs, xts = [], [], []
     for r in range(nsets):
         w = base.revalue(r + 1)
@@ -90,38 +94,59 @@ def main():
         bs.append(torch.from_numpy(np.ascontiguousarray(w.b[:, 0])).to(dev))
         xts.append(w.x_true[:, 0])
     xs = [torch.empty_like(b) for b in bs]
+    log(f"{nsets} value sets ({time.time() - t0:.1f}s)")
     v0 = torch.from_numpy(A0.val).to(dev)
     h.factorize(v0)
     torch.cuda.synchronize()
 
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(nsets)]
-    for r in range(args.warmup):
-        h.refactor(vals[r])
-        h.solve(bs[r], out=xs[r])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for r in range(args.warmup, nsets):
-        e0, e1, e2 = ev[r]
-        e0.record()
-        h.refactor(vals[r])
-        e1.record()
-        h.solve(bs[r], out=xs[r])
-        e2.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = wall * 1e3 / args.steps
-    t_ref = np.median([ev[r][0].elapsed_time(ev[r][1]) for r in range(args.warmup, nsets)])
-    t_sol = np.median([ev[r][1].elapsed_time(ev[r][2]) for r in range(args.warmup, nsets)])
-    errs = [float(np.abs(xs[r].cpu().numpy() - xts[r]).max()) for r in range(args.warmup, nsets)]
+    def run(hd, steps, warmup, first=0):
+        """warmup + timed refactor+solve steps over consecutive value sets;
+        returns (ms per step by the host clock, median refactor ms, median
+        solve ms, the value-set indices timed)"""
+        idx = [(first + r) % nsets for r in range(warmup + steps)]
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in idx]
+        for r in idx[:warmup]:
+            hd.refactor(vals[r])
+            hd.solve(bs[r], out=xs[r])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for q, r in enumerate(idx[warmup:]):
+            e0, e1, e2 = ev[q]
+            e0.record()
+            hd.refactor(vals[r])
+            e1.record()
+            hd.solve(bs[r], out=xs[r])
+            e2.record()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / steps
+        tr = float(np.median([ev[q][0].elapsed_time(ev[q][1]) for q in range(steps)]))
+        tsv = float(np.median([ev[q][1].elapsed_time(ev[q][2]) for q in range(steps)]))
+        return ms, tr, tsv, idx[warmup:]
+
+    ms_step, t_ref, t_sol, timed = run(h, args.steps, args.warmup)
+    errs = [float(np.abs(xs[r].cpu().numpy() - xts[r]).max()) for r in timed]
+    eta, res1 = h.residual(bs[timed[-1]], xs[timed[-1]])
+    # the workload as specified: every value set refactorised and solved once, back to back
+    ms_seq, _, _, _ = run(h, nsets, 0)
+    x64 = xs[timed[-1]].clone()
 
     # per-kernel-class device time from HIP events around every launch of one
     # eager refactor+solve (same stream), with the algorithmic bytes / flops
     xprof = torch.empty_like(bs[0])
-    prof = h.profile(vals[-1], bs[-1], xprof)
+    prof = h.profile(vals[timed[-1]], bs[timed[-1]], xprof)
     torch.cuda.synchronize()
-    dom = max(prof, key=lambda k: k["ms"])
     fp_peak = FP64_PEAK_TFLOPS if args.precision == "fp64" else FP32_PEAK_TFLOPS
+    kernels = {}
+    for k in prof:
+        e = {"launches": k["launches"], "ms": round(k["ms"], 4),
+             "avg_launch_us": round(k["ms"] * 1e3 / max(k["launches"], 1), 3),
+             "GBps": round(k["bytes"] / max(k["ms"], 1e-9) / 1e6, 2),
+             "TFLOPs": round(k["flops"] / max(k["ms"], 1e-9) / 1e9, 4)}
+        if k["name"] in ALGORITHMIC_CLASSES:
+            e["hbm_frac"] = round(e["GBps"] / HBM_PEAK_GBS, 5)
+        kernels[k["name"]] = e
+    dom = max(prof, key=lambda k: k["ms"])
     if dom["name"] == "tail_gemm":
         ach = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
         roof = {"kernel": dom["name"], "bound": "mfma", "achieved": round(ach, 3), "peak": fp_peak,
@@ -130,16 +155,20 @@ def main():
         ach = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roof = {"kernel": dom["name"], "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None}
+    roof["algorithmic_bytes_per_launch"] = round(dom["bytes"] / max(dom["launches"], 1))
     tr = _traffic(dom["name"]) if args.precision == "fp64" else None
     if tr is not None:
         # measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)
         roof["traffic"] = round(tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"])
-        roof["algorithmic_bytes_per_launch"] = round(dom["bytes"] / max(dom["launches"], 1))
+        roof["traffic_over_algorithmic"] = round(roof["traffic"] / max(roof["algorithmic_bytes_per_launch"], 1), 2)
     roof["launches"] = dom["launches"]
     roof["avg_launch_us"] = round(dom["ms"] * 1e3 / max(dom["launches"], 1), 3)
-    kernels = {k["name"]: {"launches": k["launches"], "ms": round(k["ms"], 4),
-                           "GBps": round(k["bytes"] / max(k["ms"], 1e-9) / 1e6, 2),
-                           "TFLOPs": round(k["flops"] / max(k["ms"], 1e-9) / 1e9, 4)} for k in prof}
+    roof["bytes_basis"] = ("exact symbolic structure, unit costs per (target, source) update and per factor "
+                           "entry of a solve; no padded or dense widths")
+
+    fp32 = None
+    if args.precision == "fp64" and not args.no_fp32:
+        fp32 = fp32_ir_leg(args, A0, opts, vals, bs, xs, xts, v0, run, x64, timed)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -158,19 +187,54 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f64ir",
         "data": "synthetic",
         "config": {"workload": f"circuit_powerlaw n={A0.n} nnz={A0.nnz} refactor+solve, 1 rhs",
-                   "n": A0.n, "nnz": A0.nnz, "precision": args.precision},
-        "refactor_ms_median": round(float(t_ref), 4),
-        "solve_ms_median": round(float(t_sol), 4),
+                   "n": A0.n, "nnz": A0.nnz, "precision": args.precision, "value_sets": nsets},
+        "refactor_ms_median": round(t_ref, 4),
+        "solve_ms_median": round(t_sol, 4),
+        "ms_per_step_all_value_sets": round(ms_seq, 4),
         "factor_gflops": round(info["flops"] / (t_ref * 1e-3) / 1e9, 3),
         "flops": info["flops"],
+        "flops_issued": info["flops_issued"],
+        "backward_error": eta,
+        "resid_1": res1,
         "max_abs_err_vs_x_true": max(errs),
         "analyze_s": round(t_analyze, 2),
         "tail_rows": info["tail_rows"],
         "roofline": roof,
         "kernels": kernels,
+        "fp32_ir": fp32,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+# kernel classes whose byte figures follow the per-update and per-entry unit
+# costs on the exact structure (the others count the blocks they issue)
+ALGORITHMIC_CLASSES = ("rows", "lsolve", "usolve", "tail_solve", "snlu", "sn_inverse", "scatter")
+
+
+def fp32_ir_leg(args, A0, opts, vals, bs, xs, xts, v0, run, x64, timed):
+    """The same workload with FP32 factors and FP64 refinement, to a backward
+    error of 1e-10 and of 1e-12: ms per step, backward error, refinement
+    steps and the difference from the FP64 solution."""
+    import torch
+    from paper_2509_07690_amd import hylu
+    out = {}
+    for tol in (1e-10, 1e-12):
+        hf = hylu.Handle(A0.row_ptr, A0.col, A0.val, precision="fp32", ir_tol=tol, **opts)
+        hf.factorize(v0)
+        ms, tr, tsv, idx = run(hf, args.steps, args.warmup)
+        r = idx[-1]
+        eta, res1 = hf.residual(bs[r], xs[r])
+        inf = hf.info()
+        d = float((xs[r] - x64).abs().max() / x64.abs().max()) if r == timed[-1] else None
+        out[f"{tol:.0e}"] = {"ms_per_step": round(ms, 4), "refactor_ms_median": round(tr, 4),
+                             "solve_ms_median": round(tsv, 4), "backward_error": eta, "resid_1": res1,
+                             "ir_iters": inf["ir_iters"], "n_perturbed": inf["n_perturbed"],
+                             "rel_diff_vs_fp64": d,
+                             "max_abs_err_vs_x_true": float(np.abs(xs[r].cpu().numpy() - xts[r]).max())}
+        hf.close()
+        torch.cuda.synchronize()
+    return out
 
 
 def bench_copy(args):
@@ -387,7 +451,19 @@ def cpu_baseline(A0, base, h, nref, first):
     err = float(np.abs(x - w.x_true[:, 0]).max())
     return {"value": round(1e3 * float(np.median(times)), 2), "unit": "ms", "cores": 1, "kind": "oracle",
             "sample": f"{nref} refactor+solve step(s) of the same n={A0.n} workload, FP64, single thread, "
-                      f"symbolic ({t_sym:.1f}s) excluded", "max_abs_err_vs_x_true": err}
+                      f"symbolic ({t_sym:.1f}s) excluded", "max_abs_err_vs_x_true": err,
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "host_cpus_usable": len(os.sched_getaffinity(0))}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":

@@ -90,6 +90,11 @@ typedef struct {
                               0: all of them in the final level (same factors either way; default 1) */
     int32_t pipeline_rows; /* reserved for the pipelined mode of Sec. 2.2.1 (one persistent launch whose
                               blocks wait per source node); switched off: must be 0, else HYLU_ERR_ARG */
+    int32_t group_min_rows;  /* blocked dense LU (large supernodes, dense tail): row panels go in groups of four
+                                (one trailing update per group) while at least this many rows remain below them
+                                (<= 0: default 2048) */
+    int32_t group_tail_rows; /* a block-sparse dense tail takes panel groups from this many rows on, or when its
+                                plan keeps over half of the dense work (<= 0: default 16384) */
 } hylu_options;
 
 /* Optional device allocator (e.g. the PyTorch caching allocator).  alloc
@@ -110,11 +115,18 @@ typedef struct {
     int32_t n_levels[4];              /* factor / L solve, U solve, U^T solve, L^T solve */
     int32_t n_perturbed;              /* perturbed pivots of the last (re)factorisation */
     int32_t ir_iters;                 /* refinement steps of the last solve */
-    double berr;                      /* normwise backward error of the last solve (if refined) */
+    double berr;                      /* normwise backward error ||b-Ax||_inf / (||A||_inf ||x||_inf + ||b||_inf)
+                                         of the last refined solve or hylu_residual call (largest over the
+                                         right-hand sides and batch members); -1 when neither has run since the
+                                         last unrefined solve */
     double pivot_tau;                 /* absolute perturbation threshold used */
     int32_t tail_rows;                /* rows of the dense tail (0: none) */
     int32_t tail_panels;              /* row panels of the dense tail */
     uint64_t flops_issued;            /* flops the kernels issue (padding, dense tail included) */
+    double resid_1;                   /* the accuracy measure of Sec. 3.3, ||Ax-b||_1 / ||b||_1, of the same
+                                         solution as berr (largest over right-hand sides and members); -1 likewise */
+    int32_t n_dense_sn;               /* supernodes outside the tail factored by the blocked dense kernels */
+    int32_t sn_groups, tail_groups;   /* panel groups of more than one panel in their plans / in the tail's */
 } hylu_info;
 
 /* Analysis export for checking: every array is host memory the caller
@@ -178,18 +190,34 @@ hylu_status hylu_refactor(hylu_handle h, const double* d_val, void* stream);
  * column-major, leading dimension ld; d_x may equal d_b.  Iterative
  * refinement in FP64 runs when a pivot was perturbed or precision = 1; its
  * residual uses the handle's copy of the values of the last (re)factorisation.
- * Synchronises the stream when refinement runs (the stopping test
- * reads the backward error on the host).  Graphs are cached per
+ * Refinement stops at ir_tol, on stagnation (a correction that does not halve
+ * the backward error) or after ir_maxit corrections, and returns the iterate
+ * with the smallest backward error (HYLU_WARN_IR_NOT_CONVERGED when that is
+ * above ir_tol).  Synchronises the stream when refinement runs (the stopping
+ * test reads the backward error on the host).  Graphs are cached per
  * (d_b, d_x, nrhs, ld, transpose) like those of hylu_refactor. */
 hylu_status hylu_solve(hylu_handle h, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
                        int32_t transpose, void* stream);
 
-/* Gradient of a scalar loss through x = A^{-1} b with respect to the values of
- * A: d_gval[p] = -lambda[row p] * x[col p] for every stored entry p, where
- * lambda = A^{-T} dL/dx (from hylu_solve with transpose = 1).  Device arrays:
- * d_lambda, d_x of n entries, d_gval of nnz entries. */
-hylu_status hylu_grad_values(hylu_handle h, const double* d_lambda, const double* d_x,
+/* Gradient of a scalar loss through X = A^{-1} B with respect to the values of
+ * A (the adjoint of the solve): d_gval[p] = -sum_k Lambda[row p, k] X[col p, k]
+ * for every stored entry p, where Lambda = A^{-T} dL/dX (from hylu_solve with
+ * transpose = 1) and the sum runs over the nrhs columns.  Device arrays:
+ * d_lambda and d_x are n x nrhs column-major with leading dimension ld >= n,
+ * d_gval holds nnz entries in the CSR order given to hylu_analyze and is
+ * overwritten.  HYLU_ERR_ARG for a null pointer, nrhs <= 0 or ld < n. */
+hylu_status hylu_grad_values(hylu_handle h, const double* d_lambda, const double* d_x, int32_t nrhs, int64_t ld,
                              double* d_gval, void* stream);
+
+/* Accuracy of a solution (Sec. 3.3): r = b - op(A) x in FP64 on the values of
+ * the last (re)factorisation (op(A) = A, or A^T when transpose = 1), then the
+ * normwise backward error ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf) in
+ * *berr and the paper's measure ||r||_1 / ||b||_1 in *resid1 (host, either may
+ * be null), each the largest over the nrhs right-hand sides and the members of
+ * a batch.  d_b, d_x: device, n x nrhs column-major, leading dimension ld.
+ * Synchronises the stream; the values also appear in hylu_get_info. */
+hylu_status hylu_residual(hylu_handle h, const double* d_b, const double* d_x, int32_t nrhs, int64_t ld,
+                          int32_t transpose, void* stream, double* berr, double* resid1);
 
 /* Statistics of the analysis and of the last numerical calls (synchronises). */
 hylu_status hylu_get_info(hylu_handle h, hylu_info* out);

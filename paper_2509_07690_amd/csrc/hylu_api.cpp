@@ -68,6 +68,19 @@ struct LevelTasks {
     std::vector<int32_t> node_level;  // execution level of every node
 };
 
+// work vectors of a solve with refinement: y, z (n x nrhs, factor precision),
+// r, bc, xbest (n x nrhs, FP64), the norms of the residual test on the device
+// and their pinned host copy
+struct SolveWs {
+    void* y = nullptr;
+    void* z = nullptr;
+    double* r = nullptr;
+    double* bc = nullptr;                   // copy of b when refining in place
+    double* xbest = nullptr;                // best refinement iterate so far
+    double* norms = nullptr;
+    double* h_norms = nullptr;              // pinned
+};
+
 // one launch of the blocked dense LU of a view (a large supernode or the tail)
 struct DenseOp {
     int32_t kind = 0;                 // 0 panel, 1 TRSM, 2 trailing GEMM
@@ -126,6 +139,7 @@ struct hylu_handle_s {
     int32_t* d_tsp = nullptr;               // the tail's solve panels (p0, p1 pairs)
     void* d_tinv = nullptr;                 // inverses of their diagonal blocks (L and U, 64 x 64 each)
     double tail_flops = 0.0;
+    int32_t tail_groups = 0, sn_groups = 0;  // panel groups (of more than one panel) of the tail / the large supernodes
     std::vector<DenseSn> dsn;
     std::vector<int32_t> dsn_ptr;           // per factor level into dsn
     std::vector<std::vector<int32_t>> dsn_l, dsn_u;   // per L-solve / U-solve level: dsn indices
@@ -158,31 +172,38 @@ struct hylu_handle_s {
     bool pert_known = false;
     // solve workspace
     int32_t ws_nrhs = 0;
-    void *d_y = nullptr, *d_z = nullptr;
-    double* d_r = nullptr;
-    double* d_bc = nullptr;                 // copy of b when refining in place
-    double* d_norms = nullptr;
-    double* h_norms = nullptr;              // pinned
+    SolveWs ws;                             // of hylu_solve (handle memory)
     // batch of matrices on one handle (block diagonal); one member otherwise
     std::vector<int64_t> member_row_off{0}, member_nnz_off{0};
     int32_t* d_seg = nullptr;               // member of every row (null for one member)
     // graphs
     std::map<const double*, GraphEntry> refac_graphs;
     std::map<std::tuple<const double*, double*, int32_t, int64_t, int32_t>, GraphEntry> solve_graphs;
-    // last solve
+    // last solve (or hylu_residual)
     int32_t ir_iters = 0;
-    double berr = 0.0;
+    double berr = 0.0, resid1 = 0.0;
+    bool berr_known = false;
     // measurement
     Profiler prof;
-    std::vector<double> lvl_bytes, lvl_flops;   // per factor level: row-kernel traffic and flops
+    std::vector<double> lvl_bytes, lvl_flops;   // per factor level: row-kernel value entries and flops
     std::vector<int32_t> pert_rows;              // standalone rows without sources: pivot check only
     int32_t* d_pert_rows = nullptr;
-    std::vector<double> tile_bytes, tile_flops; // per factor level: tile-kernel traffic and flops
+    // algorithmic traffic per factor level, as value entries (times the
+    // factor precision's size) and index bytes, and flops: row kernel, row
+    // tiles, block inverses
+    std::vector<double> lvl_idx;
+    std::vector<double> tile_bytes, tile_idx, tile_flops;
+    std::vector<double> inv_bytes, inv_flops;
+    // one right-hand side: exact factor entries consumed by the L solve and
+    // the U solve of the rows before the dense tail and by the tail's rows
+    // (both solves), each with the count of those in standalone rows
+    std::array<double, 6> solve_units{};
 };
 
 static const char* kClassNames[] = {"rows", "snlu", "tail_panel", "tail_trsm", "tail_gemm", "lsolve", "usolve",
-                                    "tail_solve", "scatter", "other_solve", "sup_tile"};
-enum { C_ROWS, C_SNLU, C_PANEL, C_TRSM, C_GEMM, C_LSOLVE, C_USOLVE, C_TSOLVE, C_SCATTER, C_OSOLVE, C_TILE, C_N };
+                                    "tail_solve", "scatter", "other_solve", "sup_tile", "sn_inverse", "tail_dinv"};
+enum { C_ROWS, C_SNLU, C_PANEL, C_TRSM, C_GEMM, C_LSOLVE, C_USOLVE, C_TSOLVE, C_SCATTER, C_OSOLVE, C_TILE, C_SNINV,
+       C_DINV, C_N };
 
 namespace {
 
@@ -305,15 +326,19 @@ hylu_status ensure_workspace(hylu_handle h, int32_t nrhs)
     h->solve_graphs.clear();
     size_t es = h->fp32 ? sizeof(float) : sizeof(double);
     size_t nn = (size_t)h->n * nrhs;
-    h->d_y = dalloc(h, es * nn);
-    h->d_z = dalloc(h, es * nn);
-    h->d_r = (double*)dalloc(h, sizeof(double) * nn);
-    h->d_bc = (double*)dalloc(h, sizeof(double) * nn);
+    SolveWs& w = h->ws;
+    w.y = dalloc(h, es * nn);
+    w.z = dalloc(h, es * nn);
+    w.r = (double*)dalloc(h, sizeof(double) * nn);
+    w.bc = (double*)dalloc(h, sizeof(double) * nn);
+    w.xbest = (double*)dalloc(h, sizeof(double) * nn);
     const size_t nseg = h->member_row_off.size() - 1;
-    h->d_norms = (double*)dalloc(h, sizeof(double) * 4 * ((size_t)nrhs + 1) * nseg);
-    if (!h->d_y || !h->d_z || !h->d_r || !h->d_bc || !h->d_norms) return HYLU_ERR_OOM;
-    if (h->h_norms) hipHostFree(h->h_norms);
-    if (hipHostMalloc((void**)&h->h_norms, sizeof(double) * 4 * ((size_t)nrhs + 1) * nseg) != hipSuccess) return HYLU_ERR_OOM;
+    w.norms = (double*)dalloc(h, sizeof(double) * kNormSlots * ((size_t)nrhs + 1) * nseg);
+    if (!w.y || !w.z || !w.r || !w.bc || !w.xbest || !w.norms) return HYLU_ERR_OOM;
+    if (w.h_norms) hipHostFree(w.h_norms);
+    w.h_norms = nullptr;
+    if (hipHostMalloc((void**)&w.h_norms, sizeof(double) * kNormSlots * ((size_t)nrhs + 1) * nseg) != hipSuccess)
+        return HYLU_ERR_OOM;
     h->ws_nrhs = nrhs;
     return HYLU_OK;
 }
@@ -365,9 +390,11 @@ hylu_status ensure_tlists(hylu_handle h)
     return HYLU_OK;
 }
 
-// blocked right-looking LU of a dense view, one row panel at a time
+// blocked right-looking LU of a dense view, one row panel at a time; panels
+// go in groups while at least group_min_rows rows remain below them (option,
+// default kGroupMinRows), and a block-sparse tail of at least group_tail_rows
+// rows (default kGroupTailRows) still takes panel groups
 constexpr int32_t kGroupMinRows = 2048;
-// a block-sparse tail of at least this many rows still takes panel groups
 constexpr int32_t kGroupTailRows = 16384;
 // a factor level of fewer rows than this counts as narrow: deferred rows may
 // join its launch on the CUs it leaves idle
@@ -383,10 +410,11 @@ constexpr int32_t kLsolveSnMin = 8;
 // the group panels that contribute, in XCD order, and every TRSM the list of
 // its blocks that hold entries (row blocks without multipliers only write
 // zeros to lbuf); the rest is exactly zero and is skipped.
-void plan_dense(const std::vector<Layout::Panel>& panels, int32_t mT, int32_t nc, const TailMasks* M, bool group,
-                std::vector<DenseOp>& ops, std::vector<uint32_t>& lists)
+int32_t plan_dense(const std::vector<Layout::Panel>& panels, int32_t mT, int32_t nc, const TailMasks* M, bool group,
+                   int32_t group_min_rows, std::vector<DenseOp>& ops, std::vector<uint32_t>& lists)
 {
     ops.clear();
+    int32_t ngroups = 0;          // groups of more than one panel
     const int32_t wd = M ? M->words : 0;
     auto bits = [&](const std::vector<uint64_t>& v, int32_t row, int32_t g0, int32_t nk) -> uint32_t {
         const uint64_t* w = v.data() + (size_t)row * wd;
@@ -502,8 +530,9 @@ void plan_dense(const std::vector<Layout::Panel>& panels, int32_t mT, int32_t nc
         // grouping pays where the trailing matrix is large and mostly dense;
         // near the end, or where block sparsity leaves small per-panel
         // updates, its extra launches cost more than the saved passes
-        const bool big = group && mT - panels[i].p1 >= kGroupMinRows;
+        const bool big = group && mT - panels[i].p1 >= group_min_rows;
         const size_t g1 = std::min(i + (size_t)(big ? kGroup : 1), panels.size());
+        if (g1 - i > 1) ngroups++;
         const int32_t kb0 = panels[i].p0, cg = panels[i].cg0;
         int32_t kofs[kGroup + 1] = {0, 0, 0, 0, 0};
         for (size_t j = i; j < g1; j++) {
@@ -527,6 +556,7 @@ void plan_dense(const std::vector<Layout::Panel>& panels, int32_t mT, int32_t nc
         gemm((int32_t)i, (int32_t)(g1 - i), kofs, kb0, Q.p1, mT, cg, Q.p1, 0, 0, 0, 0);   // everything below the group
         i = g1;
     }
+    return ngroups;
 }
 
 hylu_status enqueue_dense(hylu_handle h, const TailView& TV, const std::vector<DenseOp>& ops, const uint32_t* d_list,
@@ -561,7 +591,7 @@ hylu_status enqueue_dsn(hylu_handle h, const hylu_handle_s::DenseSn& q, bool sea
     hylu_status s = enqueue_dense(h, q.TV, q.ops, nullptr, search, st);
     if (s != HYLU_OK) return s;
     const double ns = (double)q.spanels.size();
-    LAUNCH(C_PANEL, (h->fp32 ? 4.0 : 8.0) * ns * 3.0 * kNB * kNB, ns * 2.0 * kNB * kNB * kNB / 3.0,
+    LAUNCH(C_DINV, (h->fp32 ? 4.0 : 8.0) * ns * 3.0 * kNB * kNB, ns * 2.0 * kNB * kNB * kNB / 3.0,
            launch_tail_dinv(h->fp32, q.TV, h->vals, q.d_sp, (int32_t)q.spanels.size(), q.d_inv, st));
     return HYLU_OK;
 }
@@ -613,12 +643,12 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
     int32_t nl = (int32_t)T.maxW.size();
     for (int32_t l = 0; l < T.pipe_level; l++) {
         int64_t r0 = T.row_ptr[l], r1 = T.row_ptr[l + 1];
-        LAUNCH(C_ROWS, h->lvl_bytes[l] * es / 8.0, h->lvl_flops[l],
+        LAUNCH(C_ROWS, h->lvl_bytes[l] * es + h->lvl_idx[l], h->lvl_flops[l],
                launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, h->d_rrange + 2 * r0, (int32_t)(r1 - r0),
                                   T.maxW[l], h->tau, h->d_pert,
                                   T.tune_rows ? T.tune_rows : T.row_nt[l], T.row_stage[l], T.row_cap[l], st));
         if (T.tile_ptr[l + 1] > T.tile_ptr[l])
-            LAUNCH(C_TILE, h->tile_bytes[l] * es / 8.0, h->tile_flops[l],
+            LAUNCH(C_TILE, h->tile_bytes[l] * es + h->tile_idx[l], h->tile_flops[l],
                    launch_factor_tile(h->fp32, h->D, h->vals, h->d_tiles + 2 * T.tile_ptr[l],
                                       (int32_t)(T.tile_ptr[l + 1] - T.tile_ptr[l]), st));
         int64_t s0 = T.sn_ptr[l], s1 = T.sn_ptr[l + 1];
@@ -628,7 +658,7 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
                 int32_t v = T.snodes[q];
                 double m = h->lay.m[v], wc = h->lay.W[v] - h->lay.lw[v];
                 by += 2.0 * es * m * wc;
-                fl += m * m * (2.0 * wc - m);
+                fl += 2.0 * m * m * m / 3.0 + m * m * (wc - m);
             }
             LAUNCH(C_SNLU, by, fl, launch_factor_snlu(h->fp32, h->D, h->vals, h->d_snodes + s0, (int32_t)(s1 - s0), T.maxm[l],
                                                       h->tau, h->d_pert, search ? 1 : 0,
@@ -637,7 +667,7 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
         hylu_status sd = enqueue_level_dense(h, l, search, st);
         if (sd != HYLU_OK) return sd;
         if (h->inv_ptr[l + 1] > h->inv_ptr[l])
-            LAUNCH(C_SNLU, 0.0, 0.0,
+            LAUNCH(C_SNINV, h->inv_bytes[l] * es, h->inv_flops[l],
                    launch_sn_inverse(h->fp32, h->D, h->vals, h->d_inv_nodes + h->inv_ptr[l],
                                      (int32_t)(h->inv_ptr[l + 1] - h->inv_ptr[l]), h->inv_maxm[l], h->d_inv_off,
                                      h->d_uinv, st));
@@ -645,7 +675,7 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
     if (T.pipe_level < nl) {
         // pipeline mode over the remaining levels
         double by = 0, fl = 0;
-        for (int32_t l = T.pipe_level; l < nl; l++) { by += h->lvl_bytes[l] * es / 8.0; fl += h->lvl_flops[l]; }
+        for (int32_t l = T.pipe_level; l < nl; l++) { by += h->lvl_bytes[l] * es + h->lvl_idx[l]; fl += h->lvl_flops[l]; }
         for (int64_t q = T.sn_ptr[T.pipe_level]; q < T.sn_ptr[nl]; q++) {
             int32_t v = T.snodes[q];
             double m = h->lay.m[v], wc = h->lay.W[v] - h->lay.lw[v];
@@ -663,13 +693,13 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
     hylu_status sd = enqueue_dense(h, h->TV, h->tail_ops, h->d_tail_list, search, st);
     if (sd != HYLU_OK || h->lay.mT == 0) return sd;
     const double ns = (double)h->lay.spanels.size();
-    LAUNCH(C_PANEL, es * ns * 3.0 * kNB * kNB, ns * 2.0 * kNB * kNB * kNB / 3.0,
+    LAUNCH(C_DINV, es * ns * 3.0 * kNB * kNB, ns * 2.0 * kNB * kNB * kNB / 3.0,
            launch_tail_dinv(h->fp32, h->TV, h->vals, h->d_tsp, (int32_t)h->lay.spanels.size(), h->d_tinv, st));
     return HYLU_OK;
 }
 
 // base solve in the factor precision: x = A^{-1} b (transpose 0) or A^{-T} b
-hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x, int64_t ldx, int32_t nrhs,
+hylu_status enqueue_solve(hylu_handle h, const SolveWs& w, const double* b, int64_t ldb, double* x, int64_t ldx, int32_t nrhs,
                           int32_t transpose, int32_t accumulate, hipStream_t st)
 {
     const Layout& L = h->lay;
@@ -694,19 +724,19 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
                     return (const void*)((const char*)d.d_inv + ((size_t)2 * k + kind) * kNB * kNB * esz);
                 };
                 if (g == 4) {
-                    LAUNCH(cls, 0, 0, launch_sn_lext(f, h->D, d.TV, h->vals, d.v, h->d_y, nrhs, st));
-                    LAUNCH(cls, 0, 0, launch_tail_step(f, d.TV, h->vals, 0, 0, SP[0].p0, SP[0].p1, inv(0, 0), n, h->d_y,
-                                                       h->d_y, nrhs, 0, st));
+                    LAUNCH(cls, 0, 0, launch_sn_lext(f, h->D, d.TV, h->vals, d.v, w.y, nrhs, st));
+                    LAUNCH(cls, 0, 0, launch_tail_step(f, d.TV, h->vals, 0, 0, SP[0].p0, SP[0].p1, inv(0, 0), n, w.y,
+                                                       w.y, nrhs, 0, st));
                     for (int32_t k = 0; k + 1 < ns; k++)
                         LAUNCH(cls, 0, 0, launch_tail_step(f, d.TV, h->vals, SP[k].p0, SP[k].p1, SP[k + 1].p0,
-                                                           SP[k + 1].p1, inv(k + 1, 0), n, h->d_y, h->d_y, nrhs, 0, st));
+                                                           SP[k + 1].p1, inv(k + 1, 0), n, w.y, w.y, nrhs, 0, st));
                 } else {
-                    LAUNCH(cls, 0, 0, launch_sn_utext(f, h->D, d.TV, h->vals, d.v, h->d_y, h->d_z, nrhs, st));
+                    LAUNCH(cls, 0, 0, launch_sn_utext(f, h->D, d.TV, h->vals, d.v, w.y, w.z, nrhs, st));
                     LAUNCH(cls, 0, 0, launch_tail_step(f, d.TV, h->vals, 0, 0, SP[ns - 1].p0, SP[ns - 1].p1,
-                                                       inv(ns - 1, 1), n, h->d_y, h->d_z, nrhs, 1, st));
+                                                       inv(ns - 1, 1), n, w.y, w.z, nrhs, 1, st));
                     for (int32_t k = ns - 1; k > 0; k--)
                         LAUNCH(cls, 0, 0, launch_tail_step(f, d.TV, h->vals, SP[k].p0, SP[k].p1, SP[k - 1].p0,
-                                                           SP[k - 1].p1, inv(k - 1, 1), n, h->d_y, h->d_z, nrhs, 1, st));
+                                                           SP[k - 1].p1, inv(k - 1, 1), n, w.y, w.z, nrhs, 1, st));
                 }
             }
         }
@@ -714,14 +744,14 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
     };
     hylu_status s;
     if (!transpose) {
-        HIPCHK(launch_permute_in(f, n, nrhs, h->d_perm_r, h->d_dr, b, ldb, h->d_y, st));
+        HIPCHK(launch_permute_in(f, n, nrhs, h->d_perm_r, h->d_dr, b, ldb, w.y, st));
         s = levels(4, [&](const int32_t* nodes, int32_t c, size_t l) {
             const int32_t with = l < h->lsolve_sn.size() ? h->lsolve_sn[l] : 0;
-            return launch_lsolve(f, h->D, h->vals, nodes, c, h->d_y, nrhs, kLsolveSnMin, with, st);
+            return launch_lsolve(f, h->D, h->vals, nodes, c, w.y, nrhs, kLsolveSnMin, with, st);
         });
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
-            LAUNCH(C_TSOLVE, 0, 0, launch_tail_lext(f, h->D, h->vals, L.tail_node0, L.t0, h->d_y, nrhs, st));
+            LAUNCH(C_TSOLVE, 0, 0, launch_tail_lext(f, h->D, h->vals, L.tail_node0, L.t0, w.y, nrhs, st));
             // one launch per solve panel: its contribution to the rows after it
             // and the next panel's diagonal solve (with the block inverses)
             const std::vector<Layout::Panel>& SP = L.spanels;
@@ -730,29 +760,29 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
             auto inv = [&](int32_t k, int kind) {
                 return (const void*)((const char*)h->d_tinv + ((size_t)2 * k + kind) * kNB * kNB * es);
             };
-            LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, 0, 0, SP[0].p0, SP[0].p1, inv(0, 0), n, h->d_y,
-                                                    h->d_y, nrhs, 0, st));
+            LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, 0, 0, SP[0].p0, SP[0].p1, inv(0, 0), n, w.y,
+                                                    w.y, nrhs, 0, st));
             for (int32_t k = 0; k + 1 < ns; k++)
                 LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, SP[k].p0, SP[k].p1, SP[k + 1].p0, SP[k + 1].p1,
-                                                        inv(k + 1, 0), n, h->d_y, h->d_y, nrhs, 0, st));
+                                                        inv(k + 1, 0), n, w.y, w.y, nrhs, 0, st));
             LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, 0, 0, SP[ns - 1].p0, SP[ns - 1].p1, inv(ns - 1, 1), n,
-                                                    h->d_y, h->d_z, nrhs, 1, st));
+                                                    w.y, w.z, nrhs, 1, st));
             for (int32_t k = ns - 1; k > 0; k--)
                 LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, SP[k].p0, SP[k].p1, SP[k - 1].p0, SP[k - 1].p1,
-                                                        inv(k - 1, 1), n, h->d_y, h->d_z, nrhs, 1, st));
+                                                        inv(k - 1, 1), n, w.y, w.z, nrhs, 1, st));
         }
         s = levels(1, [&](const int32_t* nodes, int32_t c, size_t l) {
             const int32_t with = l < h->usolve_sn.size() ? h->usolve_sn[l] : 0;
-            return launch_usolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, kLsolveSnMin, with, st);
+            return launch_usolve(f, h->D, h->vals, nodes, c, w.y, w.z, nrhs, kLsolveSnMin, with, st);
         });
         if (s != HYLU_OK) return s;
-        HIPCHK(launch_permute_out(f, n, nrhs, h->d_perm_c, h->d_dc, h->d_z, x, ldx, accumulate, st));
+        HIPCHK(launch_permute_out(f, n, nrhs, h->d_perm_c, h->d_dc, w.z, x, ldx, accumulate, st));
     } else {
-        HIPCHK(launch_permute_in(f, n, nrhs, h->d_perm_c, h->d_dc, b, ldb, h->d_y, st));
-        s = levels(2, [&](const int32_t* nodes, int32_t c, size_t) { return launch_utsolve(f, h->D, h->vals, nodes, c, h->d_y, h->d_z, nrhs, st); });
+        HIPCHK(launch_permute_in(f, n, nrhs, h->d_perm_c, h->d_dc, b, ldb, w.y, st));
+        s = levels(2, [&](const int32_t* nodes, int32_t c, size_t) { return launch_utsolve(f, h->D, h->vals, nodes, c, w.y, w.z, nrhs, st); });
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
-            LAUNCH(C_TSOLVE, 0, 0, launch_tail_utext(f, h->D, h->TV, h->vals, h->d_y, h->d_z, nrhs, st));
+            LAUNCH(C_TSOLVE, 0, 0, launch_tail_utext(f, h->D, h->TV, h->vals, w.y, w.z, nrhs, st));
             // U^T ascending, then L^T descending: one launch per solve panel
             // with the transposed inverses of the diagonal blocks
             const std::vector<Layout::Panel>& SP = L.spanels;
@@ -761,20 +791,20 @@ hylu_status enqueue_solve(hylu_handle h, const double* b, int64_t ldb, double* x
             auto inv = [&](int32_t k, int kind) {
                 return (const void*)((const char*)h->d_tinv + ((size_t)2 * k + kind) * kNB * kNB * esz);
             };
-            LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, 0, 0, SP[0].p0, SP[0].p1, inv(0, 1), n, h->d_y,
-                                                    h->d_z, nrhs, 2, st));
+            LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, 0, 0, SP[0].p0, SP[0].p1, inv(0, 1), n, w.y,
+                                                    w.z, nrhs, 2, st));
             for (int32_t k = 0; k + 1 < ns; k++)
                 LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, SP[k].p0, SP[k].p1, SP[k + 1].p0, SP[k + 1].p1,
-                                                        inv(k + 1, 1), n, h->d_y, h->d_z, nrhs, 2, st));
+                                                        inv(k + 1, 1), n, w.y, w.z, nrhs, 2, st));
             LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, 0, 0, SP[ns - 1].p0, SP[ns - 1].p1, inv(ns - 1, 0), n,
-                                                    h->d_z, h->d_z, nrhs, 3, st));
+                                                    w.z, w.z, nrhs, 3, st));
             for (int32_t k = ns - 1; k > 0; k--)
                 LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, SP[k].p0, SP[k].p1, SP[k - 1].p0, SP[k - 1].p1,
-                                                        inv(k - 1, 0), n, h->d_z, h->d_z, nrhs, 3, st));
+                                                        inv(k - 1, 0), n, w.z, w.z, nrhs, 3, st));
         }
-        s = levels(3, [&](const int32_t* nodes, int32_t c, size_t) { return launch_ltsolve(f, h->D, h->vals, nodes, c, h->d_z, nrhs, st); });
+        s = levels(3, [&](const int32_t* nodes, int32_t c, size_t) { return launch_ltsolve(f, h->D, h->vals, nodes, c, w.z, nrhs, st); });
         if (s != HYLU_OK) return s;
-        HIPCHK(launch_permute_out(f, n, nrhs, h->d_perm_r, h->d_dr, h->d_z, x, ldx, accumulate, st));
+        HIPCHK(launch_permute_out(f, n, nrhs, h->d_perm_r, h->d_dr, w.z, x, ldx, accumulate, st));
     }
     return HYLU_OK;
 }
@@ -1175,7 +1205,9 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     h->max_sn = 0;
     h->dsn.clear();
     h->dsn_ptr.assign(1, 0);
+    h->sn_groups = h->tail_groups = 0;
     const int32_t big = opt.sn_dense > 0 ? opt.sn_dense : std::numeric_limits<int32_t>::max();
+    const int32_t gmin = opt.group_min_rows > 0 ? opt.group_min_rows : kGroupMinRows;
     const int32_t tile_min = opt.sn_tile > 0 ? opt.sn_tile : std::numeric_limits<int32_t>::max();
     T.tile_ptr.assign(1, 0);
     T.rrange.clear();
@@ -1210,7 +1242,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 for (int32_t k = 0; k < L.m[v]; k += 64)
                     q.spanels.push_back({k, std::min(k + 64, L.m[v]), 0, L.m[v], 0});
                 std::vector<uint32_t> none;
-                plan_dense(q.panels, L.m[v], L.W[v] - L.lw[v], nullptr, true, q.ops, none);
+                h->sn_groups += plan_dense(q.panels, L.m[v], L.W[v] - L.lw[v], nullptr, true, gmin, q.ops, none);
                 h->dsn.push_back(std::move(q));
             } else {
                 T.snodes.push_back(v);
@@ -1243,17 +1275,18 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         // block-sparse plan keeps more than half of the dense work; not for a
         // small sparse tail (circuit, 8315 rows: 29.4 vs 30.7 ms).  The choice
         // does not depend on tail_sparse, so both plans sum in the same order.
-        bool group = L.mT >= kGroupTailRows;
+        bool group = L.mT >= (opt.group_tail_rows > 0 ? opt.group_tail_rows : kGroupTailRows);
         if (!group) {
             std::vector<DenseOp> probe;
             std::vector<uint32_t> plist;
-            plan_dense(L.panels, L.mT, L.mT, &M, false, probe, plist);
+            plan_dense(L.panels, L.mT, L.mT, &M, false, gmin, probe, plist);
             double fl = 0.0;
             for (const DenseOp& o : probe) fl += o.flops;
             const double mTd = L.mT;
             group = fl > 0.5 * (2.0 * mTd * mTd * mTd / 3.0);
         }
-        plan_dense(L.panels, L.mT, L.mT, opt.tail_sparse ? &M : nullptr, group, h->tail_ops, h->tail_list);
+        h->tail_groups = plan_dense(L.panels, L.mT, L.mT, opt.tail_sparse ? &M : nullptr, group, gmin, h->tail_ops,
+                                    h->tail_list);
         for (const DenseOp& o : h->tail_ops) h->tail_flops += o.flops;
     }
     plog("tail plan");
@@ -1327,49 +1360,241 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     // pipeline mode stays off: its dataflow launch did not finish on the device
     // and the reason is not established, so every level is a launch of its own
     T.pipe_level = nl;
-    // algorithmic traffic and flops of every row-kernel and tile launch
-    // (8-byte values): the row or tile is read and written once, each source's
-    // panel is read once per row (row kernel) or once per tile
+    // algorithmic traffic and flops of every row-kernel and tile launch, from
+    // the unit costs of the update kinds (Sec. 2.2) on the exact structure:
+    //  row-row (target row i, standalone source k with L(i,k) != 0):
+    //      12 u_k + 8 bytes (U(k,:) values and columns, the multiplier), 1 + 2 u_k flops;
+    //  sup-row (standalone target row i, source supernode s it has entries in):
+    //      8 m_s (m_s + w_s) + 4 w_s + 8 (m_s + w_s) bytes, m_s^2 + 2 m_s w_s flops;
+    //  sup-sup (target supernode t, source supernode s one of its rows has entries in):
+    //      8 [m_s (m_s + w_s) + 2 m_t (m_s + w_s)] bytes, m_t m_s^2 + 2 m_t m_s w_s flops
+    // (m_s rows of the source, w_s its columns past its block).  Padded slots and
+    // the dense tail's width are not counted: they are the kernels' choice.
     h->lvl_bytes.assign(nl, 0.0);
+    h->lvl_idx.assign(nl, 0.0);
     h->lvl_flops.assign(nl, 0.0);
     h->tile_bytes.assign(nl, 0.0);
+    h->tile_idx.assign(nl, 0.0);
     h->tile_flops.assign(nl, 0.0);
-    for (int32_t l = 0; l < nl; l++)
-        for (int32_t v : lvnodes[l]) {
-            if (L.eptr[v + 1] == L.eptr[v]) continue;
-            const bool tiled = nd.is_sn[v] && v < L.tail_node0 && L.m[v] >= tile_min;
-            double m = L.m[v], by = 16.0 * L.W[v], src = 0, fl = 0;
-            for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
-                int32_t u = L.esrc[e];
-                double ms = L.m[u], ws = L.W[u] - L.lw[u] - L.m[u];
-                src += 8.0 * ms * (ms + ws) + 4.0 * ws + 48.0;
-                fl += ms * (ms + 2.0 * ws);
+    {
+        const Symbolic& S = h->sym;
+        std::vector<int64_t> mark(L.nnodes, -1), seen(L.nnodes, -1);
+        int64_t stamp = 0;
+        // units of target node v's rows [ra, rb) over its sources e0..e1
+        // by: value entries moved, ix: index bytes, fl: flops
+        auto units = [&](int32_t v, int32_t ra, int32_t rb, int64_t e0, int64_t e1, double& by, double& ix,
+                         double& fl) {
+            const int64_t sm = ++stamp;
+            for (int64_t e = e0; e < e1; e++) mark[L.esrc[e]] = sm;
+            const bool tsn = nd.is_sn[v] != 0;
+            const double mt = L.m[v];
+            for (int32_t i = ra; i < rb; i++) {
+                const int64_t si = tsn ? sm : ++stamp;      // a supernode target counts (t, s) once
+                for (int64_t q = S.lp[i]; q < S.lp[i + 1]; q++)
+                    for (int32_t k = S.lint[2 * q]; k <= S.lint[2 * q + 1]; k++) {
+                        const int32_t u = nd.of_row[k];
+                        if (mark[u] != sm) continue;
+                        if (!nd.is_sn[u]) {
+                            const double uk = (double)S.ucount[k];
+                            by += uk + 1.0;
+                            ix += 4.0 * uk;
+                            fl += 1.0 + 2.0 * uk;
+                        } else if (seen[u] != si) {
+                            seen[u] = si;
+                            const double ms = L.m[u], ws = L.W[u] - L.lw[u] - L.m[u];
+                            if (tsn) {
+                                by += ms * (ms + ws) + 2.0 * mt * (ms + ws);
+                                fl += mt * ms * ms + 2.0 * mt * ms * ws;
+                            } else {
+                                by += ms * (ms + ws) + (ms + ws);
+                                ix += 4.0 * ws;
+                                fl += ms * ms + 2.0 * ms * ws;
+                            }
+                        }
+                    }
             }
-            if (tiled) {
-                double ntile = std::ceil(m / kTileRowsHost);
-                h->tile_bytes[l] += m * by + ntile * src;
-                h->tile_flops[l] += m * fl;
+        };
+        for (int32_t l = 0; l < nl; l++)
+            for (int32_t v : lvnodes[l]) {
+                if (L.eptr[v + 1] == L.eptr[v]) continue;
+                const bool tiled = nd.is_sn[v] && v < L.tail_node0 && L.m[v] >= tile_min;
+                double by = 0, ix = 0, fl = 0;
+                units(v, L.r0[v], L.r0[v] + L.m[v], L.eptr[v], L.eptr[v + 1], by, ix, fl);
+                (tiled ? h->tile_bytes : h->lvl_bytes)[l] += by;
+                (tiled ? h->tile_idx : h->lvl_idx)[l] += ix;
+                (tiled ? h->tile_flops : h->lvl_flops)[l] += fl;
+            }
+        // pieces: every row of the node takes the same source range in a level
+        for (int32_t l = 0; l < nl; l++) {
+            std::map<std::tuple<int32_t, int64_t, int64_t>, std::pair<int32_t, int32_t>> byrange;
+            for (const auto& pc : lvpieces[l]) {
+                const int32_t v = nd.of_row[pc[0]];
+                auto key = std::make_tuple(v, pc[1], pc[2]);
+                auto it = byrange.find(key);
+                if (it == byrange.end()) byrange[key] = {(int32_t)pc[0], (int32_t)pc[0] + 1};
+                else { it->second.first = std::min(it->second.first, (int32_t)pc[0]);
+                       it->second.second = std::max(it->second.second, (int32_t)pc[0] + 1); }
+            }
+            for (const auto& kv : byrange) {
+                double by = 0, ix = 0, fl = 0;
+                units(std::get<0>(kv.first), kv.second.first, kv.second.second, std::get<1>(kv.first),
+                      std::get<2>(kv.first), by, ix, fl);
+                h->lvl_bytes[l] += by;
+                h->lvl_idx[l] += ix;
+                h->lvl_flops[l] += fl;
+            }
+        }
+        // the block inverses: read and write the m x m block, m^3 / 3 flops
+        h->inv_bytes.assign(nl, 0.0);
+        h->inv_flops.assign(nl, 0.0);
+        for (int32_t l = 0; l < nl; l++)
+            for (int64_t q = h->inv_ptr[l]; q < h->inv_ptr[l + 1]; q++) {
+                const double m = L.m[h->inv_nodes[q]];
+                h->inv_bytes[l] += 2.0 * m * m;
+                h->inv_flops[l] += m * m * m / 3.0;
+            }
+        // one right-hand side through the solves: 2 flops and one value per
+        // exact factor entry, plus a 4-byte column index in standalone rows
+        // (supernode rows share their column list)
+        h->solve_units.fill(0.0);
+        for (int32_t i = 0; i < n; i++) {
+            double nl_i = 0;
+            for (int64_t q = S.lp[i]; q < S.lp[i + 1]; q++) nl_i += S.lint[2 * q + 1] - S.lint[2 * q] + 1;
+            const double nu_i = (double)S.ucount[i] + 1.0;
+            const double sa = nd.is_sn[nd.of_row[i]] ? 0.0 : 1.0;
+            if (i >= L.t0 && L.mT > 0) {
+                h->solve_units[4] += nl_i + nu_i;
+                h->solve_units[5] += sa * (nl_i + nu_i);
             } else {
-                h->lvl_bytes[l] += m * (by + src);
-                h->lvl_flops[l] += m * fl;
+                h->solve_units[0] += nl_i;
+                h->solve_units[1] += sa * nl_i;
+                h->solve_units[2] += nu_i;
+                h->solve_units[3] += sa * nu_i;
             }
         }
-    for (int32_t l = 0; l < nl; l++)
-        for (const auto& pc : lvpieces[l]) {
-            const int32_t v = nd.of_row[pc[0]];
-            double src = 0, fl = 0;
-            for (int64_t e = pc[1]; e < pc[2]; e++) {
-                int32_t u = L.esrc[e];
-                double ms = L.m[u], ws = L.W[u] - L.lw[u] - L.m[u];
-                src += 8.0 * ms * (ms + ws) + 4.0 * ws + 48.0;
-                fl += ms * (ms + 2.0 * ws);
-            }
-            h->lvl_bytes[l] += 16.0 * L.W[v] + src;
-            h->lvl_flops[l] += fl;
-        }
+    }
     plog("tasks");
     h->analyzed = true;
     return HYLU_OK;
+}
+
+// the matrix of the FP64 residual: A itself, or A^T through its column copy
+// (the values of the last (re)factorisation gathered into column order)
+hylu_status residual_operator(hylu_handle h, int32_t transpose, hipStream_t st, const double*& av,
+                              const int64_t*& rp, const int32_t*& ci)
+{
+    av = h->d_aval; rp = h->d_arp; ci = h->d_aci;
+    if (transpose) {
+        HIPCHK(launch_gather_values(h->nnz, h->d_atq, h->d_aval, h->d_atv, st));
+        av = h->d_atv; rp = h->d_atp; ci = h->d_atc;
+    }
+    return HYLU_OK;
+}
+
+// r = b - op(A) x in FP64, then on the host the normwise backward error
+// ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf) (largest over the right-hand
+// sides and the members of a batch) and the accuracy measure of Sec. 3.3,
+// ||r||_1 / ||b||_1 (largest likewise).  Synchronises the stream.
+hylu_status measure_residual(hylu_handle h, const SolveWs& w, const int64_t* rp, const int32_t* ci, const double* av,
+                             const double* b, int64_t ldb, const double* x, int64_t ldx, int32_t nrhs, hipStream_t st,
+                             double& eta, double& res1)
+{
+    const int32_t n = h->n;
+    const int32_t nseg = (int32_t)h->member_row_off.size() - 1;
+    HIPCHK(launch_residual(n, nrhs, rp, ci, av, b, ldb, x, ldx, w.r, st));
+    HIPCHK(launch_norms(n, nrhs, rp, av, w.r, x, ldx, b, ldb, h->d_seg, nseg, w.norms, st));
+    HIPCHK(hipMemcpyAsync(w.h_norms, w.norms, sizeof(double) * kNormSlots * ((size_t)nrhs + 1) * nseg,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    eta = 0.0;
+    res1 = 0.0;
+    for (int32_t sg = 0; sg < nseg; sg++) {
+        const double anorm = w.h_norms[kNormSlots * ((size_t)nrhs * nseg + sg)];
+        for (int32_t k = 0; k < nrhs; k++) {
+            const double* q = w.h_norms + kNormSlots * ((size_t)k * nseg + sg);
+            const double den = anorm * q[1] + q[2];
+            eta = std::max(eta, den > 0 ? q[0] / den : (q[0] > 0 ? std::numeric_limits<double>::infinity() : 0.0));
+            res1 = std::max(res1, q[4] > 0 ? q[3] / q[4] : (q[3] > 0 ? std::numeric_limits<double>::infinity() : 0.0));
+        }
+    }
+    return HYLU_OK;
+}
+
+// forward-backward substitution with refinement on work vectors w; the base
+// solve replays a cached graph (graphs = true) or is enqueued directly
+hylu_status solve_impl(hylu_handle h, const SolveWs& w, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
+                       int32_t transpose, hipStream_t st, bool graphs)
+{
+    const int32_t n = h->n;
+    // does refinement run?  (perturbed pivots, or FP32 factors)
+    if (!h->pert_known) {
+        HIPCHK(hipEventSynchronize(h->fact_done));
+        h->last_pert = h->h_pert[0];
+        h->pert_known = true;
+        if (h->h_pert[1]) { h->sticky_error = true; return HYLU_ERR_DEVICE; }
+    }
+    bool refine = h->fp32 || h->last_pert > 0;
+    // b is needed after x is written when refining in place
+    const double* b = d_b;
+    bool bcopy = refine && d_b == d_x;
+    if (bcopy) {
+        HIPCHK(hipMemcpy2DAsync(w.bc, sizeof(double) * (size_t)n, d_b, sizeof(double) * ld, sizeof(double) * (size_t)n,
+                                nrhs, hipMemcpyDeviceToDevice, st));
+        b = w.bc;
+    }
+    int64_t ldb = bcopy ? n : ld;
+    hylu_status s;
+    if (graphs) {
+        auto key = std::make_tuple(b, d_x, nrhs, ld, transpose);
+        if (h->solve_graphs.find(key) == h->solve_graphs.end()) trim_graphs(h->solve_graphs);
+        auto it = h->solve_graphs.find(key);
+        bool fresh = it == h->solve_graphs.end();
+        GraphEntry& g = h->solve_graphs[key];
+        s = run_graph(h, g, fresh, st, [&](hipStream_t cs) { return enqueue_solve(h, w, b, ldb, d_x, ld, nrhs, transpose, 0, cs); });
+        if (s != HYLU_OK) { if (fresh) h->solve_graphs.erase(key); return s; }
+    } else {
+        s = enqueue_solve(h, w, b, ldb, d_x, ld, nrhs, transpose, 0, st);
+        if (s != HYLU_OK) return s;
+    }
+    h->ir_iters = 0;
+    h->berr = h->resid1 = 0.0;
+    h->berr_known = false;
+    if (!refine) return HYLU_OK;
+    // FP64 iterative refinement on the original matrix (Sec. 2.3); the
+    // returned x is the iterate with the smallest backward error
+    const double* av = nullptr;
+    const int64_t* rp = nullptr;
+    const int32_t* ci = nullptr;
+    s = residual_operator(h, transpose, st, av, rp, ci);
+    if (s != HYLU_OK) return s;
+    int32_t maxit = h->opt.ir_maxit > 0 ? h->opt.ir_maxit : (h->fp32 ? 30 : 10);
+    double tol = h->opt.ir_tol > 0 ? h->opt.ir_tol : 1e-12;
+    double eta_prev = std::numeric_limits<double>::infinity();
+    double best = std::numeric_limits<double>::infinity(), best_res1 = 0.0;
+    double eta = 0.0, res1 = 0.0;
+    const size_t colb = sizeof(double) * (size_t)n;
+    for (int32_t it2 = 0;; it2++) {
+        s = measure_residual(h, w, rp, ci, av, b, ldb, d_x, ld, nrhs, st, eta, res1);
+        if (s != HYLU_OK) return s;
+        const bool improved = eta < best;
+        if (improved) { best = eta; best_res1 = res1; }
+        if (eta <= tol || it2 >= maxit || eta > eta_prev / 2) {
+            // a correction that did not improve on the saved iterate is undone
+            if (!improved)
+                HIPCHK(hipMemcpy2DAsync(d_x, sizeof(double) * ld, w.xbest, colb, colb, nrhs,
+                                        hipMemcpyDeviceToDevice, st));
+            break;
+        }
+        HIPCHK(hipMemcpy2DAsync(w.xbest, colb, d_x, sizeof(double) * ld, colb, nrhs, hipMemcpyDeviceToDevice, st));
+        eta_prev = eta;
+        s = enqueue_solve(h, w, w.r, n, d_x, ld, nrhs, transpose, 1, st);
+        if (s != HYLU_OK) return s;
+        h->ir_iters++;
+    }
+    h->berr = best;
+    h->resid1 = best_res1;
+    h->berr_known = true;
+    return best <= tol ? HYLU_OK : HYLU_WARN_IR_NOT_CONVERGED;
 }
 
 }  // namespace
@@ -1402,6 +1627,8 @@ hylu_status hylu_default_options(hylu_options* o)
     o->tail_sparse = 1;
     o->side_rows = 1;
     o->pipeline_rows = 0;
+    o->group_min_rows = kGroupMinRows;
+    o->group_tail_rows = kGroupTailRows;
     return HYLU_OK;
 }
 
@@ -1447,7 +1674,7 @@ hylu_status hylu_destroy(hylu_handle h)
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     if (h->fact_done) hipEventDestroy(h->fact_done);
     if (h->h_pert) hipHostFree(h->h_pert);
-    if (h->h_norms) hipHostFree(h->h_norms);
+    if (h->ws.h_norms) hipHostFree(h->ws.h_norms);
     for (int j = 0; j < hylu_handle_s::kSide; j++) {
         if (h->side[j]) hipStreamDestroy(h->side[j]);
         if (h->ev_join[j]) hipEventDestroy(h->ev_join[j]);
@@ -1662,85 +1889,50 @@ hylu_status hylu_solve(hylu_handle h, const double* d_b, double* d_x, int32_t nr
     if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
     if (h->sticky_error) return HYLU_ERR_DEVICE;
     if (ld < h->n) return HYLU_ERR_ARG;
+    hylu_status s = ensure_workspace(h, nrhs);
+    if (s != HYLU_OK) return s;
+    if (transpose) { s = ensure_tlists(h); if (s != HYLU_OK) return s; }
+    return solve_impl(h, h->ws, d_b, d_x, nrhs, ld, transpose, (hipStream_t)stream, true);
+}
+
+hylu_status hylu_residual(hylu_handle h, const double* d_b, const double* d_x, int32_t nrhs, int64_t ld,
+                          int32_t transpose, void* stream, double* berr, double* resid1)
+{
+    (void)hipGetLastError();
+    if (!h || !d_b || !d_x || nrhs <= 0) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
+    if (h->sticky_error) return HYLU_ERR_DEVICE;
+    if (ld < h->n) return HYLU_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     hylu_status s = ensure_workspace(h, nrhs);
     if (s != HYLU_OK) return s;
     if (transpose) { s = ensure_tlists(h); if (s != HYLU_OK) return s; }
-    const int32_t n = h->n;
-    // does refinement run?  (perturbed pivots, or FP32 factors)
-    if (!h->pert_known) {
-        HIPCHK(hipEventSynchronize(h->fact_done));
-        h->last_pert = h->h_pert[0];
-        h->pert_known = true;
-        if (h->h_pert[1]) { h->sticky_error = true; return HYLU_ERR_DEVICE; }
-    }
-    bool refine = h->fp32 || h->last_pert > 0;
-    // b is needed after x is written when refining in place
-    const double* b = d_b;
-    bool bcopy = refine && d_b == d_x;
-    if (bcopy) {
-        for (int32_t k = 0; k < nrhs; k++)
-            HIPCHK(hipMemcpyAsync(h->d_bc + (size_t)k * n, d_b + (size_t)k * ld, sizeof(double) * n,
-                                  hipMemcpyDeviceToDevice, st));
-        b = h->d_bc;
-    }
-    int64_t ldb = bcopy ? n : ld;
-    auto key = std::make_tuple(b, d_x, nrhs, ld, transpose);
-    if (h->solve_graphs.find(key) == h->solve_graphs.end()) trim_graphs(h->solve_graphs);
-    auto it = h->solve_graphs.find(key);
-    bool fresh = it == h->solve_graphs.end();
-    GraphEntry& g = h->solve_graphs[key];
-    s = run_graph(h, g, fresh, st, [&](hipStream_t cs) { return enqueue_solve(h, b, ldb, d_x, ld, nrhs, transpose, 0, cs); });
-    if (s != HYLU_OK) { if (fresh) h->solve_graphs.erase(key); return s; }
-    h->ir_iters = 0;
-    h->berr = 0.0;
-    if (!refine) return HYLU_OK;
-    // FP64 iterative refinement on the original matrix (Sec. 2.3)
-    const double* av = h->d_aval;
-    const int64_t* rp = h->d_arp;
-    const int32_t* ci = h->d_aci;
-    if (transpose) {
-        HIPCHK(launch_gather_values(h->nnz, h->d_atq, av, h->d_atv, st));
-        av = h->d_atv; rp = h->d_atp; ci = h->d_atc;
-    }
-    int32_t maxit = h->opt.ir_maxit > 0 ? h->opt.ir_maxit : (h->fp32 ? 30 : 10);
-    double tol = h->opt.ir_tol > 0 ? h->opt.ir_tol : 1e-12;
-    double eta_prev = std::numeric_limits<double>::infinity();
-    double eta = 0.0;
-    for (int32_t it2 = 0;; it2++) {
-        HIPCHK(launch_residual(n, nrhs, rp, ci, av, b, ldb, d_x, ld, h->d_r, st));
-        const int32_t nseg = (int32_t)h->member_row_off.size() - 1;
-        HIPCHK(launch_norms(n, nrhs, rp, av, h->d_r, d_x, ld, b, ldb, h->d_seg, nseg, h->d_norms, st));
-        HIPCHK(hipMemcpyAsync(h->h_norms, h->d_norms, sizeof(double) * 4 * ((size_t)nrhs + 1) * nseg,
-                              hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        // normwise backward error of every right-hand side of every member
-        eta = 0.0;
-        for (int32_t sg = 0; sg < nseg; sg++) {
-            double anorm = h->h_norms[4 * ((size_t)nrhs * nseg + sg)];
-            for (int32_t k = 0; k < nrhs; k++) {
-                const double* q = h->h_norms + 4 * ((size_t)k * nseg + sg);
-                double den = anorm * q[1] + q[2];
-                double e = den > 0 ? q[0] / den : 0.0;
-                eta = std::max(eta, e);
-            }
-        }
-        if (eta <= tol || it2 >= maxit || eta > eta_prev / 2) break;
-        eta_prev = eta;
-        s = enqueue_solve(h, h->d_r, n, d_x, ld, nrhs, transpose, 1, st);
-        if (s != HYLU_OK) return s;
-        h->ir_iters++;
-    }
+    const double* av = nullptr;
+    const int64_t* rp = nullptr;
+    const int32_t* ci = nullptr;
+    s = residual_operator(h, transpose, st, av, rp, ci);
+    if (s != HYLU_OK) return s;
+    double eta = 0.0, res1 = 0.0;
+    s = measure_residual(h, h->ws, rp, ci, av, d_b, ld, d_x, ld, nrhs, st, eta, res1);
+    if (s != HYLU_OK) return s;
     h->berr = eta;
-    return eta <= tol ? HYLU_OK : HYLU_WARN_IR_NOT_CONVERGED;
+    h->resid1 = res1;
+    h->berr_known = true;
+    if (berr) *berr = eta;
+    if (resid1) *resid1 = res1;
+    return HYLU_OK;
 }
 
-hylu_status hylu_grad_values(hylu_handle h, const double* d_lambda, const double* d_x, double* d_gval, void* stream)
+hylu_status hylu_grad_values(hylu_handle h, const double* d_lambda, const double* d_x, int32_t nrhs, int64_t ld,
+                             double* d_gval, void* stream)
 {
-    if (!h || !d_lambda || !d_x || !d_gval) return HYLU_ERR_ARG;
+    if (!h || !d_lambda || !d_x || !d_gval || nrhs <= 0) return HYLU_ERR_ARG;
     if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
     if (h->sticky_error) return HYLU_ERR_DEVICE;
-    HIPCHK(launch_grad(h->n, h->d_arp, h->d_aci, d_lambda, d_x, d_gval, (hipStream_t)stream));
+    if (ld < h->n) return HYLU_ERR_ARG;
+    HIPCHK(launch_grad(h->n, nrhs, ld, h->d_arp, h->d_aci, d_lambda, d_x, d_gval, (hipStream_t)stream));
     return HYLU_OK;
 }
 
@@ -1775,7 +1967,11 @@ hylu_status hylu_get_info(hylu_handle h, hylu_info* o)
         o->n_perturbed = h->last_pert;
     }
     o->ir_iters = h->ir_iters;
-    o->berr = h->berr;
+    o->berr = h->berr_known ? h->berr : -1.0;
+    o->resid_1 = h->berr_known ? h->resid1 : -1.0;
+    o->n_dense_sn = (int32_t)h->dsn.size();
+    o->sn_groups = h->sn_groups;
+    o->tail_groups = h->tail_groups;
     o->pivot_tau = h->tau;
     o->tail_rows = h->lay.mT;
     o->tail_panels = (int32_t)h->lay.panels.size();
@@ -1834,16 +2030,23 @@ hylu_status hylu_autotune(hylu_handle h, const double* d_val, void* stream, int3
             h->prof.on = false;
             if (s != HYLU_OK) break;
             if (hipStreamSynchronize(st) != hipSuccess) { s = HYLU_ERR_DEVICE; break; }
+            // one row launch per level and one supernode-LU launch per level
+            // that has small supernodes, in level order
             int32_t lr = 0;
             size_t ls = 0;
             for (const Profiler::Rec& r : h->prof.recs) {
+                if (r.cls == C_ROWS) lr++;
+                else if (r.cls == C_SNLU) ls++;
+            }
+            if (lr != T.pipe_level || ls != sn_levels.size()) { s = HYLU_ERR_INTERNAL; break; }
+            lr = 0;
+            ls = 0;
+            for (const Profiler::Rec& r : h->prof.recs) {
                 float ms = 0.f;
+                if (r.cls != C_ROWS && r.cls != C_SNLU) continue;
                 if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) { s = HYLU_ERR_DEVICE; break; }
-                if (r.cls == C_ROWS && lr < T.pipe_level) { trow[lr][t] = std::min(trow[lr][t], (double)ms); lr++; }
-                else if (r.cls == C_SNLU && ls < sn_levels.size()) {
-                    tsn[sn_levels[ls]][t] = std::min(tsn[sn_levels[ls]][t], (double)ms);
-                    ls++;
-                }
+                if (r.cls == C_ROWS) { trow[lr][t] = std::min(trow[lr][t], (double)ms); lr++; }
+                else { tsn[sn_levels[ls]][t] = std::min(tsn[sn_levels[ls]][t], (double)ms); ls++; }
             }
         }
     T.tune_rows = T.tune_sn = 0;
@@ -1894,7 +2097,7 @@ hylu_status hylu_profile(hylu_handle h, const double* d_val, const double* d_b, 
     h->prof.recs.clear();
     h->prof.used = 0;
     s = enqueue_factor(h, d_val, false, st);
-    if (s == HYLU_OK) s = enqueue_solve(h, d_b, h->n, d_x, h->n, 1, 0, 0, st);
+    if (s == HYLU_OK) s = enqueue_solve(h, h->ws, d_b, h->n, d_x, h->n, 1, 0, 0, st);
     h->prof.on = false;
     if (s != HYLU_OK) return s;
     HIPCHK(hipStreamSynchronize(st));
@@ -1908,6 +2111,14 @@ hylu_status hylu_profile(hylu_handle h, const double* d_val, const double* d_b, 
         acc[r.cls].bytes += r.bytes;
         acc[r.cls].flops += r.flops;
     }
+    // the solve classes take the exact entries they consume (one right-hand side)
+    const double es = h->fp32 ? 4.0 : 8.0;
+    const int scls[3] = {C_LSOLVE, C_USOLVE, C_TSOLVE};
+    for (int q = 0; q < 3; q++)
+        if (acc[scls[q]].launches) {
+            acc[scls[q]].bytes = es * h->solve_units[2 * q] + 4.0 * h->solve_units[2 * q + 1];
+            acc[scls[q]].flops = 2.0 * h->solve_units[2 * q];
+        }
     int32_t k = 0;
     for (int c = 0; c < C_N && k < max_classes; c++)
         if (acc[c].launches > 0) stats[k++] = acc[c];

@@ -947,15 +947,16 @@ __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v)
     atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
-// maxima per right-hand side and per segment of rows (the members of a
-// batch; one segment when seg is null): out[4 (k nseg + s) + q] for q = 0 |r|,
-// 1 |x|, 2 |b|; out[4 (nrhs nseg + s)] = largest row abs sum of A in segment s
+// per right-hand side and per segment of rows (the members of a batch; one
+// segment when seg is null), kNormSlots values at out[kNormSlots (k nseg + s)]:
+// 0 max|r|, 1 max|x|, 2 max|b|, 3 sum|r|, 4 sum|b|; and at
+// out[kNormSlots (nrhs nseg + s)] the largest row abs sum of A in segment s
 __global__ void k_norms(int32_t n, int32_t nrhs, const int64_t* __restrict__ rp, const double* __restrict__ av,
                         const double* __restrict__ r, const double* __restrict__ x, int64_t ldx,
                         const double* __restrict__ b, int64_t ldb, const int32_t* __restrict__ seg, int32_t nseg,
                         double* __restrict__ out)
 {
-    __shared__ double sm[3][256];
+    __shared__ double sm[5][256];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int first = blockIdx.x * blockDim.x;
     const int last = min(first + (int)blockDim.x, n) - 1;
@@ -964,39 +965,50 @@ __global__ void k_norms(int32_t n, int32_t nrhs, const int64_t* __restrict__ rp,
     const bool uniform = !seg || seg[last] == s_first;
     const int si = (i < n && seg) ? seg[i] : 0;
     for (int k = 0; k <= nrhs; k++) {
-        double m0 = 0, m1 = 0, m2 = 0;
+        double m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0;
         if (i < n) {
             if (k < nrhs) {
                 m0 = fabs(r[i + (int64_t)k * n]);
                 m1 = fabs(x[i + (int64_t)k * ldx]);
                 m2 = fabs(b[i + (int64_t)k * ldb]);
+                m3 = m0;
+                m4 = m2;
             } else {
                 for (int64_t p = rp[i]; p < rp[i + 1]; p++) m0 += fabs(av[p]);
             }
         }
-        double* o = out + 4 * ((int64_t)k * nseg);
+        double* o = out + kNormSlots * ((int64_t)k * nseg);
         if (!uniform) {
             if (i < n) {
-                atomic_max_nonneg(o + 4 * si + 0, m0);
+                double* q = o + kNormSlots * si;
+                atomic_max_nonneg(q + 0, m0);
                 if (k < nrhs) {
-                    atomic_max_nonneg(o + 4 * si + 1, m1);
-                    atomic_max_nonneg(o + 4 * si + 2, m2);
+                    atomic_max_nonneg(q + 1, m1);
+                    atomic_max_nonneg(q + 2, m2);
+                    atomicAdd(q + 3, m3);
+                    atomicAdd(q + 4, m4);
                 }
             }
             continue;
         }
         sm[0][threadIdx.x] = m0; sm[1][threadIdx.x] = m1; sm[2][threadIdx.x] = m2;
+        sm[3][threadIdx.x] = m3; sm[4][threadIdx.x] = m4;
         __syncthreads();
         for (int st = 128; st > 0; st >>= 1) {
-            if (threadIdx.x < st)
+            if (threadIdx.x < st) {
                 for (int q = 0; q < 3; q++) sm[q][threadIdx.x] = fmax(sm[q][threadIdx.x], sm[q][threadIdx.x + st]);
+                for (int q = 3; q < 5; q++) sm[q][threadIdx.x] += sm[q][threadIdx.x + st];
+            }
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            atomic_max_nonneg(o + 4 * s_first + 0, sm[0][0]);
+            double* q = o + kNormSlots * s_first;
+            atomic_max_nonneg(q + 0, sm[0][0]);
             if (k < nrhs) {
-                atomic_max_nonneg(o + 4 * s_first + 1, sm[1][0]);
-                atomic_max_nonneg(o + 4 * s_first + 2, sm[2][0]);
+                atomic_max_nonneg(q + 1, sm[1][0]);
+                atomic_max_nonneg(q + 2, sm[2][0]);
+                atomicAdd(q + 3, sm[3][0]);
+                atomicAdd(q + 4, sm[4][0]);
             }
         }
         __syncthreads();
@@ -1010,13 +1022,19 @@ __global__ void k_gather(int64_t nnz, const int64_t* __restrict__ idx, const dou
     if (q < nnz) dst[q] = src[idx[q]];
 }
 
-__global__ void k_grad(int32_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                       const double* __restrict__ lam, const double* __restrict__ x, double* __restrict__ g)
+// g[p] = -sum_k lam[i, k] x[ci[p], k] over the nrhs columns (leading dimension ld)
+__global__ void k_grad(int32_t n, int32_t nrhs, int64_t ld, const int64_t* __restrict__ rp,
+                       const int32_t* __restrict__ ci, const double* __restrict__ lam, const double* __restrict__ x,
+                       double* __restrict__ g)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double li = lam[i];
-    for (int64_t p = rp[i]; p < rp[i + 1]; p++) g[p] = -li * x[ci[p]];
+    for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+        const int64_t c = ci[p];
+        double s = 0.0;
+        for (int k = 0; k < nrhs; k++) s += lam[i + k * ld] * x[c + k * ld];
+        g[p] = -s;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -2216,7 +2234,7 @@ hipError_t launch_norms(int32_t n, int32_t nrhs, const int64_t* rp, const double
                         const double* x, int64_t ldx, const double* b, int64_t ldb, const int32_t* seg,
                         int32_t nseg, double* out, hipStream_t st)
 {
-    hipError_t e = launch_zero(out, sizeof(double) * 4 * ((size_t)nrhs + 1) * (size_t)nseg, st);
+    hipError_t e = launch_zero(out, sizeof(double) * kNormSlots * ((size_t)nrhs + 1) * (size_t)nseg, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_norms, dim3(nblk(n, 256)), dim3(256), 0, st, n, nrhs, rp, av, r, x, ldx, b, ldb, seg, nseg, out);
     return hipGetLastError();
@@ -2229,10 +2247,10 @@ hipError_t launch_gather_values(int64_t nnz, const int64_t* idx, const double* s
     return hipGetLastError();
 }
 
-hipError_t launch_grad(int32_t n, const int64_t* rp, const int32_t* ci, const double* lam, const double* x,
-                       double* g, hipStream_t st)
+hipError_t launch_grad(int32_t n, int32_t nrhs, int64_t ld, const int64_t* rp, const int32_t* ci, const double* lam,
+                       const double* x, double* g, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_grad, dim3(nblk(n, 256)), dim3(256), 0, st, n, rp, ci, lam, x, g);
+    hipLaunchKernelGGL(k_grad, dim3(nblk(n, 256)), dim3(256), 0, st, n, nrhs, ld, rp, ci, lam, x, g);
     return hipGetLastError();
 }
 

@@ -191,14 +191,17 @@ hipError_t launch_permute_out(bool fp32, int32_t n, int32_t nrhs, const int32_t*
 // r = b - op(A) x (FP64), op = A (CSR) or A^T (via the column copy)
 hipError_t launch_residual(int32_t n, int32_t nrhs, const int64_t* rp, const int32_t* ci, const double* av,
                            const double* b, int64_t ldb, const double* x, int64_t ldx, double* r, hipStream_t st);
-// per-RHS, per-segment maxima (segments: the members of a batch, seg[row] ->
-// member, or one segment when seg is null): out[4 (r nseg + s) + 0] = max|r|,
-// +1 max|x|, +2 max|b|; out[4 (nrhs nseg + s)] = max row abs sum of A
+// per-RHS, per-segment norms (segments: the members of a batch, seg[row] ->
+// member, or one segment when seg is null), kNormSlots values each:
+// out[kNormSlots (r nseg + s) + q] for q = 0 max|r|, 1 max|x|, 2 max|b|,
+// 3 sum|r|, 4 sum|b|; out[kNormSlots (nrhs nseg + s)] = max row abs sum of A
+constexpr int kNormSlots = 6;
 hipError_t launch_norms(int32_t n, int32_t nrhs, const int64_t* rp, const double* av, const double* r,
                         const double* x, int64_t ldx, const double* b, int64_t ldb, const int32_t* seg,
                         int32_t nseg, double* out, hipStream_t st);
 hipError_t launch_gather_values(int64_t nnz, const int64_t* idx, const double* src, double* dst, hipStream_t st);
-hipError_t launch_grad(int32_t n, const int64_t* rp, const int32_t* ci, const double* lam, const double* x,
-                       double* g, hipStream_t st);
+// g[p] = -sum_k lam[row p, k] x[col p, k] over nrhs columns of leading dimension ld
+hipError_t launch_grad(int32_t n, int32_t nrhs, int64_t ld, const int64_t* rp, const int32_t* ci, const double* lam,
+                       const double* x, double* g, hipStream_t st);
 
 }  // namespace hylu

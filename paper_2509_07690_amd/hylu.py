@@ -6,9 +6,11 @@ current stream.  If the library was not built, importing this module raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
-from typing import Optional
+import warnings
+import weakref
 
 import numpy as np
 # PyTorch ships its own HIP runtime (file libamdhip64.so, soname
@@ -38,7 +40,7 @@ class Options(C.Structure):
                 ("amd_dense", C.c_double), ("dense_tail", C.c_double), ("tail_min", C.c_int32),
                 ("tail_max", C.c_int32), ("sn_dense", C.c_int32),
                 ("sn_tile", C.c_int32), ("sn_inverse", C.c_int32), ("tail_sparse", C.c_int32), ("side_rows", C.c_int32),
-                ("pipeline_rows", C.c_int32)]
+                ("pipeline_rows", C.c_int32), ("group_min_rows", C.c_int32), ("group_tail_rows", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -47,7 +49,9 @@ class Info(C.Structure):
                 ("n_nodes", C.c_int32), ("n_supernodes", C.c_int32), ("rows_in_supernodes", C.c_int32),
                 ("max_supernode", C.c_int32), ("n_levels", C.c_int32 * 4), ("n_perturbed", C.c_int32),
                 ("ir_iters", C.c_int32), ("berr", C.c_double), ("pivot_tau", C.c_double),
-                ("tail_rows", C.c_int32), ("tail_panels", C.c_int32), ("flops_issued", C.c_uint64)]
+                ("tail_rows", C.c_int32), ("tail_panels", C.c_int32), ("flops_issued", C.c_uint64),
+                ("resid_1", C.c_double), ("n_dense_sn", C.c_int32), ("sn_groups", C.c_int32),
+                ("tail_groups", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,7 +79,8 @@ _sigs = {
     "hylu_factorize": [_P, _P, _P],
     "hylu_refactor": [_P, _P, _P],
     "hylu_solve": [_P, _P, _P, C.c_int32, C.c_int64, C.c_int32, _P],
-    "hylu_grad_values": [_P, _P, _P, _P, _P],
+    "hylu_grad_values": [_P, _P, _P, C.c_int32, C.c_int64, _P, _P],
+    "hylu_residual": [_P, _P, _P, C.c_int32, C.c_int64, C.c_int32, _P, _P, _P],
     "hylu_get_info": [_P, _P],
     "hylu_export_symbolic": [_P, _P],
     "hylu_export_factors": [_P, _P, _P, _P, _P, _P, _P, _P],
@@ -91,6 +96,42 @@ _lib.hylu_status_string.restype = C.c_char_p
 EXPORTED = tuple(_sigs)
 
 
+# Device memory of every handle comes from PyTorch's caching allocator
+# (hylu_allocator callbacks), so the library and torch share one pool.
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
+
+
+def _torch_alloc(ctx, nbytes, stream):
+    try:
+        dev = torch.cuda.current_device()
+        st = stream if stream else torch.cuda.current_stream(dev).cuda_stream
+        return torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
+    except Exception:         # the library reports HYLU_ERR_OOM
+        return None
+
+
+def _torch_free(ctx, ptr, stream):
+    if ptr:
+        torch.cuda.caching_allocator_delete(ptr)
+
+
+_ALLOCATOR = Allocator(None, _ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free))
+
+# handles still open at exit are destroyed while torch's allocator is alive
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for hd in list(_LIVE):
+        hd.close()
+
+
 class HyluError(RuntimeError):
     def __init__(self, code, what):
         msg = _lib.hylu_status_string(code).decode()
@@ -98,8 +139,15 @@ class HyluError(RuntimeError):
         self.code = code
 
 
+class RefinementWarning(RuntimeWarning):
+    """Iterative refinement stopped above its backward-error target."""
+
+
 def _chk(rc, what, allow_warn=False):
-    if rc == OK or (allow_warn and rc == WARN_IR_NOT_CONVERGED):
+    if rc == OK:
+        return rc
+    if allow_warn and rc == WARN_IR_NOT_CONVERGED:
+        warnings.warn(f"{what}: {_lib.hylu_status_string(rc).decode()}", RefinementWarning, stacklevel=3)
         return rc
     raise HyluError(rc, what)
 
@@ -151,7 +199,9 @@ class Handle:
     def __init__(self, row_ptr, col, val, user_perm=None, **opts):
         self.h = C.c_void_p()
         self.fact_id = 0          # bumped by every (re)factorisation
-        _chk(_lib.hylu_create(C.byref(self.h), None), "create")
+        self.last_status = OK
+        _chk(_lib.hylu_create(C.byref(self.h), C.byref(_ALLOCATOR)), "create")
+        _LIVE.add(self)
         rp = _np(row_ptr, np.int64)
         ci = _np(col, np.int32)
         va = _np(val, np.float64)
@@ -175,8 +225,10 @@ class Handle:
         self = cls.__new__(cls)
         self.h = C.c_void_p()
         self.fact_id = 0
+        self.last_status = OK
         self._perm = None
-        _chk(_lib.hylu_create(C.byref(self.h), None), "create")
+        _chk(_lib.hylu_create(C.byref(self.h), C.byref(_ALLOCATOR)), "create")
+        _LIVE.add(self)
         mats = [(_np(rp, np.int64), _np(ci, np.int32), _np(va, np.float64)) for rp, ci, va in members]
         k = len(mats)
         ns = (C.c_int32 * k)(*[m[0].size - 1 for m in mats])
@@ -231,7 +283,7 @@ class Handle:
             x = torch.empty_like(b) if out is None else out
             rc = _lib.hylu_solve(self.h, _dev_ptr(b, torch.float64), _dev_ptr(x, torch.float64), 1, self.n,
                                  1 if transpose else 0, _stream(stream))
-            _chk(rc, "solve", allow_warn=True)
+            self.last_status = _chk(rc, "solve", allow_warn=True)
             return x
         return self.solve_cols(b.t().contiguous(), transpose=transpose, stream=stream).t()
 
@@ -244,8 +296,19 @@ class Handle:
         x = torch.empty_like(bt) if out is None else out
         rc = _lib.hylu_solve(self.h, _dev_ptr(bt, torch.float64), _dev_ptr(x, torch.float64), k, n,
                              1 if transpose else 0, _stream(stream))
-        _chk(rc, "solve", allow_warn=True)
+        self.last_status = _chk(rc, "solve", allow_warn=True)
         return x
+
+    def residual(self, b, x, transpose=False, stream=None):
+        """(backward error, ||Ax-b||_1/||b||_1) of x for b, each the largest
+        over the columns: b, x (n,) or (k, n) float64 CUDA tensors (rows of a
+        (k, n) tensor are right-hand sides).  Synchronises the stream."""
+        import torch
+        k = 1 if b.dim() == 1 else b.shape[0]
+        eta, r1 = C.c_double(), C.c_double()
+        _chk(_lib.hylu_residual(self.h, _dev_ptr(b, torch.float64), _dev_ptr(x, torch.float64), k, self.n,
+                                1 if transpose else 0, _stream(stream), C.byref(eta), C.byref(r1)), "residual")
+        return eta.value, r1.value
 
     def autotune(self, values, reps=2, stream=None):
         """Pick per-level thread counts by timing (hylu_autotune); returns the
@@ -258,9 +321,12 @@ class Handle:
         return before.value, after.value
 
     def grad_values(self, lam, x, out=None, stream=None):
+        """dL/dval[p] = -sum_k lam[row p, k] x[col p, k]: lam, x are (n,) or
+        (k, n) float64 CUDA tensors (rows of a (k, n) tensor are columns)."""
         import torch
+        k = 1 if lam.dim() == 1 else lam.shape[0]
         g = torch.empty(self.nnz, dtype=torch.float64, device=lam.device) if out is None else out
-        _chk(_lib.hylu_grad_values(self.h, _dev_ptr(lam, torch.float64), _dev_ptr(x, torch.float64),
+        _chk(_lib.hylu_grad_values(self.h, _dev_ptr(lam, torch.float64), _dev_ptr(x, torch.float64), k, self.n,
                                    _dev_ptr(g, torch.float64), _stream(stream)), "grad_values")
         return g
 
@@ -343,11 +409,8 @@ class SparseSolve(torch.autograd.Function):
         if ctx.needs_input_grad[0]:
             if x.dim() == 1:
                 gval = h.grad_values(lam, x)
-            else:
-                lc, xc = lam.t().contiguous(), x.t().contiguous()
-                gval = h.grad_values(lc[0], xc[0])
-                for k in range(1, xc.shape[0]):
-                    gval += h.grad_values(lc[k], xc[k])
+            else:                 # (n, k): the library sums over the k columns
+                gval = h.grad_values(lam.t().contiguous(), x.t().contiguous())
         if ctx.needs_input_grad[1]:
             gb = lam
         return gval, gb, None

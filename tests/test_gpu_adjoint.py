@@ -39,7 +39,7 @@ def _loss_grad(hylu, h, A, b, xt):
     return float(loss), x.detach().cpu().numpy(), val.grad.cpu().numpy(), bb.grad.cpu().numpy()
 
 
-@pytest.mark.parametrize("side", [10, 16])
+@pytest.mark.parametrize("side", [10, 16, 32])
 def test_gradient_against_oracle_and_fd(hylu, side):
     w = synth.convdiff3d_7pt(side)
     A, b, xt = w.A, w.b[:, 0], w.extra["x_target"]

@@ -237,6 +237,51 @@ def test_grid3d_blocked_supernodes(hylu, side, sn_dense, tail, tile, inv):
     compare_backward_stability(h, o)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_grid27_grouped_panels(hylu, precision):
+    """27-point 3D grid 24^3 (ND, the supernode-heavy PDE path) with the
+    panel-group thresholds lowered (group_min_rows 128, group_tail_rows 256)
+    so the large supernodes' dense views and the dense tail go through the
+    grouped panels that the 64^3 grid takes at full size: pivots and structure
+    bit-exact, FP64 factors entry by entry (growth-derived tolerance) and by
+    their residual, two right-hand sides against the oracle's solutions with
+    backward error at most 1e-12 (FP32 factors: after FP64 refinement), then a
+    refactorisation with new values through the graph."""
+    w = synth.convdiff3d_27pt(24, nrhs=2)
+    A = w.A
+    opts = dict(ordering="nd", dense_tail=0.5, group_min_rows=128, group_tail_rows=256, precision=precision)
+    print(f"[case] 27-point 24^3 grouped {precision}", flush=True)
+    h = hylu.Handle(A.row_ptr, A.col, A.val, **opts)
+    inf = h.info()
+    assert inf["n_dense_sn"] > 0 and inf["sn_groups"] > 0 and inf["tail_groups"] > 0, inf
+    o, _ = oracle_for(h, A)
+    h.factorize(dev(A.val))
+    o.numeric(o.tau)
+    if precision == "fp64":
+        assert h.info()["n_perturbed"] == o.sizes()["n_perturbed"]
+        compare_factors(h, o, tol="derived")
+        print("residual ratios (device, oracle):", compare_backward_stability(h, o))
+    X = h.solve_cols(dev(w.b.T.copy())).cpu().numpy()
+    for k in range(2):
+        b = w.b[:, k]
+        assert o.backward_error(b, X[k])[0] <= 1e-12, k
+        assert rel_diff(X[k], o.solve(b)) <= 1e-10, k
+    A2 = synth.grid_values(A, 78, 26.0)
+    piv = hylu.factors_as_rows(h)[2]
+    h.refactor(dev(A2.val))
+    x2 = h.solve(dev(w.b[:, 0])).cpu().numpy()
+    o.set_values(A2.val)
+    o.numeric(o.tau, piv=piv)
+    if precision == "fp64":
+        compare_factors(h, o, tol="derived")
+        compare_backward_stability(h, o)
+    assert rel_diff(x2, o.solve(w.b[:, 0])) <= 1e-10
+    ident = np.arange(A.n, dtype=np.int32)
+    import oracle
+    o2 = oracle.Oracle(A.n, A2.row_ptr, A2.col, A2.val, ident, ident, np.ones(A.n), np.ones(A.n))
+    assert o2.backward_error(w.b[:, 0], x2)[0] <= 1e-12
+
+
 def test_fp32_refactor_fresh_values_full_circuit(hylu):
     """Circuit n = 200000, FP32 factors: refactorisations with fresh value sets
     on the first factorisation's pivot order converge under FP64 refinement
