@@ -50,6 +50,7 @@ typedef enum {
     HYLU_ERR_DEVICE = -7,           /* a HIP call failed */
     HYLU_ERR_NONFINITE = -8,        /* NaN or Inf in the input values */
     HYLU_ERR_INTERNAL = -9,
+    HYLU_ERR_SCRATCH = -10,         /* hylu_solve_noalloc: n x nrhs beyond its fixed scratch */
     HYLU_WARN_IR_NOT_CONVERGED = 1  /* solve finished, backward error above ir_tol */
 } hylu_status;
 
@@ -198,6 +199,25 @@ hylu_status hylu_refactor(hylu_handle h, const double* d_val, void* stream);
  * (d_b, d_x, nrhs, ld, transpose) like those of hylu_refactor. */
 hylu_status hylu_solve(hylu_handle h, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
                        int32_t transpose, void* stream);
+
+/* hylu_solve without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same substitution and refinement as hylu_solve, with
+ * its work vectors in a fixed device array of 64 MiB that the library holds
+ * on each GPU it runs on (set up by the first hylu_factorize on that device;
+ * no hipMalloc, hipFree or allocating library call here, and no graph: the
+ * launches go straight onto `stream`).  Limits: at most 64 right-hand sides
+ * and 2 n nrhs (factor-precision size) + 3 n nrhs 8 bytes of work vectors
+ * plus the norms, within 64 MiB (FP64 factors: n nrhs up to about 1.6e6);
+ * beyond that HYLU_ERR_SCRATCH and a message on stderr.  transpose = 1 needs
+ * the transposed column lists, built by an earlier hylu_solve with
+ * transpose = 1 on this handle; HYLU_ERR_ARG otherwise.  Every call on one
+ * GPU shares that GPU's scratch (its contents are those the last call left):
+ * calls that overlap in time on one GPU, from any handles or streams, race
+ * and must be serialised by the caller.  Arguments, layout and results as for
+ * hylu_solve. */
+hylu_status hylu_solve_noalloc(hylu_handle h, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
+                               int32_t transpose, void* stream);
 
 /* Gradient of a scalar loss through X = A^{-1} B with respect to the values of
  * A (the adjoint of the solve): d_gval[p] = -sum_k Lambda[row p, k] X[col p, k]

@@ -12,6 +12,7 @@
 #include <functional>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -28,7 +29,39 @@
 
 using namespace hylu;
 
+// Scratch of hylu_solve_noalloc: a fixed device array (each GPU the library
+// runs on holds its own copy until the process ends).  Host code never passes
+// its name to a kernel: the address on a device comes from
+// hipGetSymbolAddress, taken once per device at set-up (scratch_setup).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int32_t kNoallocRhs = 64;     // right-hand sides per call of hylu_solve_noalloc
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+void* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// the address of this device's scratch (the current device must be `dev`)
+hipError_t scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return hipSuccess;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = ptr;
+    return hipSuccess;
+}
+
+void* scratch_ptr(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[dev];
+}
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
@@ -173,6 +206,7 @@ struct hylu_handle_s {
     // solve workspace
     int32_t ws_nrhs = 0;
     SolveWs ws;                             // of hylu_solve (handle memory)
+    double* h_norms_fixed = nullptr;        // pinned norms of hylu_solve_noalloc (kNoallocRhs right-hand sides)
     // batch of matrices on one handle (block diagonal); one member otherwise
     std::vector<int64_t> member_row_off{0}, member_nnz_off{0};
     int32_t* d_seg = nullptr;               // member of every row (null for one member)
@@ -341,6 +375,17 @@ hylu_status ensure_workspace(hylu_handle h, int32_t nrhs)
         return HYLU_ERR_OOM;
     h->ws_nrhs = nrhs;
     return HYLU_OK;
+}
+
+// scratch bytes hylu_solve_noalloc carves for nrhs right-hand sides (each
+// vector rounded up to 256 bytes): the work vectors of SolveWs
+size_t noalloc_bytes(hylu_handle h, int32_t nrhs)
+{
+    auto r = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t es = h->fp32 ? sizeof(float) : sizeof(double);
+    const size_t nn = (size_t)h->n * nrhs;
+    const size_t nseg = h->member_row_off.size() - 1;
+    return 2 * r(es * nn) + 3 * r(sizeof(double) * nn) + r(sizeof(double) * kNormSlots * ((size_t)nrhs + 1) * nseg);
 }
 
 // column lists of the T and L regions for the transposed solves (built on first use)
@@ -857,6 +902,13 @@ hylu_status upload_device(hylu_handle h)
     const int32_t n = h->n;
     try {
         HIPCHK(hipGetDevice(&h->device));
+        HIPCHK(scratch_setup(h->device));
+        if (!h->h_norms_fixed) {
+            const size_t nseg = h->member_row_off.size() - 1;
+            if (hipHostMalloc((void**)&h->h_norms_fixed, sizeof(double) * kNormSlots * (kNoallocRhs + 1) * nseg) !=
+                hipSuccess)
+                return HYLU_ERR_OOM;
+        }
         if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
         if (!h->fact_done) HIPCHK(hipEventCreateWithFlags(&h->fact_done, hipEventDisableTiming));
         if (!h->h_pert && hipHostMalloc((void**)&h->h_pert, 2 * sizeof(int32_t)) != hipSuccess) return HYLU_ERR_OOM;
@@ -1645,6 +1697,7 @@ const char* hylu_status_string(hylu_status s)
     case HYLU_ERR_DEVICE: return "device error";
     case HYLU_ERR_NONFINITE: return "non-finite value";
     case HYLU_ERR_INTERNAL: return "internal error";
+    case HYLU_ERR_SCRATCH: return "problem larger than the fixed scratch of hylu_solve_noalloc";
     case HYLU_WARN_IR_NOT_CONVERGED: return "refinement did not reach the tolerance";
     }
     return "unknown status";
@@ -1675,6 +1728,7 @@ hylu_status hylu_destroy(hylu_handle h)
     if (h->fact_done) hipEventDestroy(h->fact_done);
     if (h->h_pert) hipHostFree(h->h_pert);
     if (h->ws.h_norms) hipHostFree(h->ws.h_norms);
+    if (h->h_norms_fixed) hipHostFree(h->h_norms_fixed);
     for (int j = 0; j < hylu_handle_s::kSide; j++) {
         if (h->side[j]) hipStreamDestroy(h->side[j]);
         if (h->ev_join[j]) hipEventDestroy(h->ev_join[j]);
@@ -1893,6 +1947,42 @@ hylu_status hylu_solve(hylu_handle h, const double* d_b, double* d_x, int32_t nr
     if (s != HYLU_OK) return s;
     if (transpose) { s = ensure_tlists(h); if (s != HYLU_OK) return s; }
     return solve_impl(h, h->ws, d_b, d_x, nrhs, ld, transpose, (hipStream_t)stream, true);
+}
+
+hylu_status hylu_solve_noalloc(hylu_handle h, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
+                               int32_t transpose, void* stream)
+{
+    (void)hipGetLastError();
+    if (!h || !d_b || !d_x || nrhs <= 0) return HYLU_ERR_ARG;
+    if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
+    if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
+    if (h->sticky_error) return HYLU_ERR_DEVICE;
+    if (ld < h->n) return HYLU_ERR_ARG;
+    // the transposed solve's column lists are handle memory built on first use
+    if (transpose && !h->tlists) return HYLU_ERR_ARG;
+    const int32_t nseg = (int32_t)h->member_row_off.size() - 1;
+    if (nrhs > kNoallocRhs || noalloc_bytes(h, nrhs) > kScratchBytes) {
+        std::fprintf(stderr, "hylu: hylu_solve_noalloc: n = %d with %d right-hand sides needs %zu bytes of scratch, "
+                             "more than its fixed %zu (or more than %d right-hand sides)\n",
+                     h->n, nrhs, noalloc_bytes(h, nrhs), kScratchBytes, kNoallocRhs);
+        return HYLU_ERR_SCRATCH;
+    }
+    void* base = scratch_ptr(h->device);
+    if (!base || !h->h_norms_fixed) return HYLU_ERR_DEVICE;      // set up by the first (re)factorisation
+    // carve the work vectors out of this device's scratch
+    SolveWs w;
+    const size_t es = h->fp32 ? sizeof(float) : sizeof(double);
+    const size_t nn = (size_t)h->n * nrhs;
+    char* p = static_cast<char*>(base);
+    auto take = [&](size_t bytes) { void* q = p; p += (bytes + 255) & ~size_t(255); return q; };
+    w.y = take(es * nn);
+    w.z = take(es * nn);
+    w.r = static_cast<double*>(take(sizeof(double) * nn));
+    w.bc = static_cast<double*>(take(sizeof(double) * nn));
+    w.xbest = static_cast<double*>(take(sizeof(double) * nn));
+    w.norms = static_cast<double*>(take(sizeof(double) * kNormSlots * ((size_t)nrhs + 1) * nseg));
+    w.h_norms = h->h_norms_fixed;
+    return solve_impl(h, w, d_b, d_x, nrhs, ld, transpose, (hipStream_t)stream, false);
 }
 
 hylu_status hylu_residual(hylu_handle h, const double* d_b, const double* d_x, int32_t nrhs, int64_t ld,

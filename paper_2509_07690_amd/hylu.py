@@ -79,6 +79,7 @@ _sigs = {
     "hylu_factorize": [_P, _P, _P],
     "hylu_refactor": [_P, _P, _P],
     "hylu_solve": [_P, _P, _P, C.c_int32, C.c_int64, C.c_int32, _P],
+    "hylu_solve_noalloc": [_P, _P, _P, C.c_int32, C.c_int64, C.c_int32, _P],
     "hylu_grad_values": [_P, _P, _P, C.c_int32, C.c_int64, _P, _P],
     "hylu_residual": [_P, _P, _P, C.c_int32, C.c_int64, C.c_int32, _P, _P, _P],
     "hylu_get_info": [_P, _P],
@@ -298,6 +299,17 @@ class Handle:
                              1 if transpose else 0, _stream(stream))
         self.last_status = _chk(rc, "solve", allow_warn=True)
         return x
+
+    def solve_noalloc(self, bt, out, transpose=False, stream=None):
+        """hylu_solve_noalloc: bt, out (n,) or (k, n) float64 CUDA tensors
+        (rows of a (k, n) tensor are right-hand sides); the library
+        allocates nothing (work vectors in its fixed per-GPU scratch)."""
+        import torch
+        k = 1 if bt.dim() == 1 else bt.shape[0]
+        rc = _lib.hylu_solve_noalloc(self.h, _dev_ptr(bt, torch.float64), _dev_ptr(out, torch.float64), k, self.n,
+                                     1 if transpose else 0, _stream(stream))
+        self.last_status = _chk(rc, "solve_noalloc", allow_warn=True)
+        return out
 
     def residual(self, b, x, transpose=False, stream=None):
         """(backward error, ||Ax-b||_1/||b||_1) of x for b, each the largest
