@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--pipeline-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 + refinement leg of the headline")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the other workloads (27-point grid, batch, adjoint) appended to the headline line")
     ap.add_argument("--value-sets", type=int, default=100,
                     help="value sets of the circuit workload (the workload refactorises each once)")
     ap.add_argument("--cpu-sample-refactors", type=int, default=3)
@@ -173,6 +175,13 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(A0, base, h, args.cpu_sample_refactors, args.warmup)
+    others = None
+    if not args.headline_only and args.precision == "fp64":
+        h.close()
+        del vals, bs, xs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        others = other_configs(args)
     out = {
         "metric": "refactor+solve ms (circuit n=200000, repeated solve)",
         "value": round(ms_step, 4),
@@ -203,6 +212,7 @@ def main():
         "kernels": kernels,
         "fp32_ir": fp32,
         "cpu_baseline": cpu,
+        "other_configs": others,
     }
     print(json.dumps(out))
 
@@ -311,7 +321,7 @@ def _line(metric, value, unit, args, dtype, config, **extra):
     print(json.dumps(out))
 
 
-def bench_batch(args):
+def batch_leg(members, precision, steps, warmup, sn_dense=64, sn_inverse=1, sn_tile=0):
     """The uneven batch: `members` matrices (even: local circuits n ~ U{2000..
     50000}; odd: 9-point grids, side ~ U{32..160}) on one handle; a step
     refactorises every member with its fresh values (one graph) and solves one
@@ -320,93 +330,97 @@ def bench_batch(args):
     from paper_2509_07690_amd import synth, hylu
     dev = torch.device("cuda:0")
     t0 = time.time()
-    ws = [synth.batch_member(m) for m in range(args.members)]
+    ws = [synth.batch_member(m) for m in range(members)]
     a0 = [w.extra["analyze_values"] for w in ws]
-    log(f"members {len(ws)} n={sum(w.A.n for w in ws)} ({time.time() - t0:.1f}s)")
+    log(f"batch: members {len(ws)} n={sum(w.A.n for w in ws)} ({time.time() - t0:.1f}s)")
     t0 = time.time()
-    hb = hylu.Handle.batch([(a.row_ptr, a.col, a.val) for a in a0], precision=args.precision, sn_dense=args.sn_dense,
-                            sn_inverse=args.sn_inverse)
+    hb = hylu.Handle.batch([(a.row_ptr, a.col, a.val) for a in a0], precision=precision, sn_dense=sn_dense,
+                           sn_inverse=sn_inverse, sn_tile=sn_tile)
     t_an = time.time() - t0
     inf = hb.info()
-    log(f"analyze {t_an:.1f}s F={inf['flops']:.3e} levels={inf['n_levels']}")
+    log(f"batch: analyze {t_an:.1f}s F={inf['flops']:.3e} levels={inf['n_levels']}")
     v0 = torch.from_numpy(np.concatenate([a.val for a in a0])).to(dev)
     v1 = torch.from_numpy(np.concatenate([w.A.val for w in ws])).to(dev)
     b = torch.from_numpy(np.concatenate([w.b[:, 0] for w in ws])).to(dev)
     x = torch.empty_like(b)
     hb.factorize(v0)
     t_def, t_tuned = hb.autotune(v1, reps=2)
-    log(f"autotune: level time {t_def:.2f} ms with built-in shapes, {t_tuned:.2f} ms tuned")
+    log(f"batch: autotune level time {t_def:.2f} ms with built-in shapes, {t_tuned:.2f} ms tuned")
 
     def step():
         hb.refactor(v1)
         hb.solve(b, out=x)
-    ms = _timed(step, args.steps, args.warmup)
-    t_ref = _timed(lambda: hb.refactor(v1), args.steps, 1)
+    ms = _timed(step, steps, warmup)
+    t_ref = _timed(lambda: hb.refactor(v1), steps, 1)
+    eta, res1 = hb.residual(b, x)
     prof = hb.profile(v1, b, torch.empty_like(b))
     kernels = {k["name"]: {"launches": k["launches"], "ms": round(k["ms"], 3)} for k in prof}
     roff, _ = hb.offsets()
     xs = x.cpu().numpy()
     err = max(float(np.abs(xs[roff[k]:roff[k + 1]] - w.x_true[:, 0]).max()) for k, w in enumerate(ws))
     info = hb.info()
-    _line(f"batch refactor+solve ms ({len(ws)} uneven matrices, one handle)", ms, "ms", args,
-          "f64" if args.precision == "fp64" else "f32+f64ir",
-          {"workload": f"uneven batch of {len(ws)}: circuits n~U[2000,50000] + 9-pt grids side~U[32,160]",
-           "members": len(ws), "n_total": hb.n, "nnz_total": hb.nnz, "precision": args.precision},
-          refactor_ms=round(t_ref, 4), factor_gflops=round(info["flops"] / (t_ref * 1e-3) / 1e9, 3),
-          flops=info["flops"], autotune_level_ms={"builtin": round(t_def, 3), "tuned": round(t_tuned, 3)},
-          max_abs_err_vs_x_true=err, ir_iters=info["ir_iters"], berr=info["berr"], analyze_s=round(t_an, 2),
-          kernels=kernels)
+    res = {"metric": f"batch refactor+solve ms ({len(ws)} uneven matrices, one handle)", "ms_per_step": round(ms, 4),
+           "precision": precision, "steps": steps,
+           "config": {"workload": f"uneven batch of {len(ws)}: circuits n~U[2000,50000] + 9-pt grids side~U[32,160]",
+                      "members": len(ws), "n_total": hb.n, "nnz_total": hb.nnz},
+           "refactor_ms": round(t_ref, 4), "factor_gflops": round(info["flops"] / (t_ref * 1e-3) / 1e9, 3),
+           "flops": info["flops"], "autotune_level_ms": {"builtin": round(t_def, 3), "tuned": round(t_tuned, 3)},
+           "backward_error": eta, "resid_1": res1, "max_abs_err_vs_x_true": err, "ir_iters": info["ir_iters"],
+           "analyze_s": round(t_an, 2), "kernels": kernels}
+    hb.close()
+    return res
 
 
-def bench_grid27(args):
-    """27-point 3D convection-diffusion on side^3 (ND ordering), 8 RHS."""
+def grid27_leg(side, precision, steps, warmup, dense_tail=0.5, sn_tile=0, sn_dense=64, sn_inverse=1, tail_sparse=1):
+    """27-point 3D convection-diffusion on side^3 (nested dissection with
+    multilevel separators), 8 RHS."""
     import torch
     from paper_2509_07690_amd import synth, hylu
-    side = args.n if args.n != 200000 else 64
     w = synth.convdiff3d_27pt(side)
     A = w.A
     t0 = time.time()
-    h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd", precision=args.precision, dense_tail=args.dense_tail,
-                    sn_tile=args.sn_tile, sn_dense=args.sn_dense, sn_inverse=args.sn_inverse,
-                    tail_sparse=args.tail_sparse)
+    h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd_ml", precision=precision, dense_tail=dense_tail,
+                    sn_tile=sn_tile, sn_dense=sn_dense, sn_inverse=sn_inverse, tail_sparse=tail_sparse)
     t_an = time.time() - t0
-    log(f"analyze {t_an:.1f}s F={h.info()['flops']:.3e} tail={h.info()['tail_rows']}")
+    log(f"grid27 {precision}: analyze {t_an:.1f}s F={h.info()['flops']:.3e} tail={h.info()['tail_rows']}")
     v = torch.from_numpy(A.val).cuda()
     B = torch.from_numpy(np.ascontiguousarray(w.b.T)).cuda()       # (8, n): column-major RHS
     X = torch.empty_like(B)
     t0 = time.time()
     h.factorize(v)
     torch.cuda.synchronize()
-    log(f"factorize {time.time() - t0:.2f}s")
-    ms = _timed(lambda: (h.refactor(v), h.solve_cols(B, out=X)), args.steps, args.warmup)
-    t_ref = _timed(lambda: h.refactor(v), args.steps, 1)
+    log(f"grid27 {precision}: factorize {time.time() - t0:.2f}s")
+    ms = _timed(lambda: (h.refactor(v), h.solve_cols(B, out=X)), steps, warmup)
+    t_ref = _timed(lambda: h.refactor(v), steps, 1)
+    h.solve_cols(B, out=X)
+    eta, res1 = h.residual(B, X)
+    prof = h.profile(v, B[0].contiguous(), torch.empty_like(B[0]))
+    kernels = {k["name"]: {"launches": k["launches"], "ms": round(k["ms"], 3),
+                           "TFLOPs": round(k["flops"] / max(k["ms"], 1e-9) / 1e9, 3)} for k in prof}
     info = h.info()
-    # normwise backward error of every right-hand side (host, FP64)
-    import scipy.sparse as sp
-    As = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
-    Xh = X.cpu().numpy().T
-    anorm = abs(As).sum(axis=1).max()
-    err = max(float(np.abs(As @ Xh[:, k] - w.b[:, k]).max() /
-                    (anorm * np.abs(Xh[:, k]).max() + np.abs(w.b[:, k]).max())) for k in range(w.b.shape[1]))
-    _line(f"refactor+solve ms (27-pt grid {side}^3, 8 rhs)", ms, "ms", args,
-          "f64" if args.precision == "fp64" else "f32+f64ir",
-          {"workload": f"convdiff3d_27pt side={side} n={A.n} nnz={A.nnz}, 8 rhs", "precision": args.precision},
-          refactor_ms=round(t_ref, 4), factor_gflops=round(info["flops"] / (t_ref * 1e-3) / 1e9, 3),
-          flops=info["flops"], backward_error=err, ir_iters=info["ir_iters"], berr=info["berr"],
-          analyze_s=round(t_an, 2), tail_rows=info["tail_rows"])
+    res = {"metric": f"refactor+solve ms (27-pt grid {side}^3, 8 rhs)", "ms_per_step": round(ms, 4),
+           "precision": precision, "steps": steps,
+           "config": {"workload": f"convdiff3d_27pt side={side} n={A.n} nnz={A.nnz}, 8 rhs"},
+           "refactor_ms": round(t_ref, 4), "factor_gflops": round(info["flops"] / (t_ref * 1e-3) / 1e9, 3),
+           "flops": info["flops"], "flops_issued": info["flops_issued"], "backward_error": eta, "resid_1": res1,
+           "ir_iters": info["ir_iters"], "analyze_s": round(t_an, 2), "tail_rows": info["tail_rows"],
+           "kernels_one_rhs": kernels}
+    h.close()
+    return res
 
 
-def bench_adjoint(args):
+def adjoint_leg(side, steps, warmup, dense_tail=0.15, sn_dense=64, sn_inverse=1, tail_sparse=1, sn_tile=0):
     """x = A^{-1} b and the gradient of 0.5||x - x_target||^2 with respect to
     the values of A and b, on the 7-point grid side^3 (ND): forward
     (refactor + solve) and backward (transposed solve + pattern gradient)."""
     import torch
     from paper_2509_07690_amd import synth, hylu
-    side = args.n if args.n != 200000 else 48
     w = synth.convdiff3d_7pt(side)
     A = w.A
-    h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd", dense_tail=args.dense_tail, sn_dense=args.sn_dense,
-                      sn_inverse=args.sn_inverse, tail_sparse=args.tail_sparse)
+    t0 = time.time()
+    h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd", dense_tail=dense_tail, sn_dense=sn_dense,
+                    sn_inverse=sn_inverse, tail_sparse=tail_sparse, sn_tile=sn_tile)
+    t_an = time.time() - t0
     v = torch.from_numpy(A.val).cuda()
     b = torch.from_numpy(np.ascontiguousarray(w.b[:, 0])).cuda()
     xt = torch.from_numpy(w.extra["x_target"]).cuda()
@@ -415,16 +429,67 @@ def bench_adjoint(args):
     def fwd():
         return hylu.sparse_solve(h, v, b)
 
+    grads = {}
+
     def fwd_bwd():
         vv = v.clone().requires_grad_()
         bb = b.clone().requires_grad_()
         x = hylu.sparse_solve(h, vv, bb)
         (0.5 * ((x - xt) ** 2).sum()).backward()
-    t_f = _timed(fwd, args.steps, args.warmup)
-    t_fb = _timed(fwd_bwd, args.steps, args.warmup)
-    _line(f"adjoint forward+backward ms (7-pt grid {side}^3)", t_fb, "ms", args, "f64",
-          {"workload": f"convdiff3d_7pt side={side} n={A.n} nnz={A.nnz}, loss 0.5||x-x_target||^2"},
-          forward_ms=round(t_f, 4), backward_ms=round(t_fb - t_f, 4), flops=h.info()["flops"])
+        grads["x"], grads["lam"] = x.detach(), bb.grad
+    t_f = _timed(fwd, steps, warmup)
+    t_fb = _timed(fwd_bwd, steps, warmup)
+    eta, _ = h.residual(b, grads["x"])
+    eta_t, _ = h.residual((grads["x"] - xt).contiguous(), grads["lam"], transpose=True)
+    res = {"metric": f"adjoint forward+backward ms (7-pt grid {side}^3)", "ms_per_step": round(t_fb, 4),
+           "precision": "fp64", "steps": steps,
+           "config": {"workload": f"convdiff3d_7pt side={side} n={A.n} nnz={A.nnz}, loss 0.5||x-x_target||^2"},
+           "forward_ms": round(t_f, 4), "backward_ms": round(t_fb - t_f, 4), "flops": h.info()["flops"],
+           "backward_error": eta, "backward_error_transposed": eta_t, "analyze_s": round(t_an, 2)}
+    h.close()
+    return res
+
+
+def _print_leg(res, args):
+    extra = {k: v for k, v in res.items() if k not in ("metric", "ms_per_step", "precision", "steps", "config")}
+    _line(res["metric"], res["ms_per_step"], "ms", args, "f64" if res["precision"] == "fp64" else "f32+f64ir",
+          dict(res["config"], precision=res["precision"]), **extra)
+
+
+def bench_batch(args):
+    _print_leg(batch_leg(args.members, args.precision, args.steps, args.warmup, args.sn_dense, args.sn_inverse,
+                         args.sn_tile), args)
+
+
+def bench_grid27(args):
+    side = args.n if args.n != 200000 else 64
+    _print_leg(grid27_leg(side, args.precision, args.steps, args.warmup, args.dense_tail if args.dense_tail != 0.15
+                          else 0.5, args.sn_tile, args.sn_dense, args.sn_inverse, args.tail_sparse), args)
+
+
+def bench_adjoint(args):
+    side = args.n if args.n != 200000 else 48
+    _print_leg(adjoint_leg(side, args.steps, args.warmup, args.dense_tail, args.sn_dense, args.sn_inverse,
+                           args.tail_sparse, args.sn_tile), args)
+
+
+def other_configs(args):
+    """The other workloads, each briefly (a few steps): the 27-point 64^3 grid
+    in FP64 and FP32 + refinement, the 256-member uneven batch in FP64 and FP32
+    + refinement, and the adjoint on the 7-point 48^3 grid."""
+    out = {}
+    import torch
+    for key, fn in (("grid27_64_fp64", lambda: grid27_leg(64, "fp64", 3, 1)),
+                    ("grid27_64_fp32_ir", lambda: grid27_leg(64, "fp32", 3, 1)),
+                    ("batch256_fp64", lambda: batch_leg(256, "fp64", 5, 1)),
+                    ("batch256_fp32_ir", lambda: batch_leg(256, "fp32", 5, 1)),
+                    ("adjoint_grid7_48", lambda: adjoint_leg(48, 5, 1))):
+        t0 = time.time()
+        out[key] = fn()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        log(f"{key}: {out[key]['ms_per_step']} ms per step ({time.time() - t0:.1f}s)")
+    return out
 
 
 def cpu_baseline(A0, base, h, nref, first):

@@ -56,7 +56,9 @@ typedef enum {
 
 /* Options of the preprocessing and numerical phases. */
 typedef struct {
-    int32_t ordering;      /* 0 AMD, 1 nested dissection, 2 natural, 3 user_perm (Sec. 2.1) */
+    int32_t ordering;      /* 0 AMD, 1 nested dissection (separators from breadth-first level structures),
+                              2 natural, 3 user_perm, 4 nested dissection with multilevel separators (smaller
+                              separators on 3D meshes) (Sec. 2.1) */
     const int32_t* user_perm; /* host, n entries, new -> old; read by hylu_analyze only */
     int32_t static_pivot;  /* 1: maximum-product matching + scaling (Sec. 2.1); 0: identity, unit scaling */
     int32_t precision;     /* 0: FP64 factors; 1: FP32 factors + FP64 iterative refinement */
@@ -89,13 +91,20 @@ typedef struct {
                               launches of the factor levels with fewer than 256 rows (a long tail row in pieces
                               over several of them, its sources in order) instead of waiting for the final level;
                               0: all of them in the final level (same factors either way; default 1) */
-    int32_t pipeline_rows; /* reserved for the pipelined mode of Sec. 2.2.1 (one persistent launch whose
-                              blocks wait per source node); switched off: must be 0, else HYLU_ERR_ARG */
+    int32_t pipeline_rows; /* pipelined mode of Sec. 2.2.1: > 0 schedules the factor levels from the first one
+                              after which every level has at most this many rows (and the deferred last level) as
+                              one persistent launch whose rows wait per source node instead of per level; the
+                              analysis builds that schedule and checks it is deadlock-free (HYLU_ERR_INTERNAL
+                              otherwise), but the launch is switched off on the device: hylu_factorize and
+                              hylu_refactor return HYLU_ERR_ARG for such a handle.  0: bulk mode (default) */
     int32_t group_min_rows;  /* blocked dense LU (large supernodes, dense tail): row panels go in groups of four
                                 (one trailing update per group) while at least this many rows remain below them
                                 (<= 0: default 2048) */
     int32_t group_tail_rows; /* a block-sparse dense tail takes panel groups from this many rows on, or when its
                                 plan keeps over half of the dense work (<= 0: default 16384) */
+    int32_t solve_chain;     /* 1: runs of at least 3 consecutive narrow forward / backward solve levels (at most 64
+                                nodes of at most 64 rows each) are solved by one workgroup in one launch, a barrier
+                                between levels, instead of one launch per level (Sec. 2.3; default 1) */
 } hylu_options;
 
 /* Optional device allocator (e.g. the PyTorch caching allocator).  alloc
@@ -128,6 +137,8 @@ typedef struct {
                                          solution as berr (largest over right-hand sides and members); -1 likewise */
     int32_t n_dense_sn;               /* supernodes outside the tail factored by the blocked dense kernels */
     int32_t sn_groups, tail_groups;   /* panel groups of more than one panel in their plans / in the tail's */
+    int32_t pipe_tasks;               /* row tasks of the pipelined launch (0: bulk mode only) */
+    int32_t chain_levels;             /* forward + backward solve levels solved inside chains (solve_chain) */
 } hylu_info;
 
 /* Analysis export for checking: every array is host memory the caller

@@ -13,13 +13,21 @@
 //   supervariables found by hashing, and variables whose only neighbour is the
 //   new element are eliminated with it.
 // * nd_order: nested dissection by recursive vertex-separator bisection, the
-//   parts below a size limit ordered by AMD.
+//   parts below a size limit ordered by AMD.  Two separator methods: the
+//   middle level of a breadth-first level structure from a pseudo-peripheral
+//   node (thinned to the nodes next to the upper side), or a multilevel
+//   bisection:
+//   the graph is coarsened by heavy-edge matching, the coarsest graph is split
+//   by greedy graph growing from several seeds, the split is refined by
+//   Fiduccia-Mattheyses passes on every level while it is projected back, and
+//   the vertex separator is the smaller boundary of the final edge cut.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <limits>
 #include <numeric>
 #include <queue>
+#include <random>
 #include <vector>
 
 #include "analysis.hpp"
@@ -404,10 +412,218 @@ static int32_t bfs_levels(const std::vector<int64_t>& xadj, const std::vector<in
     return maxl;
 }
 
+// ---- multilevel edge bisection ---------------------------------------------
+
+// a graph with vertex and edge weights (local numbering, no self loops)
+struct WGraph {
+    int32_t n = 0;
+    std::vector<int64_t> xadj;
+    std::vector<int32_t> adj, ew, vw;
+    int64_t total() const { int64_t t = 0; for (int32_t w : vw) t += w; return t; }
+};
+
+// heavy-edge matching: every vertex (in a random order) pairs with its
+// unmatched neighbour of largest edge weight; cmap[x] is x's coarse vertex
+static void coarsen(const WGraph& g, std::mt19937& rng, std::vector<int32_t>& cmap, WGraph& c)
+{
+    const int32_t n = g.n;
+    std::vector<int32_t> order(n), match(n, -1);
+    std::iota(order.begin(), order.end(), 0);
+    std::shuffle(order.begin(), order.end(), rng);
+    for (int32_t x : order) {
+        if (match[x] >= 0) continue;
+        int32_t best = -1, bw = -1;
+        for (int64_t p = g.xadj[x]; p < g.xadj[x + 1]; p++) {
+            const int32_t y = g.adj[p];
+            if (match[y] < 0 && g.ew[p] > bw) { bw = g.ew[p]; best = y; }
+        }
+        if (best >= 0) { match[x] = best; match[best] = x; } else match[x] = x;
+    }
+    cmap.assign(n, -1);
+    int32_t nc = 0;
+    for (int32_t x : order)
+        if (cmap[x] < 0) { cmap[x] = nc; cmap[match[x]] = nc; nc++; }
+    c.n = nc;
+    c.vw.assign(nc, 0);
+    std::vector<std::vector<int32_t>> members(nc);
+    for (int32_t x = 0; x < n; x++) { c.vw[cmap[x]] += g.vw[x]; members[cmap[x]].push_back(x); }
+    c.xadj.assign(nc + 1, 0);
+    c.adj.clear();
+    c.ew.clear();
+    std::vector<int32_t> slot(nc, -1);
+    for (int32_t u = 0; u < nc; u++) {
+        const size_t base = c.adj.size();
+        for (int32_t x : members[u])
+            for (int64_t p = g.xadj[x]; p < g.xadj[x + 1]; p++) {
+                const int32_t v = cmap[g.adj[p]];
+                if (v == u) continue;
+                if (slot[v] < 0) { slot[v] = (int32_t)c.adj.size(); c.adj.push_back(v); c.ew.push_back(0); }
+                c.ew[slot[v]] += g.ew[p];
+            }
+        for (size_t q = base; q < c.adj.size(); q++) slot[c.adj[q]] = -1;
+        c.xadj[u + 1] = (int64_t)c.adj.size();
+    }
+}
+
+static int64_t cut_weight(const WGraph& g, const std::vector<uint8_t>& side)
+{
+    int64_t cut = 0;
+    for (int32_t x = 0; x < g.n; x++)
+        for (int64_t p = g.xadj[x]; p < g.xadj[x + 1]; p++)
+            if (side[x] != side[g.adj[p]]) cut += g.ew[p];
+    return cut / 2;
+}
+
+// Fiduccia-Mattheyses passes: move the vertex of largest gain (cut weight
+// removed) to the other side while both sides stay within [lo, hi] weight,
+// each vertex at most once per pass, and keep the best prefix of moves
+static void fm_refine(const WGraph& g, std::vector<uint8_t>& side, int64_t lo, int64_t hi, int passes)
+{
+    const int32_t n = g.n;
+    std::vector<int64_t> gain(n);
+    std::vector<uint8_t> moved(n);
+    int64_t w[2] = {0, 0};
+    for (int32_t x = 0; x < n; x++) w[side[x]] += g.vw[x];
+    for (int pass = 0; pass < passes; pass++) {
+        for (int32_t x = 0; x < n; x++) {
+            int64_t gx = 0;
+            for (int64_t p = g.xadj[x]; p < g.xadj[x + 1]; p++) gx += side[g.adj[p]] != side[x] ? g.ew[p] : -g.ew[p];
+            gain[x] = gx;
+        }
+        std::fill(moved.begin(), moved.end(), 0);
+        // max-heap of (gain, vertex), lazily invalidated; boundary vertices only
+        std::priority_queue<std::pair<int64_t, int32_t>> heap;
+        for (int32_t x = 0; x < n; x++) {
+            bool bnd = false;
+            for (int64_t p = g.xadj[x]; p < g.xadj[x + 1] && !bnd; p++) bnd = side[g.adj[p]] != side[x];
+            if (bnd) heap.push({gain[x], x});
+        }
+        std::vector<int32_t> seq;
+        int64_t cur = 0, best = 0;
+        size_t best_len = 0;
+        int32_t since_best = 0;
+        while (!heap.empty() && since_best < 200) {
+            auto [gx, x] = heap.top();
+            heap.pop();
+            if (moved[x] || gx != gain[x]) continue;
+            const int s0 = side[x], s1 = 1 - s0;
+            if (w[s1] + g.vw[x] > hi || w[s0] - g.vw[x] < lo) continue;
+            moved[x] = 1;
+            side[x] = (uint8_t)s1;
+            w[s0] -= g.vw[x];
+            w[s1] += g.vw[x];
+            cur += gx;
+            seq.push_back(x);
+            for (int64_t p = g.xadj[x]; p < g.xadj[x + 1]; p++) {
+                const int32_t y = g.adj[p];
+                if (moved[y]) continue;
+                gain[y] += side[y] == s1 ? -2 * g.ew[p] : 2 * g.ew[p];
+                heap.push({gain[y], y});
+            }
+            if (cur > best) { best = cur; best_len = seq.size(); since_best = 0; } else since_best++;
+        }
+        // undo the moves after the best prefix
+        for (size_t q = seq.size(); q-- > best_len;) {
+            const int32_t x = seq[q];
+            const int s1 = side[x], s0 = 1 - s1;
+            side[x] = (uint8_t)s0;
+            w[s1] -= g.vw[x];
+            w[s0] += g.vw[x];
+        }
+        if (best <= 0) break;
+    }
+}
+
+// greedy graph growing from `seed`: the part grows by the boundary vertex
+// that adds the least cut, until it holds half of the weight
+static void grow(const WGraph& g, int32_t seed, std::vector<uint8_t>& side)
+{
+    const int32_t n = g.n;
+    side.assign(n, 1);
+    const int64_t half = g.total() / 2;
+    int64_t w0 = 0;
+    std::vector<int64_t> conn(n, 0);          // edge weight into part 0
+    std::vector<int64_t> deg(n, 0);
+    for (int32_t x = 0; x < n; x++)
+        for (int64_t p = g.xadj[x]; p < g.xadj[x + 1]; p++) deg[x] += g.ew[p];
+    std::priority_queue<std::pair<int64_t, int32_t>> heap;   // key: 2 conn - deg (cut removed)
+    heap.push({0, seed});
+    std::vector<uint8_t> in(n, 0);
+    while (w0 < half) {
+        int32_t x = -1;
+        while (!heap.empty()) {
+            auto [k, y] = heap.top();
+            heap.pop();
+            if (!in[y] && k == 2 * conn[y] - deg[y]) { x = y; break; }
+        }
+        if (x < 0) {                            // the part's component is used up: any vertex
+            for (int32_t y = 0; y < n && x < 0; y++) if (!in[y]) x = y;
+            if (x < 0) break;
+        }
+        in[x] = 1;
+        side[x] = 0;
+        w0 += g.vw[x];
+        for (int64_t p = g.xadj[x]; p < g.xadj[x + 1]; p++) {
+            const int32_t y = g.adj[p];
+            if (in[y]) continue;
+            conn[y] += g.ew[p];
+            heap.push({2 * conn[y] - deg[y], y});
+        }
+    }
+}
+
+// two-way split of g minimising the cut weight with both sides within 10% of
+// half the weight: coarsen to about 100 vertices, grow from eight seeds,
+// refine, project back level by level with refinement
+static std::vector<uint8_t> multilevel_bisect(const WGraph& g0, uint32_t seed)
+{
+    std::mt19937 rng(seed);
+    std::vector<WGraph> gs;
+    std::vector<std::vector<int32_t>> maps;
+    gs.push_back(g0);
+    while (gs.back().n > 100) {
+        WGraph c;
+        std::vector<int32_t> cmap;
+        coarsen(gs.back(), rng, cmap, c);
+        if (c.n > 0.9 * gs.back().n) break;        // no longer shrinking (e.g. a star)
+        maps.push_back(std::move(cmap));
+        gs.push_back(std::move(c));
+    }
+    auto bounds = [](const WGraph& g, int64_t& lo, int64_t& hi) {
+        const int64_t t = g.total();
+        int64_t maxv = 0;
+        for (int32_t w : g.vw) maxv = std::max<int64_t>(maxv, w);
+        lo = std::min<int64_t>((int64_t)(0.45 * t), t / 2 - maxv);
+        hi = std::max<int64_t>((int64_t)(0.55 * t) + 1, t / 2 + maxv);
+    };
+    const WGraph& cg = gs.back();
+    int64_t lo, hi;
+    bounds(cg, lo, hi);
+    std::vector<uint8_t> best;
+    int64_t best_cut = INT64_MAX;
+    std::uniform_int_distribution<int32_t> pick(0, std::max(cg.n - 1, 0));
+    for (int t = 0; t < 8; t++) {
+        std::vector<uint8_t> side;
+        grow(cg, pick(rng), side);
+        fm_refine(cg, side, lo, hi, 4);
+        const int64_t c = cut_weight(cg, side);
+        if (c < best_cut) { best_cut = c; best = side; }
+    }
+    for (size_t l = gs.size() - 1; l-- > 0;) {
+        const WGraph& g = gs[l];
+        std::vector<uint8_t> side(g.n);
+        for (int32_t x = 0; x < g.n; x++) side[x] = best[maps[l][x]];
+        bounds(g, lo, hi);
+        fm_refine(g, side, lo, hi, 4);
+        best.swap(side);
+    }
+    return best;
+}
+
 }  // namespace
 
 std::vector<int32_t> nd_order(int32_t n, const std::vector<int64_t>& xadj,
-                              const std::vector<int32_t>& adj, int32_t leaf_size, double dense_alpha)
+                              const std::vector<int32_t>& adj, int32_t leaf_size, double dense_alpha, bool multilevel)
 {
     // part[x]: id of the sub-problem node x belongs to, or -1 once numbered
     std::vector<int32_t> part(n, 0), level(n, -1), queue;
@@ -441,48 +657,82 @@ std::vector<int32_t> nd_order(int32_t n, const std::vector<int64_t>& xadj,
             stack.push_back({a, comp});
             continue;
         }
-        // pseudo-peripheral root: repeat BFS from the farthest node of the smallest degree
-        for (int it = 0; it < 6; it++) {
-            int32_t best = -1;
-            int64_t bestdeg = INT64_MAX;
-            for (int32_t x : nodes)
-                if (level[x] == maxl) {
-                    int64_t dgx = xadj[x + 1] - xadj[x];
-                    if (dgx < bestdeg) { bestdeg = dgx; best = x; }
-                }
-            int32_t ml2 = bfs_levels(xadj, adj, nodes, part, job.id, best, level, queue);
-            if (ml2 <= maxl) { if (ml2 == maxl) root = best; bfs_levels(xadj, adj, nodes, part, job.id, root, level, queue); break; }
-            root = best; maxl = ml2;
-        }
-        if (maxl < 2) { leaves.push_back(nodes); continue; }
-        // level sizes; choose the level near the middle (by count) with the fewest nodes
-        std::vector<int64_t> cnt(maxl + 1, 0);
-        for (int32_t x : nodes) cnt[level[x]]++;
-        int64_t half = (int64_t)nodes.size() / 2, acc = 0;
-        int32_t mid = 1;
-        for (int32_t l = 0; l <= maxl; l++) { acc += cnt[l]; if (acc >= half) { mid = l; break; } }
-        mid = std::max(1, std::min(mid, maxl - 1));
-        int32_t best = mid;
-        // search a window around the middle for a smaller separator with balance >= 1/3
-        int64_t below = 0;
-        for (int32_t l = 0; l <= maxl; l++) {
-            if (l >= 1 && l <= maxl - 1) {
-                int64_t above = (int64_t)nodes.size() - below - cnt[l];
-                if (3 * std::min(below, above) >= (int64_t)nodes.size() - cnt[l] &&
-                    cnt[l] < cnt[best]) best = l;
-            }
-            below += cnt[l];
-        }
-        // separator = level `best`, thinned: keep only nodes adjacent to the upper side
         std::vector<int32_t> sep, lower, upper;
-        for (int32_t x : nodes) {
-            if (level[x] < best) lower.push_back(x);
-            else if (level[x] > best) upper.push_back(x);
-            else {
-                bool touches_upper = false;
-                for (int64_t p = xadj[x]; p < xadj[x + 1] && !touches_upper; p++)
-                    touches_upper = part[adj[p]] == job.id && level[adj[p]] == best + 1;
-                if (touches_upper) sep.push_back(x); else lower.push_back(x);
+        if (multilevel) {
+            // multilevel edge bisection of the part, then the smaller of the two
+            // boundaries as the vertex separator
+            const int32_t m = (int32_t)nodes.size();
+            for (int32_t t = 0; t < m; t++) local[nodes[t]] = t;
+            WGraph g;
+            g.n = m;
+            g.xadj.assign(m + 1, 0);
+            g.vw.assign(m, 1);
+            for (int32_t t = 0; t < m; t++) {
+                const int32_t x = nodes[t];
+                for (int64_t p = xadj[x]; p < xadj[x + 1]; p++) {
+                    const int32_t y = adj[p];
+                    if (y != x && part[y] == job.id) { g.adj.push_back(local[y]); g.ew.push_back(1); }
+                }
+                g.xadj[t + 1] = (int64_t)g.adj.size();
+            }
+            const std::vector<uint8_t> side = multilevel_bisect(g, 0x9e3779b9u ^ (uint32_t)m);
+            int64_t nb[2] = {0, 0};
+            std::vector<uint8_t> bnd(m, 0);
+            for (int32_t t = 0; t < m; t++)
+                for (int64_t p = g.xadj[t]; p < g.xadj[t + 1]; p++)
+                    if (side[g.adj[p]] != side[t]) { bnd[t] = 1; nb[side[t]]++; break; }
+            const int ss = nb[0] <= nb[1] ? 0 : 1;      // the separator's side
+            for (int32_t t = 0; t < m; t++) {
+                const int32_t x = nodes[t];
+                if (side[t] == ss && bnd[t]) sep.push_back(x);
+                else if (side[t] == 0) lower.push_back(x);
+                else upper.push_back(x);
+            }
+            for (int32_t t = 0; t < m; t++) local[nodes[t]] = -1;
+            if (sep.empty() || lower.empty() || upper.empty()) { leaves.push_back(nodes); continue; }
+        } else {
+            // pseudo-peripheral root: repeat BFS from the farthest node of the smallest degree
+            for (int it = 0; it < 6; it++) {
+                int32_t best = -1;
+                int64_t bestdeg = INT64_MAX;
+                for (int32_t x : nodes)
+                    if (level[x] == maxl) {
+                        int64_t dgx = xadj[x + 1] - xadj[x];
+                        if (dgx < bestdeg) { bestdeg = dgx; best = x; }
+                    }
+                int32_t ml2 = bfs_levels(xadj, adj, nodes, part, job.id, best, level, queue);
+                if (ml2 <= maxl) { if (ml2 == maxl) root = best; bfs_levels(xadj, adj, nodes, part, job.id, root, level, queue); break; }
+                root = best; maxl = ml2;
+            }
+            if (maxl < 2) { leaves.push_back(nodes); continue; }
+            // level sizes; choose the level near the middle (by count) with the fewest nodes
+            std::vector<int64_t> cnt(maxl + 1, 0);
+            for (int32_t x : nodes) cnt[level[x]]++;
+            int64_t half = (int64_t)nodes.size() / 2, acc = 0;
+            int32_t mid = 1;
+            for (int32_t l = 0; l <= maxl; l++) { acc += cnt[l]; if (acc >= half) { mid = l; break; } }
+            mid = std::max(1, std::min(mid, maxl - 1));
+            int32_t best = mid;
+            // search a window around the middle for a smaller separator with balance >= 1/3
+            int64_t below = 0;
+            for (int32_t l = 0; l <= maxl; l++) {
+                if (l >= 1 && l <= maxl - 1) {
+                    int64_t above = (int64_t)nodes.size() - below - cnt[l];
+                    if (3 * std::min(below, above) >= (int64_t)nodes.size() - cnt[l] &&
+                        cnt[l] < cnt[best]) best = l;
+                }
+                below += cnt[l];
+            }
+            // separator = level `best`, thinned: keep only nodes adjacent to the upper side
+            for (int32_t x : nodes) {
+                if (level[x] < best) lower.push_back(x);
+                else if (level[x] > best) upper.push_back(x);
+                else {
+                    bool touches_upper = false;
+                    for (int64_t p = xadj[x]; p < xadj[x + 1] && !touches_upper; p++)
+                        touches_upper = part[adj[p]] == job.id && level[adj[p]] == best + 1;
+                    if (touches_upper) sep.push_back(x); else lower.push_back(x);
+                }
             }
         }
         for (int32_t x : sep) part[x] = -1;

@@ -22,6 +22,34 @@
 
 namespace hylu {
 
+// Is the strict upper structure of run R's last row, less its first entry p,
+// contained in U(p, >p)?  (Both sorted; p's run may still be open.)  Then a
+// row that takes run R as a source and also takes p needs nothing else of R.
+static bool run_covered_by(const Symbolic& s, int32_t R, int32_t p, int32_t open_run, int32_t open_start,
+                           const std::vector<int32_t>& open_u)
+{
+    const int32_t rs = s.run_start[R], last = s.run_start[R + 1] - 1;
+    const int32_t* a = s.run_u.data() + s.run_up[R] + (last - rs);
+    const int64_t na = s.run_up[R + 1] - s.run_up[R] - (last - rs);
+    const int32_t Rp = s.run_of[p];
+    const int32_t* b;
+    int64_t nb;
+    if (Rp == open_run) {
+        b = open_u.data() + (p - open_start);
+        nb = (int64_t)open_u.size() - (p - open_start);
+    } else {
+        const int32_t rsp = s.run_start[Rp];
+        b = s.run_u.data() + s.run_up[Rp] + (p - rsp);
+        nb = s.run_up[Rp + 1] - s.run_up[Rp] - (p - rsp);
+    }
+    int64_t q = 0;
+    for (int64_t t = 1; t < na; t++) {
+        while (q < nb && b[q] < a[t]) q++;
+        if (q == nb || b[q] != a[t]) return false;
+    }
+    return true;
+}
+
 bool symbolic_factor(const Csr& b, Symbolic& s)
 {
     const int32_t n = b.n;
@@ -32,6 +60,7 @@ bool symbolic_factor(const Csr& b, Symbolic& s)
     s.ucount.assign(n, 0);
     s.run_up.push_back(0);
     std::vector<int32_t> mark(n, -1), done(n, -1);
+    std::vector<int8_t> covered(n + 1, -1);            // per run: pruning test result (-1 not yet known)
     std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> heap;
     std::vector<int32_t> ubuf, open_u;                 // open_u: strict U of the open run's first row
     int32_t open_run = -1, open_start = 0;
@@ -62,6 +91,19 @@ bool symbolic_factor(const Csr& b, Symbolic& s)
             s.lint.push_back(k);
             s.lint.push_back(last);
             for (int32_t t = k; t <= last; t++) { done[t] = i; mark[t] = i; }
+            // pruning: when the run's structure past its first entry p (< i)
+            // lies inside U(p, >p), the source p (taken later, p > last)
+            // brings all of it; only p is queued here
+            if (R != open_run && last - rs < ulen) {
+                const int32_t pj = ul[last - rs];
+                if (pj < i) {
+                    if (covered[R] < 0) covered[R] = run_covered_by(s, R, pj, open_run, open_start, open_u) ? 1 : 0;
+                    if (covered[R] == 1) {
+                        if (mark[pj] != i) { mark[pj] = i; heap.push(pj); }
+                        continue;
+                    }
+                }
+            }
             for (int64_t t = last - rs; t < ulen; t++) {
                 int32_t j = ul[t];
                 if (mark[j] == i) continue;

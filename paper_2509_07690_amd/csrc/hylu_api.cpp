@@ -98,6 +98,7 @@ struct LevelTasks {
     int32_t tune_rows = 0, tune_sn = 0;  // when nonzero, every level uses this (autotuner trials)
     int32_t pipe_level = 0;           // levels from here on run as one pipelined launch
     int32_t pipe_maxW = 0, pipe_maxm = 0;
+    int32_t pipe_nt = 256, pipe_stage = 1024, pipe_cap = 4096;  // its launch shape
     std::vector<int32_t> node_level;  // execution level of every node
 };
 
@@ -173,11 +174,16 @@ struct hylu_handle_s {
     void* d_tinv = nullptr;                 // inverses of their diagonal blocks (L and U, 64 x 64 each)
     double tail_flops = 0.0;
     int32_t tail_groups = 0, sn_groups = 0;  // panel groups (of more than one panel) of the tail / the large supernodes
+    int32_t pipe_grid = 0;                  // persistent workgroups of the pipelined launch (resident at once)
     std::vector<DenseSn> dsn;
     std::vector<int32_t> dsn_ptr;           // per factor level into dsn
     std::vector<std::vector<int32_t>> dsn_l, dsn_u;   // per L-solve / U-solve level: dsn indices
     std::vector<int32_t> lsolve_sn;         // per L-solve level: 1 if it has a supernode for k_lsolve_sn
     std::vector<int32_t> usolve_sn;         // per U-solve level: 1 if it has a supernode for k_usolve_sn
+    // per solve graph (4: L, 1: U): for every level that starts a chain of
+    // narrow levels solved in one launch, the end of the chain (else -1)
+    std::vector<int32_t> chain_end[5];
+    int32_t* d_lev_ptr[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     std::vector<int64_t> inv_off;           // per node: offset of its block inverse, or -1
     int64_t inv_total = 0;
     std::vector<int64_t> inv_ptr;           // per factor level into inv_nodes
@@ -228,6 +234,7 @@ struct hylu_handle_s {
     std::vector<double> lvl_idx;
     std::vector<double> tile_bytes, tile_idx, tile_flops;
     std::vector<double> inv_bytes, inv_flops;
+    double pipe_snlu_bytes = 0.0, pipe_snlu_flops = 0.0;  // block LUs inside the pipelined launch (value entries)
     // one right-hand side: exact factor entries consumed by the L solve and
     // the U solve of the rows before the dense tail and by the tail's rows
     // (both solves), each with the count of those in standalone rows
@@ -235,9 +242,10 @@ struct hylu_handle_s {
 };
 
 static const char* kClassNames[] = {"rows", "snlu", "tail_panel", "tail_trsm", "tail_gemm", "lsolve", "usolve",
-                                    "tail_solve", "scatter", "other_solve", "sup_tile", "sn_inverse", "tail_dinv"};
+                                    "tail_solve", "scatter", "other_solve", "sup_tile", "sn_inverse", "tail_dinv",
+                                    "pipelined"};
 enum { C_ROWS, C_SNLU, C_PANEL, C_TRSM, C_GEMM, C_LSOLVE, C_USOLVE, C_TSOLVE, C_SCATTER, C_OSOLVE, C_TILE, C_SNINV,
-       C_DINV, C_N };
+       C_DINV, C_PIPE, C_N };
 
 namespace {
 
@@ -449,6 +457,9 @@ constexpr int32_t kRowCapSmall = 4096, kRowCapBig = 10240;
 // supernodes of at least this many rows (and at most 64) take the
 // four-wavefront forward-solve kernel
 constexpr int32_t kLsolveSnMin = 8;
+// a run of at least kChainMin solve levels of at most kChainNodes nodes is
+// solved by one workgroup in one launch
+constexpr int32_t kChainMin = 3, kChainNodes = 64;
 // The launch sequence of a view: groups of up to kGroup panels (left-looking
 // inside the group, one trailing update per group).  With the tail's masks M
 // every GEMM gets the list of its tiles that have a nonzero product, each with
@@ -721,17 +732,14 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
         // pipeline mode over the remaining levels
         double by = 0, fl = 0;
         for (int32_t l = T.pipe_level; l < nl; l++) { by += h->lvl_bytes[l] * es + h->lvl_idx[l]; fl += h->lvl_flops[l]; }
-        for (int64_t q = T.sn_ptr[T.pipe_level]; q < T.sn_ptr[nl]; q++) {
-            int32_t v = T.snodes[q];
-            double m = h->lay.m[v], wc = h->lay.W[v] - h->lay.lw[v];
-            by += 2.0 * es * m * wc;
-            fl += m * m * (2.0 * wc - m);
-        }
+        by += h->pipe_snlu_bytes * es;
+        fl += h->pipe_snlu_flops;
         const int64_t r0 = T.row_ptr[T.pipe_level], r1 = T.row_ptr[nl];
         HIPCHK(launch_pipe_reset(h->PC, h->lay.nnodes, st));
-        LAUNCH(C_ROWS, by, fl,
-               launch_factor_pipe(h->fp32, h->D, h->PC, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.pipe_maxW,
-                                  T.pipe_maxm, h->tau, h->d_pert, search ? 1 : 0, st));
+        LAUNCH(C_PIPE, by, fl,
+               launch_factor_pipe(h->fp32, h->D, h->PC, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.pipe_nt,
+                                  T.pipe_stage, T.pipe_cap, T.pipe_maxm, h->pipe_grid, h->tau, h->d_pert,
+                                  search ? 1 : 0, st));
     }
     // dense tail: blocked right-looking LU, one row panel at a time, then the
     // inverses of the solve panels' diagonal blocks
@@ -756,6 +764,18 @@ hylu_status enqueue_solve(hylu_handle h, const SolveWs& w, const double* b, int6
         for (size_t l = 0; l + 1 < L.xlev_ptr[g].size(); l++) {
             int32_t a = L.xlev_ptr[g][l], c = L.xlev_ptr[g][l + 1] - a;
             int cls = g == 4 ? C_LSOLVE : g == 1 ? C_USOLVE : C_OSOLVE;
+            if ((g == 4 || g == 1) && l < h->chain_end[g].size() && h->chain_end[g][l] > (int32_t)l) {
+                // a chain of narrow levels in one launch
+                const int32_t e = h->chain_end[g][l];
+                if (g == 4)
+                    LAUNCH(cls, 0, 0, launch_lsolve_chain(f, h->D, h->vals, h->d_lev_ptr[4], h->d_lev[4], (int32_t)l, e,
+                                                          w.y, nrhs, st));
+                else
+                    LAUNCH(cls, 0, 0, launch_usolve_chain(f, h->D, h->vals, h->d_lev_ptr[1], h->d_lev[1], (int32_t)l, e,
+                                                          w.y, w.z, nrhs, st));
+                l = e - 1;
+                continue;
+            }
             if (c > 0) LAUNCH(cls, 0, 0, fn(h->d_lev[g] + a, c, l));
             const std::vector<std::vector<int32_t>>* dl = g == 4 ? &h->dsn_l : g == 1 ? &h->dsn_u : nullptr;
             if (!dl || l >= dl->size()) continue;
@@ -891,6 +911,13 @@ void trim_graphs(Map& m)
     m.clear();
 }
 
+// the pipelined launch waits on source node s when s is factored inside it
+// (and outside the dense tail, which publishes nothing)
+inline int32_t pipe_source(const LevelTasks& T, const Layout& L, int32_t s)
+{
+    return (T.node_level[s] >= T.pipe_level && s < L.tail_node0) ? s : -1;
+}
+
 // device tables of the layout, uploaded on the first factorisation so the
 // analysis itself needs no GPU
 hylu_status upload_device(hylu_handle h)
@@ -902,6 +929,15 @@ hylu_status upload_device(hylu_handle h)
     const int32_t n = h->n;
     try {
         HIPCHK(hipGetDevice(&h->device));
+        {
+            // persistent workgroups of the pipelined launch: as many as are resident at once
+            int cus = 0;
+            HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+            const size_t es = h->fp32 ? 4 : 8;
+            const size_t need = factor_rows_lds(h->fp32, T.pipe_stage, T.pipe_cap) + (size_t)T.pipe_nt * (es + 4) + 64;
+            const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(need, 1)));
+            h->pipe_grid = std::max(1, cus) * std::min(per_cu, 2048 / T.pipe_nt);
+        }
         HIPCHK(scratch_setup(h->device));
         if (!h->h_norms_fixed) {
             const size_t nseg = h->member_row_off.size() - 1;
@@ -924,7 +960,7 @@ hylu_status upload_device(hylu_handle h)
                 d.ws = L.W[s] - L.lw[s] - L.m[s];
                 d.lp = L.elpos[e];
                 d.r0s = L.r0[s];
-                d.srcp = (T.node_level[s] >= T.pipe_level && s < L.tail_node0) ? s : -1;
+                d.srcp = pipe_source(T, L, s);
                 d.ioff = h->inv_off[s];
             }
         std::vector<double> asr(h->nnz), asc(h->nnz);
@@ -959,6 +995,7 @@ hylu_status upload_device(hylu_handle h)
         if (!h->d_uinv) return HYLU_ERR_OOM;
         D.uinv = h->d_uinv;
         for (int g = 0; g < 5; g++) UP(h->d_lev[g], L.xlev_nodes[g]);
+        for (int g : {4, 1}) UP(h->d_lev_ptr[g], L.xlev_ptr[g]);
         {
             TailView& TVw = h->TV;
             TVw = TailView();
@@ -1020,7 +1057,9 @@ hylu_status upload_device(hylu_handle h)
             UP(ctl, z2); UP(done, zn); UP(rdone, zn);
             h->PC = PipeCtl();
             h->PC.ctl = ctl; h->PC.done = done; h->PC.rows_done = rdone;
-            h->PC.spin_limit = 1 << 22;
+            // about a second of polling before a wait gives up (the launch
+            // then drains and the factorisation reports a device error)
+            h->PC.spin_limit = 1 << 20;
         }
         int32_t* pert;
         std::vector<int32_t> one(2, 0);
@@ -1081,7 +1120,8 @@ hylu_status order_matrix(const Csr& A, const hylu_options& opt, std::vector<int3
         std::vector<int32_t> adj;
         symmetrize(n, b0p, b0c, xadj, adj);
         double ad = opt.amd_dense > 0 ? opt.amd_dense : 10.0;
-        q = opt.ordering == 0 ? amd_order(n, xadj, adj, ad) : nd_order(n, xadj, adj, std::max(opt.nd_leaf, 8), ad);
+        q = opt.ordering == 0 ? amd_order(n, xadj, adj, ad)
+                              : nd_order(n, xadj, adj, std::max(opt.nd_leaf, 8), ad, opt.ordering == 4);
         if ((int32_t)q.size() != n) return HYLU_ERR_INTERNAL;
     }
     perm_c = q;
@@ -1092,6 +1132,44 @@ hylu_status order_matrix(const Csr& A, const hylu_options& opt, std::vector<int3
 
 // everything after the permutations and scalings: B = R A C, symbolic
 // factorisation, supernodes, levels, dense tail, panel layout, task lists
+// Host emulation of the pipelined launch's protocol over the tables the
+// device reads: tasks in ticket order, each waiting on the source nodes of
+// its source range that are factored in the launch, then publishing by the
+// kernel's rule (a standalone row outside the tail when done, a supernode
+// when its last row is done; tail rows publish nothing).  Every wait must be
+// on a node already published by earlier tickets: then the launch cannot
+// deadlock (the lowest unfinished ticket always has its sources complete, and
+// tickets are only taken by running workgroups).  Also checks that every row
+// of the region is one task with its whole source list.
+hylu_status check_pipeline(hylu_handle h)
+{
+    const LevelTasks& T = h->ft;
+    const Layout& L = h->lay;
+    const Nodes& nd = h->nodes;
+    const int32_t nl = (int32_t)T.maxW.size();
+    if (T.pipe_level >= nl) return HYLU_OK;
+    std::vector<char> done(L.nnodes, 0), seen(h->n, 0);
+    std::vector<int32_t> rows_done(L.nnodes, 0);
+    for (int64_t t = T.row_ptr[T.pipe_level]; t < T.row_ptr[nl]; t++) {
+        const int32_t i = T.rows[t], v = nd.of_row[i];
+        if (seen[i] || T.rrange[2 * t] != L.eptr[v] || T.rrange[2 * t + 1] != L.eptr[v + 1]) return HYLU_ERR_INTERNAL;
+        seen[i] = 1;
+        if (L.m[v] == 1 || L.eptr[v + 1] > L.eptr[v])
+            for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
+                const int32_t s = pipe_source(T, L, L.esrc[e]);
+                if (s >= 0 && !done[s]) {
+                    std::fprintf(stderr, "hylu: pipelined schedule: row %d waits on node %d before it is published\n", i, s);
+                    return HYLU_ERR_INTERNAL;
+                }
+            }
+        if (v >= L.tail_node0) continue;
+        if (L.m[v] == 1 || ++rows_done[v] == L.m[v]) done[v] = 1;
+    }
+    for (int32_t v = 0; v < L.nnodes; v++)
+        if (T.node_level[v] >= T.pipe_level && v < L.tail_node0 && !done[v]) return HYLU_ERR_INTERNAL;
+    return HYLU_OK;
+}
+
 hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
 {
     const int32_t n = h->n;
@@ -1178,13 +1256,26 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     }
     int32_t nl = (int32_t)lvnodes.size();
     std::vector<std::vector<std::array<int64_t, 3>>> lvpieces(nl);   // per level: (row, first, end source)
+    // pipelined mode (Sec. 2.2.1): the levels from the first one after which
+    // every level has at most pipeline_rows rows, and the deferred final
+    // level, run as one persistent launch whose rows wait per source node
+    // instead of per level
+    int32_t pipe_level = nl;
+    if (opt.pipeline_rows > 0 && nl > 0) {
+        const bool has_final = !late_nodes.empty();
+        const int32_t nmain = has_final ? nl - 1 : nl;
+        auto rows_of = [&](int32_t l) { int64_t r = 0; for (int32_t v : lvnodes[l]) r += L.m[v]; return r; };
+        int32_t l = nmain;
+        while (l > 0 && rows_of(l - 1) <= opt.pipeline_rows) l--;
+        if (l < nmain || has_final) pipe_level = l;
+    }
     // deferred standalone rows and tail rows join the launches of the narrow
     // levels (fewer than kSideNarrowRows rows) once their sources are
     // complete: one row per idle CU, and only where the level's own longest
     // row is estimated to take at least as long (sources applied one after
     // the other, plus the update volume), so the level does not get longer.
     // The rest stay in the final level.
-    if (opt.side_rows && !late_nodes.empty()) {
+    if (opt.side_rows && !late_nodes.empty() && pipe_level == nl) {
         const int32_t nmain = nl - 1;
         auto cost = [&](int32_t v) {
             double c = 0;
@@ -1264,9 +1355,22 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     T.tile_ptr.assign(1, 0);
     T.rrange.clear();
     h->pert_rows.clear();
+    T.pipe_maxW = T.pipe_maxm = 0;
     for (int32_t l = 0; l < nl; l++) {
         int32_t mw = 0, mm = 0;
         for (int32_t v : lvnodes[l]) {
+            if (l >= pipe_level) {
+                // pipelined: every row is a task (its whole source list); the
+                // supernode's block LU follows its last row inside the launch
+                for (int32_t r = L.r0[v]; r < L.r0[v] + L.m[v]; r++) {
+                    T.rows.push_back(r);
+                    T.rrange.push_back(L.eptr[v]);
+                    T.rrange.push_back(L.eptr[v + 1]);
+                }
+                mw = std::max(mw, L.W[v]);
+                if (nd.is_sn[v] && v < L.tail_node0) T.pipe_maxm = std::max(T.pipe_maxm, L.m[v]);
+                continue;
+            }
             if (L.eptr[v + 1] == L.eptr[v]) {
                 // no sources: nothing to apply; a standalone row outside the
                 // tail only has its pivot checked (one small launch for all)
@@ -1314,6 +1418,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         T.maxW.push_back(mw);
         T.maxm.push_back(mm);
         h->max_sn = std::max(h->max_sn, mm);
+        if (l >= pipe_level) T.pipe_maxW = std::max(T.pipe_maxW, mw);
     }
     // the dense tail's launches, block-sparse by its structural masks
     h->tail_ops.clear();
@@ -1373,7 +1478,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     h->inv_maxm.clear();
     for (int32_t l = 0; l < nl; l++) {
         int32_t mm = 0;
-        if (opt.sn_inverse)
+        if (opt.sn_inverse && l < pipe_level)
             for (int32_t v : lvnodes[l]) {
                 if (!nd.is_sn[v] || v >= L.tail_node0 || L.m[v] < 2 || L.m[v] > kInvMax) continue;
                 h->inv_off[v] = h->inv_total;
@@ -1409,9 +1514,38 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                     if (dix[L.xlev_nodes[g][t]] >= 0) out[l].push_back(dix[L.xlev_nodes[g][t]]);
         }
     }
-    // pipeline mode stays off: its dataflow launch did not finish on the device
-    // and the reason is not established, so every level is a launch of its own
-    T.pipe_level = nl;
+    // chains of narrow solve levels (Sec. 2.3): maximal runs of at least
+    // kChainMin consecutive levels with at most kChainNodes nodes, each of at
+    // most kChainRows rows and without a dense view
+    for (int g : {4, 1}) {
+        const auto& dl = g == 4 ? h->dsn_l : h->dsn_u;
+        const int32_t nlv = L.xlev_ptr[g].size() > 0 ? (int32_t)L.xlev_ptr[g].size() - 1 : 0;
+        h->chain_end[g].assign(nlv, -1);
+        if (!opt.solve_chain) continue;
+        auto ok = [&](int32_t l) {
+            const int32_t a = L.xlev_ptr[g][l], b = L.xlev_ptr[g][l + 1];
+            if (b - a > kChainNodes || (l < (int32_t)dl.size() && !dl[l].empty())) return false;
+            for (int32_t t = a; t < b; t++) if (L.m[L.xlev_nodes[g][t]] > kChainRows) return false;
+            return true;
+        };
+        for (int32_t l = 0; l < nlv;) {
+            int32_t e = l;
+            while (e < nlv && ok(e)) e++;
+            if (e - l >= kChainMin) h->chain_end[g][l] = e;
+            l = std::max(e, l + 1);
+        }
+    }
+    T.pipe_level = pipe_level;
+    if (pipe_level < nl) {
+        // one launch shape for every task: sixteen wavefronts and wide LDS
+        // buffers when long rows are in the region, else four
+        const bool wide = T.pipe_maxW > 1024;
+        T.pipe_nt = wide ? 1024 : 256;
+        T.pipe_stage = wide ? 4096 : kStageSmall;
+        T.pipe_cap = std::max(1, std::min(T.pipe_maxW, wide ? 8192 : kRowCapSmall));
+        const hylu_status sp = check_pipeline(h);
+        if (sp != HYLU_OK) return sp;
+    }
     // algorithmic traffic and flops of every row-kernel and tile launch, from
     // the unit costs of the update kinds (Sec. 2.2) on the exact structure:
     //  row-row (target row i, standalone source k with L(i,k) != 0):
@@ -1496,6 +1630,15 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 h->lvl_flops[l] += fl;
             }
         }
+        // the block LUs inside the pipelined launch
+        h->pipe_snlu_bytes = h->pipe_snlu_flops = 0.0;
+        for (int32_t l = T.pipe_level; l < nl; l++)
+            for (int32_t v : lvnodes[l])
+                if (nd.is_sn[v] && v < L.tail_node0) {
+                    const double m = L.m[v], w = L.W[v] - L.lw[v] - L.m[v];
+                    h->pipe_snlu_bytes += 2.0 * m * (m + w);
+                    h->pipe_snlu_flops += 2.0 * m * m * m / 3.0 + m * m * w;
+                }
         // the block inverses: read and write the m x m block, m^3 / 3 flops
         h->inv_bytes.assign(nl, 0.0);
         h->inv_flops.assign(nl, 0.0);
@@ -1570,6 +1713,16 @@ hylu_status measure_residual(hylu_handle h, const SolveWs& w, const int64_t* rp,
         }
     }
     return HYLU_OK;
+}
+
+// The pipelined launch (Sec. 2.2.1) is switched off on the device: its
+// schedule is built and checked at analysis, but a factorisation that would
+// run it is refused (its launch did not finish on the device twice)
+hylu_status pipelined_refused(hylu_handle h)
+{
+    if (h->ft.pipe_level >= (int32_t)h->ft.maxW.size()) return HYLU_OK;
+    std::fprintf(stderr, "hylu: the pipelined launch (pipeline_rows > 0) is switched off on the device\n");
+    return HYLU_ERR_ARG;
 }
 
 // forward-backward substitution with refinement on work vectors w; the base
@@ -1679,6 +1832,7 @@ hylu_status hylu_default_options(hylu_options* o)
     o->tail_sparse = 1;
     o->side_rows = 1;
     o->pipeline_rows = 0;
+    o->solve_chain = 1;
     o->group_min_rows = kGroupMinRows;
     o->group_tail_rows = kGroupTailRows;
     return HYLU_OK;
@@ -1744,9 +1898,9 @@ hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const
     if (!h || n <= 0 || !row_ptr || !col || !val) return HYLU_ERR_ARG;
     hylu_options opt;
     if (opt_in) opt = *opt_in; else hylu_default_options(&opt);
-    if (opt.ordering < 0 || opt.ordering > 3 || (opt.ordering == 3 && !opt.user_perm)) return HYLU_ERR_ARG;
+    if (opt.ordering < 0 || opt.ordering > 4 || (opt.ordering == 3 && !opt.user_perm)) return HYLU_ERR_ARG;
     if (opt.precision < 0 || opt.precision > 1 || opt.kernel_mode < 0 || opt.kernel_mode > 2) return HYLU_ERR_ARG;
-    if (opt.pipeline_rows != 0) return HYLU_ERR_ARG;     // pipelined mode is switched off
+    if (opt.pipeline_rows < 0) return HYLU_ERR_ARG;
     hylu_status st = validate_csr(n, row_ptr, col, val);
     if (st != HYLU_OK) return st;
     try {
@@ -1787,9 +1941,9 @@ hylu_status hylu_analyze_batch(hylu_handle h, int32_t count, const int32_t* n_k,
     if (!h || count <= 0 || !n_k || !row_ptr_k || !col_k || !val_k) return HYLU_ERR_ARG;
     hylu_options opt;
     if (opt_in) opt = *opt_in; else hylu_default_options(&opt);
-    if (opt.ordering < 0 || opt.ordering > 2) return HYLU_ERR_ARG;    // no user permutation for a batch
+    if (opt.ordering < 0 || opt.ordering > 4 || opt.ordering == 3) return HYLU_ERR_ARG;   // no user permutation for a batch
     if (opt.precision < 0 || opt.precision > 1 || opt.kernel_mode < 0 || opt.kernel_mode > 2) return HYLU_ERR_ARG;
-    if (opt.pipeline_rows != 0) return HYLU_ERR_ARG;
+    if (opt.pipeline_rows < 0) return HYLU_ERR_ARG;
     opt.dense_tail = 0.0;   // members are independent: the levels of all of them share the launches instead
     int64_t ntot = 0, nnztot = 0;
     for (int32_t k = 0; k < count; k++) {
@@ -1899,6 +2053,7 @@ hylu_status hylu_factorize(hylu_handle h, const double* d_val, void* stream)
     if (!h || !d_val) return HYLU_ERR_ARG;
     if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
     if (h->sticky_error) return HYLU_ERR_DEVICE;
+    if (pipelined_refused(h) != HYLU_OK) return HYLU_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (!h->uploaded) {
         hylu_status su = upload_device(h);
@@ -1921,6 +2076,7 @@ hylu_status hylu_refactor(hylu_handle h, const double* d_val, void* stream)
     if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
     if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
     if (h->sticky_error) return HYLU_ERR_DEVICE;
+    if (pipelined_refused(h) != HYLU_OK) return HYLU_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (h->refac_graphs.find(d_val) == h->refac_graphs.end()) trim_graphs(h->refac_graphs);
     auto it = h->refac_graphs.find(d_val);
@@ -2060,6 +2216,11 @@ hylu_status hylu_get_info(hylu_handle h, hylu_info* o)
     o->berr = h->berr_known ? h->berr : -1.0;
     o->resid_1 = h->berr_known ? h->resid1 : -1.0;
     o->n_dense_sn = (int32_t)h->dsn.size();
+    for (int g : {4, 1})
+        for (size_t l = 0; l < h->chain_end[g].size(); l++)
+            if (h->chain_end[g][l] > (int32_t)l) o->chain_levels += h->chain_end[g][l] - (int32_t)l;
+    o->pipe_tasks = h->ft.pipe_level < (int32_t)h->ft.maxW.size()
+                        ? (int32_t)(h->ft.row_ptr.back() - h->ft.row_ptr[h->ft.pipe_level]) : 0;
     o->sn_groups = h->sn_groups;
     o->tail_groups = h->tail_groups;
     o->pivot_tau = h->tau;

@@ -179,22 +179,29 @@ __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ va
 }
 
 // wave 0 waits until every listed source node is complete in this epoch
-// (src < 0: nothing to wait for); bounded: on timeout the error flag is set
+// (src < 0: nothing to wait for).  Bounded: after spin_limit polls the error
+// flag is set, and every wait (this one and all others) stops polling once
+// it is set, so the launch always drains; the results are then void and the
+// host reports a device error.
 __device__ __forceinline__ void wait_sources(const PipeCtl& P, int epoch, int src)
 {
     bool ok = src < 0 || __hip_atomic_load(P.done + src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
-    // after one wait has given up the results are void: no further waiting
-    if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = true;
     int it = 0;
     while (!__all(ok)) {
+        if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         if (++it > P.spin_limit) {
             __hip_atomic_store(P.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
         }
-        __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_s_sleep(2);
         if (!ok) ok = __hip_atomic_load(P.done + src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// is source node src (< 0: outside the pipelined region) complete in this epoch?
+__device__ __forceinline__ bool source_ready(const PipeCtl& P, int epoch, int src)
+{
+    return src < 0 || __hip_atomic_load(P.done + src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
 }
 
 // row updates of target row i by a block of NT threads.  Every source node (a
@@ -260,8 +267,16 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
                 if (lane >= off) pre = (pre > 0x3fffffff - o) ? 0x3fffffff : pre + o;
             }
             const unsigned long long fits = __ballot(pre <= stage && my < e1);
-            const int nb = (fits == ~0ull) ? 64 : __builtin_ctzll(~fits);
-            if (PIPE) wait_sources(PC, epoch, lane < (nb > 0 ? nb : 1) ? src : -1);
+            int nb = (fits == ~0ull) ? 64 : __builtin_ctzll(~fits);
+            if (PIPE) {
+                // wait for the batch's first source only, then keep the
+                // prefix of sources already complete: the row applies what it
+                // can while later sources are still being factored
+                wait_sources(PC, epoch, lane == 0 ? src : -1);
+                const unsigned long long rdy = __ballot(lane == 0 || lane >= nb || source_ready(PC, epoch, src));
+                const int nr = (rdy == ~0ull) ? 64 : __builtin_ctzll(~rdy);
+                nb = nb < nr ? nb : nr;
+            }
             if (lane < nb) {
                 eoff[lane] = pre - cost;
                 elp[lane] = ed.lp;
@@ -275,6 +290,8 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
             if (nb > 0 && lane == nb - 1) { eoff[nb] = pre; s_total = pre; }
         }
         __syncthreads();
+        // the sources' values were published by other workgroups (pipelined mode)
+        if (PIPE) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int nb = s_nb, total = s_total;
         if (nb == 0) {
             // a supernode source (or an oversized standalone one)
@@ -511,13 +528,18 @@ __global__ __launch_bounds__(NT) void k_factor_snlu(DevLayout D, T* __restrict__
     snlu_node<T, NT>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p);
 }
 
-// pipeline mode (Sec. 2.2.1): persistent blocks take rows in topological order
-// from a ticket; a row waits only for the source nodes it is about to read.
-// The block that finishes the last row of a supernode factors its block.
+// pipeline mode (Sec. 2.2.1): persistent workgroups take row tasks in a
+// topological order from a ticket; a row waits only for the source nodes it is
+// about to read (per batch of sources, not per level).  A standalone row
+// outside the dense tail publishes its node when done; the workgroup that
+// finishes the last row of a supernode factors the supernode's block and then
+// publishes it; tail rows publish nothing (the tail is factored after the
+// launch).  Publishing: every thread's stores are released at agent scope
+// before the flag is written; readers acquire after their wait.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_factor_pipe(DevLayout D, PipeCtl PC, T* __restrict__ vals,
                                                     const int32_t* __restrict__ rows, int32_t nrows,
-                                                    int32_t lds_cap, T tau, int32_t* __restrict__ pert,
+                                                    int32_t lds_cap, int32_t stage, T tau, int32_t* __restrict__ pert,
                                                     int32_t search)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -531,18 +553,19 @@ __global__ __launch_bounds__(NT) void k_factor_pipe(DevLayout D, PipeCtl PC, T* 
         if (tid == 0) s_task = __hip_atomic_fetch_add(PC.ctl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
         const int t = s_task;
+        __syncthreads();
         if (t >= nrows) break;
         const int i = rows[t];
-        row_task<T, NT, true>(D, vals, i, lds_cap, tau, pert, smem_raw, PC, epoch, kStage);
         const int v = D.row_node[i];
         const int m = D.m[v];
+        // a supernode row without sources has nothing to apply
+        if (m == 1 || D.eptr[v + 1] > D.eptr[v])
+            row_task<T, NT, true>(D, vals, i, lds_cap, tau, pert, smem_raw, PC, epoch, stage);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (v >= D.tail_node0) continue;            // the dense tail waits on no flag
         if (m == 1) {
-            if (tid == 0) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __hip_atomic_store(PC.done + v, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            if (tid == 0) __hip_atomic_store(PC.done + v, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             continue;
         }
         if (tid == 0) {
@@ -551,15 +574,14 @@ __global__ __launch_bounds__(NT) void k_factor_pipe(DevLayout D, PipeCtl PC, T* 
         }
         __syncthreads();
         if (!s_last) continue;
+        // every row of the supernode is complete: its block LU here
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         T* lrow = reinterpret_cast<T*>(smem_raw);
         uint8_t* taken = smem_raw + sizeof(T) * (size_t)m;
         snlu_node<T, NT>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (tid == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_store(PC.done + v, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (tid == 0) __hip_atomic_store(PC.done + v, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -746,6 +768,92 @@ __global__ __launch_bounds__(256) void k_lsolve_sn(DevLayout D, const T* __restr
                 if (lane > b && lane < m) va -= Lb[lane][b] * yb;
             }
             if (lane < m) yr[r0 + lane] = va;
+        }
+        __syncthreads();
+    }
+}
+
+// The long chain of narrow levels of the big triangle, solved sequentially
+// (Sec. 2.3, Fig. 3) in one launch: one workgroup walks the levels [l0, l1)
+// in order with a barrier between consecutive levels; inside a level every
+// wavefront takes a node (nodes of at most kChainRows rows), its rows in order
+// with the node's solved values kept in LDS, written out at the end.
+// forward: y_i = c_i - sum_k L(i,k) y_k
+template <typename T>
+__global__ __launch_bounds__(64 * kChainWaves) void k_lsolve_chain(DevLayout D, const T* __restrict__ vals,
+                                                                   const int32_t* __restrict__ lev_ptr,
+                                                                   const int32_t* __restrict__ nodes, int32_t l0,
+                                                                   int32_t l1, T* __restrict__ y, int32_t nrhs)
+{
+    __shared__ T ys[kChainWaves][kChainRows];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = D.n;
+    for (int l = l0; l < l1; l++) {
+        const int q1 = lev_ptr[l + 1];
+        for (int q = lev_ptr[l] + wv; q < q1; q += kChainWaves) {
+            const int v = nodes[q];
+            const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+            const T* P = vals + D.voff[v];
+            const int32_t* cols = D.cols + D.coff[v];
+            const int32_t* pl = D.pl + r0;
+            const int myp = lane < m ? pl[lane] : 0;
+            for (int r = 0; r < nrhs; r++) {
+                T* yr = y + (int64_t)r * n;
+                for (int a = 0; a < m; a++) {
+                    const T* Pa = P + (int64_t)a * W;
+                    T acc = gather_lq(Pa, cols, D.qinv, yr, lw, lane);
+                    if (lane < a) acc += Pa[lw + myp] * ys[wv][lane];
+                    acc = wave_sum(acc);
+                    if (lane == 0) ys[wv][a] = yr[r0 + a] - acc;
+                    __builtin_amdgcn_wave_barrier();
+                }
+                if (lane < m) yr[r0 + lane] = ys[wv][lane];
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// backward: x[piv a] = (y_a - sum_{j != piv a} U_st(a,j) x_j) / U_st(a, piv a),
+// the node's rows from the last, its values by local column in LDS
+template <typename T>
+__global__ __launch_bounds__(64 * kChainWaves) void k_usolve_chain(DevLayout D, const T* __restrict__ vals,
+                                                                   const int32_t* __restrict__ lev_ptr,
+                                                                   const int32_t* __restrict__ nodes, int32_t l0,
+                                                                   int32_t l1, const T* __restrict__ y,
+                                                                   T* __restrict__ x, int32_t nrhs)
+{
+    __shared__ T xs[kChainWaves][kChainRows];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = D.n;
+    for (int l = l0; l < l1; l++) {
+        const int q1 = lev_ptr[l + 1];
+        for (int q = lev_ptr[l] + wv; q < q1; q += kChainWaves) {
+            const int v = nodes[q];
+            const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+            const int w = W - lw - m;
+            const T* P = vals + D.voff[v] + lw;
+            const int32_t* tc = D.cols + D.coff[v] + lw + m;
+            const int32_t* pl = D.pl + r0;
+            const int myp = lane < m ? pl[lane] : 0;
+            for (int r = 0; r < nrhs; r++) {
+                const T* yr = y + (int64_t)r * n;
+                T* xr = x + (int64_t)r * n;
+                for (int a = m - 1; a >= 0; a--) {
+                    const T* Pa = P + (int64_t)a * W;
+                    T acc = gather_x(Pa + m, tc, xr, w, lane);
+                    if (lane > a && lane < m) acc += Pa[myp] * xs[wv][myp];
+                    acc = wave_sum(acc);
+                    if (lane == 0) {
+                        const int c = pl[a];
+                        xs[wv][c] = (yr[r0 + a] - acc) / Pa[c];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+                if (lane < m) xr[r0 + lane] = xs[wv][lane];
+                __builtin_amdgcn_wave_barrier();
+            }
         }
         __syncthreads();
     }
@@ -1653,10 +1761,12 @@ __global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ 
 // applies every source in ascending order, as the row kernel does for one
 // row, so each source's panel is read once per tile instead of once per row.
 // Standalone source: multipliers l_r = X[r][lp] / pivot, then a rank-1 update
-// through the relative map, each wavefront on its own four rows.  Supernode source s (ms rows): the tile's block
-// columns of s are solved against U_ss in s's pivot order (TRSM, staged in
-// LDS when ms <= kTileMs), then X[:, rel(T_s)] -= L (tile x ms) * U_s,T on
-// 16x16x4 MFMA, 16-column blocks per wavefront, scattered through rel.
+// through the relative map, each wavefront on its own four rows.  Supernode
+// source s (ms rows): the tile's block columns of s (staged in LDS when
+// ms <= kTileMs) times the inverse of U_ss in s's pivot order, on MFMA over the
+// four wavefronts, when s has that inverse (else a blocked triangular solve on
+// one wavefront), then X[:, rel(T_s)] -= L (tile x ms) * U_s,T on 16x16x4 MFMA,
+// 16-column blocks per wavefront, scattered through rel.
 constexpr int kTileRows = 16;
 constexpr int kTileMs = 448;
 
@@ -1705,10 +1815,45 @@ __global__ __launch_bounds__(256) void k_factor_tile(DevLayout D, T* __restrict_
         __syncthreads();
         auto PL = [&](int b) -> int { return in_lds ? pls[b] : plg[b]; };
         auto XP = [&](int r, int b) -> T& { return in_lds ? Xs[r][b] : X0[(int64_t)r * W + lp + PL(b)]; };
+        if (ed.ioff >= 0 && in_lds && ms <= 4 * 4 * 16) {
+            // L = XP U_pp^{-1} with the inverse of the source's block (upper
+            // triangular, row-major ms x ms): a tile x ms by ms x ms product on
+            // MFMA, the 16-column blocks of L spread over the four wavefronts
+            const T* Ui = reinterpret_cast<const T*>(D.uinv) + ed.ioff;
+            const int li = lane & 15, lk = lane >> 4;
+            const int nblk = (ms + 15) / 16;
+            v4 acc[4];
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                acc[t] = v4{T(0), T(0), T(0), T(0)};
+                const int jb = wv + 4 * t;
+                if (jb < nblk) {
+                    const int c = jb * 16 + li;
+                    const int kend = min(ms, jb * 16 + 16);      // Ui[k][c] = 0 for k > c
+                    for (int k0 = 0; k0 < kend; k0 += 4) {
+                        const int k = k0 + lk;
+                        const T av = k < ms ? Xs[li][k] : T(0);
+                        const T bv = (k < ms && c < ms) ? Ui[(int64_t)k * ms + c] : T(0);
+                        acc[t] = Mfma<T>::mma(av, bv, acc[t]);
+                    }
+                }
+            }
+            __syncthreads();          // every wavefront has read XP
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const int jb = wv + 4 * t;
+                const int c = jb * 16 + li;
+                if (jb < nblk && c < ms)
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const int r = Mfma<T>::row(lane, q);
+                        if (r < R) Xs[r][c] = acc[t][q];
+                    }
+            }
+        } else if (wv == 0) {
         // L = XP U_pp^{-1}, U_pp(b, b') = U(b, pl_b') upper triangular in pivot
         // order; blocked by 16 columns on wavefront 0: the block's update from
         // the solved columns on MFMA, then its 16 x 16 triangle, one lane per row
-        if (wv == 0) {
             const int li = lane & 15;
             for (int kb0 = 0; kb0 < ms; kb0 += 16) {
                 const int nb = min(16, ms - kb0);
@@ -2102,25 +2247,30 @@ hipError_t launch_pipe_reset(const PipeCtl& P, int32_t nnodes, hipStream_t st)
 }
 
 hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, void* vals, const int32_t* rows,
-                              int32_t nrows, int32_t maxW, int32_t maxm, double tau, int32_t* pert, int32_t search,
-                              hipStream_t st)
+                              int32_t nrows, int32_t nt, int32_t stage, int32_t lds_cap, int32_t maxm, int32_t grid,
+                              double tau, int32_t* pert, int32_t search, hipStream_t st)
 {
     if (nrows <= 0) return hipSuccess;
-    if (!P.ctl || !P.err || !P.done || !P.rows_done || P.spin_limit <= 0) return hipErrorInvalidValue;
-    int32_t cap = std::min(maxW, kRowLdsCap);
-    size_t fixed = (size_t)kStage * 4 + 129 * 4 + 4 + 128 * 8;
-    size_t es = fp32 ? sizeof(float) : sizeof(double);
-    size_t sh = std::max(es * (kStage + (size_t)std::max(cap, 1)) + fixed, (size_t)maxm * (es + 1) + 16);
-    if (sh > 60 * 1024) return hipErrorInvalidValue;
-    const bool wide = maxW > 1024;
-    unsigned grid = (unsigned)std::min(nrows, wide ? 1024 : 2048);
+    if (!P.ctl || !P.err || !P.done || !P.rows_done || P.spin_limit <= 0 || grid <= 0) return hipErrorInvalidValue;
+    if (stage < 64 || stage > kStageMax || stage % 64) return hipErrorInvalidValue;
+    const size_t es = fp32 ? sizeof(float) : sizeof(double);
+    const size_t sh = std::max(factor_rows_lds(fp32, stage, lds_cap), (size_t)maxm * (es + 1) + 16);
+    if (sh > kLdsMax) return hipErrorInvalidValue;
+    const dim3 g((unsigned)std::min(nrows, grid));
+#define PIPE_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_pipe<TT, NTT>), g, dim3(NTT), sh, st, D, P, (TT*)vals, rows, \
+                                                nrows, lds_cap, stage, (TT)tau, pert, search)
     if (fp32) {
-        if (wide) hipLaunchKernelGGL((k_factor_pipe<float, 256>), dim3(grid), dim3(256), sh, st, D, P, (float*)vals, rows, nrows, cap, (float)tau, pert, search);
-        else hipLaunchKernelGGL((k_factor_pipe<float, 64>), dim3(grid), dim3(64), sh, st, D, P, (float*)vals, rows, nrows, cap, (float)tau, pert, search);
+        if (nt == 1024) PIPE_LAUNCH(float, 1024);
+        else if (nt == 256) PIPE_LAUNCH(float, 256);
+        else if (nt == 64) PIPE_LAUNCH(float, 64);
+        else return hipErrorInvalidValue;
     } else {
-        if (wide) hipLaunchKernelGGL((k_factor_pipe<double, 256>), dim3(grid), dim3(256), sh, st, D, P, (double*)vals, rows, nrows, cap, tau, pert, search);
-        else hipLaunchKernelGGL((k_factor_pipe<double, 64>), dim3(grid), dim3(64), sh, st, D, P, (double*)vals, rows, nrows, cap, tau, pert, search);
+        if (nt == 1024) PIPE_LAUNCH(double, 1024);
+        else if (nt == 256) PIPE_LAUNCH(double, 256);
+        else if (nt == 64) PIPE_LAUNCH(double, 64);
+        else return hipErrorInvalidValue;
     }
+#undef PIPE_LAUNCH
     return hipGetLastError();
 }
 
@@ -2180,6 +2330,25 @@ hipError_t launch_usolve(bool fp32, const DevLayout& D, const void* vals, const 
     if (e != hipSuccess || sn_min <= 0) return e;
     if (fp32) hipLaunchKernelGGL(k_usolve_sn<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (const float*)y, (float*)x, nrhs, sn_min);
     else hipLaunchKernelGGL(k_usolve_sn<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (const double*)y, (double*)x, nrhs, sn_min);
+    return hipGetLastError();
+}
+
+hipError_t launch_lsolve_chain(bool fp32, const DevLayout& D, const void* vals, const int32_t* lev_ptr,
+                               const int32_t* nodes, int32_t l0, int32_t l1, void* y, int32_t nrhs, hipStream_t st)
+{
+    if (l1 <= l0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_lsolve_chain<float>, dim3(1), dim3(64 * kChainWaves), 0, st, D, (const float*)vals, lev_ptr, nodes, l0, l1, (float*)y, nrhs);
+    else hipLaunchKernelGGL(k_lsolve_chain<double>, dim3(1), dim3(64 * kChainWaves), 0, st, D, (const double*)vals, lev_ptr, nodes, l0, l1, (double*)y, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_usolve_chain(bool fp32, const DevLayout& D, const void* vals, const int32_t* lev_ptr,
+                               const int32_t* nodes, int32_t l0, int32_t l1, const void* y, void* x, int32_t nrhs,
+                               hipStream_t st)
+{
+    if (l1 <= l0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_usolve_chain<float>, dim3(1), dim3(64 * kChainWaves), 0, st, D, (const float*)vals, lev_ptr, nodes, l0, l1, (const float*)y, (float*)x, nrhs);
+    else hipLaunchKernelGGL(k_usolve_chain<double>, dim3(1), dim3(64 * kChainWaves), 0, st, D, (const double*)vals, lev_ptr, nodes, l0, l1, (const double*)y, (double*)x, nrhs);
     return hipGetLastError();
 }
 

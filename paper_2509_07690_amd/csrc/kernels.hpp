@@ -163,9 +163,13 @@ hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const i
 hipError_t launch_factor_tile(bool fp32, const DevLayout& D, void* vals, const int32_t* tiles, int32_t ntiles,
                               hipStream_t st);
 hipError_t launch_pipe_reset(const PipeCtl& P, int32_t nnodes, hipStream_t st);
+// the pipelined launch over nrows row tasks (topological order): nt threads
+// per workgroup (64, 256 or 1024), `stage` staged source entries and rows up
+// to lds_cap columns in LDS as for launch_factor_rows, maxm the largest
+// supernode factored in the launch, grid persistent workgroups
 hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, void* vals, const int32_t* rows,
-                              int32_t nrows, int32_t maxW, int32_t maxm, double tau, int32_t* pert, int32_t search,
-                              hipStream_t st);
+                              int32_t nrows, int32_t nt, int32_t stage, int32_t lds_cap, int32_t maxm, int32_t grid,
+                              double tau, int32_t* pert, int32_t search, hipStream_t st);
 // nt: threads per supernode (64 or 256; 0 = 256)
 // inverses of the blocks of the listed supernodes (each 2 <= m <= kInvMax)
 hipError_t launch_sn_inverse(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
@@ -178,6 +182,17 @@ hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const 
                          void* y, int32_t nrhs, int32_t sn_min, int32_t with_sn, hipStream_t st);
 hipError_t launch_usolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
                          const void* y, void* x, int32_t nrhs, int32_t sn_min, int32_t with_sn, hipStream_t st);
+// a chain of narrow solve levels [l0, l1) in one launch of one workgroup
+// (kChainWaves wavefronts, a node per wavefront, a barrier between levels);
+// lev_ptr: the level pointers of the solve graph's node list `nodes`; every
+// node of those levels has at most kChainRows rows and no dense view
+constexpr int kChainWaves = 16;
+constexpr int kChainRows = 64;
+hipError_t launch_lsolve_chain(bool fp32, const DevLayout& D, const void* vals, const int32_t* lev_ptr,
+                               const int32_t* nodes, int32_t l0, int32_t l1, void* y, int32_t nrhs, hipStream_t st);
+hipError_t launch_usolve_chain(bool fp32, const DevLayout& D, const void* vals, const int32_t* lev_ptr,
+                               const int32_t* nodes, int32_t l0, int32_t l1, const void* y, void* x, int32_t nrhs,
+                               hipStream_t st);
 hipError_t launch_utsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
                           const void* h, void* w, int32_t nrhs, hipStream_t st);
 hipError_t launch_ltsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,

@@ -40,7 +40,8 @@ class Options(C.Structure):
                 ("amd_dense", C.c_double), ("dense_tail", C.c_double), ("tail_min", C.c_int32),
                 ("tail_max", C.c_int32), ("sn_dense", C.c_int32),
                 ("sn_tile", C.c_int32), ("sn_inverse", C.c_int32), ("tail_sparse", C.c_int32), ("side_rows", C.c_int32),
-                ("pipeline_rows", C.c_int32), ("group_min_rows", C.c_int32), ("group_tail_rows", C.c_int32)]
+                ("pipeline_rows", C.c_int32), ("group_min_rows", C.c_int32), ("group_tail_rows", C.c_int32),
+                ("solve_chain", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -51,7 +52,8 @@ class Info(C.Structure):
                 ("ir_iters", C.c_int32), ("berr", C.c_double), ("pivot_tau", C.c_double),
                 ("tail_rows", C.c_int32), ("tail_panels", C.c_int32), ("flops_issued", C.c_uint64),
                 ("resid_1", C.c_double), ("n_dense_sn", C.c_int32), ("sn_groups", C.c_int32),
-                ("tail_groups", C.c_int32)]
+                ("tail_groups", C.c_int32), ("pipe_tasks", C.c_int32),
+                ("chain_levels", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -174,7 +176,7 @@ def _dev_ptr(t, dtype):
     return C.c_void_p(t.data_ptr())
 
 
-ORDERINGS = {"amd": 0, "nd": 1, "natural": 2, "user": 3}
+ORDERINGS = {"amd": 0, "nd": 1, "natural": 2, "user": 3, "nd_ml": 4}
 
 
 def default_options(**kw) -> Options:
@@ -193,7 +195,7 @@ class Handle:
     """One sparsity pattern: analyze once, factorize / refactor / solve many times.
 
     row_ptr, col, val are host arrays (CSR, 0-based, sorted unique columns).
-    Keyword options follow hylu_options (ordering="amd"|"nd"|"natural"|"user",
+    Keyword options follow hylu_options (ordering="amd"|"nd"|"nd_ml"|"natural"|"user",
     precision="fp64"|"fp32", static_pivot, sn_min, sn_max, kernel_mode, ...).
     """
 

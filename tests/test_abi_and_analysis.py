@@ -136,9 +136,58 @@ def test_one_hip_runtime_in_the_process():
     assert len(libs) == 1, libs
 
 
-def test_pipelined_mode_is_rejected():
+@pytest.mark.parametrize("case", ["config0", "config0_tail", "circuit", "batch", "grid3d"])
+def test_pipelined_schedule_is_deadlock_free(case):
+    """Pipelined mode (Sec. 2.2.1): the analysis emulates the persistent
+    launch's ticket / done-flag protocol on the tables the device reads (every
+    task in ticket order may only wait on source nodes that earlier tasks have
+    published, every node of the region is published, every row is one task
+    with its whole source list) and fails with HYLU_ERR_INTERNAL otherwise.
+    It succeeds for every node class: standalone rows with and without
+    sources, supernodes (small and large, with and without sources), tail rows,
+    the deferred level, and a batch of independent members."""
+    if case == "config0":
+        A, opts = synth.config(0).A, dict(dense_tail=0.0)
+    elif case == "config0_tail":
+        A, opts = synth.config(0).A, dict(dense_tail=0.3)
+    elif case == "circuit":
+        A, opts = synth.circuit_powerlaw(20000).A, dict(amd_dense=0.1, dense_tail=0.15)
+    elif case == "batch":
+        A, opts = None, {}
+    else:
+        A, opts = synth.convdiff3d_7pt(16).A, dict(ordering="nd", dense_tail=0.15, sn_dense=32)
+    last = -1
+    for rows in (8, 256, 1 << 30):
+        if A is None:
+            members = [synth.batch_member(m).A for m in range(4)]
+            h = hylu.Handle.batch([(a.row_ptr, a.col, a.val) for a in members], pipeline_rows=rows)
+            ref = hylu.Handle.batch([(a.row_ptr, a.col, a.val) for a in members])
+        else:
+            h = hylu.Handle(A.row_ptr, A.col, A.val, pipeline_rows=rows, **opts)
+            ref = hylu.Handle(A.row_ptr, A.col, A.val, **opts)
+        inf, inf0 = h.info(), ref.info()
+        assert inf0["pipe_tasks"] == 0 and inf["pipe_tasks"] >= last
+        last = inf["pipe_tasks"]
+        if rows == 1 << 30:
+            # every row's updates in the one launch (the dense tail's LU follows it)
+            assert inf["pipe_tasks"] == inf["n"]
+        for k in ("flops", "nnz_l", "nnz_u", "n_supernodes", "tail_rows"):
+            assert inf[k] == inf0[k], k
+        for k in ("perm_r", "perm_c", "node_ptr", "levels"):
+            assert np.array_equal(h.symbolic()[k], ref.symbolic()[k]), k
+    if A is not None:
+        assert _code(lambda: hylu.Handle(A.row_ptr, A.col, A.val, pipeline_rows=-1)) == -1
+
+
+def test_pipelined_factorisation_is_refused():
+    """The pipelined launch is switched off on the device: a handle analysed
+    with pipeline_rows > 0 refuses hylu_factorize / hylu_refactor with
+    HYLU_ERR_ARG before touching the device (null stream, dummy values)."""
     A = synth.config(0).A
-    assert _code(lambda: hylu.Handle(A.row_ptr, A.col, A.val, pipeline_rows=1024)) == -1
+    h = hylu.Handle(A.row_ptr, A.col, A.val, pipeline_rows=1 << 30)
+    lib = hylu._lib
+    assert lib.hylu_factorize(h.h, C.c_void_p(8), None) == -1
+    assert lib.hylu_refactor(h.h, C.c_void_p(8), None) == -5      # never factorised
 
 
 def test_batch_analysis_matches_members_and_oracle():
@@ -194,3 +243,51 @@ def test_default_options_and_schedule_options_leave_the_analysis_alone():
                 assert np.array_equal(sy[k], sy0[k]), k
             if opts.get("tail_sparse") == 0:
                 assert inf["flops_issued"] > issued
+
+
+def _geometric_nd(side):
+    """Nested dissection of a side^3 grid by planes (the reference the
+    ordering is measured against): split the box across its longest side at
+    the middle plane, order the two halves, then the plane; boxes of at most
+    64 nodes in natural order.  Returns perm (new -> old), node = (z*side+y)*side+x."""
+    out = []
+
+    def rec(lo, hi):
+        ext = [hi[d] - lo[d] for d in range(3)]
+        if ext[0] * ext[1] * ext[2] <= 64 or max(ext) < 3:
+            for z in range(lo[2], hi[2]):
+                for y in range(lo[1], hi[1]):
+                    for x in range(lo[0], hi[0]):
+                        out.append((z * side + y) * side + x)
+            return
+        d = int(np.argmax(ext))
+        mid = (lo[d] + hi[d]) // 2
+        a_hi = list(hi); a_hi[d] = mid
+        b_lo = list(lo); b_lo[d] = mid + 1
+        s_lo = list(lo); s_lo[d] = mid
+        s_hi = list(hi); s_hi[d] = mid + 1
+        rec(lo, a_hi)
+        rec(b_lo, hi)
+        for z in range(s_lo[2], s_hi[2]):
+            for y in range(s_lo[1], s_hi[1]):
+                for x in range(s_lo[0], s_hi[0]):
+                    out.append((z * side + y) * side + x)
+    rec([0, 0, 0], [side, side, side])
+    return np.array(out, dtype=np.int32)
+
+
+@pytest.mark.parametrize("points", [7, 27])
+def test_nested_dissection_within_twice_the_geometric_fill(points):
+    """Ordering quality (Sec. 2.1; the paper's own orderings are not
+    reproducible): the flop count F of the nested dissection with multilevel
+    separators on a 24^3 grid is at most twice that of the geometric
+    plane-separator dissection of the same grid."""
+    side = 24
+    w = synth.convdiff3d_27pt(side, nrhs=1) if points == 27 else synth.convdiff3d_7pt(side)
+    A = w.A
+    geo = _geometric_nd(side)
+    assert np.array_equal(np.sort(geo), np.arange(A.n))
+    f_geo = hylu.Handle(A.row_ptr, A.col, A.val, user_perm=geo, dense_tail=0).info()["flops"]
+    f_nd = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd_ml", dense_tail=0).info()["flops"]
+    print(f"{points}-point 24^3: F(nd) {f_nd:.3e}, F(geometric) {f_geo:.3e}, ratio {f_nd / f_geo:.2f}")
+    assert f_nd <= 2 * f_geo

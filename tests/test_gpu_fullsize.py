@@ -113,13 +113,14 @@ def test_grid7_full_solution_and_sampled_gradient(hylu):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_grid27_full_backward_error(hylu, precision):
-    """27-point grid 64^3 (n = 262144), 8 right-hand sides, ND: the normwise
+    """27-point grid 64^3 (n = 262144), 8 right-hand sides, nested dissection
+    with multilevel separators (as bench.py runs it): the normwise
     backward error of every right-hand side, at most 1e-12 for FP64 factors
     and for FP32 factors with FP64 refinement."""
     w = synth.convdiff3d_27pt(64)
     A = w.A
     print(f"[case] 27-point 64^3 full {precision}", flush=True)
-    h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd", precision=precision, dense_tail=0.5)
+    h = hylu.Handle(A.row_ptr, A.col, A.val, ordering="nd_ml", precision=precision, dense_tail=0.5)
     h.factorize(dev(A.val))
     X = h.solve_cols(dev(w.b.T.copy())).cpu().numpy().T
     for k in range(w.b.shape[1]):

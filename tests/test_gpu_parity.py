@@ -15,6 +15,13 @@ from parity import oracle_for, compare_factors, compare_backward_stability, rel_
 
 TAU64 = np.sqrt(np.finfo(np.float64).eps)
 
+# The pipelined launch (pipeline_rows > 0) did not finish on the device in two
+# runs (the second after bounded waits that also stop on the shared give-up
+# flag, per-batch waits and agent-scope fences); its schedule is checked on
+# the CPU at analysis (tests/test_abi_and_analysis.py), the factorisation
+# refuses it, and these cases stay skipped until a cause is shown.
+PIPE_OFF = pytest.mark.skip(reason="pipelined launch switched off: it did not finish on the device (twice)")
+
 
 @pytest.fixture(scope="module")
 def hylu():
@@ -45,9 +52,6 @@ def run_case(hylu, A, b, opts=None, sn=(2, 1 << 30), exact=False, tol=1e-11):
     return h, o, x, xo, eta
 
 
-PIPE_OFF = pytest.mark.skip(reason="pipelined mode is switched off: its launch did not finish on the device")
-
-
 @pytest.mark.parametrize("pipe", [0, pytest.param(1024, marks=PIPE_OFF)])
 @pytest.mark.parametrize("tail", [0.0, 0.5])
 def test_random_small(hylu, tail, pipe):
@@ -61,6 +65,7 @@ def test_random_small(hylu, tail, pipe):
         b = rng.standard_normal(n)
         h, o, x, xo, eta = run_case(hylu, A, b, opts=dict(dense_tail=tail, pipeline_rows=pipe))
         assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
+        assert (h.info()["pipe_tasks"] == n) == (pipe > 0)
         assert (h.info()["tail_rows"] > 0) == (tail > 0)
 
 
@@ -249,7 +254,7 @@ def test_grid27_grouped_panels(hylu, precision):
     refactorisation with new values through the graph."""
     w = synth.convdiff3d_27pt(24, nrhs=2)
     A = w.A
-    opts = dict(ordering="nd", dense_tail=0.5, group_min_rows=128, group_tail_rows=256, precision=precision)
+    opts = dict(ordering="nd_ml", dense_tail=0.5, group_min_rows=128, group_tail_rows=256, precision=precision)
     print(f"[case] 27-point 24^3 grouped {precision}", flush=True)
     h = hylu.Handle(A.row_ptr, A.col, A.val, **opts)
     inf = h.info()
@@ -364,3 +369,36 @@ def test_deferred_row_placement_bit_identical(hylu):
         assert np.array_equal(out[0][0][k], out[1][0][k]), k
         assert np.array_equal(out[0][1][k], out[1][1][k]), k
     assert np.array_equal(out[0][2], out[1][2])
+
+
+@pytest.mark.parametrize("case", ["circuit", "grid3d"])
+def test_solve_chains(hylu, case):
+    """Runs of narrow solve levels solved by one workgroup per run (Sec. 2.3):
+    in FP64 the solution agrees with the per-level launches' (the backward
+    solve sums each row in another order; the 7-point grid's condition number,
+    ~2e4 at 16^3, turns rounding-level differences into ~1e-13), and both
+    agree with the oracle's to 1e-10 with backward error at most 1e-12, in
+    FP64 and with FP32 factors and refinement."""
+    if case == "circuit":
+        w = synth.circuit_powerlaw(20000)
+        opts = dict(amd_dense=0.1, dense_tail=0.15)
+    else:
+        w = synth.convdiff3d_7pt(16)
+        opts = dict(ordering="nd", dense_tail=0.15, sn_dense=32)
+    A, b = w.A, w.b[:, 0]
+    print(f"[case] solve chains {case} n={A.n}", flush=True)
+    for precision in ("fp64", "fp32"):
+        h1 = hylu.Handle(A.row_ptr, A.col, A.val, precision=precision, **opts)
+        h0 = hylu.Handle(A.row_ptr, A.col, A.val, precision=precision, solve_chain=0, **opts)
+        assert h1.info()["chain_levels"] > 0 and h0.info()["chain_levels"] == 0
+        xs = []
+        for h in (h1, h0):
+            h.factorize(dev(A.val))
+            xs.append(h.solve(dev(b)).cpu().numpy())
+        if precision == "fp64":          # FP32 + refinement: two converged iterates, compared via the oracle
+            assert rel_diff(xs[0], xs[1]) <= 1e-11
+        o, _ = oracle_for(h1, A)
+        o.numeric(o.tau)
+        for x in xs:
+            assert rel_diff(x, o.solve(b)) <= 1e-10
+            assert o.backward_error(b, x)[0] <= 1e-12
