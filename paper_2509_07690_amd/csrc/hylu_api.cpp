@@ -715,10 +715,11 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
                 double m = h->lay.m[v], wc = h->lay.W[v] - h->lay.lw[v];
                 by += 2.0 * es * m * wc;
                 fl += 2.0 * m * m * m / 3.0 + m * m * (wc - m);
+                if (h->inv_off[v] >= 0) { by += 2.0 * es * m * m; fl += m * m * m / 3.0; }   // its block inverse
             }
             LAUNCH(C_SNLU, by, fl, launch_factor_snlu(h->fp32, h->D, h->vals, h->d_snodes + s0, (int32_t)(s1 - s0), T.maxm[l],
                                                       h->tau, h->d_pert, search ? 1 : 0,
-                                                      T.tune_sn ? T.tune_sn : T.sn_nt[l], st));
+                                                      T.tune_sn ? T.tune_sn : T.sn_nt[l], h->d_inv_off, st));
         }
         hylu_status sd = enqueue_level_dense(h, l, search, st);
         if (sd != HYLU_OK) return sd;
@@ -1483,6 +1484,9 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 if (!nd.is_sn[v] || v >= L.tail_node0 || L.m[v] < 2 || L.m[v] > kInvMax) continue;
                 h->inv_off[v] = h->inv_total;
                 h->inv_total += (int64_t)L.m[v] * L.m[v];
+                // the supernode-LU kernel inverts its own nodes; the large
+                // supernodes' dense views take a launch after the level
+                if (L.m[v] < big) continue;
                 h->inv_nodes.push_back(v);
                 mm = std::max(mm, L.m[v]);
             }

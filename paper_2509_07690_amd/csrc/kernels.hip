@@ -512,10 +512,33 @@ __device__ void snlu_node(const DevLayout& D, T* __restrict__ vals, int v, T tau
     }
 }
 
+// inverse of node v's block in pivot order after its LU (the rule of
+// k_sn_inverse, the block read from its panel): thread j solves U_pp x = e_j
+template <typename T, int NT>
+__device__ void sn_inverse_node(const DevLayout& D, const T* __restrict__ vals, int v, T* __restrict__ X)
+{
+    const int m = D.m[v], W = D.W[v], r0 = D.r0[v];
+    const T* P = vals + D.voff[v] + D.lw[v];
+    const int32_t* pl = D.pl + r0;
+    for (int j = threadIdx.x; j < m; j += NT) {
+        for (int i = j + 1; i < m; i++) X[(int64_t)i * m + j] = T(0);
+        X[(int64_t)j * m + j] = T(1) / P[(int64_t)j * W + pl[j]];
+        for (int i = j - 1; i >= 0; i--) {
+            const T* Pi = P + (int64_t)i * W;
+            T acc = T(0);
+            for (int k = i + 1; k <= j; k++) acc += Pi[pl[k]] * X[(int64_t)k * m + j];
+            X[(int64_t)i * m + j] = -acc / Pi[pl[i]];
+        }
+    }
+}
+
+// inv_off (optional): per node, the offset of its block inverse in D.uinv, or
+// -1; a node with one gets it right after its LU, in the same workgroup
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_factor_snlu(DevLayout D, T* __restrict__ vals,
                                                     const int32_t* __restrict__ nodes, int32_t count,
-                                                    T tau, int32_t* __restrict__ pert, int32_t search)
+                                                    T tau, int32_t* __restrict__ pert, int32_t search,
+                                                    const int64_t* __restrict__ inv_off)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ T red_v[NT];
@@ -526,6 +549,10 @@ __global__ __launch_bounds__(NT) void k_factor_snlu(DevLayout D, T* __restrict__
     T* lrow = reinterpret_cast<T*>(smem_raw);                       // m multipliers
     uint8_t* taken = smem_raw + sizeof(T) * (size_t)m;             // m flags
     snlu_node<T, NT>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p);
+    if (inv_off && inv_off[v] >= 0) {
+        __syncthreads();        // the block and its pivot order are complete
+        sn_inverse_node<T, NT>(D, vals, v, reinterpret_cast<T*>(const_cast<void*>(D.uinv)) + inv_off[v]);
+    }
 }
 
 // pipeline mode (Sec. 2.2.1): persistent workgroups take row tasks in a
@@ -2288,7 +2315,8 @@ hipError_t launch_sn_inverse(bool fp32, const DevLayout& D, const void* vals, co
 }
 
 hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const int32_t* nodes, int32_t count,
-                              int32_t maxm, double tau, int32_t* pert, int32_t search, int32_t nt, hipStream_t st)
+                              int32_t maxm, double tau, int32_t* pert, int32_t search, int32_t nt,
+                              const int64_t* inv_off, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
     size_t sh = (size_t)maxm * ((fp32 ? sizeof(float) : sizeof(double)) + 1) + 16;
@@ -2296,11 +2324,11 @@ hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const i
     if (nt == 0) nt = 256;
     if (nt != 64 && nt != 256) return hipErrorInvalidValue;
     if (fp32) {
-        if (nt == 64) hipLaunchKernelGGL((k_factor_snlu<float, 64>), dim3(count), dim3(64), sh, st, D, (float*)vals, nodes, count, (float)tau, pert, search);
-        else hipLaunchKernelGGL((k_factor_snlu<float, 256>), dim3(count), dim3(256), sh, st, D, (float*)vals, nodes, count, (float)tau, pert, search);
+        if (nt == 64) hipLaunchKernelGGL((k_factor_snlu<float, 64>), dim3(count), dim3(64), sh, st, D, (float*)vals, nodes, count, (float)tau, pert, search, inv_off);
+        else hipLaunchKernelGGL((k_factor_snlu<float, 256>), dim3(count), dim3(256), sh, st, D, (float*)vals, nodes, count, (float)tau, pert, search, inv_off);
     } else {
-        if (nt == 64) hipLaunchKernelGGL((k_factor_snlu<double, 64>), dim3(count), dim3(64), sh, st, D, (double*)vals, nodes, count, tau, pert, search);
-        else hipLaunchKernelGGL((k_factor_snlu<double, 256>), dim3(count), dim3(256), sh, st, D, (double*)vals, nodes, count, tau, pert, search);
+        if (nt == 64) hipLaunchKernelGGL((k_factor_snlu<double, 64>), dim3(count), dim3(64), sh, st, D, (double*)vals, nodes, count, tau, pert, search, inv_off);
+        else hipLaunchKernelGGL((k_factor_snlu<double, 256>), dim3(count), dim3(256), sh, st, D, (double*)vals, nodes, count, tau, pert, search, inv_off);
     }
     return hipGetLastError();
 }

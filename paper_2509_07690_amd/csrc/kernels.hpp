@@ -174,8 +174,11 @@ hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, v
 // inverses of the blocks of the listed supernodes (each 2 <= m <= kInvMax)
 hipError_t launch_sn_inverse(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
                              int32_t maxm, const int64_t* inv_off, void* uinv, hipStream_t st);
+// inv_off (optional, device): per node the offset of its block inverse in
+// D.uinv or -1; listed nodes with one compute it right after their LU
 hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const int32_t* nodes, int32_t count,
-                              int32_t maxm, double tau, int32_t* pert, int32_t search, int32_t nt, hipStream_t st);
+                              int32_t maxm, double tau, int32_t* pert, int32_t search, int32_t nt,
+                              const int64_t* inv_off, hipStream_t st);
 // forward L solve of a level's nodes; supernodes of sn_min..64 rows (sn_min > 0)
 // go to a four-wavefront kernel, launched when with_sn says the level has one
 hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
