@@ -42,7 +42,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=200000)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--amd-dense", type=float, default=0.1)
+    ap.add_argument("--amd-dense", type=float, default=0.0)
     ap.add_argument("--dense-tail", type=float, default=0.15)
     ap.add_argument("--pipeline-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -71,7 +71,8 @@ typedef struct {
     int32_t kernel_mode;   /* 0 automatic choice, 1 row-row only (no supernodes), 2 supernodal */
     int32_t repeated;      /* reserved: the relative-index maps are always precomputed */
     int32_t nd_leaf;       /* nested dissection: parts up to this size are ordered by AMD (default 256) */
-    double amd_dense;      /* AMD: rows with more than max(16, amd_dense*sqrt(n)) entries are ordered last */
+    double amd_dense;      /* AMD: rows with more than max(16, amd_dense*sqrt(n)) entries are ordered last;
+                              0 (default): more than max(16, min(10 sqrt(n), 6 x the mean degree)) */
     double dense_tail;     /* factor the trailing block of at least this density densely (0: never; default 0.5) */
     int32_t tail_min;      /* smallest dense tail in rows (default 64) */
     int32_t tail_max;      /* largest dense tail in rows (default 32768) */

@@ -26,13 +26,14 @@ bool mc64_match_scale(const Csr& a, std::vector<int32_t>& row_of_col,
                       std::vector<double>& dr, std::vector<double>& dc);
 
 // Symmetric fill-reducing orderings of an undirected graph given as CSR
-// adjacency without self loops.  Both return perm[new] = old.
+// adjacency without self loops.  Both return perm[new] = old.  dense_alpha
+// sets AMD's dense-row threshold (<= 0: relative to the mean degree).
 std::vector<int32_t> amd_order(int32_t n, const std::vector<int64_t>& xadj,
-                               const std::vector<int32_t>& adj, double dense_alpha = 10.0);
+                               const std::vector<int32_t>& adj, double dense_alpha = 0.0);
 // multilevel = false: separators from breadth-first level structures; true:
 // from multilevel edge bisections (smaller separators on meshes)
 std::vector<int32_t> nd_order(int32_t n, const std::vector<int64_t>& xadj,
-                              const std::vector<int32_t>& adj, int32_t leaf_size, double dense_alpha = 10.0,
+                              const std::vector<int32_t>& adj, int32_t leaf_size, double dense_alpha = 0.0,
                               bool multilevel = false);
 
 // ---------------------------------------------------------------- symbolic

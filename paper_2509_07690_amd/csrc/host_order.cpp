@@ -215,8 +215,16 @@ std::vector<int32_t> amd_order(int32_t n, const std::vector<int64_t>& xadj,
     A.kind.assign(n, VAR);
     A.head.assign(n + 1, -1); A.dnext.assign(n, -1); A.dprev.assign(n, -1);
     A.mfirst.assign(n, -1); A.mlast.assign(n, -1); A.mnext.assign(n, -1);
-    // dense rows are ordered last
-    const int64_t dense = std::max<int64_t>(16, (int64_t)(dense_alpha * std::sqrt((double)n)));
+    // dense rows are ordered last: more than max(16, alpha sqrt(n)) entries,
+    // or with alpha <= 0 more than max(16, min(10 sqrt(n), 6 x the mean
+    // degree)), which also catches the hub rows of power-law patterns
+    int64_t dense;
+    if (dense_alpha > 0) {
+        dense = std::max<int64_t>(16, (int64_t)(dense_alpha * std::sqrt((double)n)));
+    } else {
+        const double mean = (double)xadj[n] / n;
+        dense = std::max<int64_t>(16, (int64_t)std::min(10.0 * std::sqrt((double)n), 6.0 * mean));
+    }
     std::vector<int32_t> dense_nodes;
     for (int32_t i = 0; i < n; i++)
         if (xadj[i + 1] - xadj[i] > dense && n > 2 * dense) { A.kind[i] = DENSE; dense_nodes.push_back(i); }

@@ -1120,7 +1120,7 @@ hylu_status order_matrix(const Csr& A, const hylu_options& opt, std::vector<int3
         std::vector<int64_t> xadj;
         std::vector<int32_t> adj;
         symmetrize(n, b0p, b0c, xadj, adj);
-        double ad = opt.amd_dense > 0 ? opt.amd_dense : 10.0;
+        const double ad = opt.amd_dense > 0 ? opt.amd_dense : 0.0;
         q = opt.ordering == 0 ? amd_order(n, xadj, adj, ad)
                               : nd_order(n, xadj, adj, std::max(opt.nd_leaf, 8), ad, opt.ordering == 4);
         if ((int32_t)q.size() != n) return HYLU_ERR_INTERNAL;
@@ -1826,7 +1826,7 @@ hylu_status hylu_default_options(hylu_options* o)
     o->kernel_mode = 0;
     o->repeated = 1;
     o->nd_leaf = 256;
-    o->amd_dense = 10.0;
+    o->amd_dense = 0.0;
     o->dense_tail = 0.5;
     o->tail_min = 64;
     o->tail_max = 32768;

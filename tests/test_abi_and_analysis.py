@@ -85,6 +85,17 @@ def test_analysis_user_perm_and_kernel_modes():
     assert h.info()["n_supernodes"] == 0
 
 
+def test_default_amd_orders_hub_rows_last():
+    # the default dense-row rule (relative to the mean degree) takes the hub
+    # rows of a power-law circuit out of the minimum-degree elimination; a
+    # fixed sqrt(n) cutoff either misses them (alpha 10) or also takes
+    # ordinary rows (alpha 0.1 at this size)
+    A = synth.circuit_powerlaw(20000).A
+    f = {a: hylu.Handle(A.row_ptr, A.col, A.val, amd_dense=a).info()["flops"] for a in (0.0, 0.1, 10.0)}
+    assert f[0.0] < f[0.1] and f[0.0] < f[10.0]
+    _check_against_oracle(A)
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_matching_maximises_the_product(seed):
     rng = np.random.default_rng(40 + seed)
