@@ -106,6 +106,10 @@ typedef struct {
     int32_t solve_chain;     /* 1: runs of at least 3 consecutive narrow forward / backward solve levels (at most 64
                                 nodes of at most 64 rows each) are solved by one workgroup in one launch, a barrier
                                 between levels, instead of one launch per level (Sec. 2.3; default 1) */
+    int32_t gpu_symbolic;    /* 1: hylu_analyze computes the symbolic structure of the factors and the four level sets
+                                on the current GPU (Sec. 2.1, 2.2.1): the same structure, supernodes and levels as the
+                                host analysis, to the bit.  Independent blocks (a batch's members) of at most 1 << 20
+                                rows each; HYLU_ERR_ARG otherwise.  0: on the host (default) */
 } hylu_options;
 
 /* Optional device allocator (e.g. the PyTorch caching allocator).  alloc
@@ -140,6 +144,11 @@ typedef struct {
     int32_t sn_groups, tail_groups;   /* panel groups of more than one panel in their plans / in the tail's */
     int32_t pipe_tasks;               /* row tasks of the pipelined launch (0: bulk mode only) */
     int32_t chain_levels;             /* forward + backward solve levels solved inside chains (solve_chain) */
+    double sym_ms;                    /* wall time of the symbolic factorisation, supernodes and level sets in
+                                         hylu_analyze (host or GPU, transfers included) */
+    double sym_kernel_ms;             /* of which GPU kernel time (gpu_symbolic; else 0) */
+    uint64_t sym_hash;                /* hash of the compressed structure and the level sets (equal hashes: equal
+                                         analyses) */
 } hylu_info;
 
 /* Analysis export for checking: every array is host memory the caller

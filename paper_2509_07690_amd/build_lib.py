@@ -32,7 +32,7 @@ def build(force: bool = True, jobs: int = 4) -> str:
     objs = []
     procs = []
     for src, kind in (("host_order.cpp", "host"), ("host_symbolic.cpp", "host"),
-                      ("hylu_api.cpp", "hip"), ("kernels.hip", "hip")):
+                      ("hylu_api.cpp", "hip"), ("kernels.hip", "hip"), ("symbolic.hip", "hip")):
         obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
         path = os.path.join(CSRC, src)
         if kind == "host":

@@ -59,6 +59,8 @@ struct Symbolic {
 };
 
 bool symbolic_factor(const Csr& b, Symbolic& s);
+// lcount, nnz_l, nnz_u and flops from the intervals and ucount
+void symbolic_counts(Symbolic& s);
 
 // ---------------------------------------------------------------- nodes
 // Supernodes (Sec. 2.2: consecutive rows with identical U structure) and
@@ -77,6 +79,38 @@ struct Nodes {
 
 void make_nodes(const Symbolic& s, int32_t sn_min, int32_t sn_max, Nodes& nd);
 void make_levels(const Symbolic& s, Nodes& nd);
+
+// ---------------------------------------------------------------- on the GPU
+// Schedule of the GPU symbolic factorisation: the elimination tree of the
+// pattern of B + B^T cut into chains (a row with one child continues the
+// child's chain), chains levelled by height (a chain above all chains of its
+// children's subtrees), rows ascending inside a chain.
+struct EtreeChains {
+    std::vector<int32_t> parent;        // per row, -1 for a root
+    std::vector<int64_t> lev_ptr;       // chain levels -> chains
+    std::vector<int64_t> cptr;          // chains -> rows in crow
+    std::vector<int32_t> crow;
+    std::vector<int32_t> cbase;         // per chain: first row of its independent block
+    int64_t width = 0;                  // widest block
+};
+// blocks: row offsets of independent diagonal blocks (0, ..., n)
+void elimination_chains(const Csr& b, const std::vector<int64_t>& blocks, EtreeChains& ec);
+
+struct DeviceAlloc {
+    void* ctx;
+    void* (*alloc)(void* ctx, size_t bytes);
+    void (*free)(void* ctx, void* p);
+};
+struct GpuSymStats {
+    double ms_structure = 0, ms_levels = 0;   // kernel time (event pairs)
+    int32_t chain_levels = 0, retries = 0;
+    int64_t chains = 0;
+};
+// symbolic_factor + make_nodes + make_levels with the structure and the level
+// sets computed by kernels: the same Symbolic and Nodes to the bit.  Blocks
+// of at most 1 << 20 rows; false with err set otherwise or on a device error.
+bool gpu_symbolic_levels(const Csr& b, const std::vector<int64_t>& blocks, int32_t sn_min, int32_t sn_max,
+                         const DeviceAlloc& da, Symbolic& s, Nodes& nd, GpuSymStats& stats, std::string& err);
 
 // ---------------------------------------------------------------- layout
 // Every node v (a supernode of m rows, or a standalone row with m = 1) owns a

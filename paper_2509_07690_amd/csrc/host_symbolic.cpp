@@ -141,6 +141,14 @@ bool symbolic_factor(const Csr& b, Symbolic& s)
         s.run_up.push_back((int64_t)s.run_u.size());
     }
     s.run_start.push_back(n);
+    symbolic_counts(s);
+    return true;
+}
+
+void symbolic_counts(Symbolic& s)
+{
+    const int32_t n = s.n;
+    s.nnz_l = s.nnz_u = 0;
     // l_k from the intervals, F = sum_k l_k (1 + 2 u_k)
     std::vector<int64_t> diff(n + 1, 0);
     for (int64_t t = 0; t < s.lp[n]; t++) {
@@ -158,7 +166,6 @@ bool symbolic_factor(const Csr& b, Symbolic& s)
         s.nnz_u += 1 + s.ucount[k];
     }
     s.flops = F;
-    return true;
 }
 
 // strict upper structure of row k: a suffix of its run's stored list

@@ -222,6 +222,9 @@ struct hylu_handle_s {
     // last solve (or hylu_residual)
     int32_t ir_iters = 0;
     double berr = 0.0, resid1 = 0.0;
+    // analysis: time of the symbolic step (host or GPU) and a hash of its result
+    double sym_ms = 0.0, sym_kernel_ms = 0.0;
+    uint64_t sym_hash = 0;
     bool berr_known = false;
     // measurement
     Profiler prof;
@@ -1171,6 +1174,40 @@ hylu_status check_pipeline(hylu_handle h)
     return HYLU_OK;
 }
 
+// device memory of the analysis (GPU symbolic factorisation), freed before it returns
+void* analysis_alloc(void* ctx, size_t bytes)
+{
+    hylu_handle h = static_cast<hylu_handle>(ctx);
+    void* p = nullptr;
+    if (h->has_alloc) p = h->alloc.alloc(h->alloc.ctx, bytes, nullptr);
+    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    return p;
+}
+
+void analysis_free(void* ctx, void* p)
+{
+    hylu_handle h = static_cast<hylu_handle>(ctx);
+    if (h->has_alloc) h->alloc.free(h->alloc.ctx, p, nullptr);
+    else (void)hipFree(p);
+}
+
+// FNV-1a over the compressed structure and the level sets
+uint64_t structure_hash(const Symbolic& s, const Nodes& nd)
+{
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t bytes) {
+        const unsigned char* c = static_cast<const unsigned char*>(p);
+        for (size_t k = 0; k < bytes; k++) { x ^= c[k]; x *= 1099511628211ull; }
+    };
+    auto vec = [&](const auto& v) { mix(v.data(), v.size() * sizeof(v[0])); };
+    vec(s.lp); vec(s.lint); vec(s.run_of); vec(s.run_start); vec(s.run_up); vec(s.run_u);
+    vec(s.lcount); vec(s.ucount);
+    mix(&s.flops, sizeof(s.flops));
+    vec(nd.ptr); vec(nd.is_sn);
+    for (int t = 0; t < 4; t++) vec(nd.level[t]);
+    return x;
+}
+
 hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
 {
     const int32_t n = h->n;
@@ -1198,13 +1235,29 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     }
     // ---- symbolic factorisation, flops, supernodes, levels (Sec. 2.1, 2.2, 2.2.1)
     plog("permute");
-    if (!symbolic_factor(B, h->sym)) return HYLU_ERR_INTERNAL;
-    plog("symbolic");
     int32_t sn_min = opt.sn_min, sn_max = opt.sn_max;
     if (opt.kernel_mode == 1) sn_min = std::numeric_limits<int32_t>::max();
-    make_nodes(h->sym, sn_min, sn_max, h->nodes);
-    make_levels(h->sym, h->nodes);
-    plog("nodes");
+    const auto ts = std::chrono::steady_clock::now();
+    h->sym_kernel_ms = 0.0;
+    if (opt.gpu_symbolic) {
+        DeviceAlloc da{h, analysis_alloc, analysis_free};
+        GpuSymStats gs;
+        std::string e;
+        if (!gpu_symbolic_levels(B, h->member_row_off, sn_min, sn_max, da, h->sym, h->nodes, gs, e)) {
+            std::fprintf(stderr, "hylu: %s\n", e.c_str());
+            return e.find("1 << 20") != std::string::npos ? HYLU_ERR_ARG : HYLU_ERR_DEVICE;
+        }
+        h->sym_kernel_ms = gs.ms_structure + gs.ms_levels;
+        plog("symbolic, nodes and levels on the GPU");
+    } else {
+        if (!symbolic_factor(B, h->sym)) return HYLU_ERR_INTERNAL;
+        plog("symbolic");
+        make_nodes(h->sym, sn_min, sn_max, h->nodes);
+        make_levels(h->sym, h->nodes);
+        plog("nodes");
+    }
+    h->sym_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ts).count();
+    h->sym_hash = structure_hash(h->sym, h->nodes);
     std::string err;
     int32_t tail_node0 = choose_tail(h->sym, h->nodes, opt.dense_tail, std::max(opt.tail_min, 1),
                                      opt.tail_max > 0 ? opt.tail_max : 32768);
@@ -1837,6 +1890,7 @@ hylu_status hylu_default_options(hylu_options* o)
     o->side_rows = 1;
     o->pipeline_rows = 0;
     o->solve_chain = 1;
+    o->gpu_symbolic = 0;
     o->group_min_rows = kGroupMinRows;
     o->group_tail_rows = kGroupTailRows;
     return HYLU_OK;
@@ -1904,7 +1958,7 @@ hylu_status hylu_analyze(hylu_handle h, int32_t n, const int64_t* row_ptr, const
     if (opt_in) opt = *opt_in; else hylu_default_options(&opt);
     if (opt.ordering < 0 || opt.ordering > 4 || (opt.ordering == 3 && !opt.user_perm)) return HYLU_ERR_ARG;
     if (opt.precision < 0 || opt.precision > 1 || opt.kernel_mode < 0 || opt.kernel_mode > 2) return HYLU_ERR_ARG;
-    if (opt.pipeline_rows < 0) return HYLU_ERR_ARG;
+    if (opt.pipeline_rows < 0 || opt.gpu_symbolic < 0 || opt.gpu_symbolic > 1) return HYLU_ERR_ARG;
     hylu_status st = validate_csr(n, row_ptr, col, val);
     if (st != HYLU_OK) return st;
     try {
@@ -1947,7 +2001,7 @@ hylu_status hylu_analyze_batch(hylu_handle h, int32_t count, const int32_t* n_k,
     if (opt_in) opt = *opt_in; else hylu_default_options(&opt);
     if (opt.ordering < 0 || opt.ordering > 4 || opt.ordering == 3) return HYLU_ERR_ARG;   // no user permutation for a batch
     if (opt.precision < 0 || opt.precision > 1 || opt.kernel_mode < 0 || opt.kernel_mode > 2) return HYLU_ERR_ARG;
-    if (opt.pipeline_rows < 0) return HYLU_ERR_ARG;
+    if (opt.pipeline_rows < 0 || opt.gpu_symbolic < 0 || opt.gpu_symbolic > 1) return HYLU_ERR_ARG;
     opt.dense_tail = 0.0;   // members are independent: the levels of all of them share the launches instead
     int64_t ntot = 0, nnztot = 0;
     for (int32_t k = 0; k < count; k++) {
@@ -2227,6 +2281,9 @@ hylu_status hylu_get_info(hylu_handle h, hylu_info* o)
                         ? (int32_t)(h->ft.row_ptr.back() - h->ft.row_ptr[h->ft.pipe_level]) : 0;
     o->sn_groups = h->sn_groups;
     o->tail_groups = h->tail_groups;
+    o->sym_ms = h->sym_ms;
+    o->sym_kernel_ms = h->sym_kernel_ms;
+    o->sym_hash = h->sym_hash;
     o->pivot_tau = h->tau;
     o->tail_rows = h->lay.mT;
     o->tail_panels = (int32_t)h->lay.panels.size();
