@@ -172,6 +172,10 @@ def main():
     if args.precision == "fp64" and not args.no_fp32:
         fp32 = fp32_ir_leg(args, A0, opts, vals, bs, xs, xts, v0, run, x64, timed)
 
+    symb = None
+    if not args.headline_only:
+        symb = symbolic_compare(info, lambda: hylu.Handle(A0.row_ptr, A0.col, A0.val, precision=args.precision,
+                                                          gpu_symbolic=1, **opts))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(A0, base, h, args.cpu_sample_refactors, args.warmup)
@@ -211,6 +215,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "fp32_ir": fp32,
+        "symbolic": symb,
         "cpu_baseline": cpu,
         "other_configs": others,
     }
@@ -220,6 +225,17 @@ def main():
 # kernel classes whose byte figures follow the per-update and per-entry unit
 # costs on the exact structure (the others count the blocks they issue)
 ALGORITHMIC_CLASSES = ("rows", "lsolve", "usolve", "tail_solve", "snlu", "sn_inverse", "scatter")
+
+
+def symbolic_compare(info_host, make_gpu_handle):
+    """The same analysis with the symbolic factorisation, supernodes and
+    level sets computed on the GPU (untimed in the step): its time against the
+    host's, and whether the result is the same (structure and level hash)."""
+    hg = make_gpu_handle()
+    ig = hg.info()
+    hg.close()
+    return {"host_ms": round(info_host["sym_ms"], 2), "gpu_ms": round(ig["sym_ms"], 2),
+            "gpu_kernel_ms": round(ig["sym_kernel_ms"], 2), "identical": ig["sym_hash"] == info_host["sym_hash"]}
 
 
 def fp32_ir_leg(args, A0, opts, vals, bs, xs, xts, v0, run, x64, timed):
@@ -368,6 +384,9 @@ def batch_leg(members, precision, steps, warmup, sn_dense=64, sn_inverse=1, sn_t
            "backward_error": eta, "resid_1": res1, "max_abs_err_vs_x_true": err, "ir_iters": info["ir_iters"],
            "analyze_s": round(t_an, 2), "kernels": kernels}
     hb.close()
+    res["symbolic"] = symbolic_compare(info, lambda: hylu.Handle.batch(
+        [(a.row_ptr, a.col, a.val) for a in a0], precision=precision, sn_dense=sn_dense, sn_inverse=sn_inverse,
+        sn_tile=sn_tile, gpu_symbolic=1))
     return res
 
 
