@@ -1541,13 +1541,15 @@ __global__ __launch_bounds__(64) void k_tail_panel_reg(DevLayout D, TailView TV,
             T d = rlane(x[a], a);
             if (tabs(d) < tau) d = d < T(0) ? -tau : tau;
             if (lane == a && x[a] != d) { x[a] = d; npert++; }
+            // rows above a (and lanes past the panel) take l = 0: their values
+            // stay as they are (up to the sign of a zero), with no select per
+            // update
             const bool act = mine && lane > a;
-            T l = T(0);
-            if (act) l = x[a] / d;
+            const T l = act ? x[a] / d : T(0);
 #pragma unroll
             for (int j = a + 1; j < kNB; j++) {
                 const T u = rlane(x[j], a);
-                if (act) x[j] -= l * u;
+                x[j] -= l * u;
             }
             if (act) x[a] = l;
         }
@@ -1603,11 +1605,15 @@ __global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ v
     if (blk < nA) {
         const int c = c1 + blk * 64 + tid;
         if (c >= TV.nc) return;
+        // the column's values first (independent loads), then the forward
+        // substitution in place
         T colv[kNB];
+#pragma unroll
+        for (int a = 0; a < kNB; a++) colv[a] = a < np ? vals[rowoff[a] + c] : T(0);
 #pragma unroll
         for (int a = 0; a < kNB; a++) {
             if (a < np) {
-                T acc = vals[rowoff[a] + c];
+                T acc = colv[a];
 #pragma unroll
                 for (int b = 0; b < a; b++) acc -= M[a][b] * colv[b];
                 colv[a] = acc;
