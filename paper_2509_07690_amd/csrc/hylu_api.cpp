@@ -1474,6 +1474,25 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         h->max_sn = std::max(h->max_sn, mm);
         if (l >= pipe_level) T.pipe_maxW = std::max(T.pipe_maxW, mw);
     }
+    // HYLU_LOG=2: the row tasks of every factor level (3: and each row of the last one)
+    if (const char* lg = std::getenv("HYLU_LOG"); lg && std::atoi(lg) >= 2) {
+        for (int32_t l = 0; l < nl; l++) {
+            int64_t maxsrc = 0, sumsrc = 0, tailr = 0;
+            for (int64_t t = T.row_ptr[l]; t < T.row_ptr[l + 1]; t++) {
+                const int64_t ns = T.rrange[2 * t + 1] - T.rrange[2 * t];
+                maxsrc = std::max(maxsrc, ns);
+                sumsrc += ns;
+                if (nd.of_row[T.rows[t]] >= L.tail_node0) tailr++;
+            }
+            std::fprintf(stderr, "hylu: level %d row tasks %lld (tail %lld) sources max %lld sum %lld maxW %d\n", l,
+                         (long long)(T.row_ptr[l + 1] - T.row_ptr[l]), (long long)tailr, (long long)maxsrc,
+                         (long long)sumsrc, T.maxW[l]);
+            if (std::atoi(lg) >= 3 && l == nl - 1)
+                for (int64_t t = T.row_ptr[l]; t < T.row_ptr[l + 1]; t++)
+                    std::fprintf(stderr, "hylu:   row %d sources %lld W %d\n", T.rows[t],
+                                 (long long)(T.rrange[2 * t + 1] - T.rrange[2 * t]), L.W[nd.of_row[T.rows[t]]]);
+        }
+    }
     // the dense tail's launches, block-sparse by its structural masks
     h->tail_ops.clear();
     h->tail_list.clear();
