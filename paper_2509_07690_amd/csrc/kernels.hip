@@ -1863,11 +1863,19 @@ __global__ __launch_bounds__(256) void k_factor_tile(DevLayout D, T* __restrict_
                 if (jb < nblk) {
                     const int c = jb * 16 + li;
                     const int kend = min(ms, jb * 16 + 16);      // Ui[k][c] = 0 for k > c
-                    for (int k0 = 0; k0 < kend; k0 += 4) {
-                        const int k = k0 + lk;
-                        const T av = k < ms ? Xs[li][k] : T(0);
-                        const T bv = (k < ms && c < ms) ? Ui[(int64_t)k * ms + c] : T(0);
-                        acc[t] = Mfma<T>::mma(av, bv, acc[t]);
+                    // eight K steps per round, their loads before the MFMAs
+                    for (int k0 = 0; k0 < kend; k0 += 32) {
+                        T av[8], bv[8];
+#pragma unroll
+                        for (int u = 0; u < 8; u++) {
+                            const int k = k0 + 4 * u + lk;
+                            const bool ok = k0 + 4 * u < kend && k < ms;
+                            av[u] = ok ? Xs[li][k] : T(0);
+                            bv[u] = (ok && c < ms) ? Ui[(int64_t)k * ms + c] : T(0);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; u++)
+                            if (k0 + 4 * u < kend) acc[t] = Mfma<T>::mma(av[u], bv[u], acc[t]);
                     }
                 }
             }
@@ -1930,11 +1938,18 @@ __global__ __launch_bounds__(256) void k_factor_tile(DevLayout D, T* __restrict_
         for (int j0 = wv * 16; j0 < ws; j0 += 64) {
             v4 acc = v4{T(0), T(0), T(0), T(0)};
             const int jc = j0 + li;
-            for (int k0 = 0; k0 < ms; k0 += 4) {
-                const int k = k0 + lk;
-                const T a = (k < ms && li < R) ? XP(li, k) : T(0);
-                const T bv = (k < ms && jc < ws) ? Ut[(int64_t)k * Ws + jc] : T(0);
-                acc = Mfma<T>::mma(a, bv, acc);
+            // eight K steps per round, their loads before the MFMAs
+            for (int k0 = 0; k0 < ms; k0 += 32) {
+                T a[8], bv[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int k = k0 + 4 * u + lk;
+                    a[u] = (k < ms && li < R) ? XP(li, k) : T(0);
+                    bv[u] = (k < ms && jc < ws) ? Ut[(int64_t)k * Ws + jc] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    if (k0 + 4 * u < ms) acc = Mfma<T>::mma(a[u], bv[u], acc);
             }
             if (jc < ws) {
                 const int c = rl[jc];
