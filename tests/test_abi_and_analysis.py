@@ -127,6 +127,10 @@ def test_error_paths():
     assert _code(lambda: hylu.Handle(rp, np.array([0, 1, 1], np.int32), np.array([1, np.nan, 1]))) == -8
     # structurally singular: column 1 empty
     assert _code(lambda: hylu.Handle(np.array([0, 1, 2], np.int64), np.array([0, 0], np.int32), np.ones(2))) == -3
+    # an option out of range is refused before any work (gpu_symbolic is 0 or 1)
+    eye = (np.array([0, 1, 2], np.int64), np.array([0, 1], np.int32), np.ones(2))
+    assert _code(lambda: hylu.Handle(*eye, gpu_symbolic=2)) == -1
+    assert _code(lambda: hylu.Handle.batch([eye, eye], gpu_symbolic=-1)) == -1
     h = hylu.Handle(np.array([0, 1, 2], np.int64), np.array([0, 1], np.int32), np.ones(2))
     lib = hylu._lib
     # a solve before any factorisation fails without touching the device
