@@ -1298,6 +1298,7 @@ __global__ __launch_bounds__(NT) void k_tail_panel_wide(DevLayout D, TailView TV
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int64_t rowoff[kNB];
+    __shared__ int rlo[kNB], rhi[kNB], rpiv[kNB];      // per panel row: block range, known pivot
     __shared__ T lrow[kNB];
     __shared__ T red_v[NT / 64];
     __shared__ int red_i[NT / 64];
@@ -1306,12 +1307,29 @@ __global__ __launch_bounds__(NT) void k_tail_panel_wide(DevLayout D, TailView TV
     const int wc = c1 - c0, np = p1 - p0;
     int* tsw = reinterpret_cast<int*>(smem_raw);                              // wc: step pivoting the column
     T* Xs = reinterpret_cast<T*>(smem_raw + (((size_t)wc * 4 + 15) & ~(size_t)15));   // STAGE: np x wc
-    for (int r = tid; r < np; r += NT) rowoff[r] = TV.trow[p0 + r];
+    for (int r = tid; r < np; r += NT) {
+        rowoff[r] = TV.trow[p0 + r];
+        rlo[r] = TV.tlo[p0 + r];
+        rhi[r] = TV.thi[p0 + r];
+        rpiv[r] = search ? 0 : TV.tpiv[p0 + r];
+    }
     for (int c = tid; c < wc; c += NT) tsw[c] = TV.tstep[c0 + c];
     __syncthreads();
     if (STAGE) {
-        for (int r = 0; r < np; r++)
-            for (int c = tid; c < wc; c += NT) Xs[r * wc + c] = vals[rowoff[r] + c0 + c];
+        // eight loads per thread in flight before their LDS stores
+        for (int i0 = tid; i0 < np * wc; i0 += 8 * NT) {
+            T t[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int i = i0 + u * NT;
+                t[u] = i < np * wc ? vals[rowoff[i / wc] + c0 + i % wc] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int i = i0 + u * NT;
+                if (i < np * wc) Xs[i] = t[u];
+            }
+        }
         __syncthreads();
     }
     auto X = [&](int r, int c) -> T& {   // panel-local row r, window-local column c
@@ -1321,7 +1339,7 @@ __global__ __launch_bounds__(NT) void k_tail_panel_wide(DevLayout D, TailView TV
     T cv = T(-1);
     int ci = wc;
     if (search) {
-        const int lo0 = TV.tlo[p0] - c0, hi0 = TV.thi[p0] - c0;
+        const int lo0 = rlo[0] - c0, hi0 = rhi[0] - c0;
         for (int c = tid; c < wc; c += NT) {
             if (tsw[c] <= p0 || c < lo0 || c >= hi0) continue;
             const T x = pmag(X(0, c));
@@ -1330,10 +1348,10 @@ __global__ __launch_bounds__(NT) void k_tail_panel_wide(DevLayout D, TailView TV
     }
     for (int a = 0; a < np; a++) {
         const int ga = p0 + a;
-        const int lo = TV.tlo[ga], hi = TV.thi[ga];
+        const int lo = rlo[a], hi = rhi[a];
         int p;
         if (!search) {
-            p = TV.tpiv[ga] - c0;
+            p = rpiv[a] - c0;
         } else if (hi - lo == 1) {
             p = lo - c0;
         } else {
@@ -1377,7 +1395,7 @@ __global__ __launch_bounds__(NT) void k_tail_panel_wide(DevLayout D, TailView TV
         __syncthreads();
         cv = T(-1);
         ci = wc;
-        const int nlo = a + 1 < np ? TV.tlo[ga + 1] - c0 : 0, nhi = a + 1 < np ? TV.thi[ga + 1] - c0 : 0;
+        const int nlo = a + 1 < np ? rlo[a + 1] - c0 : 0, nhi = a + 1 < np ? rhi[a + 1] - c0 : 0;
         for (int c = tid; c < wc; c += NT) {
             if (tsw[c] <= ga) continue;             // pivoted (this step's pivot included)
             const T u = X(a, c);
