@@ -176,6 +176,15 @@ struct hylu_handle_s {
     int32_t tail_groups = 0, sn_groups = 0;  // panel groups (of more than one panel) of the tail / the large supernodes
     int32_t pipe_grid = 0;                  // persistent workgroups of the pipelined launch (resident at once)
     std::vector<DenseSn> dsn;
+    // the large supernodes of a level whose launches are shared: per level the
+    // steps (panels of all of them, then their TRSMs, then their GEMMs, panel by
+    // panel; then all their inverses), each one launch over a range of jobs
+    struct ViewStep { int32_t kind; int64_t j0; int32_t nj; size_t lds; double elems, flops; };
+    std::vector<std::vector<ViewStep>> vsteps;
+    std::vector<std::vector<int32_t>> vshared;   // per level: the dense views in its shared steps
+    std::vector<ViewJob> vjobs;
+    ViewJob* d_vjobs = nullptr;
+    ViewDesc* d_vdesc = nullptr;
     std::vector<int32_t> dsn_ptr;           // per factor level into dsn
     std::vector<std::vector<int32_t>> dsn_l, dsn_u;   // per L-solve / U-solve level: dsn indices
     std::vector<int32_t> lsolve_sn;         // per L-solve level: 1 if it has a supernode for k_lsolve_sn
@@ -644,6 +653,126 @@ hylu_status enqueue_dense(hylu_handle h, const TailView& TV, const std::vector<D
 // and joined back into st; under capture they become parallel graph branches)
 // a large supernode's blocked LU, then the inverses of its solve panels'
 // diagonal blocks (used by its forward and backward solve steps)
+// Shared launches for the large supernodes of a level (Sec. 2.2: their internal
+// factorisations are independent): views whose plan is the plain one-panel
+// sequence (panel, TRSM, every-tile GEMM per 16-row panel) and whose panels
+// fit the wide-window kernel with the window in LDS take step k of all of
+// them in three launches; the same kernels on the same arguments, so the
+// factors are those of the per-view launches.
+void plan_shared_views(hylu_handle h)
+{
+    h->vsteps.assign(h->dsn_ptr.size() > 0 ? h->dsn_ptr.size() - 1 : 0, {});
+    h->vshared.assign(h->vsteps.size(), {});
+    h->vjobs.clear();
+    const double es = h->fp32 ? 4.0 : 8.0;
+    for (size_t l = 0; l < h->vsteps.size(); l++) {
+        struct Step { const DenseOp* op[3]; };
+        std::vector<int32_t> qs;
+        std::vector<std::vector<Step>> steps;
+        for (int32_t q = h->dsn_ptr[l]; q < h->dsn_ptr[l + 1]; q++) {
+            const hylu_handle_s::DenseSn& d = h->dsn[q];
+            const int32_t m = h->lay.m[d.v];
+            std::vector<Step> st;
+            bool ok = !d.ops.empty();
+            for (size_t i = 0; ok && i < d.ops.size();) {
+                const DenseOp& p = d.ops[i];
+                if (p.kind != 0 || p.a[2] != 0 || p.a[3] != m || tail_panel_wide_lds(h->fp32, p.a[1] - p.a[0], m) == 0) {
+                    ok = false;
+                    break;
+                }
+                Step x{{&p, nullptr, nullptr}};
+                i++;
+                if (i < d.ops.size() && d.ops[i].kind == 1) {
+                    const DenseOp& t = d.ops[i];
+                    if (t.a[0] != p.a[0] || t.a[1] != p.a[1] || t.list >= 0) { ok = false; break; }
+                    x.op[1] = &t;
+                    i++;
+                }
+                if (i < d.ops.size() && d.ops[i].kind == 2) {
+                    const DenseOp& g = d.ops[i];
+                    if (g.a[0] != p.a[0] || g.a[1] != p.a[1] - p.a[0] || g.a[2] != p.a[1] || g.a[7] != 0 ||
+                        g.list >= 0 || g.kb[1] != g.a[1]) { ok = false; break; }
+                    x.op[2] = &g;
+                    i++;
+                }
+                st.push_back(x);
+            }
+            if (!ok) continue;
+            qs.push_back(q);
+            steps.push_back(std::move(st));
+        }
+        if (qs.size() < 2) continue;
+        h->vshared[l] = qs;
+        size_t nk = 0;
+        for (const auto& st : steps) nk = std::max(nk, st.size());
+        auto begin = [&](int32_t kind) {
+            hylu_handle_s::ViewStep vs{kind, (int64_t)h->vjobs.size(), 0, 0, 0.0, 0.0};
+            return vs;
+        };
+        auto finish = [&](hylu_handle_s::ViewStep& vs) {
+            vs.nj = (int32_t)((int64_t)h->vjobs.size() - vs.j0);
+            if (vs.nj > 0) h->vsteps[l].push_back(vs);
+        };
+        for (size_t k = 0; k < nk; k++) {
+            for (int kind = 0; kind < 3; kind++) {
+                hylu_handle_s::ViewStep vs = begin(kind);
+                for (size_t w = 0; w < qs.size(); w++) {
+                    if (k >= steps[w].size() || !steps[w][k].op[kind]) continue;
+                    const DenseOp& o = *steps[w][k].op[kind];
+                    const hylu_handle_s::DenseSn& d = h->dsn[qs[w]];
+                    const int32_t m = h->lay.m[d.v], nc = h->lay.W[d.v] - h->lay.lw[d.v];
+                    vs.elems += es * o.elems;
+                    vs.flops += o.flops;
+                    ViewJob j{};
+                    j.v = qs[w];
+                    if (kind == 0) {
+                        const int32_t a[6] = {o.a[0], o.a[1], o.a[2], o.a[3], 0, 0};
+                        std::copy(a, a + 6, j.a);
+                        vs.lds = std::max(vs.lds, tail_panel_wide_lds(h->fp32, o.a[1] - o.a[0], m));
+                        h->vjobs.push_back(j);
+                    } else if (kind == 1) {
+                        const int32_t nA = (std::max(nc - o.a[2], 0) + 63) / 64, nB = (std::max(m - o.a[1], 0) + 63) / 64;
+                        const int32_t a[6] = {o.a[0], o.a[1], o.a[2], nA, o.a[3], o.a[4]};
+                        std::copy(a, a + 6, j.a);
+                        for (int32_t b = 0; b < nA + nB; b++) { j.blk = b; h->vjobs.push_back(j); }
+                    } else {
+                        const int32_t rb = o.a[2], re = o.a[3], cg0 = o.a[4];
+                        const int32_t gy = (re - rb + 63) / 64, gx = (nc - cg0 + 63) / 64;
+                        const int32_t a[6] = {o.a[0], o.a[1], rb, re, cg0, o.a[5]};
+                        std::copy(a, a + 6, j.a);
+                        for (int32_t ty = 0; ty < gy; ty++)
+                            for (int32_t tx = 0; tx < gx; tx++) { j.blk = (ty << 16) | tx; h->vjobs.push_back(j); }
+                    }
+                }
+                finish(vs);
+            }
+        }
+        hylu_handle_s::ViewStep vs = begin(3);
+        for (int32_t q : qs) {
+            const int32_t ns = (int32_t)h->dsn[q].spanels.size();
+            vs.elems += es * ns * 3.0 * kNB * kNB;
+            vs.flops += ns * 2.0 * kNB * kNB * kNB / 3.0;
+            for (int32_t b = 0; b < 2 * ns; b++) {
+                ViewJob j{};
+                j.v = q;
+                j.blk = b;
+                h->vjobs.push_back(j);
+            }
+        }
+        finish(vs);
+    }
+    if (const char* lg = std::getenv("HYLU_LOG"); lg && std::atoi(lg) >= 2) {
+        size_t nv = 0, ns = 0, nops = 0;
+        for (size_t l = 0; l < h->vsteps.size(); l++) {
+            nv += h->vshared[l].size();
+            ns += h->vsteps[l].size();
+            for (int32_t q : h->vshared[l]) nops += h->dsn[q].ops.size() + 1;
+        }
+        std::fprintf(stderr, "hylu: shared dense-view steps: %zu views, %zu launches for their %zu, %zu jobs\n", nv, ns,
+                     nops, h->vjobs.size());
+    }
+}
+
 hylu_status enqueue_dsn(hylu_handle h, const hylu_handle_s::DenseSn& q, bool search, hipStream_t st)
 {
     if (search) HIPCHK(launch_tail_init(q.TV, st));
@@ -659,19 +788,45 @@ hylu_status enqueue_level_dense(hylu_handle h, int32_t l, bool search, hipStream
 {
     const int32_t d0 = h->dsn_ptr[l], d1 = h->dsn_ptr[l + 1];
     if (d1 == d0) return HYLU_OK;
-    if (h->prof.on || d1 - d0 == 1) {          // one supernode, or measuring: stay on st
+    // the views of the level's shared steps first, on st
+    std::vector<char> shared(d1 - d0, 0);
+    if ((size_t)l < h->vshared.size() && !h->vshared[l].empty()) {
+        for (int32_t q : h->vshared[l]) {
+            shared[q - d0] = 1;
+            if (search) HIPCHK(launch_tail_init(h->dsn[q].TV, st));
+        }
+        for (const hylu_handle_s::ViewStep& vs : h->vsteps[l]) {
+            const ViewJob* jb = h->d_vjobs + vs.j0;
+            if (vs.kind == 0)
+                LAUNCH(C_PANEL, vs.elems, vs.flops,
+                       launch_tail_panel_views(h->fp32, h->D, h->d_vdesc, h->vals, jb, vs.nj, vs.lds, h->tau, h->d_pert,
+                                               search ? 1 : 0, st));
+            else if (vs.kind == 1)
+                LAUNCH(C_TRSM, vs.elems, vs.flops, launch_tail_trsm_views(h->fp32, h->d_vdesc, h->vals, jb, vs.nj, st));
+            else if (vs.kind == 2)
+                LAUNCH(C_GEMM, vs.elems, vs.flops, launch_tail_gemm_views(h->fp32, h->d_vdesc, h->vals, jb, vs.nj, st));
+            else
+                LAUNCH(C_DINV, vs.elems, vs.flops, launch_tail_dinv_views(h->fp32, h->d_vdesc, h->vals, jb, vs.nj, st));
+        }
+    }
+    int32_t rest = 0;
+    for (int32_t q = d0; q < d1; q++) rest += !shared[q - d0];
+    if (rest == 0) return HYLU_OK;
+    if (h->prof.on || rest == 1) {             // one supernode, or measuring: stay on st
         for (int32_t q = d0; q < d1; q++) {
+            if (shared[q - d0]) continue;
             hylu_status s = enqueue_dsn(h, h->dsn[q], search, st);
             if (s != HYLU_OK) return s;
         }
         return HYLU_OK;
     }
-    const int k = std::min<int>(hylu_handle_s::kSide, d1 - d0);
+    const int k = std::min<int>(hylu_handle_s::kSide, rest);
     HIPCHK(hipEventRecord(h->ev_fork, st));
     for (int j = 0; j < k; j++) HIPCHK(hipStreamWaitEvent(h->side[j], h->ev_fork, 0));
     // largest first, each to the least loaded stream
     std::vector<double> load(k, 0.0);
     for (int32_t q = d0; q < d1; q++) {
+        if (shared[q - d0]) continue;
         int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         const TailView& TV = h->dsn[q].TV;
         load[j] += (double)TV.mT * TV.mT * TV.nc;
@@ -1030,6 +1185,16 @@ hylu_status upload_device(hylu_handle h)
             UP(q.d_sp, sp);
             q.d_inv = dalloc(h, std::max<size_t>(q.spanels.size(), 1) * 2 * kNB * kNB * (h->fp32 ? 4 : 8));
             if (!q.d_inv) return HYLU_ERR_OOM;
+        }
+        if (!h->vjobs.empty()) {
+            std::vector<ViewDesc> vd(h->dsn.size());
+            for (size_t q = 0; q < h->dsn.size(); q++) {
+                vd[q].TV = h->dsn[q].TV;
+                vd[q].sp = h->dsn[q].d_sp;
+                vd[q].inv = h->dsn[q].d_inv;
+            }
+            UP(h->d_vdesc, vd);
+            UP(h->d_vjobs, h->vjobs);
         }
         if (!h->dsn.empty()) {
             std::vector<uint8_t> fl(L.nnodes, 0);
@@ -1519,6 +1684,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                                     h->tail_list);
         for (const DenseOp& o : h->tail_ops) h->tail_flops += o.flops;
     }
+    plan_shared_views(h);
     plog("tail plan");
     T.row_nt.assign(nl, 0);
     // a level of few rows runs one row per CU at most: its rows may take

@@ -1292,10 +1292,17 @@ __global__ __launch_bounds__(256) void k_tail_panel(DevLayout D, TailView TV, T*
 // row's candidate is taken while that row is updated, so each step makes one
 // pass.  The window's pivot steps sit in LDS; STAGE also stages the window.
 template <typename T, int NT, bool STAGE>
-__global__ __launch_bounds__(NT) void k_tail_panel_wide(DevLayout D, TailView TV, T* __restrict__ vals, int p0,
+__global__ __launch_bounds__(NT) void k_tail_panel_wide(DevLayout D, TailView TVp, T* __restrict__ vals, int p0,
                                                         int p1, int c0, int c1, T tau, int32_t* __restrict__ pert,
-                                                        int search)
+                                                        int search, const ViewDesc* __restrict__ vd,
+                                                        const ViewJob* __restrict__ jobs)
 {
+    TailView TV = TVp;
+    if (jobs) {                 // one panel of several views' launch
+        const ViewJob j = jobs[blockIdx.x];
+        TV = vd[j.v].TV;
+        p0 = j.a[0]; p1 = j.a[1]; c0 = j.a[2]; c1 = j.a[3];
+    }
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int64_t rowoff[kNB];
     __shared__ int rlo[kNB], rhi[kNB], rpiv[kNB];      // per panel row: block range, known pivot
@@ -1587,16 +1594,25 @@ __global__ __launch_bounds__(64) void k_tail_panel_reg(DevLayout D, TailView TV,
 // blocks [0, nA): panel rows' U for columns >= c1 (one thread per column);
 // blocks [nA, ...): trailing rows' multipliers (one thread per row)
 template <typename T>
-__global__ __launch_bounds__(64) void k_tail_trsm(TailView TV, T* __restrict__ vals, int p0, int p1, int c1, int nA,
-                                                  int kb0, int kof, const int32_t* __restrict__ bl)
+__global__ __launch_bounds__(64) void k_tail_trsm(TailView TVp, T* __restrict__ vals, int p0, int p1, int c1, int nA,
+                                                  int kb0, int kof, const int32_t* __restrict__ bl,
+                                                  const ViewDesc* __restrict__ vd, const ViewJob* __restrict__ jobs)
 {
+    TailView TV = TVp;
+    int jblk = -1;
+    if (jobs) {                 // a block of several views' launch
+        const ViewJob j = jobs[blockIdx.x];
+        TV = vd[j.v].TV;
+        p0 = j.a[0]; p1 = j.a[1]; c1 = j.a[2]; nA = j.a[3]; kb0 = j.a[4]; kof = j.a[5];
+        jblk = j.blk;
+    }
     __shared__ T M[kNB][kNB + 1];       // M[i][j] = X_{p0+i}[tpiv[p0+j]]
     __shared__ int64_t rowoff[kNB];
     __shared__ int piv[kNB];
     const int np = p1 - p0, tid = threadIdx.x;
     // block list (structurally sparse tail): column blocks of U that hold
     // entries, and every row block, flagged when its multipliers are all zero
-    int blk = blockIdx.x;
+    int blk = jblk >= 0 ? jblk : (int)blockIdx.x;
     if (bl) {
         const int e = bl[blockIdx.x];
         blk = e & ~kTrsmZero;
@@ -1683,12 +1699,22 @@ template <> struct Mfma<float> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ vals, int kb0, int K, int rb, int re,
+__global__ __launch_bounds__(256) void k_tail_gemm(TailView TVp, T* __restrict__ vals, int kb0, int K, int rb, int re,
                                                    int cg0, int mstep, int gx, int gy, int swz, int gp0, int gnp,
-                                                   const uint32_t* __restrict__ tl, int kb1, int kb2, int kb3)
+                                                   const uint32_t* __restrict__ tl, int kb1, int kb2, int kb3,
+                                                   const ViewDesc* __restrict__ vd, const ViewJob* __restrict__ jobs)
 {
     typedef typename Mfma<T>::v4 v4;
     static_assert(kGroup == 4, "the K ranges below assume four panels per group");
+    TailView TV = TVp;
+    int jblk = -1;
+    if (jobs) {                 // a tile of several views' launch: one panel, every tile
+        const ViewJob j = jobs[blockIdx.x];
+        TV = vd[j.v].TV;
+        kb0 = j.a[0]; K = j.a[1]; rb = j.a[2]; re = j.a[3]; cg0 = j.a[4]; mstep = j.a[5];
+        gp0 = 0; gnp = 0; kb1 = kb2 = kb3 = K;
+        jblk = j.blk;
+    }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int mT = re, nc = TV.nc, lds = TV.mT;
     // tile of this workgroup.  Workgroups go to the 8 XCDs round robin by
@@ -1699,7 +1725,10 @@ __global__ __launch_bounds__(256) void k_tail_gemm(TailView TV, T* __restrict__ 
     int tx, ty, pmask = 0xF;
     {
         const int L = blockIdx.x;
-        if (tl) {
+        if (jblk >= 0) {
+            ty = jblk >> 16;
+            tx = jblk & 0xFFFF;
+        } else if (tl) {
             const uint32_t e = tl[L];
             if (e == kTileNone) return;
             ty = (int)(e >> 16);
@@ -2029,14 +2058,26 @@ __global__ __launch_bounds__(256) void k_tail_utext(DevLayout D, TailView TV, co
 // U^-1, column-major 64 x 64 at out + (2 s + kind) * 64 * 64.  Thread j
 // substitutes for column j.
 template <typename T>
-__global__ __launch_bounds__(64) void k_tail_dinv(TailView TV, const T* __restrict__ vals, const int32_t* __restrict__ sp,
-                                                  T* __restrict__ out)
+__global__ __launch_bounds__(64) void k_tail_dinv(TailView TVp, const T* __restrict__ vals, const int32_t* __restrict__ spp,
+                                                  T* __restrict__ outp, const ViewDesc* __restrict__ vd,
+                                                  const ViewJob* __restrict__ jobs)
 {
     __shared__ T M[kNB][kNB + 1];
     __shared__ T X[kNB][kNB + 1];
     __shared__ int piv[kNB];
     __shared__ int64_t ro[kNB];
-    const int s = blockIdx.x >> 1, kind = blockIdx.x & 1;
+    TailView TV = TVp;
+    const int32_t* sp = spp;
+    T* out = outp;
+    int bid = blockIdx.x;
+    if (jobs) {                 // an inverse of several views' launch
+        const ViewJob j = jobs[blockIdx.x];
+        TV = vd[j.v].TV;
+        sp = vd[j.v].sp;
+        out = reinterpret_cast<T*>(vd[j.v].inv);
+        bid = j.blk;
+    }
+    const int s = bid >> 1, kind = bid & 1;
     const int p0 = sp[2 * s], np = sp[2 * s + 1] - p0;
     const int lane = threadIdx.x;
     if (lane < np) { piv[lane] = TV.tpiv[p0 + lane]; ro[lane] = TV.trow[p0 + lane]; }
@@ -2514,11 +2555,11 @@ hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, v
         const size_t tsz = ((size_t)(c1 - c0) * 4 + 15) & ~(size_t)15;
         const size_t stg = tsz + sh;
         if (stg <= 60 * 1024) {
-            if (fp32) hipLaunchKernelGGL((k_tail_panel_wide<float, 256, true>), dim3(1), dim3(256), stg, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
-            else hipLaunchKernelGGL((k_tail_panel_wide<double, 256, true>), dim3(1), dim3(256), stg, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+            if (fp32) hipLaunchKernelGGL((k_tail_panel_wide<float, 256, true>), dim3(1), dim3(256), stg, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search, (const ViewDesc*)nullptr, (const ViewJob*)nullptr);
+            else hipLaunchKernelGGL((k_tail_panel_wide<double, 256, true>), dim3(1), dim3(256), stg, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search, (const ViewDesc*)nullptr, (const ViewJob*)nullptr);
         } else if (tsz <= 60 * 1024) {
-            if (fp32) hipLaunchKernelGGL((k_tail_panel_wide<float, 1024, false>), dim3(1), dim3(1024), tsz, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
-            else hipLaunchKernelGGL((k_tail_panel_wide<double, 1024, false>), dim3(1), dim3(1024), tsz, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
+            if (fp32) hipLaunchKernelGGL((k_tail_panel_wide<float, 1024, false>), dim3(1), dim3(1024), tsz, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search, (const ViewDesc*)nullptr, (const ViewJob*)nullptr);
+            else hipLaunchKernelGGL((k_tail_panel_wide<double, 1024, false>), dim3(1), dim3(1024), tsz, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search, (const ViewDesc*)nullptr, (const ViewJob*)nullptr);
         } else {
             if (fp32) hipLaunchKernelGGL((k_tail_panel<float, false>), dim3(1), dim3(256), 0, st, D, T, (float*)vals, p0, p1, c0, c1, (float)tau, pert, search);
             else hipLaunchKernelGGL((k_tail_panel<double, false>), dim3(1), dim3(256), 0, st, D, T, (double*)vals, p0, p1, c0, c1, tau, pert, search);
@@ -2535,8 +2576,8 @@ hipError_t launch_tail_trsm(bool fp32, const TailView& T, void* vals, int32_t p0
     const int grid = blocks ? nblocks : nA + nB;
     if (grid <= 0) return hipSuccess;
     if (kof < 0 || kof + (p1 - p0) > kNB * kGroup) return hipErrorInvalidValue;
-    if (fp32) hipLaunchKernelGGL(k_tail_trsm<float>, dim3(grid), dim3(64), 0, st, T, (float*)vals, p0, p1, c1, nA, kb0, kof, blocks);
-    else hipLaunchKernelGGL(k_tail_trsm<double>, dim3(grid), dim3(64), 0, st, T, (double*)vals, p0, p1, c1, nA, kb0, kof, blocks);
+    if (fp32) hipLaunchKernelGGL(k_tail_trsm<float>, dim3(grid), dim3(64), 0, st, T, (float*)vals, p0, p1, c1, nA, kb0, kof, blocks, (const ViewDesc*)nullptr, (const ViewJob*)nullptr);
+    else hipLaunchKernelGGL(k_tail_trsm<double>, dim3(grid), dim3(64), 0, st, T, (double*)vals, p0, p1, c1, nA, kb0, kof, blocks, (const ViewDesc*)nullptr, (const ViewJob*)nullptr);
     return hipGetLastError();
 }
 
@@ -2559,8 +2600,8 @@ hipError_t launch_tail_gemm(bool fp32, const TailView& T, void* vals, int32_t kb
         if (ntiles <= 0) return hipSuccess;
         grid = (unsigned)ntiles;
     }
-    if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(grid), dim3(256), 0, st, T, (float*)vals, kb0, K, rb, re, cg0, mstep, gx, gy, swz, gp0, gnp, tiles, kb1, kb2, kb3);
-    else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(grid), dim3(256), 0, st, T, (double*)vals, kb0, K, rb, re, cg0, mstep, gx, gy, swz, gp0, gnp, tiles, kb1, kb2, kb3);
+    if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(grid), dim3(256), 0, st, T, (float*)vals, kb0, K, rb, re, cg0, mstep, gx, gy, swz, gp0, gnp, tiles, kb1, kb2, kb3, (const ViewDesc*)nullptr, (const ViewJob*)nullptr);
+    else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(grid), dim3(256), 0, st, T, (double*)vals, kb0, K, rb, re, cg0, mstep, gx, gy, swz, gp0, gnp, tiles, kb1, kb2, kb3, (const ViewDesc*)nullptr, (const ViewJob*)nullptr);
     return hipGetLastError();
 }
 
@@ -2588,8 +2629,60 @@ hipError_t launch_tail_dinv(bool fp32, const TailView& T, const void* vals, cons
                             void* out, hipStream_t st)
 {
     if (nsp <= 0) return hipSuccess;
-    if (fp32) hipLaunchKernelGGL(k_tail_dinv<float>, dim3(2 * nsp), dim3(64), 0, st, T, (const float*)vals, spanels, (float*)out);
-    else hipLaunchKernelGGL(k_tail_dinv<double>, dim3(2 * nsp), dim3(64), 0, st, T, (const double*)vals, spanels, (double*)out);
+    if (fp32) hipLaunchKernelGGL(k_tail_dinv<float>, dim3(2 * nsp), dim3(64), 0, st, T, (const float*)vals, spanels, (float*)out, (const ViewDesc*)nullptr, (const ViewJob*)nullptr);
+    else hipLaunchKernelGGL(k_tail_dinv<double>, dim3(2 * nsp), dim3(64), 0, st, T, (const double*)vals, spanels, (double*)out, (const ViewDesc*)nullptr, (const ViewJob*)nullptr);
+    return hipGetLastError();
+}
+
+size_t tail_panel_wide_lds(bool fp32, int32_t np, int32_t wc)
+{
+    const size_t es = fp32 ? sizeof(float) : sizeof(double);
+    const size_t tsz = ((size_t)wc * 4 + 15) & ~(size_t)15;
+    const size_t stg = tsz + (size_t)np * wc * es;
+    return (wc > 64 && np <= kNB && stg <= 60 * 1024) ? stg : 0;
+}
+
+hipError_t launch_tail_panel_views(bool fp32, const DevLayout& D, const ViewDesc* vd, void* vals, const ViewJob* jobs,
+                                   int32_t njobs, size_t lds, double tau, int32_t* pert, int32_t search, hipStream_t st)
+{
+    if (njobs <= 0) return hipSuccess;
+    if (!vd || !jobs || lds == 0 || lds > 60 * 1024) return hipErrorInvalidValue;
+    const TailView none{};
+    if (fp32) hipLaunchKernelGGL((k_tail_panel_wide<float, 256, true>), dim3(njobs), dim3(256), lds, st, D, none, (float*)vals, 0, 0, 0, 0, (float)tau, pert, search, vd, jobs);
+    else hipLaunchKernelGGL((k_tail_panel_wide<double, 256, true>), dim3(njobs), dim3(256), lds, st, D, none, (double*)vals, 0, 0, 0, 0, tau, pert, search, vd, jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_trsm_views(bool fp32, const ViewDesc* vd, void* vals, const ViewJob* jobs, int32_t njobs,
+                                  hipStream_t st)
+{
+    if (njobs <= 0) return hipSuccess;
+    if (!vd || !jobs) return hipErrorInvalidValue;
+    const TailView none{};
+    if (fp32) hipLaunchKernelGGL(k_tail_trsm<float>, dim3(njobs), dim3(64), 0, st, none, (float*)vals, 0, 0, 0, 0, 0, 0, (const int32_t*)nullptr, vd, jobs);
+    else hipLaunchKernelGGL(k_tail_trsm<double>, dim3(njobs), dim3(64), 0, st, none, (double*)vals, 0, 0, 0, 0, 0, 0, (const int32_t*)nullptr, vd, jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_gemm_views(bool fp32, const ViewDesc* vd, void* vals, const ViewJob* jobs, int32_t njobs,
+                                  hipStream_t st)
+{
+    if (njobs <= 0) return hipSuccess;
+    if (!vd || !jobs) return hipErrorInvalidValue;
+    const TailView none{};
+    if (fp32) hipLaunchKernelGGL(k_tail_gemm<float>, dim3(njobs), dim3(256), 0, st, none, (float*)vals, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, (const uint32_t*)nullptr, 0, 0, 0, vd, jobs);
+    else hipLaunchKernelGGL(k_tail_gemm<double>, dim3(njobs), dim3(256), 0, st, none, (double*)vals, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, (const uint32_t*)nullptr, 0, 0, 0, vd, jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_dinv_views(bool fp32, const ViewDesc* vd, const void* vals, const ViewJob* jobs, int32_t njobs,
+                                  hipStream_t st)
+{
+    if (njobs <= 0) return hipSuccess;
+    if (!vd || !jobs) return hipErrorInvalidValue;
+    const TailView none{};
+    if (fp32) hipLaunchKernelGGL(k_tail_dinv<float>, dim3(njobs), dim3(64), 0, st, none, (const float*)vals, (const int32_t*)nullptr, (float*)nullptr, vd, jobs);
+    else hipLaunchKernelGGL(k_tail_dinv<double>, dim3(njobs), dim3(64), 0, st, none, (const double*)vals, (const int32_t*)nullptr, (double*)nullptr, vd, jobs);
     return hipGetLastError();
 }
 

@@ -82,6 +82,34 @@ struct TailView {
     void* lbuf;             // kNB x mT workspace: the current panel's multipliers, transposed
 };
 
+// Several dense views in one launch (the large supernodes of one level): a
+// table of the views, and per workgroup its view, its block within that
+// view's own launch and the operation's arguments.
+struct ViewDesc {
+    TailView TV;
+    const int32_t* sp;      // solve panels (p0, p1 pairs)
+    void* inv;              // inverses of their diagonal blocks
+};
+struct ViewJob {
+    int32_t v;              // view
+    int32_t blk;            // TRSM block; GEMM tile (ty << 16 | tx); inverse block (2 panel + kind)
+    int32_t a[6];           // panel: p0 p1 c0 c1 | TRSM: p0 p1 c1 nA kb0 kof | GEMM: kb0 K rb re cg0 mstep
+};
+// every job's panel by the wide-window kernel with the window in LDS
+// (lds: the largest job's bytes); TRSM, trailing GEMM (every tile, one
+// panel) and diagonal-block inverses of the jobs
+hipError_t launch_tail_panel_views(bool fp32, const DevLayout& D, const ViewDesc* vd, void* vals, const ViewJob* jobs,
+                                   int32_t njobs, size_t lds, double tau, int32_t* pert, int32_t search, hipStream_t st);
+hipError_t launch_tail_trsm_views(bool fp32, const ViewDesc* vd, void* vals, const ViewJob* jobs, int32_t njobs,
+                                  hipStream_t st);
+hipError_t launch_tail_gemm_views(bool fp32, const ViewDesc* vd, void* vals, const ViewJob* jobs, int32_t njobs,
+                                  hipStream_t st);
+hipError_t launch_tail_dinv_views(bool fp32, const ViewDesc* vd, const void* vals, const ViewJob* jobs, int32_t njobs,
+                                  hipStream_t st);
+// LDS bytes of the wide-window panel kernel with the window staged (0 when it
+// does not fit that kernel)
+size_t tail_panel_wide_lds(bool fp32, int32_t np, int32_t wc);
+
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_tail_init(const TailView& T, hipStream_t st);
 hipError_t launch_tail_panel(bool fp32, const DevLayout& D, const TailView& T, void* vals, int32_t p0, int32_t p1,
