@@ -695,6 +695,43 @@ __device__ __forceinline__ T gather_x(const T* __restrict__ P, const int32_t* __
     return acc;
 }
 
+// chunk staging for the node solves: out[t] = y[qinv[cols[t]]] (forward) or
+// x[cols[t]] (backward), t < len, NT threads, four loads per thread in flight
+constexpr int kSolveChunk = 1024;
+constexpr int kChainChunk = 256;     // per wavefront in the solve chains
+template <typename T, int NT>
+__device__ __forceinline__ void stage_lq(const int32_t* __restrict__ cols, const int32_t* __restrict__ qinv,
+                                         const T* __restrict__ y, int len, int tid, T* out)
+{
+    for (int t0 = tid; t0 < len; t0 += 4 * NT) {
+        int c[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) c[u] = t0 + NT * u < len ? cols[t0 + NT * u] : 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) c[u] = t0 + NT * u < len ? qinv[c[u]] : 0;
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = t0 + NT * u < len ? y[c[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; u++) if (t0 + NT * u < len) out[t0 + NT * u] = v[u];
+    }
+}
+template <typename T, int NT>
+__device__ __forceinline__ void stage_x(const int32_t* __restrict__ cols, const T* __restrict__ x, int len, int tid,
+                                        T* out)
+{
+    for (int t0 = tid; t0 < len; t0 += 4 * NT) {
+        int c[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) c[u] = t0 + NT * u < len ? cols[t0 + NT * u] : 0;
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = t0 + NT * u < len ? x[c[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; u++) if (t0 + NT * u < len) out[t0 + NT * u] = v[u];
+    }
+}
+
 // sum over q = q0 + lane, .. < q1 (stride S) of vals[slot[q]] * w[row[q]],
 // four entries per lane at a time with their dependent loads issued together
 template <typename T, int S>
@@ -765,6 +802,7 @@ __global__ __launch_bounds__(256) void k_lsolve_sn(DevLayout D, const T* __restr
 {
     __shared__ T Lb[kSnSolveRows][kSnSolveRows + 1];   // Lb[r][b] = L(r, b), b < r
     __shared__ T ys[kSnSolveRows];
+    __shared__ T ychunk[kSolveChunk];
     const int v = nodes[blockIdx.x];
     if (D.dense_sn && D.dense_sn[v]) return;
     const int m = D.m[v];
@@ -781,11 +819,33 @@ __global__ __launch_bounds__(256) void k_lsolve_sn(DevLayout D, const T* __restr
     }
     for (int r = 0; r < nrhs; r++) {
         T* yr = y + (int64_t)r * n;
-        for (int a = wv; a < m; a += 4) {
-            const T* Pa = P + (int64_t)a * W;
-            T acc = gather_lq(Pa, cols, D.qinv, yr, lw, lane);
-            acc = wave_sum(acc);
-            if (lane == 0) ys[a] = yr[r0 + a] - acc;
+        // the outside values every row of the node multiplies, y at the rows
+        // pivoting on its L columns, staged once per chunk (each lane still
+        // sums its entries t = lane + 64 k in ascending order)
+        T acc[kSnSolveRows / 4];
+#pragma unroll
+        for (int i = 0; i < kSnSolveRows / 4; i++) acc[i] = T(0);
+        for (int c0 = 0; c0 < lw; c0 += kSolveChunk) {
+            const int nc = min(kSolveChunk, lw - c0);
+            stage_lq<T, 256>(cols + c0, D.qinv, yr, nc, tid, ychunk);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < kSnSolveRows / 4; i++) {
+                const int a = wv + 4 * i;
+                if (a < m) {
+                    const T* Pa = P + (int64_t)a * W + c0;
+                    for (int t = lane; t < nc; t += 64) acc[i] += Pa[t] * ychunk[t];
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < kSnSolveRows / 4; i++) {
+            const int a = wv + 4 * i;
+            if (a < m) {
+                const T s = wave_sum(acc[i]);
+                if (lane == 0) ys[a] = yr[r0 + a] - s;
+            }
         }
         __syncthreads();
         if (wv == 0) {
@@ -813,6 +873,7 @@ __global__ __launch_bounds__(64 * kChainWaves) void k_lsolve_chain(DevLayout D, 
                                                                    int32_t l1, T* __restrict__ y, int32_t nrhs)
 {
     __shared__ T ys[kChainWaves][kChainRows];
+    __shared__ T yc[kChainWaves][kChainChunk];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = D.n;
     for (int l = l0; l < l1; l++) {
@@ -826,13 +887,41 @@ __global__ __launch_bounds__(64 * kChainWaves) void k_lsolve_chain(DevLayout D, 
             const int myp = lane < m ? pl[lane] : 0;
             for (int r = 0; r < nrhs; r++) {
                 T* yr = y + (int64_t)r * n;
-                for (int a = 0; a < m; a++) {
-                    const T* Pa = P + (int64_t)a * W;
-                    T acc = gather_lq(Pa, cols, D.qinv, yr, lw, lane);
-                    if (lane < a) acc += Pa[lw + myp] * ys[wv][lane];
-                    acc = wave_sum(acc);
-                    if (lane == 0) ys[wv][a] = yr[r0 + a] - acc;
-                    __builtin_amdgcn_wave_barrier();
+                // a node of several rows: the outside values its rows share
+                // staged once per chunk, eight rows' sums at a time (each lane
+                // in the same order as the direct gather)
+                for (int g0 = 0; g0 < m; g0 += 8) {
+                    T acc[8];
+#pragma unroll
+                    for (int i = 0; i < 8; i++) acc[i] = T(0);
+                    if (m == 1) {
+                        acc[0] = gather_lq(P, cols, D.qinv, yr, lw, lane);
+                    } else {
+                        for (int c0 = 0; c0 < lw; c0 += kChainChunk) {
+                            const int nc = min(kChainChunk, lw - c0);
+                            stage_lq<T, 64>(cols + c0, D.qinv, yr, nc, lane, yc[wv]);
+                            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                            for (int i = 0; i < 8; i++) {
+                                if (g0 + i < m) {
+                                    const T* Pa = P + (int64_t)(g0 + i) * W + c0;
+                                    for (int t = lane; t < nc; t += 64) acc[i] += Pa[t] * yc[wv][t];
+                                }
+                            }
+                            __builtin_amdgcn_wave_barrier();
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; i++) {
+                        const int a = g0 + i;
+                        if (a >= m) break;
+                        const T* Pa = P + (int64_t)a * W;
+                        T s = acc[i];
+                        if (lane < a) s += Pa[lw + myp] * ys[wv][lane];
+                        s = wave_sum(s);
+                        if (lane == 0) ys[wv][a] = yr[r0 + a] - s;
+                        __builtin_amdgcn_wave_barrier();
+                    }
                 }
                 if (lane < m) yr[r0 + lane] = ys[wv][lane];
                 __builtin_amdgcn_wave_barrier();
@@ -937,6 +1026,7 @@ __global__ __launch_bounds__(256) void k_usolve_sn(DevLayout D, const T* __restr
     __shared__ T Ub[kSnSolveRows][kSnSolveRows + 1];
     __shared__ T ys[kSnSolveRows];
     __shared__ int pls[kSnSolveRows];
+    __shared__ T ychunk[kSolveChunk];
     const int v = nodes[blockIdx.x];
     if (D.dense_sn && D.dense_sn[v]) return;
     const int m = D.m[v];
@@ -956,10 +1046,31 @@ __global__ __launch_bounds__(256) void k_usolve_sn(DevLayout D, const T* __restr
     for (int r = 0; r < nrhs; r++) {
         const T* yr = y + (int64_t)r * n;
         T* xr = x + (int64_t)r * n;
-        for (int a = wv; a < m; a += 4) {
-            T acc = gather_x(P + (int64_t)a * W + m, tc, xr, w, lane);
-            acc = wave_sum(acc);
-            if (lane == 0) ys[a] = yr[r0 + a] - acc;
+        // x at the node's columns past its block, staged once per chunk
+        T acc[kSnSolveRows / 4];
+#pragma unroll
+        for (int i = 0; i < kSnSolveRows / 4; i++) acc[i] = T(0);
+        for (int c0 = 0; c0 < w; c0 += kSolveChunk) {
+            const int nc = min(kSolveChunk, w - c0);
+            stage_x<T, 256>(tc + c0, xr, nc, tid, ychunk);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < kSnSolveRows / 4; i++) {
+                const int a = wv + 4 * i;
+                if (a < m) {
+                    const T* Pa = P + (int64_t)a * W + m + c0;
+                    for (int t = lane; t < nc; t += 64) acc[i] += Pa[t] * ychunk[t];
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < kSnSolveRows / 4; i++) {
+            const int a = wv + 4 * i;
+            if (a < m) {
+                const T s = wave_sum(acc[i]);
+                if (lane == 0) ys[a] = yr[r0 + a] - s;
+            }
         }
         __syncthreads();
         if (wv == 0) {
@@ -2025,11 +2136,12 @@ __global__ __launch_bounds__(256) void k_tail_lext(DevLayout D, const T* __restr
     const int W = D.W[v];
     const T* P = vals + D.voff[v] + (int64_t)(i - D.r0[v]) * W;
     const int32_t* cols = D.cols + D.coff[v];
-    // outside sources come first in the column list and are the only columns < t0
+    // outside sources come first in the column list and are the only columns
+    // < t0: the L region's first lw - (r0 - t0) entries
+    const int next = D.lw[v] - (D.r0[v] - t0);
     for (int r = 0; r < nrhs; r++) {
         T* yr = y + (int64_t)r * D.n;
-        T acc = T(0);
-        for (int t = lane; t < W && cols[t] < t0; t += 64) acc += P[t] * yr[D.qinv[cols[t]]];
+        T acc = gather_lq<T, 64>(P, cols, D.qinv, yr, next, lane);
         acc = wave_sum(acc);
         if (lane == 0) yr[i] -= acc;
     }
@@ -2045,8 +2157,28 @@ __global__ __launch_bounds__(256) void k_tail_utext(DevLayout D, TailView TV, co
     if (c >= D.n) return;
     for (int r = 0; r < nrhs; r++) {
         const T* wr = w + (int64_t)r * D.n;
+        // four entries per lane at a time: slots and rows, then values
         T acc = T(0);
-        for (int64_t q = D.ut_ptr[c] + lane; q < D.ut_ptr[c + 1]; q += 64) acc += vals[D.ut_slot[q]] * wr[D.ut_row[q]];
+        const int64_t q1 = D.ut_ptr[c + 1];
+        for (int64_t q0 = D.ut_ptr[c] + lane; q0 < q1; q0 += 4 * 64) {
+            int64_t sl[4];
+            int32_t rw[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int64_t q = q0 + 64 * u;
+                sl[u] = q < q1 ? D.ut_slot[q] : 0;
+                rw[u] = q < q1 ? D.ut_row[q] : 0;
+            }
+            T pv[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const bool ok = q0 + 64 * u < q1;
+                pv[u] = ok ? vals[sl[u]] : T(0);
+                xv[u] = ok ? wr[rw[u]] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) acc += pv[u] * xv[u];
+        }
         acc = wave_sum(acc);
         if (lane == 0) h[(int64_t)r * D.n + c] -= acc;
     }
@@ -2227,9 +2359,9 @@ __global__ __launch_bounds__(256) void k_sn_ext(DevLayout D, const T* __restrict
     for (int r = 0; r < nrhs; r++) {
         T* yr = y + (int64_t)r * n;
         const T* xr = upper ? x + (int64_t)r * n : nullptr;
-        T acc = T(0);
-        if (upper) for (int t = t0 + lane; t < t1; t += 64) acc += Pa[t] * xr[cols[t]];
-        else for (int t = t0 + lane; t < t1; t += 64) acc += Pa[t] * yr[D.qinv[cols[t]]];
+        // the grouped gathers of the level solves (four entries per lane in flight)
+        T acc = upper ? gather_x<T, 64>(Pa + t0, cols + t0, xr, t1 - t0, lane)
+                      : gather_lq<T, 64>(Pa, cols, D.qinv, yr, t1, lane);
         acc = wave_sum(acc);
         if (lane == 0) yr[r0 + a] -= acc;
     }
