@@ -22,6 +22,15 @@ namespace hylu {
 namespace {
 
 template <typename T> __device__ __forceinline__ T tabs(T x) { return x < T(0) ? -x : x; }
+
+// value of v in lane l (l the same in every lane), all lanes active
+__device__ __forceinline__ double rlane(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float rlane(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
 // magnitude for the pivot search: a NaN ranks above every number, so a search
 // over a non-empty set of columns always returns one of them
 template <typename T> __device__ __forceinline__ T pmag(T x)
@@ -405,38 +414,61 @@ __global__ __launch_bounds__(256) void k_perturb_rows(DevLayout D, T* __restrict
 // inverse of a supernode's block in pivot order, once its LU is complete: one
 // workgroup per supernode, thread j solving U_pp x = e_j by back substitution
 // for column j of the inverse (U_pp staged in LDS when it fits)
+// inverse of a supernode's block in pivot order, U_pp(i, k) = U(i, pl_k)
+// (upper triangular), X = U_pp^{-1} row-major m x m: a wavefront per column
+// j of X.  Lane l holds x[l + 64 u]; from i = j down to 0 the lane holding
+// x_i divides it by U_pp(i, i) and every lane takes x_i (a lane read) off its
+// entries above i, with column i of U_pp loaded one step ahead.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sn_inverse(DevLayout D, const T* __restrict__ vals,
                                                     const int32_t* __restrict__ nodes, const int64_t* __restrict__ inv_off,
-                                                    T* __restrict__ uinv, int32_t lds_m)
+                                                    T* __restrict__ uinv, int32_t cpb)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int pls[kInvMax];
-    const int v = nodes[blockIdx.x];
+    static_assert(kInvMax <= 256, "four entries per lane");
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int v = nodes[blockIdx.x / cpb];
     const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const int j = (blockIdx.x % cpb) * 4 + wv;
+    if (j >= m) return;
     const T* P = vals + D.voff[v] + lw;
+    const int32_t* pl = D.pl + r0;
     T* X = uinv + inv_off[v];
-    const int tid = threadIdx.x;
-    for (int b = tid; b < m; b += 256) pls[b] = D.pl[r0 + b];
-    __syncthreads();
-    const bool in_lds = m <= lds_m;
-    T* Us = reinterpret_cast<T*>(smem_raw);          // m x m, Us[i*m + k] = U_pp(i, k)
-    if (in_lds) {
-        for (int idx = tid; idx < m * m; idx += 256) {
-            const int i = idx / m, k = idx - (idx / m) * m;
-            Us[idx] = k >= i ? P[(int64_t)i * W + pls[k]] : T(0);
+    T x[4], uc[4], un[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) x[u] = lane + 64 * u == j ? T(1) : T(0);
+    // column i of U_pp, rows 0..i: U(k, pl_i) for the lane's k
+    auto load_col = [&](int i, T* dst) {
+        const int pc = pl[i];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int k = lane + 64 * u;
+            dst[u] = k <= i ? P[(int64_t)k * W + pc] : T(0);
         }
-        __syncthreads();
+    };
+    load_col(j, uc);
+    for (int i = j; i >= 0; i--) {
+        if (i > 0) load_col(i - 1, un);
+        const int ui = i >> 6, li = i & 63;
+        // the owner of x_i divides by the diagonal; everyone reads it
+        T xi = T(0), di = T(0);
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (u == ui) { xi = x[u]; di = uc[u]; }
+        xi = xi / di;
+        const T q = rlane(xi, li);
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int k = lane + 64 * u;
+            if (k == i) x[u] = q;
+            else if (k < i) x[u] -= uc[u] * q;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) uc[u] = un[u];
     }
-    auto U = [&](int i, int k) -> T { return in_lds ? Us[i * m + k] : P[(int64_t)i * W + pls[k]]; };
-    for (int j = tid; j < m; j += 256) {
-        for (int i = j + 1; i < m; i++) X[(int64_t)i * m + j] = T(0);
-        X[(int64_t)j * m + j] = T(1) / U(j, j);
-        for (int i = j - 1; i >= 0; i--) {
-            T acc = T(0);
-            for (int k = i + 1; k <= j; k++) acc += U(i, k) * X[(int64_t)k * m + j];
-            X[(int64_t)i * m + j] = -acc / U(i, i);
-        }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int k = lane + 64 * u;
+        if (k < m) X[(int64_t)k * m + j] = k <= j ? x[u] : T(0);
     }
 }
 
@@ -1644,14 +1676,6 @@ __global__ __launch_bounds__(64 * NW) void k_tail_panel_lds4(DevLayout D, TailVi
     if (tid == 0 && npert > 0) atomicAdd(pert, npert);
 }
 
-// value of v in lane l (l the same in every lane), all lanes active
-__device__ __forceinline__ double rlane(double v, int l)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ float rlane(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
 
 // refactorisation of a panel whose pivot window is its own rows (pivots
 // known): one wavefront, lane r holding row r of the window in registers in
@@ -2517,12 +2541,10 @@ hipError_t launch_sn_inverse(bool fp32, const DevLayout& D, const void* vals, co
                              int32_t maxm, const int64_t* inv_off, void* uinv, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    if (maxm > kInvMax) return hipErrorInvalidValue;
-    const size_t es = fp32 ? sizeof(float) : sizeof(double);
-    const int lds_m = std::min(maxm, fp32 ? 180 : 128);    // m x m block staged in LDS up to this m
-    const size_t sh = (size_t)lds_m * lds_m * es;
-    if (fp32) hipLaunchKernelGGL(k_sn_inverse<float>, dim3(count), dim3(256), sh, st, D, (const float*)vals, nodes, inv_off, (float*)uinv, lds_m);
-    else hipLaunchKernelGGL(k_sn_inverse<double>, dim3(count), dim3(256), sh, st, D, (const double*)vals, nodes, inv_off, (double*)uinv, lds_m);
+    if (maxm > kInvMax || maxm < 1) return hipErrorInvalidValue;
+    const int cpb = (maxm + 3) / 4;                // workgroups per node: four columns each
+    if (fp32) hipLaunchKernelGGL(k_sn_inverse<float>, dim3(count * cpb), dim3(256), 0, st, D, (const float*)vals, nodes, inv_off, (float*)uinv, cpb);
+    else hipLaunchKernelGGL(k_sn_inverse<double>, dim3(count * cpb), dim3(256), 0, st, D, (const double*)vals, nodes, inv_off, (double*)uinv, cpb);
     return hipGetLastError();
 }
 
