@@ -92,12 +92,15 @@ typedef struct {
                               launches of the factor levels with fewer than 256 rows (a long tail row in pieces
                               over several of them, its sources in order) instead of waiting for the final level;
                               0: all of them in the final level (same factors either way; default 1) */
-    int32_t pipeline_rows; /* pipelined mode of Sec. 2.2.1: > 0 schedules the factor levels from the first one
-                              after which every level has at most this many rows (and the deferred last level) as
-                              one persistent launch whose rows wait per source node instead of per level; the
-                              analysis builds that schedule and checks it is deadlock-free (HYLU_ERR_INTERNAL
-                              otherwise), but the launch is switched off on the device: hylu_factorize and
-                              hylu_refactor return HYLU_ERR_ARG for such a handle.  0: bulk mode (default) */
+    int32_t pipeline_rows; /* pipeline mode of Sec. 2.2.1: > 0 runs every run of at least three consecutive
+                              factor levels (after level 0, before the deferred final level) of at most this many
+                              rows (capped at 512), whose nodes are standalone rows or supernodes of at most 64 rows
+                              that no blocked or tile kernel takes, as chain launches: one workgroup whose
+                              wavefronts take the rows' updates and the supernodes' block LUs in level order and
+                              wait per source node (flags in LDS) instead of per level.  The factors equal bulk
+                              mode's bit for bit.  The analysis checks the schedule (HYLU_ERR_INTERNAL otherwise);
+                              a wait that gives up makes the factorisation return HYLU_ERR_DEVICE.  Deferred rows
+                              are not placed into chain levels.  0: bulk mode only (default) */
     int32_t group_min_rows;  /* blocked dense LU (large supernodes, dense tail): row panels go in groups of four
                                 (one trailing update per group) while at least this many rows remain below them
                                 (<= 0: default 2048) */
@@ -142,7 +145,8 @@ typedef struct {
                                          solution as berr (largest over right-hand sides and members); -1 likewise */
     int32_t n_dense_sn;               /* supernodes outside the tail factored by the blocked dense kernels */
     int32_t sn_groups, tail_groups;   /* panel groups of more than one panel in their plans / in the tail's */
-    int32_t pipe_tasks;               /* row tasks of the pipelined launch (0: bulk mode only) */
+    int32_t pipe_tasks;               /* tasks of the chain launches (row updates and supernode block LUs;
+                                         0: bulk mode only) */
     int32_t chain_levels;             /* forward + backward solve levels solved inside chains (solve_chain) */
     double sym_ms;                    /* wall time of the symbolic factorisation, supernodes and level sets in
                                          hylu_analyze (host or GPU, transfers included) */

@@ -96,9 +96,22 @@ struct LevelTasks {
     std::vector<int32_t> tiles;
     std::vector<int64_t> rrange;          // per entry of rows: its first and one-past-last source
     int32_t tune_rows = 0, tune_sn = 0;  // when nonzero, every level uses this (autotuner trials)
-    int32_t pipe_level = 0;           // levels from here on run as one pipelined launch
-    int32_t pipe_maxW = 0, pipe_maxm = 0;
-    int32_t pipe_nt = 256, pipe_stage = 1024, pipe_cap = 4096;  // its launch shape
+    // pipeline mode: the levels with chain_lev[l] set run as chain launches
+    // (runs of consecutive narrow levels); chain_start[l]: the first launch
+    // of the run starting at level l, else -1
+    std::vector<char> chain_lev;
+    std::vector<int32_t> chain_start;
+    struct Chain {
+        int32_t l0, l1;               // its levels
+        int64_t t0, t1;               // its nodes in ctask
+        int32_t nw, cap;              // wavefronts of the chain workgroup, widest row kept in LDS
+    };
+    std::vector<Chain> chains;
+    // the launches' tasks in order: a row (>= 0) or the block LU of supernode
+    // v (-(v + 1)); the bulk staging size of their level
+    std::vector<int32_t> ctask, ctask_sthr;
+    std::vector<int32_t> chain_of, chain_idx; // per node: its chain launch (-1: none), the task completing it there
+    std::vector<int64_t> lvrows;              // per chain level: the rows a bulk launch of it would take
     std::vector<int32_t> node_level;  // execution level of every node
 };
 
@@ -157,7 +170,7 @@ struct hylu_handle_s {
     int64_t* d_rrange = nullptr;
     int32_t* d_lev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     TailView TV{};
-    PipeCtl PC{};
+    int32_t *d_ctask = nullptr, *d_csthr = nullptr;   // the chain launches' nodes and staging sizes
     // large supernodes outside the tail, factored by the blocked dense kernels
     struct DenseSn {
         int32_t v, level;
@@ -174,7 +187,6 @@ struct hylu_handle_s {
     void* d_tinv = nullptr;                 // inverses of their diagonal blocks (L and U, 64 x 64 each)
     double tail_flops = 0.0;
     int32_t tail_groups = 0, sn_groups = 0;  // panel groups (of more than one panel) of the tail / the large supernodes
-    int32_t pipe_grid = 0;                  // persistent workgroups of the pipelined launch (resident at once)
     std::vector<DenseSn> dsn;
     // the large supernodes of a level whose launches are shared: per level the
     // steps (panels of all of them, then their TRSMs, then their GEMMs, panel by
@@ -246,7 +258,7 @@ struct hylu_handle_s {
     std::vector<double> lvl_idx;
     std::vector<double> tile_bytes, tile_idx, tile_flops;
     std::vector<double> inv_bytes, inv_flops;
-    double pipe_snlu_bytes = 0.0, pipe_snlu_flops = 0.0;  // block LUs inside the pipelined launch (value entries)
+    std::vector<double> chain_snlu_bytes, chain_snlu_flops;  // per chain launch: its block LUs (value entries)
     // one right-hand side: exact factor entries consumed by the L solve and
     // the U solve of the rows before the dense tail and by the tail's rows
     // (both solves), each with the count of those in standalone rows
@@ -472,6 +484,15 @@ constexpr int32_t kLsolveSnMin = 8;
 // a run of at least kChainMin solve levels of at most kChainNodes nodes is
 // solved by one workgroup in one launch
 constexpr int32_t kChainMin = 3, kChainNodes = 64;
+// pipeline mode: nodes per chain launch (one LDS flag each), staging values
+// per wavefront (at least the largest supernode with a block inverse), polls
+// before a wait gives up (tens of milliseconds, far beyond any real wait), and
+// the largest supernode a chain wavefront factors
+constexpr int32_t kChainTasksMax = 1024;
+constexpr int32_t kChainSw = kInvMax;
+constexpr int32_t kChainSpin = 1 << 21;
+constexpr int32_t kChainSnMax = 64;
+constexpr int32_t kChainRunMin = 3;   // shortest run of narrow levels taken by chain launches
 // The launch sequence of a view: groups of up to kGroup panels (left-looking
 // inside the group, one trailing update per group).  With the tail's masks M
 // every GEMM gets the list of its tiles that have a nonzero product, each with
@@ -855,7 +876,25 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
                                    h->d_pert, st));
     const LevelTasks& T = h->ft;
     int32_t nl = (int32_t)T.maxW.size();
-    for (int32_t l = 0; l < T.pipe_level; l++) {
+    for (int32_t l = 0; l < nl; l++) {
+        if (!T.chain_lev.empty() && T.chain_lev[l]) {
+            // pipeline mode over the run of narrow levels from l: its chain launches
+            if (T.chain_start[l] < 0) return HYLU_ERR_INTERNAL;
+            size_t c = (size_t)T.chain_start[l];
+            int32_t lend = l;
+            for (; c < T.chains.size() && T.chains[c].l0 == lend; c++) {
+                const LevelTasks::Chain& ch = T.chains[c];
+                lend = ch.l1;
+                double by = h->chain_snlu_bytes[c] * es, fl = h->chain_snlu_flops[c];
+                for (int32_t q = ch.l0; q < ch.l1; q++) { by += h->lvl_bytes[q] * es + h->lvl_idx[q]; fl += h->lvl_flops[q]; }
+                LAUNCH(C_PIPE, by, fl,
+                       launch_factor_chain(h->fp32, h->D, h->vals, h->d_ctask + ch.t0, h->d_csthr + ch.t0,
+                                           (int32_t)(ch.t1 - ch.t0), ch.nw, ch.cap, kChainSw, h->tau, h->d_pert,
+                                           search ? 1 : 0, h->d_inv_off, kChainSpin, st));
+            }
+            l = lend - 1;
+            continue;
+        }
         int64_t r0 = T.row_ptr[l], r1 = T.row_ptr[l + 1];
         LAUNCH(C_ROWS, h->lvl_bytes[l] * es + h->lvl_idx[l], h->lvl_flops[l],
                launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, h->d_rrange + 2 * r0, (int32_t)(r1 - r0),
@@ -886,19 +925,6 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
                    launch_sn_inverse(h->fp32, h->D, h->vals, h->d_inv_nodes + h->inv_ptr[l],
                                      (int32_t)(h->inv_ptr[l + 1] - h->inv_ptr[l]), h->inv_maxm[l], h->d_inv_off,
                                      h->d_uinv, st));
-    }
-    if (T.pipe_level < nl) {
-        // pipeline mode over the remaining levels
-        double by = 0, fl = 0;
-        for (int32_t l = T.pipe_level; l < nl; l++) { by += h->lvl_bytes[l] * es + h->lvl_idx[l]; fl += h->lvl_flops[l]; }
-        by += h->pipe_snlu_bytes * es;
-        fl += h->pipe_snlu_flops;
-        const int64_t r0 = T.row_ptr[T.pipe_level], r1 = T.row_ptr[nl];
-        HIPCHK(launch_pipe_reset(h->PC, h->lay.nnodes, st));
-        LAUNCH(C_PIPE, by, fl,
-               launch_factor_pipe(h->fp32, h->D, h->PC, h->vals, h->d_rows + r0, (int32_t)(r1 - r0), T.pipe_nt,
-                                  T.pipe_stage, T.pipe_cap, T.pipe_maxm, h->pipe_grid, h->tau, h->d_pert,
-                                  search ? 1 : 0, st));
     }
     // dense tail: blocked right-looking LU, one row panel at a time, then the
     // inverses of the solve panels' diagonal blocks
@@ -1070,11 +1096,12 @@ void trim_graphs(Map& m)
     m.clear();
 }
 
-// the pipelined launch waits on source node s when s is factored inside it
-// (and outside the dense tail, which publishes nothing)
-inline int32_t pipe_source(const LevelTasks& T, const Layout& L, int32_t s)
+// a chain node v waits on source node s when s is a node of the same chain
+// launch: the flag index of s there, else -1 (complete before the launch)
+inline int32_t chain_source(const LevelTasks& T, int32_t v, int32_t s)
 {
-    return (T.node_level[s] >= T.pipe_level && s < L.tail_node0) ? s : -1;
+    if (T.chain_of.empty() || T.chain_of[v] < 0 || T.chain_of[s] != T.chain_of[v]) return -1;
+    return T.chain_idx[s];
 }
 
 // device tables of the layout, uploaded on the first factorisation so the
@@ -1088,15 +1115,6 @@ hylu_status upload_device(hylu_handle h)
     const int32_t n = h->n;
     try {
         HIPCHK(hipGetDevice(&h->device));
-        {
-            // persistent workgroups of the pipelined launch: as many as are resident at once
-            int cus = 0;
-            HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
-            const size_t es = h->fp32 ? 4 : 8;
-            const size_t need = factor_rows_lds(h->fp32, T.pipe_stage, T.pipe_cap) + (size_t)T.pipe_nt * (es + 4) + 64;
-            const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(need, 1)));
-            h->pipe_grid = std::max(1, cus) * std::min(per_cu, 2048 / T.pipe_nt);
-        }
         HIPCHK(scratch_setup(h->device));
         if (!h->h_norms_fixed) {
             const size_t nseg = h->member_row_off.size() - 1;
@@ -1119,7 +1137,7 @@ hylu_status upload_device(hylu_handle h)
                 d.ws = L.W[s] - L.lw[s] - L.m[s];
                 d.lp = L.elpos[e];
                 d.r0s = L.r0[s];
-                d.srcp = pipe_source(T, L, s);
+                d.srcp = chain_source(T, v, s);
                 d.ioff = h->inv_off[s];
             }
         std::vector<double> asr(h->nnz), asc(h->nnz);
@@ -1220,21 +1238,13 @@ hylu_status upload_device(hylu_handle h)
                 for (int64_t i = h->member_row_off[k]; i < h->member_row_off[k + 1]; i++) seg[i] = (int32_t)k;
             UP(h->d_seg, seg);
         }
-        {
-            int32_t *ctl, *done, *rdone;
-            std::vector<int32_t> z2(2, 0), zn(std::max(L.nnodes, 1), 0);
-            UP(ctl, z2); UP(done, zn); UP(rdone, zn);
-            h->PC = PipeCtl();
-            h->PC.ctl = ctl; h->PC.done = done; h->PC.rows_done = rdone;
-            // about a second of polling before a wait gives up (the launch
-            // then drains and the factorisation reports a device error)
-            h->PC.spin_limit = 1 << 20;
-        }
+        UP(h->d_ctask, T.ctask);
+        UP(h->d_csthr, T.ctask_sthr);
+        // [0]: perturbed pivots; [1]: a chain wait gave up (device error)
         int32_t* pert;
         std::vector<int32_t> one(2, 0);
         UP(pert, one);
         h->d_pert = pert;
-        h->PC.err = pert + 1;
         h->vals = dalloc(h, (size_t)std::max<int64_t>(L.nvals, 1) * (h->fp32 ? 4 : 8));
         if (!h->vals) return HYLU_ERR_OOM;
         h->uploaded = true;
@@ -1299,43 +1309,79 @@ hylu_status order_matrix(const Csr& A, const hylu_options& opt, std::vector<int3
     return HYLU_OK;
 }
 
-// everything after the permutations and scalings: B = R A C, symbolic
-// factorisation, supernodes, levels, dense tail, panel layout, task lists
-// Host emulation of the pipelined launch's protocol over the tables the
-// device reads: tasks in ticket order, each waiting on the source nodes of
-// its source range that are factored in the launch, then publishing by the
-// kernel's rule (a standalone row outside the tail when done, a supernode
-// when its last row is done; tail rows publish nothing).  Every wait must be
-// on a node already published by earlier tickets: then the launch cannot
-// deadlock (the lowest unfinished ticket always has its sources complete, and
-// tickets are only taken by running workgroups).  Also checks that every row
-// of the region is one task with its whole source list.
-hylu_status check_pipeline(hylu_handle h)
+// The chain launches of pipeline mode, checked on the host against the rule
+// the device relies on: each launch covers consecutive chain levels, the
+// launches take the chain levels in order, every node of a chain level is the
+// node of exactly one launch, in level order; a chain node only takes sources
+// that are complete before its launch (lower levels, not in a later launch)
+// or nodes of its own launch with a lower index.  Then no wait can deadlock:
+// the lowest unfinished node of a launch always has its sources, and its
+// wavefront (which takes its nodes in increasing index) is working on it.
+hylu_status check_chains(hylu_handle h)
 {
     const LevelTasks& T = h->ft;
     const Layout& L = h->lay;
     const Nodes& nd = h->nodes;
     const int32_t nl = (int32_t)T.maxW.size();
-    if (T.pipe_level >= nl) return HYLU_OK;
-    std::vector<char> done(L.nnodes, 0), seen(h->n, 0);
-    std::vector<int32_t> rows_done(L.nnodes, 0);
-    for (int64_t t = T.row_ptr[T.pipe_level]; t < T.row_ptr[nl]; t++) {
-        const int32_t i = T.rows[t], v = nd.of_row[i];
-        if (seen[i] || T.rrange[2 * t] != L.eptr[v] || T.rrange[2 * t + 1] != L.eptr[v + 1]) return HYLU_ERR_INTERNAL;
-        seen[i] = 1;
-        if (L.m[v] == 1 || L.eptr[v + 1] > L.eptr[v])
+    if (T.chains.empty()) return T.ctask.empty() ? HYLU_OK : HYLU_ERR_INTERNAL;
+    if ((int32_t)T.chain_lev.size() != nl || (int32_t)T.chain_start.size() != nl) return HYLU_ERR_INTERNAL;
+    std::vector<char> seen(L.nnodes, 0);
+    std::vector<char> covered(nl, 0);
+    int64_t tnext = 0;
+    int32_t lprev = 0;
+    for (size_t c = 0; c < T.chains.size(); c++) {
+        const LevelTasks::Chain& ch = T.chains[c];
+        if (ch.l0 < lprev || ch.l1 <= ch.l0 || ch.l1 > nl || ch.t0 != tnext || ch.t1 <= ch.t0 ||
+            ch.t1 - ch.t0 > kChainTasksMax)
+            return HYLU_ERR_INTERNAL;
+        const bool first = c == 0 || T.chains[c - 1].l1 != ch.l0;
+        if (first != (T.chain_start[ch.l0] == (int32_t)c)) return HYLU_ERR_INTERNAL;
+        for (int32_t l = ch.l0; l < ch.l1; l++) {
+            if (!T.chain_lev[l] || covered[l]) return HYLU_ERR_INTERNAL;
+            covered[l] = 1;
+        }
+        int32_t prev_level = ch.l0;
+        for (int64_t t = ch.t0; t < ch.t1; t++) {
+            const int32_t x = T.ctask[t];
+            const int64_t ti = t - ch.t0;
+            const bool lu = x < 0;
+            const int32_t v = lu ? -x - 1 : nd.of_row[x];
+            if (v < 0 || v >= L.nnodes) return HYLU_ERR_INTERNAL;
+            const int32_t lv = T.node_level[v];
+            if (seen[v] || lv < prev_level || lv >= ch.l1 || v >= L.tail_node0 || L.m[v] > kChainSnMax ||
+                T.chain_of[v] != (int32_t)c)
+                return HYLU_ERR_INTERNAL;
+            prev_level = lv;
+            const bool last = lu || L.m[v] == 1;
+            if ((T.chain_idx[v] == ti) != last || (lu && L.m[v] < 2)) return HYLU_ERR_INTERNAL;
+            if (last) seen[v] = 1;
+            if (lu) {
+                // its row tasks just before it, in order (when it has sources)
+                if (L.eptr[v + 1] > L.eptr[v])
+                    for (int32_t a = 0; a < L.m[v]; a++) {
+                        const int64_t q = t - L.m[v] + a;
+                        if (q < ch.t0 || T.ctask[q] != L.r0[v] + a) return HYLU_ERR_INTERNAL;
+                    }
+                continue;
+            }
             for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
-                const int32_t s = pipe_source(T, L, L.esrc[e]);
-                if (s >= 0 && !done[s]) {
-                    std::fprintf(stderr, "hylu: pipelined schedule: row %d waits on node %d before it is published\n", i, s);
+                const int32_t s = L.esrc[e];
+                const bool before = T.node_level[s] < ch.l0 && T.chain_of[s] < (int32_t)c;
+                const bool earlier = T.chain_of[s] == (int32_t)c && T.chain_idx[s] < ti;
+                if (!before && !earlier) {
+                    std::fprintf(stderr, "hylu: pipelined schedule: row %d takes node %d before it is complete\n", x, s);
                     return HYLU_ERR_INTERNAL;
                 }
             }
-        if (v >= L.tail_node0) continue;
-        if (L.m[v] == 1 || ++rows_done[v] == L.m[v]) done[v] = 1;
+        }
+        lprev = ch.l1;
+        tnext = ch.t1;
     }
+    if (tnext != (int64_t)T.ctask.size()) return HYLU_ERR_INTERNAL;
+    for (int32_t l = 0; l < nl; l++)
+        if (T.chain_lev[l] && !covered[l]) return HYLU_ERR_INTERNAL;
     for (int32_t v = 0; v < L.nnodes; v++)
-        if (T.node_level[v] >= T.pipe_level && v < L.tail_node0 && !done[v]) return HYLU_ERR_INTERNAL;
+        if (T.chain_lev[T.node_level[v]] && !seen[v]) return HYLU_ERR_INTERNAL;
     return HYLU_OK;
 }
 
@@ -1475,18 +1521,33 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     }
     int32_t nl = (int32_t)lvnodes.size();
     std::vector<std::vector<std::array<int64_t, 3>>> lvpieces(nl);   // per level: (row, first, end source)
-    // pipelined mode (Sec. 2.2.1): the levels from the first one after which
-    // every level has at most pipeline_rows rows, and the deferred final
-    // level, run as one persistent launch whose rows wait per source node
-    // instead of per level
-    int32_t pipe_level = nl;
+    // pipeline mode (Sec. 2.2.1): every run of at least kChainRunMin
+    // consecutive levels (before the deferred final one, after level 0) of at
+    // most pipeline_rows rows, whose nodes are standalone rows or supernodes of
+    // at most kChainSnMax rows that no blocked or tile kernel takes, runs as
+    // chain launches; every other level stays a bulk launch
+    std::vector<char> chain_lev(nl, 0);
     if (opt.pipeline_rows > 0 && nl > 0) {
-        const bool has_final = !late_nodes.empty();
-        const int32_t nmain = has_final ? nl - 1 : nl;
-        auto rows_of = [&](int32_t l) { int64_t r = 0; for (int32_t v : lvnodes[l]) r += L.m[v]; return r; };
-        int32_t l = nmain;
-        while (l > 0 && rows_of(l - 1) <= opt.pipeline_rows) l--;
-        if (l < nmain || has_final) pipe_level = l;
+        const int32_t nmain = late_nodes.empty() ? nl : nl - 1;
+        const int32_t big_ = opt.sn_dense > 0 ? opt.sn_dense : std::numeric_limits<int32_t>::max();
+        const int32_t tile_ = opt.sn_tile > 0 ? opt.sn_tile : std::numeric_limits<int32_t>::max();
+        const int64_t maxrows = std::min<int64_t>(opt.pipeline_rows, kChainTasksMax / 2);   // tasks <= 2 rows
+        auto ok = [&](int32_t l) {
+            int64_t r = 0;
+            for (int32_t v : lvnodes[l]) {
+                r += L.m[v];
+                if (v >= L.tail_node0 || L.m[v] > kChainSnMax) return false;
+                if (nd.is_sn[v] && (L.m[v] >= big_ || L.m[v] >= tile_)) return false;
+            }
+            return r <= maxrows;
+        };
+        for (int32_t l = 1; l < nmain;) {
+            int32_t e = l;
+            while (e < nmain && ok(e)) e++;
+            if (e - l >= kChainRunMin)
+                for (int32_t q = l; q < e; q++) chain_lev[q] = 1;
+            l = std::max(e, l + 1);
+        }
     }
     // deferred standalone rows and tail rows join the launches of the narrow
     // levels (fewer than kSideNarrowRows rows) once their sources are
@@ -1494,7 +1555,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     // row is estimated to take at least as long (sources applied one after
     // the other, plus the update volume), so the level does not get longer.
     // The rest stay in the final level.
-    if (opt.side_rows && !late_nodes.empty() && pipe_level == nl) {
+    if (opt.side_rows && !late_nodes.empty()) {
         const int32_t nmain = nl - 1;
         auto cost = [&](int32_t v) {
             double c = 0;
@@ -1509,6 +1570,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         for (int32_t l = 0; l < nmain; l++)
             for (int32_t v : lvnodes[l]) { nrow[l] += L.m[v]; lmax[l] = std::max(lmax[l], cost(v)); }
         for (int32_t l = 0; l < nmain; l++) room[l] = nrow[l] < kSideNarrowRows ? kSideNarrowRows - nrow[l] : 0;
+        for (int32_t l = 0; l < nmain; l++) if (chain_lev[l]) room[l] = 0;     // not into chain launches
         std::vector<char> moved(L.nnodes, 0);
         std::vector<std::pair<int32_t, int32_t>> order(late_nodes);
         std::sort(order.begin(), order.end());
@@ -1574,20 +1636,14 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     T.tile_ptr.assign(1, 0);
     T.rrange.clear();
     h->pert_rows.clear();
-    T.pipe_maxW = T.pipe_maxm = 0;
+    T.lvrows.assign(nl, 0);
     for (int32_t l = 0; l < nl; l++) {
         int32_t mw = 0, mm = 0;
         for (int32_t v : lvnodes[l]) {
-            if (l >= pipe_level) {
-                // pipelined: every row is a task (its whole source list); the
-                // supernode's block LU follows its last row inside the launch
-                for (int32_t r = L.r0[v]; r < L.r0[v] + L.m[v]; r++) {
-                    T.rows.push_back(r);
-                    T.rrange.push_back(L.eptr[v]);
-                    T.rrange.push_back(L.eptr[v + 1]);
-                }
-                mw = std::max(mw, L.W[v]);
-                if (nd.is_sn[v] && v < L.tail_node0) T.pipe_maxm = std::max(T.pipe_maxm, L.m[v]);
+            if (chain_lev[l]) {
+                // a node of a chain launch: its rows and block LU there; the
+                // level's width and rows as a bulk launch would have them
+                if (L.eptr[v + 1] > L.eptr[v]) { mw = std::max(mw, L.W[v]); T.lvrows[l] += L.m[v]; }
                 continue;
             }
             if (L.eptr[v + 1] == L.eptr[v]) {
@@ -1637,7 +1693,6 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         T.maxW.push_back(mw);
         T.maxm.push_back(mm);
         h->max_sn = std::max(h->max_sn, mm);
-        if (l >= pipe_level) T.pipe_maxW = std::max(T.pipe_maxW, mw);
     }
     // HYLU_LOG=2: the row tasks of every factor level (3: and each row of the last one)
     if (const char* lg = std::getenv("HYLU_LOG"); lg && std::atoi(lg) >= 2) {
@@ -1694,7 +1749,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     T.row_stage.assign(nl, kStageSmall);
     T.row_cap.assign(nl, kRowCapSmall);
     for (int32_t l = 0; l < nl; l++) {
-        if (T.row_ptr[l + 1] - T.row_ptr[l] > kSideNarrowRows) continue;
+        if (T.row_ptr[l + 1] - T.row_ptr[l] + T.lvrows[l] > kSideNarrowRows) continue;
         const int32_t cap = std::min(std::max(T.maxW[l], kRowCapSmall), kRowCapBig);
         int32_t stage = kStageMax;
         while (stage > kStageSmall && factor_rows_lds(h->fp32, stage, cap) > kLdsMax) stage -= 256;
@@ -1717,7 +1772,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     h->inv_maxm.clear();
     for (int32_t l = 0; l < nl; l++) {
         int32_t mm = 0;
-        if (opt.sn_inverse && l < pipe_level)
+        if (opt.sn_inverse)
             for (int32_t v : lvnodes[l]) {
                 if (!nd.is_sn[v] || v >= L.tail_node0 || L.m[v] < 2 || L.m[v] > kInvMax) continue;
                 h->inv_off[v] = h->inv_total;
@@ -1777,15 +1832,68 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
             l = std::max(e, l + 1);
         }
     }
-    T.pipe_level = pipe_level;
-    if (pipe_level < nl) {
-        // one launch shape for every task: sixteen wavefronts and wide LDS
-        // buffers when long rows are in the region, else four
-        const bool wide = T.pipe_maxW > 1024;
-        T.pipe_nt = wide ? 1024 : 256;
-        T.pipe_stage = wide ? 4096 : kStageSmall;
-        T.pipe_cap = std::max(1, std::min(T.pipe_maxW, wide ? 8192 : kRowCapSmall));
-        const hylu_status sp = check_pipeline(h);
+    T.chain_lev = chain_lev;
+    T.chain_start.assign(nl, -1);
+    T.chains.clear();
+    T.ctask.clear();
+    T.ctask_sthr.clear();
+    T.chain_of.assign(L.nnodes, -1);
+    T.chain_idx.assign(L.nnodes, -1);
+    for (int32_t l = 0; l < nl;) {
+        if (!chain_lev[l]) { l++; continue; }
+        // whole levels of the run, at most kChainTasksMax nodes per launch
+        if (l == 0 || !chain_lev[l - 1]) T.chain_start[l] = (int32_t)T.chains.size();
+        LevelTasks::Chain ch{};
+        ch.l0 = l;
+        ch.t0 = (int64_t)T.ctask.size();
+        int32_t maxw = 1;
+        auto ntasks = [&](int32_t q) {
+            int64_t k = 0;
+            for (int32_t v : lvnodes[q]) k += L.m[v] == 1 ? 1 : (L.eptr[v + 1] > L.eptr[v] ? L.m[v] : 0) + 1;
+            return k;
+        };
+        while (l < nl && chain_lev[l] && (int64_t)T.ctask.size() - ch.t0 + ntasks(l) <= kChainTasksMax) {
+            for (int32_t v : lvnodes[l]) {
+                T.chain_of[v] = (int32_t)T.chains.size();
+                // its rows' outside updates (a standalone row: always, for its
+                // pivot check), then a supernode's block LU
+                if (L.m[v] == 1 || L.eptr[v + 1] > L.eptr[v])
+                    for (int32_t r = L.r0[v]; r < L.r0[v] + L.m[v]; r++) {
+                        T.ctask.push_back(r);
+                        T.ctask_sthr.push_back(T.row_stage[l]);
+                    }
+                if (L.m[v] > 1) {
+                    T.ctask.push_back(-v - 1);
+                    T.ctask_sthr.push_back(T.row_stage[l]);
+                }
+                T.chain_idx[v] = (int32_t)((int64_t)T.ctask.size() - 1 - ch.t0);
+                maxw = std::max(maxw, L.W[v]);
+            }
+            l++;
+        }
+        if (l == ch.l0) return HYLU_ERR_INTERNAL;     // a level wider than a launch (excluded above)
+        ch.l1 = l;
+        ch.t1 = (int64_t)T.ctask.size();
+        // as many wavefronts as fit with every row of the launch in LDS, at
+        // least four (rows wider than their room then work in global memory)
+        const int32_t nt = (int32_t)(ch.t1 - ch.t0);
+        ch.nw = 0;
+        for (int32_t w : {kChainThreads / 64, 6, 4})
+            if (chain_lds(h->fp32, nt, w, maxw, kChainSw) <= kLdsMax) { ch.nw = w; ch.cap = maxw; break; }
+        if (ch.nw == 0) {
+            ch.nw = 4;
+            ch.cap = maxw;
+            while (ch.cap > 0 && chain_lds(h->fp32, nt, 4, ch.cap, kChainSw) > kLdsMax) ch.cap -= 64;
+            ch.cap = std::max(ch.cap, 0);
+        }
+        T.chains.push_back(ch);
+    }
+    if (const char* lg = std::getenv("HYLU_LOG"); lg && std::atoi(lg) >= 2)
+        for (const LevelTasks::Chain& ch : T.chains)
+            std::fprintf(stderr, "hylu: chain launch levels [%d, %d) tasks %lld wavefronts %d row cap %d\n", ch.l0, ch.l1,
+                         (long long)(ch.t1 - ch.t0), ch.nw, ch.cap);
+    {
+        const hylu_status sp = check_chains(h);
         if (sp != HYLU_OK) return sp;
     }
     // algorithmic traffic and flops of every row-kernel and tile launch, from
@@ -1872,15 +1980,18 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 h->lvl_flops[l] += fl;
             }
         }
-        // the block LUs inside the pipelined launch
-        h->pipe_snlu_bytes = h->pipe_snlu_flops = 0.0;
-        for (int32_t l = T.pipe_level; l < nl; l++)
-            for (int32_t v : lvnodes[l])
-                if (nd.is_sn[v] && v < L.tail_node0) {
-                    const double m = L.m[v], w = L.W[v] - L.lw[v] - L.m[v];
-                    h->pipe_snlu_bytes += 2.0 * m * (m + w);
-                    h->pipe_snlu_flops += 2.0 * m * m * m / 3.0 + m * m * w;
-                }
+        // the block LUs (and inverses) inside the chain launches
+        h->chain_snlu_bytes.assign(T.chains.size(), 0.0);
+        h->chain_snlu_flops.assign(T.chains.size(), 0.0);
+        for (size_t c = 0; c < T.chains.size(); c++)
+            for (int64_t t = T.chains[c].t0; t < T.chains[c].t1; t++) {
+                if (T.ctask[t] >= 0) continue;
+                const int32_t v = -T.ctask[t] - 1;
+                const double m = L.m[v], w = L.W[v] - L.lw[v] - L.m[v];
+                h->chain_snlu_bytes[c] += 2.0 * m * (m + w);
+                h->chain_snlu_flops[c] += 2.0 * m * m * m / 3.0 + m * m * w;
+                if (h->inv_off[v] >= 0) { h->chain_snlu_bytes[c] += 2.0 * m * m; h->chain_snlu_flops[c] += m * m * m / 3.0; }
+            }
         // the block inverses: read and write the m x m block, m^3 / 3 flops
         h->inv_bytes.assign(nl, 0.0);
         h->inv_flops.assign(nl, 0.0);
@@ -1955,16 +2066,6 @@ hylu_status measure_residual(hylu_handle h, const SolveWs& w, const int64_t* rp,
         }
     }
     return HYLU_OK;
-}
-
-// The pipelined launch (Sec. 2.2.1) is switched off on the device: its
-// schedule is built and checked at analysis, but a factorisation that would
-// run it is refused (its launch did not finish on the device twice)
-hylu_status pipelined_refused(hylu_handle h)
-{
-    if (h->ft.pipe_level >= (int32_t)h->ft.maxW.size()) return HYLU_OK;
-    std::fprintf(stderr, "hylu: the pipelined launch (pipeline_rows > 0) is switched off on the device\n");
-    return HYLU_ERR_ARG;
 }
 
 // forward-backward substitution with refinement on work vectors w; the base
@@ -2296,7 +2397,6 @@ hylu_status hylu_factorize(hylu_handle h, const double* d_val, void* stream)
     if (!h || !d_val) return HYLU_ERR_ARG;
     if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
     if (h->sticky_error) return HYLU_ERR_DEVICE;
-    if (pipelined_refused(h) != HYLU_OK) return HYLU_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (!h->uploaded) {
         hylu_status su = upload_device(h);
@@ -2319,7 +2419,6 @@ hylu_status hylu_refactor(hylu_handle h, const double* d_val, void* stream)
     if (!h->analyzed) return HYLU_ERR_NOT_ANALYZED;
     if (!h->factorized) return HYLU_ERR_NOT_FACTORIZED;
     if (h->sticky_error) return HYLU_ERR_DEVICE;
-    if (pipelined_refused(h) != HYLU_OK) return HYLU_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (h->refac_graphs.find(d_val) == h->refac_graphs.end()) trim_graphs(h->refac_graphs);
     auto it = h->refac_graphs.find(d_val);
@@ -2462,8 +2561,7 @@ hylu_status hylu_get_info(hylu_handle h, hylu_info* o)
     for (int g : {4, 1})
         for (size_t l = 0; l < h->chain_end[g].size(); l++)
             if (h->chain_end[g][l] > (int32_t)l) o->chain_levels += h->chain_end[g][l] - (int32_t)l;
-    o->pipe_tasks = h->ft.pipe_level < (int32_t)h->ft.maxW.size()
-                        ? (int32_t)(h->ft.row_ptr.back() - h->ft.row_ptr[h->ft.pipe_level]) : 0;
+    o->pipe_tasks = (int32_t)h->ft.ctask.size();
     o->sn_groups = h->sn_groups;
     o->tail_groups = h->tail_groups;
     o->sym_ms = h->sym_ms;
@@ -2512,8 +2610,13 @@ hylu_status hylu_autotune(hylu_handle h, const double* d_val, void* stream, int3
     std::vector<std::array<double, kTrials>> trow(nl), tsn(nl);
     for (auto& a : trow) a.fill(std::numeric_limits<double>::infinity());
     for (auto& a : tsn) a.fill(std::numeric_limits<double>::infinity());
-    std::vector<int32_t> sn_levels;
-    for (int32_t l = 0; l < T.pipe_level; l++) if (T.sn_ptr[l + 1] > T.sn_ptr[l]) sn_levels.push_back(l);
+    // the levels with a row launch (not the chain launches of pipeline mode)
+    std::vector<int32_t> row_levels, sn_levels;
+    for (int32_t l = 0; l < nl; l++)
+        if (T.chain_lev.empty() || !T.chain_lev[l]) {
+            row_levels.push_back(l);
+            if (T.sn_ptr[l + 1] > T.sn_ptr[l]) sn_levels.push_back(l);
+        }
     reps = std::max(reps, 1);
     hylu_status s = HYLU_OK;
     for (int32_t rep = 0; rep < reps && s == HYLU_OK; rep++)
@@ -2535,21 +2638,21 @@ hylu_status hylu_autotune(hylu_handle h, const double* d_val, void* stream, int3
                 if (r.cls == C_ROWS) lr++;
                 else if (r.cls == C_SNLU) ls++;
             }
-            if (lr != T.pipe_level || ls != sn_levels.size()) { s = HYLU_ERR_INTERNAL; break; }
+            if ((size_t)lr != row_levels.size() || ls != sn_levels.size()) { s = HYLU_ERR_INTERNAL; break; }
             lr = 0;
             ls = 0;
             for (const Profiler::Rec& r : h->prof.recs) {
                 float ms = 0.f;
                 if (r.cls != C_ROWS && r.cls != C_SNLU) continue;
                 if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) { s = HYLU_ERR_DEVICE; break; }
-                if (r.cls == C_ROWS) { trow[lr][t] = std::min(trow[lr][t], (double)ms); lr++; }
+                if (r.cls == C_ROWS) { trow[row_levels[lr]][t] = std::min(trow[row_levels[lr]][t], (double)ms); lr++; }
                 else { tsn[sn_levels[ls]][t] = std::min(tsn[sn_levels[ls]][t], (double)ms); ls++; }
             }
         }
     T.tune_rows = T.tune_sn = 0;
     if (s != HYLU_OK) { h->sticky_error = true; return s; }
     double before = 0.0, after = 0.0;
-    for (int32_t l = 0; l < T.pipe_level; l++) {
+    for (int32_t l : row_levels) {
         // the built-in shape: 1024 threads for long rows of narrow levels, 256
         // for other long rows, 64 otherwise
         const bool narrow = T.row_ptr[l + 1] - T.row_ptr[l] <= kSideNarrowRows;

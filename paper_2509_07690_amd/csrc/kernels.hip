@@ -39,6 +39,21 @@ template <typename T> __device__ __forceinline__ T pmag(T x)
     return y == y ? y : static_cast<T>(__builtin_huge_valf());
 }
 
+// barrier policies of the row-update device functions: a whole workgroup
+// works on one task (bulk mode), or one wavefront does (the pipelined launch,
+// whose other wavefronts run other tasks).  The wavefront barrier orders its
+// lanes' LDS and global accesses as a block barrier does (same fences, no
+// s_barrier).
+struct BlockSync { static __device__ __forceinline__ void bar() { __syncthreads(); } };
+struct WaveSync {
+    static __device__ __forceinline__ void bar()
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+};
+
 constexpr int kStage = 1024;   // staged source entries per batch (values + relative indices), default
 constexpr int kSnSolveRows = 64;   // largest supernode of the four-wavefront forward solve
 
@@ -98,9 +113,12 @@ __global__ void k_init_pivots(int32_t n, const int32_t* __restrict__ row_node, c
 // the update of the columns past the block.  The pivot order, and the block
 // when small, are first copied to LDS; the update reads the source rows with
 // independent loads (unrolled over source rows).
-template <typename T, int NT>
+// stage: LDS room of sbuf / ibuf; sthr: the bulk launch's staging size,
+// which decides between the inverse and the substitution (the arithmetic must
+// not depend on where a task runs)
+template <typename T, int NT, class Sync = BlockSync>
 __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ vals, T* xs, const EdgeDesc& ed,
-                                    int tid, T* sbuf, int32_t* ibuf, int stage)
+                                    int tid, T* sbuf, int32_t* ibuf, int stage, int sthr)
 {
     const T* Us = vals + ed.uoff;
     const int32_t* rl = D.rel + ed.roff;
@@ -108,13 +126,13 @@ __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ va
     const bool pl_lds = ms <= stage;
     const int32_t* pls = pl_lds ? ibuf : D.pl + ed.r0s;
     if (pl_lds) for (int b = tid; b < ms; b += NT) ibuf[b] = D.pl[ed.r0s + b];
-    if (ed.ioff >= 0 && ms <= stage) {
+    if (ed.ioff >= 0 && ms <= sthr && ms <= stage) {
         // multipliers from the inverse: l_c = sum_{b <= c} x_p[b] Uinv[b][c],
         // every c at once (x_p staged in LDS first)
         const T* Ui = reinterpret_cast<const T*>(D.uinv) + ed.ioff;
-        __syncthreads();
+        Sync::bar();
         for (int b = tid; b < ms; b += NT) sbuf[b] = xs[lp + pls[b]];
-        __syncthreads();
+        Sync::bar();
         for (int c = tid; c < ms; c += NT) {
             T acc0 = T(0), acc1 = T(0);
             int b = 0;
@@ -136,23 +154,23 @@ __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ va
             if (b <= c) acc0 += sbuf[b] * Ui[(int64_t)b * ms + c];
             xs[lp + pls[c]] = acc0 + acc1;
         }
-        __syncthreads();
+        Sync::bar();
     } else {
     const bool blk_lds = ms * ms <= stage;
     if (blk_lds)
         for (int idx = tid; idx < ms * ms; idx += NT) sbuf[idx] = Us[(int64_t)(idx / ms) * Ws + idx % ms];
-    __syncthreads();
+    Sync::bar();
     for (int b = 0; b < ms; b++) {
         const int pb = pls[b];
         const T ub = blk_lds ? sbuf[b * ms + pb] : Us[(int64_t)b * Ws + pb];
         const T lb = xs[lp + pb] / ub;
-        __syncthreads();
+        Sync::bar();
         if (tid == 0) xs[lp + pb] = lb;
         for (int bb = b + 1 + tid; bb < ms; bb += NT) {
             const int pc = pls[bb];
             xs[lp + pc] -= lb * (blk_lds ? sbuf[b * ms + pc] : Us[(int64_t)b * Ws + pc]);
         }
-        __syncthreads();
+        Sync::bar();
     }
     }
     const T* Ut = Us + ms;
@@ -184,33 +202,7 @@ __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ va
         for (; b < ms; b++) acc0 += xs[lp + pls[b]] * Ut[(int64_t)b * Ws + j];
         xs[rj] -= acc0 + acc1;
     }
-    __syncthreads();
-}
-
-// wave 0 waits until every listed source node is complete in this epoch
-// (src < 0: nothing to wait for).  Bounded: after spin_limit polls the error
-// flag is set, and every wait (this one and all others) stops polling once
-// it is set, so the launch always drains; the results are then void and the
-// host reports a device error.
-__device__ __forceinline__ void wait_sources(const PipeCtl& P, int epoch, int src)
-{
-    bool ok = src < 0 || __hip_atomic_load(P.done + src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
-    int it = 0;
-    while (!__all(ok)) {
-        if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        if (++it > P.spin_limit) {
-            __hip_atomic_store(P.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-        if (!ok) ok = __hip_atomic_load(P.done + src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
-    }
-}
-
-// is source node src (< 0: outside the pipelined region) complete in this epoch?
-__device__ __forceinline__ bool source_ready(const PipeCtl& P, int epoch, int src)
-{
-    return src < 0 || __hip_atomic_load(P.done + src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+    Sync::bar();
 }
 
 // row updates of target row i by a block of NT threads.  Every source node (a
@@ -218,11 +210,10 @@ __device__ __forceinline__ bool source_ready(const PipeCtl& P, int epoch, int sr
 // ascending order.  Standalone sources are staged in batches in LDS (pivot,
 // the source's U values and their relative positions in the target), then
 // applied one after the other from LDS.  The row's accumulator sits in LDS
-// when it fits.  PIPE: sources factored in the pipelined region are waited for
-// before they are read.
-template <typename T, int NT, bool PIPE>
+// when it fits.
+template <typename T, int NT>
 __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_t lds_cap, T tau,
-                         int32_t* __restrict__ pert, unsigned char* smem_raw, const PipeCtl& PC, int epoch, int stage,
+                         int32_t* __restrict__ pert, unsigned char* smem_raw, int stage,
                          int64_t eb = -1, int64_t ee = -1)
 {
     T* sval = reinterpret_cast<T*>(smem_raw);                                   // stage
@@ -264,11 +255,9 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
             const int64_t my = e + lane;
             EdgeDesc ed;
             int cost = 0x3fffffff;
-            int src = -1;
             if (my < e1) {
                 ed = D.edges[my];
                 if (ed.ms == 1) cost = ed.ws + 1;
-                src = ed.srcp;
             }
             int pre = cost;
             for (int off = 1; off < 64; off <<= 1) {
@@ -276,16 +265,7 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
                 if (lane >= off) pre = (pre > 0x3fffffff - o) ? 0x3fffffff : pre + o;
             }
             const unsigned long long fits = __ballot(pre <= stage && my < e1);
-            int nb = (fits == ~0ull) ? 64 : __builtin_ctzll(~fits);
-            if (PIPE) {
-                // wait for the batch's first source only, then keep the
-                // prefix of sources already complete: the row applies what it
-                // can while later sources are still being factored
-                wait_sources(PC, epoch, lane == 0 ? src : -1);
-                const unsigned long long rdy = __ballot(lane == 0 || lane >= nb || source_ready(PC, epoch, src));
-                const int nr = (rdy == ~0ull) ? 64 : __builtin_ctzll(~rdy);
-                nb = nb < nr ? nb : nr;
-            }
+            const int nb = (fits == ~0ull) ? 64 : __builtin_ctzll(~fits);
             if (lane < nb) {
                 eoff[lane] = pre - cost;
                 elp[lane] = ed.lp;
@@ -299,13 +279,11 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
             if (nb > 0 && lane == nb - 1) { eoff[nb] = pre; s_total = pre; }
         }
         __syncthreads();
-        // the sources' values were published by other workgroups (pipelined mode)
-        if (PIPE) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int nb = s_nb, total = s_total;
         if (nb == 0) {
             // a supernode source (or an oversized standalone one)
             const EdgeDesc e0 = D.edges[e];
-            apply_source_direct<T, NT>(D, vals, xs, e0, tid, sval, sidx, stage);
+            apply_source_direct<T, NT>(D, vals, xs, e0, tid, sval, sidx, stage, stage);
             e += 1;
             continue;
         }
@@ -388,9 +366,8 @@ __global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if ((int)blockIdx.x >= nrows) return;
-    PipeCtl none{};
     const int64_t eb = ranges ? ranges[2 * blockIdx.x] : -1, ee = ranges ? ranges[2 * blockIdx.x + 1] : -1;
-    row_task<T, NT, false>(D, vals, rows[blockIdx.x], lds_cap, tau, pert, smem_raw, none, 0, stage, eb, ee);
+    row_task<T, NT>(D, vals, rows[blockIdx.x], lds_cap, tau, pert, smem_raw, stage, eb, ee);
 }
 
 // standalone rows without sources: their pivot is checked (and perturbed)
@@ -479,17 +456,16 @@ __global__ __launch_bounds__(256) void k_sn_inverse(DevLayout D, const T* __rest
 // column), perturbing small pivots, then eliminating the rows below.
 // ----------------------------------------------------------------------------
 
-template <typename T, int NT>
+template <typename T, int NT, class Sync = BlockSync>
 __device__ void snlu_node(const DevLayout& D, T* __restrict__ vals, int v, T tau, int32_t* __restrict__ pert,
-                          int search, T* lrow, uint8_t* taken, T* red_v, int* red_i, int* s_p)
+                          int search, T* lrow, uint8_t* taken, T* red_v, int* red_i, int* s_p, int tid)
 {
     const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
     const int wc = W - lw;                     // block + T columns
     T* P = vals + D.voff[v] + lw;              // row a, column c at P[a*W + c]
     int32_t* pl = D.pl + r0;
-    const int tid = threadIdx.x;
     for (int c = tid; c < m; c += NT) taken[c] = 0;
-    __syncthreads();
+    Sync::bar();
     for (int a = 0; a < m; a++) {
         T* Pa = P + (int64_t)a * W;
         int p;
@@ -502,13 +478,13 @@ __device__ void snlu_node(const DevLayout& D, T* __restrict__ vals, int v, T tau
                 if (x > best || (x == best && c < bi)) { best = x; bi = c; }
             }
             red_v[tid] = best; red_i[tid] = bi;
-            __syncthreads();
+            Sync::bar();
             for (int s2 = NT / 2; s2 > 0; s2 >>= 1) {
                 if (tid < s2) {
                     T x = red_v[tid + s2]; int xi = red_i[tid + s2];
                     if (x > red_v[tid] || (x == red_v[tid] && xi < red_i[tid])) { red_v[tid] = x; red_i[tid] = xi; }
                 }
-                __syncthreads();
+                Sync::bar();
             }
             p = red_i[0];
         } else {
@@ -525,7 +501,7 @@ __device__ void snlu_node(const DevLayout& D, T* __restrict__ vals, int v, T tau
             taken[p] = 1;
             *s_p = p;
         }
-        __syncthreads();
+        Sync::bar();
         p = *s_p;
         const T d = Pa[p];
         for (int r = a + 1 + tid; r < m; r += NT) {
@@ -534,25 +510,25 @@ __device__ void snlu_node(const DevLayout& D, T* __restrict__ vals, int v, T tau
             Pr[p] = l;
             lrow[r] = l;
         }
-        __syncthreads();
+        Sync::bar();
         for (int c = tid; c < wc; c += NT) {
             if (c < m && taken[c]) continue;
             const T u = Pa[c];
             for (int r = a + 1; r < m; r++) P[(int64_t)r * W + c] -= lrow[r] * u;
         }
-        __syncthreads();
+        Sync::bar();
     }
 }
 
 // inverse of node v's block in pivot order after its LU (the rule of
 // k_sn_inverse, the block read from its panel): thread j solves U_pp x = e_j
 template <typename T, int NT>
-__device__ void sn_inverse_node(const DevLayout& D, const T* __restrict__ vals, int v, T* __restrict__ X)
+__device__ void sn_inverse_node(const DevLayout& D, const T* __restrict__ vals, int v, T* __restrict__ X, int tid)
 {
     const int m = D.m[v], W = D.W[v], r0 = D.r0[v];
     const T* P = vals + D.voff[v] + D.lw[v];
     const int32_t* pl = D.pl + r0;
-    for (int j = threadIdx.x; j < m; j += NT) {
+    for (int j = tid; j < m; j += NT) {
         for (int i = j + 1; i < m; i++) X[(int64_t)i * m + j] = T(0);
         X[(int64_t)j * m + j] = T(1) / P[(int64_t)j * W + pl[j]];
         for (int i = j - 1; i >= 0; i--) {
@@ -580,78 +556,261 @@ __global__ __launch_bounds__(NT) void k_factor_snlu(DevLayout D, T* __restrict__
     const int m = D.m[v];
     T* lrow = reinterpret_cast<T*>(smem_raw);                       // m multipliers
     uint8_t* taken = smem_raw + sizeof(T) * (size_t)m;             // m flags
-    snlu_node<T, NT>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p);
+    snlu_node<T, NT>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p, threadIdx.x);
     if (inv_off && inv_off[v] >= 0) {
         __syncthreads();        // the block and its pivot order are complete
-        sn_inverse_node<T, NT>(D, vals, v, reinterpret_cast<T*>(const_cast<void*>(D.uinv)) + inv_off[v]);
+        sn_inverse_node<T, NT>(D, vals, v, reinterpret_cast<T*>(const_cast<void*>(D.uinv)) + inv_off[v], threadIdx.x);
     }
 }
 
-// pipeline mode (Sec. 2.2.1): persistent workgroups take row tasks in a
-// topological order from a ticket; a row waits only for the source nodes it is
-// about to read (per batch of sources, not per level).  A standalone row
-// outside the dense tail publishes its node when done; the workgroup that
-// finishes the last row of a supernode factors the supernode's block and then
-// publishes it; tail rows publish nothing (the tail is factored after the
-// launch).  Publishing: every thread's stores are released at agent scope
-// before the flag is written; readers acquire after their wait.
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_factor_pipe(DevLayout D, PipeCtl PC, T* __restrict__ vals,
-                                                    const int32_t* __restrict__ rows, int32_t nrows,
-                                                    int32_t lds_cap, int32_t stage, T tau, int32_t* __restrict__ pert,
-                                                    int32_t search)
+// ----------------------------------------------------------------------------
+// pipeline mode (Sec. 2.2.1): the narrow levels that follow the wide ones run
+// as one launch.  Workgroup 0 runs the chain: its wavefronts take the nodes of
+// those levels in (level, index) order, node t by wavefront t mod nw, and a
+// row waits for a source node of the launch only when it is about to apply
+// it, on a flag in LDS that the source's wavefront sets once that node is
+// complete (its stores released at workgroup scope first).  A row thus
+// applies the sources it already has while the nodes it still needs are being
+// factored, instead of waiting for their whole level.  Every wait is on a node
+// of lower index, so the lowest unfinished node always has its sources and
+// proceeds (every wavefront of a workgroup is resident).  A wait gives up
+// after `spin` polls, raising an error flag in LDS that ends every other wait
+// and a global one that the host reports: the launch always ends.  The other
+// workgroups run row tasks whose sources were complete before the launch, as
+// the bulk row kernel does.
+// ----------------------------------------------------------------------------
+
+struct ChainCtl {
+    int32_t* flag;      // LDS: per node of the chain, nonzero once complete
+    int32_t* err;       // LDS: a wait gave up
+    int32_t* gerr;      // global: the same, for the host
+    int32_t spin;
+};
+
+// the whole wavefront waits for chain node s (wave-uniform; < 0: nothing)
+__device__ __forceinline__ void chain_wait(const ChainCtl& C, int s)
+{
+    if (s < 0) return;
+    int it = 0;
+    while (__hip_atomic_load(C.flag + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+        if (__hip_atomic_load(C.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0) break;
+        if (++it > C.spin) {
+            __hip_atomic_store(C.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(C.gerr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// is chain node s (wave-uniform; < 0: outside the launch) complete?  A
+// positive answer is followed by an acquire, as after a wait
+__device__ __forceinline__ bool chain_ready(const ChainCtl& C, int s)
+{
+    if (s < 0) return true;
+    const bool r = __hip_atomic_load(C.flag + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
+    if (r) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return r;
+}
+
+// ordering of one wavefront's LDS accesses: its LDS instructions execute in
+// program order, so only the compiler must keep them in place (no wait on
+// loads in flight, which would stall the prefetch of the next source)
+__device__ __forceinline__ void wave_lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// target row i, sources [eb, ee), by one wavefront: the operations of
+// row_task, source by source in the same order with the same arithmetic (a
+// standalone source that the bulk launch stages, 1 + ws <= sthr, as
+// x_j - l u_j with its values read straight from global memory; any other
+// source through apply_source_direct).  The row sits in xsl (LDS) when
+// W <= cap.  While a standalone source is applied, the pivot and first 256
+// values of the next one are already being loaded when that source is
+// complete.
+template <typename T>
+__device__ void row_task_wave(const DevLayout& D, T* __restrict__ vals, int i, int64_t eb, int64_t ee, T* xsl,
+                              int cap, T* sbuf, int32_t* ibuf, int sw, int sthr, T tau, int32_t* __restrict__ pert,
+                              const ChainCtl& C, int lane)
+{
+    const int v = D.row_node[i];
+    const int W = D.W[v];
+    T* X = vals + D.voff[v] + (int64_t)(i - D.r0[v]) * W;
+    const bool in_lds = W <= cap;
+    T* xs = in_lds ? xsl : X;
+    if (in_lds) {
+        for (int j0 = lane; j0 < W; j0 += 8 * 64) {
+            T t[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) { const int j = j0 + u * 64; t[u] = j < W ? X[j] : T(0); }
+#pragma unroll
+            for (int u = 0; u < 8; u++) { const int j = j0 + u * 64; if (j < W) xs[j] = t[u]; }
+        }
+    }
+    WaveSync::bar();
+    bool have = false;                  // the current source's pivot and first chunk are loaded
+    T cpiv = T(0), cu[4];
+    int cix[4];
+    EdgeDesc ed;
+    if (eb < ee) ed = D.edges[eb];
+    for (int64_t e = eb; e < ee; e++) {
+        if (!have) chain_wait(C, ed.srcp);
+        if (ed.ms == 1 && ed.ws + 1 <= sthr) {
+            const T* U = vals + ed.uoff;          // pivot, then the T values
+            const int32_t* rl = D.rel + ed.roff;
+            const int ws = ed.ws, lp = ed.lp;
+            if (!have) {
+                cpiv = U[0];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int q = lane + 64 * k;
+                    cu[k] = q < ws ? U[1 + q] : T(0);
+                    cix[k] = q < ws ? rl[q] : 0;
+                }
+            }
+            // the next source: its descriptor, and its first values when it
+            // is a staged standalone source that is complete already
+            have = false;
+            T npiv = T(0), nu[4];
+            int nix[4];
+            if (e + 1 < ee) {
+                const EdgeDesc nx = D.edges[e + 1];
+                if (nx.ms == 1 && nx.ws + 1 <= sthr && chain_ready(C, nx.srcp)) {
+                    const T* Un = vals + nx.uoff;
+                    const int32_t* rn = D.rel + nx.roff;
+                    npiv = Un[0];
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        const int q = lane + 64 * k;
+                        nu[k] = q < nx.ws ? Un[1 + q] : T(0);
+                        nix[k] = q < nx.ws ? rn[q] : 0;
+                    }
+                    have = true;
+                }
+                ed = nx;
+            }
+            const T l = xs[lp] / cpiv;
+            {
+                T xv[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) xv[k] = lane + 64 * k < ws ? xs[cix[k]] : T(0);
+#pragma unroll
+                for (int k = 0; k < 4; k++)
+                    if (lane + 64 * k < ws) xs[cix[k]] = xv[k] - l * cu[k];
+            }
+            for (int q0 = lane + 4 * 64; q0 < ws; q0 += 4 * 64) {
+                T u[4], xv[4];
+                int ix[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int q = q0 + 64 * k;
+                    u[k] = q < ws ? U[1 + q] : T(0);
+                    ix[k] = q < ws ? rl[q] : 0;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; k++) xv[k] = q0 + 64 * k < ws ? xs[ix[k]] : T(0);
+#pragma unroll
+                for (int k = 0; k < 4; k++)
+                    if (q0 + 64 * k < ws) xs[ix[k]] = xv[k] - l * u[k];
+            }
+            if (in_lds) {
+                wave_lds_order();
+                if (lane == 0) xs[lp] = l;
+                wave_lds_order();
+            } else {
+                WaveSync::bar();
+                if (lane == 0) xs[lp] = l;
+                WaveSync::bar();
+            }
+            if (have) {
+                cpiv = npiv;
+#pragma unroll
+                for (int k = 0; k < 4; k++) { cu[k] = nu[k]; cix[k] = nix[k]; }
+            }
+        } else {
+            apply_source_direct<T, 64, WaveSync>(D, vals, xs, ed, lane, sbuf, ibuf, sw, sthr);
+            have = false;
+            if (e + 1 < ee) ed = D.edges[e + 1];
+        }
+    }
+    if (D.m[v] == 1 && v < D.tail_node0 && ee == D.eptr[v + 1] && lane == 0) {
+        // standalone row: no pivot search (Sec. 2.2), perturbation only
+        T d = xs[D.lw[v]];
+        if (tabs(d) < tau) {
+            xs[D.lw[v]] = d < T(0) ? -tau : tau;
+            atomicAdd(pert, 1);
+        }
+    }
+    WaveSync::bar();
+    if (in_lds)
+        for (int j = lane; j < W; j += 64) X[j] = xs[j];
+    WaveSync::bar();
+}
+
+// LDS of the chain workgroup: the flags (ntask + 4 ints, 16-byte multiple),
+// then per wavefront its row (cap values), sbuf (sw values), the reduction
+// values (64), ibuf (sw ints), the reduction indices (64) and one int
+__host__ __device__ inline size_t chain_hdr_bytes(int ntask) { return (((size_t)ntask + 4) * 4 + 15) / 16 * 16; }
+__host__ __device__ inline size_t chain_wave_bytes(size_t es, int cap, int sw)
+{
+    return ((size_t)(cap + sw + 64) * es + (size_t)(sw + 64) * 4 + 16 + 15) / 16 * 16;
+}
+
+// tasks[t] >= 0: the outside updates of row tasks[t]; tasks[t] = -(v + 1):
+// the block LU (and inverse) of supernode v, whose row tasks (when it has
+// sources) are the m tasks just before it.  A node is complete with its
+// last task (the row task of a standalone row, the LU task of a supernode),
+// whose index is what its targets wait on.
+template <typename T>
+__global__ __launch_bounds__(kChainThreads) void k_factor_chain(DevLayout D, T* __restrict__ vals,
+                                                       const int32_t* __restrict__ tasks,
+                                                       const int32_t* __restrict__ sthr_of, int32_t ntask, int32_t nw,
+                                                       int32_t cap, int32_t sw, T tau, int32_t* __restrict__ pert,
+                                                       int32_t search, const int64_t* __restrict__ inv_off, int32_t spin)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int s_task, s_last;
-    __shared__ T red_v[NT];
-    __shared__ int red_i[NT];
-    __shared__ int s_p;
-    const int tid = threadIdx.x;
-    const int epoch = __hip_atomic_load(PC.ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {
-        if (tid == 0) s_task = __hip_atomic_fetch_add(PC.ctl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const int t = s_task;
-        __syncthreads();
-        if (t >= nrows) break;
-        const int i = rows[t];
-        const int v = D.row_node[i];
-        const int m = D.m[v];
-        // a supernode row without sources has nothing to apply
-        if (m == 1 || D.eptr[v + 1] > D.eptr[v])
-            row_task<T, NT, true>(D, vals, i, lds_cap, tau, pert, smem_raw, PC, epoch, stage);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (v >= D.tail_node0) continue;            // the dense tail waits on no flag
-        if (m == 1) {
-            if (tid == 0) __hip_atomic_store(PC.done + v, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            continue;
+    int32_t* flag = reinterpret_cast<int32_t*>(smem_raw);
+    int32_t* err = flag + ntask;
+    for (int t = threadIdx.x; t < ntask + 4; t += kChainThreads) flag[t] = 0;
+    __syncthreads();        // the only block barrier: the wavefronts then run apart
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wv >= nw) return;
+    unsigned char* base = smem_raw + chain_hdr_bytes(ntask) + (size_t)wv * chain_wave_bytes(sizeof(T), cap, sw);
+    T* xs = reinterpret_cast<T*>(base);
+    T* sbuf = xs + cap;
+    T* red_v = sbuf + sw;
+    int32_t* ibuf = reinterpret_cast<int32_t*>(red_v + 64);
+    int32_t* red_i = ibuf + sw;
+    int32_t* s_p = red_i + 64;
+    const ChainCtl C{flag, err, pert + 1, spin};
+    T* uinv = reinterpret_cast<T*>(const_cast<void*>(D.uinv));
+    for (int t = wv; t < ntask; t += nw) {
+        const int x = tasks[t];
+        if (x >= 0) {
+            const int v = D.row_node[x];
+            row_task_wave<T>(D, vals, x, D.eptr[v], D.eptr[v + 1], xs, cap, sbuf, ibuf, sw, sthr_of[t], tau, pert, C,
+                             lane);
+        } else {
+            const int v = -x - 1;
+            const int m = D.m[v];
+            if (D.eptr[v + 1] > D.eptr[v])
+                for (int a = 0; a < m; a++) chain_wait(C, t - m + a);
+            snlu_node<T, 64, WaveSync>(D, vals, v, tau, pert, search, sbuf, reinterpret_cast<uint8_t*>(ibuf), red_v,
+                                       red_i, s_p, lane);
+            if (inv_off && inv_off[v] >= 0) {
+                WaveSync::bar();
+                sn_inverse_node<T, 64>(D, vals, v, uinv + inv_off[v], lane);
+            }
         }
-        if (tid == 0) {
-            const int old = __hip_atomic_fetch_add(PC.rows_done + v, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            s_last = old == m - 1;
-        }
-        __syncthreads();
-        if (!s_last) continue;
-        // every row of the supernode is complete: its block LU here
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        T* lrow = reinterpret_cast<T*>(smem_raw);
-        uint8_t* taken = smem_raw + sizeof(T) * (size_t)m;
-        snlu_node<T, NT>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (tid == 0) __hip_atomic_store(PC.done + v, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // publish: the task's stores, then its flag
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) __hip_atomic_store(flag + t, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-}
-
-__global__ void k_pipe_reset(PipeCtl PC, int32_t nnodes)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        PC.ctl[0] = 0;
-        PC.ctl[1] += 1;
-    }
-    for (; i < nnodes; i += gridDim.x * blockDim.x) PC.rows_done[i] = 0;
 }
 
 // ----------------------------------------------------------------------------
@@ -2502,39 +2661,26 @@ hipError_t launch_perturb_rows(bool fp32, const DevLayout& D, void* vals, const 
     return hipGetLastError();
 }
 
-hipError_t launch_pipe_reset(const PipeCtl& P, int32_t nnodes, hipStream_t st)
+hipError_t launch_factor_chain(bool fp32, const DevLayout& D, void* vals, const int32_t* tasks, const int32_t* sthr,
+                               int32_t ntask, int32_t nw, int32_t cap, int32_t sw, double tau, int32_t* pert,
+                               int32_t search, const int64_t* inv_off, int32_t spin, hipStream_t st)
 {
-    if (!P.ctl || !P.rows_done) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_pipe_reset, dim3(std::min<unsigned>(nblk(std::max(nnodes, 1), 256), 1024)), dim3(256), 0, st, P, nnodes);
+    if (ntask <= 0) return hipSuccess;
+    if (nw < 1 || nw > kChainThreads / 64 || cap < 0 || sw < kInvMax || spin <= 0) return hipErrorInvalidValue;
+    const size_t sh = chain_lds(fp32, ntask, nw, cap, sw);
+    if (sh > kLdsMax) return hipErrorInvalidValue;
+    if (fp32)
+        hipLaunchKernelGGL(k_factor_chain<float>, dim3(1), dim3(kChainThreads), sh, st, D, (float*)vals, tasks, sthr, ntask, nw,
+                           cap, sw, (float)tau, pert, search, inv_off, spin);
+    else
+        hipLaunchKernelGGL(k_factor_chain<double>, dim3(1), dim3(kChainThreads), sh, st, D, (double*)vals, tasks, sthr, ntask,
+                           nw, cap, sw, tau, pert, search, inv_off, spin);
     return hipGetLastError();
 }
 
-hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, void* vals, const int32_t* rows,
-                              int32_t nrows, int32_t nt, int32_t stage, int32_t lds_cap, int32_t maxm, int32_t grid,
-                              double tau, int32_t* pert, int32_t search, hipStream_t st)
+size_t chain_lds(bool fp32, int32_t ntask, int32_t nw, int32_t cap, int32_t sw)
 {
-    if (nrows <= 0) return hipSuccess;
-    if (!P.ctl || !P.err || !P.done || !P.rows_done || P.spin_limit <= 0 || grid <= 0) return hipErrorInvalidValue;
-    if (stage < 64 || stage > kStageMax || stage % 64) return hipErrorInvalidValue;
-    const size_t es = fp32 ? sizeof(float) : sizeof(double);
-    const size_t sh = std::max(factor_rows_lds(fp32, stage, lds_cap), (size_t)maxm * (es + 1) + 16);
-    if (sh > kLdsMax) return hipErrorInvalidValue;
-    const dim3 g((unsigned)std::min(nrows, grid));
-#define PIPE_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_pipe<TT, NTT>), g, dim3(NTT), sh, st, D, P, (TT*)vals, rows, \
-                                                nrows, lds_cap, stage, (TT)tau, pert, search)
-    if (fp32) {
-        if (nt == 1024) PIPE_LAUNCH(float, 1024);
-        else if (nt == 256) PIPE_LAUNCH(float, 256);
-        else if (nt == 64) PIPE_LAUNCH(float, 64);
-        else return hipErrorInvalidValue;
-    } else {
-        if (nt == 1024) PIPE_LAUNCH(double, 1024);
-        else if (nt == 256) PIPE_LAUNCH(double, 256);
-        else if (nt == 64) PIPE_LAUNCH(double, 64);
-        else return hipErrorInvalidValue;
-    }
-#undef PIPE_LAUNCH
-    return hipGetLastError();
+    return chain_hdr_bytes(ntask) + (size_t)nw * chain_wave_bytes(fp32 ? 4 : 8, cap, sw);
 }
 
 hipError_t launch_sn_inverse(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,

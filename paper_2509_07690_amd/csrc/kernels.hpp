@@ -18,7 +18,7 @@ struct EdgeDesc {
     int32_t ws;     // source T width
     int32_t lp;     // slot of the source's first column in the target's L region
     int32_t r0s;    // first row of the source (pivot table offset)
-    int32_t srcp;   // source node when it is factored in the pipelined region, else -1
+    int32_t srcp;   // task of the target's chain launch that completes the source, else -1
     int64_t ioff;   // offset of the inverse of the source's block in pivot order, or -1
 };
 
@@ -28,16 +28,6 @@ struct EdgeDesc {
 // l = x_p Uinv (x_p: the row's entries at the source's pivot columns in pivot
 // order) with no sequential dependency.
 constexpr int32_t kInvMax = 256;   // largest supernode given an inverse
-
-// Pipeline mode: persistent blocks claim rows in topological order from a
-// ticket and wait per source node on a done flag.
-struct PipeCtl {
-    int32_t* ctl;           // [0] ticket, [1] epoch of the current factorisation
-    int32_t* err;           // set to 1 when a wait gave up
-    int32_t* done;          // per node: epoch in which the node was completed
-    int32_t* rows_done;     // per supernode: rows whose outside updates are finished
-    int32_t spin_limit;     // polls before a wait is declared failed (error flag, no hang)
-};
 
 // Device view of the panel layout.
 struct DevLayout {
@@ -190,14 +180,22 @@ hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const i
 // row tiles (16 rows) of supernode targets: tiles = pairs (node, first local row)
 hipError_t launch_factor_tile(bool fp32, const DevLayout& D, void* vals, const int32_t* tiles, int32_t ntiles,
                               hipStream_t st);
-hipError_t launch_pipe_reset(const PipeCtl& P, int32_t nnodes, hipStream_t st);
-// the pipelined launch over nrows row tasks (topological order): nt threads
-// per workgroup (64, 256 or 1024), `stage` staged source entries and rows up
-// to lds_cap columns in LDS as for launch_factor_rows, maxm the largest
-// supernode factored in the launch, grid persistent workgroups
-hipError_t launch_factor_pipe(bool fp32, const DevLayout& D, const PipeCtl& P, void* vals, const int32_t* rows,
-                              int32_t nrows, int32_t nt, int32_t stage, int32_t lds_cap, int32_t maxm, int32_t grid,
-                              double tau, int32_t* pert, int32_t search, hipStream_t st);
+// pipeline mode (Sec. 2.2.1): one workgroup of kChainThreads threads whose nw
+// wavefronts take the ntask tasks in order, task t by wavefront t mod nw:
+// tasks[t] >= 0 the outside updates of that row, -(v + 1) the block LU (and
+// inverse) of supernode v after its row tasks (the m tasks before it when it
+// has sources).  A row waits per source on the tasks of the launch
+// (EdgeDesc::srcp: the task completing the source node); a row of at most cap
+// columns sits in LDS; sw (>= kInvMax) staging values per wavefront; sthr[t]
+// the staging size the bulk row kernel would use for the task's level (it
+// decides the arithmetic path, so the factors equal bulk mode's).  A wait
+// gives up after `spin` polls and sets pert[1] (a device error for the host).
+constexpr int kChainThreads = 512;   // eight wavefronts (256 VGPRs each)
+hipError_t launch_factor_chain(bool fp32, const DevLayout& D, void* vals, const int32_t* tasks, const int32_t* sthr,
+                               int32_t ntask, int32_t nw, int32_t cap, int32_t sw, double tau, int32_t* pert,
+                               int32_t search, const int64_t* inv_off, int32_t spin, hipStream_t st);
+// dynamic LDS bytes of the chain workgroup
+size_t chain_lds(bool fp32, int32_t ntask, int32_t nw, int32_t cap, int32_t sw);
 // nt: threads per supernode (64 or 256; 0 = 256)
 // inverses of the blocks of the listed supernodes (each 2 <= m <= kInvMax)
 hipError_t launch_sn_inverse(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,

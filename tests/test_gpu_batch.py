@@ -118,17 +118,17 @@ def test_autotune_keeps_factors(hylu, batch):
     compare_factors(hb, o)
 
 
-@pytest.mark.skip(reason="pipelined launch switched off: it did not finish on the device (twice)")
-def test_batch_one_persistent_launch(hylu, batch):
-    """The whole batch's updates and block LUs in one pipelined persistent
-    launch (pipeline_rows above every level's width; Sec. 2.2.1): factors of
-    the union entry by entry against the oracle after factorisation and after
-    a refactorisation with every member's fresh values, and every member's
-    solution and backward error."""
+def test_batch_pipelined(hylu, batch):
+    """Pipeline mode on the batch (Sec. 2.2.1): every level from the first one
+    after which all levels have at most 1024 rows runs in chain launches, the
+    members' nodes waiting per source: factors of the union entry by entry
+    against the oracle after factorisation and after a refactorisation with
+    every member's fresh values, and every member's solution and backward
+    error."""
     ws, a0 = batch
     print(f"[case] batch of {len(ws)} pipelined", flush=True)
     hb = hylu.Handle.batch([(a.row_ptr, a.col, a.val) for a in a0], pipeline_rows=1 << 30)
-    assert hb.info()["pipe_tasks"] == hb.n
+    assert hb.info()["pipe_tasks"] > 0
     roff, _ = hb.offsets()
     U0 = _union(hb, [a.val for a in a0])
     hb.factorize(dev(U0.val))
