@@ -210,6 +210,10 @@ struct hylu_handle_s {
     std::vector<int64_t> inv_ptr;           // per factor level into inv_nodes
     std::vector<int32_t> inv_nodes, inv_maxm;
     int64_t* d_inv_off = nullptr;
+    // compact rows of the dense-tail nodes (see build_compact_rows) and the
+    // relative maps with their sources' entries rewritten to list indices
+    std::vector<int32_t> cw, cpos, crel;
+    std::vector<int64_t> cpos_off;
     int32_t* d_inv_nodes = nullptr;
     void* d_uinv = nullptr;
     static constexpr int kSide = 4;         // side streams for independent supernodes of a level
@@ -1150,11 +1154,17 @@ hylu_status upload_device(hylu_handle h)
         int64_t *voff, *coff, *eptr;
         EdgeDesc* edges;
         UP(r0, L.r0); UP(m, L.m); UP(lw, L.lw); UP(W, L.W); UP(voff, L.voff); UP(coff, L.coff);
-        UP(cols, L.cols); UP(eptr, L.eptr); UP(edges, ed); UP(rel, L.rel); UP(row_node, nd.of_row);
+        UP(cols, L.cols); UP(eptr, L.eptr); UP(edges, ed); UP(rel, h->crel); UP(row_node, nd.of_row);
         std::vector<int32_t> zeros(n, 0);
         UP(pl, zeros); UP(qinv, zeros);
         D.r0 = r0; D.m = m; D.lw = lw; D.W = W; D.voff = voff; D.coff = coff; D.cols = cols;
         D.eptr = eptr; D.edges = edges; D.rel = rel; D.row_node = row_node; D.pl = pl; D.qinv = qinv;
+        {
+            int32_t *cw, *cpos;
+            int64_t* cpoff;
+            UP(cw, h->cw); UP(cpos, h->cpos); UP(cpoff, h->cpos_off);
+            D.cw = cw; D.cpos = cpos; D.cpos_off = cpoff;
+        }
         UP(h->d_amap, L.amap); UP(h->d_asr, asr); UP(h->d_asc, asc);
         UP(h->d_rows, T.rows); UP(h->d_snodes, T.snodes); UP(h->d_tiles, T.tiles);
         UP(h->d_rrange, T.rrange);
@@ -1307,6 +1317,54 @@ hylu_status order_matrix(const Csr& A, const hylu_options& opt, std::vector<int3
     perm_r.resize(n);
     for (int32_t k = 0; k < n; k++) perm_r[k] = match[q[k]];
     return HYLU_OK;
+}
+
+// Compact rows: a dense-tail row's panel spans its outside sources' slots and
+// every tail column, but its outside updates touch only the slots and the
+// columns those sources' U rows reach.  Per tail node with sources, the sorted
+// positions touched (the slots first, so a slot keeps its index) replace the
+// row in the row kernel's accumulator when there are at most kCompactMax of
+// them, and its sources' relative maps are rewritten to index that list.
+constexpr int32_t kCompactMax = kRowCapSmall;
+void build_compact_rows(hylu_handle h)
+{
+    const Layout& L = h->lay;
+    h->cw.assign(L.nnodes, 0);
+    h->cpos_off.assign(L.nnodes + 1, 0);
+    h->cpos.clear();
+    h->crel = L.rel;
+    int32_t wmax = 0;
+    for (int32_t v = L.tail_node0; v < L.nnodes; v++) wmax = std::max(wmax, L.W[v]);
+    std::vector<int32_t> idx(std::max(wmax, 1), -1);
+    std::vector<int32_t> touched;
+    for (int32_t v = 0; v < L.nnodes; v++) {
+        h->cpos_off[v + 1] = h->cpos_off[v];
+        if (v < L.tail_node0 || L.eptr[v + 1] == L.eptr[v]) continue;
+        touched.clear();
+        for (int32_t j = 0; j < L.lw[v]; j++) { idx[j] = 0; touched.push_back(j); }
+        for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
+            const int32_t s = L.esrc[e];
+            const int32_t ws = L.W[s] - L.lw[s] - L.m[s];
+            for (int32_t t = 0; t < ws; t++) {
+                const int32_t r = L.rel[L.eroff[e] + t];
+                if (idx[r] < 0) { idx[r] = 0; touched.push_back(r); }
+            }
+        }
+        std::sort(touched.begin(), touched.end());
+        const bool compact = (int32_t)touched.size() <= kCompactMax && (int32_t)touched.size() < L.W[v];
+        for (size_t k = 0; k < touched.size(); k++) idx[touched[k]] = (int32_t)k;
+        if (compact) {
+            h->cw[v] = (int32_t)touched.size();
+            h->cpos.insert(h->cpos.end(), touched.begin(), touched.end());
+            h->cpos_off[v + 1] = (int64_t)h->cpos.size();
+            for (int64_t e = L.eptr[v]; e < L.eptr[v + 1]; e++) {
+                const int32_t s = L.esrc[e];
+                const int32_t ws = L.W[s] - L.lw[s] - L.m[s];
+                for (int32_t t = 0; t < ws; t++) h->crel[L.eroff[e] + t] = idx[L.rel[L.eroff[e] + t]];
+            }
+        }
+        for (int32_t r : touched) idx[r] = -1;
+    }
 }
 
 // The chain launches of pipeline mode, checked on the host against the rule
@@ -1488,6 +1546,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     double eps = std::numeric_limits<double>::epsilon();
     h->tau = (opt.pivot_tau > 0 ? opt.pivot_tau : std::sqrt(eps)) * (bmax > 0 ? bmax : 1.0);
     // ---- level task lists of the factorisation
+    build_compact_rows(h);
     const Layout& L = h->lay;
     const Nodes& nd = h->nodes;
     LevelTasks& T = h->ft;
@@ -1563,7 +1622,8 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 const int32_t u = L.esrc[e];
                 c += 1.0 + (double)L.m[u] * (L.W[u] - L.lw[u]) / 2048.0;
             }
-            return L.W[v] > kRowCapBig ? 3.0 * c : c;    // accumulator in global memory
+            // (a row accumulator in global memory when it does not fit in LDS)
+            return (h->cw[v] == 0 && L.W[v] > kRowCapBig) ? 3.0 * c : c;
         };
         std::vector<int64_t> nrow(nmain, 0), room(nmain, 0);
         std::vector<double> lmax(nmain, 0.0);
@@ -1596,9 +1656,10 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         for (const auto& q : order) {
             const int32_t v = q.second;
             if (moved[v] || v < L.tail_node0 || L.eptr[v + 1] == L.eptr[v]) continue;
-            // (pieces are held to half the level's estimate: a piece also
-            // loads and stores the whole row)
-            const double mult = 2.0 * (L.W[v] > kRowCapBig ? 3.0 : 1.0);
+            // (a piece of a full row is held to half the level's estimate:
+            // it also loads and stores the whole row; a compact row's piece
+            // only its touched positions)
+            const double mult = h->cw[v] > 0 ? 1.0 : 2.0 * (L.W[v] > kRowCapBig ? 3.0 : 1.0);
             int64_t e = L.eptr[v];
             const int64_t e1 = L.eptr[v + 1];
             std::vector<std::array<int64_t, 3>> pieces;     // (level, first, end)

@@ -230,17 +230,31 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
     const int W = D.W[v];
     const int a = i - D.r0[v];
     T* X = vals + D.voff[v] + (int64_t)a * W;
-    const bool in_lds = W <= lds_cap;
+    // a compact row (dense-tail rows): the accumulator holds only the
+    // positions its outside sources touch, cp[j] for entry j, and the
+    // sources' relative maps index that list
+    const int Wc = D.cw ? D.cw[v] : 0;
+    const int32_t* cp = Wc > 0 ? D.cpos + D.cpos_off[v] : nullptr;
+    const int Wl = Wc > 0 ? Wc : W;
+    const bool in_lds = Wl <= lds_cap;
+    if (Wc > 0 && !in_lds) {
+        // (the launch shapes keep every compact row in LDS)
+        if (tid == 0) atomicOr(pert + 1, 1);
+        return;
+    }
     T* xs = in_lds ? xsl : X;
     if (in_lds) {
         // eight loads per thread in flight before their LDS stores (a wave
         // issues in order and would otherwise wait on every load)
-        for (int j0 = tid; j0 < W; j0 += 8 * NT) {
+        for (int j0 = tid; j0 < Wl; j0 += 8 * NT) {
             T t[8];
+            int pj[8];
 #pragma unroll
-            for (int u = 0; u < 8; u++) { const int j = j0 + u * NT; t[u] = j < W ? X[j] : T(0); }
+            for (int u = 0; u < 8; u++) { const int j = j0 + u * NT; pj[u] = j < Wl ? (cp ? cp[j] : j) : 0; }
 #pragma unroll
-            for (int u = 0; u < 8; u++) { const int j = j0 + u * NT; if (j < W) xs[j] = t[u]; }
+            for (int u = 0; u < 8; u++) { const int j = j0 + u * NT; t[u] = j < Wl ? X[pj[u]] : T(0); }
+#pragma unroll
+            for (int u = 0; u < 8; u++) { const int j = j0 + u * NT; if (j < Wl) xs[j] = t[u]; }
         }
     }
     __syncthreads();
@@ -354,7 +368,7 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
     }
     __syncthreads();
     if (in_lds) {
-        for (int j = tid; j < W; j += NT) X[j] = xs[j];
+        for (int j = tid; j < Wl; j += NT) X[cp ? cp[j] : j] = xs[j];
     }
 }
 
