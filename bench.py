@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--sn-inverse", type=int, default=1)
     ap.add_argument("--tail-sparse", type=int, default=1)
     ap.add_argument("--side-rows", type=int, default=1)
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="pick per-level launch shapes with hylu_autotune before timing (untimed setup)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -100,6 +102,12 @@ def main():
     v0 = torch.from_numpy(A0.val).to(dev)
     h.factorize(v0)
     torch.cuda.synchronize()
+    tune = None
+    if args.autotune:
+        t0 = time.time()
+        t_def, t_tuned = h.autotune(v0, reps=2)
+        tune = {"builtin": round(t_def, 3), "tuned": round(t_tuned, 3), "s": round(time.time() - t0, 2)}
+        log(f"autotune: level launches {t_def:.2f} ms with built-in shapes, {t_tuned:.2f} ms tuned")
 
     def run(hd, steps, warmup, first=0):
         """warmup + timed refactor+solve steps over consecutive value sets;
@@ -211,6 +219,7 @@ def main():
         "resid_1": res1,
         "max_abs_err_vs_x_true": max(errs),
         "analyze_s": round(t_analyze, 2),
+        "autotune_level_ms": tune,
         "tail_rows": info["tail_rows"],
         "roofline": roof,
         "kernels": kernels,
@@ -248,6 +257,8 @@ def fp32_ir_leg(args, A0, opts, vals, bs, xs, xts, v0, run, x64, timed):
     for tol in (1e-10, 1e-12):
         hf = hylu.Handle(A0.row_ptr, A0.col, A0.val, precision="fp32", ir_tol=tol, **opts)
         hf.factorize(v0)
+        if args.autotune:
+            hf.autotune(v0, reps=2)
         ms, tr, tsv, idx = run(hf, args.steps, args.warmup)
         r = idx[-1]
         eta, res1 = hf.residual(bs[r], xs[r])

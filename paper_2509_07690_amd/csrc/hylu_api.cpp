@@ -1154,16 +1154,18 @@ hylu_status upload_device(hylu_handle h)
         int64_t *voff, *coff, *eptr;
         EdgeDesc* edges;
         UP(r0, L.r0); UP(m, L.m); UP(lw, L.lw); UP(W, L.W); UP(voff, L.voff); UP(coff, L.coff);
-        UP(cols, L.cols); UP(eptr, L.eptr); UP(edges, ed); UP(rel, h->crel); UP(row_node, nd.of_row);
+        UP(cols, L.cols); UP(eptr, L.eptr); UP(edges, ed); UP(rel, L.rel); UP(row_node, nd.of_row);
         std::vector<int32_t> zeros(n, 0);
         UP(pl, zeros); UP(qinv, zeros);
         D.r0 = r0; D.m = m; D.lw = lw; D.W = W; D.voff = voff; D.coff = coff; D.cols = cols;
         D.eptr = eptr; D.edges = edges; D.rel = rel; D.row_node = row_node; D.pl = pl; D.qinv = qinv;
         {
-            int32_t *cw, *cpos;
+            int32_t *cw, *cpos, *crel;
             int64_t* cpoff;
             UP(cw, h->cw); UP(cpos, h->cpos); UP(cpoff, h->cpos_off);
-            D.cw = cw; D.cpos = cpos; D.cpos_off = cpoff;
+            if (h->cpos.empty()) crel = rel;
+            else UP(crel, h->crel);
+            D.cw = cw; D.cpos = cpos; D.cpos_off = cpoff; D.crel = crel;
         }
         UP(h->d_amap, L.amap); UP(h->d_asr, asr); UP(h->d_asc, asc);
         UP(h->d_rows, T.rows); UP(h->d_snodes, T.snodes); UP(h->d_tiles, T.tiles);
@@ -1322,10 +1324,12 @@ hylu_status order_matrix(const Csr& A, const hylu_options& opt, std::vector<int3
 // Compact rows: a dense-tail row's panel spans its outside sources' slots and
 // every tail column, but its outside updates touch only the slots and the
 // columns those sources' U rows reach.  Per tail node with sources, the sorted
-// positions touched (the slots first, so a slot keeps its index) replace the
-// row in the row kernel's accumulator when there are at most kCompactMax of
-// them, and its sources' relative maps are rewritten to index that list.
-constexpr int32_t kCompactMax = kRowCapSmall;
+// positions touched (the slots first, so a slot keeps its index) are listed
+// when there are at most kCompactMax of them, with a copy of the relative maps
+// whose entries for its sources index that list.  The row kernel takes the
+// compact row where the whole row does not fit the launch's LDS row capacity
+// and the compact one does (instead of accumulating in global memory).
+constexpr int32_t kCompactMax = kRowCapBig;
 void build_compact_rows(hylu_handle h)
 {
     const Layout& L = h->lay;
@@ -1364,6 +1368,17 @@ void build_compact_rows(hylu_handle h)
             }
         }
         for (int32_t r : touched) idx[r] = -1;
+    }
+    if (const char* lg = std::getenv("HYLU_LOG"); lg && std::atoi(lg) >= 2) {
+        int64_t nc = 0, wc = 0, wf = 0, nt = 0;
+        for (int32_t v = L.tail_node0; v < L.nnodes; v++) {
+            if (L.eptr[v + 1] == L.eptr[v]) continue;
+            nt++;
+            wf += (int64_t)L.W[v] * L.m[v];
+            if (h->cw[v] > 0) { nc++; wc += (int64_t)h->cw[v] * L.m[v]; }
+        }
+        std::fprintf(stderr, "hylu: compact rows: %lld of %lld tail nodes with sources, %lld of %lld row entries\n",
+                     (long long)nc, (long long)nt, (long long)wc, (long long)wf);
     }
 }
 
@@ -1656,10 +1671,9 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         for (const auto& q : order) {
             const int32_t v = q.second;
             if (moved[v] || v < L.tail_node0 || L.eptr[v + 1] == L.eptr[v]) continue;
-            // (a piece of a full row is held to half the level's estimate:
-            // it also loads and stores the whole row; a compact row's piece
-            // only its touched positions)
-            const double mult = h->cw[v] > 0 ? 1.0 : 2.0 * (L.W[v] > kRowCapBig ? 3.0 : 1.0);
+            // (pieces are held to half the level's estimate: a piece also
+            // loads and stores the whole row)
+            const double mult = 2.0 * ((h->cw[v] == 0 && L.W[v] > kRowCapBig) ? 3.0 : 1.0);
             int64_t e = L.eptr[v];
             const int64_t e1 = L.eptr[v + 1];
             std::vector<std::array<int64_t, 3>> pieces;     // (level, first, end)

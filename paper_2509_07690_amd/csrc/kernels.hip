@@ -118,10 +118,10 @@ __global__ void k_init_pivots(int32_t n, const int32_t* __restrict__ row_node, c
 // not depend on where a task runs)
 template <typename T, int NT, class Sync = BlockSync>
 __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ vals, T* xs, const EdgeDesc& ed,
-                                    int tid, T* sbuf, int32_t* ibuf, int stage, int sthr)
+                                    int tid, T* sbuf, int32_t* ibuf, int stage, int sthr, const int32_t* relb)
 {
     const T* Us = vals + ed.uoff;
-    const int32_t* rl = D.rel + ed.roff;
+    const int32_t* rl = relb + ed.roff;
     const int lp = ed.lp, ms = ed.ms, Ws = ed.Ws, ws = ed.ws;
     const bool pl_lds = ms <= stage;
     const int32_t* pls = pl_lds ? ibuf : D.pl + ed.r0s;
@@ -230,18 +230,16 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
     const int W = D.W[v];
     const int a = i - D.r0[v];
     T* X = vals + D.voff[v] + (int64_t)a * W;
-    // a compact row (dense-tail rows): the accumulator holds only the
-    // positions its outside sources touch, cp[j] for entry j, and the
-    // sources' relative maps index that list
+    // a compact row (a dense-tail row too wide for LDS whose touched
+    // positions fit): the accumulator holds only the positions its outside
+    // sources touch, cp[j] for entry j, and the sources' compact relative maps
+    // index that list (a row that fits whole keeps its plain contiguous loads)
     const int Wc = D.cw ? D.cw[v] : 0;
-    const int32_t* cp = Wc > 0 ? D.cpos + D.cpos_off[v] : nullptr;
-    const int Wl = Wc > 0 ? Wc : W;
+    const bool compact = Wc > 0 && Wc <= lds_cap && W > lds_cap;
+    const int32_t* cp = compact ? D.cpos + D.cpos_off[v] : nullptr;
+    const int32_t* relb = compact ? D.crel : D.rel;
+    const int Wl = compact ? Wc : W;
     const bool in_lds = Wl <= lds_cap;
-    if (Wc > 0 && !in_lds) {
-        // (the launch shapes keep every compact row in LDS)
-        if (tid == 0) atomicOr(pert + 1, 1);
-        return;
-    }
     T* xs = in_lds ? xsl : X;
     if (in_lds) {
         // eight loads per thread in flight before their LDS stores (a wave
@@ -297,7 +295,7 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
         if (nb == 0) {
             // a supernode source (or an oversized standalone one)
             const EdgeDesc e0 = D.edges[e];
-            apply_source_direct<T, NT>(D, vals, xs, e0, tid, sval, sidx, stage, stage);
+            apply_source_direct<T, NT>(D, vals, xs, e0, tid, sval, sidx, stage, stage, relb);
             e += 1;
             continue;
         }
@@ -316,7 +314,7 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
                     while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (eoff[mid] <= idx) lo = mid; else hi = mid - 1; }
                     const int tt = idx - eoff[lo];
                     sv[u] = vals[eu[lo] + tt];       // pivot, then the T values
-                    if (tt > 0) si[u] = D.rel[er[lo] + tt - 1];
+                    if (tt > 0) si[u] = relb[er[lo] + tt - 1];
                 }
             }
 #pragma unroll
@@ -746,7 +744,7 @@ __device__ void row_task_wave(const DevLayout& D, T* __restrict__ vals, int i, i
                 for (int k = 0; k < 4; k++) { cu[k] = nu[k]; cix[k] = nix[k]; }
             }
         } else {
-            apply_source_direct<T, 64, WaveSync>(D, vals, xs, ed, lane, sbuf, ibuf, sw, sthr);
+            apply_source_direct<T, 64, WaveSync>(D, vals, xs, ed, lane, sbuf, ibuf, sw, sthr, D.rel);
             have = false;
             if (e + 1 < ee) ed = D.edges[e + 1];
         }

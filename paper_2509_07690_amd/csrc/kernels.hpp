@@ -56,12 +56,13 @@ struct DevLayout {
     const int64_t* lt_slot;
     const int32_t* lt_row;
     // compact rows (dense-tail nodes): per node the number of positions its
-    // outside sources touch (0: the full row), and those positions (sorted,
-    // from cpos_off[v]); the relative maps of a compact node's sources index
-    // that list instead of the row
+    // outside sources touch (0: none kept), and those positions (sorted, from
+    // cpos_off[v]); crel: the relative maps with those of a compact node's
+    // sources indexing that list instead of the row (rel: always the row)
     const int32_t* cw;
     const int64_t* cpos_off;
     const int32_t* cpos;
+    const int32_t* crel;
 };
 
 // Dense tail: rows and columns [t0, n) of the factors as one dense block whose
