@@ -292,7 +292,7 @@ def bench_copy(args):
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "circuit_n200000_hbm_traffic.md")
 # kernel class -> (kernel family, first and last marker of its source in kernels.hip)
 TRAFFIC_SOURCES = {
-    "rows": ("k_factor_rows", "__device__ void apply_source_direct(", "// internal factorisation of a supernode"),
+    "rows": ("k_factor_rows", "__device__ void apply_source_direct(", "// pipeline mode (Sec. 2.2.1): the narrow levels"),
     "tail_gemm": ("k_tail_gemm", "template <typename T> struct Mfma;", "// ---- row tiles of supernode targets"),
 }
 

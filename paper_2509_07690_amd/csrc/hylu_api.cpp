@@ -214,6 +214,7 @@ struct hylu_handle_s {
     // relative maps with their sources' entries rewritten to list indices
     std::vector<int32_t> cw, cpos, crel;
     std::vector<int64_t> cpos_off;
+    std::vector<uint8_t> snfuse;            // per node: its block LU done by its level's row launch
     int32_t* d_inv_nodes = nullptr;
     void* d_uinv = nullptr;
     static constexpr int kSide = 4;         // side streams for independent supernodes of a level
@@ -497,6 +498,9 @@ constexpr int32_t kChainSw = kInvMax;
 constexpr int32_t kChainSpin = 1 << 21;
 constexpr int32_t kChainSnMax = 64;
 constexpr int32_t kChainRunMin = 3;   // shortest run of narrow levels taken by chain launches
+// a supernode of at most this many rows whose rows are row tasks has its block
+// LU done by the last of those row tasks (the row launch's LDS holds its work)
+constexpr int32_t kFuseSnMax = 64;
 // The launch sequence of a view: groups of up to kGroup panels (left-looking
 // inside the group, one trailing update per group).  With the tail's masks M
 // every GEMM gets the list of its tiles that have a nonzero product, each with
@@ -903,7 +907,8 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
         LAUNCH(C_ROWS, h->lvl_bytes[l] * es + h->lvl_idx[l], h->lvl_flops[l],
                launch_factor_rows(h->fp32, h->D, h->vals, h->d_rows + r0, h->d_rrange + 2 * r0, (int32_t)(r1 - r0),
                                   T.maxW[l], h->tau, h->d_pert,
-                                  T.tune_rows ? T.tune_rows : T.row_nt[l], T.row_stage[l], T.row_cap[l], st));
+                                  T.tune_rows ? T.tune_rows : T.row_nt[l], T.row_stage[l], T.row_cap[l],
+                                  search ? 1 : 0, h->d_inv_off, st));
         if (T.tile_ptr[l + 1] > T.tile_ptr[l])
             LAUNCH(C_TILE, h->tile_bytes[l] * es + h->tile_idx[l], h->tile_flops[l],
                    launch_factor_tile(h->fp32, h->D, h->vals, h->d_tiles + 2 * T.tile_ptr[l],
@@ -1166,6 +1171,11 @@ hylu_status upload_device(hylu_handle h)
             if (h->cpos.empty()) crel = rel;
             else UP(crel, h->crel);
             D.cw = cw; D.cpos = cpos; D.cpos_off = cpoff; D.crel = crel;
+            uint8_t* snf;
+            int32_t* sncnt;
+            std::vector<int32_t> zn(std::max(L.nnodes, 1), 0);
+            UP(snf, h->snfuse); UP(sncnt, zn);
+            D.snfuse = snf; D.sncnt = sncnt;
         }
         UP(h->d_amap, L.amap); UP(h->d_asr, asr); UP(h->d_asc, asc);
         UP(h->d_rows, T.rows); UP(h->d_snodes, T.snodes); UP(h->d_tiles, T.tiles);
@@ -1712,6 +1722,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     T.rrange.clear();
     h->pert_rows.clear();
     T.lvrows.assign(nl, 0);
+    h->snfuse.assign(L.nnodes, 0);
     for (int32_t l = 0; l < nl; l++) {
         int32_t mw = 0, mm = 0;
         for (int32_t v : lvnodes[l]) {
@@ -1750,6 +1761,9 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 std::vector<uint32_t> none;
                 h->sn_groups += plan_dense(q.panels, L.m[v], L.W[v] - L.lw[v], nullptr, true, gmin, q.ops, none);
                 h->dsn.push_back(std::move(q));
+            } else if (L.eptr[v + 1] > L.eptr[v] && L.m[v] < tile_min && L.m[v] <= kFuseSnMax) {
+                // its rows are this level's row tasks: the last of them factors it
+                h->snfuse[v] = 1;
             } else {
                 T.snodes.push_back(v);
                 mm = std::max(mm, L.m[v]);
@@ -2055,6 +2069,15 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 h->lvl_flops[l] += fl;
             }
         }
+        // the block LUs (and inverses) that row launches do
+        for (int32_t l = 0; l < nl; l++)
+            for (int32_t v : lvnodes[l]) {
+                if (!h->snfuse[v]) continue;
+                const double m = L.m[v], wc = L.W[v] - L.lw[v];
+                h->lvl_bytes[l] += 2.0 * m * wc;
+                h->lvl_flops[l] += 2.0 * m * m * m / 3.0 + m * m * (wc - m);
+                if (h->inv_off[v] >= 0) { h->lvl_bytes[l] += 2.0 * m * m; h->lvl_flops[l] += m * m * m / 3.0; }
+            }
         // the block LUs (and inverses) inside the chain launches
         h->chain_snlu_bytes.assign(T.chains.size(), 0.0);
         h->chain_snlu_flops.assign(T.chains.size(), 0.0);

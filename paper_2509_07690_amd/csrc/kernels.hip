@@ -370,18 +370,6 @@ __device__ void row_task(const DevLayout& D, T* __restrict__ vals, int i, int32_
     }
 }
 
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__ vals,
-                                                    const int32_t* __restrict__ rows, const int64_t* __restrict__ ranges,
-                                                    int32_t nrows, int32_t lds_cap, T tau, int32_t* __restrict__ pert,
-                                                    int32_t stage)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    if ((int)blockIdx.x >= nrows) return;
-    const int64_t eb = ranges ? ranges[2 * blockIdx.x] : -1, ee = ranges ? ranges[2 * blockIdx.x + 1] : -1;
-    row_task<T, NT>(D, vals, rows[blockIdx.x], lds_cap, tau, pert, smem_raw, stage, eb, ee);
-}
-
 // standalone rows without sources: their pivot is checked (and perturbed)
 // in place, one thread per row
 template <typename T>
@@ -573,6 +561,43 @@ __global__ __launch_bounds__(NT) void k_factor_snlu(DevLayout D, T* __restrict__
         __syncthreads();        // the block and its pivot order are complete
         sn_inverse_node<T, NT>(D, vals, v, reinterpret_cast<T*>(const_cast<void*>(D.uinv)) + inv_off[v], threadIdx.x);
     }
+}
+
+// one row task per workgroup (bulk mode)
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__ vals,
+                                                    const int32_t* __restrict__ rows, const int64_t* __restrict__ ranges,
+                                                    int32_t nrows, int32_t lds_cap, T tau, int32_t* __restrict__ pert,
+                                                    int32_t stage, int32_t search, const int64_t* __restrict__ inv_off)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_last, s_p;
+    if ((int)blockIdx.x >= nrows) return;
+    const int64_t eb = ranges ? ranges[2 * blockIdx.x] : -1, ee = ranges ? ranges[2 * blockIdx.x + 1] : -1;
+    const int i = rows[blockIdx.x];
+    row_task<T, NT>(D, vals, i, lds_cap, tau, pert, smem_raw, stage, eb, ee);
+    const int v = D.row_node[i];
+    if (!D.snfuse || !D.snfuse[v]) return;
+    // a small supernode of this launch: the workgroup that finishes its last
+    // row factors its block (and inverse).  Every row's stores are made
+    // visible at device scope before its count; the last one acquires them.
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(D.sncnt + v, 1) == D.m[v] - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const int m = D.m[v];
+    T* red_v = reinterpret_cast<T*>(smem_raw);                      // NT
+    T* lrow = red_v + NT;                                           // m
+    int* red_i = reinterpret_cast<int*>(lrow + m);                  // NT
+    uint8_t* taken = reinterpret_cast<uint8_t*>(red_i + NT);        // m
+    snlu_node<T, NT>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p, threadIdx.x);
+    if (inv_off && inv_off[v] >= 0) {
+        __syncthreads();        // the block and its pivot order are complete
+        sn_inverse_node<T, NT>(D, vals, v, reinterpret_cast<T*>(const_cast<void*>(D.uinv)) + inv_off[v], threadIdx.x);
+    }
+    if (threadIdx.x == 0) D.sncnt[v] = 0;       // ready for the next factorisation
 }
 
 // ----------------------------------------------------------------------------
@@ -2635,7 +2660,7 @@ size_t factor_rows_lds(bool fp32, int32_t stage, int32_t cap)
 
 hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, const int64_t* ranges,
                               int32_t nrows, int32_t maxW, double tau, int32_t* pert, int32_t nt, int32_t stage,
-                              int32_t lds_cap, hipStream_t st)
+                              int32_t lds_cap, int32_t search, const int64_t* inv_off, hipStream_t st)
 {
     if (nrows <= 0) return hipSuccess;
     if (stage < kStage || stage > kStageMax || stage % 64) return hipErrorInvalidValue;
@@ -2644,7 +2669,7 @@ hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const i
     const size_t sh = factor_rows_lds(fp32, stage, cap);
     if (sh > kLdsMax) return hipErrorInvalidValue;
     const dim3 g(nrows);
-#define ROWS_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_rows<TT, NTT>), g, dim3(NTT), sh, st, D, (TT*)vals, rows, ranges, nrows, cap, (TT)tau, pert, stage)
+#define ROWS_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_rows<TT, NTT>), g, dim3(NTT), sh, st, D, (TT*)vals, rows, ranges, nrows, cap, (TT)tau, pert, stage, search, inv_off)
     if (fp32) {
         if (nt == 1024) ROWS_LAUNCH(float, 1024);
         else if (nt == 512) ROWS_LAUNCH(float, 512);

@@ -63,6 +63,11 @@ struct DevLayout {
     const int64_t* cpos_off;
     const int32_t* cpos;
     const int32_t* crel;
+    // small supernodes whose block LU the row launch of their level does
+    // (snfuse[v] = 1): per node the rows finished so far (zero between
+    // factorisations)
+    const uint8_t* snfuse;
+    int32_t* sncnt;
 };
 
 // Dense tail: rows and columns [t0, n) of the factors as one dense block whose
@@ -181,10 +186,13 @@ hipError_t launch_perturb_rows(bool fp32, const DevLayout& D, void* vals, const 
                                double tau, int32_t* pert, hipStream_t st);
 // ranges (optional, device): per row, the first and one-past-last index of
 // the sources it takes in this launch (a long row's sources may be split over
-// several launches, in order); null: every source
+// several launches, in order); null: every source.  A row of a supernode with
+// D.snfuse set also counts itself done, and the last row of that supernode
+// factors its block (pivot search when `search`) and, when inv_off[v] >= 0,
+// its inverse
 hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const int32_t* rows, const int64_t* ranges,
                               int32_t nrows, int32_t maxW, double tau, int32_t* pert, int32_t nt, int32_t stage,
-                              int32_t lds_cap, hipStream_t st);
+                              int32_t lds_cap, int32_t search, const int64_t* inv_off, hipStream_t st);
 // row tiles (16 rows) of supernode targets: tiles = pairs (node, first local row)
 hipError_t launch_factor_tile(bool fp32, const DevLayout& D, void* vals, const int32_t* tiles, int32_t ntiles,
                               hipStream_t st);
