@@ -498,8 +498,9 @@ constexpr int32_t kChainSw = kInvMax;
 constexpr int32_t kChainSpin = 1 << 21;
 constexpr int32_t kChainSnMax = 64;
 constexpr int32_t kChainRunMin = 3;   // shortest run of narrow levels taken by chain launches
-// a supernode of at most this many rows whose rows are row tasks has its block
-// LU done by the last of those row tasks (the row launch's LDS holds its work)
+// a supernode of at most this many rows whose rows are row tasks of a narrow
+// level has its block LU done by the last of those row tasks (the row
+// launch's LDS holds its work)
 constexpr int32_t kFuseSnMax = 64;
 // The launch sequence of a view: groups of up to kGroup panels (left-looking
 // inside the group, one trailing update per group).  With the tail's masks M
@@ -1725,6 +1726,12 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     h->snfuse.assign(L.nnodes, 0);
     for (int32_t l = 0; l < nl; l++) {
         int32_t mw = 0, mm = 0;
+        // a narrow level's row launch also factors its small supernodes (one
+        // launch fewer); a wide level keeps a launch of its own for them, where
+        // every supernode has a full workgroup
+        int64_t lrows = (int64_t)lvpieces[l].size();
+        for (int32_t v : lvnodes[l]) lrows += L.m[v];
+        const bool narrow = lrows <= kSideNarrowRows;
         for (int32_t v : lvnodes[l]) {
             if (chain_lev[l]) {
                 // a node of a chain launch: its rows and block LU there; the
@@ -1761,7 +1768,7 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                 std::vector<uint32_t> none;
                 h->sn_groups += plan_dense(q.panels, L.m[v], L.W[v] - L.lw[v], nullptr, true, gmin, q.ops, none);
                 h->dsn.push_back(std::move(q));
-            } else if (L.eptr[v + 1] > L.eptr[v] && L.m[v] < tile_min && L.m[v] <= kFuseSnMax) {
+            } else if (narrow && L.eptr[v + 1] > L.eptr[v] && L.m[v] < tile_min && L.m[v] <= kFuseSnMax) {
                 // its rows are this level's row tasks: the last of them factors it
                 h->snfuse[v] = 1;
             } else {
