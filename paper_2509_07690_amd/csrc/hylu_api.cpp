@@ -488,7 +488,7 @@ constexpr int32_t kRowCapSmall = 4096, kRowCapBig = 10240;
 constexpr int32_t kLsolveSnMin = 8;
 // a run of at least kChainMin solve levels of at most kChainNodes nodes is
 // solved by one workgroup in one launch
-constexpr int32_t kChainMin = 3, kChainNodes = 64;
+constexpr int32_t kChainMin = 3, kChainNodes = 16;
 // pipeline mode: nodes per chain launch (one LDS flag each), staging values
 // per wavefront (at least the largest supernode with a block inverse), polls
 // before a wait gives up (tens of milliseconds, far beyond any real wait), and
