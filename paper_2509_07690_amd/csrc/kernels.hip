@@ -520,6 +520,103 @@ __device__ void snlu_node(const DevLayout& D, T* __restrict__ vals, int v, T tau
     }
 }
 
+// The same LU for a supernode of at most kSnLds rows, its block in LDS: the
+// block is factored as above (the same operations in the same order), then
+// every column c past the block is finished by one thread with the forward
+// substitution x_r = B_rc - sum_{a < r} l_ra x_a in a = 0, 1, .., which is the
+// sequence of updates the row-by-row elimination applies to that column; the
+// panel is read and written once instead of once per pivot step.  blk, lm:
+// m x m each (lm: the multipliers in pivot order), lrow m, pls m, taken m.
+constexpr int kSnLds = 64;
+template <typename T, int NT>
+__device__ void snlu_node_lds(const DevLayout& D, T* __restrict__ vals, int v, T tau, int32_t* __restrict__ pert,
+                              int search, T* blk, T* lm, T* lrow, int* pls, uint8_t* taken, T* red_v, int* red_i,
+                              int* s_p, int tid)
+{
+    const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const int wc = W - lw;                     // block + T columns
+    T* P = vals + D.voff[v] + lw;              // row a, column c at P[a*W + c]
+    int32_t* pl = D.pl + r0;
+    for (int idx = tid; idx < m * m; idx += NT) blk[idx] = P[(int64_t)(idx / m) * W + idx % m];
+    for (int c = tid; c < m; c += NT) taken[c] = 0;
+    __syncthreads();
+    for (int a = 0; a < m; a++) {
+        T* Ba = blk + a * m;
+        int p;
+        if (search) {
+            T best = T(-1);
+            int bi = m;
+            for (int c = tid; c < m; c += NT) {
+                if (taken[c]) continue;
+                T x = pmag(Ba[c]);
+                if (x > best || (x == best && c < bi)) { best = x; bi = c; }
+            }
+            red_v[tid] = best; red_i[tid] = bi;
+            __syncthreads();
+            for (int s2 = NT / 2; s2 > 0; s2 >>= 1) {
+                if (tid < s2) {
+                    T x = red_v[tid + s2]; int xi = red_i[tid + s2];
+                    if (x > red_v[tid] || (x == red_v[tid] && xi < red_i[tid])) { red_v[tid] = x; red_i[tid] = xi; }
+                }
+                __syncthreads();
+            }
+            p = red_i[0];
+        } else {
+            p = pl[a];
+        }
+        if (tid == 0) {
+            T d = Ba[p];
+            if (tabs(d) < tau) {
+                Ba[p] = d < T(0) ? -tau : tau;
+                atomicAdd(pert, 1);
+            }
+            pl[a] = p;
+            D.qinv[r0 + p] = r0 + a;
+            taken[p] = 1;
+            pls[a] = p;
+            *s_p = p;
+        }
+        __syncthreads();
+        p = *s_p;
+        const T d = Ba[p];
+        for (int r = a + 1 + tid; r < m; r += NT) {
+            const T l = blk[r * m + p] / d;
+            blk[r * m + p] = l;
+            lrow[r] = l;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < (m - a - 1) * m; idx += NT) {
+            const int r = a + 1 + idx / m, c = idx % m;
+            if (taken[c]) continue;
+            blk[r * m + c] -= lrow[r] * Ba[c];
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < m * m; idx += NT) {
+        const int r = idx / m, a = idx % m;
+        P[(int64_t)r * W + a] = blk[idx];
+        lm[idx] = a < r ? blk[r * m + pls[a]] : T(0);
+    }
+    __syncthreads();
+    for (int c = m + tid; c < wc; c += NT) {
+        T x[kSnLds];
+#pragma unroll
+        for (int r = 0; r < kSnLds; r++) x[r] = r < m ? P[(int64_t)r * W + c] : T(0);
+#pragma unroll
+        for (int r = 1; r < kSnLds; r++) {
+            if (r < m) {
+                T acc = x[r];
+#pragma unroll
+                for (int a = 0; a < r; a++) acc -= lm[r * m + a] * x[a];
+                x[r] = acc;
+            }
+        }
+#pragma unroll
+        for (int r = 1; r < kSnLds; r++)
+            if (r < m) P[(int64_t)r * W + c] = x[r];
+    }
+}
+
 // inverse of node v's block in pivot order after its LU (the rule of
 // k_sn_inverse, the block read from its panel): thread j solves U_pp x = e_j
 template <typename T, int NT>
@@ -554,9 +651,19 @@ __global__ __launch_bounds__(NT) void k_factor_snlu(DevLayout D, T* __restrict__
     __shared__ int s_p;
     const int v = nodes[blockIdx.x];
     const int m = D.m[v];
-    T* lrow = reinterpret_cast<T*>(smem_raw);                       // m multipliers
-    uint8_t* taken = smem_raw + sizeof(T) * (size_t)m;             // m flags
-    snlu_node<T, NT>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p, threadIdx.x);
+    if (m <= kSnLds) {
+        T* blk = reinterpret_cast<T*>(smem_raw);                    // m x m
+        T* lm = blk + m * m;                                        // m x m
+        T* lrow = lm + m * m;                                       // m
+        int* pls = reinterpret_cast<int*>(lrow + m);                // m
+        uint8_t* taken = reinterpret_cast<uint8_t*>(pls + m);       // m
+        snlu_node_lds<T, NT>(D, vals, v, tau, pert, search, blk, lm, lrow, pls, taken, red_v, red_i, &s_p,
+                             threadIdx.x);
+    } else {
+        T* lrow = reinterpret_cast<T*>(smem_raw);                   // m multipliers
+        uint8_t* taken = smem_raw + sizeof(T) * (size_t)m;         // m flags
+        snlu_node<T, NT>(D, vals, v, tau, pert, search, lrow, taken, red_v, red_i, &s_p, threadIdx.x);
+    }
     if (inv_off && inv_off[v] >= 0) {
         __syncthreads();        // the block and its pivot order are complete
         sn_inverse_node<T, NT>(D, vals, v, reinterpret_cast<T*>(const_cast<void*>(D.uinv)) + inv_off[v], threadIdx.x);
@@ -2736,8 +2843,12 @@ hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const i
                               const int64_t* inv_off, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    size_t sh = (size_t)maxm * ((fp32 ? sizeof(float) : sizeof(double)) + 1) + 16;
+    const size_t es = fp32 ? sizeof(float) : sizeof(double);
+    size_t sh = (size_t)maxm * (es + 1) + 16;
     if (sh > 60 * 1024) return hipErrorInvalidValue;   // larger blocks need the tiled path
+    // blocks of at most kSnLds rows in LDS (two m x m buffers)
+    const size_t sl = (size_t)std::min(maxm, kSnLds);
+    sh = std::max(sh, 2 * sl * sl * es + sl * (es + 4 + 1) + 16);
     if (nt == 0) nt = 256;
     if (nt != 64 && nt != 256) return hipErrorInvalidValue;
     if (fp32) {
