@@ -47,7 +47,7 @@ typedef enum {
     HYLU_ERR_NOT_ANALYZED = -4,     /* factorize/solve before analyze */
     HYLU_ERR_NOT_FACTORIZED = -5,   /* refactor/solve before factorize */
     HYLU_ERR_OOM = -6,              /* host or device allocation failed; handle stays valid */
-    HYLU_ERR_DEVICE = -7,           /* a HIP call failed */
+    HYLU_ERR_DEVICE = -7,           /* a HIP call failed, or a kernel reported a failure (a pipeline-mode wait that gave up) */
     HYLU_ERR_NONFINITE = -8,        /* NaN or Inf in the input values */
     HYLU_ERR_INTERNAL = -9,
     HYLU_ERR_SCRATCH = -10,         /* hylu_solve_noalloc: n x nrhs beyond its fixed scratch */
@@ -106,13 +106,16 @@ typedef struct {
                                 (<= 0: default 2048) */
     int32_t group_tail_rows; /* a block-sparse dense tail takes panel groups from this many rows on, or when its
                                 plan keeps over half of the dense work (<= 0: default 16384) */
-    int32_t solve_chain;     /* 1: runs of at least 3 consecutive narrow forward / backward solve levels (at most 64
+    int32_t solve_chain;     /* 1: runs of at least 3 consecutive narrow forward / backward solve levels (at most 16
                                 nodes of at most 64 rows each) are solved by one workgroup in one launch, a barrier
                                 between levels, instead of one launch per level (Sec. 2.3; default 1) */
     int32_t gpu_symbolic;    /* 1: hylu_analyze computes the symbolic structure of the factors and the four level sets
                                 on the current GPU (Sec. 2.1, 2.2.1): the same structure, supernodes and levels as the
                                 host analysis, to the bit.  Independent blocks (a batch's members) of at most 1 << 20
                                 rows each; HYLU_ERR_ARG otherwise.  0: on the host (default) */
+    int32_t pipeline_spin;   /* pipeline mode: polls of a wait before it gives up, which ends every other wait of
+                                the launch and makes the factorisation return HYLU_ERR_DEVICE (the factors are
+                                void); <= 0: default 2^21 (tens of milliseconds, far beyond any real wait) */
 } hylu_options;
 
 /* Optional device allocator (e.g. the PyTorch caching allocator).  alloc

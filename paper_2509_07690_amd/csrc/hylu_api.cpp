@@ -899,7 +899,8 @@ hylu_status enqueue_factor(hylu_handle h, const double* d_val, bool search, hipS
                 LAUNCH(C_PIPE, by, fl,
                        launch_factor_chain(h->fp32, h->D, h->vals, h->d_ctask + ch.t0, h->d_csthr + ch.t0,
                                            (int32_t)(ch.t1 - ch.t0), ch.nw, ch.cap, kChainSw, h->tau, h->d_pert,
-                                           search ? 1 : 0, h->d_inv_off, kChainSpin, st));
+                                           search ? 1 : 0, h->d_inv_off,
+                                           h->opt.pipeline_spin > 0 ? h->opt.pipeline_spin : kChainSpin, st));
             }
             l = lend - 1;
             continue;
@@ -2282,6 +2283,7 @@ hylu_status hylu_default_options(hylu_options* o)
     o->pipeline_rows = 0;
     o->solve_chain = 1;
     o->gpu_symbolic = 0;
+    o->pipeline_spin = 0;
     o->group_min_rows = kGroupMinRows;
     o->group_tail_rows = kGroupTailRows;
     return HYLU_OK;

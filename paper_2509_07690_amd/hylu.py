@@ -41,7 +41,7 @@ class Options(C.Structure):
                 ("tail_max", C.c_int32), ("sn_dense", C.c_int32),
                 ("sn_tile", C.c_int32), ("sn_inverse", C.c_int32), ("tail_sparse", C.c_int32), ("side_rows", C.c_int32),
                 ("pipeline_rows", C.c_int32), ("group_min_rows", C.c_int32), ("group_tail_rows", C.c_int32),
-                ("solve_chain", C.c_int32), ("gpu_symbolic", C.c_int32)]
+                ("solve_chain", C.c_int32), ("gpu_symbolic", C.c_int32), ("pipeline_spin", C.c_int32)]
 
 
 class Info(C.Structure):

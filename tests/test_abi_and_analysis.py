@@ -257,6 +257,7 @@ def test_default_options_and_schedule_options_leave_the_analysis_alone():
     block-sparse tail issues fewer flops than the dense one."""
     o = hylu.default_options()
     assert (o.sn_dense, o.sn_tile, o.sn_inverse, o.tail_sparse, o.side_rows, o.pipeline_rows) == (64, 0, 1, 1, 1, 0)
+    assert (o.solve_chain, o.gpu_symbolic, o.pipeline_spin) == (1, 0, 0)
     A = synth.circuit_powerlaw(20000).A
     ref = None
     for opts in ({}, dict(tail_sparse=0), dict(side_rows=0), dict(sn_inverse=0)):

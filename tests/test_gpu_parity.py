@@ -436,3 +436,24 @@ def test_pipelined_bit_identical(hylu, case):
         assert np.array_equal(out[0][1][k], out[1][1][k]), k
     assert np.array_equal(out[0][2], out[1][2])
     assert out[0][3] == out[1][3]
+
+
+def test_pipelined_wait_gives_up_cleanly(hylu):
+    """The waits of a chain launch are bounded: with the poll limit forced to
+    one from the host, a wait gives up at once, every other wait of the launch
+    stops, the launch ends, and the factorisation reports a device error (its
+    factors void) instead of hanging.  A handle with the default limit then
+    factorises the same matrix and matches the oracle."""
+    w = synth.circuit_powerlaw(20000)
+    A = w.A
+    opts = dict(amd_dense=0.1, dense_tail=0.15, pipeline_rows=16)
+    print("[case] circuit 20000 pipeline_spin=1", flush=True)
+    h = hylu.Handle(A.row_ptr, A.col, A.val, pipeline_spin=1, **opts)
+    assert h.info()["pipe_tasks"] > 0
+    h.factorize(dev(A.val))
+    torch.cuda.synchronize()
+    with pytest.raises(hylu.HyluError) as e:
+        h.info()
+    assert e.value.code == -7                # HYLU_ERR_DEVICE
+    h2, o, x, xo, eta = run_case(hylu, A, w.b[:, 0], opts=opts)
+    assert rel_diff(x, xo) <= 1e-10 and eta <= 1e-12
