@@ -2773,7 +2773,9 @@ hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const i
     if (stage < kStage || stage > kStageMax || stage % 64) return hipErrorInvalidValue;
     const int32_t cap = std::min(maxW, lds_cap > 0 ? lds_cap : kRowLdsCap);
     if (nt == 0) nt = maxW > 1024 ? 256 : 64;                      // default: 4 waves per row for long rows
-    const size_t sh = factor_rows_lds(fp32, stage, cap);
+    // (room for the block LU of a supernode of up to 64 rows done in this launch)
+    const size_t es = fp32 ? sizeof(float) : sizeof(double);
+    const size_t sh = std::max(factor_rows_lds(fp32, stage, cap), (size_t)nt * (es + 4) + 64 * (es + 1) + 16);
     if (sh > kLdsMax) return hipErrorInvalidValue;
     const dim3 g(nrows);
 #define ROWS_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_rows<TT, NTT>), g, dim3(NTT), sh, st, D, (TT*)vals, rows, ranges, nrows, cap, (TT)tau, pert, stage, search, inv_off)
