@@ -107,8 +107,9 @@ typedef struct {
     int32_t group_tail_rows; /* a block-sparse dense tail takes panel groups from this many rows on, or when its
                                 plan keeps over half of the dense work (<= 0: default 16384) */
     int32_t solve_chain;     /* 1: runs of at least 3 consecutive narrow forward / backward solve levels (at most 16
-                                nodes of at most 64 rows each) are solved by one workgroup in one launch, a barrier
-                                between levels, instead of one launch per level (Sec. 2.3; default 1) */
+                                nodes of at most 64 rows and 8192 entries in their L (U) part each) are solved by one
+                                workgroup in one launch, a barrier between levels, instead of one launch per level
+                                (Sec. 2.3; default 1) */
     int32_t gpu_symbolic;    /* 1: hylu_analyze computes the symbolic structure of the factors and the four level sets
                                 on the current GPU (Sec. 2.1, 2.2.1): the same structure, supernodes and levels as the
                                 host analysis, to the bit.  Independent blocks (a batch's members) of at most 1 << 20
@@ -116,6 +117,10 @@ typedef struct {
     int32_t pipeline_spin;   /* pipeline mode: polls of a wait before it gives up, which ends every other wait of
                                 the launch and makes the factorisation return HYLU_ERR_DEVICE (the factors are
                                 void); <= 0: default 2^21 (tens of milliseconds, far beyond any real wait) */
+    int32_t solve_split;     /* 1: in the forward solve, a supernode of 8..64 rows with at least 8192 entries in its L
+                                region has the sums over that region spread over workgroups of 8 rows each, then its
+                                diagonal block solved, with the same values to the bit (default 1); 0: one
+                                workgroup per supernode */
 } hylu_options;
 
 /* Optional device allocator (e.g. the PyTorch caching allocator).  alloc
@@ -156,6 +161,8 @@ typedef struct {
     double sym_kernel_ms;             /* of which GPU kernel time (gpu_symbolic; else 0) */
     uint64_t sym_hash;                /* hash of the compressed structure and the level sets (equal hashes: equal
                                          analyses) */
+    int32_t split_sn;                 /* supernodes whose forward solve (Sec. 2.3) spreads the sums over their long
+                                         L region across workgroups, a group of rows each */
 } hylu_info;
 
 /* Analysis export for checking: every array is host memory the caller

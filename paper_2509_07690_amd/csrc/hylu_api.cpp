@@ -199,7 +199,13 @@ struct hylu_handle_s {
     ViewDesc* d_vdesc = nullptr;
     std::vector<int32_t> dsn_ptr;           // per factor level into dsn
     std::vector<std::vector<int32_t>> dsn_l, dsn_u;   // per L-solve / U-solve level: dsn indices
-    std::vector<int32_t> lsolve_sn;         // per L-solve level: 1 if it has a supernode for k_lsolve_sn
+    // per L-solve level (offsets into the lists, nl + 1 each): its supernodes
+    // of kLsolveSnMin..64 rows solved whole by k_lsolve_sn, those whose
+    // outside sums are split over workgroups (k_lsolve_out tasks: node, first
+    // row), and whether it has a node for the one-wavefront kernel
+    std::vector<int32_t> lsn_ptr, lsp_ptr, ltask_ptr, lsn_nodes, lsp_nodes, ltasks;
+    std::vector<uint8_t> lsolve_small;
+    int32_t *d_lsn_nodes = nullptr, *d_lsp_nodes = nullptr, *d_ltasks = nullptr;
     std::vector<int32_t> usolve_sn;         // per U-solve level: 1 if it has a supernode for k_usolve_sn
     // per solve graph (4: L, 1: U): for every level that starts a chain of
     // narrow levels solved in one launch, the end of the chain (else -1)
@@ -487,8 +493,11 @@ constexpr int32_t kRowCapSmall = 4096, kRowCapBig = 10240;
 // four-wavefront forward-solve kernel
 constexpr int32_t kLsolveSnMin = 8;
 // a run of at least kChainMin solve levels of at most kChainNodes nodes is
-// solved by one workgroup in one launch
+// solved by one workgroup in one launch (one wavefront per node), if no node
+// has more than kChainWork entries in its L (U) part; a supernode with more
+// takes workgroups by groups of rows in the forward solve
 constexpr int32_t kChainMin = 3, kChainNodes = 16;
+constexpr int64_t kChainWork = 8192, kSplitWork = 8192;
 // pipeline mode: nodes per chain launch (one LDS flag each), staging values
 // per wavefront (at least the largest supernode with a block inverse), polls
 // before a wait gives up (tens of milliseconds, far beyond any real wait), and
@@ -1007,8 +1016,10 @@ hylu_status enqueue_solve(hylu_handle h, const SolveWs& w, const double* b, int6
     if (!transpose) {
         HIPCHK(launch_permute_in(f, n, nrhs, h->d_perm_r, h->d_dr, b, ldb, w.y, st));
         s = levels(4, [&](const int32_t* nodes, int32_t c, size_t l) {
-            const int32_t with = l < h->lsolve_sn.size() ? h->lsolve_sn[l] : 0;
-            return launch_lsolve(f, h->D, h->vals, nodes, c, w.y, nrhs, kLsolveSnMin, with, st);
+            const int32_t s0 = h->lsn_ptr[l], p0 = h->lsp_ptr[l], k0 = h->ltask_ptr[l];
+            return launch_lsolve(f, h->D, h->vals, nodes, h->lsolve_small[l] ? c : 0, h->d_lsn_nodes + s0,
+                                 h->lsn_ptr[l + 1] - s0, h->d_lsp_nodes + p0, h->lsp_ptr[l + 1] - p0,
+                                 h->d_ltasks + 2 * (int64_t)k0, h->ltask_ptr[l + 1] - k0, w.y, nrhs, kLsolveSnMin, st);
         });
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
@@ -1196,6 +1207,7 @@ hylu_status upload_device(hylu_handle h)
         if (!h->d_uinv) return HYLU_ERR_OOM;
         D.uinv = h->d_uinv;
         for (int g = 0; g < 5; g++) UP(h->d_lev[g], L.xlev_nodes[g]);
+        UP(h->d_lsn_nodes, h->lsn_nodes); UP(h->d_lsp_nodes, h->lsp_nodes); UP(h->d_ltasks, h->ltasks);
         for (int g : {4, 1}) UP(h->d_lev_ptr[g], L.xlev_ptr[g]);
         {
             TailView& TVw = h->TV;
@@ -1883,13 +1895,29 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         h->inv_ptr.push_back((int64_t)h->inv_nodes.size());
         h->inv_maxm.push_back(mm);
     }
-    // L-solve levels with a supernode of kLsolveSnMin..64 rows
-    h->lsolve_sn.assign(L.xlev_ptr[4].size() > 0 ? L.xlev_ptr[4].size() - 1 : 0, 0);
-    for (size_t l = 0; l + 1 < L.xlev_ptr[4].size(); l++)
-        for (int32_t t = L.xlev_ptr[4][l]; t < L.xlev_ptr[4][l + 1]; t++) {
-            const int32_t m = L.m[L.xlev_nodes[4][t]];
-            if (m >= kLsolveSnMin && m <= 64) h->lsolve_sn[l] = 1;
+    // the L-solve levels' supernodes of kLsolveSnMin..64 rows: whole, or with
+    // their outside sums split by rows when the L region is long
+    {
+        std::vector<uint8_t> dense(L.nnodes, 0);
+        for (const hylu_handle_s::DenseSn& q : h->dsn) dense[q.v] = 1;
+        h->lsn_ptr.assign(1, 0); h->lsp_ptr.assign(1, 0); h->ltask_ptr.assign(1, 0);
+        h->lsn_nodes.clear(); h->lsp_nodes.clear(); h->ltasks.clear(); h->lsolve_small.clear();
+        for (size_t l = 0; l + 1 < L.xlev_ptr[4].size(); l++) {
+            uint8_t small = 0;
+            for (int32_t t = L.xlev_ptr[4][l]; t < L.xlev_ptr[4][l + 1]; t++) {
+                const int32_t v = L.xlev_nodes[4][t], m = L.m[v];
+                if (dense[v]) continue;
+                if (m < kLsolveSnMin || m > 64) { small = 1; continue; }
+                if (!opt.solve_split || (int64_t)m * L.lw[v] < kSplitWork) { h->lsn_nodes.push_back(v); continue; }
+                h->lsp_nodes.push_back(v);
+                for (int32_t g0 = 0; g0 < m; g0 += kSplitRows) { h->ltasks.push_back(v); h->ltasks.push_back(g0); }
+            }
+            h->lsolve_small.push_back(small);
+            h->lsn_ptr.push_back((int32_t)h->lsn_nodes.size());
+            h->lsp_ptr.push_back((int32_t)h->lsp_nodes.size());
+            h->ltask_ptr.push_back((int32_t)h->ltasks.size() / 2);
         }
+    }
     h->usolve_sn.assign(L.xlev_ptr[1].size() > 0 ? L.xlev_ptr[1].size() - 1 : 0, 0);
     for (size_t l = 0; l + 1 < L.xlev_ptr[1].size(); l++)
         for (int32_t t = L.xlev_ptr[1][l]; t < L.xlev_ptr[1][l + 1]; t++) {
@@ -1919,7 +1947,11 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         auto ok = [&](int32_t l) {
             const int32_t a = L.xlev_ptr[g][l], b = L.xlev_ptr[g][l + 1];
             if (b - a > kChainNodes || (l < (int32_t)dl.size() && !dl[l].empty())) return false;
-            for (int32_t t = a; t < b; t++) if (L.m[L.xlev_nodes[g][t]] > kChainRows) return false;
+            for (int32_t t = a; t < b; t++) {
+                const int32_t v = L.xlev_nodes[g][t];
+                if (L.m[v] > kChainRows) return false;
+                if ((int64_t)L.m[v] * (g == 4 ? L.lw[v] : L.W[v] - L.lw[v]) > kChainWork) return false;
+            }
             return true;
         };
         for (int32_t l = 0; l < nlv;) {
@@ -1928,6 +1960,22 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
             if (e - l >= kChainMin) h->chain_end[g][l] = e;
             l = std::max(e, l + 1);
         }
+        // HYLU_LOG=2: every solve chain with its factor entries (the L or U
+        // part of its nodes' rows)
+        if (const char* lg = std::getenv("HYLU_LOG"); lg && std::atoi(lg) >= 2)
+            for (int32_t l = 0; l < nlv; l++) {
+                if (h->chain_end[g][l] <= l) continue;
+                int64_t nodes = 0, sum = 0, mx = 0;
+                for (int32_t t = L.xlev_ptr[g][l]; t < L.xlev_ptr[g][h->chain_end[g][l]]; t++) {
+                    const int32_t v = L.xlev_nodes[g][t];
+                    const int64_t e = (int64_t)L.m[v] * (g == 4 ? L.lw[v] : L.W[v] - L.lw[v]);
+                    nodes++;
+                    sum += e;
+                    mx = std::max(mx, e);
+                }
+                std::fprintf(stderr, "hylu: %s solve chain levels [%d, %d) nodes %lld entries %lld max/node %lld\n",
+                             g == 4 ? "L" : "U", l, h->chain_end[g][l], (long long)nodes, (long long)sum, (long long)mx);
+            }
     }
     T.chain_lev = chain_lev;
     T.chain_start.assign(nl, -1);
@@ -2284,6 +2332,7 @@ hylu_status hylu_default_options(hylu_options* o)
     o->solve_chain = 1;
     o->gpu_symbolic = 0;
     o->pipeline_spin = 0;
+    o->solve_split = 1;
     o->group_min_rows = kGroupMinRows;
     o->group_tail_rows = kGroupTailRows;
     return HYLU_OK;
@@ -2668,6 +2717,7 @@ hylu_status hylu_get_info(hylu_handle h, hylu_info* o)
     for (int g : {4, 1})
         for (size_t l = 0; l < h->chain_end[g].size(); l++)
             if (h->chain_end[g][l] > (int32_t)l) o->chain_levels += h->chain_end[g][l] - (int32_t)l;
+    o->split_sn = (int32_t)h->lsp_nodes.size();
     o->pipe_tasks = (int32_t)h->ft.ctask.size();
     o->sn_groups = h->sn_groups;
     o->tail_groups = h->tail_groups;

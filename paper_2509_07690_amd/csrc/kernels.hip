@@ -1129,11 +1129,12 @@ __global__ __launch_bounds__(64) void k_lsolve(DevLayout D, const T* __restrict_
 // the rows' gathers over the L region are independent and run first, spread
 // over the wavefronts; the unit-lower block (row a's multiplier for an earlier
 // row b at b's pivot column) is then swept column by column on wavefront 0,
-// one lane per row, with the block staged in LDS
+// one lane per row, with the block staged in LDS.  pre = 1: the outside sums
+// were already subtracted from y by k_lsolve_out (only the block is swept)
 template <typename T>
 __global__ __launch_bounds__(256) void k_lsolve_sn(DevLayout D, const T* __restrict__ vals,
                                                    const int32_t* __restrict__ nodes, int32_t count,
-                                                   T* __restrict__ y, int32_t nrhs, int32_t sn_min)
+                                                   T* __restrict__ y, int32_t nrhs, int32_t sn_min, int32_t pre)
 {
     __shared__ T Lb[kSnSolveRows][kSnSolveRows + 1];   // Lb[r][b] = L(r, b), b < r
     __shared__ T ys[kSnSolveRows];
@@ -1144,6 +1145,7 @@ __global__ __launch_bounds__(256) void k_lsolve_sn(DevLayout D, const T* __restr
     if (m < sn_min || m > kSnSolveRows) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const int lwo = pre ? 0 : lw;        // columns of the outside sums done here
     const T* P = vals + D.voff[v];
     const int32_t* cols = D.cols + D.coff[v];
     const int32_t* pl = D.pl + r0;
@@ -1160,8 +1162,8 @@ __global__ __launch_bounds__(256) void k_lsolve_sn(DevLayout D, const T* __restr
         T acc[kSnSolveRows / 4];
 #pragma unroll
         for (int i = 0; i < kSnSolveRows / 4; i++) acc[i] = T(0);
-        for (int c0 = 0; c0 < lw; c0 += kSolveChunk) {
-            const int nc = min(kSolveChunk, lw - c0);
+        for (int c0 = 0; c0 < lwo; c0 += kSolveChunk) {
+            const int nc = min(kSolveChunk, lwo - c0);
             stage_lq<T, 256>(cols + c0, D.qinv, yr, nc, tid, ychunk);
             __syncthreads();
 #pragma unroll
@@ -1192,6 +1194,64 @@ __global__ __launch_bounds__(256) void k_lsolve_sn(DevLayout D, const T* __restr
             if (lane < m) yr[r0 + lane] = va;
         }
         __syncthreads();
+    }
+}
+
+// the outside sums of the forward solve of a supernode with a long L region,
+// spread over workgroups by groups of kSplitRows rows (task: node, first
+// row), two rows per wavefront: row a subtracts sum_k L(a,k) y_k from y_a in
+// place, each lane summing its entries t = lane + 64 j in ascending order as
+// k_lsolve_sn does, so that k_lsolve_sn (pre = 1) finishing the block gives
+// the same values to the bit
+template <typename T>
+__global__ __launch_bounds__(256) void k_lsolve_out(DevLayout D, const T* __restrict__ vals,
+                                                    const int32_t* __restrict__ tasks, int32_t count,
+                                                    T* __restrict__ y, int32_t nrhs)
+{
+    __shared__ T ychunk[kSolveChunk];
+    const int v = tasks[2 * blockIdx.x], g0 = tasks[2 * blockIdx.x + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const T* P = vals + D.voff[v];
+    const int32_t* cols = D.cols + D.coff[v];
+    const int n = D.n;
+    for (int r = 0; r < nrhs; r++) {
+        T* yr = y + (int64_t)r * n;
+        T acc[kSplitRows / 4];
+#pragma unroll
+        for (int i = 0; i < kSplitRows / 4; i++) acc[i] = T(0);
+        for (int c0 = 0; c0 < lw; c0 += kSolveChunk) {
+            const int nc = min(kSolveChunk, lw - c0);
+            stage_lq<T, 256>(cols + c0, D.qinv, yr, nc, tid, ychunk);
+            __syncthreads();
+            // four entries of each row per lane loaded before they are used
+            for (int t0 = lane; t0 < nc; t0 += 256) {
+                T p[kSplitRows / 4][4];
+#pragma unroll
+                for (int i = 0; i < kSplitRows / 4; i++) {
+                    const int a = g0 + wv + 4 * i;
+                    const T* Pa = P + (int64_t)min(a, m - 1) * W + c0;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) p[i][u] = a < m && t0 + 64 * u < nc ? Pa[t0 + 64 * u] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    if (t0 + 64 * u >= nc) break;
+                    const T yv = ychunk[t0 + 64 * u];
+#pragma unroll
+                    for (int i = 0; i < kSplitRows / 4; i++) acc[i] += p[i][u] * yv;
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < kSplitRows / 4; i++) {
+            const int a = g0 + wv + 4 * i;
+            if (a < m) {
+                const T s = wave_sum(acc[i]);
+                if (lane == 0) yr[r0 + a] -= s;
+            }
+        }
     }
 }
 
@@ -2864,16 +2924,30 @@ hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const i
 }
 
 hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
-                         void* y, int32_t nrhs, int32_t sn_min, int32_t with_sn, hipStream_t st)
+                         const int32_t* sn_nodes, int32_t sn_count, const int32_t* split_nodes, int32_t split_count,
+                         const int32_t* tasks, int32_t ntasks, void* y, int32_t nrhs, int32_t sn_min, hipStream_t st)
 {
-    if (count <= 0) return hipSuccess;
-    if (!with_sn || sn_min > kSnSolveRows) sn_min = 0;    // every node by k_lsolve
-    if (fp32) hipLaunchKernelGGL(k_lsolve<float>, dim3(count), dim3(64), 0, st, D, (const float*)vals, nodes, count, (float*)y, nrhs, sn_min);
-    else hipLaunchKernelGGL(k_lsolve<double>, dim3(count), dim3(64), 0, st, D, (const double*)vals, nodes, count, (double*)y, nrhs, sn_min);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || sn_min <= 0) return e;
-    if (fp32) hipLaunchKernelGGL(k_lsolve_sn<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (float*)y, nrhs, sn_min);
-    else hipLaunchKernelGGL(k_lsolve_sn<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (double*)y, nrhs, sn_min);
+    if (sn_min <= 0 || sn_min > kSnSolveRows) sn_min = 0;    // every node by k_lsolve
+    if (count > 0) {
+        if (fp32) hipLaunchKernelGGL(k_lsolve<float>, dim3(count), dim3(64), 0, st, D, (const float*)vals, nodes, count, (float*)y, nrhs, sn_min);
+        else hipLaunchKernelGGL(k_lsolve<double>, dim3(count), dim3(64), 0, st, D, (const double*)vals, nodes, count, (double*)y, nrhs, sn_min);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (sn_min <= 0) return hipSuccess;
+    if (sn_count > 0) {
+        if (fp32) hipLaunchKernelGGL(k_lsolve_sn<float>, dim3(sn_count), dim3(256), 0, st, D, (const float*)vals, sn_nodes, sn_count, (float*)y, nrhs, sn_min, 0);
+        else hipLaunchKernelGGL(k_lsolve_sn<double>, dim3(sn_count), dim3(256), 0, st, D, (const double*)vals, sn_nodes, sn_count, (double*)y, nrhs, sn_min, 0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (split_count <= 0 || ntasks <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_lsolve_out<float>, dim3(ntasks), dim3(256), 0, st, D, (const float*)vals, tasks, ntasks, (float*)y, nrhs);
+    else hipLaunchKernelGGL(k_lsolve_out<double>, dim3(ntasks), dim3(256), 0, st, D, (const double*)vals, tasks, ntasks, (double*)y, nrhs);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (fp32) hipLaunchKernelGGL(k_lsolve_sn<float>, dim3(split_count), dim3(256), 0, st, D, (const float*)vals, split_nodes, split_count, (float*)y, nrhs, sn_min, 1);
+    else hipLaunchKernelGGL(k_lsolve_sn<double>, dim3(split_count), dim3(256), 0, st, D, (const double*)vals, split_nodes, split_count, (double*)y, nrhs, sn_min, 1);
     return hipGetLastError();
 }
 

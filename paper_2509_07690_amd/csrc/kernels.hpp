@@ -221,10 +221,16 @@ hipError_t launch_sn_inverse(bool fp32, const DevLayout& D, const void* vals, co
 hipError_t launch_factor_snlu(bool fp32, const DevLayout& D, void* vals, const int32_t* nodes, int32_t count,
                               int32_t maxm, double tau, int32_t* pert, int32_t search, int32_t nt,
                               const int64_t* inv_off, hipStream_t st);
-// forward L solve of a level's nodes; supernodes of sn_min..64 rows (sn_min > 0)
-// go to a four-wavefront kernel, launched when with_sn says the level has one
+// forward L solve of a level.  The one-wavefront kernel takes the `count`
+// nodes of `nodes` except supernodes of sn_min..64 rows (sn_min > 0; count 0:
+// no launch); those are listed in sn_nodes (solved by one four-wavefront
+// workgroup each) or, with a long L region, in split_nodes: their outside sums
+// first by `ntasks` workgroups of kSplitRows rows (tasks: node, first row
+// pairs), then their diagonal blocks
+constexpr int kSplitRows = 8;
 hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
-                         void* y, int32_t nrhs, int32_t sn_min, int32_t with_sn, hipStream_t st);
+                         const int32_t* sn_nodes, int32_t sn_count, const int32_t* split_nodes, int32_t split_count,
+                         const int32_t* tasks, int32_t ntasks, void* y, int32_t nrhs, int32_t sn_min, hipStream_t st);
 hipError_t launch_usolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
                          const void* y, void* x, int32_t nrhs, int32_t sn_min, int32_t with_sn, hipStream_t st);
 // a chain of narrow solve levels [l0, l1) in one launch of one workgroup

@@ -41,7 +41,8 @@ class Options(C.Structure):
                 ("tail_max", C.c_int32), ("sn_dense", C.c_int32),
                 ("sn_tile", C.c_int32), ("sn_inverse", C.c_int32), ("tail_sparse", C.c_int32), ("side_rows", C.c_int32),
                 ("pipeline_rows", C.c_int32), ("group_min_rows", C.c_int32), ("group_tail_rows", C.c_int32),
-                ("solve_chain", C.c_int32), ("gpu_symbolic", C.c_int32), ("pipeline_spin", C.c_int32)]
+                ("solve_chain", C.c_int32), ("gpu_symbolic", C.c_int32), ("pipeline_spin", C.c_int32),
+                ("solve_split", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -54,7 +55,7 @@ class Info(C.Structure):
                 ("resid_1", C.c_double), ("n_dense_sn", C.c_int32), ("sn_groups", C.c_int32),
                 ("tail_groups", C.c_int32), ("pipe_tasks", C.c_int32),
                 ("chain_levels", C.c_int32), ("sym_ms", C.c_double), ("sym_kernel_ms", C.c_double),
-                ("sym_hash", C.c_uint64)]
+                ("sym_hash", C.c_uint64), ("split_sn", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

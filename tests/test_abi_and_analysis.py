@@ -250,6 +250,21 @@ def test_analysis_full_size_batch():
     assert np.array_equal(o.level_arrays(), sym["levels"])
 
 
+def test_solve_split_leaves_the_analysis_alone():
+    """solve_split only decides how the forward solve of long supernodes is
+    launched: the symbolic result and the solve chains stay the same, and a
+    batch member with long separator supernodes has some to split."""
+    A = synth.batch_member(0).A
+    h1 = hylu.Handle(A.row_ptr, A.col, A.val)
+    h0 = hylu.Handle(A.row_ptr, A.col, A.val, solve_split=0)
+    i1, i0 = h1.info(), h0.info()
+    assert i1["split_sn"] > 0 and i0["split_sn"] == 0
+    assert i1["chain_levels"] == i0["chain_levels"] and i1["sym_hash"] == i0["sym_hash"]
+    s1, s0 = h1.symbolic(), h0.symbolic()
+    for k in ("perm_r", "perm_c", "node_ptr", "levels"):
+        assert np.array_equal(s1[k], s0[k]), k
+
+
 def test_default_options_and_schedule_options_leave_the_analysis_alone():
     """Defaults as documented in include/hylu.h; the options that only change
     how the numerical work is launched (block-sparse tail, deferred-row
@@ -257,7 +272,7 @@ def test_default_options_and_schedule_options_leave_the_analysis_alone():
     block-sparse tail issues fewer flops than the dense one."""
     o = hylu.default_options()
     assert (o.sn_dense, o.sn_tile, o.sn_inverse, o.tail_sparse, o.side_rows, o.pipeline_rows) == (64, 0, 1, 1, 1, 0)
-    assert (o.solve_chain, o.gpu_symbolic, o.pipeline_spin) == (1, 0, 0)
+    assert (o.solve_chain, o.gpu_symbolic, o.pipeline_spin, o.solve_split) == (1, 0, 0, 1)
     A = synth.circuit_powerlaw(20000).A
     ref = None
     for opts in ({}, dict(tail_sparse=0), dict(side_rows=0), dict(sn_inverse=0)):

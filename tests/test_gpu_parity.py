@@ -396,6 +396,35 @@ def test_solve_chains(hylu, case):
             assert o.backward_error(b, x)[0] <= 1e-12
 
 
+@pytest.mark.parametrize("member", [0, 2])
+def test_solve_split_bit_identical(hylu, member):
+    """Forward solve of supernodes with a long L region (Sec. 2.3): the sums
+    over that region spread over workgroups of eight rows, then the diagonal
+    block, give the solution of one workgroup per supernode to the bit (the
+    same per-row order), in FP64 and FP32; with nrhs 3 as well; and the FP64
+    solution agrees with the oracle's."""
+    w = synth.batch_member(member)
+    A = w.A
+    rng = np.random.default_rng(7)
+    B = rng.standard_normal((A.n, 3))
+    print(f"[case] solve split, batch member {member} n={A.n}", flush=True)
+    for precision in ("fp64", "fp32"):
+        h1 = hylu.Handle(A.row_ptr, A.col, A.val, precision=precision)
+        h0 = hylu.Handle(A.row_ptr, A.col, A.val, precision=precision, solve_split=0)
+        assert h1.info()["split_sn"] > 0 and h0.info()["split_sn"] == 0
+        xs = []
+        for h in (h1, h0):
+            h.factorize(dev(A.val))
+            xs.append((h.solve(dev(B[:, 0])).cpu().numpy(), h.solve(dev(B)).cpu().numpy()))
+        assert np.array_equal(h1.factors_raw()["vals"], h0.factors_raw()["vals"])
+        assert np.array_equal(xs[0][0], xs[1][0]) and np.array_equal(xs[0][1], xs[1][1])
+        if precision == "fp64":
+            o, _ = oracle_for(h1, A)
+            o.numeric(o.tau)
+            assert rel_diff(xs[0][0], o.solve(B[:, 0])) <= 1e-10
+            assert o.backward_error(B[:, 0], xs[0][0])[0] <= 1e-12
+
+
 @pytest.mark.parametrize("case", ["config0", "circuit", "circuit_fp32", "grid3d"])
 def test_pipelined_bit_identical(hylu, case):
     """Pipeline mode (Sec. 2.2.1): the runs of narrow levels in chain launches,
