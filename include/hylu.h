@@ -117,10 +117,10 @@ typedef struct {
     int32_t pipeline_spin;   /* pipeline mode: polls of a wait before it gives up, which ends every other wait of
                                 the launch and makes the factorisation return HYLU_ERR_DEVICE (the factors are
                                 void); <= 0: default 2^21 (tens of milliseconds, far beyond any real wait) */
-    int32_t solve_split;     /* 1: in the forward solve, a supernode of 8..64 rows with at least 8192 entries in its L
-                                region has the sums over that region spread over workgroups of 8 rows each, then its
-                                diagonal block solved, with the same values to the bit (default 1); 0: one
-                                workgroup per supernode */
+    int32_t solve_split;     /* 1: a supernode of 8..64 rows with at least 8192 entries in its L region (forward
+                                solve) or in its U columns past the diagonal block (backward solve) has the sums over
+                                them spread over workgroups of 8 rows each, then its diagonal block solved, with the
+                                same values to the bit (default 1); 0: one workgroup per supernode */
 } hylu_options;
 
 /* Optional device allocator (e.g. the PyTorch caching allocator).  alloc
@@ -161,8 +161,8 @@ typedef struct {
     double sym_kernel_ms;             /* of which GPU kernel time (gpu_symbolic; else 0) */
     uint64_t sym_hash;                /* hash of the compressed structure and the level sets (equal hashes: equal
                                          analyses) */
-    int32_t split_sn;                 /* supernodes whose forward solve (Sec. 2.3) spreads the sums over their long
-                                         L region across workgroups, a group of rows each */
+    int32_t split_sn;                 /* forward plus backward solves of supernodes (Sec. 2.3) whose sums over a long
+                                         L region / U columns are spread across workgroups by rows (solve_split) */
 } hylu_info;
 
 /* Analysis export for checking: every array is host memory the caller

@@ -199,14 +199,16 @@ struct hylu_handle_s {
     ViewDesc* d_vdesc = nullptr;
     std::vector<int32_t> dsn_ptr;           // per factor level into dsn
     std::vector<std::vector<int32_t>> dsn_l, dsn_u;   // per L-solve / U-solve level: dsn indices
-    // per L-solve level (offsets into the lists, nl + 1 each): its supernodes
-    // of kLsolveSnMin..64 rows solved whole by k_lsolve_sn, those whose
-    // outside sums are split over workgroups (k_lsolve_out tasks: node, first
-    // row), and whether it has a node for the one-wavefront kernel
-    std::vector<int32_t> lsn_ptr, lsp_ptr, ltask_ptr, lsn_nodes, lsp_nodes, ltasks;
-    std::vector<uint8_t> lsolve_small;
-    int32_t *d_lsn_nodes = nullptr, *d_lsp_nodes = nullptr, *d_ltasks = nullptr;
-    std::vector<int32_t> usolve_sn;         // per U-solve level: 1 if it has a supernode for k_usolve_sn
+    // per forward (0) / backward (1) solve level (offsets into the lists,
+    // levels + 1 each): its supernodes of kLsolveSnMin..64 rows solved whole
+    // by the four-wavefront kernel, those whose sums over their L region (U
+    // columns past the block) are split over workgroups by rows (tasks: node,
+    // first row), and whether it has a node for the per-row kernel
+    struct SolveLists {
+        std::vector<int32_t> sn_ptr, sp_ptr, task_ptr, sn_nodes, sp_nodes, tasks;
+        std::vector<uint8_t> small;
+        int32_t *d_sn = nullptr, *d_sp = nullptr, *d_tasks = nullptr;
+    } sl[2];
     // per solve graph (4: L, 1: U): for every level that starts a chain of
     // narrow levels solved in one launch, the end of the chain (else -1)
     std::vector<int32_t> chain_end[5];
@@ -1016,10 +1018,11 @@ hylu_status enqueue_solve(hylu_handle h, const SolveWs& w, const double* b, int6
     if (!transpose) {
         HIPCHK(launch_permute_in(f, n, nrhs, h->d_perm_r, h->d_dr, b, ldb, w.y, st));
         s = levels(4, [&](const int32_t* nodes, int32_t c, size_t l) {
-            const int32_t s0 = h->lsn_ptr[l], p0 = h->lsp_ptr[l], k0 = h->ltask_ptr[l];
-            return launch_lsolve(f, h->D, h->vals, nodes, h->lsolve_small[l] ? c : 0, h->d_lsn_nodes + s0,
-                                 h->lsn_ptr[l + 1] - s0, h->d_lsp_nodes + p0, h->lsp_ptr[l + 1] - p0,
-                                 h->d_ltasks + 2 * (int64_t)k0, h->ltask_ptr[l + 1] - k0, w.y, nrhs, kLsolveSnMin, st);
+            const hylu_handle_s::SolveLists& S = h->sl[0];
+            const int32_t s0 = S.sn_ptr[l], p0 = S.sp_ptr[l], k0 = S.task_ptr[l];
+            return launch_lsolve(f, h->D, h->vals, nodes, S.small[l] ? c : 0, S.d_sn + s0, S.sn_ptr[l + 1] - s0,
+                                 S.d_sp + p0, S.sp_ptr[l + 1] - p0, S.d_tasks + 2 * (int64_t)k0,
+                                 S.task_ptr[l + 1] - k0, w.y, nrhs, kLsolveSnMin, st);
         });
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
@@ -1044,8 +1047,11 @@ hylu_status enqueue_solve(hylu_handle h, const SolveWs& w, const double* b, int6
                                                         inv(k - 1, 1), n, w.y, w.z, nrhs, 1, st));
         }
         s = levels(1, [&](const int32_t* nodes, int32_t c, size_t l) {
-            const int32_t with = l < h->usolve_sn.size() ? h->usolve_sn[l] : 0;
-            return launch_usolve(f, h->D, h->vals, nodes, c, w.y, w.z, nrhs, kLsolveSnMin, with, st);
+            const hylu_handle_s::SolveLists& S = h->sl[1];
+            const int32_t s0 = S.sn_ptr[l], p0 = S.sp_ptr[l], k0 = S.task_ptr[l];
+            return launch_usolve(f, h->D, h->vals, nodes, S.small[l] ? c : 0, S.d_sn + s0, S.sn_ptr[l + 1] - s0,
+                                 S.d_sp + p0, S.sp_ptr[l + 1] - p0, S.d_tasks + 2 * (int64_t)k0,
+                                 S.task_ptr[l + 1] - k0, w.y, w.z, nrhs, kLsolveSnMin, st);
         });
         if (s != HYLU_OK) return s;
         HIPCHK(launch_permute_out(f, n, nrhs, h->d_perm_c, h->d_dc, w.z, x, ldx, accumulate, st));
@@ -1207,7 +1213,7 @@ hylu_status upload_device(hylu_handle h)
         if (!h->d_uinv) return HYLU_ERR_OOM;
         D.uinv = h->d_uinv;
         for (int g = 0; g < 5; g++) UP(h->d_lev[g], L.xlev_nodes[g]);
-        UP(h->d_lsn_nodes, h->lsn_nodes); UP(h->d_lsp_nodes, h->lsp_nodes); UP(h->d_ltasks, h->ltasks);
+        for (hylu_handle_s::SolveLists& S : h->sl) { UP(S.d_sn, S.sn_nodes); UP(S.d_sp, S.sp_nodes); UP(S.d_tasks, S.tasks); }
         for (int g : {4, 1}) UP(h->d_lev_ptr[g], L.xlev_ptr[g]);
         {
             TailView& TVw = h->TV;
@@ -1895,35 +1901,35 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
         h->inv_ptr.push_back((int64_t)h->inv_nodes.size());
         h->inv_maxm.push_back(mm);
     }
-    // the L-solve levels' supernodes of kLsolveSnMin..64 rows: whole, or with
-    // their outside sums split by rows when the L region is long
+    // the forward and backward solve levels' supernodes of kLsolveSnMin..64
+    // rows: whole, or split by rows when their L region (the U columns past
+    // their block) is long
     {
         std::vector<uint8_t> dense(L.nnodes, 0);
         for (const hylu_handle_s::DenseSn& q : h->dsn) dense[q.v] = 1;
-        h->lsn_ptr.assign(1, 0); h->lsp_ptr.assign(1, 0); h->ltask_ptr.assign(1, 0);
-        h->lsn_nodes.clear(); h->lsp_nodes.clear(); h->ltasks.clear(); h->lsolve_small.clear();
-        for (size_t l = 0; l + 1 < L.xlev_ptr[4].size(); l++) {
-            uint8_t small = 0;
-            for (int32_t t = L.xlev_ptr[4][l]; t < L.xlev_ptr[4][l + 1]; t++) {
-                const int32_t v = L.xlev_nodes[4][t], m = L.m[v];
-                if (dense[v]) continue;
-                if (m < kLsolveSnMin || m > 64) { small = 1; continue; }
-                if (!opt.solve_split || (int64_t)m * L.lw[v] < kSplitWork) { h->lsn_nodes.push_back(v); continue; }
-                h->lsp_nodes.push_back(v);
-                for (int32_t g0 = 0; g0 < m; g0 += kSplitRows) { h->ltasks.push_back(v); h->ltasks.push_back(g0); }
+        for (int k = 0; k < 2; k++) {
+            const int g = k == 0 ? 4 : 1;
+            hylu_handle_s::SolveLists& S = h->sl[k];
+            S.sn_ptr.assign(1, 0); S.sp_ptr.assign(1, 0); S.task_ptr.assign(1, 0);
+            S.sn_nodes.clear(); S.sp_nodes.clear(); S.tasks.clear(); S.small.clear();
+            for (size_t l = 0; l + 1 < L.xlev_ptr[g].size(); l++) {
+                uint8_t small = 0;
+                for (int32_t t = L.xlev_ptr[g][l]; t < L.xlev_ptr[g][l + 1]; t++) {
+                    const int32_t v = L.xlev_nodes[g][t], m = L.m[v];
+                    if (dense[v]) continue;
+                    if (m < kLsolveSnMin || m > 64) { small = 1; continue; }
+                    const int64_t len = k == 0 ? L.lw[v] : L.W[v] - L.lw[v] - m;
+                    if (!opt.solve_split || (int64_t)m * len < kSplitWork) { S.sn_nodes.push_back(v); continue; }
+                    S.sp_nodes.push_back(v);
+                    for (int32_t g0 = 0; g0 < m; g0 += kSplitRows) { S.tasks.push_back(v); S.tasks.push_back(g0); }
+                }
+                S.small.push_back(small);
+                S.sn_ptr.push_back((int32_t)S.sn_nodes.size());
+                S.sp_ptr.push_back((int32_t)S.sp_nodes.size());
+                S.task_ptr.push_back((int32_t)S.tasks.size() / 2);
             }
-            h->lsolve_small.push_back(small);
-            h->lsn_ptr.push_back((int32_t)h->lsn_nodes.size());
-            h->lsp_ptr.push_back((int32_t)h->lsp_nodes.size());
-            h->ltask_ptr.push_back((int32_t)h->ltasks.size() / 2);
         }
     }
-    h->usolve_sn.assign(L.xlev_ptr[1].size() > 0 ? L.xlev_ptr[1].size() - 1 : 0, 0);
-    for (size_t l = 0; l + 1 < L.xlev_ptr[1].size(); l++)
-        for (int32_t t = L.xlev_ptr[1][l]; t < L.xlev_ptr[1][l + 1]; t++) {
-            const int32_t m = L.m[L.xlev_nodes[1][t]];
-            if (m >= kLsolveSnMin && m <= 64) h->usolve_sn[l] = 1;
-        }
     // the large supernodes' places in the L-solve and U-solve level sequences
     {
         std::vector<int32_t> dix(L.nnodes, -1);
@@ -2717,7 +2723,7 @@ hylu_status hylu_get_info(hylu_handle h, hylu_info* o)
     for (int g : {4, 1})
         for (size_t l = 0; l < h->chain_end[g].size(); l++)
             if (h->chain_end[g][l] > (int32_t)l) o->chain_levels += h->chain_end[g][l] - (int32_t)l;
-    o->split_sn = (int32_t)h->lsp_nodes.size();
+    o->split_sn = (int32_t)(h->sl[0].sp_nodes.size() + h->sl[1].sp_nodes.size());
     o->pipe_tasks = (int32_t)h->ft.ctask.size();
     o->sn_groups = h->sn_groups;
     o->tail_groups = h->tail_groups;

@@ -1411,12 +1411,13 @@ __global__ __launch_bounds__(256) void k_usolve(DevLayout D, const T* __restrict
 // rows' gathers over the shared T columns do not depend on the block and run
 // first, spread over the wavefronts; the block (U_st(a, piv b), b >= a, in
 // pivot order, staged in LDS) is then swept column by column from the last
-// one on wavefront 0, one lane per row
+// one on wavefront 0, one lane per row.  pre = 1: the gathers' sums were
+// already subtracted from y by k_usolve_out (only the block is swept)
 template <typename T>
 __global__ __launch_bounds__(256) void k_usolve_sn(DevLayout D, const T* __restrict__ vals,
                                                    const int32_t* __restrict__ nodes, int32_t count,
                                                    const T* __restrict__ y, T* __restrict__ x, int32_t nrhs,
-                                                   int32_t sn_min)
+                                                   int32_t sn_min, int32_t pre)
 {
     __shared__ T Ub[kSnSolveRows][kSnSolveRows + 1];
     __shared__ T ys[kSnSolveRows];
@@ -1428,7 +1429,7 @@ __global__ __launch_bounds__(256) void k_usolve_sn(DevLayout D, const T* __restr
     if (m < sn_min || m > kSnSolveRows) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
-    const int w = W - lw - m;
+    const int w = pre ? 0 : W - lw - m;          // columns of the gathers done here
     const T* P = vals + D.voff[v] + lw;
     const int32_t* tc = D.cols + D.coff[v] + lw + m;
     const int n = D.n;
@@ -1479,6 +1480,64 @@ __global__ __launch_bounds__(256) void k_usolve_sn(DevLayout D, const T* __restr
             if (lane < m) xr[r0 + pls[lane]] = xv;
         }
         __syncthreads();
+    }
+}
+
+// the gathers of the backward solve of a supernode with many columns past its
+// block, spread over workgroups of kSplitRows rows (task: node, first row),
+// two rows per wavefront: row a subtracts sum_j U(a,j) x_j over those
+// columns from its y_a in place (y is the solve's work vector, read by no
+// one else afterwards), each lane in k_usolve_sn's order
+template <typename T>
+__global__ __launch_bounds__(256) void k_usolve_out(DevLayout D, const T* __restrict__ vals,
+                                                    const int32_t* __restrict__ tasks, int32_t count,
+                                                    T* __restrict__ y, const T* __restrict__ x, int32_t nrhs)
+{
+    __shared__ T xchunk[kSolveChunk];
+    const int v = tasks[2 * blockIdx.x], g0 = tasks[2 * blockIdx.x + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const int w = W - lw - m;
+    const T* P = vals + D.voff[v] + lw + m;
+    const int32_t* tc = D.cols + D.coff[v] + lw + m;
+    const int n = D.n;
+    for (int r = 0; r < nrhs; r++) {
+        T* yr = y + (int64_t)r * n;
+        const T* xr = x + (int64_t)r * n;
+        T acc[kSplitRows / 4];
+#pragma unroll
+        for (int i = 0; i < kSplitRows / 4; i++) acc[i] = T(0);
+        for (int c0 = 0; c0 < w; c0 += kSolveChunk) {
+            const int nc = min(kSolveChunk, w - c0);
+            stage_x<T, 256>(tc + c0, xr, nc, tid, xchunk);
+            __syncthreads();
+            for (int t0 = lane; t0 < nc; t0 += 256) {
+                T p[kSplitRows / 4][4];
+#pragma unroll
+                for (int i = 0; i < kSplitRows / 4; i++) {
+                    const int a = g0 + wv + 4 * i;
+                    const T* Pa = P + (int64_t)min(a, m - 1) * W + c0;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) p[i][u] = a < m && t0 + 64 * u < nc ? Pa[t0 + 64 * u] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    if (t0 + 64 * u >= nc) break;
+                    const T xv = xchunk[t0 + 64 * u];
+#pragma unroll
+                    for (int i = 0; i < kSplitRows / 4; i++) acc[i] += p[i][u] * xv;
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < kSplitRows / 4; i++) {
+            const int a = g0 + wv + 4 * i;
+            if (a < m) {
+                const T s = wave_sum(acc[i]);
+                if (lane == 0) yr[r0 + a] -= s;
+            }
+        }
     }
 }
 
@@ -2952,16 +3011,31 @@ hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const 
 }
 
 hipError_t launch_usolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
-                         const void* y, void* x, int32_t nrhs, int32_t sn_min, int32_t with_sn, hipStream_t st)
+                         const int32_t* sn_nodes, int32_t sn_count, const int32_t* split_nodes, int32_t split_count,
+                         const int32_t* tasks, int32_t ntasks, void* y, void* x, int32_t nrhs, int32_t sn_min,
+                         hipStream_t st)
 {
-    if (count <= 0) return hipSuccess;
-    if (!with_sn || sn_min > kSnSolveRows) sn_min = 0;    // every node by k_usolve
-    if (fp32) hipLaunchKernelGGL(k_usolve<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (const float*)y, (float*)x, nrhs, sn_min);
-    else hipLaunchKernelGGL(k_usolve<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (const double*)y, (double*)x, nrhs, sn_min);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || sn_min <= 0) return e;
-    if (fp32) hipLaunchKernelGGL(k_usolve_sn<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (const float*)y, (float*)x, nrhs, sn_min);
-    else hipLaunchKernelGGL(k_usolve_sn<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (const double*)y, (double*)x, nrhs, sn_min);
+    if (sn_min <= 0 || sn_min > kSnSolveRows) sn_min = 0;    // every node by k_usolve
+    if (count > 0) {
+        if (fp32) hipLaunchKernelGGL(k_usolve<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (const float*)y, (float*)x, nrhs, sn_min);
+        else hipLaunchKernelGGL(k_usolve<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (const double*)y, (double*)x, nrhs, sn_min);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (sn_min <= 0) return hipSuccess;
+    if (sn_count > 0) {
+        if (fp32) hipLaunchKernelGGL(k_usolve_sn<float>, dim3(sn_count), dim3(256), 0, st, D, (const float*)vals, sn_nodes, sn_count, (const float*)y, (float*)x, nrhs, sn_min, 0);
+        else hipLaunchKernelGGL(k_usolve_sn<double>, dim3(sn_count), dim3(256), 0, st, D, (const double*)vals, sn_nodes, sn_count, (const double*)y, (double*)x, nrhs, sn_min, 0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (split_count <= 0 || ntasks <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_usolve_out<float>, dim3(ntasks), dim3(256), 0, st, D, (const float*)vals, tasks, ntasks, (float*)y, (const float*)x, nrhs);
+    else hipLaunchKernelGGL(k_usolve_out<double>, dim3(ntasks), dim3(256), 0, st, D, (const double*)vals, tasks, ntasks, (double*)y, (const double*)x, nrhs);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (fp32) hipLaunchKernelGGL(k_usolve_sn<float>, dim3(split_count), dim3(256), 0, st, D, (const float*)vals, split_nodes, split_count, (const float*)y, (float*)x, nrhs, sn_min, 1);
+    else hipLaunchKernelGGL(k_usolve_sn<double>, dim3(split_count), dim3(256), 0, st, D, (const double*)vals, split_nodes, split_count, (const double*)y, (double*)x, nrhs, sn_min, 1);
     return hipGetLastError();
 }
 

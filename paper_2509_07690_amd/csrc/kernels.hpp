@@ -231,8 +231,12 @@ constexpr int kSplitRows = 8;
 hipError_t launch_lsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
                          const int32_t* sn_nodes, int32_t sn_count, const int32_t* split_nodes, int32_t split_count,
                          const int32_t* tasks, int32_t ntasks, void* y, int32_t nrhs, int32_t sn_min, hipStream_t st);
+// backward U solve of a level, the same way (split_nodes: the gathers over
+// the columns past the block spread by rows, subtracted from y in place)
 hipError_t launch_usolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
-                         const void* y, void* x, int32_t nrhs, int32_t sn_min, int32_t with_sn, hipStream_t st);
+                         const int32_t* sn_nodes, int32_t sn_count, const int32_t* split_nodes, int32_t split_count,
+                         const int32_t* tasks, int32_t ntasks, void* y, void* x, int32_t nrhs, int32_t sn_min,
+                         hipStream_t st);
 // a chain of narrow solve levels [l0, l1) in one launch of one workgroup
 // (kChainWaves wavefronts, a node per wavefront, a barrier between levels);
 // lev_ptr: the level pointers of the solve graph's node list `nodes`; every
