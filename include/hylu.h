@@ -120,7 +120,10 @@ typedef struct {
     int32_t solve_split;     /* 1: a supernode of 8..64 rows with at least 8192 entries in its L region (forward
                                 solve) or in its U columns past the diagonal block (backward solve) has the sums over
                                 them spread over workgroups of 8 rows each, then its diagonal block solved, with the
-                                same values to the bit (default 1); 0: one workgroup per supernode */
+                                same values to the bit; in the transposed solves every node of 8 rows or more has
+                                its sums over the entries outside its block spread over workgroups of 8 columns,
+                                then its block solved 64 columns at a time (another summation order; default 1).
+                                0: one workgroup per node, its rows (columns) one after the other */
 } hylu_options;
 
 /* Optional device allocator (e.g. the PyTorch caching allocator).  alloc
@@ -161,8 +164,9 @@ typedef struct {
     double sym_kernel_ms;             /* of which GPU kernel time (gpu_symbolic; else 0) */
     uint64_t sym_hash;                /* hash of the compressed structure and the level sets (equal hashes: equal
                                          analyses) */
-    int32_t split_sn;                 /* forward plus backward solves of supernodes (Sec. 2.3) whose sums over a long
-                                         L region / U columns are spread across workgroups by rows (solve_split) */
+    int32_t split_sn;                 /* supernode solves (Sec. 2.3), summed over the forward, backward and two
+                                         transposed solves, whose sums over the entries outside the node's block are
+                                         spread across workgroups by rows (columns when transposed; solve_split) */
 } hylu_info;
 
 /* Analysis export for checking: every array is host memory the caller

@@ -209,6 +209,10 @@ struct hylu_handle_s {
         std::vector<uint8_t> small;
         int32_t *d_sn = nullptr, *d_sp = nullptr, *d_tasks = nullptr;
     } sl[2];
+    // the same for the transposed U^T (0) / L^T (1) solve levels: sn = the
+    // nodes solved column by column, sp = those of kLsolveSnMin rows or more
+    // (outside sums split by columns, then the block)
+    SolveLists tl[2];
     // per solve graph (4: L, 1: U): for every level that starts a chain of
     // narrow levels solved in one launch, the end of the chain (else -1)
     std::vector<int32_t> chain_end[5];
@@ -1057,7 +1061,13 @@ hylu_status enqueue_solve(hylu_handle h, const SolveWs& w, const double* b, int6
         HIPCHK(launch_permute_out(f, n, nrhs, h->d_perm_c, h->d_dc, w.z, x, ldx, accumulate, st));
     } else {
         HIPCHK(launch_permute_in(f, n, nrhs, h->d_perm_c, h->d_dc, b, ldb, w.y, st));
-        s = levels(2, [&](const int32_t* nodes, int32_t c, size_t) { return launch_utsolve(f, h->D, h->vals, nodes, c, w.y, w.z, nrhs, st); });
+        s = levels(2, [&](const int32_t*, int32_t, size_t l) {
+            const hylu_handle_s::SolveLists& S = h->tl[0];
+            const int32_t s0 = S.sn_ptr[l], p0 = S.sp_ptr[l], k0 = S.task_ptr[l];
+            return launch_utsolve(f, h->D, h->vals, S.d_sn + s0, S.sn_ptr[l + 1] - s0, S.d_sp + p0,
+                                  S.sp_ptr[l + 1] - p0, S.d_tasks + 2 * (int64_t)k0, S.task_ptr[l + 1] - k0, w.y, w.z,
+                                  nrhs, st);
+        });
         if (s != HYLU_OK) return s;
         if (L.mT > 0) {
             LAUNCH(C_TSOLVE, 0, 0, launch_tail_utext(f, h->D, h->TV, h->vals, w.y, w.z, nrhs, st));
@@ -1080,7 +1090,13 @@ hylu_status enqueue_solve(hylu_handle h, const SolveWs& w, const double* b, int6
                 LAUNCH(C_TSOLVE, 0, 0, launch_tail_step(f, h->TV, h->vals, SP[k].p0, SP[k].p1, SP[k - 1].p0, SP[k - 1].p1,
                                                         inv(k - 1, 0), n, w.z, w.z, nrhs, 3, st));
         }
-        s = levels(3, [&](const int32_t* nodes, int32_t c, size_t) { return launch_ltsolve(f, h->D, h->vals, nodes, c, w.z, nrhs, st); });
+        s = levels(3, [&](const int32_t*, int32_t, size_t l) {
+            const hylu_handle_s::SolveLists& S = h->tl[1];
+            const int32_t s0 = S.sn_ptr[l], p0 = S.sp_ptr[l], k0 = S.task_ptr[l];
+            return launch_ltsolve(f, h->D, h->vals, S.d_sn + s0, S.sn_ptr[l + 1] - s0, S.d_sp + p0,
+                                  S.sp_ptr[l + 1] - p0, S.d_tasks + 2 * (int64_t)k0, S.task_ptr[l + 1] - k0, w.z, nrhs,
+                                  st);
+        });
         if (s != HYLU_OK) return s;
         HIPCHK(launch_permute_out(f, n, nrhs, h->d_perm_r, h->d_dr, w.z, x, ldx, accumulate, st));
     }
@@ -1214,6 +1230,7 @@ hylu_status upload_device(hylu_handle h)
         D.uinv = h->d_uinv;
         for (int g = 0; g < 5; g++) UP(h->d_lev[g], L.xlev_nodes[g]);
         for (hylu_handle_s::SolveLists& S : h->sl) { UP(S.d_sn, S.sn_nodes); UP(S.d_sp, S.sp_nodes); UP(S.d_tasks, S.tasks); }
+        for (hylu_handle_s::SolveLists& S : h->tl) { UP(S.d_sn, S.sn_nodes); UP(S.d_sp, S.sp_nodes); UP(S.d_tasks, S.tasks); }
         for (int g : {4, 1}) UP(h->d_lev_ptr[g], L.xlev_ptr[g]);
         {
             TailView& TVw = h->TV;
@@ -1924,6 +1941,23 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
                     for (int32_t g0 = 0; g0 < m; g0 += kSplitRows) { S.tasks.push_back(v); S.tasks.push_back(g0); }
                 }
                 S.small.push_back(small);
+                S.sn_ptr.push_back((int32_t)S.sn_nodes.size());
+                S.sp_ptr.push_back((int32_t)S.sp_nodes.size());
+                S.task_ptr.push_back((int32_t)S.tasks.size() / 2);
+            }
+        }
+        for (int k = 0; k < 2; k++) {
+            const int g = k == 0 ? 2 : 3;
+            hylu_handle_s::SolveLists& S = h->tl[k];
+            S.sn_ptr.assign(1, 0); S.sp_ptr.assign(1, 0); S.task_ptr.assign(1, 0);
+            S.sn_nodes.clear(); S.sp_nodes.clear(); S.tasks.clear(); S.small.clear();
+            for (size_t l = 0; l + 1 < L.xlev_ptr[g].size(); l++) {
+                for (int32_t t = L.xlev_ptr[g][l]; t < L.xlev_ptr[g][l + 1]; t++) {
+                    const int32_t v = L.xlev_nodes[g][t], m = L.m[v];
+                    if (!opt.solve_split || m < kLsolveSnMin) { S.sn_nodes.push_back(v); continue; }
+                    S.sp_nodes.push_back(v);
+                    for (int32_t g0 = 0; g0 < m; g0 += kSplitRows) { S.tasks.push_back(v); S.tasks.push_back(g0); }
+                }
                 S.sn_ptr.push_back((int32_t)S.sn_nodes.size());
                 S.sp_ptr.push_back((int32_t)S.sp_nodes.size());
                 S.task_ptr.push_back((int32_t)S.tasks.size() / 2);
@@ -2723,7 +2757,8 @@ hylu_status hylu_get_info(hylu_handle h, hylu_info* o)
     for (int g : {4, 1})
         for (size_t l = 0; l < h->chain_end[g].size(); l++)
             if (h->chain_end[g][l] > (int32_t)l) o->chain_levels += h->chain_end[g][l] - (int32_t)l;
-    o->split_sn = (int32_t)(h->sl[0].sp_nodes.size() + h->sl[1].sp_nodes.size());
+    o->split_sn = (int32_t)(h->sl[0].sp_nodes.size() + h->sl[1].sp_nodes.size() + h->tl[0].sp_nodes.size() +
+                            h->tl[1].sp_nodes.size());
     o->pipe_tasks = (int32_t)h->ft.ctask.size();
     o->sn_groups = h->sn_groups;
     o->tail_groups = h->tail_groups;

@@ -1599,6 +1599,147 @@ __global__ __launch_bounds__(256) void k_ltsolve(DevLayout D, const T* __restric
     }
 }
 
+// Transposed solves of a node of at least 8 rows in two launches.  First the
+// sums over the entries outside the node, which only need solved values of
+// other nodes: for each of the node's columns c_a = r0 + piv a, by
+// workgroups of kSplitRows columns (task: node, first column), two per
+// wavefront, gathered through the transposed index (U^T: the entries of
+// column c_a in rows of earlier nodes, against w; L^T: in rows of later
+// nodes, against u) and subtracted in place (U^T: from h[c_a], h being the
+// solve's work vector; L^T: from w[r0 + a]).  Then the node's own
+// triangular block, 64 columns at a time (k_utsolve_blk, k_ltsolve_blk).
+template <typename T, bool UT>
+__global__ __launch_bounds__(256) void k_tsolve_out(DevLayout D, const T* __restrict__ vals,
+                                                    const int32_t* __restrict__ tasks, int32_t count,
+                                                    T* __restrict__ h, const T* __restrict__ w, int32_t nrhs)
+{
+    const int v = tasks[2 * blockIdx.x], g0 = tasks[2 * blockIdx.x + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = D.m[v], r0 = D.r0[v];
+    const int32_t* pl = D.pl + r0;
+    const int64_t* ptr = UT ? D.ut_ptr : D.lt_ptr;
+    const int64_t* slot = UT ? D.ut_slot : D.lt_slot;
+    const int32_t* row = UT ? D.ut_row : D.lt_row;
+    const int n = D.n;
+    for (int r = 0; r < nrhs; r++) {
+        T* hr = h + (int64_t)r * n;
+        const T* wr = w + (int64_t)r * n;
+#pragma unroll
+        for (int i = 0; i < kSplitRows / 4; i++) {
+            const int a = g0 + wv + 4 * i;
+            if (a >= m) break;
+            const int c = r0 + pl[a];
+            T s = gather_sr<T, 64>(vals, slot, row, wr, ptr[c], ptr[c + 1], lane);
+            s = wave_sum(s);
+            if (lane == 0) hr[UT ? c : r0 + a] -= s;
+        }
+    }
+}
+
+// U^T w = h on a node's block after k_tsolve_out: columns in ascending blocks
+// of 64; in a block, wavefront 0 sweeps w_a = h[c_a] / U(a, c_a) and takes
+// U(a, c_k) w_a off the later columns k of the block (one lane each); the
+// whole workgroup then takes the block's products off the node's later
+// columns
+template <typename T>
+__global__ __launch_bounds__(256) void k_utsolve_blk(DevLayout D, const T* __restrict__ vals,
+                                                     const int32_t* __restrict__ nodes, int32_t count,
+                                                     T* __restrict__ h, T* __restrict__ w, int32_t nrhs)
+{
+    __shared__ T Ub[64][65];          // Ub[i][k] = U(a0+i, c_{a0+k}), k >= i
+    __shared__ T wb[64];
+    const int v = nodes[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const T* P = vals + D.voff[v] + lw;
+    const int32_t* pl = D.pl + r0;
+    const int n = D.n;
+    for (int r = 0; r < nrhs; r++) {
+        T* hr = h + (int64_t)r * n;
+        T* wr = w + (int64_t)r * n;
+        for (int a0 = 0; a0 < m; a0 += 64) {
+            const int mb = min(64, m - a0);
+            for (int idx = tid; idx < mb * mb; idx += 256) {
+                const int i = idx / mb, k = idx - (idx / mb) * mb;
+                Ub[i][k] = k >= i ? P[(int64_t)(a0 + i) * W + pl[a0 + k]] : T(0);
+            }
+            __syncthreads();
+            if (wv == 0) {
+                T va = lane < mb ? hr[r0 + pl[a0 + lane]] : T(0);
+                T wv0 = T(0);
+                for (int i = 0; i < mb; i++) {
+                    const T wi = bcast(va, i) / Ub[i][i];
+                    if (lane == i) wv0 = wi;
+                    if (lane > i && lane < mb) va -= Ub[i][lane] * wi;
+                }
+                if (lane < mb) {
+                    wb[lane] = wv0;
+                    wr[r0 + a0 + lane] = wv0;
+                }
+            }
+            __syncthreads();
+            for (int k = a0 + mb + tid; k < m; k += 256) {
+                const int pk = pl[k];
+                T acc = T(0);
+                for (int i = 0; i < mb; i++) acc += P[(int64_t)(a0 + i) * W + pk] * wb[i];
+                hr[r0 + pk] -= acc;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// L^T u = w on a node's block after k_tsolve_out (in place): columns in
+// descending blocks of 64; in a block, wavefront 0 sweeps from the last
+// column, taking L(a, k) u_a off the earlier columns k of the block; the
+// whole workgroup then takes the block's products off the node's earlier
+// columns
+template <typename T>
+__global__ __launch_bounds__(256) void k_ltsolve_blk(DevLayout D, const T* __restrict__ vals,
+                                                     const int32_t* __restrict__ nodes, int32_t count,
+                                                     T* __restrict__ w, int32_t nrhs)
+{
+    __shared__ T Lb[64][65];          // Lb[i][k] = L(a0+i, a0+k) at column piv(a0+k), k < i
+    __shared__ T ub[64];
+    const int v = nodes[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = D.m[v], W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
+    const T* P = vals + D.voff[v] + lw;
+    const int32_t* pl = D.pl + r0;
+    const int n = D.n;
+    const int nb = (m + 63) / 64;
+    for (int r = 0; r < nrhs; r++) {
+        T* wr = w + (int64_t)r * n;
+        for (int jb = nb - 1; jb >= 0; jb--) {
+            const int a0 = jb * 64, mb = min(64, m - a0);
+            for (int idx = tid; idx < mb * mb; idx += 256) {
+                const int i = idx / mb, k = idx - (idx / mb) * mb;
+                Lb[i][k] = k < i ? P[(int64_t)(a0 + i) * W + pl[a0 + k]] : T(0);
+            }
+            __syncthreads();
+            if (wv == 0) {
+                T va = lane < mb ? wr[r0 + a0 + lane] : T(0);
+                for (int i = mb - 1; i >= 0; i--) {
+                    const T ui = bcast(va, i);
+                    if (lane < i) va -= Lb[i][lane] * ui;
+                }
+                if (lane < mb) {
+                    ub[lane] = va;
+                    wr[r0 + a0 + lane] = va;
+                }
+            }
+            __syncthreads();
+            for (int k = tid; k < a0; k += 256) {
+                const int pk = pl[k];
+                T acc = T(0);
+                for (int i = 0; i < mb; i++) acc += P[(int64_t)(a0 + i) * W + pk] * ub[i];
+                wr[r0 + k] -= acc;
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------
 // permutation / scaling, FP64 residual and norms, gradient
 // ----------------------------------------------------------------------------
@@ -3059,20 +3200,46 @@ hipError_t launch_usolve_chain(bool fp32, const DevLayout& D, const void* vals, 
 }
 
 hipError_t launch_utsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
-                          const void* h, void* w, int32_t nrhs, hipStream_t st)
+                          const int32_t* blk_nodes, int32_t blk_count, const int32_t* tasks, int32_t ntasks,
+                          void* h, void* w, int32_t nrhs, hipStream_t st)
 {
-    if (count <= 0) return hipSuccess;
-    if (fp32) hipLaunchKernelGGL(k_utsolve<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (const float*)h, (float*)w, nrhs);
-    else hipLaunchKernelGGL(k_utsolve<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (const double*)h, (double*)w, nrhs);
+    if (count > 0) {
+        if (fp32) hipLaunchKernelGGL(k_utsolve<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (const float*)h, (float*)w, nrhs);
+        else hipLaunchKernelGGL(k_utsolve<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (const double*)h, (double*)w, nrhs);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (blk_count <= 0) return hipSuccess;
+    if (ntasks > 0) {
+        if (fp32) hipLaunchKernelGGL((k_tsolve_out<float, true>), dim3(ntasks), dim3(256), 0, st, D, (const float*)vals, tasks, ntasks, (float*)h, (const float*)w, nrhs);
+        else hipLaunchKernelGGL((k_tsolve_out<double, true>), dim3(ntasks), dim3(256), 0, st, D, (const double*)vals, tasks, ntasks, (double*)h, (const double*)w, nrhs);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (fp32) hipLaunchKernelGGL(k_utsolve_blk<float>, dim3(blk_count), dim3(256), 0, st, D, (const float*)vals, blk_nodes, blk_count, (float*)h, (float*)w, nrhs);
+    else hipLaunchKernelGGL(k_utsolve_blk<double>, dim3(blk_count), dim3(256), 0, st, D, (const double*)vals, blk_nodes, blk_count, (double*)h, (double*)w, nrhs);
     return hipGetLastError();
 }
 
 hipError_t launch_ltsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
+                          const int32_t* blk_nodes, int32_t blk_count, const int32_t* tasks, int32_t ntasks,
                           void* w, int32_t nrhs, hipStream_t st)
 {
-    if (count <= 0) return hipSuccess;
-    if (fp32) hipLaunchKernelGGL(k_ltsolve<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (float*)w, nrhs);
-    else hipLaunchKernelGGL(k_ltsolve<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (double*)w, nrhs);
+    if (count > 0) {
+        if (fp32) hipLaunchKernelGGL(k_ltsolve<float>, dim3(count), dim3(256), 0, st, D, (const float*)vals, nodes, count, (float*)w, nrhs);
+        else hipLaunchKernelGGL(k_ltsolve<double>, dim3(count), dim3(256), 0, st, D, (const double*)vals, nodes, count, (double*)w, nrhs);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (blk_count <= 0) return hipSuccess;
+    if (ntasks > 0) {
+        if (fp32) hipLaunchKernelGGL((k_tsolve_out<float, false>), dim3(ntasks), dim3(256), 0, st, D, (const float*)vals, tasks, ntasks, (float*)w, (const float*)w, nrhs);
+        else hipLaunchKernelGGL((k_tsolve_out<double, false>), dim3(ntasks), dim3(256), 0, st, D, (const double*)vals, tasks, ntasks, (double*)w, (const double*)w, nrhs);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (fp32) hipLaunchKernelGGL(k_ltsolve_blk<float>, dim3(blk_count), dim3(256), 0, st, D, (const float*)vals, blk_nodes, blk_count, (float*)w, nrhs);
+    else hipLaunchKernelGGL(k_ltsolve_blk<double>, dim3(blk_count), dim3(256), 0, st, D, (const double*)vals, blk_nodes, blk_count, (double*)w, nrhs);
     return hipGetLastError();
 }
 

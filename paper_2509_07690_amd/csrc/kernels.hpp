@@ -248,9 +248,16 @@ hipError_t launch_lsolve_chain(bool fp32, const DevLayout& D, const void* vals, 
 hipError_t launch_usolve_chain(bool fp32, const DevLayout& D, const void* vals, const int32_t* lev_ptr,
                                const int32_t* nodes, int32_t l0, int32_t l1, const void* y, void* x, int32_t nrhs,
                                hipStream_t st);
+// transposed solves of a level: the `count` nodes of `nodes` column by column
+// (one workgroup each), the blk_count nodes of blk_nodes by their outside
+// sums (ntasks workgroups of kSplitRows columns; tasks: node, first column)
+// and then their blocks 64 columns at a time.  U^T: h is the permuted
+// right-hand side, updated in place; L^T: in place in w
 hipError_t launch_utsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
-                          const void* h, void* w, int32_t nrhs, hipStream_t st);
+                          const int32_t* blk_nodes, int32_t blk_count, const int32_t* tasks, int32_t ntasks,
+                          void* h, void* w, int32_t nrhs, hipStream_t st);
 hipError_t launch_ltsolve(bool fp32, const DevLayout& D, const void* vals, const int32_t* nodes, int32_t count,
+                          const int32_t* blk_nodes, int32_t blk_count, const int32_t* tasks, int32_t ntasks,
                           void* w, int32_t nrhs, hipStream_t st);
 // c[i + r n] = scale[perm[i]] * src[perm[i] + r ld]  (gather, into the factor precision)
 hipError_t launch_permute_in(bool fp32, int32_t n, int32_t nrhs, const int32_t* perm, const double* scale,
