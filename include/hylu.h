@@ -122,8 +122,11 @@ typedef struct {
                                 them spread over workgroups of 8 rows each, then its diagonal block solved, with the
                                 same values to the bit; in the transposed solves every node of 8 rows or more has
                                 its sums over the entries outside its block spread over workgroups of 8 columns,
-                                then its block solved 64 columns at a time (another summation order; default 1).
-                                0: one workgroup per node, its rows (columns) one after the other */
+                                then its block solved 64 columns at a time (another summation order); and the
+                                large supernodes of a forward / backward solve level share their launches (their
+                                gathers, then each panel step; the same values to the bit).  Default 1.  0: one
+                                workgroup per node, its rows (columns) one after the other, and one launch
+                                sequence per large supernode */
 } hylu_options;
 
 /* Optional device allocator (e.g. the PyTorch caching allocator).  alloc

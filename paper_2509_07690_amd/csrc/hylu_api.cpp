@@ -213,6 +213,19 @@ struct hylu_handle_s {
     // nodes solved column by column, sp = those of kLsolveSnMin rows or more
     // (outside sums split by columns, then the block)
     SolveLists tl[2];
+    // per forward (0) / backward (1) solve level with two or more large
+    // supernodes (solve_split): their gathers in one launch (ext jobs [e0,
+    // e1)) and their panel steps together, step k of every supernode that has
+    // one in the k-th launch (job ranges)
+    struct ViewSolve {
+        int64_t e0 = 0, e1 = 0;
+        std::vector<std::pair<int64_t, int64_t>> steps;
+    };
+    std::vector<ViewSolve> vsolve[2];
+    std::vector<int32_t> vext_jobs;
+    std::vector<SolveJob> vstep_jobs;
+    int32_t* d_vext = nullptr;
+    SolveJob* d_vstep = nullptr;
     // per solve graph (4: L, 1: U): for every level that starts a chain of
     // narrow levels solved in one launch, the end of the chain (else -1)
     std::vector<int32_t> chain_end[5];
@@ -990,6 +1003,17 @@ hylu_status enqueue_solve(hylu_handle h, const SolveWs& w, const double* b, int6
             if (c > 0) LAUNCH(cls, 0, 0, fn(h->d_lev[g] + a, c, l));
             const std::vector<std::vector<int32_t>>* dl = g == 4 ? &h->dsn_l : g == 1 ? &h->dsn_u : nullptr;
             if (!dl || l >= dl->size()) continue;
+            const std::vector<hylu_handle_s::ViewSolve>& VS = h->vsolve[g == 4 ? 0 : 1];
+            if (l < VS.size() && !VS[l].steps.empty()) {
+                // the level's large supernodes together: gathers, then each step
+                const hylu_handle_s::ViewSolve& V = VS[l];
+                LAUNCH(cls, 0, 0, launch_sn_ext_views(f, h->D, h->vals, h->d_vext + 2 * V.e0, (int32_t)(V.e1 - V.e0), w.y,
+                                                      g == 4 ? nullptr : w.z, nrhs, g == 4 ? 0 : 1, st));
+                for (const auto& J : V.steps)
+                    LAUNCH(cls, 0, 0, launch_view_steps(f, h->d_vdesc, h->d_vstep + J.first, (int32_t)(J.second - J.first),
+                                                        h->vals, n, w.y, g == 4 ? w.y : w.z, nrhs, g == 4 ? 0 : 1, st));
+                continue;
+            }
             for (int32_t q : (*dl)[l]) {
                 const hylu_handle_s::DenseSn& d = h->dsn[q];
                 // one launch per solve panel with the diagonal blocks' inverses
@@ -1263,7 +1287,9 @@ hylu_status upload_device(hylu_handle h)
             q.d_inv = dalloc(h, std::max<size_t>(q.spanels.size(), 1) * 2 * kNB * kNB * (h->fp32 ? 4 : 8));
             if (!q.d_inv) return HYLU_ERR_OOM;
         }
-        if (!h->vjobs.empty()) {
+        UP(h->d_vext, h->vext_jobs);
+        UP(h->d_vstep, h->vstep_jobs);
+        if (!h->vjobs.empty() || !h->vstep_jobs.empty()) {
             std::vector<ViewDesc> vd(h->dsn.size());
             for (size_t q = 0; q < h->dsn.size(); q++) {
                 vd[q].TV = h->dsn[q].TV;
@@ -1271,7 +1297,7 @@ hylu_status upload_device(hylu_handle h)
                 vd[q].inv = h->dsn[q].d_inv;
             }
             UP(h->d_vdesc, vd);
-            UP(h->d_vjobs, h->vjobs);
+            if (!h->vjobs.empty()) UP(h->d_vjobs, h->vjobs);
         }
         if (!h->dsn.empty()) {
             std::vector<uint8_t> fl(L.nnodes, 0);
@@ -1968,12 +1994,60 @@ hylu_status analyze_structure(hylu_handle h, PhaseLog& plog)
     {
         std::vector<int32_t> dix(L.nnodes, -1);
         for (size_t q = 0; q < h->dsn.size(); q++) dix[h->dsn[q].v] = (int32_t)q;
+        h->vext_jobs.clear();
+        h->vstep_jobs.clear();
         for (int g : {4, 1}) {
             auto& out = g == 4 ? h->dsn_l : h->dsn_u;
             out.assign(L.xlev_ptr[g].size() > 0 ? L.xlev_ptr[g].size() - 1 : 0, {});
             for (size_t l = 0; l + 1 < L.xlev_ptr[g].size(); l++)
                 for (int32_t t = L.xlev_ptr[g][l]; t < L.xlev_ptr[g][l + 1]; t++)
                     if (dix[L.xlev_nodes[g][t]] >= 0) out[l].push_back(dix[L.xlev_nodes[g][t]]);
+            // the levels' large supernodes launched together (solve_split)
+            auto& VS = h->vsolve[g == 4 ? 0 : 1];
+            VS.assign(out.size(), {});
+            for (size_t l = 0; opt.solve_split && l < out.size(); l++) {
+                if (out[l].size() < 2) continue;
+                hylu_handle_s::ViewSolve& V = VS[l];
+                V.e0 = (int64_t)h->vext_jobs.size() / 2;
+                size_t nsmax = 0;
+                for (int32_t q : out[l]) {
+                    const hylu_handle_s::DenseSn& d = h->dsn[q];
+                    for (int32_t b = 0; b < (L.m[d.v] + 3) / 4; b++) { h->vext_jobs.push_back(d.v); h->vext_jobs.push_back(b); }
+                    nsmax = std::max(nsmax, d.spanels.size());
+                }
+                V.e1 = (int64_t)h->vext_jobs.size() / 2;
+                for (size_t k = 0; k < nsmax; k++) {
+                    const int64_t j0 = (int64_t)h->vstep_jobs.size();
+                    for (int32_t q : out[l]) {
+                        const hylu_handle_s::DenseSn& d = h->dsn[q];
+                        const std::vector<Layout::Panel>& SP = d.spanels;
+                        const int32_t ns = (int32_t)SP.size(), mT = L.m[d.v];
+                        if ((int32_t)k >= ns) continue;
+                        // the arguments launch_tail_step gets for this step
+                        SolveJob J{};
+                        J.view = q;
+                        if (g == 4) {
+                            const int32_t c = (int32_t)k;          // solved panel
+                            J.q0 = SP[c].p0; J.q1 = SP[c].p1; J.inv = 2 * c;
+                            if (c > 0) { J.p0 = SP[c - 1].p0; J.p1 = SP[c - 1].p1; J.first = J.q1; J.count = mT - J.q1; }
+                        } else {
+                            const int32_t c = ns - 1 - (int32_t)k;
+                            J.q0 = SP[c].p0; J.q1 = SP[c].p1; J.inv = 2 * c + 1;
+                            if (c < ns - 1) { J.p0 = SP[c + 1].p0; J.p1 = SP[c + 1].p1; J.first = 0; J.count = J.q0; }
+                        }
+                        const int32_t nb = 1 + (J.count + 3) / 4;
+                        for (int32_t b = 0; b < nb; b++) { J.blk = b; h->vstep_jobs.push_back(J); }
+                    }
+                    V.steps.push_back({j0, (int64_t)h->vstep_jobs.size()});
+                }
+            }
+            // HYLU_LOG=2: the large supernodes per solve level
+            if (const char* lg = std::getenv("HYLU_LOG"); lg && std::atoi(lg) >= 2) {
+                size_t lv = 0, nv = 0, mx = 0;
+                for (const auto& q : out) if (!q.empty()) { lv++; nv += q.size(); mx = std::max(mx, q.size()); }
+                std::fprintf(stderr, "hylu: %s solve: %zu large supernodes in %zu levels (at most %zu in one)\n",
+                             g == 4 ? "forward" : "backward", nv, lv, mx);
+            }
         }
     }
     // chains of narrow solve levels (Sec. 2.3): maximal runs of at least

@@ -2844,9 +2844,9 @@ __global__ __launch_bounds__(64) void k_tail_dinv(TailView TVp, const T* __restr
 // (modes 0, 1, 3) or a column (mode 2: only those pivoted after the next
 // panel).  p0 == p1: the next panel's diagonal solve only.
 template <typename T>
-__global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restrict__ vals, int p0, int p1, int q0, int q1,
-                                                   const T* __restrict__ inv, int n, T* __restrict__ y,
-                                                   T* __restrict__ x, int nrhs, int mode, int first, int count)
+__device__ __forceinline__ void tail_step_body(const TailView& TV, const T* __restrict__ vals, int p0, int p1, int q0,
+                                               int q1, const T* __restrict__ inv, int n, T* __restrict__ y,
+                                               T* __restrict__ x, int nrhs, int mode, int first, int count, int blk)
 {
     __shared__ T ys[kNB];
     __shared__ T part[4][kNB];
@@ -2859,7 +2859,7 @@ __global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restr
     const int64_t rb = (tr && lane < np) ? TV.trow[b] : 0;    // row b of the current panel
     // coefficient of target e for the current panel's lane b:
     //   modes 0, 1: X_e[piv b];  mode 2: X_b[e];  mode 3: X_b[piv e]
-    if (blockIdx.x == 0) {
+    if (blk == 0) {
         // every load of a phase is issued before its first use: wavefront w
         // takes the next panel's targets w, w+4, ..; the inverse's columns are
         // split the same way and the four partial sums combined in LDS
@@ -2907,7 +2907,7 @@ __global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restr
         }
         return;
     }
-    const int k = (blockIdx.x - 1) * 4 + wv;
+    const int k = (blk - 1) * 4 + wv;
     if (k >= count) return;
     const int e = first + k;
     if (mode == 2 && TV.tstep[e] < q1) return;             // a column solved at or before the next panel
@@ -2929,14 +2929,36 @@ __global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restr
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_tail_step(TailView TV, const T* __restrict__ vals, int p0, int p1, int q0, int q1,
+                                                   const T* __restrict__ inv, int n, T* __restrict__ y,
+                                                   T* __restrict__ x, int nrhs, int mode, int first, int count)
+{
+    tail_step_body<T>(TV, vals, p0, p1, q0, q1, inv, n, y, x, nrhs, mode, first, count, blockIdx.x);
+}
+
+// the same step of several large supernodes of one solve level in one
+// launch: a job per workgroup (its view, that view's step and the
+// workgroup's block within it), each block doing what k_tail_step's does
+template <typename T>
+__global__ __launch_bounds__(256) void k_view_steps(const ViewDesc* __restrict__ vd, const SolveJob* __restrict__ jobs,
+                                                    const T* __restrict__ vals, int n, T* __restrict__ y,
+                                                    T* __restrict__ x, int nrhs, int mode)
+{
+    const SolveJob J = jobs[blockIdx.x];
+    const ViewDesc& V = vd[J.view];
+    const T* inv = reinterpret_cast<const T*>(V.inv) + (int64_t)J.inv * kNB * kNB;
+    tail_step_body<T>(V.TV, vals, J.p0, J.p1, J.q0, J.q1, inv, n, y, x, nrhs, mode, J.first, J.count, J.blk);
+}
+
 // one wavefront per row of a large supernode: the gathers outside its block
 template <typename T>
-__global__ __launch_bounds__(256) void k_sn_ext(DevLayout D, const T* __restrict__ vals, int v,
-                                                T* __restrict__ y, const T* __restrict__ x, int nrhs, int upper)
+__device__ __forceinline__ void sn_ext_body(const DevLayout& D, const T* __restrict__ vals, int v,
+                                            T* __restrict__ y, const T* __restrict__ x, int nrhs, int upper, int blk)
 {
     const int lane = threadIdx.x & 63;
     const int m = D.m[v];
-    const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int a = blk * 4 + (threadIdx.x >> 6);
     if (a >= m) return;
     const int W = D.W[v], lw = D.lw[v], r0 = D.r0[v];
     const T* Pa = vals + D.voff[v] + (int64_t)a * W;
@@ -2952,6 +2974,20 @@ __global__ __launch_bounds__(256) void k_sn_ext(DevLayout D, const T* __restrict
         acc = wave_sum(acc);
         if (lane == 0) yr[r0 + a] -= acc;
     }
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_sn_ext(DevLayout D, const T* __restrict__ vals, int v,
+                                                T* __restrict__ y, const T* __restrict__ x, int nrhs, int upper)
+{
+    sn_ext_body<T>(D, vals, v, y, x, nrhs, upper, blockIdx.x);
+}
+// several large supernodes' gathers in one launch (jobs: node, block pairs)
+template <typename T>
+__global__ __launch_bounds__(256) void k_sn_ext_views(DevLayout D, const T* __restrict__ vals,
+                                                      const int32_t* __restrict__ jobs, T* __restrict__ y,
+                                                      const T* __restrict__ x, int nrhs, int upper)
+{
+    sn_ext_body<T>(D, vals, jobs[2 * blockIdx.x], y, x, nrhs, upper, jobs[2 * blockIdx.x + 1]);
 }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -2999,6 +3035,25 @@ hipError_t launch_sn_utext(bool fp32, const DevLayout& D, const TailView& TV, co
     if (TV.mT <= 0) return hipSuccess;
     if (fp32) hipLaunchKernelGGL(k_sn_ext<float>, dim3(nblk(TV.mT, 4)), dim3(256), 0, st, D, (const float*)vals, v, (float*)y, (const float*)x, nrhs, 1);
     else hipLaunchKernelGGL(k_sn_ext<double>, dim3(nblk(TV.mT, 4)), dim3(256), 0, st, D, (const double*)vals, v, (double*)y, (const double*)x, nrhs, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_sn_ext_views(bool fp32, const DevLayout& D, const void* vals, const int32_t* jobs, int32_t njobs,
+                               void* y, const void* x, int32_t nrhs, int32_t upper, hipStream_t st)
+{
+    if (njobs <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_sn_ext_views<float>, dim3(njobs), dim3(256), 0, st, D, (const float*)vals, jobs, (float*)y, (const float*)x, nrhs, upper);
+    else hipLaunchKernelGGL(k_sn_ext_views<double>, dim3(njobs), dim3(256), 0, st, D, (const double*)vals, jobs, (double*)y, (const double*)x, nrhs, upper);
+    return hipGetLastError();
+}
+
+hipError_t launch_view_steps(bool fp32, const ViewDesc* vd, const SolveJob* jobs, int32_t njobs, const void* vals,
+                             int32_t n, void* y, void* x, int32_t nrhs, int32_t mode, hipStream_t st)
+{
+    if (njobs <= 0) return hipSuccess;
+    if (mode < 0 || mode > 1) return hipErrorInvalidValue;
+    if (fp32) hipLaunchKernelGGL(k_view_steps<float>, dim3(njobs), dim3(256), 0, st, vd, jobs, (const float*)vals, n, (float*)y, (float*)x, nrhs, mode);
+    else hipLaunchKernelGGL(k_view_steps<double>, dim3(njobs), dim3(256), 0, st, vd, jobs, (const double*)vals, n, (double*)y, (double*)x, nrhs, mode);
     return hipGetLastError();
 }
 

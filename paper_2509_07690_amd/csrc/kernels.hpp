@@ -93,6 +93,15 @@ struct ViewDesc {
     const int32_t* sp;      // solve panels (p0, p1 pairs)
     void* inv;              // inverses of their diagonal blocks
 };
+// one workgroup of a forward / backward solve step of one large supernode,
+// several supernodes per launch: the view, the step's panels (p: the one
+// whose contribution goes out, empty on the first step; q: the one solved
+// with the inverse of its diagonal block, number `inv` of the view's
+// inverses), the range of rows the contribution reaches and the
+// workgroup's block (0: the solve of q; 1..: four rows each)
+struct SolveJob {
+    int32_t view, blk, p0, p1, q0, q1, inv, first, count;
+};
 struct ViewJob {
     int32_t v;              // view
     int32_t blk;            // TRSM block; GEMM tile (ty << 16 | tx); inverse block (2 panel + kind)
@@ -167,6 +176,15 @@ hipError_t launch_sn_lext(bool fp32, const DevLayout& D, const TailView& TV, con
                           int32_t nrhs, hipStream_t st);
 hipError_t launch_sn_utext(bool fp32, const DevLayout& D, const TailView& TV, const void* vals, int32_t v, void* y,
                            const void* x, int32_t nrhs, hipStream_t st);
+// the same gathers for several large supernodes in one launch (jobs: node,
+// block of four rows pairs; upper: the backward solve's T-region gathers)
+hipError_t launch_sn_ext_views(bool fp32, const DevLayout& D, const void* vals, const int32_t* jobs, int32_t njobs,
+                               void* y, const void* x, int32_t nrhs, int32_t upper, hipStream_t st);
+// one forward (mode 0) or backward (mode 1) solve step of several large
+// supernodes (views vd) in one launch, a SolveJob per workgroup; each
+// workgroup computes what the same block of launch_tail_step computes
+hipError_t launch_view_steps(bool fp32, const ViewDesc* vd, const SolveJob* jobs, int32_t njobs, const void* vals,
+                             int32_t n, void* y, void* x, int32_t nrhs, int32_t mode, hipStream_t st);
 hipError_t launch_scatter(bool fp32, const double* aval, const int64_t* amap, const double* asr,
                           const double* asc, int64_t nnz, void* vals, double* acopy, hipStream_t st);
 hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st);

@@ -149,3 +149,30 @@ def test_batch_pipelined(hylu, batch):
         e, _ = o.backward_error(np.concatenate([v.b[:, 0] for v in ws]), x) if k == 0 else (0.0, 0.0)
         assert e <= 1e-12
         assert np.abs(xk - w.x_true[:, 0]).max() <= 1e-9, k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_solve_launch_packing(hylu, batch, precision):
+    """The batch's solves with the large supernodes of a level launched
+    together (their gathers in one launch, then each panel step of all of
+    them in one launch) and the long supernodes split over workgroups
+    (solve_split, default) against one launch sequence per supernode and one
+    workgroup per supernode: the same factors and, for one and for three
+    right-hand sides, the same solutions to the bit."""
+    ws, a0 = batch
+    print(f"[case] batch of {len(ws)} solve launch packing, {precision}", flush=True)
+    U1 = None
+    out = []
+    for split in (1, 0):
+        hb = hylu.Handle.batch([(a.row_ptr, a.col, a.val) for a in a0], precision=precision, solve_split=split)
+        assert (hb.info()["split_sn"] > 0) == (split == 1)
+        U1 = _union(hb, [w.A.val for w in ws])
+        hb.factorize(dev(U1.val))
+        b = np.concatenate([w.b[:, 0] for w in ws])
+        B = np.stack([b, 2.0 * b - 1.0, np.sin(np.arange(hb.n))], axis=1)
+        x1 = hb.solve(dev(b)).cpu().numpy()
+        x3 = hb.solve(dev(B)).cpu().numpy()
+        out.append((hb.factors_raw()["vals"], x1, x3))
+        hb.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
