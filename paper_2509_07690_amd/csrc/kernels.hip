@@ -675,13 +675,24 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_factor_rows(DevLayout D, T* __restrict__ vals,
                                                     const int32_t* __restrict__ rows, const int64_t* __restrict__ ranges,
                                                     int32_t nrows, int32_t lds_cap, T tau, int32_t* __restrict__ pert,
-                                                    int32_t stage, int32_t search, const int64_t* __restrict__ inv_off)
+                                                    int32_t stage, int32_t search, const int64_t* __restrict__ inv_off,
+                                                    int32_t xc)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_last, s_p;
-    if ((int)blockIdx.x >= nrows) return;
-    const int64_t eb = ranges ? ranges[2 * blockIdx.x] : -1, ee = ranges ? ranges[2 * blockIdx.x + 1] : -1;
-    const int i = rows[blockIdx.x];
+    // xc > 0: workgroups go to the eight XCDs in turn, so workgroup b takes
+    // task ((b/8)/xc * 8 + b%8) * xc + (b/8)%xc: every XCD gets runs of xc
+    // consecutive tasks (rows of one node, which share their sources, share
+    // an L2) and the runs alternate between XCDs (the grid is a multiple of
+    // 8 xc; the workgroups past the last task leave)
+    int t = blockIdx.x;
+    if (xc > 0) {
+        const int x = t & 7, slot = t >> 3;
+        t = ((slot / xc) * 8 + x) * xc + slot % xc;
+    }
+    if (t >= nrows) return;
+    const int64_t eb = ranges ? ranges[2 * t] : -1, ee = ranges ? ranges[2 * t + 1] : -1;
+    const int i = rows[t];
     row_task<T, NT>(D, vals, i, lds_cap, tau, pert, smem_raw, stage, eb, ee);
     const int v = D.row_node[i];
     if (!D.snfuse || !D.snfuse[v]) return;
@@ -3073,6 +3084,7 @@ hipError_t launch_init_pivots(const DevLayout& D, hipStream_t st)
 }
 
 static const int32_t kRowLdsCap = 4096;   // row accumulator in LDS up to this width
+static const int32_t kXcdChunk = 16, kXcdMin = 2048;
 
 size_t factor_rows_lds(bool fp32, int32_t stage, int32_t cap)
 {
@@ -3092,8 +3104,10 @@ hipError_t launch_factor_rows(bool fp32, const DevLayout& D, void* vals, const i
     const size_t es = fp32 ? sizeof(float) : sizeof(double);
     const size_t sh = std::max(factor_rows_lds(fp32, stage, cap), (size_t)nt * (es + 4) + 64 * (es + 1) + 16);
     if (sh > kLdsMax) return hipErrorInvalidValue;
-    const dim3 g(nrows);
-#define ROWS_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_rows<TT, NTT>), g, dim3(NTT), sh, st, D, (TT*)vals, rows, ranges, nrows, cap, (TT)tau, pert, stage, search, inv_off)
+    // launches of many rows: runs of kXcdChunk consecutive rows per XCD
+    const int32_t xc = nrows >= kXcdMin ? kXcdChunk : 0;
+    const dim3 g(xc ? (unsigned)((nrows + 8 * xc - 1) / (8 * xc) * (8 * xc)) : (unsigned)nrows);
+#define ROWS_LAUNCH(TT, NTT) hipLaunchKernelGGL((k_factor_rows<TT, NTT>), g, dim3(NTT), sh, st, D, (TT*)vals, rows, ranges, nrows, cap, (TT)tau, pert, stage, search, inv_off, xc)
     if (fp32) {
         if (nt == 1024) ROWS_LAUNCH(float, 1024);
         else if (nt == 512) ROWS_LAUNCH(float, 512);
