@@ -420,6 +420,11 @@ def grid27_leg(side, precision, steps, warmup, dense_tail=0.5, sn_tile=0, sn_den
     h.factorize(v)
     torch.cuda.synchronize()
     log(f"grid27 {precision}: factorize {time.time() - t0:.2f}s")
+    t0 = time.time()
+    t_def, t_tuned = h.autotune(v, reps=1)      # launch shapes per level (untimed setup)
+    tune = {"builtin": round(t_def, 3), "tuned": round(t_tuned, 3), "s": round(time.time() - t0, 2)}
+    log(f"grid27 {precision}: autotune level time {t_def:.1f} ms with built-in shapes, {t_tuned:.1f} ms tuned "
+        f"({tune['s']} s)")
     ms = _timed(lambda: (h.refactor(v), h.solve_cols(B, out=X)), steps, warmup)
     t_ref = _timed(lambda: h.refactor(v), steps, 1)
     h.solve_cols(B, out=X)
@@ -434,7 +439,7 @@ def grid27_leg(side, precision, steps, warmup, dense_tail=0.5, sn_tile=0, sn_den
            "refactor_ms": round(t_ref, 4), "factor_gflops": round(info["flops"] / (t_ref * 1e-3) / 1e9, 3),
            "flops": info["flops"], "flops_issued": info["flops_issued"], "backward_error": eta, "resid_1": res1,
            "ir_iters": info["ir_iters"], "analyze_s": round(t_an, 2), "tail_rows": info["tail_rows"],
-           "kernels_one_rhs": kernels}
+           "autotune_level_ms": tune, "kernels_one_rhs": kernels}
     h.close()
     return res
 
@@ -455,6 +460,9 @@ def adjoint_leg(side, steps, warmup, dense_tail=0.15, sn_dense=64, sn_inverse=1,
     b = torch.from_numpy(np.ascontiguousarray(w.b[:, 0])).cuda()
     xt = torch.from_numpy(w.extra["x_target"]).cuda()
     h.factorize(v)
+    t0 = time.time()
+    t_def, t_tuned = h.autotune(v, reps=2)      # launch shapes per level (untimed setup)
+    tune = {"builtin": round(t_def, 3), "tuned": round(t_tuned, 3), "s": round(time.time() - t0, 2)}
 
     def fwd():
         return hylu.sparse_solve(h, v, b)
@@ -475,7 +483,8 @@ def adjoint_leg(side, steps, warmup, dense_tail=0.15, sn_dense=64, sn_inverse=1,
            "precision": "fp64", "steps": steps,
            "config": {"workload": f"convdiff3d_7pt side={side} n={A.n} nnz={A.nnz}, loss 0.5||x-x_target||^2"},
            "forward_ms": round(t_f, 4), "backward_ms": round(t_fb - t_f, 4), "flops": h.info()["flops"],
-           "backward_error": eta, "backward_error_transposed": eta_t, "analyze_s": round(t_an, 2)}
+           "backward_error": eta, "backward_error_transposed": eta_t, "analyze_s": round(t_an, 2),
+           "autotune_level_ms": tune}
     h.close()
     return res
 
