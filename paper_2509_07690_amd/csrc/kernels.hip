@@ -174,33 +174,84 @@ __device__ void apply_source_direct(const DevLayout& D, const T* __restrict__ va
     }
     }
     const T* Ut = Us + ms;
-    for (int j = tid; j < ws; j += NT) {
-        T acc0 = T(0), acc1 = T(0);
-        const int rj = rl[j];
-        int b = 0;
-        // sixteen loads in flight per step
-        for (; b + 16 <= ms; b += 16) {
-            T u[16];
+    // wide T regions (4 NT columns or more): two columns per thread, each
+    // summed as by one column alone in the loop below (even rows of the
+    // source into the first partial sum, odd ones into the second, in
+    // ascending order, the last ms mod 4 rows into the first), eight rows of
+    // both columns loaded per step
+    if (ws >= 4 * NT) {
+        for (int j0 = tid; j0 < ws; j0 += 2 * NT) {
+            const int j1 = j0 + NT;
+            const bool two = j1 < ws;
+            T a0 = T(0), a1 = T(0), c0 = T(0), c1 = T(0);
+            int b = 0;
+            for (; b + 8 <= ms; b += 8) {
+                T u[8], w[8];
 #pragma unroll
-            for (int k = 0; k < 16; k++) u[k] = Ut[(int64_t)(b + k) * Ws + j];
+                for (int k = 0; k < 8; k++) u[k] = Ut[(int64_t)(b + k) * Ws + j0];
 #pragma unroll
-            for (int k = 0; k < 16; k += 2) {
-                acc0 += xs[lp + pls[b + k]] * u[k];
-                acc1 += xs[lp + pls[b + k + 1]] * u[k + 1];
+                for (int k = 0; k < 8; k++) w[k] = two ? Ut[(int64_t)(b + k) * Ws + j1] : T(0);
+#pragma unroll
+                for (int k = 0; k < 8; k += 2) {
+                    const T x0 = xs[lp + pls[b + k]], x1 = xs[lp + pls[b + k + 1]];
+                    a0 += x0 * u[k];
+                    a1 += x1 * u[k + 1];
+                    c0 += x0 * w[k];
+                    c1 += x1 * w[k + 1];
+                }
             }
+            for (; b + 4 <= ms; b += 4) {
+                T u[4], w[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) u[k] = Ut[(int64_t)(b + k) * Ws + j0];
+#pragma unroll
+                for (int k = 0; k < 4; k++) w[k] = two ? Ut[(int64_t)(b + k) * Ws + j1] : T(0);
+#pragma unroll
+                for (int k = 0; k < 4; k += 2) {
+                    const T x0 = xs[lp + pls[b + k]], x1 = xs[lp + pls[b + k + 1]];
+                    a0 += x0 * u[k];
+                    a1 += x1 * u[k + 1];
+                    c0 += x0 * w[k];
+                    c1 += x1 * w[k + 1];
+                }
+            }
+            for (; b < ms; b++) {
+                const T x0 = xs[lp + pls[b]];
+                a0 += x0 * Ut[(int64_t)b * Ws + j0];
+                if (two) c0 += x0 * Ut[(int64_t)b * Ws + j1];
+            }
+            xs[rl[j0]] -= a0 + a1;
+            if (two) xs[rl[j1]] -= c0 + c1;
         }
-        for (; b + 4 <= ms; b += 4) {
-            const T u0 = Ut[(int64_t)(b + 0) * Ws + j];
-            const T u1 = Ut[(int64_t)(b + 1) * Ws + j];
-            const T u2 = Ut[(int64_t)(b + 2) * Ws + j];
-            const T u3 = Ut[(int64_t)(b + 3) * Ws + j];
-            acc0 += xs[lp + pls[b + 0]] * u0;
-            acc1 += xs[lp + pls[b + 1]] * u1;
-            acc0 += xs[lp + pls[b + 2]] * u2;
-            acc1 += xs[lp + pls[b + 3]] * u3;
+    } else {
+        for (int j = tid; j < ws; j += NT) {
+            T acc0 = T(0), acc1 = T(0);
+            const int rj = rl[j];
+            int b = 0;
+            // sixteen loads in flight per step
+            for (; b + 16 <= ms; b += 16) {
+                T u[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) u[k] = Ut[(int64_t)(b + k) * Ws + j];
+#pragma unroll
+                for (int k = 0; k < 16; k += 2) {
+                    acc0 += xs[lp + pls[b + k]] * u[k];
+                    acc1 += xs[lp + pls[b + k + 1]] * u[k + 1];
+                }
+            }
+            for (; b + 4 <= ms; b += 4) {
+                const T u0 = Ut[(int64_t)(b + 0) * Ws + j];
+                const T u1 = Ut[(int64_t)(b + 1) * Ws + j];
+                const T u2 = Ut[(int64_t)(b + 2) * Ws + j];
+                const T u3 = Ut[(int64_t)(b + 3) * Ws + j];
+                acc0 += xs[lp + pls[b + 0]] * u0;
+                acc1 += xs[lp + pls[b + 1]] * u1;
+                acc0 += xs[lp + pls[b + 2]] * u2;
+                acc1 += xs[lp + pls[b + 3]] * u3;
+            }
+            for (; b < ms; b++) acc0 += xs[lp + pls[b]] * Ut[(int64_t)b * Ws + j];
+            xs[rj] -= acc0 + acc1;
         }
-        for (; b < ms; b++) acc0 += xs[lp + pls[b]] * Ut[(int64_t)b * Ws + j];
-        xs[rj] -= acc0 + acc1;
     }
     Sync::bar();
 }
