@@ -2342,17 +2342,16 @@ hylu_status solve_impl(hylu_handle h, const SolveWs& w, const double* d_b, doubl
                        int32_t transpose, hipStream_t st, bool graphs)
 {
     const int32_t n = h->n;
-    // does refinement run?  (perturbed pivots, or FP32 factors)
-    if (!h->pert_known) {
-        HIPCHK(hipEventSynchronize(h->fact_done));
-        h->last_pert = h->h_pert[0];
-        h->pert_known = true;
-        if (h->h_pert[1]) { h->sticky_error = true; return HYLU_ERR_DEVICE; }
-    }
-    bool refine = h->fp32 || h->last_pert > 0;
-    // b is needed after x is written when refining in place
+    // does refinement run?  (perturbed pivots, or FP32 factors).  After a
+    // refactorisation the count of perturbed pivots is read only once the
+    // base solve is queued behind it, so the device goes from one to the
+    // other without waiting for the host
+    const bool pert_pending = !h->pert_known;
+    bool refine = h->fp32 || (!pert_pending && h->last_pert > 0);
+    // b is needed after x is written when refining in place (or when that is
+    // not known yet)
     const double* b = d_b;
-    bool bcopy = refine && d_b == d_x;
+    bool bcopy = (refine || pert_pending) && d_b == d_x;
     if (bcopy) {
         HIPCHK(hipMemcpy2DAsync(w.bc, sizeof(double) * (size_t)n, d_b, sizeof(double) * ld, sizeof(double) * (size_t)n,
                                 nrhs, hipMemcpyDeviceToDevice, st));
@@ -2371,6 +2370,13 @@ hylu_status solve_impl(hylu_handle h, const SolveWs& w, const double* d_b, doubl
     } else {
         s = enqueue_solve(h, w, b, ldb, d_x, ld, nrhs, transpose, 0, st);
         if (s != HYLU_OK) return s;
+    }
+    if (pert_pending) {
+        HIPCHK(hipEventSynchronize(h->fact_done));
+        h->last_pert = h->h_pert[0];
+        h->pert_known = true;
+        if (h->h_pert[1]) { h->sticky_error = true; return HYLU_ERR_DEVICE; }
+        refine = h->fp32 || h->last_pert > 0;
     }
     h->ir_iters = 0;
     h->berr = h->resid1 = 0.0;
